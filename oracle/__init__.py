@@ -1,0 +1,391 @@
+"""FP64 CPU oracle (ctypes front end of ``oracle/oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and
+the CPU-baseline leg of the benchmark. The product library never imports,
+links or calls anything here, and nothing here imports the product package.
+
+Functions follow the paper's Section 3.2 (octahedral irradiance and
+visibility maps with guard bands), Section 3.3 (FP16 values split into two
+bytes) and Section 3.4 (repacking without guard bands, delta-coded 2-byte
+probe index buffer, per-client last-transmitted textures, change
+thresholding). The probe update itself is the irradiance-volume method the
+paper adopts (Section 3.2) but does not restate; the oracle takes its steps
+in order: ray directions, closest hit, shading, weighted means, hysteresis,
+guard-band copy.
+
+Parity pins: every function here is pinned by ``tests/test_oracle_pins.py``
+against closed forms, special cases, brute force, library routines or the
+paper's worked numbers; the shading of fully shadowed scenes at scale is
+covered only through those small-scene pins (see the test module docstring).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_F = ctypes.POINTER(ctypes.c_float)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_U16 = ctypes.POINTER(ctypes.c_uint16)
+_U8 = ctypes.POINTER(ctypes.c_uint8)
+
+
+class _Volume(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("n", ctypes.c_int), ("irr_res", ctypes.c_int), ("vis_res", ctypes.c_int),
+                ("vis_sharpness", ctypes.c_int), ("first_frame_no_history", ctypes.c_int),
+                ("origin", ctypes.c_double * 3), ("spacing", ctypes.c_double * 3),
+                ("hysteresis", ctypes.c_double), ("max_distance", ctypes.c_double),
+                ("sky", ctypes.c_double * 3)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        L.or_half_to_double.restype = ctypes.c_double
+        L.or_half_to_double.argtypes = [ctypes.c_uint16]
+        L.or_double_to_half.restype = ctypes.c_uint16
+        L.or_double_to_half.argtypes = [ctypes.c_double]
+        L.or_round_half_array.argtypes = [_D, _D, ctypes.c_int64]
+        L.or_oct_decode.argtypes = [ctypes.c_double, ctypes.c_double, _D]
+        L.or_oct_encode.argtypes = [_D, _D]
+        L.or_texel_dirs.argtypes = [ctypes.c_int, _D]
+        L.or_ray_dirs.argtypes = [ctypes.c_int, _F, _D]
+        L.or_scene_create.restype = ctypes.c_void_p
+        L.or_scene_create.argtypes = [ctypes.c_int, _F, _F, _F, ctypes.c_int]
+        L.or_scene_destroy.argtypes = [ctypes.c_void_p]
+        L.or_scene_eps.restype = ctypes.c_double
+        L.or_scene_eps.argtypes = [ctypes.c_void_p]
+        L.or_scene_diag.restype = ctypes.c_double
+        L.or_scene_diag.argtypes = [ctypes.c_void_p]
+        L.or_trace_shade.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Volume), _F, ctypes.c_int, _F,
+                                     ctypes.c_double, _D, _D, _D, _D, _D, _D, _I32, _D, _I32, _I32,
+                                     ctypes.c_int, ctypes.c_int]
+        L.or_closest_hits.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D, _I32, _D, _I32, ctypes.c_double]
+        L.or_closest_hits_brute.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D, _I32, _D]
+        L.or_border.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D]
+        L.or_blend_update.argtypes = [ctypes.POINTER(_Volume), _D, _D, _D, ctypes.c_int, ctypes.c_int,
+                                      _D, _D, ctypes.c_int]
+        L.or_payload_checksum.restype = ctypes.c_uint32
+        L.or_payload_checksum.argtypes = [_U8, ctypes.c_int64]
+        L.or_packet_bytes.restype = ctypes.c_int64
+        L.or_packet_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.or_pack.restype = ctypes.c_int64
+        L.or_pack.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _U16, _U16, _U16, _U16,
+                              ctypes.c_double, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32,
+                              _U8, ctypes.c_int64, _U8, _U8]
+        L.or_client_apply.restype = ctypes.c_int
+        L.or_client_apply.argtypes = [_U8, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      _U16, _U16, ctypes.POINTER(ctypes.c_uint32)]
+        L.or_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# --------------------------------------------------------------------------
+# scalar helpers
+# --------------------------------------------------------------------------
+def half_to_double(bits: int) -> float:
+    return lib().or_half_to_double(int(bits))
+
+
+def double_to_half(x: float) -> int:
+    return lib().or_double_to_half(float(x))
+
+
+def round_half(a: np.ndarray) -> np.ndarray:
+    a = _c(a, np.float64)
+    out = np.empty_like(a)
+    lib().or_round_half_array(_p(a, _D), _p(out, _D), a.size)
+    return out
+
+
+def oct_decode(u: float, w: float) -> np.ndarray:
+    out = np.zeros(3)
+    lib().or_oct_decode(float(u), float(w), _p(out, _D))
+    return out
+
+
+def oct_encode(v) -> np.ndarray:
+    v = _c(v, np.float64)
+    out = np.zeros(2)
+    lib().or_oct_encode(_p(v, _D), _p(out, _D))
+    return out
+
+
+def texel_dirs(N: int) -> np.ndarray:
+    out = np.zeros((N * N, 3))
+    lib().or_texel_dirs(N, _p(out, _D))
+    return out
+
+
+def ray_dirs(n: int, R) -> np.ndarray:
+    R = _c(R, np.float32).reshape(9)
+    out = np.zeros((n, 3))
+    lib().or_ray_dirs(n, _p(R, _F), _p(out, _D))
+    return out
+
+
+# --------------------------------------------------------------------------
+# scene
+# --------------------------------------------------------------------------
+class OracleScene:
+    """Triangles (float32 [T,3,3]) with per-triangle albedo/emission and the
+    oracle's own median-split BVH. ``n_static`` leading triangles define the
+    scene extent (and the shadow-ray offset)."""
+
+    def __init__(self, tris, albedo, emission=None, n_static: Optional[int] = None):
+        tris = _c(tris, np.float32).reshape(-1, 9)
+        self.ntri = tris.shape[0]
+        self._tris = tris
+        self._alb = _c(albedo, np.float32).reshape(-1, 3)
+        self._emi = _c(emission if emission is not None else np.zeros_like(self._alb), np.float32).reshape(-1, 3)
+        ns = self.ntri if n_static is None else int(n_static)
+        self.h = lib().or_scene_create(self.ntri, _p(self._tris, _F), _p(self._alb, _F), _p(self._emi, _F), ns)
+
+    @classmethod
+    def from_scene(cls, scene, n_static: Optional[int] = None):
+        if n_static is None:
+            n_static = scene.n_triangles - scene.n_dynamic
+        return cls(scene.triangles(), scene.albedo, scene.emission, n_static=n_static)
+
+    @property
+    def eps(self) -> float:
+        return lib().or_scene_eps(self.h)
+
+    @property
+    def diag(self) -> float:
+        return lib().or_scene_diag(self.h)
+
+    def closest_hits(self, o, d, margin: float = 0.0):
+        o = _c(o, np.float64).reshape(-1, 3)
+        d = _c(d, np.float64).reshape(-1, 3)
+        n = o.shape[0]
+        tri = np.zeros(n, np.int32)
+        t = np.zeros(n)
+        near = np.zeros(n, np.int32)
+        lib().or_closest_hits(self.h, n, _p(o, _D), _p(d, _D), _p(tri, _I32), _p(t, _D), _p(near, _I32), margin)
+        return tri, t, near
+
+    def closest_hits_brute(self, o, d):
+        o = _c(o, np.float64).reshape(-1, 3)
+        d = _c(d, np.float64).reshape(-1, 3)
+        n = o.shape[0]
+        tri = np.zeros(n, np.int32)
+        t = np.zeros(n)
+        lib().or_closest_hits_brute(self.h, n, _p(o, _D), _p(d, _D), _p(tri, _I32), _p(t, _D))
+        return tri, t
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().or_scene_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def _volume_struct(cfg) -> _Volume:
+    v = _Volume()
+    v.nx, v.ny, v.nz = cfg.nx, cfg.ny, cfg.nz
+    v.n = cfg.rays_per_probe
+    v.irr_res, v.vis_res = cfg.irr_res, cfg.vis_res
+    v.vis_sharpness = cfg.vis_sharpness
+    v.first_frame_no_history = 1 if cfg.first_frame_no_history else 0
+    for k in range(3):
+        # the volume description is FP32 data on both sides
+        v.origin[k] = float(np.float32(cfg.origin[k]))
+        v.spacing[k] = float(np.float32(cfg.spacing[k]))
+        v.sky[k] = float(np.float32(cfg.sky[k]))
+    v.hysteresis = float(np.float32(cfg.hysteresis))
+    v.max_distance = float(np.float32(cfg.max_distance))
+    return v
+
+
+def trace_shade(scene: OracleScene, cfg, R, lights, delta_rel: float = 1e-6, maxc: int = 4,
+                nthreads: int = 0, bounds: bool = True):
+    """Trace and shade every (probe, ray). Returns a dict of arrays shaped
+    [P, n(, 3)]: L, r (nominal), L_lo, L_hi, r_lo, r_hi (tie bounds),
+    hit, hit_t, cand [P, n, maxc], ncand."""
+    v = _volume_struct(cfg)
+    P, n = cfg.n_probes, cfg.rays_per_probe
+    R = _c(R, np.float32).reshape(9)
+    lights = _c(lights, np.float32).reshape(-1, 6)
+    L = np.zeros((P, n, 3))
+    r = np.zeros((P, n))
+    Llo = np.zeros((P, n, 3)) if bounds else None
+    Lhi = np.zeros((P, n, 3)) if bounds else None
+    rlo = np.zeros((P, n)) if bounds else None
+    rhi = np.zeros((P, n)) if bounds else None
+    hit = np.zeros((P, n), np.int32)
+    hit_t = np.zeros((P, n))
+    cand = np.zeros((P, n, maxc), np.int32)
+    ncand = np.zeros((P, n), np.int32)
+    lib().or_trace_shade(scene.h, ctypes.byref(v), _p(R, _F), lights.shape[0], _p(lights, _F), delta_rel,
+                         _p(L, _D), _p(Llo, _D), _p(Lhi, _D), _p(r, _D), _p(rlo, _D), _p(rhi, _D),
+                         _p(hit, _I32), _p(hit_t, _D), _p(cand, _I32), _p(ncand, _I32), maxc, nthreads)
+    out = dict(L=L, r=r, hit=hit, hit_t=hit_t, cand=cand, ncand=ncand)
+    if bounds:
+        out.update(L_lo=Llo, L_hi=Lhi, r_lo=rlo, r_hi=rhi)
+    return out
+
+
+def border(tiles: np.ndarray) -> np.ndarray:
+    """Guard-band copy of a float tile set [P, C, N+2, N+2] (returns a copy)."""
+    t = _c(tiles, np.float64).copy()
+    P, C, S, _ = t.shape
+    lib().or_border(P, C, S - 2, _p(t, _D))
+    return t
+
+
+def empty_maps(cfg):
+    """Zero-initialised float64 maps: irradiance [P,3,Ni+2,Ni+2], visibility
+    [P,2,Nv+2,Nv+2]."""
+    P = cfg.n_probes
+    return (np.zeros((P, 3, cfg.irr_res + 2, cfg.irr_res + 2)),
+            np.zeros((P, 2, cfg.vis_res + 2, cfg.vis_res + 2)))
+
+
+def blend_update(cfg, dirs, L, r, irr, vis, first: bool, fp16: Optional[bool] = None, nthreads: int = 0):
+    """One blend + hysteresis + guard-band step on float64 maps (in place,
+    also returned). ``dirs``: [n,3] ray directions of the frame."""
+    v = _volume_struct(cfg)
+    fp16 = cfg.fp16 if fp16 is None else fp16
+    dirs = _c(dirs, np.float64)
+    L = _c(L, np.float64)
+    r = _c(r, np.float64)
+    assert irr.dtype == np.float64 and irr.flags.c_contiguous
+    assert vis.dtype == np.float64 and vis.flags.c_contiguous
+    lib().or_blend_update(ctypes.byref(v), _p(dirs, _D), _p(L, _D), _p(r, _D), 1 if first else 0,
+                          1 if fp16 else 0, _p(irr, _D), _p(vis, _D), nthreads)
+    return irr, vis
+
+
+class OracleVolume:
+    """Oracle state of one probe volume over frames: nominal maps plus the
+    lower/upper tie-bound maps (all float64; FP16-valued when cfg.fp16)."""
+
+    def __init__(self, cfg):
+        self.cfg = cfg
+        self.irr, self.vis = empty_maps(cfg)
+        self.irr_lo, self.vis_lo = empty_maps(cfg)
+        self.irr_hi, self.vis_hi = empty_maps(cfg)
+        self.frame = 0
+        self.last = None
+
+    def update(self, scene: OracleScene, R, lights, nthreads: int = 0, delta_rel: float = 1e-6):
+        cfg = self.cfg
+        rays = trace_shade(scene, cfg, R, lights, delta_rel=delta_rel, nthreads=nthreads)
+        dirs = ray_dirs(cfg.rays_per_probe, R)
+        first = self.frame == 0
+        blend_update(cfg, dirs, rays["L"], rays["r"], self.irr, self.vis, first, nthreads=nthreads)
+        blend_update(cfg, dirs, rays["L_lo"], rays["r_lo"], self.irr_lo, self.vis_lo, first, nthreads=nthreads)
+        blend_update(cfg, dirs, rays["L_hi"], rays["r_hi"], self.irr_hi, self.vis_hi, first, nthreads=nthreads)
+        self.frame += 1
+        self.last = rays
+        return rays
+
+
+# --------------------------------------------------------------------------
+# packing
+# --------------------------------------------------------------------------
+def packet_bytes(K_irr: int, K_vis: int, irr_res: int = 8, vis_res: int = 16) -> int:
+    return int(lib().or_packet_bytes(K_irr, K_vis, irr_res, vis_res))
+
+
+def payload_checksum(payload: bytes) -> int:
+    a = np.frombuffer(payload, np.uint8).copy()
+    return int(lib().or_payload_checksum(_p(a, _U8), a.size))
+
+
+class OracleClientState:
+    """Server-side per-client last-transmitted interiors (uint16)."""
+
+    def __init__(self, n_probes: int, irr_res: int = 8, vis_res: int = 16, client: int = 0):
+        self.P, self.Ni, self.Nv = n_probes, irr_res, vis_res
+        self.ref_irr = np.zeros((n_probes, 3, irr_res * irr_res), np.uint16)
+        self.ref_vis = np.zeros((n_probes, 2, vis_res * vis_res), np.uint16)
+        self.client = client
+        self.seq = 0
+
+    def pack(self, cur_irr: np.ndarray, cur_vis: np.ndarray, tau_irr: float = 0.0, tau_vis: float = 0.0):
+        """Pack FP16 tiles (uint16 [P,3,Ni+2,Ni+2] / [P,2,Nv+2,Nv+2]).
+        Returns (packet bytes, mask_irr, mask_vis)."""
+        cur_irr = _c(cur_irr, np.uint16)
+        cur_vis = _c(cur_vis, np.uint16)
+        assert cur_irr.shape == (self.P, 3, self.Ni + 2, self.Ni + 2)
+        assert cur_vis.shape == (self.P, 2, self.Nv + 2, self.Nv + 2)
+        cap = packet_bytes(self.P, self.P, self.Ni, self.Nv)
+        out = np.zeros(cap, np.uint8)
+        mi = np.zeros(self.P, np.uint8)
+        mv = np.zeros(self.P, np.uint8)
+        n = lib().or_pack(self.P, self.Ni, self.Nv, _p(cur_irr, _U16), _p(cur_vis, _U16),
+                          _p(self.ref_irr, _U16), _p(self.ref_vis, _U16), float(tau_irr), float(tau_vis),
+                          self.client, self.seq, _p(out, _U8), cap, _p(mi, _U8), _p(mv, _U8))
+        assert n > 0
+        self.seq += 1
+        return out[:n].tobytes(), mi.astype(bool), mv.astype(bool)
+
+    def reset(self):
+        self.ref_irr[:] = 0
+        self.ref_vis[:] = 0
+
+
+class OracleClientDecoder:
+    """The receiving client: FP16 tiles updated from packets."""
+
+    def __init__(self, n_probes: int, irr_res: int = 8, vis_res: int = 16):
+        self.P, self.Ni, self.Nv = n_probes, irr_res, vis_res
+        self.irr = np.zeros((n_probes, 3, irr_res + 2, irr_res + 2), np.uint16)
+        self.vis = np.zeros((n_probes, 2, vis_res + 2, vis_res + 2), np.uint16)
+        self.seq = None
+
+    def apply(self, packet: bytes) -> int:
+        a = np.frombuffer(packet, np.uint8).copy()
+        seq = ctypes.c_uint32(0)
+        rc = lib().or_client_apply(_p(a, _U8), a.size, self.P, self.Ni, self.Nv, _p(self.irr, _U16),
+                                   _p(self.vis, _U16), ctypes.byref(seq))
+        if rc == 0:
+            self.seq = seq.value
+        return rc
+
+    def reset(self):
+        self.irr[:] = 0
+        self.vis[:] = 0
+        self.seq = None
+
+
+def max_threads() -> int:
+    return int(lib().or_max_threads())

@@ -1,0 +1,530 @@
+"""Pins of the FP64 oracle against things other than itself (CPU only).
+
+Each test ties one oracle function to a closed form, a special case that
+reduces to a known answer, brute force on tiny inputs, a library routine
+(numpy), an invariant of the mathematics, or the paper's printed numbers.
+Absolute radiance of shadowed scenes at scale is not pinned beyond these
+small-scene cases ("parity unpinned" for that part; the GPU is compared with
+the oracle, which is trusted through these pins).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.usefixtures("oracle_lib")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+# ---------------------------------------------------------------- binary16
+def test_half_to_double_all_patterns_match_numpy(O):
+    bits = np.arange(65536, dtype=np.uint16)
+    ref = bits.view(np.float16).astype(np.float64)
+    got = np.array([O.half_to_double(int(b)) for b in bits])
+    finite = np.isfinite(ref)
+    assert np.array_equal(got[finite], ref[finite])
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    assert np.array_equal(got[np.isinf(ref)], ref[np.isinf(ref)])
+
+
+def test_double_to_half_rounding_matches_numpy(O):
+    rng = np.random.default_rng(0)
+    x = np.concatenate([
+        rng.uniform(-70000, 70000, 20000),
+        np.exp(rng.uniform(-20, 11.5, 20000)) * rng.choice([-1, 1], 20000),
+        np.ldexp(rng.integers(0, 4096, 5000).astype(np.float64), -26),   # subnormal region
+        [0.0, -0.0, 65504.0, 65519.99, 65520.0, 1e9, 2.0 ** -25, 3 * 2.0 ** -26],
+    ])
+    # exact ties between binary16 neighbours
+    h = rng.integers(0, 0x7bff, 5000).astype(np.uint16)
+    a = h.view(np.float16).astype(np.float64)
+    b = (h + 1).astype(np.uint16).view(np.float16).astype(np.float64)
+    x = np.concatenate([x, (a + b) / 2])
+    got = np.array([O.double_to_half(v) for v in x], dtype=np.uint16)
+    ref = x.astype(np.float16).view(np.uint16)
+    assert np.array_equal(got, ref)
+
+
+# ---------------------------------------------------------------- octahedral
+def test_octahedral_round_trip(O):
+    rng = np.random.default_rng(1)
+    v = rng.normal(size=(3000, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    for d in v:
+        uw = O.oct_encode(d)
+        assert np.all(np.abs(uw) <= 1.0 + 1e-15)
+        assert np.allclose(O.oct_decode(*uw), d, atol=1e-12)
+    for u, w in rng.uniform(-1, 1, size=(3000, 2)):
+        assert np.allclose(O.oct_encode(O.oct_decode(u, w)), (u, w), atol=1e-12)
+
+
+def test_octahedral_landmarks(O):
+    assert np.allclose(O.oct_decode(0.0, 0.0), (0, 0, 1))
+    for cu, cw in ((1, 1), (-1, 1), (1, -1), (-1, -1)):
+        assert np.allclose(O.oct_decode(cu, cw), (0, 0, -1))
+    # the diamond |u|+|w| = 1 is the equator
+    for a in np.linspace(0, 1, 7):
+        assert abs(O.oct_decode(a, 1 - a)[2]) < 1e-15
+    # edge points (1, w) and (1, -w) are the same direction (the fold)
+    for w in np.linspace(-1, 1, 9):
+        assert np.allclose(O.oct_decode(1.0, w), O.oct_decode(1.0, -w), atol=1e-15)
+        assert np.allclose(O.oct_decode(w, 1.0), O.oct_decode(-w, 1.0), atol=1e-15)
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_texel_centres_round_trip_to_their_texel(O, N):
+    dirs = O.texel_dirs(N)
+    assert np.allclose(np.linalg.norm(dirs, axis=1), 1.0, atol=1e-14)
+    for t, d in enumerate(dirs):
+        u, w = O.oct_encode(d)
+        i = int(math.floor((u + 1) * 0.5 * N))
+        j = int(math.floor((w + 1) * 0.5 * N))
+        assert j * N + i == t
+
+
+# ---------------------------------------------------------------- ray directions
+@pytest.mark.parametrize("n", [64, 128, 256, 1000])
+def test_spherical_fibonacci_properties(O, n):
+    I = np.eye(3, dtype=np.float32).reshape(9)
+    d = O.ray_dirs(n, I)
+    assert np.allclose(np.linalg.norm(d, axis=1), 1.0, atol=1e-14)
+    z = np.sort(d[:, 2])
+    assert np.allclose(np.diff(z), 2.0 / n, atol=1e-12)          # equal-area bands
+    assert np.allclose(z, -z[::-1], atol=1e-12)                   # symmetric about the equator
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    golden_angle = 2 * math.pi * (2 - (1 + math.sqrt(5)) / 2)     # 137.5 degrees
+    step = np.mod(phi[:-1] - phi[1:], 2 * math.pi)               # clockwise steps
+    assert np.allclose(step, golden_angle, atol=1e-9)
+    # near-uniform: first moment ~0, second moment ~I/3
+    assert np.linalg.norm(d.mean(axis=0)) < 2.0 / n
+    assert np.abs(d.T @ d / n - np.eye(3) / 3).max() < 4.0 / n
+
+
+def test_ray_dirs_rotate_with_R(O):
+    I = np.eye(3, dtype=np.float32).reshape(9)
+    for f in range(5):
+        R = synth.rotation(2, f)
+        Rm = R.reshape(3, 3).astype(np.float64)
+        assert abs(np.linalg.det(Rm) - 1) < 1e-6
+        assert np.allclose(Rm @ Rm.T, np.eye(3), atol=1e-6)
+        assert np.allclose(O.ray_dirs(128, R), O.ray_dirs(128, I) @ Rm.T, atol=1e-14)
+
+
+# ---------------------------------------------------------------- intersection
+@pytest.mark.parametrize("n_tris,seed", [(1, 0), (7, 1), (60, 2), (500, 3), (2000, 4)])
+def test_bvh_matches_brute_force(O, n_tris, seed):
+    sc = synth.random_triangle_soup(n_tris, seed, extent=10.0, size=1.5)
+    osc = O.OracleScene.from_scene(sc)
+    rng = np.random.default_rng(100 + seed)
+    o = rng.uniform(-2, 12, size=(4000, 3))
+    d = rng.normal(size=(4000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    tb, tt, _ = osc.closest_hits(o, d)
+    bb, bt = osc.closest_hits_brute(o, d)
+    assert np.array_equal(tb, bb)
+    hit = bb >= 0
+    assert np.array_equal(tt[hit], bt[hit])
+    if n_tris >= 60:
+        assert hit.mean() > 0.05
+
+
+def test_tie_flag_on_shared_edge(O):
+    sc = synth.box_room()
+    osc = O.OracleScene.from_scene(sc)
+    # wall x = -1 is split along its diagonal from (-1,-1,-1) to (-1,4,4)
+    o = np.array([[1.0, 0.5, 0.7]])
+    target = np.array([-1.0, 1.3, 1.3])               # on that diagonal
+    d = (target - o) / np.linalg.norm(target - o)
+    _, _, near = osc.closest_hits(o, d, margin=1e-5)
+    assert near[0] == 1
+    target2 = np.array([-1.0, 0.2, 2.9])              # well inside one triangle
+    d2 = (target2 - o) / np.linalg.norm(target2 - o)
+    tri, t, near2 = osc.closest_hits(o, d2, margin=1e-5)
+    assert near2[0] == 0 and tri[0] >= 0
+    assert np.isclose(t[0], np.linalg.norm(target2 - o[0]), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- trace + shade special cases
+def _cfg(**kw):
+    base = dict(nx=2, ny=2, nz=2, origin=(0.0, 0.0, 0.0), spacing=(0.5, 0.5, 0.5), rays_per_probe=256,
+                max_distance=4.0, fp16=False)
+    base.update(kw)
+    return synth.VolumeConfig(**base)
+
+
+def test_empty_scene_uniform_sky_gives_constant_maps(O):
+    """Uniform radiance environment: irradiance equals the sky radiance and
+    visibility equals (D_max, D_max^2) in every texel."""
+    sky = (0.3, 0.6, 1.2)
+    cfg = _cfg(sky=sky, max_distance=2.5)
+    sc = O.OracleScene(np.zeros((0, 3, 3), np.float32), np.zeros((0, 3), np.float32))
+    vol = O.OracleVolume(cfg)
+    vol.update(sc, synth.rotation(5, 0), np.zeros((0, 6), np.float32))
+    irr = vol.irr[:, :, 1:-1, 1:-1]
+    skyf = np.array(sky, np.float32).astype(np.float64)
+    for c in range(3):
+        assert np.allclose(irr[:, c], skyf[c], rtol=1e-13)
+    dm = float(np.float32(2.5))
+    assert np.allclose(vol.vis[:, 0, 1:-1, 1:-1], dm, rtol=1e-13)
+    assert np.allclose(vol.vis[:, 1, 1:-1, 1:-1], dm * dm, rtol=1e-13)
+
+
+def test_closed_emissive_box_gives_its_emission(O):
+    E = (0.7, 0.4, 0.2)
+    sc = synth.emissive_box(half_width=3.0, center=(0.5, 0.5, 0.5), emission=E)
+    cfg = _cfg(rays_per_probe=128)
+    vol = O.OracleVolume(cfg)
+    vol.update(O.OracleScene.from_scene(sc), synth.rotation(6, 0), sc.lights)
+    Ef = np.array(E, np.float32).astype(np.float64)
+    for c in range(3):
+        assert np.allclose(vol.irr[:, c, 1:-1, 1:-1], Ef[c], rtol=1e-13)
+
+
+def test_distance_in_centred_cube_closed_form(O):
+    a = 1.25
+    for dmax in (5.0, 1.5):
+        sc = synth.cube_shell(a, center=(0.0, 0.0, 0.0))
+        cfg = _cfg(nx=1, ny=1, nz=1, origin=(0.0, 0.0, 0.0), rays_per_probe=300, max_distance=dmax)
+        R = synth.rotation(7, 1)
+        rays = O.trace_shade(O.OracleScene.from_scene(sc), cfg, R, np.zeros((0, 6), np.float32))
+        d = O.ray_dirs(300, R)
+        expect = np.minimum(a / np.abs(d).max(axis=1), float(np.float32(dmax)))
+        assert np.allclose(rays["r"][0], expect, rtol=1e-12)
+
+
+def test_convex_room_direct_light_closed_form(O):
+    """Room without occluder: each ray's radiance is rho/pi * I cos / d^2 at
+    the wall point found by the slab method (no shadowing possible)."""
+    room = synth.box_room()
+    tris = room.triangles()[:12]                        # the 6 walls only
+    alb = room.albedo[:12]
+    light = np.array([[1.1, 2.9, 0.3, 15.0, 12.0, 9.0]], np.float32)
+    osc = O.OracleScene(tris, alb)
+    cfg = _cfg(nx=2, ny=2, nz=2, origin=(0.2, 0.3, 0.4), spacing=(1.7, 1.9, 2.1), rays_per_probe=128)
+    R = synth.rotation(8, 0)
+    rays = O.trace_shade(osc, cfg, R, light)
+    d = O.ray_dirs(128, R)
+    lo, hi = -1.0, 4.0
+    Lp = light[0, :3].astype(np.float64)
+    I = light[0, 3:].astype(np.float64)
+    for p in range(8):
+        x, y, z = p % 2, (p // 2) % 2, p // 4
+        f = lambda v: float(np.float32(v))                 # the description is FP32 data
+        o = np.array([f(0.2) + f(1.7) * x, f(0.3) + f(1.9) * y, f(0.4) + f(2.1) * z])
+        for j in range(128):
+            dj = d[j]
+            ts = [((hi if dj[k] > 0 else lo) - o[k]) / dj[k] for k in range(3)]
+            k = int(np.argmin(ts))
+            t = ts[k]
+            xh = o + t * dj
+            nrm = np.zeros(3)
+            nrm[k] = -np.sign(dj[k])
+            face = 2 * k + (1 if dj[k] > 0 else 0)
+            rho = alb[2 * face].astype(np.float64)
+            lv = Lp - xh
+            dist = np.linalg.norm(lv)
+            cos = max(0.0, nrm @ lv / dist)
+            expect = rho / math.pi * I * cos / dist ** 2
+            assert np.allclose(rays["L"][p, j], expect, rtol=1e-9, atol=1e-12), (p, j)
+            assert np.isclose(rays["r"][p, j], min(t, 4.0), rtol=1e-12)
+
+
+def test_box_room_invariants_and_bounds(O):
+    cfg = synth.config("box_room")
+    sc = synth.box_room()
+    vol = O.OracleVolume(cfg)
+    rays = vol.update(O.OracleScene.from_scene(sc), synth.rotation(2, 0), sc.lights)
+    dmax = float(np.float32(cfg.max_distance))
+    m1 = vol.vis[:, 0, 1:-1, 1:-1]
+    m2 = vol.vis[:, 1, 1:-1, 1:-1]
+    assert np.all(m1 <= dmax * (1 + 1e-15)) and np.all(m1 > 0)
+    assert np.all(m2 >= m1 * m1 * (1 - 1e-12))                    # Jensen
+    assert np.all(vol.irr >= 0)
+    assert np.all(rays["L_lo"] <= rays["L"] + 1e-15) and np.all(rays["L"] <= rays["L_hi"] + 1e-15)
+    assert np.all(rays["r_lo"] <= rays["r"]) and np.all(rays["r"] <= rays["r_hi"])
+    assert np.all(vol.irr_lo <= vol.irr + 1e-12) and np.all(vol.irr <= vol.irr_hi + 1e-12)
+    # the floating cube casts shadows: some lit-side rays see occluded points
+    assert (rays["L"] == 0).any() and (rays["L"] > 0).any()
+
+
+# ---------------------------------------------------------------- blend
+def _blend_linear(O, n, s, a, c):
+    """Blend ray radiance L_j = c + a.d_j (and distance r_j the same) with
+    the oracle; compare with the exact integrals of the weighted means."""
+    cfg = _cfg(nx=1, ny=1, nz=1, rays_per_probe=n, vis_sharpness=s, fp16=False)
+    R = synth.rotation(9, 0)
+    d = O.ray_dirs(n, R)
+    val = c + d @ a
+    L = np.repeat(val[None, :, None], 3, axis=2)
+    r = val[None, :]
+    irr, vis = O.empty_maps(cfg)
+    O.blend_update(cfg, d, L, r, irr, vis, first=True)
+    wi = O.texel_dirs(cfg.irr_res)
+    wv = O.texel_dirs(cfg.vis_res)
+    # cosine lobe: E[d] = (2/3) omega; cosine^s lobe: E[d] = (s+1)/(s+2) omega
+    exp_irr = c + (2.0 / 3.0) * (wi @ a)
+    exp_vis = c + (s + 1.0) / (s + 2.0) * (wv @ a)
+    got_irr = irr[0, 0, 1:-1, 1:-1].reshape(-1)
+    got_vis = vis[0, 0, 1:-1, 1:-1].reshape(-1)
+    return np.abs(got_irr - exp_irr).max(), np.abs(got_vis - exp_vis).max()
+
+
+def test_blend_weighted_means_match_lobe_integrals(O):
+    a = np.array([0.3, -0.5, 0.8])
+    e_irr, e_vis = _blend_linear(O, 8192, 50, a, 2.0)
+    assert e_irr < 2e-3 and e_vis < 1e-2
+    # a wrong exponent would move the visibility mean by >= 0.08 |a| here
+    e_irr2, e_vis2 = _blend_linear(O, 8192, 2, a, 2.0)
+    assert e_vis2 < 2e-3
+    # convergence with n
+    e_small, _ = _blend_linear(O, 256, 50, a, 2.0)
+    assert e_irr < e_small
+
+
+def test_hysteresis_constant_estimate(O):
+    """Constant estimate e from zero-initialised maps: map_k = e (1 - h^k)
+    without the first-frame rule, and e from the first frame with it."""
+    sky = (0.5, 1.0, 2.0)
+    sc = O.OracleScene(np.zeros((0, 3, 3), np.float32), np.zeros((0, 3), np.float32))
+    h = float(np.float32(0.97))
+    skyf = np.array(sky, np.float32).astype(np.float64)
+    for flag in (False, True):
+        cfg = _cfg(sky=sky, first_frame_no_history=flag, rays_per_probe=64, hysteresis=0.97)
+        vol = O.OracleVolume(cfg)
+        for k in range(1, 6):
+            vol.update(sc, synth.rotation(10, k), np.zeros((0, 6), np.float32))
+            for c in range(3):
+                expect = skyf[c] if flag else skyf[c] * (1 - h ** k)
+                assert np.allclose(vol.irr[:, c, 1:-1, 1:-1], expect, rtol=1e-12)
+
+
+def test_fp16_maps_are_binary16_values(O):
+    cfg = synth.config("box_room")
+    cfg.fp16 = True
+    sc = synth.box_room()
+    vol = O.OracleVolume(cfg)
+    vol.update(O.OracleScene.from_scene(sc), synth.rotation(2, 0), sc.lights)
+    for m in (vol.irr, vol.vis):
+        assert np.array_equal(m, m.astype(np.float16).astype(np.float64))
+
+
+# ---------------------------------------------------------------- border
+def _bilinear(tile, N, u, w):
+    """Bilinear lookup of a guard-banded tile at octahedral coords (u, w),
+    as a texture unit would sample it."""
+    # continuous tile coordinate: tile column c spans [c, c+1); interior
+    # texel i sits in column i+1 with its centre at u = 2(i+1/2)/N - 1
+    x = (u + 1) * 0.5 * N + 1.0
+    y = (w + 1) * 0.5 * N + 1.0
+    x0, y0 = int(math.floor(x - 0.5)), int(math.floor(y - 0.5))
+    fx, fy = x - 0.5 - x0, y - 0.5 - y0
+    v00, v10 = tile[y0, x0], tile[y0, x0 + 1]
+    v01, v11 = tile[y0 + 1, x0], tile[y0 + 1, x0 + 1]
+    return (1 - fy) * ((1 - fx) * v00 + fx * v10) + fy * ((1 - fx) * v01 + fx * v11)
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_border_makes_bilinear_lookup_continuous_across_the_fold(O, N):
+    rng = np.random.default_rng(N)
+    tiles = np.zeros((3, 1, N + 2, N + 2))
+    tiles[:, :, 1:-1, 1:-1] = rng.uniform(0, 1, size=(3, 1, N, N))
+    tiles = O.border(tiles)
+    for p in range(3):
+        T = tiles[p, 0]
+        for w in rng.uniform(-1, 1, 50):
+            # (1, w) and (1, -w) are one direction; so are (w, 1) and (-w, 1)
+            assert math.isclose(_bilinear(T, N, 1.0, w), _bilinear(T, N, 1.0, -w), abs_tol=1e-12)
+            assert math.isclose(_bilinear(T, N, -1.0, w), _bilinear(T, N, -1.0, -w), abs_tol=1e-12)
+            assert math.isclose(_bilinear(T, N, w, 1.0), _bilinear(T, N, -w, 1.0), abs_tol=1e-12)
+            assert math.isclose(_bilinear(T, N, w, -1.0), _bilinear(T, N, -w, -1.0), abs_tol=1e-12)
+        corners = [_bilinear(T, N, cu, cw) for cu in (-1.0, 1.0) for cw in (-1.0, 1.0)]
+        assert np.allclose(corners, corners[0], atol=1e-12)
+        # interior untouched
+        assert np.array_equal(T[1:-1, 1:-1], tiles[p, 0, 1:-1, 1:-1])
+
+
+# ---------------------------------------------------------------- packing
+def _np_masks(cur_irr, cur_vis, ref_irr, ref_vis, tau_irr, tau_vis):
+    ci = cur_irr[:, :, 1:-1, 1:-1].reshape(cur_irr.shape[0], 3, -1)
+    cv = cur_vis[:, :, 1:-1, 1:-1].reshape(cur_vis.shape[0], 2, -1)
+
+    def changed(c, r, tau):
+        if tau == 0:
+            return (c != r).any(axis=(1, 2))
+        diff = np.abs(c.view(np.float16).astype(np.float64) - r.view(np.float16).astype(np.float64))
+        return (diff > tau).any(axis=(1, 2))
+    return changed(ci, ref_irr, tau_irr), changed(cv, ref_vis, tau_vis)
+
+
+def _parse(pkt, Ni=8, Nv=16):
+    hdr = np.frombuffer(pkt[:32], np.uint32)
+    magic, _, client, seq, P, Ki, Kv, chk = hdr
+    idx = np.frombuffer(pkt[32:32 + 2 * (Ki + Kv)], np.uint16)
+    off = 32 + ((2 * (Ki + Kv) + 15) // 16) * 16
+    pi = np.frombuffer(pkt[off:off + Ki * 6 * Ni * Ni], np.uint8).reshape(6, Ki, Ni * Ni)
+    off += Ki * 6 * Ni * Ni
+    pv = np.frombuffer(pkt[off:off + Kv * 4 * Nv * Nv], np.uint8).reshape(4, Kv, Nv * Nv)
+    assert off + Kv * 4 * Nv * Nv == len(pkt)
+    return dict(magic=magic, client=client, seq=seq, P=P, Ki=Ki, Kv=Kv, chk=chk,
+                idx_irr=np.cumsum(idx[:Ki].astype(np.int64)), idx_vis=np.cumsum(idx[Ki:].astype(np.int64)),
+                planes_irr=pi, planes_vis=pv)
+
+
+@pytest.mark.parametrize("tau", [0.0, 1.0 / 1024])
+def test_pack_matches_numpy_definition(O, tau):
+    P = 300
+    cur_i, cur_v = synth.random_fp16_maps(P, 8, 16, seed=3)
+    ref_i0, ref_v0 = synth.perturb_fp16_maps(cur_i, cur_v, seed=4, p_probe=0.4, p_texel=0.02, rel=2e-3)
+    st = O.OracleClientState(P)
+    st.ref_irr[:] = ref_i0[:, :, 1:-1, 1:-1].reshape(P, 3, -1)
+    st.ref_vis[:] = ref_v0[:, :, 1:-1, 1:-1].reshape(P, 2, -1)
+    ref_i, ref_v = st.ref_irr.copy(), st.ref_vis.copy()
+    pkt, mi, mv = st.pack(cur_i, cur_v, tau, tau)
+    ei, ev = _np_masks(cur_i, cur_v, ref_i, ref_v, tau, tau)
+    assert np.array_equal(mi, ei) and np.array_equal(mv, ev)
+    assert 0 < ei.sum() < P and 0 < ev.sum() < P
+    d = _parse(pkt)
+    assert d["magic"] == 0x4B505650 and d["P"] == P and d["Ki"] == ei.sum() and d["Kv"] == ev.sum()
+    assert np.array_equal(d["idx_irr"], np.nonzero(ei)[0]) and np.array_equal(d["idx_vis"], np.nonzero(ev)[0])
+    ci = cur_i[:, :, 1:-1, 1:-1].reshape(P, 3, -1)
+    cv = cur_v[:, :, 1:-1, 1:-1].reshape(P, 2, -1)
+    xi = (ci[ei] ^ ref_i[ei])                 # [Ki, 3, 64]
+    xv = (cv[ev] ^ ref_v[ev])
+    for c in range(3):
+        assert np.array_equal(d["planes_irr"][2 * c], (xi[:, c] & 0xff).astype(np.uint8))
+        assert np.array_equal(d["planes_irr"][2 * c + 1], (xi[:, c] >> 8).astype(np.uint8))
+    for c in range(2):
+        assert np.array_equal(d["planes_vis"][2 * c], (xv[:, c] & 0xff).astype(np.uint8))
+        assert np.array_equal(d["planes_vis"][2 * c + 1], (xv[:, c] >> 8).astype(np.uint8))
+    # reference: sent probes take the current interior, others keep theirs
+    assert np.array_equal(st.ref_irr[ei], ci[ei]) and np.array_equal(st.ref_irr[~ei], ref_i[~ei])
+    assert np.array_equal(st.ref_vis[ev], cv[ev]) and np.array_equal(st.ref_vis[~ev], ref_v[~ev])
+
+
+def test_threshold_compare_exhaustive_pairs(O):
+    """The tau > 0 decision equals the exact real comparison |a - b| > tau for
+    every finite binary16 a against sampled b (one probe per pair)."""
+    rng = np.random.default_rng(11)
+    a_bits = np.arange(0, 0x7c00, dtype=np.uint16)                # all finite non-negative
+    a_bits = np.concatenate([a_bits, a_bits | 0x8000])
+    tau = 1.0 / 1024
+    fa = a_bits.view(np.float16).astype(np.float64)
+    # partners: exactly at +-tau, one ulp around it, and random nearby values
+    cand = np.stack([fa + tau, fa - tau, fa + rng.uniform(-3, 3, fa.size) * tau,
+                     fa * (1 + rng.uniform(-1e-3, 1e-3, fa.size))], axis=1)
+    b_bits = cand[np.arange(fa.size), rng.integers(0, 4, fa.size)].astype(np.float16).view(np.uint16)
+    B = 4096
+    for s in range(0, a_bits.size, B):
+        a = a_bits[s:s + B]
+        b = b_bits[s:s + B]
+        P = a.size
+        cur_i = np.zeros((P, 3, 10, 10), np.uint16)
+        cur_v = np.zeros((P, 2, 18, 18), np.uint16)
+        cur_i[:, 1, 4, 6] = a
+        st = O.OracleClientState(P)
+        st.ref_irr[:, 1, 3 * 8 + 5] = b
+        _, mi, mv = st.pack(cur_i, cur_v, tau, tau)
+        exact = np.abs(a.view(np.float16).astype(np.float64) - b.view(np.float16).astype(np.float64)) > tau
+        assert np.array_equal(mi, exact)
+        assert not mv.any()
+
+
+def test_pack_round_trip_replay_and_checksum(O):
+    """120-frame replay: after every packet the client's interiors equal the
+    server's last-transmitted state, and with tau = 0 also the current maps;
+    guard bands are rebuilt from the interiors. A corrupted packet is refused."""
+    P = 64
+    cur_i, cur_v = synth.random_fp16_maps(P, 8, 16, seed=20)
+    st0 = O.OracleClientState(P)
+    st1 = O.OracleClientState(P)
+    cl0 = O.OracleClientDecoder(P)
+    cl1 = O.OracleClientDecoder(P)
+    for f in range(120):
+        cur_i, cur_v = synth.perturb_fp16_maps(cur_i, cur_v, seed=1000 + f, p_probe=0.2, p_texel=0.1, rel=4e-3)
+        for st, cl, tau in ((st0, cl0, 0.0), (st1, cl1, 1.0 / 1024)):
+            pkt, _, _ = st.pack(cur_i, cur_v, tau, tau)
+            assert cl.apply(pkt) == 0 and cl.seq == st.seq - 1
+            assert np.array_equal(cl.irr[:, :, 1:-1, 1:-1].reshape(P, 3, -1), st.ref_irr)
+            assert np.array_equal(cl.vis[:, :, 1:-1, 1:-1].reshape(P, 2, -1), st.ref_vis)
+        assert np.array_equal(cl0.irr[:, :, 1:-1, 1:-1], cur_i[:, :, 1:-1, 1:-1])
+        assert np.array_equal(cl0.vis[:, :, 1:-1, 1:-1], cur_v[:, :, 1:-1, 1:-1])
+    # guard bands of the client tiles equal the fold copy of their interiors
+    b = O.border(cl0.irr.view(np.float16).astype(np.float64)).astype(np.float16).view(np.uint16)
+    assert np.array_equal(b, cl0.irr)
+    # XOR is an involution: applying the same packet twice restores the state
+    cur_i2, cur_v2 = synth.perturb_fp16_maps(cur_i, cur_v, seed=5, p_probe=0.5, p_texel=0.5)
+    pkt, _, _ = st0.pack(cur_i2, cur_v2)
+    before = cl0.irr.copy()
+    assert cl0.apply(pkt) == 0
+    assert cl0.apply(pkt) == 0
+    assert np.array_equal(cl0.irr[:, :, 1:-1, 1:-1], before[:, :, 1:-1, 1:-1])
+    bad = bytearray(pkt)
+    bad[-5] ^= 0x10
+    assert cl0.apply(bytes(bad)) == -2
+
+
+def test_unchanged_state_sends_empty_packet(O):
+    P = 40
+    cur_i, cur_v = synth.random_fp16_maps(P, 8, 16, seed=7)
+    st = O.OracleClientState(P)
+    pkt, mi, mv = st.pack(cur_i, cur_v)
+    assert mi.all() and mv.all() and len(pkt) == O.packet_bytes(P, P)
+    pkt2, mi2, mv2 = st.pack(cur_i, cur_v)
+    assert not mi2.any() and not mv2.any() and len(pkt2) == 32
+    # -0 versus +0: bit patterns differ (tau = 0) but values are equal (tau > 0)
+    z_i = cur_i.copy()
+    z_i[3, 0, 1, 1] = 0x8000
+    st.ref_irr[3, 0, 0] = 0x0000
+    _, mi3, _ = st.pack(z_i, cur_v, 1.0 / 1024, 1.0 / 1024)
+    assert not mi3[3]
+    st.ref_irr[3, 0, 0] = 0x0000
+    _, mi4, _ = st.pack(z_i, cur_v, 0.0, 0.0)
+    assert mi4[3]
+
+
+# ---------------------------------------------------------------- the paper's sizes
+def _r(x, nd=0):
+    """Round half away from zero, as printed numbers are rounded."""
+    return math.floor(x * 10 ** nd + 0.5) / 10 ** nd
+
+
+def test_paper_worked_sizes():
+    g = json.load(open(os.path.join(GOLDEN, "paper_sizes.json")))
+    ni, nv, b = g["irr_texels_per_probe_side"]["value"], g["vis_texels_per_probe_side"]["value"], g["bits_per_texel"]["value"]
+    kb = 1024.0
+    irr_kb = ni * ni * b / kb
+    vis_kb = nv * nv * b / kb
+    assert irr_kb == g["irr_kb_per_probe"]["value"]
+    assert vis_kb == g["vis_kb_per_probe"]["value"]
+    assert 2048 * irr_kb / 1024 == g["irr_Mb_2048"]["value"]
+    assert _r(2048 * ni * ni * b / 8 / 2 ** 20, 2) == g["irr_MB_2048"]["value"]
+    assert 10 * 2048 * irr_kb / 1024 == g["irr_Mbps_2048_10Hz"]["value"]
+    assert _r(vis_kb / irr_kb, 2) == g["vis_over_irr_ratio"]["value"]
+    assert _r(2048 * vis_kb / 1024, 1) == g["vis_Mb_2048"]["value"]
+    assert _r(2048 * nv * nv * b / 8 / 2 ** 20, 1) == g["vis_MB_2048"]["value"]
+    assert 10 * 2048 * vis_kb / 1024 == g["vis_Mbps_2048_10Hz"]["value"]
+    assert _r(10 * 2048 * (irr_kb + vis_kb) / 1024) == g["total_Mbps_2048_10Hz"]["value"]
+    for P, mb in zip(g["uncompressed_color_MB"]["probes"], g["uncompressed_color_MB"]["value"]):
+        assert _r(P * ni * ni * b / 8 / 2 ** 20, 2) == mb
+    for P, mb in zip(g["uncompressed_vis_MB"]["probes"], g["uncompressed_vis_MB"]["value"]):
+        assert _r(P * nv * nv * b / 8 / 2 ** 20, 2) == mb
+    # guard-band removal: the interiors (8x8, 16x16) are what the packet carries
+    assert _r(100 * (1 - 8 * 8 / (ni * ni))) == g["guard_band_drop_irr_pct"]["value"]
+    assert _r(100 * (1 - 16 * 16 / (nv * nv))) == g["guard_band_drop_vis_pct"]["value"]
+
+
+def test_packet_sizes_follow_the_layout(O):
+    g = json.load(open(os.path.join(GOLDEN, "paper_sizes.json")))
+    ib = g["index_bytes_per_probe"]["value"]
+    for Ki, Kv in ((0, 0), (1, 0), (0, 1), (7, 3), (2048, 2048)):
+        idx = ((ib * (Ki + Kv) + 15) // 16) * 16
+        assert O.packet_bytes(Ki, Kv) == 32 + idx + Ki * 8 * 8 * 3 * 2 + Kv * 16 * 16 * 2 * 2
