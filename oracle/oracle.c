@@ -743,11 +743,15 @@ OR_API void or_border(int P, int C, int N, double *tiles)
  * est_irr[t][c] = sum_j w_tj L_jc / sum_j w_tj,      w_tj = max(0, omega_t . d_j)
  * est_vis[t]    = (sum_j v_tj r_j, sum_j v_tj r_j^2) / sum_j v_tj,  v_tj = w_tj^s
  * new = h*old + (1-h)*est (h = 0 on the first frame when requested); a texel
- * whose weight sum is zero keeps its old value. With fp16 set each new value
+ * whose weight sum is at most OR_WEIGHT_FLOOR keeps its old value (no ray
+ * lies in its lobe to any useful degree; the floor sits far above where FP32
+ * weights underflow, so the decision does not depend on precision). With fp16 set each new value
  * is rounded to binary16 (ties to even) before it is stored. Then the guard
  * bands are rebuilt.
  * irr: [P][3][Ni+2][Ni+2], vis: [P][2][Nv+2][Nv+2], updated in place.
  */
+#define OR_WEIGHT_FLOOR 1e-20
+
 OR_API void or_blend_update(const or_volume *v, const double *dirs, const double *L, const double *r, int first,
                             int fp16, double *irr, double *vis, int nthreads)
 {
@@ -777,7 +781,7 @@ OR_API void or_blend_update(const or_volume *v, const double *dirs, const double
             int i = t % Ni, jj = t / Ni;
             for (int ch = 0; ch < 3; ++ch) {
                 double *dst = irr + (((int64_t)p * 3 + ch) * Si + (jj + 1)) * Si + (i + 1);
-                if (ws > 0.0) {
+                if (ws > OR_WEIGHT_FLOOR) {
                     double nv = h * (*dst) + (1.0 - h) * (acc[ch] / ws);
                     *dst = fp16 ? or_half_to_double(or_double_to_half(nv)) : nv;
                 }
@@ -797,7 +801,7 @@ OR_API void or_blend_update(const or_volume *v, const double *dirs, const double
             double est[2] = {a1 / ws, a2 / ws};
             for (int ch = 0; ch < 2; ++ch) {
                 double *dst = vis + (((int64_t)p * 2 + ch) * Sv + (jj + 1)) * Sv + (i + 1);
-                if (ws > 0.0) {
+                if (ws > OR_WEIGHT_FLOOR) {
                     double nv = h * (*dst) + (1.0 - h) * est[ch];
                     *dst = fp16 ? or_half_to_double(or_double_to_half(nv)) : nv;
                 }

@@ -290,6 +290,32 @@ def test_blend_weighted_means_match_lobe_integrals(O):
     assert e_irr < e_small
 
 
+def test_single_ray_blend_is_that_ray_or_the_old_value(O):
+    """One ray: every texel whose lobe holds the ray takes that ray's value
+    exactly (the weighted mean of one sample); texels whose weight sum is
+    at most the floor (1e-20) keep their old value."""
+    cfg = _cfg(nx=1, ny=1, nz=1, rays_per_probe=1, fp16=False)
+    R = synth.rotation(12, 3)
+    d = O.ray_dirs(1, R)
+    L = np.array([[[0.25, 0.5, 0.75]]])
+    r = np.array([[1.5]])
+    irr, vis = O.empty_maps(cfg)
+    irr[:] = 9.0
+    vis[:] = 9.0
+    O.blend_update(cfg, d, L, r, irr, vis, first=True)
+    ci = O.texel_dirs(8) @ d[0]
+    cv = O.texel_dirs(16) @ d[0]
+    gi = irr[0, :, 1:-1, 1:-1].reshape(3, -1)
+    gv = vis[0, :, 1:-1, 1:-1].reshape(2, -1)
+    for c in range(3):
+        assert np.allclose(gi[c][ci > 1e-20], L[0, 0, c], rtol=1e-14)
+        assert np.all(gi[c][ci <= 0] == 9.0)
+    lobe = np.maximum(cv, 0) ** 50 > 1e-20
+    assert lobe.any() and (~lobe).any()
+    assert np.allclose(gv[0][lobe], 1.5, rtol=1e-14) and np.allclose(gv[1][lobe], 2.25, rtol=1e-14)
+    assert np.all(gv[:, ~lobe] == 9.0)
+
+
 def test_hysteresis_constant_estimate(O):
     """Constant estimate e from zero-initialised maps: map_k = e (1 - h^k)
     without the first-frame rule, and e from the first frame with it."""
