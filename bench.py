@@ -1,0 +1,212 @@
+"""Benchmark of the probe-volume hot path on one MI355X.
+
+One step = one pass of the whole path on the at-scale workload: the
+16x8x16-probe volume (2048 probes, 256 rays per probe) over the procedural
+50k-triangle city, FP16 maps with FP32 arithmetic, light moving on its
+spline; the step updates the volume (ray directions, trace + shade, blend +
+hysteresis + guard bands) and packs the delta for one client (change mask,
+ordered compaction, XOR byte planes, index buffer, reference update), all on
+the device. Inputs are resident in HBM before timing starts.
+
+Prints one JSON line. ``value`` is primary probe-rays per second; the line
+also carries probes/s, per-stage kernel times measured with HIP events on the
+launch stream, the roofline of the dominant kernel (the trace), and the FP64
+oracle timed on the host cores on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "probe-rays/s and probes updated/s at 1 GPU (plain vs batched/served); p50/p99 latency"
+
+# Algorithmic FP32 work of the traversal (FMA = 2, add/mul/min/max/compare = 1):
+# one node visit tests two child boxes (12 FMA, 16 min/max, 2 compares);
+# one triangle test (two crosses, four dots, a reciprocal, compares).
+FLOP_PER_NODE_VISIT = 42
+FLOP_PER_TRI_TEST = 52
+PEAK_FP32_VECTOR = 157.3e12        # MI355X published FP32 vector peak (FLOP/s)
+PEAK_HBM = 8.0e12                  # MI355X published HBM3E bandwidth (B/s)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, scene, path, budget_s: float):
+    """The oracle as it stands on the host cores: full frames of the same
+    workload (trace + shade, blend, pack), as many as fit the budget
+    (at least one)."""
+    import numpy as np
+
+    import oracle
+    import synth
+    osc = oracle.OracleScene.from_scene(scene)
+    irr, vis = oracle.empty_maps(cfg)
+    st = oracle.OracleClientState(cfg.n_probes)
+    frames = 0
+    t0 = time.perf_counter()
+    while True:
+        R = synth.rotation(13, frames)
+        lights = scene.lights.copy()
+        lights[0, :3] = path[frames % len(path)]
+        rays = oracle.trace_shade(osc, cfg, R, lights, bounds=False)
+        oracle.blend_update(cfg, oracle.ray_dirs(cfg.rays_per_probe, R), rays["L"], rays["r"], irr, vis,
+                            first=(frames == 0))
+        bi = irr.astype(np.float16).view(np.uint16)
+        bv = vis.astype(np.float16).view(np.uint16)
+        st.pack(bi, bv)
+        frames += 1
+        if time.perf_counter() - t0 > budget_s or frames >= 50:
+            break
+    dt = time.perf_counter() - t0
+    rays_total = frames * cfg.n_probes * cfg.rays_per_probe
+    return {"value": rays_total / dt, "unit": "probe-rays/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "probes_per_s": frames * cfg.n_probes / dt,
+            "sample": f"{frames} full frame(s) of the same workload (trace + shade, blend, pack), "
+                      f"{dt:.1f} s wall, OpenMP over probes"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the hot path has no cross-GPU exchange; see DESIGN.md for how it shards)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2103_05875_amd as ps
+
+    cfg = synth.config("city")
+    scene = synth.box_city()
+    K, W = args.steps, args.warmup
+    path = synth.light_path(12, 60)
+    frames = []
+    for f in range(K + W):
+        l = scene.lights.copy()
+        l[0, :3] = path[f % 60]
+        frames.append((synth.rotation(13, f), l))
+
+    print(f"bench: city workload, {cfg.n_probes} probes x {cfg.rays_per_probe} rays, "
+          f"{scene.n_triangles} triangles; warmup {W}, steps {K}", file=sys.stderr, flush=True)
+    ctx = ps.Context(0)
+    sc = ps.Scene.from_synth(ctx, scene)
+    vol = ps.Volume(ctx, cfg)
+    vol.set_scene(sc)
+    cl = ps.Client(vol, client_id=0)
+    stream = torch.cuda.current_stream()
+
+    def step(i):
+        R, l = frames[i]
+        vol.update_probes(R, l, stream=stream)
+        cl.pack_delta(0.0, 0.0, stream=stream)
+
+    for i in range(W):
+        step(i)
+    torch.cuda.synchronize()
+
+    # timed region (clean: no instrumentation)
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for i in range(W, W + K):
+        step(i)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    gpu_ms = t_start.elapsed_time(t_end)
+    ms_per_step = max(gpu_ms, wall * 1e3) / K
+    rays = cfg.n_probes * cfg.rays_per_probe
+    value = rays * K / (ms_per_step * K / 1e3)
+    print(f"bench: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # same steps again with every kernel bracketed by HIP events on its stream
+    ctx.set_timing(True)
+    ctx.stage_times()
+    for i in range(W, W + K):
+        step(i)
+    torch.cuda.synchronize()
+    stages = ctx.stage_times()
+    ctx.set_timing(False)
+    stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
+
+    # algorithmic traversal work of the same frames (instrumented trace)
+    node_visits = tri_tests = shadow = 0
+    for i in range(W, W + K):
+        c = vol.trace_counts(*frames[i])
+        node_visits += c["node_visits"]
+        tri_tests += c["tri_tests"]
+        shadow += c["shadow_rays"]
+    flop_per_launch = (node_visits * FLOP_PER_NODE_VISIT + tri_tests * FLOP_PER_TRI_TEST) / K
+    trace_s = stage_ms["trace"] / 1e3
+    achieved = flop_per_launch / trace_s if trace_s > 0 else 0.0
+
+    # HBM figures of the blend and pack kernels (algorithmic bytes)
+    P, n = cfg.n_probes, cfg.rays_per_probe
+    blend_bytes = P * (16 * n + (192 + 512) * 2 + (300 + 648) * 2)
+    blend_flop = P * 1408 * n
+    mi, mv = cl.read_masks()
+    k_changed = (int(mi.sum()) + int(mv.sum())) / 2.0
+    pack_bytes = P * 1408 * 2 + (int(mi.sum()) * 384 + int(mv.sum()) * 1024) * 2 + P * 2
+    pack_ms = stage_ms["pack_mask"] + stage_ms["pack_scan"] + stage_ms["pack_compact"]
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "probe-rays/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "city: 16x8x16 probes, 256 rays/probe, 50k-triangle procedural city, FP16 maps, "
+                               "moving light; step = full update + delta pack for one client (tau = 0)",
+                   "probes": P, "rays_per_probe": n, "triangles": scene.n_triangles},
+        "probes_per_s": P * 1e3 / ms_per_step,
+        "stage_ms": stage_ms,
+        "roofline": {"bound": "alu", "kernel": "k_trace", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+                     "flop_per_launch": flop_per_launch, "node_visits_per_ray": node_visits / (K * rays),
+                     "tri_tests_per_ray": tri_tests / (K * rays), "shadow_rays_per_ray": shadow / (K * rays)},
+        "blend": {"ms": stage_ms["blend"], "hbm_GBps": blend_bytes / (stage_ms["blend"] / 1e3) / 1e9 if stage_ms["blend"] else None,
+                  "hbm_frac": blend_bytes / (stage_ms["blend"] / 1e3) / PEAK_HBM if stage_ms["blend"] else None,
+                  "alu_frac": blend_flop / (stage_ms["blend"] / 1e3) / PEAK_FP32_VECTOR if stage_ms["blend"] else None},
+        "pack": {"ms": pack_ms, "changed_probes": k_changed,
+                 "hbm_GBps": pack_bytes / (pack_ms / 1e3) / 1e9 if pack_ms else None,
+                 "hbm_frac": pack_bytes / (pack_ms / 1e3) / PEAK_HBM if pack_ms else None},
+        "paper_context": "5.63 ms per full-volume update (mean of 2048/4096/8192-probe scenes, 256 rays/probe) on a "
+                         "Quadro RTX 8000 with RT cores, i.e. about 0.22 G probe-rays/s and 0.85 M probes/s; "
+                         "different scenes and hardware, so not a ratio",
+    }
+    if not args.no_cpu_baseline:
+        print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, scene, path, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    for h in (cl, vol, sc, ctx):
+        h.close()
+
+
+if __name__ == "__main__":
+    main()

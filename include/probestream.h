@@ -1,0 +1,273 @@
+/*
+ * probestream.h -- C ABI of the MI355X (gfx950) probe-volume update and
+ * lossless delta-pack library.
+ *
+ * The operations follow "A Distributed, Decoupled System for Losslessly
+ * Streaming Dynamic Light Probes to Thin Clients" (Stengel et al. 2021):
+ *
+ *   - a GI server computes view-independent probe textures from the current
+ *     scene state (Section 3.1, architecture overview): pv_update_probes;
+ *   - each probe holds an octahedral irradiance map (8x8 interior texels in a
+ *     10x10 tile) and a visibility map of mean distance and mean squared
+ *     distance (16x16 interior in an 18x18 tile) (Section 3.2, Eq. 1 and
+ *     Eq. 2 and the visibility paragraph); the update itself is the
+ *     irradiance-volume method the paper adopts (Section 3.2, first
+ *     paragraph): rays per probe, closest hit, shading, cosine-weighted blend
+ *     with hysteresis, guard-band copy;
+ *   - for each client the server keeps last-transmitted textures, selects the
+ *     probes that changed (Section 3.4, change thresholding), drops the
+ *     guard bands and sends an index-based update with a delta-coded 2-byte
+ *     probe index buffer (Section 3.4, repacking and update textures), with
+ *     every FP16 value split into its two bytes (Section 3.3, visibility
+ *     encoding): pv_pack_delta.
+ *
+ * Conventions
+ *   - Every call returns a pv_status; outputs are written only on PV_OK and
+ *     pv_last_error() (thread-local) describes the last failure.
+ *   - Work is enqueued asynchronously on the given HIP stream (a
+ *     hipStream_t passed as void*; NULL means the context's own stream).
+ *     Device faults surface as PV_ERR_DEVICE at the next pv_sync or
+ *     blocking call.
+ *   - The library owns every handle and all device memory (maps, client
+ *     references, BVHs, ray buffers, packets). Host arrays passed in are
+ *     copied before the call returns and never retained. Device pointers
+ *     handed out (pv_get_maps, pv_get_rays, pv_packet_device) are borrowed:
+ *     valid until the handle is destroyed, contents valid until the next
+ *     update / pack on that handle.
+ *   - Handles are not thread-safe. Different volumes may be updated on
+ *     different streams concurrently; a scene may be shared by volumes.
+ *   - destroy(NULL) is PV_OK.
+ */
+#ifndef PROBESTREAM_H
+#define PROBESTREAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* every entry point below is exported from the shared library */
+#pragma GCC visibility push(default)
+
+typedef struct pv_ctx pv_ctx;
+typedef struct pv_scene pv_scene;
+typedef struct pv_volume pv_volume;
+typedef struct pv_client pv_client;
+
+typedef enum {
+    PV_OK = 0,
+    PV_ERR_ARG = -1,         /* invalid argument (message says which) */
+    PV_ERR_OOM = -2,         /* device or host allocation failed */
+    PV_ERR_DEVICE = -3,      /* HIP runtime / device error */
+    PV_ERR_STATE = -4,       /* call not valid in the handle's state */
+    PV_ERR_CAPACITY = -5,    /* caller buffer or memory budget too small */
+    PV_ERR_UNSUPPORTED = -6  /* valid request this build does not implement */
+} pv_status;
+
+typedef enum { PV_MAP_FP32 = 0, PV_MAP_FP16 = 1 } pv_map_format;
+
+/* pv_volume_desc.flags */
+#define PV_FIRST_FRAME_NO_HISTORY 1u /* first update of a volume uses h = 0 */
+#define PV_KEEP_HITS 2u              /* keep the hit triangle id of every ray */
+
+#define PV_MAX_LIGHTS 8
+#define PV_MAX_PROBES 65536          /* the 2-byte probe index (Section 3.4) */
+#define PV_MAX_RAYS 4096
+
+/*
+ * A regular probe grid. Probe p = x + nx*(y + ny*z) sits at
+ * origin + spacing * (x, y, z). Ray directions: a spherical-Fibonacci set of
+ * rays_per_probe directions under the frame's rotation, shared by every probe.
+ * Maps: irradiance tiles [P][3][irr_res+2][irr_res+2] and visibility tiles
+ * [P][2][vis_res+2][vis_res+2] (channel-planar, row-major, 1-texel guard
+ * band), FP32 or FP16 storage, FP32 arithmetic. This build supports
+ * irr_res = 8 and vis_res = 16 (the paper's 10x10 and 18x18 tiles).
+ */
+typedef struct {
+    int nx, ny, nz;
+    float origin[3], spacing[3];
+    int rays_per_probe;      /* 1 .. PV_MAX_RAYS */
+    int irr_res, vis_res;    /* 8, 16 */
+    float hysteresis;        /* h in [0, 1): new = h*old + (1-h)*estimate */
+    float max_distance;      /* distances are clamped to this (> 0) */
+    int vis_sharpness;       /* visibility weight = max(0, cos)^s, s in [1, 128] */
+    pv_map_format format;
+    float sky[3];            /* radiance of rays that leave the scene */
+    uint32_t flags;          /* PV_FIRST_FRAME_NO_HISTORY | PV_KEEP_HITS */
+} pv_volume_desc;
+
+typedef struct {
+    float pos[3];
+    float intensity[3];      /* radiant intensity (inverse-square falloff) */
+} pv_point_light;
+
+/*
+ * Triangle scene. positions: n_vertices*3 floats; indices: n_triangles*3;
+ * albedo: n_triangles*3 (diffuse reflectance per triangle); emission:
+ * n_triangles*3 or NULL. The last n_dynamic_triangles triangles may be moved
+ * per frame with pv_scene_set_dynamic. lights: the default lights of a
+ * frame that passes none. Triangles are two-sided.
+ */
+typedef struct {
+    int n_vertices;
+    const float *positions;
+    int n_triangles;
+    const uint32_t *indices;
+    const float *albedo;
+    const float *emission;
+    int n_dynamic_triangles;
+    int n_lights;
+    const pv_point_light *lights;
+} pv_scene_desc;
+
+/* Per-frame input: the ray-set rotation (row-major 3x3, a proper rotation)
+ * and the point lights (n_lights = 0 and lights = NULL: the scene's). */
+typedef struct {
+    float rotation[9];
+    int n_lights;
+    const pv_point_light *lights;
+} pv_frame;
+
+const char *pv_last_error(void);
+const char *pv_version(void);
+
+/* Context bound to one HIP device; owns a default stream. */
+pv_status pv_ctx_create(int hip_device, pv_ctx **out);
+pv_status pv_ctx_destroy(pv_ctx *ctx);
+
+/*
+ * Copies the scene to the device and builds its BVH on the host (binned
+ * surface-area heuristic). Inputs must be finite and indices < n_vertices.
+ * The shadow-ray offset is 1e-4 times the diagonal of the bounding box of
+ * the static triangles.
+ */
+pv_status pv_scene_create(pv_ctx *ctx, const pv_scene_desc *desc, pv_scene **out);
+/* New positions (n_dynamic_triangles*9 floats, host) of the dynamic
+ * triangles, in effect for work enqueued on 'stream' after this call. */
+pv_status pv_scene_set_dynamic(pv_scene *scene, const float *positions, void *stream);
+pv_status pv_scene_destroy(pv_scene *scene);
+
+/* Maps zeroed, frame counter 0. */
+pv_status pv_create_volume(pv_ctx *ctx, const pv_volume_desc *desc, pv_volume **out);
+pv_status pv_volume_destroy(pv_volume *vol);
+/* Device bytes pv_create_volume would allocate for desc (admission). */
+pv_status pv_volume_footprint(const pv_volume_desc *desc, uint64_t *bytes);
+pv_status pv_set_scene(pv_volume *vol, pv_scene *scene);
+
+/*
+ * One full update (async): ray directions, trace + shade every
+ * (probe, ray), blend both maps with hysteresis, rebuild guard bands.
+ * A texel whose weight sum over the rays is at most 1e-20 keeps its value.
+ * Ray records are kept in the volume's ray buffer (pv_get_rays).
+ */
+pv_status pv_update_probes(pv_volume *vol, const pv_frame *frame, void *stream);
+
+/*
+ * The same update for n volumes in one go: one ray-direction launch, one
+ * persistent trace-and-blend launch whose work queue covers every volume
+ * (each volume's blend starts when its own rays are done), enqueued on
+ * 'stream'. Results are bit-identical to n pv_update_probes calls.
+ */
+pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_frame *frames, int n, void *stream);
+
+/*
+ * Blend + hysteresis + guard bands from externally supplied ray records
+ * (device pointer, [P][rays_per_probe] x float4 {L.r, L.g, L.b, distance}),
+ * with the directions of 'frame'. Advances the frame counter like an update.
+ */
+pv_status pv_blend_rays(pv_volume *vol, const pv_frame *frame, const void *rays_dev, void *stream);
+
+/* Borrowed device pointers to the current tiles (layout in pv_volume_desc). */
+pv_status pv_get_maps(pv_volume *vol, void **irr_dev, void **vis_dev);
+/* Borrowed device pointers: ray records [P][n] float4, hit triangle ids
+ * [P][n] int32 (-1 = miss; NULL unless PV_KEEP_HITS), directions [n] float4. */
+pv_status pv_get_rays(pv_volume *vol, void **rays_dev, void **hits_dev, void **dirs_dev);
+/* Replace the maps from host memory (checkpoint import) and set the frame
+ * counter; synchronous. */
+pv_status pv_set_maps(pv_volume *vol, const void *irr_host, const void *vis_host, int64_t frame);
+/* Copy the maps to host memory (checkpoint export); synchronous. */
+pv_status pv_read_maps(pv_volume *vol, void *irr_host, void *vis_host, int64_t *frame);
+
+/*
+ * Per-client server state: last-transmitted interiors (all-zero bits at
+ * creation, i.e. the first pack sends every probe that is not all zero) and
+ * a device packet buffer sized for a full update. FP16 volumes only.
+ */
+pv_status pv_client_create(pv_volume *vol, uint32_t client_id, pv_client **out);
+pv_status pv_client_destroy(pv_client *client);
+/* Zero the client's reference: the next pack resends everything (as a
+ * video I-frame would after loss). */
+pv_status pv_client_reset(pv_client *client, void *stream);
+pv_status pv_client_footprint(const pv_volume_desc *desc, uint64_t *bytes);
+
+/*
+ * Build the client's next packet on the device (async) from the volume's
+ * current maps. A probe is sent for a texture when any interior texel
+ * differs from the client's reference: bit pattern differs (tau = 0), or
+ * |cur - ref| > tau exactly (tau > 0). Sent probes are written to the
+ * reference. Packet layout (little endian):
+ *   header 32 B: u32 magic 0x4B505650 ("PVPK"), u16 version 1, u16 32,
+ *                u32 client, u32 seq, u32 P, u32 K_irr, u32 K_vis,
+ *                u32 checksum
+ *   index: K_irr then K_vis u16 entries, delta coded (first = probe index,
+ *          then difference to the previous sent probe), zero padded to a
+ *          multiple of 16 bytes
+ *   irradiance planes (R lo, R hi, G lo, G hi, B lo, B hi), each K_irr*64
+ *          bytes: byte k*64 + t = that byte of cur XOR ref for the k-th sent
+ *          probe, interior texel t = row*8 + column
+ *   visibility planes (mean lo, mean hi, mean^2 lo, mean^2 hi), K_vis*256 B
+ *   checksum = sum over payload u32 words w_i (i from 0 after the header) of
+ *          fmix32(w_i ^ (i * 0x9E3779B9)) mod 2^32 (MurmurHash3 finaliser).
+ * seq counts the client's packs from 0.
+ */
+pv_status pv_pack_delta(pv_client *client, float tau_irr, float tau_vis, void *stream);
+/* Borrowed device pointer to the packet buffer and its capacity. */
+pv_status pv_packet_device(pv_client *client, const void **packet_dev, uint64_t *capacity);
+/* Synchronous: wait for the last pack on 'stream', copy only the packet's
+ * bytes to host_buf. PV_ERR_CAPACITY with *bytes = needed size when cap is
+ * too small. */
+pv_status pv_packet_download(pv_client *client, void *host_buf, uint64_t cap, uint64_t *bytes, void *stream);
+/* Changed-probe masks of the last pack (device, [P] uint8 each). */
+pv_status pv_get_masks(pv_client *client, void **mask_irr_dev, void **mask_vis_dev);
+
+/* Wait for the stream (NULL: the whole device); report asynchronous device
+ * errors. */
+pv_status pv_sync(void *stream);
+/* Synchronous: status word of the batched work queue, 0 when every bounded
+ * wait of the persistent launch completed, 1 when one expired (its result
+ * is then invalid). */
+pv_status pv_ctx_check(pv_ctx *ctx, int *status);
+
+/* Kernel stages that can be timed with HIP events. */
+typedef enum {
+    PV_STAGE_RAYDIRS = 0,
+    PV_STAGE_TRACE = 1,
+    PV_STAGE_BLEND = 2,
+    PV_STAGE_PACK_MASK = 3,
+    PV_STAGE_PACK_SCAN = 4,
+    PV_STAGE_PACK_COMPACT = 5,
+    PV_STAGE_BATCHED = 6,
+    PV_STAGE_COUNT = 7
+} pv_stage;
+
+/* When enabled, every kernel launch of the context is bracketed by a pair
+ * of HIP events recorded on the launch stream. */
+pv_status pv_ctx_set_timing(pv_ctx *ctx, int enable);
+/* Synchronous: total milliseconds and launch counts per stage since the
+ * previous call (which are then reset). Arrays of PV_STAGE_COUNT. */
+pv_status pv_ctx_stage_times(pv_ctx *ctx, double *ms, uint64_t *launches);
+
+/* Instrumented trace of one frame (for measurement): the same work as
+ * pv_update_probes with per-ray counts of box-pair and triangle tests,
+ * summed into counts[0] (node visits, two boxes each), counts[1] (triangle
+ * tests), counts[2] (shadow rays). Synchronous. */
+pv_status pv_trace_counts(pv_volume *vol, const pv_frame *frame, uint64_t counts[3]);
+
+#pragma GCC visibility pop
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PROBESTREAM_H */

@@ -1,0 +1,319 @@
+// Host BVH builder: binned surface-area heuristic over triangle centroids,
+// binary tree, flattened into 64-byte two-box nodes for the GPU traversal.
+//
+// Depth is bounded by kMaxDepth (the traversal's stack size): a node whose
+// remaining depth budget is tight switches to balanced median splits.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace pv {
+namespace {
+
+struct Box {
+    float lo[3], hi[3];
+    void reset() {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = INFINITY;
+            hi[k] = -INFINITY;
+        }
+    }
+    void grow(const float *p) {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], p[k]);
+            hi[k] = std::max(hi[k], p[k]);
+        }
+    }
+    void grow(const Box &b) {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], b.lo[k]);
+            hi[k] = std::max(hi[k], b.hi[k]);
+        }
+    }
+    bool empty() const { return !(lo[0] <= hi[0]); }
+    float half_area() const {
+        if (empty()) return 0.f;
+        float dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+        return dx * dy + dy * dz + dz * dx;
+    }
+};
+
+struct Ref {
+    Box box;
+    float c[3];
+    int tri;
+};
+
+struct BNode {
+    Box box;
+    int left = -1, right = -1;
+    int first = 0, count = 0;  // leaf range in refs
+};
+
+int levels_needed(int count) {
+    int leaves = (count + kLeafMax - 1) / kLeafMax;
+    int d = 0;
+    while ((1 << d) < leaves) ++d;
+    return d;
+}
+
+class Builder {
+  public:
+    Builder(std::vector<Ref> &refs) : refs_(refs) {}
+
+    int build(int first, int count, int depth) {
+        int id = (int)nodes_.size();
+        nodes_.emplace_back();
+        Box box, cbox;
+        box.reset();
+        cbox.reset();
+        for (int i = first; i < first + count; ++i) {
+            box.grow(refs_[i].box);
+            cbox.grow(refs_[i].c);
+        }
+        nodes_[id].box = box;
+        max_depth_ = std::max(max_depth_, depth);
+        if (count <= 1 || (count <= kLeafMax && prefer_leaf(first, count, box))) {
+            make_leaf(id, first, count);
+            return id;
+        }
+        int mid = -1;
+        bool tight = depth + levels_needed(count) + 1 >= kMaxDepth;
+        if (!tight) mid = sah_split(first, count, box, cbox);
+        if (mid <= first || mid >= first + count) mid = median_split(first, count, cbox);
+        int l = build(first, mid - first, depth + 1);
+        int r = build(mid, first + count - mid, depth + 1);
+        nodes_[id].left = l;
+        nodes_[id].right = r;
+        return id;
+    }
+
+    std::vector<BNode> nodes_;
+    int max_depth_ = 0;
+
+  private:
+    void make_leaf(int id, int first, int count) {
+        nodes_[id].first = first;
+        nodes_[id].count = count;
+    }
+
+    bool prefer_leaf(int first, int count, const Box &box) {
+        // leaf cost N against the best binned split; small leaves are kept
+        // when splitting does not pay
+        if (count <= 2) return true;
+        Box cb;
+        cb.reset();
+        for (int i = first; i < first + count; ++i) cb.grow(refs_[i].c);
+        float best;
+        int axis, bin;
+        if (!best_bin(first, count, box, cb, best, axis, bin)) return true;
+        return (float)count <= best;
+    }
+
+    static constexpr int kBins = 16;
+
+    bool best_bin(int first, int count, const Box &box, const Box &cbox, float &best_cost, int &best_axis,
+                  int &best_split) {
+        best_cost = INFINITY;
+        best_axis = -1;
+        best_split = -1;
+        float parent = box.half_area();
+        if (parent <= 0.f) parent = 1.f;
+        for (int a = 0; a < 3; ++a) {
+            float ext = cbox.hi[a] - cbox.lo[a];
+            if (!(ext > 0.f)) continue;
+            Box bb[kBins];
+            int bn[kBins] = {0};
+            for (int b = 0; b < kBins; ++b) bb[b].reset();
+            float scale = kBins / ext;
+            for (int i = first; i < first + count; ++i) {
+                int b = (int)((refs_[i].c[a] - cbox.lo[a]) * scale);
+                b = std::min(std::max(b, 0), kBins - 1);
+                bb[b].grow(refs_[i].box);
+                bn[b]++;
+            }
+            float right_area[kBins];
+            int right_n[kBins];
+            Box acc;
+            acc.reset();
+            int n = 0;
+            for (int b = kBins - 1; b > 0; --b) {
+                acc.grow(bb[b]);
+                n += bn[b];
+                right_area[b] = acc.half_area();
+                right_n[b] = n;
+            }
+            acc.reset();
+            n = 0;
+            for (int b = 0; b < kBins - 1; ++b) {
+                acc.grow(bb[b]);
+                n += bn[b];
+                int nr = right_n[b + 1];
+                if (n == 0 || nr == 0) continue;
+                float cost = 1.0f + (acc.half_area() * n + right_area[b + 1] * nr) / parent;
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best_axis = a;
+                    best_split = b;
+                }
+            }
+        }
+        return best_axis >= 0;
+    }
+
+    int sah_split(int first, int count, const Box &box, const Box &cbox) {
+        float cost;
+        int axis, split;
+        if (!best_bin(first, count, box, cbox, cost, axis, split)) return -1;
+        float ext = cbox.hi[axis] - cbox.lo[axis];
+        float scale = kBins / ext;
+        auto it = std::partition(refs_.begin() + first, refs_.begin() + first + count, [&](const Ref &r) {
+            int b = (int)((r.c[axis] - cbox.lo[axis]) * scale);
+            b = std::min(std::max(b, 0), kBins - 1);
+            return b <= split;
+        });
+        return (int)(it - refs_.begin());
+    }
+
+    int median_split(int first, int count, const Box &cbox) {
+        int axis = 0;
+        for (int a = 1; a < 3; ++a)
+            if (cbox.hi[a] - cbox.lo[a] > cbox.hi[axis] - cbox.lo[axis]) axis = a;
+        int mid = first + count / 2;
+        std::nth_element(refs_.begin() + first, refs_.begin() + mid, refs_.begin() + first + count,
+                         [&](const Ref &x, const Ref &y) {
+                             if (x.c[axis] != y.c[axis]) return x.c[axis] < y.c[axis];
+                             return x.tri < y.tri;
+                         });
+        return mid;
+    }
+
+    std::vector<Ref> &refs_;
+};
+
+float bits_as_float(int v) {
+    float f;
+    std::memcpy(&f, &v, 4);
+    return f;
+}
+
+}  // namespace
+
+bool build_bvh(const float *tri9, int n, int id_base, HostBvh &out, std::string &err) {
+    out.nodes.clear();
+    out.tris.clear();
+    out.depth = 0;
+    if (n <= 0) return true;
+    std::vector<Ref> refs(n);
+    Box scene;
+    scene.reset();
+    for (int i = 0; i < n; ++i) {
+        const float *t = tri9 + 9 * (size_t)i;
+        for (int k = 0; k < 9; ++k)
+            if (!std::isfinite(t[k])) {
+                err = "triangle " + std::to_string(i) + " has a non-finite coordinate";
+                return false;
+            }
+        refs[i].box.reset();
+        for (int v = 0; v < 3; ++v) refs[i].box.grow(t + 3 * v);
+        for (int k = 0; k < 3; ++k) refs[i].c[k] = (t[k] + t[3 + k] + t[6 + k]) / 3.0f;
+        refs[i].tri = i;
+        scene.grow(refs[i].box);
+    }
+    Builder b(refs);
+    b.build(0, n, 0);
+    out.depth = b.max_depth_;
+    if (out.depth > kMaxDepth) {
+        err = "BVH depth exceeds the traversal stack";
+        return false;
+    }
+    // conservative padding of child boxes (rounding of the slab test)
+    float diag = 0.f;
+    for (int k = 0; k < 3; ++k) diag += (scene.hi[k] - scene.lo[k]) * (scene.hi[k] - scene.lo[k]);
+    diag = std::sqrt(diag);
+    const float pad_abs = diag * 9.5367431640625e-7f;  // 2^-20 of the extent
+
+    // triangles in leaf order
+    out.tris.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const float *t = tri9 + 9 * (size_t)refs[i].tri;
+        GpuTri g;
+        g.v0 = make_float4(t[0], t[1], t[2], bits_as_float(id_base + refs[i].tri));
+        g.e1 = make_float4(t[3] - t[0], t[4] - t[1], t[5] - t[2], 0.f);
+        g.e2 = make_float4(t[6] - t[0], t[7] - t[1], t[8] - t[2], 0.f);
+        out.tris[i] = g;
+    }
+
+    // flatten: GPU nodes are the inner nodes in depth-first preorder
+    const std::vector<BNode> &bn = b.nodes_;
+    std::vector<int> gpu_id(bn.size(), -1);
+    std::vector<int> order;
+    std::vector<int> stack = {0};
+    if (bn[0].count > 0) {
+        // a single leaf: wrap it in one inner node with an empty slot
+        order.push_back(0);
+    } else {
+        while (!stack.empty()) {
+            int id = stack.back();
+            stack.pop_back();
+            if (bn[id].count > 0) continue;
+            gpu_id[id] = (int)order.size();
+            order.push_back(id);
+            stack.push_back(bn[id].right);
+            stack.push_back(bn[id].left);
+        }
+    }
+    auto padded = [&](const Box &bx, int k, bool hi) {
+        float v = hi ? bx.hi[k] : bx.lo[k];
+        float pad = pad_abs + std::fabs(v) * 2.384185791015625e-7f;  // + 2^-22 relative
+        return hi ? v + pad : v - pad;
+    };
+    out.nodes.resize(order.size());
+    for (size_t g = 0; g < order.size(); ++g) {
+        const BNode &nd = bn[order[g]];
+        int ch[2], cnt[2];
+        Box cb[2];
+        if (nd.count > 0) {  // single-leaf root
+            ch[0] = nd.first;
+            cnt[0] = nd.count;
+            cb[0] = nd.box;
+            ch[1] = -1;
+            cnt[1] = 0;
+            cb[1].reset();
+        } else {
+            const int kids[2] = {nd.left, nd.right};
+            for (int c = 0; c < 2; ++c) {
+                const BNode &k = bn[kids[c]];
+                cb[c] = k.box;
+                if (k.count > 0) {
+                    ch[c] = k.first;
+                    cnt[c] = k.count;
+                } else {
+                    ch[c] = gpu_id[kids[c]];
+                    cnt[c] = 0;
+                }
+            }
+        }
+        float lo[2][3], hi[2][3];
+        for (int c = 0; c < 2; ++c)
+            for (int k = 0; k < 3; ++k) {
+                if (cb[c].empty()) {
+                    lo[c][k] = INFINITY;
+                    hi[c][k] = -INFINITY;
+                } else {
+                    lo[c][k] = padded(cb[c], k, false);
+                    hi[c][k] = padded(cb[c], k, true);
+                }
+            }
+        GpuNode &o = out.nodes[g];
+        o.bx = make_float4(lo[0][0], lo[1][0], hi[0][0], hi[1][0]);
+        o.by = make_float4(lo[0][1], lo[1][1], hi[0][1], hi[1][1]);
+        o.bz = make_float4(lo[0][2], lo[1][2], hi[0][2], hi[1][2]);
+        o.meta = make_int4(ch[0], ch[1], cnt[0], cnt[1]);
+    }
+    return true;
+}
+
+}  // namespace pv

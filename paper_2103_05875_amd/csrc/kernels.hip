@@ -1,0 +1,894 @@
+// gfx950 kernels of the probe-volume update and the lossless delta pack.
+//
+//   k_raydirs   spherical-Fibonacci ray set under the frame rotation
+//   k_trace     closest hit (BVH, per-lane stack in LDS) + direct shading with
+//               a shadow ray; one wavefront = one ray direction x a 4x4x4 brick
+//               of probes, so the 64 rays of a wave are parallel and start
+//               close together (coherent traversal)
+//   k_blend     cosine / cosine^s weighted means over the rays, hysteresis,
+//               FP32 or FP16 store, guard bands written by scatter
+//   k_pack_*    change mask, ordered compaction, XOR byte planes, reference
+//               update, checksum
+#include <hip/hip_fp16.h>
+
+#include "internal.h"
+
+namespace pv {
+
+constexpr int kTraceBlock = 128;  // two wavefronts
+constexpr int kStack = kMaxDepth;
+constexpr int kBlendBlock = 256;
+constexpr int kBlendProbes = 4;
+constexpr int kBlendChunk = 256;
+// A texel whose weight sum is at most this keeps its old value: no ray falls
+// usefully inside its lobe. Far above where FP32 weights underflow.
+constexpr float kWeightFloor = 1e-20f;
+
+// ---------------------------------------------------------------------------
+// small vector helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float3 xyz(float4 a) { return make_float3(a.x, a.y, a.z); }
+__device__ __forceinline__ float3 operator-(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+    return make_float3(fmaf(a.y, b.z, -a.z * b.y), fmaf(a.z, b.x, -a.x * b.z), fmaf(a.x, b.y, -a.y * b.x));
+}
+
+// XCD-aware block order: the hardware deals consecutive workgroups to the 8
+// XCDs in turn; renumber so that each XCD runs one contiguous range of the
+// logical work (neighbouring rays share that XCD's L2).
+__device__ __forceinline__ int xcd_logical_block() {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// ray directions
+// ---------------------------------------------------------------------------
+__device__ void raydir_one(const FrameParams &fp, int n, int i, float4 *dirs) {
+    // z evenly spaced in (-1, 1); azimuth steps by the golden angle
+    const double z = 1.0 - (2.0 * i + 1.0) / n;
+    const double a = (double)i * 0.61803398874989484820;  // frac(i * (phi - 1))
+    const double az = 6.28318530717958647692 * (a - floor(a));
+    const double rr = sqrt(fmax(0.0, 1.0 - z * z));
+    const double sx = rr * cos(az), sy = rr * sin(az);
+    const float *R = fp.rot;
+    dirs[i] = make_float4((float)(R[0] * sx + R[1] * sy + R[2] * z), (float)(R[3] * sx + R[4] * sy + R[5] * z),
+                          (float)(R[6] * sx + R[7] * sy + R[8] * z), 0.f);
+}
+
+__global__ void k_raydirs(FrameParams fp, int n, float4 *dirs) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += blockDim.x * gridDim.x) raydir_one(fp, n, i, dirs);
+}
+
+__global__ void k_raydirs_batched(const FrameParams *fps, const int *ns, float4 *const *dirs, int n_vols) {
+    const int v = blockIdx.x;
+    if (v >= n_vols) return;
+    const int n = ns[v];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) raydir_one(fps[v], n, i, dirs[v]);
+}
+
+// ---------------------------------------------------------------------------
+// traversal
+// ---------------------------------------------------------------------------
+struct Ray {
+    float3 o, d, inv, oinv;
+};
+
+__device__ __forceinline__ Ray make_ray(float3 o, float3 d) {
+    Ray r;
+    r.o = o;
+    r.d = d;
+    // keep 1/d finite so the slab products never form inf - inf
+    float dx = fabsf(d.x) < 1e-20f ? copysignf(1e-20f, d.x) : d.x;
+    float dy = fabsf(d.y) < 1e-20f ? copysignf(1e-20f, d.y) : d.y;
+    float dz = fabsf(d.z) < 1e-20f ? copysignf(1e-20f, d.z) : d.z;
+    r.inv = make_float3(1.0f / dx, 1.0f / dy, 1.0f / dz);
+    r.oinv = make_float3(o.x * r.inv.x, o.y * r.inv.y, o.z * r.inv.z);
+    return r;
+}
+
+// Both child boxes of a node against [tmin, tmax]: entry distances and hits.
+__device__ __forceinline__ void box2(const GpuNode &nd, const Ray &r, float tmin, float tmax, float &t0, float &t1,
+                                     bool &h0, bool &h1) {
+    float ax0 = fmaf(nd.bx.x, r.inv.x, -r.oinv.x), ax1 = fmaf(nd.bx.z, r.inv.x, -r.oinv.x);
+    float ay0 = fmaf(nd.by.x, r.inv.y, -r.oinv.y), ay1 = fmaf(nd.by.z, r.inv.y, -r.oinv.y);
+    float az0 = fmaf(nd.bz.x, r.inv.z, -r.oinv.z), az1 = fmaf(nd.bz.z, r.inv.z, -r.oinv.z);
+    float bx0 = fmaf(nd.bx.y, r.inv.x, -r.oinv.x), bx1 = fmaf(nd.bx.w, r.inv.x, -r.oinv.x);
+    float by0 = fmaf(nd.by.y, r.inv.y, -r.oinv.y), by1 = fmaf(nd.by.w, r.inv.y, -r.oinv.y);
+    float bz0 = fmaf(nd.bz.y, r.inv.z, -r.oinv.z), bz1 = fmaf(nd.bz.w, r.inv.z, -r.oinv.z);
+    float an = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), tmin));
+    float af = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tmax));
+    float bn = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), tmin));
+    float bf = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tmax));
+    t0 = an;
+    t1 = bn;
+    // an empty slot (child -1, count 0) stores lo = +inf, hi = -inf
+    h0 = an <= af && (nd.meta.x >= 0 || nd.meta.z > 0);
+    h1 = bn <= bf && (nd.meta.y >= 0 || nd.meta.w > 0);
+}
+
+// Two-sided Moller-Trumbore: true when the ray line crosses the triangle
+// (barycentrics inside, det != 0); t receives the distance along the ray.
+__device__ __forceinline__ bool tri_cross(const GpuTri &T, const Ray &r, float &t) {
+    const float3 e1 = xyz(T.e1), e2 = xyz(T.e2);
+    const float3 p = cross3(r.d, e2);
+    const float det = dot3(e1, p);
+    const float inv = __builtin_amdgcn_rcpf(det);
+    const float3 s = r.o - xyz(T.v0);
+    const float u = dot3(s, p) * inv;
+    const float3 q = cross3(s, e1);
+    const float v = dot3(r.d, q) * inv;
+    t = dot3(e2, q) * inv;
+    // written so that NaN (det == 0) fails every test
+    return (u >= 0.f) && (v >= 0.f) && (u + v <= 1.f) && (t == t);
+}
+
+__device__ __forceinline__ int tri_id(const GpuTri &T) { return __float_as_int(T.v0.w); }
+
+struct Counts {
+    uint32_t nodes, tris;
+};
+
+// Per-lane traversal stack in LDS: entry sp of lane 'col' at stk[sp*W + col].
+template <int W>
+struct Stack {
+    int *base;
+    __device__ __forceinline__ void push(int &sp, int v) { base[(sp++) * W] = v; }
+    __device__ __forceinline__ int pop(int &sp) { return base[(--sp) * W]; }
+};
+
+// Closest hit in one BVH; updates (tbest, best tri index, best array) when a
+// nearer hit is found; equal distances go to the smaller original id.
+template <bool COUNT, int W>
+__device__ void closest(const DeviceBvh &bvh, const Ray &r, float tmin, float &tbest, int &best, int &best_id,
+                        const GpuTri *&best_arr, Stack<W> stk, Counts &cnt) {
+    if (bvh.n_nodes == 0) return;
+    int node = 0, sp = 0;
+    while (true) {
+        const GpuNode nd = bvh.nodes[node];
+        float t0, t1;
+        bool h0, h1;
+        box2(nd, r, tmin, tbest, t0, t1, h0, h1);
+        if (COUNT) cnt.nodes++;
+        // leaves are tested in place
+        for (int c = 0; c < 2; ++c) {
+            const bool hc = c == 0 ? h0 : h1;
+            const int cnt_c = c == 0 ? nd.meta.z : nd.meta.w;
+            if (hc && cnt_c > 0) {
+                const int first = c == 0 ? nd.meta.x : nd.meta.y;
+                for (int k = first; k < first + cnt_c; ++k) {
+                    const GpuTri T = bvh.tris[k];
+                    float t;
+                    if (COUNT) cnt.tris++;
+                    if (tri_cross(T, r, t) && t > tmin && (t < tbest || (t == tbest && tri_id(T) < best_id))) {
+                        tbest = t;
+                        best = k;
+                        best_id = tri_id(T);
+                        best_arr = bvh.tris;
+                    }
+                }
+            }
+        }
+        const bool i0 = h0 && nd.meta.z == 0, i1 = h1 && nd.meta.w == 0;
+        if (i0 && i1) {
+            const bool first0 = t0 <= t1;
+            stk.push(sp, first0 ? nd.meta.y : nd.meta.x);
+            node = first0 ? nd.meta.x : nd.meta.y;
+        } else if (i0) {
+            node = nd.meta.x;
+        } else if (i1) {
+            node = nd.meta.y;
+        } else {
+            if (sp == 0) break;
+            node = stk.pop(sp);
+        }
+    }
+}
+
+// Any hit with tmin < t < tmax in one BVH.
+template <bool COUNT, int W>
+__device__ bool any_hit(const DeviceBvh &bvh, const Ray &r, float tmin, float tmax, Stack<W> stk, Counts &cnt) {
+    if (bvh.n_nodes == 0) return false;
+    int node = 0, sp = 0;
+    while (true) {
+        const GpuNode nd = bvh.nodes[node];
+        float t0, t1;
+        bool h0, h1;
+        box2(nd, r, tmin, tmax, t0, t1, h0, h1);
+        if (COUNT) cnt.nodes++;
+        for (int c = 0; c < 2; ++c) {
+            const bool hc = c == 0 ? h0 : h1;
+            const int cnt_c = c == 0 ? nd.meta.z : nd.meta.w;
+            if (hc && cnt_c > 0) {
+                const int first = c == 0 ? nd.meta.x : nd.meta.y;
+                for (int k = first; k < first + cnt_c; ++k) {
+                    float t;
+                    if (COUNT) cnt.tris++;
+                    if (tri_cross(bvh.tris[k], r, t) && t > tmin && t < tmax) return true;
+                }
+            }
+        }
+        const bool i0 = h0 && nd.meta.z == 0, i1 = h1 && nd.meta.w == 0;
+        if (i0 && i1) {
+            const bool first0 = t0 <= t1;
+            stk.push(sp, first0 ? nd.meta.y : nd.meta.x);
+            node = first0 ? nd.meta.x : nd.meta.y;
+        } else if (i0) {
+            node = nd.meta.x;
+        } else if (i1) {
+            node = nd.meta.y;
+        } else {
+            if (sp == 0) return false;
+            node = stk.pop(sp);
+        }
+    }
+}
+
+// Trace and shade the ray of probe (x, y, z), direction j; writes its record.
+template <bool COUNT, int W>
+__device__ void trace_shade_one(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp, const float4 *dirs,
+                                float4 *rays, int32_t *hits, int x, int y, int z, int j, Stack<W> stk, Counts &cnt,
+                                uint32_t &shadow_rays) {
+    const float3 o = make_float3(fmaf(vp.sx, (float)x, vp.ox), fmaf(vp.sy, (float)y, vp.oy),
+                                 fmaf(vp.sz, (float)z, vp.oz));
+    const float4 dj = dirs[j];
+    const Ray ray = make_ray(o, xyz(dj));
+    float tbest = INFINITY;
+    int best = -1, best_id = -1;
+    const GpuTri *arr = nullptr;
+    closest<COUNT, W>(sv.stat, ray, 0.f, tbest, best, best_id, arr, stk, cnt);
+    closest<COUNT, W>(sv.dyn, ray, 0.f, tbest, best, best_id, arr, stk, cnt);
+    float3 L;
+    float dist;
+    if (best >= 0) {
+        const GpuTri T = arr[best];
+        float3 nrm = cross3(xyz(T.e1), xyz(T.e2));
+        const float il = rsqrtf(dot3(nrm, nrm));
+        nrm = make_float3(nrm.x * il, nrm.y * il, nrm.z * il);
+        if (dot3(nrm, ray.d) > 0.f) nrm = make_float3(-nrm.x, -nrm.y, -nrm.z);
+        const float3 xh = make_float3(fmaf(tbest, ray.d.x, o.x), fmaf(tbest, ray.d.y, o.y), fmaf(tbest, ray.d.z, o.z));
+        const float4 alb = sv.mats[2 * best_id], emi = sv.mats[2 * best_id + 1];
+        L = make_float3(emi.x, emi.y, emi.z);
+        for (int li = 0; li < fp.n_lights; ++li) {
+            const float3 lp = make_float3(fp.light_pos[li][0], fp.light_pos[li][1], fp.light_pos[li][2]);
+            const float3 lv = lp - xh;
+            const float d2 = dot3(lv, lv);
+            const float dl = sqrtf(d2);
+            const float cosv = dot3(nrm, lv) / dl;
+            if (!(cosv > 0.f)) continue;
+            const float3 so = make_float3(fmaf(sv.eps, nrm.x, xh.x), fmaf(sv.eps, nrm.y, xh.y), fmaf(sv.eps, nrm.z, xh.z));
+            float3 sd = lp - so;
+            const float slen = sqrtf(dot3(sd, sd));
+            const float isl = 1.0f / slen;
+            sd = make_float3(sd.x * isl, sd.y * isl, sd.z * isl);
+            const Ray sr = make_ray(so, sd);
+            const float smax = slen - sv.eps;
+            if (COUNT) shadow_rays++;
+            bool occ = any_hit<COUNT, W>(sv.stat, sr, 0.f, smax, stk, cnt);
+            if (!occ) occ = any_hit<COUNT, W>(sv.dyn, sr, 0.f, smax, stk, cnt);
+            if (!occ) {
+                const float g = cosv / d2 * 0.31830988618379067f;  // 1/pi
+                L.x = fmaf(alb.x * fp.light_int[li][0], g, L.x);
+                L.y = fmaf(alb.y * fp.light_int[li][1], g, L.y);
+                L.z = fmaf(alb.z * fp.light_int[li][2], g, L.z);
+            }
+        }
+        dist = fminf(tbest, vp.max_distance);
+    } else {
+        L = make_float3(vp.sky[0], vp.sky[1], vp.sky[2]);
+        dist = vp.max_distance;
+    }
+    const size_t p = (size_t)x + (size_t)vp.nx * ((size_t)y + (size_t)vp.ny * z);
+    const size_t q = p * vp.n + j;
+    rays[q] = make_float4(L.x, L.y, L.z, dist);
+    if (hits) hits[q] = best_id;
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeParams vp, SceneView sv, FrameParams fp,
+                                                      const float4 *dirs, float4 *rays, int32_t *hits,
+                                                      unsigned long long *counts, int bricks_x, int bricks_y,
+                                                      int n_waves) {
+    __shared__ int stk[kStack * kTraceBlock];
+    const int w = xcd_logical_block() * (kTraceBlock / 64) + (threadIdx.x >> 6);
+    if (w >= n_waves) return;
+    const int lane = threadIdx.x & 63;
+    const int n_bricks = n_waves / vp.n;
+    const int j = w / n_bricks, brick = w - j * n_bricks;
+    const int bxi = brick % bricks_x, byi = (brick / bricks_x) % bricks_y, bzi = brick / (bricks_x * bricks_y);
+    const int x = bxi * 4 + (lane & 3), y = byi * 4 + ((lane >> 2) & 3), z = bzi * 4 + (lane >> 4);
+    Counts cnt = {0, 0};
+    uint32_t shadow = 0;
+    if (x < vp.nx && y < vp.ny && z < vp.nz)
+        trace_shade_one<COUNT, kTraceBlock>(vp, sv, fp, dirs, rays, hits, x, y, z, j,
+                                            Stack<kTraceBlock>{stk + threadIdx.x}, cnt, shadow);
+    if (COUNT) {
+        atomicAdd(&counts[0], (unsigned long long)cnt.nodes);
+        atomicAdd(&counts[1], (unsigned long long)cnt.tris);
+        atomicAdd(&counts[2], (unsigned long long)shadow);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// blend
+// ---------------------------------------------------------------------------
+// Centre direction of interior texel (i, j) of an N x N octahedral map.
+__device__ __forceinline__ float3 oct_texel_dir(int N, int i, int j) {
+    const float u = (2.0f * i + 1.0f) / N - 1.0f;
+    const float w = (2.0f * j + 1.0f) / N - 1.0f;
+    float x = u, y = w;
+    const float zz = 1.0f - fabsf(u) - fabsf(w);
+    if (zz < 0.f) {
+        x = (1.0f - fabsf(w)) * (u >= 0.f ? 1.f : -1.f);
+        y = (1.0f - fabsf(u)) * (w >= 0.f ? 1.f : -1.f);
+    }
+    const float il = rsqrtf(x * x + y * y + zz * zz);
+    return make_float3(x * il, y * il, zz * il);
+}
+
+template <int S>
+__device__ __forceinline__ float pow_int(float x, int s) {
+    if (S == 50) {
+        const float x2 = x * x, x4 = x2 * x2, x8 = x4 * x4, x16 = x8 * x8, x32 = x16 * x16;
+        return x32 * x16 * x2;
+    }
+    float r = 1.f, b = x;
+    for (int e = s; e > 0; e >>= 1) {
+        if (e & 1) r *= b;
+        b *= b;
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ float load_map(const T *p);
+template <>
+__device__ __forceinline__ float load_map<float>(const float *p) { return *p; }
+template <>
+__device__ __forceinline__ float load_map<__half>(const __half *p) { return __half2float(*p); }
+
+template <typename T>
+__device__ __forceinline__ T to_map(float v);
+template <>
+__device__ __forceinline__ float to_map<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ __half to_map<__half>(float v) { return __float2half_rn(v); }
+
+// Store interior texel (i, j) of an N x N map into its (N+2)^2 tile together
+// with every guard texel that replicates it. Across an edge the octahedral
+// square continues mirrored, so a texel on the top row also lands on the
+// top guard row at the mirrored column, and so on; the four corner guard
+// texels replicate the diagonally opposite interior corner.
+template <typename T>
+__device__ __forceinline__ void store_with_guard(T *tile, int N, int i, int j, T v) {
+    const int S = N + 2;
+    tile[(j + 1) * S + (i + 1)] = v;
+    if (j == 0) tile[0 * S + (N - i)] = v;
+    if (j == N - 1) tile[(N + 1) * S + (N - i)] = v;
+    if (i == 0) tile[(N - j) * S + 0] = v;
+    if (i == N - 1) tile[(N - j) * S + (N + 1)] = v;
+    if (i == N - 1 && j == N - 1) tile[0] = v;
+    if (i == 0 && j == N - 1) tile[N + 1] = v;
+    if (i == N - 1 && j == 0) tile[(N + 1) * S] = v;
+    if (i == 0 && j == 0) tile[(N + 1) * S + (N + 1)] = v;
+}
+
+struct BlendSmem {
+    float4 sd[kBlendChunk];
+    float4 sL[kBlendProbes][kBlendChunk];
+    float2 sR[kBlendProbes][kBlendChunk];
+};
+
+// One block: 4 probes; thread t owns visibility texel t of all 4 probes and
+// irradiance texel (t mod 64) of probe t/64.
+template <typename T, int S>
+__device__ void blend_group(const VolumeParams &vp, const float4 *dirs, const float4 *rays, T *irr, T *vis,
+                            float h, int p0, BlendSmem &sm) {
+    float4 *sd = sm.sd;
+    float4 (*sL)[kBlendChunk] = sm.sL;
+    float2 (*sR)[kBlendChunk] = sm.sR;
+    const int tid = threadIdx.x;
+    const int n = vp.n, P = vp.P;
+    const float3 wv = oct_texel_dir(16, tid & 15, tid >> 4);
+    const int ti = tid & 63, qi = tid >> 6;
+    const float3 wi = oct_texel_dir(8, ti & 7, ti >> 3);
+    float sv = 0.f, a1[kBlendProbes], a2[kBlendProbes];
+#pragma unroll
+    for (int q = 0; q < kBlendProbes; ++q) a1[q] = a2[q] = 0.f;
+    float sw = 0.f, ar = 0.f, ag = 0.f, ab = 0.f;
+    for (int j0 = 0; j0 < n; j0 += kBlendChunk) {
+        const int m = min(kBlendChunk, n - j0);
+        __syncthreads();
+        for (int k = tid; k < m; k += kBlendBlock) sd[k] = dirs[j0 + k];
+        for (int k = tid; k < kBlendProbes * m; k += kBlendBlock) {
+            const int q = k / m, jj = k - q * m, p = p0 + q;
+            const float4 rec = p < P ? rays[(size_t)p * n + j0 + jj] : make_float4(0.f, 0.f, 0.f, 0.f);
+            sL[q][jj] = rec;
+            sR[q][jj] = make_float2(rec.w, rec.w * rec.w);
+        }
+        __syncthreads();
+        for (int jj = 0; jj < m; ++jj) {
+            const float3 d = xyz(sd[jj]);
+            const float cv = fmaxf(dot3(wv, d), 0.f);
+            const float v = pow_int<S>(cv, vp.vis_sharpness);
+            sv += v;
+#pragma unroll
+            for (int q = 0; q < kBlendProbes; ++q) {
+                const float2 rr = sR[q][jj];
+                a1[q] = fmaf(v, rr.x, a1[q]);
+                a2[q] = fmaf(v, rr.y, a2[q]);
+            }
+            const float ci = fmaxf(dot3(wi, d), 0.f);
+            const float4 L = sL[qi][jj];
+            sw += ci;
+            ar = fmaf(ci, L.x, ar);
+            ag = fmaf(ci, L.y, ag);
+            ab = fmaf(ci, L.z, ab);
+        }
+    }
+    const float g = 1.0f - h;
+    // visibility: 2 channels, 18x18 tiles
+    if (sv > kWeightFloor) {
+        const float isv = 1.0f / sv;
+        const int i = tid & 15, jr = tid >> 4;
+#pragma unroll
+        for (int q = 0; q < kBlendProbes; ++q) {
+            const int p = p0 + q;
+            if (p >= P) break;
+            T *base = vis + (size_t)p * 2 * 324;
+            const float est[2] = {a1[q] * isv, a2[q] * isv};
+            for (int c = 0; c < 2; ++c) {
+                T *tile = base + c * 324;
+                float nv = est[c];
+                if (h > 0.f) nv = fmaf(h, load_map<T>(tile + (jr + 1) * 18 + (i + 1)), g * est[c]);
+                store_with_guard<T>(tile, 16, i, jr, to_map<T>(nv));
+            }
+        }
+    }
+    // irradiance: 3 channels, 10x10 tiles
+    const int p = p0 + qi;
+    if (p < P && sw > kWeightFloor) {
+        const float isw = 1.0f / sw;
+        const int i = ti & 7, jr = ti >> 3;
+        T *base = irr + (size_t)p * 3 * 100;
+        const float est[3] = {ar * isw, ag * isw, ab * isw};
+        for (int c = 0; c < 3; ++c) {
+            T *tile = base + c * 100;
+            float nv = est[c];
+            if (h > 0.f) nv = fmaf(h, load_map<T>(tile + (jr + 1) * 10 + (i + 1)), g * est[c]);
+            store_with_guard<T>(tile, 8, i, jr, to_map<T>(nv));
+        }
+    }
+}
+
+template <typename T, int S>
+__global__ __launch_bounds__(kBlendBlock) void k_blend(VolumeParams vp, const float4 *dirs, const float4 *rays,
+                                                      T *irr, T *vis, float h) {
+    __shared__ BlendSmem sm;
+    const int p0 = xcd_logical_block() * kBlendProbes;
+    if (p0 >= vp.P) return;
+    blend_group<T, S>(vp, dirs, rays, irr, vis, h, p0, sm);
+}
+
+// ---------------------------------------------------------------------------
+// batched persistent launch
+// ---------------------------------------------------------------------------
+// Work queue over all volumes: first every trace item (4 waves), then every
+// blend group (4 probes). A blend group of volume v waits until all
+// trace items of v have completed; every item it waits on was dequeued
+// earlier by a running block that never waits on later items, so the
+// queue drains. The wait is bounded; on expiry the block records an error
+// and skips its item.
+constexpr int kBatchBlock = 256;
+constexpr long long kSpinLimit = 1ll << 26;
+
+union BatchSmem {
+    int stk[kStack * kBatchBlock];
+    BlendSmem blend;
+};
+
+__device__ __forceinline__ int volume_of_wave(const BatchVolume *vols, int n_vols, int wave) {
+    int v = 0;
+    while (v + 1 < n_vols && vols[v + 1].first_wave <= wave) ++v;
+    return v;
+}
+
+__global__ __launch_bounds__(kBatchBlock) void k_batched(const BatchVolume *vols, int n_vols, int wave_items,
+                                                        int total_blend, const FrameParams *frames, int *queue,
+                                                        int *done, int *status) {
+    __shared__ BatchSmem sm;
+    __shared__ int item_s;
+    const int total = wave_items + total_blend;
+    const int wpi = kBatchBlock / 64;  // trace waves per item
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) item_s = atomicAdd(queue, 1);
+        __syncthreads();
+        const int item = item_s;
+        if (item >= total) break;
+        if (item < wave_items) {
+            const int wave = item * wpi + (threadIdx.x >> 6);
+            const int v = volume_of_wave(vols, n_vols, wave);
+            const BatchVolume &bv = vols[v];
+            const int local = wave - bv.first_wave;
+            if (local >= 0 && local < bv.n_waves) {
+                const int lane = threadIdx.x & 63;
+                const int n_bricks = bv.n_waves / bv.vp.n;
+                const int j = local / n_bricks, brick = local - j * n_bricks;
+                const int bxi = brick % bv.bricks_x, byi = (brick / bv.bricks_x) % bv.bricks_y,
+                          bzi = brick / (bv.bricks_x * bv.bricks_y);
+                const int x = bxi * 4 + (lane & 3), y = byi * 4 + ((lane >> 2) & 3), z = bzi * 4 + (lane >> 4);
+                Counts cnt = {0, 0};
+                uint32_t sh = 0;
+                if (x < bv.vp.nx && y < bv.vp.ny && z < bv.vp.nz)
+                    trace_shade_one<false, kBatchBlock>(bv.vp, bv.sv, frames[v], bv.dirs, bv.rays, bv.hits, x, y, z,
+                                                        j, Stack<kBatchBlock>{sm.stk + threadIdx.x}, cnt, sh);
+            }
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                for (int k = 0; k < wpi; ++k) {
+                    const int wk = item * wpi + k;
+                    const int vk = volume_of_wave(vols, n_vols, wk);
+                    const int lk = wk - vols[vk].first_wave;
+                    if (lk >= 0 && lk < vols[vk].n_waves) atomicAdd(&done[vk], 1);
+                }
+            }
+        } else {
+            const int g = item - wave_items;
+            int v = 0;
+            while (v + 1 < n_vols && vols[v + 1].first_blend <= g) ++v;
+            const BatchVolume &bv = vols[v];
+            if (threadIdx.x == 0) {
+                long long spins = 0;
+                while (__hip_atomic_load(&done[v], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < bv.n_waves) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (++spins > kSpinLimit) {
+                        atomicExch(status, 1);
+                        break;
+                    }
+                }
+                __threadfence();
+            }
+            __syncthreads();
+            const int p0 = (g - bv.first_blend) * kBlendProbes;
+            if (bv.fp16) {
+                if (bv.vp.vis_sharpness == 50)
+                    blend_group<__half, 50>(bv.vp, bv.dirs, bv.rays, (__half *)bv.irr, (__half *)bv.vis, bv.h, p0,
+                                            sm.blend);
+                else
+                    blend_group<__half, 0>(bv.vp, bv.dirs, bv.rays, (__half *)bv.irr, (__half *)bv.vis, bv.h, p0,
+                                           sm.blend);
+            } else {
+                if (bv.vp.vis_sharpness == 50)
+                    blend_group<float, 50>(bv.vp, bv.dirs, bv.rays, (float *)bv.irr, (float *)bv.vis, bv.h, p0,
+                                           sm.blend);
+                else
+                    blend_group<float, 0>(bv.vp, bv.dirs, bv.rays, (float *)bv.irr, (float *)bv.vis, bv.h, p0,
+                                          sm.blend);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pack
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ __forceinline__ uint32_t word_hash(uint32_t w, uint32_t word_index) {
+    return fmix32(w ^ (word_index * 0x9E3779B9u));
+}
+
+__device__ __forceinline__ bool texel_changed(uint16_t a, uint16_t b, float tau) {
+    if (tau == 0.f) return a != b;
+    // binary16 values are exact in double and so is their difference
+    const double da = (double)__half2float(__ushort_as_half(a));
+    const double db = (double)__half2float(__ushort_as_half(b));
+    return fabs(da - db) > (double)tau;
+}
+
+// One wavefront per probe: any interior texel changed -> mask = 1.
+__global__ __launch_bounds__(256) void k_pack_mask(PackBuffers b, int P, float tau_irr, float tau_vis) {
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= P) return;
+    const int lane = threadIdx.x & 63;
+    const uint16_t *ci = b.cur_irr + (size_t)p * 300;
+    const uint16_t *ri = b.ref_irr + (size_t)p * 192;
+    bool ch_i = false;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int t = lane;  // interior texel, row-major 8x8
+        const uint16_t a = ci[c * 100 + ((t >> 3) + 1) * 10 + (t & 7) + 1];
+        ch_i |= texel_changed(a, ri[c * 64 + t], tau_irr);
+    }
+    const uint16_t *cv = b.cur_vis + (size_t)p * 648;
+    const uint16_t *rv = b.ref_vis + (size_t)p * 512;
+    bool ch_v = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int c = k >> 2, t = lane + 64 * (k & 3);
+        const uint16_t a = cv[c * 324 + ((t >> 4) + 1) * 18 + (t & 15) + 1];
+        ch_v |= texel_changed(a, rv[c * 256 + t], tau_vis);
+    }
+    const bool any_i = __any(ch_i), any_v = __any(ch_v);
+    if (lane == 0) {
+        b.mask_irr[p] = any_i ? 1 : 0;
+        b.mask_vis[p] = any_v ? 1 : 0;
+    }
+}
+
+constexpr int kScanBlock = 1024;
+
+__device__ int block_exclusive_sum(int v, int *sh, int &total) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        const int add = tid >= off ? sh[tid - off] : 0;
+        __syncthreads();
+        sh[tid] += add;
+        __syncthreads();
+    }
+    total = sh[kScanBlock - 1];
+    const int excl = sh[tid] - v;
+    __syncthreads();
+    return excl;
+}
+
+__device__ int block_exclusive_max(int v, int *sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        const int o = tid >= off ? sh[tid - off] : -1;
+        __syncthreads();
+        sh[tid] = max(sh[tid], o);
+        __syncthreads();
+    }
+    const int excl = tid > 0 ? sh[tid - 1] : -1;
+    __syncthreads();
+    return excl;
+}
+
+// One block: ordered ranks of the changed probes, delta-coded index buffers,
+// the header, and the checksum share of the index section.
+__global__ __launch_bounds__(kScanBlock) void k_pack_scan(PackBuffers b, int P, uint32_t client, uint32_t seq) {
+    __shared__ int sh[kScanBlock];
+    __shared__ uint32_t shu[kScanBlock / 64];
+    const int tid = threadIdx.x;
+    const int per = (P + kScanBlock - 1) / kScanBlock;
+    const int lo = min(P, tid * per), hi = min(P, lo + per);
+    int ki = 0, kv = 0, last_i = -1, last_v = -1;
+    for (int p = lo; p < hi; ++p) {
+        if (b.mask_irr[p]) { ++ki; last_i = p; }
+        if (b.mask_vis[p]) { ++kv; last_v = p; }
+    }
+    int K_irr, K_vis;
+    const int base_i = block_exclusive_sum(ki, sh, K_irr);
+    const int base_v = block_exclusive_sum(kv, sh, K_vis);
+    int prev_i = block_exclusive_max(last_i, sh);
+    int prev_v = block_exclusive_max(last_v, sh);
+    uint8_t *pk = b.packet;
+    uint16_t *idx_i = reinterpret_cast<uint16_t *>(pk + 32);
+    uint16_t *idx_v = idx_i + K_irr;
+    int k_i = base_i, k_v = base_v;
+    for (int p = lo; p < hi; ++p) {
+        if (b.mask_irr[p]) {
+            b.rank_irr[p] = k_i;
+            idx_i[k_i] = (uint16_t)(k_i == 0 ? p : p - prev_i);
+            prev_i = p;
+            ++k_i;
+        }
+        if (b.mask_vis[p]) {
+            b.rank_vis[p] = k_v;
+            idx_v[k_v] = (uint16_t)(k_v == 0 ? p : p - prev_v);
+            prev_v = p;
+            ++k_v;
+        }
+    }
+    const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
+    if (tid < 16) {  // zero the padding after the entries
+        const int pos = 2 * (K_irr + K_vis) + tid;
+        if (pos < idx_bytes) pk[32 + pos] = 0;
+    }
+    __syncthreads();
+    // checksum of the index section (payload words 0 .. idx_bytes/4 - 1)
+    uint32_t part = 0;
+    const uint32_t *words = reinterpret_cast<const uint32_t *>(pk + 32);
+    for (int wi = tid; wi < idx_bytes / 4; wi += kScanBlock) part += word_hash(words[wi], (uint32_t)wi);
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if ((tid & 63) == 0) shu[tid >> 6] = part;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t sum = 0;
+        for (int k = 0; k < kScanBlock / 64; ++k) sum += shu[k];
+        uint32_t *h = reinterpret_cast<uint32_t *>(pk);
+        h[0] = 0x4B505650u;
+        h[1] = 1u | (32u << 16);
+        h[2] = client;
+        h[3] = seq;
+        h[4] = (uint32_t)P;
+        h[5] = (uint32_t)K_irr;
+        h[6] = (uint32_t)K_vis;
+        h[7] = sum;
+    }
+}
+
+// One block of 192 threads per probe: XOR byte planes of the sent probes,
+// reference update, checksum share. Threads 0..47 take irradiance (3
+// channels x 16 groups of 4 texels), 48..175 visibility (2 x 64 groups).
+__global__ __launch_bounds__(192) void k_pack_compact(PackBuffers b, int P) {
+    __shared__ uint32_t shu[3];
+    const int p = blockIdx.x;
+    if (p >= P) return;
+    const bool si = b.mask_irr[p] != 0, svv = b.mask_vis[p] != 0;
+    if (!si && !svv) return;
+    const int tid = threadIdx.x;
+    const uint32_t *h = reinterpret_cast<const uint32_t *>(b.packet);
+    const int K_irr = (int)h[5], K_vis = (int)h[6];
+    const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
+    uint8_t *planes_i = b.packet + 32 + idx_bytes;
+    uint8_t *planes_v = planes_i + (size_t)K_irr * 6 * 64;
+    uint32_t part = 0;
+    int N = 0, c = 0, m = 0, K = 0, k = 0;
+    const uint16_t *tile = nullptr;
+    uint16_t *ref = nullptr;
+    uint8_t *planes = nullptr;
+    bool act = false;
+    if (tid < 48 && si) {
+        N = 8;
+        c = tid >> 4;
+        m = tid & 15;
+        K = K_irr;
+        k = (int)b.rank_irr[p];
+        tile = b.cur_irr + (size_t)p * 300 + c * 100;
+        ref = b.ref_irr + (size_t)p * 192 + c * 64;
+        planes = planes_i;
+        act = true;
+    } else if (tid >= 48 && tid < 176 && svv) {
+        const int u = tid - 48;
+        N = 16;
+        c = u >> 6;
+        m = u & 63;
+        K = K_vis;
+        k = (int)b.rank_vis[p];
+        tile = b.cur_vis + (size_t)p * 648 + c * 324;
+        ref = b.ref_vis + (size_t)p * 512 + c * 256;
+        planes = planes_v;
+        act = true;
+    }
+    if (act) {
+        const int t0 = 4 * m, row = t0 / N, col = t0 - row * N;
+        const uint16_t *src = tile + (row + 1) * (N + 2) + col + 1;
+        const uint16_t a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3];
+        const uint2 rf = *reinterpret_cast<const uint2 *>(ref + t0);
+        const uint16_t x0 = a0 ^ (uint16_t)(rf.x & 0xffff), x1 = a1 ^ (uint16_t)(rf.x >> 16);
+        const uint16_t x2 = a2 ^ (uint16_t)(rf.y & 0xffff), x3 = a3 ^ (uint16_t)(rf.y >> 16);
+        const uint32_t lo = (x0 & 0xffu) | ((x1 & 0xffu) << 8) | ((x2 & 0xffu) << 16) | ((uint32_t)(x3 & 0xffu) << 24);
+        const uint32_t hi = (x0 >> 8) | ((x1 >> 8) << 8) | ((x2 >> 8) << 16) | ((uint32_t)(x3 >> 8) << 24);
+        const size_t plane_bytes = (size_t)K * N * N;
+        uint8_t *dlo = planes + (size_t)(2 * c) * plane_bytes + (size_t)k * N * N + t0;
+        uint8_t *dhi = dlo + plane_bytes;
+        *reinterpret_cast<uint32_t *>(dlo) = lo;
+        *reinterpret_cast<uint32_t *>(dhi) = hi;
+        *reinterpret_cast<uint2 *>(ref + t0) =
+            make_uint2((uint32_t)a0 | ((uint32_t)a1 << 16), (uint32_t)a2 | ((uint32_t)a3 << 16));
+        part = word_hash(lo, (uint32_t)((dlo - (b.packet + 32)) >> 2)) +
+               word_hash(hi, (uint32_t)((dhi - (b.packet + 32)) >> 2));
+    }
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if ((tid & 63) == 0) shu[tid >> 6] = part;
+    __syncthreads();
+    if (tid == 0) atomicAdd(reinterpret_cast<uint32_t *>(b.packet) + 7, shu[0] + shu[1] + shu[2]);
+}
+
+__global__ void k_zero(uint32_t *p, size_t words) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)blockDim.x * gridDim.x)
+        p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_raydirs(const FrameParams &fp, int n, float4 *dirs, hipStream_t s) {
+    hipLaunchKernelGGL(k_raydirs, dim3((n + 255) / 256), dim3(256), 0, s, fp, n, dirs);
+    return hipGetLastError();
+}
+
+hipError_t launch_raydirs_batched(const FrameParams *frames_dev, const int *ns_dev, float4 *const *dirs_dev,
+                                  int n_vols, hipStream_t s) {
+    hipLaunchKernelGGL(k_raydirs_batched, dim3(n_vols), dim3(256), 0, s, frames_dev, ns_dev, dirs_dev, n_vols);
+    return hipGetLastError();
+}
+
+static void brick_counts(const VolumeParams &vp, int &bx, int &by, int &bz) {
+    bx = (vp.nx + 3) / 4;
+    by = (vp.ny + 3) / 4;
+    bz = (vp.nz + 3) / 4;
+}
+
+hipError_t launch_trace(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp, const float4 *dirs,
+                        float4 *rays, int32_t *hits, unsigned long long *counts, hipStream_t s) {
+    int bx, by, bz;
+    brick_counts(vp, bx, by, bz);
+    const long long n_waves = (long long)bx * by * bz * vp.n;
+    const int waves_per_block = kTraceBlock / 64;
+    const long long blocks = (n_waves + waves_per_block - 1) / waves_per_block;
+    if (counts)
+        hipLaunchKernelGGL(k_trace<true>, dim3((unsigned)blocks), dim3(kTraceBlock), 0, s, vp, sv, fp, dirs, rays,
+                           hits, counts, bx, by, (int)n_waves);
+    else
+        hipLaunchKernelGGL(k_trace<false>, dim3((unsigned)blocks), dim3(kTraceBlock), 0, s, vp, sv, fp, dirs, rays,
+                           hits, counts, bx, by, (int)n_waves);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4 *rays, void *irr, void *vis,
+                        int fp16, float h, hipStream_t s) {
+    const int blocks = (vp.P + kBlendProbes - 1) / kBlendProbes;
+    const bool s50 = vp.vis_sharpness == 50;
+    if (fp16) {
+        if (s50)
+            hipLaunchKernelGGL((k_blend<__half, 50>), dim3(blocks), dim3(kBlendBlock), 0, s, vp, dirs, rays,
+                               (__half *)irr, (__half *)vis, h);
+        else
+            hipLaunchKernelGGL((k_blend<__half, 0>), dim3(blocks), dim3(kBlendBlock), 0, s, vp, dirs, rays,
+                               (__half *)irr, (__half *)vis, h);
+    } else {
+        if (s50)
+            hipLaunchKernelGGL((k_blend<float, 50>), dim3(blocks), dim3(kBlendBlock), 0, s, vp, dirs, rays,
+                               (float *)irr, (float *)vis, h);
+        else
+            hipLaunchKernelGGL((k_blend<float, 0>), dim3(blocks), dim3(kBlendBlock), 0, s, vp, dirs, rays,
+                               (float *)irr, (float *)vis, h);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, int total_blend,
+                          const FrameParams *frames_dev, int *queue_dev, int *done_dev, int *status_dev,
+                          hipStream_t s) {
+    const int wave_items = (total_waves + kBatchBlock / 64 - 1) / (kBatchBlock / 64);
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int blocks = cus * 4;
+    hipLaunchKernelGGL(k_batched, dim3(blocks), dim3(kBatchBlock), 0, s, vols_dev, n_vols, wave_items, total_blend,
+                       frames_dev, queue_dev, done_dev, status_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_mask(const PackBuffers &b, int P, float tau_irr, float tau_vis, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_mask, dim3((P + 3) / 4), dim3(256), 0, s, b, P, tau_irr, tau_vis);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_scan(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_scan, dim3(1), dim3(kScanBlock), 0, s, b, P, client, seq);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_compact(const PackBuffers &b, int P, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_compact, dim3(P), dim3(192), 0, s, b, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
+    const size_t words = bytes / 4;
+    if (words == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)p, words);
+    return hipGetLastError();
+}
+
+}  // namespace pv

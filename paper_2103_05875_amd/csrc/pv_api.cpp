@@ -1,0 +1,922 @@
+// C ABI of the probe-volume library: handles, validation, device memory,
+// launch sequencing. Kernels live in kernels.hip, the BVH builder in bvh.cpp.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace pv;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static pv_status fail(pv_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                                \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) return fail(PV_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char *pv_last_error(void) { return g_err.c_str(); }
+extern "C" const char *pv_version(void) { return "probestream 1.0 gfx950"; }
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct pv_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // batched launch scratch
+    BatchVolume *batch_dev = nullptr;
+    FrameParams *frames_dev = nullptr;
+    int *ns_dev = nullptr;
+    float4 **dirs_ptrs_dev = nullptr;
+    int *counters_dev = nullptr;  // [0] queue, [1] status, [2..] done per volume
+    int batch_cap = 0;
+    // pinned staging ring for the batched descriptors
+    static constexpr int kRing = 4;
+    void *stage_host[kRing] = {};
+    size_t stage_bytes = 0;
+    hipEvent_t stage_ev[kRing] = {};
+    int stage_next = 0;
+    unsigned long long *counts_dev = nullptr;
+    // optional per-stage event timing
+    struct Timed {
+        int stage;
+        hipEvent_t a, b;
+    };
+    bool timing = false;
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> pool;
+};
+
+// Runs 'launch' and, when timing is on, brackets it with events on 's'.
+template <class F>
+static hipError_t timed(pv_ctx *c, int stage, hipStream_t s, F launch) {
+    if (!c->timing) return launch();
+    hipEvent_t ev[2];
+    for (int i = 0; i < 2; ++i) {
+        if (!c->pool.empty()) {
+            ev[i] = c->pool.back();
+            c->pool.pop_back();
+        } else {
+            hipError_t e = hipEventCreate(&ev[i]);
+            if (e != hipSuccess) return e;
+        }
+    }
+    hipError_t e = hipEventRecord(ev[0], s);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ev[1], s);
+    c->pending.push_back({stage, ev[0], ev[1]});
+    return e;
+}
+
+struct pv_scene {
+    pv_ctx *ctx = nullptr;
+    int n_static = 0, n_dyn = 0;
+    DeviceBvh stat;
+    float4 *mats = nullptr;
+    float eps = 1e-4f;
+    std::vector<pv_point_light> lights;
+    // dynamic triangles: ring of device BVH slots fed from pinned staging
+    static constexpr int kRing = 4;
+    GpuNode *dyn_nodes[kRing] = {};
+    GpuTri *dyn_tris[kRing] = {};
+    void *dyn_stage[kRing] = {};
+    hipEvent_t dyn_use[kRing] = {};
+    bool dyn_used[kRing] = {};
+    int dyn_nodes_n[kRing] = {};
+    int dyn_slot = 0;
+    size_t dyn_node_cap = 0;
+};
+
+struct pv_volume {
+    pv_ctx *ctx = nullptr;
+    pv_volume_desc desc;
+    int P = 0, n = 0;
+    size_t elem = 4;
+    void *irr = nullptr, *vis = nullptr;
+    float4 *rays = nullptr, *dirs = nullptr;
+    int32_t *hits = nullptr;
+    int64_t frame = 0;
+    pv_scene *scene = nullptr;
+};
+
+struct pv_client {
+    pv_volume *vol = nullptr;
+    uint32_t id = 0, seq = 0;
+    uint16_t *ref_irr = nullptr, *ref_vis = nullptr;
+    uint8_t *mask_irr = nullptr, *mask_vis = nullptr;
+    uint32_t *rank_irr = nullptr, *rank_vis = nullptr;
+    uint8_t *packet = nullptr;
+    uint64_t packet_cap = 0;
+    uint32_t *hdr_host = nullptr;  // pinned, 32 bytes
+};
+
+static hipStream_t pick(pv_ctx *ctx, void *s) { return s ? (hipStream_t)s : ctx->stream; }
+
+static uint64_t irr_bytes(int P, size_t elem) { return (uint64_t)P * 3 * 100 * elem; }
+static uint64_t vis_bytes(int P, size_t elem) { return (uint64_t)P * 2 * 324 * elem; }
+static uint64_t packet_capacity(int P) {
+    uint64_t idx = ((2ull * 2 * P + 15) / 16) * 16;
+    return 32 + idx + (uint64_t)P * (6 * 64 + 4 * 256);
+}
+
+template <typename T>
+static pv_status dev_alloc(T **p, size_t bytes, const char *what) {
+    *p = nullptr;
+    if (bytes == 0) return PV_OK;
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(PV_ERR_OOM, std::string("device allocation of ") + what + " (" + std::to_string(bytes) +
+                                    " bytes) failed: " + hipGetErrorString(e));
+    }
+    return PV_OK;
+}
+
+#define PV_TRY(expr)                      \
+    do {                                  \
+        pv_status s_ = (expr);            \
+        if (s_ != PV_OK) return s_;       \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" pv_status pv_ctx_create(int hip_device, pv_ctx **out) {
+    if (!out) return fail(PV_ERR_ARG, "out is NULL");
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (hip_device < 0 || hip_device >= count)
+        return fail(PV_ERR_ARG, "hip_device " + std::to_string(hip_device) + " out of range");
+    HIP_TRY(hipSetDevice(hip_device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(PV_ERR_UNSUPPORTED, std::string("built for gfx950, device is ") + prop.gcnArchName);
+    pv_ctx *c = new pv_ctx();
+    c->device = hip_device;
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(PV_ERR_DEVICE, std::string("stream: ") + hipGetErrorString(e));
+    }
+    for (int i = 0; i < pv_ctx::kRing; ++i) HIP_TRY(hipEventCreateWithFlags(&c->stage_ev[i], hipEventDisableTiming));
+    *out = c;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_ctx_destroy(pv_ctx *c) {
+    if (!c) return PV_OK;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    hipFree(c->batch_dev);
+    hipFree(c->frames_dev);
+    hipFree(c->ns_dev);
+    hipFree(c->dirs_ptrs_dev);
+    hipFree(c->counters_dev);
+    hipFree(c->counts_dev);
+    for (int i = 0; i < pv_ctx::kRing; ++i) {
+        if (c->stage_host[i]) hipHostFree(c->stage_host[i]);
+        if (c->stage_ev[i]) hipEventDestroy(c->stage_ev[i]);
+    }
+    for (auto &t : c->pending) {
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    for (auto e : c->pool) hipEventDestroy(e);
+    hipStreamDestroy(c->stream);
+    delete c;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_ctx_set_timing(pv_ctx *c, int enable) {
+    if (!c) return fail(PV_ERR_ARG, "ctx is NULL");
+    c->timing = enable != 0;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_ctx_stage_times(pv_ctx *c, double *ms, uint64_t *launches) {
+    if (!c || !ms || !launches) return fail(PV_ERR_ARG, "NULL argument");
+    HIP_TRY(hipSetDevice(c->device));
+    for (int i = 0; i < PV_STAGE_COUNT; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    for (auto &t : c->pending) {
+        HIP_TRY(hipEventSynchronize(t.b));
+        float m = 0.f;
+        HIP_TRY(hipEventElapsedTime(&m, t.a, t.b));
+        ms[t.stage] += m;
+        launches[t.stage] += 1;
+        c->pool.push_back(t.a);
+        c->pool.push_back(t.b);
+    }
+    c->pending.clear();
+    return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// scene
+// ---------------------------------------------------------------------------
+static bool finite_all(const float *p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+static pv_status upload_bvh(const HostBvh &hb, DeviceBvh &db, hipStream_t s) {
+    db.n_nodes = (int)hb.nodes.size();
+    db.n_tris = (int)hb.tris.size();
+    PV_TRY(dev_alloc(&db.nodes, hb.nodes.size() * sizeof(GpuNode), "BVH nodes"));
+    PV_TRY(dev_alloc(&db.tris, hb.tris.size() * sizeof(GpuTri), "BVH triangles"));
+    if (db.n_nodes) HIP_TRY(hipMemcpyAsync(db.nodes, hb.nodes.data(), hb.nodes.size() * sizeof(GpuNode), hipMemcpyHostToDevice, s));
+    if (db.n_tris) HIP_TRY(hipMemcpyAsync(db.tris, hb.tris.data(), hb.tris.size() * sizeof(GpuTri), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PV_OK;
+}
+
+static pv_status validate_lights(int n, const pv_point_light *l) {
+    if (n < 0 || n > PV_MAX_LIGHTS) return fail(PV_ERR_ARG, "n_lights must be in [0, 8]");
+    if (n > 0 && !l) return fail(PV_ERR_ARG, "lights is NULL");
+    for (int i = 0; i < n; ++i)
+        if (!finite_all(l[i].pos, 3) || !finite_all(l[i].intensity, 3))
+            return fail(PV_ERR_ARG, "light " + std::to_string(i) + " is not finite");
+    return PV_OK;
+}
+
+static void destroy_scene(pv_scene *s) {
+    if (!s) return;
+    hipFree(s->stat.nodes);
+    hipFree(s->stat.tris);
+    hipFree(s->mats);
+    for (int i = 0; i < pv_scene::kRing; ++i) {
+        hipFree(s->dyn_nodes[i]);
+        hipFree(s->dyn_tris[i]);
+        if (s->dyn_stage[i]) hipHostFree(s->dyn_stage[i]);
+        if (s->dyn_use[i]) hipEventDestroy(s->dyn_use[i]);
+    }
+    delete s;
+}
+
+static pv_status set_dynamic_impl(pv_scene *s, const float *pos, hipStream_t st);
+
+extern "C" pv_status pv_scene_create(pv_ctx *ctx, const pv_scene_desc *d, pv_scene **out) {
+    if (!ctx || !d || !out) return fail(PV_ERR_ARG, "NULL argument");
+    if (d->n_triangles < 0 || d->n_vertices < 0) return fail(PV_ERR_ARG, "negative counts");
+    if (d->n_dynamic_triangles < 0 || d->n_dynamic_triangles > d->n_triangles)
+        return fail(PV_ERR_ARG, "n_dynamic_triangles must be in [0, n_triangles]");
+    if (d->n_triangles > 0 && (!d->positions || !d->indices || !d->albedo))
+        return fail(PV_ERR_ARG, "positions, indices and albedo are required");
+    if (d->n_vertices > 0 && !finite_all(d->positions, 3ull * d->n_vertices))
+        return fail(PV_ERR_ARG, "vertex positions must be finite");
+    PV_TRY(validate_lights(d->n_lights, d->lights));
+    const int T = d->n_triangles;
+    for (int64_t i = 0; i < 3ll * T; ++i)
+        if (d->indices[i] >= (uint32_t)d->n_vertices)
+            return fail(PV_ERR_ARG, "triangle index out of range at " + std::to_string(i));
+    if (T > 0 && !finite_all(d->albedo, 3ull * T)) return fail(PV_ERR_ARG, "albedo must be finite");
+    if (T > 0 && d->emission && !finite_all(d->emission, 3ull * T)) return fail(PV_ERR_ARG, "emission must be finite");
+    HIP_TRY(hipSetDevice(ctx->device));
+    pv_scene *s = new pv_scene();
+    s->ctx = ctx;
+    s->n_dyn = d->n_dynamic_triangles;
+    s->n_static = T - s->n_dyn;
+    s->lights.assign(d->lights, d->lights + d->n_lights);
+    std::vector<float> tri9((size_t)T * 9);
+    for (int t = 0; t < T; ++t)
+        for (int v = 0; v < 3; ++v)
+            for (int k = 0; k < 3; ++k) tri9[9 * (size_t)t + 3 * v + k] = d->positions[3 * (size_t)d->indices[3 * (size_t)t + v] + k];
+    // shadow offset from the static bounding box (all triangles if none is static)
+    const int ns = s->n_static > 0 ? s->n_static : T;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int t = 0; t < ns; ++t)
+        for (int v = 0; v < 3; ++v)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], (double)tri9[9 * (size_t)t + 3 * v + k]);
+                hi[k] = std::max(hi[k], (double)tri9[9 * (size_t)t + 3 * v + k]);
+            }
+    double diag = ns > 0 ? std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                     (hi[2] - lo[2]) * (hi[2] - lo[2]))
+                         : 1.0;
+    s->eps = (float)(1e-4 * diag);
+    HostBvh hb;
+    std::string err;
+    if (!build_bvh(tri9.data(), s->n_static, 0, hb, err)) {
+        destroy_scene(s);
+        return fail(PV_ERR_ARG, err);
+    }
+    pv_status st = upload_bvh(hb, s->stat, ctx->stream);
+    if (st != PV_OK) {
+        destroy_scene(s);
+        return st;
+    }
+    std::vector<float4> mats((size_t)std::max(T, 1) * 2);
+    for (int t = 0; t < T; ++t) {
+        mats[2 * t] = make_float4(d->albedo[3 * t], d->albedo[3 * t + 1], d->albedo[3 * t + 2], 0.f);
+        mats[2 * t + 1] = d->emission ? make_float4(d->emission[3 * t], d->emission[3 * t + 1], d->emission[3 * t + 2], 0.f)
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    st = dev_alloc(&s->mats, mats.size() * sizeof(float4), "materials");
+    if (st != PV_OK) {
+        destroy_scene(s);
+        return st;
+    }
+    hipError_t e = hipMemcpy(s->mats, mats.data(), mats.size() * sizeof(float4), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        destroy_scene(s);
+        return fail(PV_ERR_DEVICE, std::string("materials upload: ") + hipGetErrorString(e));
+    }
+    if (s->n_dyn > 0) {
+        s->dyn_node_cap = (size_t)s->n_dyn;  // a binary tree over n leaves has < n inner nodes
+        for (int i = 0; i < pv_scene::kRing; ++i) {
+            st = dev_alloc(&s->dyn_nodes[i], s->dyn_node_cap * sizeof(GpuNode), "dynamic BVH nodes");
+            if (st == PV_OK) st = dev_alloc(&s->dyn_tris[i], (size_t)s->n_dyn * sizeof(GpuTri), "dynamic triangles");
+            if (st == PV_OK && hipHostMalloc(&s->dyn_stage[i], s->dyn_node_cap * sizeof(GpuNode) + (size_t)s->n_dyn * sizeof(GpuTri)) != hipSuccess)
+                st = fail(PV_ERR_OOM, "pinned staging for dynamic triangles");
+            if (st == PV_OK && hipEventCreateWithFlags(&s->dyn_use[i], hipEventDisableTiming) != hipSuccess)
+                st = fail(PV_ERR_DEVICE, "event");
+            if (st != PV_OK) {
+                destroy_scene(s);
+                return st;
+            }
+        }
+        s->dyn_slot = pv_scene::kRing - 1;
+        st = set_dynamic_impl(s, tri9.data() + 9 * (size_t)s->n_static, ctx->stream);
+        if (st == PV_OK) st = hipStreamSynchronize(ctx->stream) == hipSuccess ? PV_OK : fail(PV_ERR_DEVICE, "sync");
+        if (st != PV_OK) {
+            destroy_scene(s);
+            return st;
+        }
+    }
+    *out = s;
+    return PV_OK;
+}
+
+static pv_status set_dynamic_impl(pv_scene *s, const float *pos, hipStream_t st) {
+    if (!finite_all(pos, 9ull * s->n_dyn)) return fail(PV_ERR_ARG, "dynamic positions must be finite");
+    HostBvh hb;
+    std::string err;
+    if (!build_bvh(pos, s->n_dyn, s->n_static, hb, err)) return fail(PV_ERR_ARG, err);
+    if (hb.nodes.size() > s->dyn_node_cap) return fail(PV_ERR_STATE, "dynamic BVH larger than its slot");
+    const int k = (s->dyn_slot + 1) % pv_scene::kRing;
+    // the slot may still be read by earlier work: wait for its last use
+    if (s->dyn_used[k]) HIP_TRY(hipEventSynchronize(s->dyn_use[k]));
+    char *stage = (char *)s->dyn_stage[k];
+    const size_t nb = hb.nodes.size() * sizeof(GpuNode), tb = hb.tris.size() * sizeof(GpuTri);
+    std::memcpy(stage, hb.nodes.data(), nb);
+    std::memcpy(stage + s->dyn_node_cap * sizeof(GpuNode), hb.tris.data(), tb);
+    HIP_TRY(hipMemcpyAsync(s->dyn_nodes[k], stage, nb, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->dyn_tris[k], stage + s->dyn_node_cap * sizeof(GpuNode), tb, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(s->dyn_use[k], st));
+    s->dyn_used[k] = true;
+    s->dyn_nodes_n[k] = (int)hb.nodes.size();
+    s->dyn_slot = k;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_scene_set_dynamic(pv_scene *s, const float *positions, void *stream) {
+    if (!s || !positions) return fail(PV_ERR_ARG, "NULL argument");
+    if (s->n_dyn == 0) return fail(PV_ERR_STATE, "scene has no dynamic triangles");
+    HIP_TRY(hipSetDevice(s->ctx->device));
+    return set_dynamic_impl(s, positions, pick(s->ctx, stream));
+}
+
+extern "C" pv_status pv_scene_destroy(pv_scene *s) {
+    if (!s) return PV_OK;
+    hipSetDevice(s->ctx->device);
+    hipDeviceSynchronize();
+    destroy_scene(s);
+    return PV_OK;
+}
+
+static SceneView scene_view(pv_scene *s) {
+    SceneView v;
+    v.stat = s->stat;
+    v.dyn = DeviceBvh();
+    if (s->n_dyn > 0) {
+        v.dyn.nodes = s->dyn_nodes[s->dyn_slot];
+        v.dyn.tris = s->dyn_tris[s->dyn_slot];
+        v.dyn.n_nodes = s->dyn_nodes_n[s->dyn_slot];
+        v.dyn.n_tris = s->n_dyn;
+    }
+    v.mats = s->mats;
+    v.eps = s->eps;
+    return v;
+}
+
+static pv_status note_scene_use(pv_scene *s, hipStream_t st) {
+    if (s->n_dyn > 0) HIP_TRY(hipEventRecord(s->dyn_use[s->dyn_slot], st));
+    return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// volume
+// ---------------------------------------------------------------------------
+static pv_status validate_desc(const pv_volume_desc *d) {
+    if (!d) return fail(PV_ERR_ARG, "desc is NULL");
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(PV_ERR_ARG, "grid dimensions must be >= 1");
+    const long long P = (long long)d->nx * d->ny * d->nz;
+    if (P > PV_MAX_PROBES) return fail(PV_ERR_ARG, "at most 65536 probes per volume (2-byte probe index)");
+    if (d->rays_per_probe < 1 || d->rays_per_probe > PV_MAX_RAYS) return fail(PV_ERR_ARG, "rays_per_probe must be in [1, 4096]");
+    if (!(d->hysteresis >= 0.f && d->hysteresis < 1.f)) return fail(PV_ERR_ARG, "hysteresis must be in [0, 1)");
+    if (!(d->max_distance > 0.f) || !std::isfinite(d->max_distance)) return fail(PV_ERR_ARG, "max_distance must be finite and > 0");
+    if (d->vis_sharpness < 1 || d->vis_sharpness > 128) return fail(PV_ERR_ARG, "vis_sharpness must be in [1, 128]");
+    if (d->format != PV_MAP_FP32 && d->format != PV_MAP_FP16) return fail(PV_ERR_ARG, "unknown map format");
+    if (!finite_all(d->origin, 3) || !finite_all(d->spacing, 3) || !finite_all(d->sky, 3))
+        return fail(PV_ERR_ARG, "origin, spacing and sky must be finite");
+    if (d->irr_res != 8 || d->vis_res != 16)
+        return fail(PV_ERR_UNSUPPORTED, "this build supports irr_res = 8 and vis_res = 16");
+    if (d->flags & ~(PV_FIRST_FRAME_NO_HISTORY | PV_KEEP_HITS)) return fail(PV_ERR_ARG, "unknown flags");
+    return PV_OK;
+}
+
+static uint64_t volume_bytes(const pv_volume_desc *d) {
+    const int P = d->nx * d->ny * d->nz, n = d->rays_per_probe;
+    const size_t elem = d->format == PV_MAP_FP16 ? 2 : 4;
+    uint64_t b = irr_bytes(P, elem) + vis_bytes(P, elem) + (uint64_t)P * n * 16 + (uint64_t)n * 16;
+    if (d->flags & PV_KEEP_HITS) b += (uint64_t)P * n * 4;
+    return b;
+}
+
+extern "C" pv_status pv_volume_footprint(const pv_volume_desc *d, uint64_t *bytes) {
+    PV_TRY(validate_desc(d));
+    if (!bytes) return fail(PV_ERR_ARG, "bytes is NULL");
+    *bytes = volume_bytes(d);
+    return PV_OK;
+}
+
+static void free_volume(pv_volume *v) {
+    hipFree(v->irr);
+    hipFree(v->vis);
+    hipFree(v->rays);
+    hipFree(v->dirs);
+    hipFree(v->hits);
+    delete v;
+}
+
+extern "C" pv_status pv_create_volume(pv_ctx *ctx, const pv_volume_desc *d, pv_volume **out) {
+    if (!ctx || !out) return fail(PV_ERR_ARG, "NULL argument");
+    PV_TRY(validate_desc(d));
+    HIP_TRY(hipSetDevice(ctx->device));
+    pv_volume *v = new pv_volume();
+    v->ctx = ctx;
+    v->desc = *d;
+    v->P = d->nx * d->ny * d->nz;
+    v->n = d->rays_per_probe;
+    v->elem = d->format == PV_MAP_FP16 ? 2 : 4;
+    pv_status st = dev_alloc(&v->irr, irr_bytes(v->P, v->elem), "irradiance maps");
+    if (st == PV_OK) st = dev_alloc(&v->vis, vis_bytes(v->P, v->elem), "visibility maps");
+    if (st == PV_OK) st = dev_alloc(&v->rays, (size_t)v->P * v->n * 16, "ray buffer");
+    if (st == PV_OK) st = dev_alloc(&v->dirs, (size_t)v->n * 16, "directions");
+    if (st == PV_OK && (d->flags & PV_KEEP_HITS)) st = dev_alloc(&v->hits, (size_t)v->P * v->n * 4, "hit ids");
+    if (st == PV_OK && launch_zero(v->irr, irr_bytes(v->P, v->elem), ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "zero fill");
+    if (st == PV_OK && launch_zero(v->vis, vis_bytes(v->P, v->elem), ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "zero fill");
+    if (st == PV_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "sync after zero fill");
+    if (st != PV_OK) {
+        free_volume(v);
+        return st;
+    }
+    *out = v;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_volume_destroy(pv_volume *v) {
+    if (!v) return PV_OK;
+    hipSetDevice(v->ctx->device);
+    hipDeviceSynchronize();
+    free_volume(v);
+    return PV_OK;
+}
+
+extern "C" pv_status pv_set_scene(pv_volume *v, pv_scene *s) {
+    if (!v || !s) return fail(PV_ERR_ARG, "NULL argument");
+    if (s->ctx != v->ctx) return fail(PV_ERR_ARG, "scene and volume belong to different contexts");
+    v->scene = s;
+    return PV_OK;
+}
+
+static pv_status frame_params(const pv_frame *f, const pv_scene *s, FrameParams &fp) {
+    if (!f) return fail(PV_ERR_ARG, "frame is NULL");
+    if (!finite_all(f->rotation, 9)) return fail(PV_ERR_ARG, "rotation must be finite");
+    // a proper rotation: orthonormal rows to FP32 rounding
+    const float *R = f->rotation;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double dot = (double)R[3 * a] * R[3 * b] + (double)R[3 * a + 1] * R[3 * b + 1] + (double)R[3 * a + 2] * R[3 * b + 2];
+            if (std::fabs(dot - (a == b ? 1.0 : 0.0)) > 1e-4) return fail(PV_ERR_ARG, "rotation is not orthonormal");
+        }
+    std::memcpy(fp.rot, R, sizeof(fp.rot));
+    const pv_point_light *L = f->lights;
+    int nl = f->n_lights;
+    if (nl == 0 && !L && s) {
+        L = s->lights.data();
+        nl = (int)s->lights.size();
+    }
+    PV_TRY(validate_lights(nl, L));
+    fp.n_lights = nl;
+    for (int i = 0; i < nl; ++i)
+        for (int k = 0; k < 3; ++k) {
+            fp.light_pos[i][k] = L[i].pos[k];
+            fp.light_int[i][k] = L[i].intensity[k];
+        }
+    return PV_OK;
+}
+
+static VolumeParams volume_params(const pv_volume *v) {
+    VolumeParams p;
+    const pv_volume_desc &d = v->desc;
+    p.nx = d.nx;
+    p.ny = d.ny;
+    p.nz = d.nz;
+    p.P = v->P;
+    p.n = v->n;
+    p.ox = d.origin[0];
+    p.oy = d.origin[1];
+    p.oz = d.origin[2];
+    p.sx = d.spacing[0];
+    p.sy = d.spacing[1];
+    p.sz = d.spacing[2];
+    p.max_distance = d.max_distance;
+    for (int k = 0; k < 3; ++k) p.sky[k] = d.sky[k];
+    p.vis_sharpness = d.vis_sharpness;
+    return p;
+}
+
+static float effective_h(const pv_volume *v) {
+    return (v->frame == 0 && (v->desc.flags & PV_FIRST_FRAME_NO_HISTORY)) ? 0.f : v->desc.hysteresis;
+}
+
+extern "C" pv_status pv_update_probes(pv_volume *v, const pv_frame *f, void *stream) {
+    if (!v) return fail(PV_ERR_ARG, "volume is NULL");
+    if (!v->scene) return fail(PV_ERR_STATE, "no scene set on the volume");
+    FrameParams fp;
+    PV_TRY(frame_params(f, v->scene, fp));
+    HIP_TRY(hipSetDevice(v->ctx->device));
+    hipStream_t s = pick(v->ctx, stream);
+    const VolumeParams vp = volume_params(v);
+    pv_ctx *c = v->ctx;
+    const SceneView sv = scene_view(v->scene);
+    const int fp16 = v->desc.format == PV_MAP_FP16;
+    const float h = effective_h(v);
+    HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s, [&] { return launch_raydirs(fp, v->n, v->dirs, s); }));
+    HIP_TRY(timed(c, PV_STAGE_TRACE, s, [&] { return launch_trace(vp, sv, fp, v->dirs, v->rays, v->hits, nullptr, s); }));
+    HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend(vp, v->dirs, v->rays, v->irr, v->vis, fp16, h, s); }));
+    PV_TRY(note_scene_use(v->scene, s));
+    v->frame++;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_trace_counts(pv_volume *v, const pv_frame *f, uint64_t counts[3]) {
+    if (!v || !counts) return fail(PV_ERR_ARG, "NULL argument");
+    if (!v->scene) return fail(PV_ERR_STATE, "no scene set on the volume");
+    FrameParams fp;
+    PV_TRY(frame_params(f, v->scene, fp));
+    HIP_TRY(hipSetDevice(v->ctx->device));
+    pv_ctx *c = v->ctx;
+    if (!c->counts_dev) PV_TRY(dev_alloc(&c->counts_dev, 4 * sizeof(unsigned long long), "counters"));
+    hipStream_t s = c->stream;
+    HIP_TRY(launch_zero(c->counts_dev, 4 * sizeof(unsigned long long), s));
+    const VolumeParams vp = volume_params(v);
+    HIP_TRY(launch_raydirs(fp, v->n, v->dirs, s));
+    HIP_TRY(launch_trace(vp, scene_view(v->scene), fp, v->dirs, v->rays, v->hits, c->counts_dev, s));
+    PV_TRY(note_scene_use(v->scene, s));
+    unsigned long long host[4];
+    HIP_TRY(hipMemcpyAsync(host, c->counts_dev, sizeof(host), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < 3; ++i) counts[i] = host[i];
+    return PV_OK;
+}
+
+extern "C" pv_status pv_blend_rays(pv_volume *v, const pv_frame *f, const void *rays_dev, void *stream) {
+    if (!v || !rays_dev) return fail(PV_ERR_ARG, "NULL argument");
+    FrameParams fp;
+    PV_TRY(frame_params(f, v->scene, fp));
+    HIP_TRY(hipSetDevice(v->ctx->device));
+    hipStream_t s = pick(v->ctx, stream);
+    const VolumeParams vp = volume_params(v);
+    HIP_TRY(launch_raydirs(fp, v->n, v->dirs, s));
+    HIP_TRY(launch_blend(vp, v->dirs, (const float4 *)rays_dev, v->irr, v->vis, v->desc.format == PV_MAP_FP16,
+                         effective_h(v), s));
+    v->frame++;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_get_maps(pv_volume *v, void **irr, void **vis) {
+    if (!v || !irr || !vis) return fail(PV_ERR_ARG, "NULL argument");
+    *irr = v->irr;
+    *vis = v->vis;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_get_rays(pv_volume *v, void **rays, void **hits, void **dirs) {
+    if (!v) return fail(PV_ERR_ARG, "NULL argument");
+    if (rays) *rays = v->rays;
+    if (hits) *hits = v->hits;
+    if (dirs) *dirs = v->dirs;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_set_maps(pv_volume *v, const void *irr, const void *vis, int64_t frame) {
+    if (!v || !irr || !vis) return fail(PV_ERR_ARG, "NULL argument");
+    if (frame < 0) return fail(PV_ERR_ARG, "frame must be >= 0");
+    HIP_TRY(hipSetDevice(v->ctx->device));
+    HIP_TRY(hipStreamSynchronize(v->ctx->stream));
+    HIP_TRY(hipMemcpy(v->irr, irr, irr_bytes(v->P, v->elem), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(v->vis, vis, vis_bytes(v->P, v->elem), hipMemcpyHostToDevice));
+    v->frame = frame;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_read_maps(pv_volume *v, void *irr, void *vis, int64_t *frame) {
+    if (!v || !irr || !vis) return fail(PV_ERR_ARG, "NULL argument");
+    HIP_TRY(hipSetDevice(v->ctx->device));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(irr, v->irr, irr_bytes(v->P, v->elem), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(vis, v->vis, vis_bytes(v->P, v->elem), hipMemcpyDeviceToHost));
+    if (frame) *frame = v->frame;
+    return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched update
+// ---------------------------------------------------------------------------
+static pv_status ensure_batch(pv_ctx *c, int n) {
+    if (n <= c->batch_cap) return PV_OK;
+    hipFree(c->batch_dev);
+    hipFree(c->frames_dev);
+    hipFree(c->ns_dev);
+    hipFree(c->dirs_ptrs_dev);
+    hipFree(c->counters_dev);
+    c->batch_dev = nullptr;
+    c->frames_dev = nullptr;
+    c->ns_dev = nullptr;
+    c->dirs_ptrs_dev = nullptr;
+    c->counters_dev = nullptr;
+    c->batch_cap = 0;
+    PV_TRY(dev_alloc(&c->batch_dev, sizeof(BatchVolume) * n, "batch descriptors"));
+    PV_TRY(dev_alloc(&c->frames_dev, sizeof(FrameParams) * n, "batch frames"));
+    PV_TRY(dev_alloc(&c->ns_dev, sizeof(int) * n, "batch ray counts"));
+    PV_TRY(dev_alloc(&c->dirs_ptrs_dev, sizeof(float4 *) * n, "batch direction pointers"));
+    PV_TRY(dev_alloc(&c->counters_dev, sizeof(int) * (2 + n), "batch counters"));
+    // a fresh status word
+    HIP_TRY(launch_zero(c->counters_dev, sizeof(int) * (2 + n), c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const size_t bytes = (sizeof(BatchVolume) + sizeof(FrameParams) + sizeof(int) + sizeof(float4 *)) * n + 256;
+    for (int i = 0; i < pv_ctx::kRing; ++i) {
+        if (c->stage_host[i]) {
+            hipEventSynchronize(c->stage_ev[i]);
+            hipHostFree(c->stage_host[i]);
+        }
+        c->stage_host[i] = nullptr;
+        HIP_TRY(hipHostMalloc(&c->stage_host[i], bytes));
+    }
+    c->stage_bytes = bytes;
+    c->batch_cap = n;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_frame *frames, int n, void *stream) {
+    if (!vols || !frames || n < 1) return fail(PV_ERR_ARG, "need at least one volume and frame");
+    pv_ctx *c = vols[0] ? vols[0]->ctx : nullptr;
+    if (!c) return fail(PV_ERR_ARG, "volume 0 is NULL");
+    for (int i = 0; i < n; ++i) {
+        if (!vols[i]) return fail(PV_ERR_ARG, "volume " + std::to_string(i) + " is NULL");
+        if (vols[i]->ctx != c) return fail(PV_ERR_ARG, "volumes belong to different contexts");
+        if (!vols[i]->scene) return fail(PV_ERR_STATE, "volume " + std::to_string(i) + " has no scene");
+        for (int k = 0; k < i; ++k)
+            if (vols[k] == vols[i]) return fail(PV_ERR_ARG, "a volume appears twice in one batch");
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = pick(c, stream);
+    PV_TRY(ensure_batch(c, n));
+    std::vector<BatchVolume> bv(n);
+    std::vector<FrameParams> fps(n);
+    std::vector<int> ns(n);
+    std::vector<float4 *> dps(n);
+    int waves = 0, blend = 0;
+    for (int i = 0; i < n; ++i) {
+        pv_volume *v = vols[i];
+        PV_TRY(frame_params(&frames[i], v->scene, fps[i]));
+        BatchVolume &b = bv[i];
+        b.vp = volume_params(v);
+        b.sv = scene_view(v->scene);
+        b.dirs = v->dirs;
+        b.rays = v->rays;
+        b.hits = v->hits;
+        b.irr = v->irr;
+        b.vis = v->vis;
+        b.h = effective_h(v);
+        b.fp16 = v->desc.format == PV_MAP_FP16;
+        b.bricks_x = (v->desc.nx + 3) / 4;
+        b.bricks_y = (v->desc.ny + 3) / 4;
+        b.bricks_z = (v->desc.nz + 3) / 4;
+        b.n_waves = b.bricks_x * b.bricks_y * b.bricks_z * v->n;
+        // trace items hold 4 waves; each volume starts on an item boundary
+        waves = (waves + 3) / 4 * 4;
+        b.first_wave = waves;
+        waves += b.n_waves;
+        b.n_blend = (v->P + 3) / 4;
+        b.first_blend = blend;
+        blend += b.n_blend;
+        ns[i] = v->n;
+        dps[i] = v->dirs;
+    }
+    // stage descriptors through pinned memory (ring; wait for the slot's last copy)
+    const int k = c->stage_next;
+    c->stage_next = (k + 1) % pv_ctx::kRing;
+    HIP_TRY(hipEventSynchronize(c->stage_ev[k]));
+    char *h = (char *)c->stage_host[k];
+    size_t off = 0;
+    auto put = [&](const void *src, size_t bytes) {
+        std::memcpy(h + off, src, bytes);
+        size_t o = off;
+        off += (bytes + 15) / 16 * 16;
+        return o;
+    };
+    const size_t o_b = put(bv.data(), sizeof(BatchVolume) * n);
+    const size_t o_f = put(fps.data(), sizeof(FrameParams) * n);
+    const size_t o_n = put(ns.data(), sizeof(int) * n);
+    const size_t o_d = put(dps.data(), sizeof(float4 *) * n);
+    HIP_TRY(hipMemcpyAsync(c->batch_dev, h + o_b, sizeof(BatchVolume) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c->frames_dev, h + o_f, sizeof(FrameParams) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c->ns_dev, h + o_n, sizeof(int) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c->dirs_ptrs_dev, h + o_d, sizeof(float4 *) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(c->stage_ev[k], s));
+    // queue counter and per-volume done counters start at zero (status word kept)
+    HIP_TRY(launch_zero(c->counters_dev, sizeof(int), s));
+    HIP_TRY(launch_zero(c->counters_dev + 2, sizeof(int) * n, s));
+    HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s, [&] { return launch_raydirs_batched(c->frames_dev, c->ns_dev, c->dirs_ptrs_dev, n, s); }));
+    HIP_TRY(timed(c, PV_STAGE_BATCHED, s, [&] {
+        return launch_batched(c->batch_dev, n, waves, blend, c->frames_dev, c->counters_dev, c->counters_dev + 2,
+                              c->counters_dev + 1, s);
+    }));
+    for (int i = 0; i < n; ++i) {
+        PV_TRY(note_scene_use(vols[i]->scene, s));
+        vols[i]->frame++;
+    }
+    return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// client + pack
+// ---------------------------------------------------------------------------
+extern "C" pv_status pv_client_footprint(const pv_volume_desc *d, uint64_t *bytes) {
+    PV_TRY(validate_desc(d));
+    if (!bytes) return fail(PV_ERR_ARG, "bytes is NULL");
+    const uint64_t P = (uint64_t)d->nx * d->ny * d->nz;
+    *bytes = P * (192 + 512) * 2 + P * 2 + P * 8 + packet_capacity((int)P);
+    return PV_OK;
+}
+
+static void free_client(pv_client *c) {
+    hipFree(c->ref_irr);
+    hipFree(c->ref_vis);
+    hipFree(c->mask_irr);
+    hipFree(c->mask_vis);
+    hipFree(c->rank_irr);
+    hipFree(c->rank_vis);
+    hipFree(c->packet);
+    if (c->hdr_host) hipHostFree(c->hdr_host);
+    delete c;
+}
+
+extern "C" pv_status pv_client_create(pv_volume *v, uint32_t id, pv_client **out) {
+    if (!v || !out) return fail(PV_ERR_ARG, "NULL argument");
+    if (v->desc.format != PV_MAP_FP16)
+        return fail(PV_ERR_UNSUPPORTED, "delta packing is defined on FP16 maps (FP32 byte planes not built)");
+    HIP_TRY(hipSetDevice(v->ctx->device));
+    pv_client *c = new pv_client();
+    c->vol = v;
+    c->id = id;
+    const int P = v->P;
+    c->packet_cap = packet_capacity(P);
+    pv_status st = dev_alloc(&c->ref_irr, (size_t)P * 192 * 2, "irradiance reference");
+    if (st == PV_OK) st = dev_alloc(&c->ref_vis, (size_t)P * 512 * 2, "visibility reference");
+    if (st == PV_OK) st = dev_alloc(&c->mask_irr, (size_t)P, "mask");
+    if (st == PV_OK) st = dev_alloc(&c->mask_vis, (size_t)P, "mask");
+    if (st == PV_OK) st = dev_alloc(&c->rank_irr, (size_t)P * 4, "ranks");
+    if (st == PV_OK) st = dev_alloc(&c->rank_vis, (size_t)P * 4, "ranks");
+    if (st == PV_OK) st = dev_alloc(&c->packet, c->packet_cap, "packet");
+    if (st == PV_OK && hipHostMalloc((void **)&c->hdr_host, 32) != hipSuccess) st = fail(PV_ERR_OOM, "pinned header");
+    hipStream_t s = v->ctx->stream;
+    if (st == PV_OK && (launch_zero(c->ref_irr, (size_t)P * 192 * 2, s) != hipSuccess ||
+                        launch_zero(c->ref_vis, (size_t)P * 512 * 2, s) != hipSuccess ||
+                        launch_zero(c->packet, 32, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess))
+        st = fail(PV_ERR_DEVICE, "client initialisation");
+    if (st != PV_OK) {
+        free_client(c);
+        return st;
+    }
+    *out = c;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_client_destroy(pv_client *c) {
+    if (!c) return PV_OK;
+    hipSetDevice(c->vol->ctx->device);
+    hipDeviceSynchronize();
+    free_client(c);
+    return PV_OK;
+}
+
+extern "C" pv_status pv_client_reset(pv_client *c, void *stream) {
+    if (!c) return fail(PV_ERR_ARG, "client is NULL");
+    HIP_TRY(hipSetDevice(c->vol->ctx->device));
+    hipStream_t s = pick(c->vol->ctx, stream);
+    HIP_TRY(launch_zero(c->ref_irr, (size_t)c->vol->P * 192 * 2, s));
+    HIP_TRY(launch_zero(c->ref_vis, (size_t)c->vol->P * 512 * 2, s));
+    return PV_OK;
+}
+
+extern "C" pv_status pv_pack_delta(pv_client *c, float tau_irr, float tau_vis, void *stream) {
+    if (!c) return fail(PV_ERR_ARG, "client is NULL");
+    if (!(tau_irr >= 0.f) || !(tau_vis >= 0.f) || !std::isfinite(tau_irr) || !std::isfinite(tau_vis))
+        return fail(PV_ERR_ARG, "thresholds must be finite and >= 0");
+    pv_volume *v = c->vol;
+    HIP_TRY(hipSetDevice(v->ctx->device));
+    hipStream_t s = pick(v->ctx, stream);
+    PackBuffers b;
+    b.cur_irr = (const uint16_t *)v->irr;
+    b.cur_vis = (const uint16_t *)v->vis;
+    b.ref_irr = c->ref_irr;
+    b.ref_vis = c->ref_vis;
+    b.mask_irr = c->mask_irr;
+    b.mask_vis = c->mask_vis;
+    b.rank_irr = c->rank_irr;
+    b.rank_vis = c->rank_vis;
+    b.packet = c->packet;
+    pv_ctx *cx = v->ctx;
+    const int P = v->P;
+    const uint32_t id = c->id, seq = c->seq;
+    HIP_TRY(timed(cx, PV_STAGE_PACK_MASK, s, [&] { return launch_pack_mask(b, P, tau_irr, tau_vis, s); }));
+    HIP_TRY(timed(cx, PV_STAGE_PACK_SCAN, s, [&] { return launch_pack_scan(b, P, id, seq, s); }));
+    HIP_TRY(timed(cx, PV_STAGE_PACK_COMPACT, s, [&] { return launch_pack_compact(b, P, s); }));
+    c->seq++;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_packet_device(pv_client *c, const void **p, uint64_t *cap) {
+    if (!c || !p || !cap) return fail(PV_ERR_ARG, "NULL argument");
+    *p = c->packet;
+    *cap = c->packet_cap;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_get_masks(pv_client *c, void **mi, void **mv) {
+    if (!c || !mi || !mv) return fail(PV_ERR_ARG, "NULL argument");
+    *mi = c->mask_irr;
+    *mv = c->mask_vis;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_packet_download(pv_client *c, void *host, uint64_t cap, uint64_t *bytes, void *stream) {
+    if (!c || !bytes) return fail(PV_ERR_ARG, "NULL argument");
+    HIP_TRY(hipSetDevice(c->vol->ctx->device));
+    hipStream_t s = pick(c->vol->ctx, stream);
+    HIP_TRY(hipMemcpyAsync(c->hdr_host, c->packet, 32, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t K_irr = c->hdr_host[5], K_vis = c->hdr_host[6];
+    if (c->hdr_host[0] != 0x4B505650u) return fail(PV_ERR_STATE, "no packet has been built");
+    const uint64_t idx = ((2ull * (K_irr + K_vis) + 15) / 16) * 16;
+    const uint64_t total = 32 + idx + (uint64_t)K_irr * 384 + (uint64_t)K_vis * 1024;
+    *bytes = total;
+    if (!host || cap < total) return fail(PV_ERR_CAPACITY, "packet needs " + std::to_string(total) + " bytes");
+    std::memcpy(host, c->hdr_host, 32);
+    if (total > 32) HIP_TRY(hipMemcpyAsync((char *)host + 32, c->packet + 32, total - 32, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PV_OK;
+}
+
+extern "C" pv_status pv_sync(void *stream) {
+    hipError_t e = stream ? hipStreamSynchronize((hipStream_t)stream) : hipDeviceSynchronize();
+    if (e != hipSuccess) return fail(PV_ERR_DEVICE, std::string("device error: ") + hipGetErrorString(e));
+    return PV_OK;
+}
+
+extern "C" pv_status pv_ctx_check(pv_ctx *c, int *status) {
+    // status word of the batched work queue (1 = a bounded wait expired)
+    if (!c || !status) return fail(PV_ERR_ARG, "NULL argument");
+    *status = 0;
+    if (!c->counters_dev) return PV_OK;
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    int st = 0;
+    HIP_TRY(hipMemcpy(&st, c->counters_dev + 1, sizeof(int), hipMemcpyDeviceToHost));
+    *status = st;
+    return PV_OK;
+}

@@ -1,0 +1,464 @@
+"""ctypes binding of ``libprobestream.so`` (argument marshalling only).
+
+Names follow the C ABI: ``Context`` (pv_ctx), ``Scene`` (pv_scene),
+``Volume`` (pv_volume: ``update_probes``, ``blend_rays``, ``get_maps`` ...),
+``Client`` (pv_client: ``pack_delta``, ``packet_download`` ...).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(HERE, "libprobestream.so")
+
+PV_OK = 0
+PV_MAP_FP32 = 0
+PV_MAP_FP16 = 1
+PV_FIRST_FRAME_NO_HISTORY = 1
+PV_KEEP_HITS = 2
+PV_MAX_LIGHTS = 8
+
+# every symbol include/probestream.h declares
+EXPORTED_SYMBOLS = [
+    "pv_last_error", "pv_version", "pv_ctx_create", "pv_ctx_destroy", "pv_scene_create",
+    "pv_scene_set_dynamic", "pv_scene_destroy", "pv_create_volume", "pv_volume_destroy",
+    "pv_volume_footprint", "pv_set_scene", "pv_update_probes", "pv_update_probes_batched",
+    "pv_blend_rays", "pv_get_maps", "pv_get_rays", "pv_set_maps", "pv_read_maps",
+    "pv_client_create", "pv_client_destroy", "pv_client_reset", "pv_client_footprint",
+    "pv_pack_delta", "pv_packet_device", "pv_packet_download", "pv_get_masks", "pv_sync",
+    "pv_ctx_check", "pv_trace_counts", "pv_ctx_set_timing", "pv_ctx_stage_times",
+]
+
+STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched"]
+
+
+class NativeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"probestream status {status}: {msg}")
+        self.status = status
+
+
+class VolumeDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("origin", ctypes.c_float * 3), ("spacing", ctypes.c_float * 3),
+                ("rays_per_probe", ctypes.c_int), ("irr_res", ctypes.c_int), ("vis_res", ctypes.c_int),
+                ("hysteresis", ctypes.c_float), ("max_distance", ctypes.c_float),
+                ("vis_sharpness", ctypes.c_int), ("format", ctypes.c_int),
+                ("sky", ctypes.c_float * 3), ("flags", ctypes.c_uint32)]
+
+
+class PointLight(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_float * 3), ("intensity", ctypes.c_float * 3)]
+
+
+class SceneDesc(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int), ("positions", ctypes.c_void_p),
+                ("n_triangles", ctypes.c_int), ("indices", ctypes.c_void_p),
+                ("albedo", ctypes.c_void_p), ("emission", ctypes.c_void_p),
+                ("n_dynamic_triangles", ctypes.c_int), ("n_lights", ctypes.c_int),
+                ("lights", ctypes.c_void_p)]
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("rotation", ctypes.c_float * 9), ("n_lights", ctypes.c_int),
+                ("lights", ctypes.POINTER(PointLight))]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _SO
+
+
+def build(verbose: bool = False) -> str:
+    from . import native_build as _b
+    return _b.build(verbose=verbose)
+
+
+def lib():
+    """Load the native library; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        raise ImportError(f"native library {_SO} is missing: build it first "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(_SO)
+    vp, i32, u32, u64, f32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float
+    P = ctypes.POINTER
+    sig = {
+        "pv_last_error": ([], ctypes.c_char_p),
+        "pv_version": ([], ctypes.c_char_p),
+        "pv_ctx_create": ([i32, P(vp)], i32),
+        "pv_ctx_destroy": ([vp], i32),
+        "pv_scene_create": ([vp, P(SceneDesc), P(vp)], i32),
+        "pv_scene_set_dynamic": ([vp, vp, vp], i32),
+        "pv_scene_destroy": ([vp], i32),
+        "pv_create_volume": ([vp, P(VolumeDesc), P(vp)], i32),
+        "pv_volume_destroy": ([vp], i32),
+        "pv_volume_footprint": ([P(VolumeDesc), P(u64)], i32),
+        "pv_set_scene": ([vp, vp], i32),
+        "pv_update_probes": ([vp, P(Frame), vp], i32),
+        "pv_update_probes_batched": ([P(vp), P(Frame), i32, vp], i32),
+        "pv_blend_rays": ([vp, P(Frame), vp, vp], i32),
+        "pv_get_maps": ([vp, P(vp), P(vp)], i32),
+        "pv_get_rays": ([vp, P(vp), P(vp), P(vp)], i32),
+        "pv_set_maps": ([vp, vp, vp, ctypes.c_int64], i32),
+        "pv_read_maps": ([vp, vp, vp, P(ctypes.c_int64)], i32),
+        "pv_client_create": ([vp, u32, P(vp)], i32),
+        "pv_client_destroy": ([vp], i32),
+        "pv_client_reset": ([vp, vp], i32),
+        "pv_client_footprint": ([P(VolumeDesc), P(u64)], i32),
+        "pv_pack_delta": ([vp, f32, f32, vp], i32),
+        "pv_packet_device": ([vp, P(vp), P(u64)], i32),
+        "pv_packet_download": ([vp, vp, u64, P(u64), vp], i32),
+        "pv_get_masks": ([vp, P(vp), P(vp)], i32),
+        "pv_sync": ([vp], i32),
+        "pv_ctx_check": ([vp, P(i32)], i32),
+        "pv_trace_counts": ([vp, P(Frame), P(u64)], i32),
+        "pv_ctx_set_timing": ([vp, i32], i32),
+        "pv_ctx_stage_times": ([vp, P(ctypes.c_double), P(u64)], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != PV_OK:
+        raise NativeError(st, lib().pv_last_error().decode(errors="replace"))
+
+
+def _stream_handle(stream) -> Optional[int]:
+    """None -> the library's stream; torch.cuda.Stream or raw int accepted."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+# --------------------------------------------------------------------------
+# device buffer views (torch plumbing)
+# --------------------------------------------------------------------------
+class _DevArray:
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"data": (int(ptr), False), "shape": tuple(shape),
+                                         "typestr": typestr, "version": 2, "strides": None}
+
+
+_TYPESTR = {"float32": "<f4", "float16": "<f2", "int32": "<i4", "uint8": "|u1", "uint16": "<u2", "int16": "<i2"}
+
+
+def device_view(ptr: int, shape, dtype: str):
+    """Zero-copy torch view of library-owned device memory."""
+    import torch
+    return torch.as_tensor(_DevArray(ptr, shape, _TYPESTR[dtype]), device="cuda")
+
+
+_hip = None
+
+
+def device_to_host(ptr: int, shape, dtype: str) -> np.ndarray:
+    """Copy library-owned device memory to a new numpy array."""
+    try:
+        return device_view(ptr, shape, dtype).cpu().numpy()
+    except Exception:
+        global _hip
+        if _hip is None:
+            _hip = ctypes.CDLL("libamdhip64.so")
+            _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        out = np.empty(shape, np.dtype(_TYPESTR[dtype]))
+        if _hip.hipMemcpy(out.ctypes.data, ctypes.c_void_p(ptr), out.nbytes, 2) != 0:  # device to host
+            raise RuntimeError("hipMemcpy failed")
+        return out
+
+
+# --------------------------------------------------------------------------
+# handles
+# --------------------------------------------------------------------------
+class Context:
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().pv_ctx_create(device, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def set_timing(self, enable: bool):
+        _check(lib().pv_ctx_set_timing(self.h, 1 if enable else 0))
+
+    def stage_times(self) -> dict:
+        """{stage: (total ms, launches)} since the previous call."""
+        ms = (ctypes.c_double * len(STAGES))()
+        cnt = (ctypes.c_uint64 * len(STAGES))()
+        _check(lib().pv_ctx_stage_times(self.h, ms, cnt))
+        return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
+
+    def check(self) -> int:
+        st = ctypes.c_int(0)
+        _check(lib().pv_ctx_check(self.h, ctypes.byref(st)))
+        return st.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pv_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _lights_array(lights) -> tuple:
+    lights = np.ascontiguousarray(lights, np.float32).reshape(-1, 6)
+    arr = (PointLight * max(len(lights), 1))()
+    for i, l in enumerate(lights):
+        arr[i].pos[:] = [float(x) for x in l[:3]]
+        arr[i].intensity[:] = [float(x) for x in l[3:]]
+    return arr, len(lights)
+
+
+class Scene:
+    def __init__(self, ctx: Context, positions, indices, albedo, emission=None, lights=None,
+                 n_dynamic: int = 0):
+        self.ctx = ctx
+        self._pos = np.ascontiguousarray(positions, np.float32).reshape(-1, 3)
+        self._idx = np.ascontiguousarray(indices, np.uint32).reshape(-1, 3)
+        self._alb = np.ascontiguousarray(albedo, np.float32).reshape(-1, 3)
+        self._emi = None if emission is None else np.ascontiguousarray(emission, np.float32).reshape(-1, 3)
+        self._lights, nl = _lights_array(np.zeros((0, 6)) if lights is None else lights)
+        d = SceneDesc()
+        d.n_vertices = self._pos.shape[0]
+        d.positions = self._pos.ctypes.data
+        d.n_triangles = self._idx.shape[0]
+        d.indices = self._idx.ctypes.data
+        d.albedo = self._alb.ctypes.data
+        d.emission = None if self._emi is None else self._emi.ctypes.data
+        d.n_dynamic_triangles = int(n_dynamic)
+        d.n_lights = nl
+        d.lights = ctypes.cast(self._lights, ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        _check(lib().pv_scene_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+        self.n_dynamic = int(n_dynamic)
+
+    @classmethod
+    def from_synth(cls, ctx: Context, scene):
+        return cls(ctx, scene.positions, scene.indices, scene.albedo, scene.emission, scene.lights,
+                   n_dynamic=scene.n_dynamic)
+
+    def set_dynamic(self, positions, stream=None):
+        pos = np.ascontiguousarray(positions, np.float32).reshape(-1)
+        _check(lib().pv_scene_set_dynamic(self.h, pos.ctypes.data, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pv_scene_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_desc(cfg, flags: Optional[int] = None) -> VolumeDesc:
+    """pv_volume_desc from a volume description object with the fields of
+    synth.VolumeConfig."""
+    d = VolumeDesc()
+    d.nx, d.ny, d.nz = cfg.nx, cfg.ny, cfg.nz
+    d.origin[:] = [float(v) for v in cfg.origin]
+    d.spacing[:] = [float(v) for v in cfg.spacing]
+    d.rays_per_probe = cfg.rays_per_probe
+    d.irr_res, d.vis_res = cfg.irr_res, cfg.vis_res
+    d.hysteresis = cfg.hysteresis
+    d.max_distance = cfg.max_distance
+    d.vis_sharpness = cfg.vis_sharpness
+    d.format = PV_MAP_FP16 if cfg.fp16 else PV_MAP_FP32
+    d.sky[:] = [float(v) for v in cfg.sky]
+    if flags is None:
+        flags = PV_FIRST_FRAME_NO_HISTORY if cfg.first_frame_no_history else 0
+    d.flags = flags
+    return d
+
+
+def make_frame(rotation, lights=None):
+    f = Frame()
+    f.rotation[:] = [float(v) for v in np.asarray(rotation, np.float32).reshape(9)]
+    keep = None
+    if lights is not None and len(np.asarray(lights).reshape(-1, 6)) > 0:
+        keep, nl = _lights_array(lights)
+        f.n_lights = nl
+        f.lights = ctypes.cast(keep, ctypes.POINTER(PointLight))
+    else:
+        f.n_lights = 0
+        f.lights = None
+    return f, keep
+
+
+def volume_footprint(cfg, flags: Optional[int] = None) -> int:
+    b = ctypes.c_uint64(0)
+    _check(lib().pv_volume_footprint(ctypes.byref(make_desc(cfg, flags)), ctypes.byref(b)))
+    return b.value
+
+
+def client_footprint(cfg) -> int:
+    b = ctypes.c_uint64(0)
+    _check(lib().pv_client_footprint(ctypes.byref(make_desc(cfg)), ctypes.byref(b)))
+    return b.value
+
+
+class Volume:
+    def __init__(self, ctx: Context, cfg, keep_hits: bool = False):
+        self.ctx = ctx
+        self.cfg = cfg
+        flags = (PV_FIRST_FRAME_NO_HISTORY if cfg.first_frame_no_history else 0) | (PV_KEEP_HITS if keep_hits else 0)
+        self._desc = make_desc(cfg, flags)
+        h = ctypes.c_void_p()
+        _check(lib().pv_create_volume(ctx.h, ctypes.byref(self._desc), ctypes.byref(h)))
+        self.h = h
+        self.P = cfg.nx * cfg.ny * cfg.nz
+        self.n = cfg.rays_per_probe
+        self.fp16 = bool(cfg.fp16)
+        self.keep_hits = keep_hits
+        self.scene = None
+
+    def set_scene(self, scene: Scene):
+        _check(lib().pv_set_scene(self.h, scene.h))
+        self.scene = scene
+
+    def update_probes(self, rotation, lights=None, stream=None):
+        f, keep = make_frame(rotation, lights)
+        _check(lib().pv_update_probes(self.h, ctypes.byref(f), _stream_handle(stream)))
+        del keep
+
+    def trace_counts(self, rotation, lights=None):
+        f, keep = make_frame(rotation, lights)
+        out = (ctypes.c_uint64 * 3)()
+        _check(lib().pv_trace_counts(self.h, ctypes.byref(f), out))
+        return {"node_visits": out[0], "tri_tests": out[1], "shadow_rays": out[2]}
+
+    def blend_rays(self, rotation, rays_dev_ptr: int, stream=None):
+        f, keep = make_frame(rotation)
+        _check(lib().pv_blend_rays(self.h, ctypes.byref(f), ctypes.c_void_p(rays_dev_ptr), _stream_handle(stream)))
+
+    def get_maps(self):
+        a, b = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib().pv_get_maps(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def get_rays(self):
+        r, h, d = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib().pv_get_rays(self.h, ctypes.byref(r), ctypes.byref(h), ctypes.byref(d)))
+        return r.value, h.value, d.value
+
+    def read_maps(self):
+        """Synchronous copy of the maps: (irr [P,3,10,10], vis [P,2,18,18],
+        frame); float32, or uint16 bit patterns for FP16 maps."""
+        dt = np.uint16 if self.fp16 else np.float32
+        irr = np.zeros((self.P, 3, 10, 10), dt)
+        vis = np.zeros((self.P, 2, 18, 18), dt)
+        fr = ctypes.c_int64(0)
+        _check(lib().pv_read_maps(self.h, irr.ctypes.data, vis.ctypes.data, ctypes.byref(fr)))
+        return irr, vis, fr.value
+
+    def set_maps(self, irr, vis, frame: int):
+        dt = np.uint16 if self.fp16 else np.float32
+        irr = np.ascontiguousarray(irr, dt)
+        vis = np.ascontiguousarray(vis, dt)
+        assert irr.shape == (self.P, 3, 10, 10) and vis.shape == (self.P, 2, 18, 18)
+        _check(lib().pv_set_maps(self.h, irr.ctypes.data, vis.ctypes.data, int(frame)))
+
+    def read_rays(self):
+        """Ray records [P,n,4] float32 (L rgb, distance), hit ids [P,n]
+        (None unless keep_hits) and directions [n,4], copied to the host."""
+        sync()
+        r, h, d = self.get_rays()
+        rays = device_to_host(r, (self.P, self.n, 4), "float32")
+        dirs = device_to_host(d, (self.n, 4), "float32")
+        hits = device_to_host(h, (self.P, self.n), "int32") if h else None
+        return rays, hits, dirs
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pv_volume_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def update_probes_batched(volumes: Sequence[Volume], rotations, lights=None, stream=None):
+    n = len(volumes)
+    arr = (ctypes.c_void_p * n)(*[v.h.value for v in volumes])
+    frames = (Frame * n)()
+    keeps = []
+    for i in range(n):
+        f, keep = make_frame(rotations[i], None if lights is None else lights[i])
+        frames[i] = f
+        keeps.append(keep)
+    _check(lib().pv_update_probes_batched(arr, frames, n, _stream_handle(stream)))
+
+
+class Client:
+    def __init__(self, volume: Volume, client_id: int = 0):
+        self.volume = volume
+        h = ctypes.c_void_p()
+        _check(lib().pv_client_create(volume.h, int(client_id), ctypes.byref(h)))
+        self.h = h
+        self.client_id = client_id
+
+    def pack_delta(self, tau_irr: float = 0.0, tau_vis: float = 0.0, stream=None):
+        _check(lib().pv_pack_delta(self.h, float(tau_irr), float(tau_vis), _stream_handle(stream)))
+
+    def reset(self, stream=None):
+        _check(lib().pv_client_reset(self.h, _stream_handle(stream)))
+
+    def packet_device(self):
+        p, cap = ctypes.c_void_p(), ctypes.c_uint64()
+        _check(lib().pv_packet_device(self.h, ctypes.byref(p), ctypes.byref(cap)))
+        return p.value, cap.value
+
+    def packet_download(self, stream=None) -> bytes:
+        _, cap = self.packet_device()
+        buf = np.zeros(cap, np.uint8)
+        nb = ctypes.c_uint64(0)
+        _check(lib().pv_packet_download(self.h, buf.ctypes.data, cap, ctypes.byref(nb), _stream_handle(stream)))
+        return buf[:nb.value].tobytes()
+
+    def read_masks(self):
+        sync()
+        a, b = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib().pv_get_masks(self.h, ctypes.byref(a), ctypes.byref(b)))
+        P = self.volume.P
+        return (device_to_host(a.value, (P,), "uint8").astype(bool),
+                device_to_host(b.value, (P,), "uint8").astype(bool))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pv_client_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sync(stream=None):
+    _check(lib().pv_sync(_stream_handle(stream)))

@@ -1,0 +1,418 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (see the module helpers for the exact measures):
+  - packing, deltas, masks, index buffers: bit-exact;
+  - hit triangle per ray: inside the oracle's accepted set (the nominal hit,
+    or another triangle a tiny perturbation of the ray reaches) for every
+    ray, and equal to the nominal hit for >= 99.99% of rays;
+  - per-ray radiance and distance, FP32 maps: inside the oracle's tie
+    bounds with relative slack 1e-4 (dark texels: 1e-3 of the map maximum);
+  - FP16 maps: inside the oracle's FP16 tie bounds with 2 binary16 ulps of
+    slack, and >= 99.9% of texels within 1 ulp of the nominal trajectory.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import (excess_fp16_ulps, excess_fp32, f16, fold_consistent, hit_agreement, ulps_from)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ps():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2103_05875_amd as ps
+    ps.lib()
+    return ps
+
+
+@pytest.fixture(scope="module")
+def ctx(ps):
+    c = ps.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+# ------------------------------------------------------------------ a1
+@pytest.mark.parametrize("n", [1, 7, 128, 256, 1000, 4096])
+def test_ray_directions(ps, ctx, O, n):
+    _say(f"ray directions n={n}")
+    cfg = synth.VolumeConfig(1, 1, 1, (0, 0, 0), (1, 1, 1), n, fp16=False)
+    vol = ps.Volume(ctx, cfg)
+    sc = ps.Scene.from_synth(ctx, synth.empty_scene())
+    vol.set_scene(sc)
+    R = synth.rotation(3, n)
+    vol.update_probes(R)
+    _, _, dirs = vol.read_rays()
+    want = O.ray_dirs(n, R)
+    assert np.abs(dirs[:, :3] - want).max() < 1e-6
+
+
+# ------------------------------------------------------------------ a2..a6 on the box room
+def _update_both(ps, ctx, O, cfg, scene, frames, keep_hits=True, dyn=None, lights_per_frame=None):
+    """Run ``frames`` updates on the GPU and in the oracle; yields per frame
+    (gpu maps, oracle volume, gpu rays, gpu hits, oracle rays)."""
+    sc = ps.Scene.from_synth(ctx, scene)
+    vol = ps.Volume(ctx, cfg, keep_hits=keep_hits)
+    vol.set_scene(sc)
+    ov = O.OracleVolume(cfg)
+    n_static = scene.n_triangles - scene.n_dynamic
+    osc = O.OracleScene.from_scene(scene, n_static=n_static)
+    for f, R in enumerate(frames):
+        lights = scene.lights if lights_per_frame is None else lights_per_frame[f]
+        if dyn is not None:
+            d = dyn(f)
+            sc.set_dynamic(d)
+            osc = O.OracleScene(np.concatenate([scene.triangles()[:n_static], d]), scene.albedo, scene.emission,
+                                n_static=n_static)
+        vol.update_probes(R, lights)
+        rays = ov.update(osc, R, lights)
+        irr, vis, fr = vol.read_maps()
+        grays, ghits, _ = vol.read_rays()
+        assert fr == f + 1
+        yield irr, vis, ov, grays, ghits, rays
+    sc.close()
+    vol.close()
+
+
+def _check_rays(grays, ghits, rays, min_equal=0.9999):
+    eq, ok = hit_agreement(ghits, rays)
+    assert ok == 1.0, f"hits outside the accepted set: {1 - ok:.2e}"
+    assert eq >= min_equal, f"nominal hit agreement {eq:.6f}"
+    L = grays[..., :3].astype(np.float64)
+    r = grays[..., 3].astype(np.float64)
+    scale = max(float(np.abs(rays["L_hi"]).max()), 1e-30)
+    tolL = 1e-4 * np.maximum(np.maximum(np.abs(rays["L_lo"]), np.abs(rays["L_hi"])), 1e-2 * scale)
+    assert np.all(L >= rays["L_lo"] - tolL) and np.all(L <= rays["L_hi"] + tolL)
+    tolr = 1e-4 * np.maximum(rays["r_hi"], 1e-3)
+    assert np.all(r >= rays["r_lo"] - tolr) and np.all(r <= rays["r_hi"] + tolr)
+
+
+def test_box_room_update_fp32(ps, ctx, O):
+    """The box-room workload: 4x4x4 probes, 24 triangles, 128 rays, FP32
+    maps, one frame."""
+    _say("box room, FP32 maps, 1 frame")
+    cfg = synth.config("box_room")
+    scene = synth.box_room()
+    for irr, vis, ov, grays, ghits, rays in _update_both(ps, ctx, O, cfg, scene, [synth.rotation(2, 0)]):
+        _check_rays(grays, ghits, rays, min_equal=0.999)
+        e1, _ = excess_fp32(irr, ov.irr_lo, ov.irr_hi)
+        e2, _ = excess_fp32(vis, ov.vis_lo, ov.vis_hi)
+        _say(f"  irradiance excess {e1:.2e}, visibility excess {e2:.2e}")
+        assert e1 <= 1e-4 and e2 <= 1e-4
+        assert fold_consistent(irr) and fold_consistent(vis)
+        assert (rays["L"] == 0).any()  # the cube casts shadows into the record
+
+
+def _fp16_checks(irr, vis, ov, label):
+    for name, g, lo, hi, nom in (("irr", irr, ov.irr_lo, ov.irr_hi, ov.irr), ("vis", vis, ov.vis_lo, ov.vis_hi, ov.vis)):
+        ex, _ = excess_fp16_ulps(g, lo, hi)
+        within1 = float((ulps_from(g, nom) <= 1.0).mean())
+        _say(f"  {label} {name}: bound excess {ex:.2f} ulp, within 1 ulp of nominal {within1:.5f}")
+        assert ex <= 2.0
+        assert within1 >= 0.999
+        assert fold_consistent(g)
+
+
+def test_box_room_fp16_moving_light(ps, ctx, O):
+    _say("box room, FP16 maps, 12 frames, moving light, hysteresis")
+    cfg = synth.config("box_room")
+    cfg.fp16 = True
+    scene = synth.box_room()
+    frames = [synth.rotation(2, f) for f in range(12)]
+    lights = []
+    for f in range(12):
+        l = scene.lights.copy()
+        l[0, :3] = [0.4 + 0.2 * f, 3.6 - 0.1 * f, 0.4 + 0.15 * f]
+        lights.append(l)
+    for f, (irr, vis, ov, grays, ghits, rays) in enumerate(
+            _update_both(ps, ctx, O, cfg, scene, frames, lights_per_frame=lights)):
+        _check_rays(grays, ghits, rays, min_equal=0.999)
+        _fp16_checks(irr, vis, ov, f"frame {f}")
+
+
+@pytest.mark.parametrize("grid,n", [((5, 3, 7), 64), ((1, 1, 1), 1), ((2, 9, 1), 300)])
+def test_ragged_grids_and_ray_counts(ps, ctx, O, grid, n):
+    """Grids that do not fill 4x4x4 bricks, a single ray, ray counts that
+    straddle the blend's chunk of 256."""
+    _say(f"ragged grid {grid}, n={n}")
+    cfg = synth.VolumeConfig(*grid, (-0.3, -0.2, -0.1), (0.7, 0.45, 0.6), n, fp16=False, max_distance=3.0,
+                             sky=(0.2, 0.1, 0.05))
+    scene = synth.box_room()
+    for irr, vis, ov, grays, ghits, rays in _update_both(ps, ctx, O, cfg, scene,
+                                                          [synth.rotation(4, 0), synth.rotation(4, 1)]):
+        _check_rays(grays, ghits, rays, min_equal=0.999)
+        assert excess_fp32(irr, ov.irr_lo, ov.irr_hi)[0] <= 1e-4
+        assert excess_fp32(vis, ov.vis_lo, ov.vis_hi)[0] <= 1e-4
+
+
+def test_empty_scene_and_emissive_box(ps, ctx, O):
+    _say("empty scene (sky) and closed emissive box")
+    cfg = synth.VolumeConfig(2, 3, 2, (0, 0, 0), (0.4, 0.4, 0.4), 128, fp16=False, max_distance=2.5,
+                             sky=(0.3, 0.6, 1.2))
+    for irr, vis, ov, grays, ghits, rays in _update_both(ps, ctx, O, cfg, synth.empty_scene(), [synth.rotation(5, 0)]):
+        sky = np.array(cfg.sky, np.float32)
+        for c in range(3):
+            assert np.allclose(irr[:, c], sky[c], rtol=2e-6)
+        assert np.allclose(vis[:, 0], np.float32(2.5), rtol=2e-6)
+        assert np.allclose(vis[:, 1], np.float32(2.5) ** 2, rtol=2e-6)
+    E = (0.7, 0.4, 0.2)
+    box = synth.emissive_box(half_width=3.0, center=(0.5, 0.5, 0.5), emission=E)
+    for irr, vis, ov, grays, ghits, rays in _update_both(ps, ctx, O, cfg, box, [synth.rotation(6, 0)]):
+        for c in range(3):
+            assert np.allclose(irr[:, c], np.float32(E[c]), rtol=2e-6)
+        _check_rays(grays, ghits, rays)
+
+
+# ------------------------------------------------------------------ the city at full size
+def test_city_full_size_frames(ps, ctx, O):
+    """The at-scale workload: 16x8x16 probes, 256 rays, 50k-triangle city,
+    FP16 maps; three frames with the light moving on its spline."""
+    cfg = synth.config("city")
+    scene = synth.box_city()
+    path = synth.light_path(12, 60)
+    frames, lights = [], []
+    for f in range(3):
+        frames.append(synth.rotation(13, f))
+        l = scene.lights.copy()
+        l[0, :3] = path[f]
+        lights.append(l)
+    for f, (irr, vis, ov, grays, ghits, rays) in enumerate(
+            _update_both(ps, ctx, O, cfg, scene, frames, lights_per_frame=lights)):
+        _say(f"city frame {f}")
+        _check_rays(grays, ghits, rays)
+        _fp16_checks(irr, vis, ov, f"city frame {f}")
+
+
+def test_dynamic_occluders(ps, ctx, O):
+    """Moving occluder boxes (dynamic triangles) over a small box field."""
+    _say("moving occluders, 4 frames")
+    scene = synth.box_field(3000, seed=40, extent=24.0, n_moving=3)
+    cfg = synth.VolumeConfig(8, 4, 8, (1.0, 0.3, 1.0), (3.0, 2.0, 3.0), 64, max_distance=5.0, fp16=True,
+                             sky=(0.1, 0.15, 0.25))
+    dyn = lambda f: synth.moving_occluders(40, f * 7, 3, 24.0)
+    frames = [synth.rotation(41, f) for f in range(4)]
+    for f, (irr, vis, ov, grays, ghits, rays) in enumerate(_update_both(ps, ctx, O, cfg, scene, frames, dyn=dyn)):
+        _check_rays(grays, ghits, rays)
+        _fp16_checks(irr, vis, ov, f"dyn frame {f}")
+        # the occluders are actually hit
+        if f == 0:
+            assert (ghits >= scene.n_triangles - scene.n_dynamic).any()
+
+
+# ------------------------------------------------------------------ blend from given rays
+@pytest.mark.parametrize("fp16,n,grid", [(False, 64, (37, 1, 1)), (False, 300, (3, 2, 2)),
+                                         (True, 256, (9, 5, 3)), (True, 513, (2, 1, 3))])
+def test_blend_from_given_rays(ps, ctx, O, fp16, n, grid):
+    """a4-a6 alone: both sides blend the same seeded ray records over five
+    frames of hysteresis."""
+    import torch
+    _say(f"blend from given rays fp16={fp16} n={n} grid={grid}")
+    cfg = synth.VolumeConfig(*grid, (0, 0, 0), (1, 1, 1), n, fp16=fp16, max_distance=4.0)
+    vol = ps.Volume(ctx, cfg)
+    irr_o, vis_o = O.empty_maps(cfg)
+    for f in range(5):
+        R = synth.rotation(60 + n, f)
+        L, r = synth.synthetic_rays(cfg.n_probes, n, seed=100 * f + n)
+        rec = np.concatenate([L, r[..., None]], axis=-1).astype(np.float32)
+        dev = torch.from_numpy(rec).cuda()
+        torch.cuda.synchronize()
+        vol.blend_rays(R, dev.data_ptr())
+        ps.native.sync()
+        O.blend_update(cfg, O.ray_dirs(n, R), L, r, irr_o, vis_o, first=(f == 0))
+        irr, vis, _ = vol.read_maps()
+        if fp16:
+            for g, o in ((irr, irr_o), (vis, vis_o)):
+                d = ulps_from(g, o)
+                assert d.max() <= 2.0 and (d <= 1.0).mean() >= 0.999
+        else:
+            assert excess_fp32(irr, irr_o, irr_o)[0] <= 1e-5
+            assert excess_fp32(vis, vis_o, vis_o)[0] <= 1e-5
+        assert fold_consistent(irr) and fold_consistent(vis)
+        del dev
+    vol.close()
+
+
+# ------------------------------------------------------------------ pack (bit-exact)
+def _grid_for(P):
+    for nx in range(min(P, 64), 0, -1):
+        if P % nx == 0 and P // nx <= 1024:
+            return nx, P // nx, 1
+    return P, 1, 1
+
+
+@pytest.mark.parametrize("P,taus", [(1, (0.0, 0.0)), (37, (1.0 / 1024, 0.0)), (2048, (0.0, 1.0 / 1024)),
+                                    (16384, (1.0 / 1024, 1.0 / 1024)), (1000, (0.01, 0.003))])
+def test_pack_bit_exact(ps, ctx, O, P, taus):
+    _say(f"pack P={P} taus={taus}")
+    nx, ny, nz = _grid_for(P)
+    if ny > 1024:
+        nx, ny, nz = 64, P // 64, 1
+    cfg = synth.VolumeConfig(nx, ny, nz, (0, 0, 0), (1, 1, 1), 1, fp16=True)
+    vol = ps.Volume(ctx, cfg)
+    cl = ps.Client(vol, client_id=P)
+    st = O.OracleClientState(P, client=P)
+    dec = O.OracleClientDecoder(P)
+    cur_i, cur_v = synth.random_fp16_maps(P, 8, 16, seed=P)
+    for f in range(8):
+        vol.set_maps(cur_i, cur_v, f)
+        cl.pack_delta(*taus)
+        got = cl.packet_download()
+        want, mi, mv = st.pack(cur_i, cur_v, *taus)
+        gmi, gmv = cl.read_masks()
+        assert np.array_equal(gmi, mi) and np.array_equal(gmv, mv)
+        assert got == want, f"frame {f}: packet differs ({len(got)} vs {len(want)} bytes)"
+        assert dec.apply(got) == 0
+        assert np.array_equal(dec.irr[:, :, 1:-1, 1:-1].reshape(P, 3, -1), st.ref_irr)
+        cur_i, cur_v = synth.perturb_fp16_maps(cur_i, cur_v, seed=1000 * P + f, p_probe=0.3, p_texel=0.05)
+    # forced resend after a reset: every non-zero probe again
+    cl.reset()
+    st.reset()
+    vol.set_maps(cur_i, cur_v, 9)
+    cl.pack_delta(*taus)
+    assert cl.packet_download() == st.pack(cur_i, cur_v, *taus)[0]
+    cl.close()
+    vol.close()
+
+
+def test_pack_maximum_probe_count(ps, ctx, O):
+    P = 65536
+    _say("pack P=65536")
+    cfg = synth.VolumeConfig(64, 32, 32, (0, 0, 0), (1, 1, 1), 1, fp16=True)
+    vol = ps.Volume(ctx, cfg)
+    cl = ps.Client(vol, client_id=3)
+    st = O.OracleClientState(P, client=3)
+    cur_i, cur_v = synth.random_fp16_maps(P, 8, 16, seed=5)
+    for f in range(2):
+        vol.set_maps(cur_i, cur_v, f)
+        cl.pack_delta(0.0, 0.0)
+        assert cl.packet_download() == st.pack(cur_i, cur_v)[0]
+        cur_i, cur_v = synth.perturb_fp16_maps(cur_i, cur_v, seed=77, p_probe=0.1)
+    cl.close()
+    vol.close()
+
+
+def test_update_then_pack_round_trip(ps, ctx, O):
+    """GPU update + GPU pack over 20 frames; a client applying the packets
+    holds exactly the server's current interiors (tau = 0) every frame."""
+    _say("update + pack round trip, 20 frames")
+    scene = synth.box_city(n_tris=6000, extent=32.0)
+    cfg = synth.VolumeConfig(8, 4, 8, (2.0, 0.25, 2.0), (4.0, 1.5, 4.0), 64, fp16=True, max_distance=6.0,
+                             sky=(0.1, 0.15, 0.25))
+    sc = ps.Scene.from_synth(ctx, scene)
+    vol = ps.Volume(ctx, cfg)
+    vol.set_scene(sc)
+    cl = ps.Client(vol, client_id=11)
+    dec = O.OracleClientDecoder(cfg.n_probes)
+    path = synth.light_path(12, 20, extent=32.0)
+    sent = []
+    for f in range(20):
+        l = scene.lights.copy()
+        l[0, :3] = path[f]
+        vol.update_probes(synth.rotation(13, f), l)
+        cl.pack_delta(0.0, 0.0)
+        pkt = cl.packet_download()
+        assert dec.apply(pkt) == 0 and dec.seq == f
+        irr, vis, _ = vol.read_maps()
+        assert np.array_equal(dec.irr[:, :, 1:-1, 1:-1], irr[:, :, 1:-1, 1:-1])
+        assert np.array_equal(dec.vis[:, :, 1:-1, 1:-1], vis[:, :, 1:-1, 1:-1])
+        assert np.array_equal(dec.irr, irr) and np.array_equal(dec.vis, vis)   # guard bands rebuilt
+        sent.append(len(pkt))
+    assert sent[0] >= sent[-1]
+    cl.close()
+    vol.close()
+    sc.close()
+
+
+# ------------------------------------------------------------------ batched = plain
+def test_batched_matches_plain_bitwise(ps, ctx, O):
+    _say("batched vs plain, 6 uneven volumes, 3 frames")
+    specs = [((4, 4, 4), 64, True, 2000), ((5, 3, 7), 128, True, 800), ((16, 2, 16), 256, True, 5000),
+             ((1, 1, 1), 512, False, 300), ((8, 8, 4), 64, False, 1200), ((3, 3, 3), 1, True, 100)]
+    plain, batched, scenes = [], [], []
+    for i, (g, n, fp16, nt) in enumerate(specs):
+        sc_syn = synth.box_city(n_tris=nt, seed_layout=70 + i, seed_heights=80 + i, extent=16.0)
+        sc = ps.Scene.from_synth(ctx, sc_syn)
+        scenes.append(sc)
+        cfg = synth.VolumeConfig(*g, (1.0, 0.3, 1.0), (2.0, 1.0, 2.0), n, fp16=fp16, max_distance=5.0,
+                                 sky=(0.1, 0.15, 0.25))
+        a, b = ps.Volume(ctx, cfg), ps.Volume(ctx, cfg)
+        a.set_scene(sc)
+        b.set_scene(sc)
+        plain.append(a)
+        batched.append(b)
+    for f in range(3):
+        rots = [synth.rotation(90 + i, f) for i in range(len(specs))]
+        for v, R in zip(plain, rots):
+            v.update_probes(R)
+        ps.update_probes_batched(batched, rots)
+        ps.native.sync()
+        assert ctx.check() == 0
+        for a, b in zip(plain, batched):
+            ia, va, fa = a.read_maps()
+            ib, vb, fb = b.read_maps()
+            assert fa == fb == f + 1
+            assert np.array_equal(ia.view(np.uint8), ib.view(np.uint8))
+            assert np.array_equal(va.view(np.uint8), vb.view(np.uint8))
+    for h in plain + batched + scenes:
+        h.close()
+
+
+def test_checkpoint_export_import_continues_identically(ps, ctx, O):
+    _say("checkpoint export/import")
+    scene = synth.box_room()
+    cfg = synth.config("box_room")
+    cfg.fp16 = True
+    sc = ps.Scene.from_synth(ctx, scene)
+    a = ps.Volume(ctx, cfg)
+    a.set_scene(sc)
+    for f in range(3):
+        a.update_probes(synth.rotation(2, f))
+    irr, vis, fr = a.read_maps()
+    b = ps.Volume(ctx, cfg)
+    b.set_scene(sc)
+    b.set_maps(irr, vis, fr)
+    for f in range(3, 6):
+        a.update_probes(synth.rotation(2, f))
+        b.update_probes(synth.rotation(2, f))
+    ia, va, _ = a.read_maps()
+    ib, vb, _ = b.read_maps()
+    assert np.array_equal(ia, ib) and np.array_equal(va, vb)
+    for h in (a, b, sc):
+        h.close()
+
+
+def test_invalid_arguments_are_refused(ps, ctx):
+    cfg = synth.config("box_room")
+    v = ps.Volume(ctx, cfg)
+    with pytest.raises(ps.NativeError) as e:
+        v.update_probes(synth.rotation(1, 0))      # no scene set
+    assert e.value.status == -4
+    sc = ps.Scene.from_synth(ctx, synth.box_room())
+    v.set_scene(sc)
+    with pytest.raises(ps.NativeError):
+        v.update_probes(np.full(9, 2.0, np.float32))   # not a rotation
+    with pytest.raises(ps.NativeError) as e:
+        ps.Client(v)                                 # FP32 maps cannot be packed
+    assert e.value.status == -6
+    bad = synth.box_room()
+    bad.indices = bad.indices.copy()
+    bad.indices[0, 0] = 10 ** 6
+    with pytest.raises(ps.NativeError):
+        ps.Scene.from_synth(ctx, bad)
+    v.close()
+    sc.close()
