@@ -360,13 +360,16 @@ typedef struct {
     int tri;
     double t;
     int near;
+    int nties;           /* other triangles within 2m of the nominal distance */
+    int ties[4];
+    double ties_t[4];
 } or_hit;
 
 #define OR_STACK 128
 
 static or_hit closest_hit(const or_scene *s, const double o[3], const double d[3], double tmin, double m)
 {
-    or_hit h = {-1, INFINITY, 0};
+    or_hit h = {-1, INFINITY, 0, 0, {0, 0, 0, 0}, {0, 0, 0, 0}};
     if (s->ntri == 0) return h;
     double t_limit = INFINITY;  /* closest 'sure' distance so far + margin */
     int stack[OR_STACK];
@@ -416,7 +419,16 @@ static or_hit closest_hit(const or_scene *s, const double o[3], const double d[3
     for (int i = 0; i < npos; ++i) {
         if (poss_t[i] > front + 2.0 * m) continue;
         if (!poss_sure[i]) h.near = 1;
-        if (poss_id[i] != h.tri && fabs(poss_t[i] - h.t) <= 2.0 * m) h.near = 1;
+        if (poss_id[i] != h.tri && fabs(poss_t[i] - h.t) <= 2.0 * m) {
+            h.near = 1;
+            int dup = 0;
+            for (int k = 0; k < h.nties; ++k) dup |= h.ties[k] == poss_id[i];
+            if (!dup && h.nties < 4) {
+                h.ties[h.nties] = poss_id[i];
+                h.ties_t[h.nties] = poss_t[i];
+                h.nties++;
+            }
+        }
     }
     if (overflow) h.near = 1;
     return h;
@@ -562,8 +574,10 @@ static double plane_t(const or_scene *s, int k, const double o[3], const double 
  *                            lower precision could legitimately produce:
  *                            hit candidates found by perturbing the ray origin
  *                            by +-delta along each axis when the ray is near a
- *                            tie, and either shadow decision when a shadow ray
- *                            is near a tie;
+ *                            tie, triangles within the tie margin of the
+ *                            nominal distance (coplanar or crossing surfaces),
+ *                            and either shadow decision when a shadow ray is
+ *                            near a tie;
  *   hit[q]                 : nominal triangle (-1 = miss);
  *   cand[q*maxc..], ncand  : the accepted triangle set (nominal first).
  * delta_rel scales the perturbation with the scene diagonal.
@@ -608,6 +622,16 @@ OR_API int or_trace_shade(const or_scene *s, const or_volume *v, const float R[9
                             cands[nc++] = hp.tri;
                         }
                     }
+                /* triangles at the same distance (coplanar or crossing
+                 * surfaces) are equally valid answers */
+                for (int k = 0; k < h.nties; ++k) {
+                    int seen = 0;
+                    for (int c = 0; c < nc; ++c) seen |= cands[c] == h.ties[k];
+                    if (!seen && nc < 16) {
+                        cand_t[nc] = h.ties_t[k];
+                        cands[nc++] = h.ties[k];
+                    }
+                }
             }
             double Ln[3], rn;
             double Llo[3] = {INFINITY, INFINITY, INFINITY}, Lhi[3] = {-INFINITY, -INFINITY, -INFINITY};

@@ -166,8 +166,10 @@ def box_city(n_tris: int = 50_000, seed_layout: int = 10,
     z0 = cz * cell + oz
     tris = [np.array([[[-1.0, 0.0, -1.0], [extent + 1, 0.0, -1.0], [extent + 1, 0.0, extent + 1]],
                       [[-1.0, 0.0, -1.0], [extent + 1, 0.0, extent + 1], [-1.0, 0.0, extent + 1]]])]
+    # box bottoms sit just below the ground plane, so no face is coplanar
+    # with the ground (no overlapping surfaces)
     for b in range(n_boxes):
-        tris.append(_box_triangles([x0[b], 0.0, z0[b]],
+        tris.append(_box_triangles([x0[b], -0.05, z0[b]],
                                    [x0[b] + fx[b], heights[b], z0[b] + fz[b]]))
     tris = np.concatenate(tris)
     t = tris.shape[0]

@@ -91,6 +91,11 @@ def _update_both(ps, ctx, O, cfg, scene, frames, keep_hits=True, dyn=None, light
 
 def _check_rays(grays, ghits, rays, min_equal=0.9999):
     eq, ok = hit_agreement(ghits, rays)
+    if ok != 1.0:
+        bad = np.argwhere(~np.any(rays["cand"] == ghits[..., None], axis=-1) & (ghits != rays["hit"]))
+        for p, j in bad[:10]:
+            _say(f"  ray ({p},{j}): gpu {ghits[p, j]} nominal {rays['hit'][p, j]} t {rays['hit_t'][p, j]:.6f} "
+                 f"cand {rays['cand'][p, j].tolist()} L {grays[p, j].tolist()}")
     assert ok == 1.0, f"hits outside the accepted set: {1 - ok:.2e}"
     assert eq >= min_equal, f"nominal hit agreement {eq:.6f}"
     L = grays[..., :3].astype(np.float64)
