@@ -62,7 +62,7 @@ typedef enum {
     PV_ERR_DEVICE = -3,      /* HIP runtime / device error */
     PV_ERR_STATE = -4,       /* call not valid in the handle's state */
     PV_ERR_CAPACITY = -5,    /* caller buffer or memory budget too small */
-    PV_ERR_UNSUPPORTED = -6  /* valid request this build does not implement */
+    PV_ERR_UNSUPPORTED = -6  /* valid request the library does not implement */
 } pv_status;
 
 typedef enum { PV_MAP_FP32 = 0, PV_MAP_FP16 = 1 } pv_map_format;
@@ -81,7 +81,7 @@ typedef enum { PV_MAP_FP32 = 0, PV_MAP_FP16 = 1 } pv_map_format;
  * rays_per_probe directions under the frame's rotation, shared by every probe.
  * Maps: irradiance tiles [P][3][irr_res+2][irr_res+2] and visibility tiles
  * [P][2][vis_res+2][vis_res+2] (channel-planar, row-major, 1-texel guard
- * band), FP32 or FP16 storage, FP32 arithmetic. This build supports
+ * band), FP32 or FP16 storage, FP32 arithmetic. The library supports
  * irr_res = 8 and vis_res = 16 (the paper's 10x10 and 18x18 tiles).
  */
 typedef struct {
@@ -228,6 +228,11 @@ pv_status pv_packet_device(pv_client *client, const void **packet_dev, uint64_t 
  * bytes to host_buf. PV_ERR_CAPACITY with *bytes = needed size when cap is
  * too small. */
 pv_status pv_packet_download(pv_client *client, void *host_buf, uint64_t cap, uint64_t *bytes, void *stream);
+/* Client reference export / import (host buffers [P][3][64] and
+ * [P][2][256] uint16, plus the sequence counter); synchronous. Lets a
+ * server evict a client's state from HBM and bring it back later. */
+pv_status pv_client_read_state(pv_client *client, void *ref_irr_host, void *ref_vis_host, uint32_t *seq);
+pv_status pv_client_set_state(pv_client *client, const void *ref_irr_host, const void *ref_vis_host, uint32_t seq);
 /* Changed-probe masks of the last pack (device, [P] uint8 each). */
 pv_status pv_get_masks(pv_client *client, void **mask_irr_dev, void **mask_vis_dev);
 

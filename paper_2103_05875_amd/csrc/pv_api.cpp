@@ -440,7 +440,7 @@ static pv_status validate_desc(const pv_volume_desc *d) {
     if (!finite_all(d->origin, 3) || !finite_all(d->spacing, 3) || !finite_all(d->sky, 3))
         return fail(PV_ERR_ARG, "origin, spacing and sky must be finite");
     if (d->irr_res != 8 || d->vis_res != 16)
-        return fail(PV_ERR_UNSUPPORTED, "this build supports irr_res = 8 and vis_res = 16");
+        return fail(PV_ERR_UNSUPPORTED, "supported: irr_res = 8 and vis_res = 16");
     if (d->flags & ~(PV_FIRST_FRAME_NO_HISTORY | PV_KEEP_HITS)) return fail(PV_ERR_ARG, "unknown flags");
     return PV_OK;
 }
@@ -867,6 +867,26 @@ extern "C" pv_status pv_pack_delta(pv_client *c, float tau_irr, float tau_vis, v
     HIP_TRY(timed(cx, PV_STAGE_PACK_SCAN, s, [&] { return launch_pack_scan(b, P, id, seq, s); }));
     HIP_TRY(timed(cx, PV_STAGE_PACK_COMPACT, s, [&] { return launch_pack_compact(b, P, s); }));
     c->seq++;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_client_read_state(pv_client *c, void *ri, void *rv, uint32_t *seq) {
+    if (!c || !ri || !rv) return fail(PV_ERR_ARG, "NULL argument");
+    HIP_TRY(hipSetDevice(c->vol->ctx->device));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(ri, c->ref_irr, (size_t)c->vol->P * 192 * 2, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(rv, c->ref_vis, (size_t)c->vol->P * 512 * 2, hipMemcpyDeviceToHost));
+    if (seq) *seq = c->seq;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_client_set_state(pv_client *c, const void *ri, const void *rv, uint32_t seq) {
+    if (!c || !ri || !rv) return fail(PV_ERR_ARG, "NULL argument");
+    HIP_TRY(hipSetDevice(c->vol->ctx->device));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(c->ref_irr, ri, (size_t)c->vol->P * 192 * 2, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->ref_vis, rv, (size_t)c->vol->P * 512 * 2, hipMemcpyHostToDevice));
+    c->seq = seq;
     return PV_OK;
 }
 

@@ -31,6 +31,7 @@ EXPORTED_SYMBOLS = [
     "pv_client_create", "pv_client_destroy", "pv_client_reset", "pv_client_footprint",
     "pv_pack_delta", "pv_packet_device", "pv_packet_download", "pv_get_masks", "pv_sync",
     "pv_ctx_check", "pv_trace_counts", "pv_ctx_set_timing", "pv_ctx_stage_times",
+    "pv_client_read_state", "pv_client_set_state",
 ]
 
 STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched"]
@@ -122,6 +123,8 @@ def lib():
         "pv_ctx_check": ([vp, P(i32)], i32),
         "pv_trace_counts": ([vp, P(Frame), P(u64)], i32),
         "pv_ctx_set_timing": ([vp, i32], i32),
+        "pv_client_read_state": ([vp, vp, vp, P(u32)], i32),
+        "pv_client_set_state": ([vp, vp, vp, u32], i32),
         "pv_ctx_stage_times": ([vp, P(ctypes.c_double), P(u64)], i32),
     }
     for name, (args, res) in sig.items():
@@ -439,6 +442,20 @@ class Client:
         nb = ctypes.c_uint64(0)
         _check(lib().pv_packet_download(self.h, buf.ctypes.data, cap, ctypes.byref(nb), _stream_handle(stream)))
         return buf[:nb.value].tobytes()
+
+    def read_state(self):
+        P = self.volume.P
+        ri = np.zeros((P, 3, 64), np.uint16)
+        rv = np.zeros((P, 2, 256), np.uint16)
+        seq = ctypes.c_uint32(0)
+        _check(lib().pv_client_read_state(self.h, ri.ctypes.data, rv.ctypes.data, ctypes.byref(seq)))
+        return ri, rv, seq.value
+
+    def set_state(self, ref_irr, ref_vis, seq: int):
+        ri = np.ascontiguousarray(ref_irr, np.uint16)
+        rv = np.ascontiguousarray(ref_vis, np.uint16)
+        assert ri.size == self.volume.P * 192 and rv.size == self.volume.P * 512
+        _check(lib().pv_client_set_state(self.h, ri.ctypes.data, rv.ctypes.data, int(seq)))
 
     def read_masks(self):
         sync()

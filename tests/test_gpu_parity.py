@@ -421,3 +421,49 @@ def test_invalid_arguments_are_refused(ps, ctx):
         ps.Scene.from_synth(ctx, bad)
     v.close()
     sc.close()
+
+
+# ------------------------------------------------------------------ served: alone = in the mix
+def test_served_results_equal_alone_results(ps, ctx, O):
+    """Requests of 8 clients arrive as a Poisson trace and are served with
+    continuous batching under an HBM budget that forces evictions; every
+    client's packets equal the packets of the same requests served alone."""
+    from paper_2103_05875_amd import serve
+    _say("served vs alone, 8 clients, 64 requests, budget forcing evictions")
+    scene_syn = synth.box_city(n_tris=8000, extent=32.0)
+    scene = ps.Scene.from_synth(ctx, scene_syn)
+    rng = np.random.default_rng(31)
+    cfgs = []
+    for c in range(8):
+        ny = int(rng.integers(1, 4))
+        cfgs.append(synth.VolumeConfig(8, ny, 8, (2.0, 0.25, 2.0), (4.0, 1.5, 4.0), int(rng.choice([32, 64, 128])),
+                                       fp16=True, max_distance=6.0, sky=(0.1, 0.15, 0.25)))
+    path = synth.light_path(12, 64, extent=32.0)
+    t = np.cumsum(rng.exponential(1.0 / 800.0, 64))
+    frame_of = [0] * 8
+
+    def make():
+        reqs, fo = [], [0] * 8
+        for i in range(64):
+            c = int(rng_c[i])
+            l = scene_syn.lights.copy()
+            l[0, :3] = path[fo[c] % 64]
+            reqs.append(serve.Request(c, synth.rotation(200 + c, fo[c]), l, float(t[i])))
+            fo[c] += 1
+        return reqs
+    rng_c = rng.integers(0, 8, 64)
+    fps = [ps.volume_footprint(c) + ps.client_footprint(c) for c in cfgs]
+    budget = int(sum(sorted(fps)[-4:]) * 1.05)       # about half the clients fit at once
+    srv = serve.Server(ctx, scene, cfgs, hbm_budget=budget, n_streams=3, max_batch=8)
+    served = srv.run(make())
+    srv.close()
+    assert srv.evictions > 0 and max(r.batch_size for r in served) > 1
+    alone = serve.serve_plain(ctx, scene, cfgs, make())
+    by_client = lambda rs: {c: [r.packet for r in sorted((r for r in rs if r.client == c), key=lambda r: r.arrival)]
+                            for c in range(8)}
+    a, b = by_client(served), by_client(alone)
+    for c in range(8):
+        assert a[c] == b[c], f"client {c} differs"
+    _say(f"  evictions {srv.evictions}, largest batch {max(r.batch_size for r in served)}, "
+         f"latency {serve.latency_stats(served)}")
+    scene.close()
