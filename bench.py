@@ -23,15 +23,18 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "probe-rays/s and probes updated/s at 1 GPU (plain vs batched/served); p50/p99 latency"
 
 # Algorithmic FP32 work of the traversal (FMA = 2, add/mul/min/max/compare = 1):
-# one node visit tests two child boxes (12 FMA, 16 min/max, 2 compares);
-# one triangle test (two crosses, four dots, a reciprocal, compares).
-FLOP_PER_NODE_VISIT = 42
+# one node visit tests four child boxes (per box 6 plane FMAs, 10 min/max, one
+# compare = 23) after 9 ops of per-node decode; one triangle test (two
+# crosses, four dots, a reciprocal, compares) = 52.
+FLOP_PER_NODE_VISIT = 101
 FLOP_PER_TRI_TEST = 52
 PEAK_FP32_VECTOR = 157.3e12        # MI355X published FP32 vector peak (FLOP/s)
 PEAK_HBM = 8.0e12                  # MI355X published HBM3E bandwidth (B/s)
@@ -44,6 +47,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--legs", default="batched,served,encode",
+                    help="extra workloads reported in the same line (comma list, or 'none')")
+    ap.add_argument("--served-seconds", type=float, default=1.0)
+    ap.add_argument("--encode-frames", type=int, default=120)
     return ap.parse_args()
 
 
@@ -51,7 +58,6 @@ def cpu_baseline(cfg, scene, path, budget_s: float):
     """The oracle as it stands on the host cores: full frames of the same
     workload (trace + shade, blend, pack), as many as fit the budget
     (at least one)."""
-    import numpy as np
 
     import oracle
     import synth
@@ -79,6 +85,160 @@ def cpu_baseline(cfg, scene, path, budget_s: float):
             "probes_per_s": frames * cfg.n_probes / dt,
             "sample": f"{frames} full frame(s) of the same workload (trace + shade, blend, pack), "
                       f"{dt:.1f} s wall, OpenMP over probes"}
+
+
+def leg_batched(ps, torch, reps: int):
+    """Batched workload: 32 volumes (probes log-uniform 256-8192, rays from
+    {64,128,256,512}, each over its own 5k-100k-triangle box scene), one
+    persistent launch per frame, against the same volumes updated one by
+    one on the plain path."""
+    import synth
+    specs = synth.batched_volumes(32, seed=20)
+    ctx = ps.Context(0)
+    scenes, plain, batched = [], [], []
+    for s in specs:
+        sc_syn = synth.box_field(s["n_tris"], seed=s["scene_seed"])
+        sc = ps.Scene.from_synth(ctx, sc_syn)
+        scenes.append(sc)
+        a, b = ps.Volume(ctx, s["config"]), ps.Volume(ctx, s["config"])
+        a.set_scene(sc)
+        b.set_scene(sc)
+        plain.append(a)
+        batched.append(b)
+    rays = sum(s["config"].n_probes * s["config"].rays_per_probe for s in specs)
+    probes = sum(s["config"].n_probes for s in specs)
+    stream = torch.cuda.current_stream()
+
+    def run(f, which):
+        rots = [synth.rotation(20 + i, f) for i in range(len(specs))]
+        if which == "plain":
+            for v, R in zip(plain, rots):
+                v.update_probes(R, stream=stream)
+        else:
+            ps.update_probes_batched(batched, rots, stream=stream)
+
+    out = {}
+    for which in ("plain", "batched"):
+        for f in range(2):
+            run(f, which)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for f in range(2, 2 + reps):
+            run(f, which)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[which] = {"ms_per_frame": ms, "probe_rays_per_s": rays / (ms / 1e3), "probes_per_s": probes / (ms / 1e3)}
+    same = all(np.array_equal(a.read_maps()[0], b.read_maps()[0]) for a, b in zip(plain, batched))
+    assert ctx.check() == 0
+    out.update({"volumes": len(specs), "probes": probes, "probe_rays": rays, "bit_identical_to_plain": bool(same),
+                "speedup": out["plain"]["ms_per_frame"] / out["batched"]["ms_per_frame"]})
+    for h in plain + batched + scenes:
+        h.close()
+    ctx.close()
+    return out
+
+
+def leg_served(ps, duration_s: float):
+    """Served workload: 64 clients (probes log-uniform 512-16384, rays from
+    {64,128,256}) over one shared 200k-triangle scene, Poisson requests at
+    2000/s, continuous batching with HBM admission; against the same trace
+    served one request at a time."""
+    import synth
+    from paper_2103_05875_amd import serve
+    cfgs = synth.served_clients(64, seed=30)
+    scene_syn = synth.box_field(200_000, seed=31)
+    arrivals = synth.poisson_arrivals(2000.0, duration_s, len(cfgs), seed=30)
+    path = synth.light_path(12, 240)
+
+    def make():
+        fo = [0] * len(cfgs)
+        reqs = []
+        for t, c in arrivals:
+            l = scene_syn.lights.copy()
+            l[0, :3] = path[fo[c] % 240]
+            reqs.append(serve.Request(c, synth.rotation(300 + c, fo[c]), l, t))
+            fo[c] += 1
+        return reqs
+    ctx = ps.Context(0)
+    scene = ps.Scene.from_synth(ctx, scene_syn)
+    total_fp = sum(ps.volume_footprint(c) + ps.client_footprint(c) for c in cfgs)
+    budget = int(0.75 * total_fp)
+    srv = serve.Server(ctx, scene, cfgs, hbm_budget=budget, n_streams=3, max_batch=32)
+    t0 = time.perf_counter()
+    served = srv.run(make(), timeout_s=120.0)
+    span = max(r.done for r in served)
+    srv.close()
+    plain = serve.serve_plain(ctx, scene, cfgs, make(), timeout_s=240.0)
+    span_p = max(r.done for r in plain)
+    probes = sum(cfgs[r.client].n_probes for r in served)
+    rays = sum(cfgs[r.client].n_probes * cfgs[r.client].rays_per_probe for r in served)
+    same = all(a.packet == b.packet for a, b in zip(sorted(served, key=lambda r: r.arrival),
+                                                     sorted(plain, key=lambda r: r.arrival)))
+    out = {"clients": len(cfgs), "requests": len(served), "arrival_rate_hz": 2000.0, "duration_s": duration_s,
+           "offered_probes_per_s": probes / duration_s, "hbm_budget_bytes": budget, "footprint_all_bytes": total_fp,
+           "served": dict(serve.latency_stats(served), probes_per_s=probes / span, probe_rays_per_s=rays / span,
+                          mean_batch=float(np.mean([r.batch_size for r in served])),
+                          evictions=srv.evictions, admissions=srv.admissions),
+           "plain": dict(serve.latency_stats(plain), probes_per_s=probes / span_p, probe_rays_per_s=rays / span_p),
+           "packets_identical": bool(same)}
+    scene.close()
+    ctx.close()
+    return out
+
+
+def leg_encode(ps, torch, frames: int):
+    """Encode path: 32x16x32 = 16,384 probes, 256 rays, 200k-triangle field
+    with 4 moving occluders and a moving light; each frame updates and packs
+    with tau = 1/1024 for both textures; pack throughput against HBM."""
+    import synth
+    import oracle
+    cfg = synth.config("encode")
+    scene_syn = synth.box_field(200_000, seed=40, n_moving=4)
+    ctx = ps.Context(0)
+    sc = ps.Scene.from_synth(ctx, scene_syn)
+    vol = ps.Volume(ctx, cfg)
+    vol.set_scene(sc)
+    cl = ps.Client(vol, 0)
+    dec = oracle.OracleClientDecoder(cfg.n_probes)
+    path = synth.light_path(12, frames)
+    stream = torch.cuda.current_stream()
+    ctx.set_timing(True)
+    ctx.stage_times()
+    sent_bytes, ok, changed = 0, True, []
+    for f in range(frames):
+        sc.set_dynamic(synth.moving_occluders(40, f, 4), stream=stream)
+        l = scene_syn.lights.copy()
+        l[0, :3] = path[f]
+        vol.update_probes(synth.rotation(41, f), l, stream=stream)
+        cl.pack_delta(1.0 / 1024, 1.0 / 1024, stream=stream)
+        pkt = cl.packet_download(stream=stream)
+        sent_bytes += len(pkt)
+        ok &= dec.apply(pkt) == 0
+        if f % 20 == 19 or f == frames - 1:
+            ri, rv, _ = cl.read_state()
+            ok &= bool(np.array_equal(dec.irr[:, :, 1:-1, 1:-1].reshape(cfg.n_probes, 3, -1), ri))
+            ok &= bool(np.array_equal(dec.vis[:, :, 1:-1, 1:-1].reshape(cfg.n_probes, 2, -1), rv))
+        mi, mv = cl.read_masks()
+        changed.append((int(mi.sum()), int(mv.sum())))
+    st = ctx.stage_times()
+    ctx.set_timing(False)
+    P = cfg.n_probes
+    pack_ms = sum(st[k][0] for k in ("pack_mask", "pack_scan", "pack_compact")) / frames
+    ki = np.mean([c[0] for c in changed])
+    kv = np.mean([c[1] for c in changed])
+    pack_bytes = P * 1408 * 2 + (ki * 384 + kv * 1024) * 2 + P * 2
+    upd_ms = (st["raydirs"][0] + st["trace"][0] + st["blend"][0]) / frames
+    out = {"probes": P, "frames": frames, "round_trip_bit_exact": bool(ok), "mean_changed_irr": ki,
+           "mean_changed_vis": kv, "packet_bytes_per_frame": sent_bytes / frames,
+           "Mbps_at_10Hz": sent_bytes / frames * 8 * 10 / 1e6,
+           "update_ms": upd_ms, "probe_rays_per_s": P * cfg.rays_per_probe / (upd_ms / 1e3),
+           "pack_ms": pack_ms, "pack_hbm_GBps": pack_bytes / (pack_ms / 1e3) / 1e9,
+           "pack_hbm_frac": pack_bytes / (pack_ms / 1e3) / PEAK_HBM}
+    for h in (cl, vol, sc, ctx):
+        h.close()
+    return out
 
 
 def main():
@@ -200,12 +360,24 @@ def main():
                          "Quadro RTX 8000 with RT cores, i.e. about 0.22 G probe-rays/s and 0.85 M probes/s; "
                          "different scenes and hardware, so not a ratio",
     }
+    legs = [] if args.legs in ("", "none") else args.legs.split(",")
+    for h in (cl, vol, sc, ctx):
+        h.close()
+    runners = {"batched": lambda: leg_batched(ps, torch, reps=5),
+               "served": lambda: leg_served(ps, args.served_seconds),
+               "encode": lambda: leg_encode(ps, torch, args.encode_frames)}
+    for name in legs:
+        print(f"bench: {name} leg", file=sys.stderr, flush=True)
+        try:
+            out[name] = runners[name]()
+        except Exception as e:  # a failed leg is reported, the headline line is still printed
+            import traceback
+            traceback.print_exc()
+            out[name] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
         print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, scene, path, args.cpu_seconds)
     print(json.dumps(out), flush=True)
-    for h in (cl, vol, sc, ctx):
-        h.close()
 
 
 if __name__ == "__main__":

@@ -244,6 +244,24 @@ pv_status pv_sync(void *stream);
  * is then invalid). */
 pv_status pv_ctx_check(pv_ctx *ctx, int *status);
 
+/*
+ * Launch shape of the trace kernel (a tuning choice; every shape computes
+ * identical results): probes per wavefront packet as a brick
+ * brick[0] x brick[1] x brick[2] = 64 of one ray direction, a persistent grid
+ * with per-XCD work queues (1) or one wavefront per packet (0), the number of
+ * top BVH nodes staged in LDS (0, 21 or 85: one, three or four levels), and
+ * threads per block (128 or 256). Defaults: 4x4x4, 0, 0, 128.
+ */
+typedef struct {
+    int brick[3];
+    int persistent;
+    int top_nodes;
+    int block_threads;
+} pv_trace_config;
+
+pv_status pv_volume_set_trace_config(pv_volume *vol, const pv_trace_config *cfg);
+pv_status pv_volume_get_trace_config(pv_volume *vol, pv_trace_config *cfg);
+
 /* Kernel stages that can be timed with HIP events. */
 typedef enum {
     PV_STAGE_RAYDIRS = 0,

@@ -61,7 +61,7 @@ int levels_needed(int count) {
 
 class Builder {
   public:
-    Builder(std::vector<Ref> &refs) : refs_(refs) {}
+    Builder(std::vector<Ref> &refs, int max_depth = kMaxDepth) : refs_(refs), limit_(max_depth) {}
 
     int build(int first, int count, int depth) {
         int id = (int)nodes_.size();
@@ -80,7 +80,7 @@ class Builder {
             return id;
         }
         int mid = -1;
-        bool tight = depth + levels_needed(count) + 1 >= kMaxDepth;
+        bool tight = depth + levels_needed(count) + 1 >= limit_;
         if (!tight) mid = sah_split(first, count, box, cbox);
         if (mid <= first || mid >= first + count) mid = median_split(first, count, cbox);
         int l = build(first, mid - first, depth + 1);
@@ -191,6 +191,7 @@ class Builder {
     }
 
     std::vector<Ref> &refs_;
+    int limit_;
 };
 
 float bits_as_float(int v) {
@@ -314,6 +315,209 @@ bool build_bvh(const float *tri9, int n, int id_base, HostBvh &out, std::string 
         o.meta = make_int4(ch[0], ch[1], cnt[0], cnt[1]);
     }
     return true;
+}
+
+// ---------------------------------------------------------------------------
+// 4-wide quantized BVH
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Collapse {
+    const std::vector<BNode> &bn;
+    // tree of 4-wide nodes in creation order: children slots hold either a
+    // leaf BNode (count > 0) or a 4-wide node id (count == 0)
+    struct N4 {
+        int nk = 0;
+        int kid_bnode[4] = {-1, -1, -1, -1};
+        int kid_n4[4] = {-1, -1, -1, -1};
+    };
+    std::vector<N4> tree;
+    std::vector<GpuNode4> out;
+    Collapse(const std::vector<BNode> &b) : bn(b) {}
+
+    // children of a 4-wide node: expand the largest inner child until 4
+    void gather(int id, std::vector<int> &kids) const {
+        kids = {bn[id].left, bn[id].right};
+        while (kids.size() < 4) {
+            int best = -1;
+            float area = -1.f;
+            for (size_t i = 0; i < kids.size(); ++i)
+                if (bn[kids[i]].count == 0 && bn[kids[i]].box.half_area() > area) {
+                    area = bn[kids[i]].box.half_area();
+                    best = (int)i;
+                }
+            if (best < 0) break;
+            int k = kids[best];
+            kids.erase(kids.begin() + best);
+            kids.push_back(bn[k].left);
+            kids.push_back(bn[k].right);
+        }
+    }
+
+    // builds the subtree of BNode id; returns its N4 id, depth and the
+    // worst-case number of stack entries its traversal can add
+    int build(int id, int &depth, int &need) {
+        std::vector<int> kids;
+        if (bn[id].count > 0)
+            kids = {id};  // single-leaf root
+        else
+            gather(id, kids);
+        const int me = (int)tree.size();
+        tree.emplace_back();
+        int sub_depth = 0, sub_need = 0, inner = 0;
+        for (size_t c = 0; c < kids.size(); ++c) {
+            tree[me].kid_bnode[c] = kids[c];
+            if (bn[kids[c]].count == 0) {
+                int cd, cn;
+                const int ci = build(kids[c], cd, cn);
+                tree[me].kid_n4[c] = ci;
+                sub_depth = std::max(sub_depth, cd);
+                sub_need = std::max(sub_need, cn);
+                ++inner;
+            }
+        }
+        tree[me].nk = (int)kids.size();
+        depth = sub_depth + 1;
+        // descending into one inner child leaves at most the other inner
+        // children of this node on the stack
+        need = inner > 0 ? sub_need + (inner - 1) : 0;
+        return me;
+    }
+
+    // nodes numbered breadth first, so the top levels are a prefix
+    void emit(int root) {
+        std::vector<int> order, index(tree.size(), -1);
+        order.push_back(root);
+        for (size_t i = 0; i < order.size(); ++i)
+            for (int c = 0; c < tree[order[i]].nk; ++c)
+                if (tree[order[i]].kid_n4[c] >= 0) order.push_back(tree[order[i]].kid_n4[c]);
+        for (size_t i = 0; i < order.size(); ++i) index[order[i]] = (int)i;
+        out.resize(order.size());
+        for (size_t i = 0; i < order.size(); ++i) {
+            const N4 &t = tree[order[i]];
+            int child[4] = {-1, -1, -1, -1}, count[4] = {0, 0, 0, 0};
+            Box box[4];
+            for (int c = 0; c < t.nk; ++c) {
+                const BNode &k = bn[t.kid_bnode[c]];
+                box[c] = k.box;
+                if (k.count > 0) {
+                    child[c] = k.first;
+                    count[c] = k.count;
+                } else {
+                    child[c] = index[t.kid_n4[c]];
+                }
+            }
+            quantize(out[i], (size_t)t.nk, box, child, count);
+        }
+    }
+
+    void quantize(GpuNode4 &g, size_t nk, const Box *box, const int *child, const int *count) const {
+        float L[3], H[3];
+        for (int a = 0; a < 3; ++a) {
+            L[a] = INFINITY;
+            H[a] = -INFINITY;
+            for (size_t c = 0; c < nk; ++c) {
+                L[a] = std::min(L[a], box[c].lo[a]);
+                H[a] = std::max(H[a], box[c].hi[a]);
+            }
+        }
+        int eb[3];
+        double scale[3];
+        for (int a = 0; a < 3; ++a) {
+            const double ext = (double)H[a] - (double)L[a];
+            int e = -126;
+            while (std::ldexp(255.0, e) < ext) ++e;
+            eb[a] = e + 127;
+            scale[a] = std::ldexp(1.0, e);
+        }
+        uint8_t q[6][4];
+        for (int c = 0; c < 4; ++c)
+            for (int a = 0; a < 3; ++a) {
+                if ((size_t)c < nk) {
+                    double lo = std::floor(((double)box[c].lo[a] - L[a]) / scale[a]);
+                    double hi = std::ceil(((double)box[c].hi[a] - L[a]) / scale[a]);
+                    // outward: decoded lo <= box lo, decoded hi >= box hi
+                    while (lo > 0 && L[a] + lo * scale[a] > box[c].lo[a]) lo -= 1;
+                    while (hi < 255 && L[a] + hi * scale[a] < box[c].hi[a]) hi += 1;
+                    q[2 * a][c] = (uint8_t)std::min(std::max(lo, 0.0), 255.0);
+                    q[2 * a + 1][c] = (uint8_t)std::min(std::max(hi, 0.0), 255.0);
+                } else {
+                    q[2 * a][c] = 255;  // empty: lo above hi
+                    q[2 * a + 1][c] = 0;
+                }
+            }
+        auto pack = [](const uint8_t *v) {
+            return (uint32_t)v[0] | ((uint32_t)v[1] << 8) | ((uint32_t)v[2] << 16) | ((uint32_t)v[3] << 24);
+        };
+        uint32_t fb[3];
+        std::memcpy(fb, L, 12);
+        g.w0 = make_uint4(fb[0], fb[1], fb[2], (uint32_t)eb[0] | ((uint32_t)eb[1] << 8) | ((uint32_t)eb[2] << 16));
+        g.w1 = make_uint4(pack(q[0]), pack(q[1]), pack(q[2]), pack(q[3]));
+        uint8_t cnt[4];
+        for (int c = 0; c < 4; ++c) cnt[c] = (uint8_t)count[c];
+        g.w2 = make_uint4(pack(q[4]), pack(q[5]), pack(cnt), 0u);
+        g.w3 = make_uint4((uint32_t)child[0], (uint32_t)child[1], (uint32_t)child[2], (uint32_t)child[3]);
+    }
+};
+
+}  // namespace
+
+bool build_bvh4(const float *tri9, int n, int id_base, HostBvh4 &out, std::string &err) {
+    out.nodes.clear();
+    out.tris.clear();
+    out.depth = out.stack_need = 0;
+    if (n <= 0) return true;
+    for (int limit = kMaxDepth; limit >= 8; limit -= 2) {
+        std::vector<Ref> refs(n);
+        Box scene;
+        scene.reset();
+        for (int i = 0; i < n; ++i) {
+            const float *t = tri9 + 9 * (size_t)i;
+            for (int k = 0; k < 9; ++k)
+                if (!std::isfinite(t[k])) {
+                    err = "triangle " + std::to_string(i) + " has a non-finite coordinate";
+                    return false;
+                }
+            refs[i].box.reset();
+            for (int v = 0; v < 3; ++v) refs[i].box.grow(t + 3 * v);
+            for (int k = 0; k < 3; ++k) refs[i].c[k] = (t[k] + t[3 + k] + t[6 + k]) / 3.0f;
+            refs[i].tri = i;
+            scene.grow(refs[i].box);
+        }
+        if (levels_needed(n) + 2 > limit) break;
+        Builder b(refs, limit);
+        b.build(0, n, 0);
+        // conservative padding of every box (rounding of the slab test)
+        float diag = 0.f;
+        for (int k = 0; k < 3; ++k) diag += (scene.hi[k] - scene.lo[k]) * (scene.hi[k] - scene.lo[k]);
+        diag = std::sqrt(diag);
+        const float pad_abs = diag * 9.5367431640625e-7f;
+        for (BNode &nd : b.nodes_)
+            for (int k = 0; k < 3; ++k) {
+                nd.box.lo[k] -= pad_abs + std::fabs(nd.box.lo[k]) * 2.384185791015625e-7f;
+                nd.box.hi[k] += pad_abs + std::fabs(nd.box.hi[k]) * 2.384185791015625e-7f;
+            }
+        Collapse col(b.nodes_);
+        int depth, need;
+        const int root = col.build(0, depth, need);
+        if (need > kStack4) continue;  // lower the binary depth limit and retry
+        col.emit(root);
+        out.nodes = std::move(col.out);
+        out.depth = depth;
+        out.stack_need = need;
+        out.tris.resize(n);
+        for (int i = 0; i < n; ++i) {
+            const float *t = tri9 + 9 * (size_t)refs[i].tri;
+            GpuTri g;
+            g.v0 = make_float4(t[0], t[1], t[2], bits_as_float(id_base + refs[i].tri));
+            g.e1 = make_float4(t[3] - t[0], t[4] - t[1], t[5] - t[2], 0.f);
+            g.e2 = make_float4(t[6] - t[0], t[7] - t[1], t[8] - t[2], 0.f);
+            out.tris[i] = g;
+        }
+        return true;
+    }
+    err = "cannot bound the traversal stack of this scene";
+    return false;
 }
 
 }  // namespace pv

@@ -33,8 +33,10 @@ struct alignas(16) GpuTri {
     float4 v0, e1, e2;
 };
 
+struct GpuNode4;
+
 struct DeviceBvh {
-    GpuNode *nodes = nullptr;
+    GpuNode4 *nodes = nullptr;
     GpuTri *tris = nullptr;
     int n_nodes = 0;
     int n_tris = 0;
@@ -55,6 +57,33 @@ constexpr int kLeafMax = 4;
 // Builds a BVH over triangles (tri9: [n][9] float) with original ids
 // id_base + i. Returns false if a triangle is not finite.
 bool build_bvh(const float *tri9, int n, int id_base, HostBvh &out, std::string &err);
+
+// 4-wide node with 8-bit quantized child boxes, one 64-byte line:
+//   w0 = origin.x, origin.y, origin.z (float bits), exps = ex | ey<<8 | ez<<16
+//        (biased exponents: scale_a = 2^(e_a - 127), so lo = origin + q*scale)
+//   w1 = bytes qlo_x[4] | qhi_x[4] | qlo_y[4] | qhi_y[4]  (byte c = child c)
+//   w2 = bytes qlo_z[4] | qhi_z[4] | count[4] | 0
+//   w3 = child[4]: inner node index (count 0), first triangle of a leaf
+//        (count > 0), or -1 for an empty slot
+// Quantization rounds outward (floor / ceil), so decoded boxes contain the
+// exact ones.
+struct alignas(16) GpuNode4 {
+    uint4 w0, w1, w2, w3;
+};
+
+struct HostBvh4 {
+    std::vector<GpuNode4> nodes;
+    std::vector<GpuTri> tris;
+    int depth = 0;
+    int stack_need = 0;  // worst-case traversal stack entries (proved bound)
+};
+
+// Stack entries the 4-wide traversal may hold at once.
+constexpr int kStack4 = 32;
+
+// Builds the 4-wide quantized BVH (collapsed from the binary SAH tree, with
+// the binary depth limit lowered until the worst-case stack fits kStack4).
+bool build_bvh4(const float *tri9, int n, int id_base, HostBvh4 &out, std::string &err);
 
 // ---------------------------------------------------------------------------
 // Kernel parameter blocks (passed by value)
@@ -99,12 +128,25 @@ struct BatchVolume {
     int bricks_x, bricks_y, bricks_z;
 };
 
+// Launch shape of the trace: probe brick per wavefront (bx*by*bz = 64),
+// persistent grid with per-XCD work queues or one wave per packet, number of
+// top BVH nodes staged in LDS (0, 21 or 85 = the top 1, 3 or 4 levels), and
+// threads per block (128 or 256).
+struct TraceConfig {
+    int bx = 4, by = 4, bz = 4;
+    int persistent = 0;
+    int top_nodes = 0;
+    int block = 128;
+};
+
 // ---------------------------------------------------------------------------
 // Launchers (kernels.hip)
 // ---------------------------------------------------------------------------
-hipError_t launch_raydirs(const FrameParams &fp, int n, float4 *dirs, hipStream_t s);
+// queue: 8 ints zeroed by this kernel for the persistent trace that follows
+hipError_t launch_raydirs(const FrameParams &fp, int n, float4 *dirs, int *queue, hipStream_t s);
 hipError_t launch_trace(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp, const float4 *dirs,
-                        float4 *rays, int32_t *hits, unsigned long long *counts, hipStream_t s);
+                        float4 *rays, int32_t *hits, unsigned long long *counts, const TraceConfig &tc,
+                        int *queue, hipStream_t s);
 hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4 *rays, void *irr, void *vis,
                         int fp16, float h, hipStream_t s);
 hipError_t launch_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, int total_blend,

@@ -16,7 +16,7 @@
 namespace pv {
 
 constexpr int kTraceBlock = 128;  // two wavefronts
-constexpr int kStack = kMaxDepth;
+constexpr int kStack = kStack4;
 constexpr int kBlendBlock = 256;
 constexpr int kBlendProbes = 4;
 constexpr int kBlendChunk = 256;
@@ -58,7 +58,8 @@ __device__ void raydir_one(const FrameParams &fp, int n, int i, float4 *dirs) {
                           (float)(R[6] * sx + R[7] * sy + R[8] * z), 0.f);
 }
 
-__global__ void k_raydirs(FrameParams fp, int n, float4 *dirs) {
+__global__ void k_raydirs(FrameParams fp, int n, float4 *dirs, int *queue) {
+    if (queue && blockIdx.x == 0 && threadIdx.x < 8) queue[threadIdx.x] = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += blockDim.x * gridDim.x) raydir_one(fp, n, i, dirs);
 }
 
@@ -87,26 +88,6 @@ __device__ __forceinline__ Ray make_ray(float3 o, float3 d) {
     r.inv = make_float3(1.0f / dx, 1.0f / dy, 1.0f / dz);
     r.oinv = make_float3(o.x * r.inv.x, o.y * r.inv.y, o.z * r.inv.z);
     return r;
-}
-
-// Both child boxes of a node against [tmin, tmax]: entry distances and hits.
-__device__ __forceinline__ void box2(const GpuNode &nd, const Ray &r, float tmin, float tmax, float &t0, float &t1,
-                                     bool &h0, bool &h1) {
-    float ax0 = fmaf(nd.bx.x, r.inv.x, -r.oinv.x), ax1 = fmaf(nd.bx.z, r.inv.x, -r.oinv.x);
-    float ay0 = fmaf(nd.by.x, r.inv.y, -r.oinv.y), ay1 = fmaf(nd.by.z, r.inv.y, -r.oinv.y);
-    float az0 = fmaf(nd.bz.x, r.inv.z, -r.oinv.z), az1 = fmaf(nd.bz.z, r.inv.z, -r.oinv.z);
-    float bx0 = fmaf(nd.bx.y, r.inv.x, -r.oinv.x), bx1 = fmaf(nd.bx.w, r.inv.x, -r.oinv.x);
-    float by0 = fmaf(nd.by.y, r.inv.y, -r.oinv.y), by1 = fmaf(nd.by.w, r.inv.y, -r.oinv.y);
-    float bz0 = fmaf(nd.bz.y, r.inv.z, -r.oinv.z), bz1 = fmaf(nd.bz.w, r.inv.z, -r.oinv.z);
-    float an = fmaxf(fmaxf(fminf(ax0, ax1), fminf(ay0, ay1)), fmaxf(fminf(az0, az1), tmin));
-    float af = fminf(fminf(fmaxf(ax0, ax1), fmaxf(ay0, ay1)), fminf(fmaxf(az0, az1), tmax));
-    float bn = fmaxf(fmaxf(fminf(bx0, bx1), fminf(by0, by1)), fmaxf(fminf(bz0, bz1), tmin));
-    float bf = fminf(fminf(fmaxf(bx0, bx1), fmaxf(by0, by1)), fminf(fmaxf(bz0, bz1), tmax));
-    t0 = an;
-    t1 = bn;
-    // an empty slot (child -1, count 0) stores lo = +inf, hi = -inf
-    h0 = an <= af && (nd.meta.x >= 0 || nd.meta.z > 0);
-    h1 = bn <= bf && (nd.meta.y >= 0 || nd.meta.w > 0);
 }
 
 // Two-sided Moller-Trumbore: true when the ray line crosses the triangle
@@ -139,26 +120,121 @@ struct Stack {
     __device__ __forceinline__ int pop(int &sp) { return base[(--sp) * W]; }
 };
 
+// Four quantized child boxes of a node against [tmin, tmax]. The byte
+// coordinates decode as origin + q * 2^e; the slab distance of a plane is
+// (origin + q*s - o) / d = q * (s/d) + (origin - o)/d, one FMA per plane.
+struct Node4Hits {
+    float tn[4];
+    bool hit[4];
+    int child[4];
+    int count[4];
+};
+
+__device__ __forceinline__ float ubyte(uint32_t w, int c) { return (float)((w >> (8 * c)) & 0xffu); }
+
+__device__ __forceinline__ void box4(const uint4 w0, const uint4 w1, const uint4 w2, const uint4 w3, const Ray &r,
+                                     float tmin, float tmax, Node4Hits &o) {
+    const float ax = __uint_as_float((w0.w & 0xffu) << 23) * r.inv.x;
+    const float ay = __uint_as_float(((w0.w >> 8) & 0xffu) << 23) * r.inv.y;
+    const float az = __uint_as_float(((w0.w >> 16) & 0xffu) << 23) * r.inv.z;
+    const float bx = (__uint_as_float(w0.x) - r.o.x) * r.inv.x;
+    const float by = (__uint_as_float(w0.y) - r.o.y) * r.inv.y;
+    const float bz = (__uint_as_float(w0.z) - r.o.z) * r.inv.z;
+    o.child[0] = (int)w3.x;
+    o.child[1] = (int)w3.y;
+    o.child[2] = (int)w3.z;
+    o.child[3] = (int)w3.w;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float x0 = fmaf(ubyte(w1.x, c), ax, bx), x1 = fmaf(ubyte(w1.y, c), ax, bx);
+        const float y0 = fmaf(ubyte(w1.z, c), ay, by), y1 = fmaf(ubyte(w1.w, c), ay, by);
+        const float z0 = fmaf(ubyte(w2.x, c), az, bz), z1 = fmaf(ubyte(w2.y, c), az, bz);
+        const float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tmin));
+        const float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tmax));
+        o.tn[c] = tn;
+        o.hit[c] = tn <= tf && o.child[c] >= 0;
+        o.count[c] = (int)((w2.z >> (8 * c)) & 0xffu);
+    }
+}
+
+// Orders the hit inner children by entry distance; returns how many.
+__device__ __forceinline__ int sort_inner(const Node4Hits &h, int ids[4]) {
+    float k[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const bool inner = h.hit[c] && h.count[c] == 0;
+        k[c] = inner ? h.tn[c] : 3.0e38f;
+        ids[c] = h.child[c];
+    }
+    int m = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) m += (h.hit[c] && h.count[c] == 0) ? 1 : 0;
+#define PV_CSWAP(a, b)                                   \
+    if (k[b] < k[a]) {                                   \
+        const float tk = k[a];                           \
+        k[a] = k[b];                                     \
+        k[b] = tk;                                       \
+        const int ti = ids[a];                           \
+        ids[a] = ids[b];                                 \
+        ids[b] = ti;                                     \
+    }
+    PV_CSWAP(0, 1)
+    PV_CSWAP(2, 3)
+    PV_CSWAP(0, 2)
+    PV_CSWAP(1, 3)
+    PV_CSWAP(1, 2)
+#undef PV_CSWAP
+    return m;
+}
+
+// LDS copy of the top BVH nodes (dynamic shared memory of the trace kernel).
+extern __shared__ uint4 pv_top_nodes[];
+
+// Node fetch: the first 'top' nodes (breadth-first order, so the top levels)
+// may be staged in LDS; the rest come from global memory.
+struct NodeSrc {
+    const uint4 *global;
+    int top;
+    __device__ __forceinline__ void load(int node, uint4 &w0, uint4 &w1, uint4 &w2, uint4 &w3) const {
+        if (node < top) {
+            w0 = pv_top_nodes[4 * node];
+            w1 = pv_top_nodes[4 * node + 1];
+            w2 = pv_top_nodes[4 * node + 2];
+            w3 = pv_top_nodes[4 * node + 3];
+        } else {
+            const uint4 *q = global + 4 * (size_t)node;
+            w0 = q[0];
+            w1 = q[1];
+            w2 = q[2];
+            w3 = q[3];
+        }
+    }
+};
+
+__device__ __forceinline__ NodeSrc global_nodes(const DeviceBvh &bvh) {
+    return NodeSrc{reinterpret_cast<const uint4 *>(bvh.nodes), 0};
+}
+
 // Closest hit in one BVH; updates (tbest, best tri index, best array) when a
 // nearer hit is found; equal distances go to the smaller original id.
+// Leaves are tested where they are met; hit inner children are visited
+// nearest first, the others pushed (the builder bounds the stack).
 template <bool COUNT, int W>
-__device__ void closest(const DeviceBvh &bvh, const Ray &r, float tmin, float &tbest, int &best, int &best_id,
-                        const GpuTri *&best_arr, Stack<W> stk, Counts &cnt) {
+__device__ void closest(const DeviceBvh &bvh, const NodeSrc &src, const Ray &r, float tmin, float &tbest, int &best,
+                        int &best_id, const GpuTri *&best_arr, Stack<W> stk, Counts &cnt) {
     if (bvh.n_nodes == 0) return;
     int node = 0, sp = 0;
     while (true) {
-        const GpuNode nd = bvh.nodes[node];
-        float t0, t1;
-        bool h0, h1;
-        box2(nd, r, tmin, tbest, t0, t1, h0, h1);
+        Node4Hits h;
+        uint4 w0, w1, w2, w3;
+        src.load(node, w0, w1, w2, w3);
+        box4(w0, w1, w2, w3, r, tmin, tbest, h);
         if (COUNT) cnt.nodes++;
-        // leaves are tested in place
-        for (int c = 0; c < 2; ++c) {
-            const bool hc = c == 0 ? h0 : h1;
-            const int cnt_c = c == 0 ? nd.meta.z : nd.meta.w;
-            if (hc && cnt_c > 0) {
-                const int first = c == 0 ? nd.meta.x : nd.meta.y;
-                for (int k = first; k < first + cnt_c; ++k) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (h.hit[c] && h.count[c] > 0) {
+                const int first = h.child[c];
+                for (int k = first; k < first + h.count[c]; ++k) {
                     const GpuTri T = bvh.tris[k];
                     float t;
                     if (COUNT) cnt.tris++;
@@ -171,15 +247,14 @@ __device__ void closest(const DeviceBvh &bvh, const Ray &r, float tmin, float &t
                 }
             }
         }
-        const bool i0 = h0 && nd.meta.z == 0, i1 = h1 && nd.meta.w == 0;
-        if (i0 && i1) {
-            const bool first0 = t0 <= t1;
-            stk.push(sp, first0 ? nd.meta.y : nd.meta.x);
-            node = first0 ? nd.meta.x : nd.meta.y;
-        } else if (i0) {
-            node = nd.meta.x;
-        } else if (i1) {
-            node = nd.meta.y;
+        int ids[4];
+        const int m = sort_inner(h, ids);
+        if (m > 0) {
+            // constant indices keep ids[] in registers
+            if (m > 3) stk.push(sp, ids[3]);
+            if (m > 2) stk.push(sp, ids[2]);
+            if (m > 1) stk.push(sp, ids[1]);
+            node = ids[0];
         } else {
             if (sp == 0) break;
             node = stk.pop(sp);
@@ -189,36 +264,35 @@ __device__ void closest(const DeviceBvh &bvh, const Ray &r, float tmin, float &t
 
 // Any hit with tmin < t < tmax in one BVH.
 template <bool COUNT, int W>
-__device__ bool any_hit(const DeviceBvh &bvh, const Ray &r, float tmin, float tmax, Stack<W> stk, Counts &cnt) {
+__device__ bool any_hit(const DeviceBvh &bvh, const NodeSrc &src, const Ray &r, float tmin, float tmax, Stack<W> stk,
+                        Counts &cnt) {
     if (bvh.n_nodes == 0) return false;
     int node = 0, sp = 0;
     while (true) {
-        const GpuNode nd = bvh.nodes[node];
-        float t0, t1;
-        bool h0, h1;
-        box2(nd, r, tmin, tmax, t0, t1, h0, h1);
+        Node4Hits h;
+        uint4 w0, w1, w2, w3;
+        src.load(node, w0, w1, w2, w3);
+        box4(w0, w1, w2, w3, r, tmin, tmax, h);
         if (COUNT) cnt.nodes++;
-        for (int c = 0; c < 2; ++c) {
-            const bool hc = c == 0 ? h0 : h1;
-            const int cnt_c = c == 0 ? nd.meta.z : nd.meta.w;
-            if (hc && cnt_c > 0) {
-                const int first = c == 0 ? nd.meta.x : nd.meta.y;
-                for (int k = first; k < first + cnt_c; ++k) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (h.hit[c] && h.count[c] > 0) {
+                const int first = h.child[c];
+                for (int k = first; k < first + h.count[c]; ++k) {
                     float t;
                     if (COUNT) cnt.tris++;
                     if (tri_cross(bvh.tris[k], r, t) && t > tmin && t < tmax) return true;
                 }
             }
         }
-        const bool i0 = h0 && nd.meta.z == 0, i1 = h1 && nd.meta.w == 0;
-        if (i0 && i1) {
-            const bool first0 = t0 <= t1;
-            stk.push(sp, first0 ? nd.meta.y : nd.meta.x);
-            node = first0 ? nd.meta.x : nd.meta.y;
-        } else if (i0) {
-            node = nd.meta.x;
-        } else if (i1) {
-            node = nd.meta.y;
+        int ids[4];
+        const int m = sort_inner(h, ids);
+        if (m > 0) {
+            // constant indices keep ids[] in registers
+            if (m > 3) stk.push(sp, ids[3]);
+            if (m > 2) stk.push(sp, ids[2]);
+            if (m > 1) stk.push(sp, ids[1]);
+            node = ids[0];
         } else {
             if (sp == 0) return false;
             node = stk.pop(sp);
@@ -228,9 +302,10 @@ __device__ bool any_hit(const DeviceBvh &bvh, const Ray &r, float tmin, float tm
 
 // Trace and shade the ray of probe (x, y, z), direction j; writes its record.
 template <bool COUNT, int W>
-__device__ void trace_shade_one(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp, const float4 *dirs,
-                                float4 *rays, int32_t *hits, int x, int y, int z, int j, Stack<W> stk, Counts &cnt,
-                                uint32_t &shadow_rays) {
+__device__ void trace_shade_one(const VolumeParams &vp, const SceneView &sv, const NodeSrc &stat_src,
+                                const FrameParams &fp, const float4 *dirs, float4 *rays, int32_t *hits, int x, int y,
+                                int z, int j, Stack<W> stk, Counts &cnt, uint32_t &shadow_rays) {
+    const NodeSrc dyn_src = global_nodes(sv.dyn);
     const float3 o = make_float3(fmaf(vp.sx, (float)x, vp.ox), fmaf(vp.sy, (float)y, vp.oy),
                                  fmaf(vp.sz, (float)z, vp.oz));
     const float4 dj = dirs[j];
@@ -238,8 +313,8 @@ __device__ void trace_shade_one(const VolumeParams &vp, const SceneView &sv, con
     float tbest = INFINITY;
     int best = -1, best_id = -1;
     const GpuTri *arr = nullptr;
-    closest<COUNT, W>(sv.stat, ray, 0.f, tbest, best, best_id, arr, stk, cnt);
-    closest<COUNT, W>(sv.dyn, ray, 0.f, tbest, best, best_id, arr, stk, cnt);
+    closest<COUNT, W>(sv.stat, stat_src, ray, 0.f, tbest, best, best_id, arr, stk, cnt);
+    closest<COUNT, W>(sv.dyn, dyn_src, ray, 0.f, tbest, best, best_id, arr, stk, cnt);
     float3 L;
     float dist;
     if (best >= 0) {
@@ -266,8 +341,8 @@ __device__ void trace_shade_one(const VolumeParams &vp, const SceneView &sv, con
             const Ray sr = make_ray(so, sd);
             const float smax = slen - sv.eps;
             if (COUNT) shadow_rays++;
-            bool occ = any_hit<COUNT, W>(sv.stat, sr, 0.f, smax, stk, cnt);
-            if (!occ) occ = any_hit<COUNT, W>(sv.dyn, sr, 0.f, smax, stk, cnt);
+            bool occ = any_hit<COUNT, W>(sv.stat, stat_src, sr, 0.f, smax, stk, cnt);
+            if (!occ) occ = any_hit<COUNT, W>(sv.dyn, dyn_src, sr, 0.f, smax, stk, cnt);
             if (!occ) {
                 const float g = cosv / d2 * 0.31830988618379067f;  // 1/pi
                 L.x = fmaf(alb.x * fp.light_int[li][0], g, L.x);
@@ -286,24 +361,63 @@ __device__ void trace_shade_one(const VolumeParams &vp, const SceneView &sv, con
     if (hits) hits[q] = best_id;
 }
 
-template <bool COUNT>
-__global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeParams vp, SceneView sv, FrameParams fp,
-                                                      const float4 *dirs, float4 *rays, int32_t *hits,
-                                                      unsigned long long *counts, int bricks_x, int bricks_y,
-                                                      int n_waves) {
-    __shared__ int stk[kStack * kTraceBlock];
-    const int w = xcd_logical_block() * (kTraceBlock / 64) + (threadIdx.x >> 6);
-    if (w >= n_waves) return;
+struct TraceGrid {
+    int bx, by, bz;        // brick shape (64 probes)
+    int nbx, nby, nbz;     // bricks per axis
+    int n_bricks, n_waves; // n_waves = n_bricks * rays per probe
+    int persistent;
+    int chunk;             // waves per XCD queue (persistent)
+};
+
+// One wavefront = one ray direction j over one brick of probes.
+template <bool COUNT, int W>
+__device__ __forceinline__ void trace_wave(const VolumeParams &vp, const SceneView &sv, const NodeSrc &src,
+                                           const FrameParams &fp, const float4 *dirs, float4 *rays, int32_t *hits,
+                                           const TraceGrid &g, int w, Stack<W> stk, Counts &cnt, uint32_t &shadow) {
     const int lane = threadIdx.x & 63;
-    const int n_bricks = n_waves / vp.n;
-    const int j = w / n_bricks, brick = w - j * n_bricks;
-    const int bxi = brick % bricks_x, byi = (brick / bricks_x) % bricks_y, bzi = brick / (bricks_x * bricks_y);
-    const int x = bxi * 4 + (lane & 3), y = byi * 4 + ((lane >> 2) & 3), z = bzi * 4 + (lane >> 4);
+    const int j = w / g.n_bricks, brick = w - j * g.n_bricks;
+    const int bxi = brick % g.nbx, byi = (brick / g.nbx) % g.nby, bzi = brick / (g.nbx * g.nby);
+    const int x = bxi * g.bx + lane % g.bx;
+    const int y = byi * g.by + (lane / g.bx) % g.by;
+    const int z = bzi * g.bz + lane / (g.bx * g.by);
+    if (x < vp.nx && y < vp.ny && z < vp.nz)
+        trace_shade_one<COUNT, W>(vp, sv, src, fp, dirs, rays, hits, x, y, z, j, stk, cnt, shadow);
+}
+
+template <bool COUNT, int W, int TOP>
+__global__ __launch_bounds__(W) void k_trace(VolumeParams vp, SceneView sv, FrameParams fp, const float4 *dirs,
+                                             float4 *rays, int32_t *hits, unsigned long long *counts, TraceGrid g,
+                                             int *queue) {
+    __shared__ int stk[kStack * W];
+    NodeSrc src = global_nodes(sv.stat);
+    if (TOP > 0) {
+        const int nt = min(TOP, sv.stat.n_nodes);
+        const uint4 *gn = reinterpret_cast<const uint4 *>(sv.stat.nodes);
+        for (int i = threadIdx.x; i < nt * 4; i += W) pv_top_nodes[i] = gn[i];
+        __syncthreads();
+        src.top = nt;
+    }
+    Stack<W> st{stk + threadIdx.x};
     Counts cnt = {0, 0};
     uint32_t shadow = 0;
-    if (x < vp.nx && y < vp.ny && z < vp.nz)
-        trace_shade_one<COUNT, kTraceBlock>(vp, sv, fp, dirs, rays, hits, x, y, z, j,
-                                            Stack<kTraceBlock>{stk + threadIdx.x}, cnt, shadow);
+    if (!g.persistent) {
+        const int w = xcd_logical_block() * (W / 64) + (threadIdx.x >> 6);
+        if (w < g.n_waves) trace_wave<COUNT, W>(vp, sv, src, fp, dirs, rays, hits, g, w, st, cnt, shadow);
+    } else {
+        // each wave takes packets from its XCD's range, then from the others
+        const int home = blockIdx.x & 7;
+        for (int q = 0; q < 8; ++q) {
+            const int k = (home + q) & 7;
+            const int lo = k * g.chunk, hi = min(g.n_waves, lo + g.chunk);
+            while (lo < hi) {
+                int t = 0;
+                if ((threadIdx.x & 63) == 0) t = atomicAdd(&queue[k], 1);
+                t = __shfl(t, 0);
+                if (lo + t >= hi) break;
+                trace_wave<COUNT, W>(vp, sv, src, fp, dirs, rays, hits, g, lo + t, st, cnt, shadow);
+            }
+        }
+    }
     if (COUNT) {
         atomicAdd(&counts[0], (unsigned long long)cnt.nodes);
         atomicAdd(&counts[1], (unsigned long long)cnt.tris);
@@ -523,8 +637,9 @@ __global__ __launch_bounds__(kBatchBlock) void k_batched(const BatchVolume *vols
                 Counts cnt = {0, 0};
                 uint32_t sh = 0;
                 if (x < bv.vp.nx && y < bv.vp.ny && z < bv.vp.nz)
-                    trace_shade_one<false, kBatchBlock>(bv.vp, bv.sv, frames[v], bv.dirs, bv.rays, bv.hits, x, y, z,
-                                                        j, Stack<kBatchBlock>{sm.stk + threadIdx.x}, cnt, sh);
+                    trace_shade_one<false, kBatchBlock>(bv.vp, bv.sv, global_nodes(bv.sv.stat), frames[v], bv.dirs,
+                                                        bv.rays, bv.hits, x, y, z, j,
+                                                        Stack<kBatchBlock>{sm.stk + threadIdx.x}, cnt, sh);
             }
             __threadfence();
             __syncthreads();
@@ -800,8 +915,8 @@ __global__ void k_zero(uint32_t *p, size_t words) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_raydirs(const FrameParams &fp, int n, float4 *dirs, hipStream_t s) {
-    hipLaunchKernelGGL(k_raydirs, dim3((n + 255) / 256), dim3(256), 0, s, fp, n, dirs);
+hipError_t launch_raydirs(const FrameParams &fp, int n, float4 *dirs, int *queue, hipStream_t s) {
+    hipLaunchKernelGGL(k_raydirs, dim3((n + 255) / 256), dim3(256), 0, s, fp, n, dirs, queue);
     return hipGetLastError();
 }
 
@@ -811,26 +926,61 @@ hipError_t launch_raydirs_batched(const FrameParams *frames_dev, const int *ns_d
     return hipGetLastError();
 }
 
-static void brick_counts(const VolumeParams &vp, int &bx, int &by, int &bz) {
-    bx = (vp.nx + 3) / 4;
-    by = (vp.ny + 3) / 4;
-    bz = (vp.nz + 3) / 4;
+template <bool COUNT, int W, int TOP>
+static hipError_t launch_trace_t(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp,
+                                 const float4 *dirs, float4 *rays, int32_t *hits, unsigned long long *counts,
+                                 const TraceGrid &g, int *queue, hipStream_t s) {
+    unsigned blocks;
+    if (g.persistent) {
+        int dev = 0, cus = 256, per_cu = 1;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<COUNT, W, TOP>, W,
+                                                           (size_t)TOP * sizeof(GpuNode4));
+        const long long need = ((long long)g.n_waves * 64 + W - 1) / W;
+        blocks = (unsigned)std::max(1ll, std::min<long long>((long long)cus * std::max(per_cu, 1), need));
+    } else {
+        blocks = (unsigned)(((long long)g.n_waves * 64 + W - 1) / W);
+    }
+    const size_t smem = (size_t)TOP * sizeof(GpuNode4);
+    hipLaunchKernelGGL((k_trace<COUNT, W, TOP>), dim3(blocks), dim3(W), smem, s, vp, sv, fp, dirs, rays, hits, counts,
+                       g, queue);
+    return hipGetLastError();
+}
+
+template <bool COUNT>
+static hipError_t launch_trace_c(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp,
+                                 const float4 *dirs, float4 *rays, int32_t *hits, unsigned long long *counts,
+                                 const TraceConfig &tc, const TraceGrid &g, int *queue, hipStream_t s) {
+#define PV_TRACE_CASE(Wv, Tv)                                                                                   \
+    if (tc.block == Wv && tc.top_nodes == Tv)                                                                  \
+        return launch_trace_t<COUNT, Wv, Tv>(vp, sv, fp, dirs, rays, hits, counts, g, queue, s);
+    PV_TRACE_CASE(128, 0)
+    PV_TRACE_CASE(128, 21)
+    PV_TRACE_CASE(128, 85)
+    PV_TRACE_CASE(256, 0)
+    PV_TRACE_CASE(256, 21)
+    PV_TRACE_CASE(256, 85)
+#undef PV_TRACE_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_trace(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp, const float4 *dirs,
-                        float4 *rays, int32_t *hits, unsigned long long *counts, hipStream_t s) {
-    int bx, by, bz;
-    brick_counts(vp, bx, by, bz);
-    const long long n_waves = (long long)bx * by * bz * vp.n;
-    const int waves_per_block = kTraceBlock / 64;
-    const long long blocks = (n_waves + waves_per_block - 1) / waves_per_block;
-    if (counts)
-        hipLaunchKernelGGL(k_trace<true>, dim3((unsigned)blocks), dim3(kTraceBlock), 0, s, vp, sv, fp, dirs, rays,
-                           hits, counts, bx, by, (int)n_waves);
-    else
-        hipLaunchKernelGGL(k_trace<false>, dim3((unsigned)blocks), dim3(kTraceBlock), 0, s, vp, sv, fp, dirs, rays,
-                           hits, counts, bx, by, (int)n_waves);
-    return hipGetLastError();
+                        float4 *rays, int32_t *hits, unsigned long long *counts, const TraceConfig &tc, int *queue,
+                        hipStream_t s) {
+    TraceGrid g;
+    g.bx = tc.bx;
+    g.by = tc.by;
+    g.bz = tc.bz;
+    g.nbx = (vp.nx + tc.bx - 1) / tc.bx;
+    g.nby = (vp.ny + tc.by - 1) / tc.by;
+    g.nbz = (vp.nz + tc.bz - 1) / tc.bz;
+    g.n_bricks = g.nbx * g.nby * g.nbz;
+    g.n_waves = g.n_bricks * vp.n;
+    g.persistent = tc.persistent && queue != nullptr;
+    g.chunk = (g.n_waves + 7) / 8;
+    if (counts) return launch_trace_c<true>(vp, sv, fp, dirs, rays, hits, counts, tc, g, queue, s);
+    return launch_trace_c<false>(vp, sv, fp, dirs, rays, hits, counts, tc, g, queue, s);
 }
 
 hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4 *rays, void *irr, void *vis,

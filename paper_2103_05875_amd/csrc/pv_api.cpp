@@ -34,22 +34,26 @@ extern "C" const char *pv_version(void) { return "probestream 1.0 gfx950"; }
 // ---------------------------------------------------------------------------
 // handles
 // ---------------------------------------------------------------------------
-struct pv_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    // batched launch scratch
+// Device and pinned host buffers of one batched launch. Launches in flight
+// on different streams use different slots; a slot is reused only after
+// its previous launch has finished (its event).
+struct BatchSlot {
     BatchVolume *batch_dev = nullptr;
     FrameParams *frames_dev = nullptr;
     int *ns_dev = nullptr;
     float4 **dirs_ptrs_dev = nullptr;
     int *counters_dev = nullptr;  // [0] queue, [1] status, [2..] done per volume
-    int batch_cap = 0;
-    // pinned staging ring for the batched descriptors
-    static constexpr int kRing = 4;
-    void *stage_host[kRing] = {};
-    size_t stage_bytes = 0;
-    hipEvent_t stage_ev[kRing] = {};
-    int stage_next = 0;
+    int cap = 0;
+    void *stage_host = nullptr;
+    hipEvent_t done = nullptr;
+};
+
+struct pv_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    static constexpr int kRing = 8;
+    BatchSlot slots[kRing];
+    int slot_next = 0;
     unsigned long long *counts_dev = nullptr;
     // optional per-stage event timing
     struct Timed {
@@ -93,7 +97,7 @@ struct pv_scene {
     std::vector<pv_point_light> lights;
     // dynamic triangles: ring of device BVH slots fed from pinned staging
     static constexpr int kRing = 4;
-    GpuNode *dyn_nodes[kRing] = {};
+    GpuNode4 *dyn_nodes[kRing] = {};
     GpuTri *dyn_tris[kRing] = {};
     void *dyn_stage[kRing] = {};
     hipEvent_t dyn_use[kRing] = {};
@@ -111,8 +115,10 @@ struct pv_volume {
     void *irr = nullptr, *vis = nullptr;
     float4 *rays = nullptr, *dirs = nullptr;
     int32_t *hits = nullptr;
+    int *queue = nullptr;  // 8 work-queue counters of the persistent trace
     int64_t frame = 0;
     pv_scene *scene = nullptr;
+    TraceConfig tc;
 };
 
 struct pv_client {
@@ -175,7 +181,7 @@ extern "C" pv_status pv_ctx_create(int hip_device, pv_ctx **out) {
         delete c;
         return fail(PV_ERR_DEVICE, std::string("stream: ") + hipGetErrorString(e));
     }
-    for (int i = 0; i < pv_ctx::kRing; ++i) HIP_TRY(hipEventCreateWithFlags(&c->stage_ev[i], hipEventDisableTiming));
+    for (int i = 0; i < pv_ctx::kRing; ++i) HIP_TRY(hipEventCreateWithFlags(&c->slots[i].done, hipEventDisableTiming));
     *out = c;
     return PV_OK;
 }
@@ -184,15 +190,17 @@ extern "C" pv_status pv_ctx_destroy(pv_ctx *c) {
     if (!c) return PV_OK;
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
-    hipFree(c->batch_dev);
-    hipFree(c->frames_dev);
-    hipFree(c->ns_dev);
-    hipFree(c->dirs_ptrs_dev);
-    hipFree(c->counters_dev);
+    hipDeviceSynchronize();
     hipFree(c->counts_dev);
     for (int i = 0; i < pv_ctx::kRing; ++i) {
-        if (c->stage_host[i]) hipHostFree(c->stage_host[i]);
-        if (c->stage_ev[i]) hipEventDestroy(c->stage_ev[i]);
+        BatchSlot &b = c->slots[i];
+        hipFree(b.batch_dev);
+        hipFree(b.frames_dev);
+        hipFree(b.ns_dev);
+        hipFree(b.dirs_ptrs_dev);
+        hipFree(b.counters_dev);
+        if (b.stage_host) hipHostFree(b.stage_host);
+        if (b.done) hipEventDestroy(b.done);
     }
     for (auto &t : c->pending) {
         hipEventDestroy(t.a);
@@ -239,12 +247,12 @@ static bool finite_all(const float *p, size_t n) {
     return true;
 }
 
-static pv_status upload_bvh(const HostBvh &hb, DeviceBvh &db, hipStream_t s) {
+static pv_status upload_bvh(const HostBvh4 &hb, DeviceBvh &db, hipStream_t s) {
     db.n_nodes = (int)hb.nodes.size();
     db.n_tris = (int)hb.tris.size();
-    PV_TRY(dev_alloc(&db.nodes, hb.nodes.size() * sizeof(GpuNode), "BVH nodes"));
+    PV_TRY(dev_alloc(&db.nodes, hb.nodes.size() * sizeof(GpuNode4), "BVH nodes"));
     PV_TRY(dev_alloc(&db.tris, hb.tris.size() * sizeof(GpuTri), "BVH triangles"));
-    if (db.n_nodes) HIP_TRY(hipMemcpyAsync(db.nodes, hb.nodes.data(), hb.nodes.size() * sizeof(GpuNode), hipMemcpyHostToDevice, s));
+    if (db.n_nodes) HIP_TRY(hipMemcpyAsync(db.nodes, hb.nodes.data(), hb.nodes.size() * sizeof(GpuNode4), hipMemcpyHostToDevice, s));
     if (db.n_tris) HIP_TRY(hipMemcpyAsync(db.tris, hb.tris.data(), hb.tris.size() * sizeof(GpuTri), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     return PV_OK;
@@ -314,9 +322,9 @@ extern "C" pv_status pv_scene_create(pv_ctx *ctx, const pv_scene_desc *d, pv_sce
                                      (hi[2] - lo[2]) * (hi[2] - lo[2]))
                          : 1.0;
     s->eps = (float)(1e-4 * diag);
-    HostBvh hb;
+    HostBvh4 hb;
     std::string err;
-    if (!build_bvh(tri9.data(), s->n_static, 0, hb, err)) {
+    if (!build_bvh4(tri9.data(), s->n_static, 0, hb, err)) {
         destroy_scene(s);
         return fail(PV_ERR_ARG, err);
     }
@@ -342,11 +350,11 @@ extern "C" pv_status pv_scene_create(pv_ctx *ctx, const pv_scene_desc *d, pv_sce
         return fail(PV_ERR_DEVICE, std::string("materials upload: ") + hipGetErrorString(e));
     }
     if (s->n_dyn > 0) {
-        s->dyn_node_cap = (size_t)s->n_dyn;  // a binary tree over n leaves has < n inner nodes
+        s->dyn_node_cap = (size_t)s->n_dyn;  // a tree over n leaves has fewer than n inner nodes
         for (int i = 0; i < pv_scene::kRing; ++i) {
-            st = dev_alloc(&s->dyn_nodes[i], s->dyn_node_cap * sizeof(GpuNode), "dynamic BVH nodes");
+            st = dev_alloc(&s->dyn_nodes[i], s->dyn_node_cap * sizeof(GpuNode4), "dynamic BVH nodes");
             if (st == PV_OK) st = dev_alloc(&s->dyn_tris[i], (size_t)s->n_dyn * sizeof(GpuTri), "dynamic triangles");
-            if (st == PV_OK && hipHostMalloc(&s->dyn_stage[i], s->dyn_node_cap * sizeof(GpuNode) + (size_t)s->n_dyn * sizeof(GpuTri)) != hipSuccess)
+            if (st == PV_OK && hipHostMalloc(&s->dyn_stage[i], s->dyn_node_cap * sizeof(GpuNode4) + (size_t)s->n_dyn * sizeof(GpuTri)) != hipSuccess)
                 st = fail(PV_ERR_OOM, "pinned staging for dynamic triangles");
             if (st == PV_OK && hipEventCreateWithFlags(&s->dyn_use[i], hipEventDisableTiming) != hipSuccess)
                 st = fail(PV_ERR_DEVICE, "event");
@@ -369,19 +377,19 @@ extern "C" pv_status pv_scene_create(pv_ctx *ctx, const pv_scene_desc *d, pv_sce
 
 static pv_status set_dynamic_impl(pv_scene *s, const float *pos, hipStream_t st) {
     if (!finite_all(pos, 9ull * s->n_dyn)) return fail(PV_ERR_ARG, "dynamic positions must be finite");
-    HostBvh hb;
+    HostBvh4 hb;
     std::string err;
-    if (!build_bvh(pos, s->n_dyn, s->n_static, hb, err)) return fail(PV_ERR_ARG, err);
+    if (!build_bvh4(pos, s->n_dyn, s->n_static, hb, err)) return fail(PV_ERR_ARG, err);
     if (hb.nodes.size() > s->dyn_node_cap) return fail(PV_ERR_STATE, "dynamic BVH larger than its slot");
     const int k = (s->dyn_slot + 1) % pv_scene::kRing;
     // the slot may still be read by earlier work: wait for its last use
     if (s->dyn_used[k]) HIP_TRY(hipEventSynchronize(s->dyn_use[k]));
     char *stage = (char *)s->dyn_stage[k];
-    const size_t nb = hb.nodes.size() * sizeof(GpuNode), tb = hb.tris.size() * sizeof(GpuTri);
+    const size_t nb = hb.nodes.size() * sizeof(GpuNode4), tb = hb.tris.size() * sizeof(GpuTri);
     std::memcpy(stage, hb.nodes.data(), nb);
-    std::memcpy(stage + s->dyn_node_cap * sizeof(GpuNode), hb.tris.data(), tb);
+    std::memcpy(stage + s->dyn_node_cap * sizeof(GpuNode4), hb.tris.data(), tb);
     HIP_TRY(hipMemcpyAsync(s->dyn_nodes[k], stage, nb, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(s->dyn_tris[k], stage + s->dyn_node_cap * sizeof(GpuNode), tb, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->dyn_tris[k], stage + s->dyn_node_cap * sizeof(GpuNode4), tb, hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(s->dyn_use[k], st));
     s->dyn_used[k] = true;
     s->dyn_nodes_n[k] = (int)hb.nodes.size();
@@ -448,7 +456,7 @@ static pv_status validate_desc(const pv_volume_desc *d) {
 static uint64_t volume_bytes(const pv_volume_desc *d) {
     const int P = d->nx * d->ny * d->nz, n = d->rays_per_probe;
     const size_t elem = d->format == PV_MAP_FP16 ? 2 : 4;
-    uint64_t b = irr_bytes(P, elem) + vis_bytes(P, elem) + (uint64_t)P * n * 16 + (uint64_t)n * 16;
+    uint64_t b = irr_bytes(P, elem) + vis_bytes(P, elem) + (uint64_t)P * n * 16 + (uint64_t)n * 16 + 32;
     if (d->flags & PV_KEEP_HITS) b += (uint64_t)P * n * 4;
     return b;
 }
@@ -466,6 +474,7 @@ static void free_volume(pv_volume *v) {
     hipFree(v->rays);
     hipFree(v->dirs);
     hipFree(v->hits);
+    hipFree(v->queue);
     delete v;
 }
 
@@ -484,6 +493,7 @@ extern "C" pv_status pv_create_volume(pv_ctx *ctx, const pv_volume_desc *d, pv_v
     if (st == PV_OK) st = dev_alloc(&v->rays, (size_t)v->P * v->n * 16, "ray buffer");
     if (st == PV_OK) st = dev_alloc(&v->dirs, (size_t)v->n * 16, "directions");
     if (st == PV_OK && (d->flags & PV_KEEP_HITS)) st = dev_alloc(&v->hits, (size_t)v->P * v->n * 4, "hit ids");
+    if (st == PV_OK) st = dev_alloc(&v->queue, 8 * sizeof(int), "work queues");
     if (st == PV_OK && launch_zero(v->irr, irr_bytes(v->P, v->elem), ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "zero fill");
     if (st == PV_OK && launch_zero(v->vis, vis_bytes(v->P, v->elem), ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "zero fill");
     if (st == PV_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "sync after zero fill");
@@ -573,8 +583,9 @@ extern "C" pv_status pv_update_probes(pv_volume *v, const pv_frame *f, void *str
     const SceneView sv = scene_view(v->scene);
     const int fp16 = v->desc.format == PV_MAP_FP16;
     const float h = effective_h(v);
-    HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s, [&] { return launch_raydirs(fp, v->n, v->dirs, s); }));
-    HIP_TRY(timed(c, PV_STAGE_TRACE, s, [&] { return launch_trace(vp, sv, fp, v->dirs, v->rays, v->hits, nullptr, s); }));
+    HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s, [&] { return launch_raydirs(fp, v->n, v->dirs, v->queue, s); }));
+    HIP_TRY(timed(c, PV_STAGE_TRACE, s,
+                  [&] { return launch_trace(vp, sv, fp, v->dirs, v->rays, v->hits, nullptr, v->tc, v->queue, s); }));
     HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend(vp, v->dirs, v->rays, v->irr, v->vis, fp16, h, s); }));
     PV_TRY(note_scene_use(v->scene, s));
     v->frame++;
@@ -592,8 +603,8 @@ extern "C" pv_status pv_trace_counts(pv_volume *v, const pv_frame *f, uint64_t c
     hipStream_t s = c->stream;
     HIP_TRY(launch_zero(c->counts_dev, 4 * sizeof(unsigned long long), s));
     const VolumeParams vp = volume_params(v);
-    HIP_TRY(launch_raydirs(fp, v->n, v->dirs, s));
-    HIP_TRY(launch_trace(vp, scene_view(v->scene), fp, v->dirs, v->rays, v->hits, c->counts_dev, s));
+    HIP_TRY(launch_raydirs(fp, v->n, v->dirs, v->queue, s));
+    HIP_TRY(launch_trace(vp, scene_view(v->scene), fp, v->dirs, v->rays, v->hits, c->counts_dev, v->tc, v->queue, s));
     PV_TRY(note_scene_use(v->scene, s));
     unsigned long long host[4];
     HIP_TRY(hipMemcpyAsync(host, c->counts_dev, sizeof(host), hipMemcpyDeviceToHost, s));
@@ -609,10 +620,37 @@ extern "C" pv_status pv_blend_rays(pv_volume *v, const pv_frame *f, const void *
     HIP_TRY(hipSetDevice(v->ctx->device));
     hipStream_t s = pick(v->ctx, stream);
     const VolumeParams vp = volume_params(v);
-    HIP_TRY(launch_raydirs(fp, v->n, v->dirs, s));
+    HIP_TRY(launch_raydirs(fp, v->n, v->dirs, nullptr, s));
     HIP_TRY(launch_blend(vp, v->dirs, (const float4 *)rays_dev, v->irr, v->vis, v->desc.format == PV_MAP_FP16,
                          effective_h(v), s));
     v->frame++;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_volume_set_trace_config(pv_volume *v, const pv_trace_config *c) {
+    if (!v || !c) return fail(PV_ERR_ARG, "NULL argument");
+    if (c->brick[0] < 1 || c->brick[1] < 1 || c->brick[2] < 1 || c->brick[0] * c->brick[1] * c->brick[2] != 64)
+        return fail(PV_ERR_ARG, "brick must hold 64 probes");
+    if (c->persistent != 0 && c->persistent != 1) return fail(PV_ERR_ARG, "persistent must be 0 or 1");
+    if (c->top_nodes != 0 && c->top_nodes != 21 && c->top_nodes != 85) return fail(PV_ERR_ARG, "top_nodes must be 0, 21 or 85");
+    if (c->block_threads != 128 && c->block_threads != 256) return fail(PV_ERR_ARG, "block_threads must be 128 or 256");
+    v->tc.bx = c->brick[0];
+    v->tc.by = c->brick[1];
+    v->tc.bz = c->brick[2];
+    v->tc.persistent = c->persistent;
+    v->tc.top_nodes = c->top_nodes;
+    v->tc.block = c->block_threads;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_volume_get_trace_config(pv_volume *v, pv_trace_config *c) {
+    if (!v || !c) return fail(PV_ERR_ARG, "NULL argument");
+    c->brick[0] = v->tc.bx;
+    c->brick[1] = v->tc.by;
+    c->brick[2] = v->tc.bz;
+    c->persistent = v->tc.persistent;
+    c->top_nodes = v->tc.top_nodes;
+    c->block_threads = v->tc.block;
     return PV_OK;
 }
 
@@ -655,38 +693,31 @@ extern "C" pv_status pv_read_maps(pv_volume *v, void *irr, void *vis, int64_t *f
 // ---------------------------------------------------------------------------
 // batched update
 // ---------------------------------------------------------------------------
-static pv_status ensure_batch(pv_ctx *c, int n) {
-    if (n <= c->batch_cap) return PV_OK;
-    hipFree(c->batch_dev);
-    hipFree(c->frames_dev);
-    hipFree(c->ns_dev);
-    hipFree(c->dirs_ptrs_dev);
-    hipFree(c->counters_dev);
-    c->batch_dev = nullptr;
-    c->frames_dev = nullptr;
-    c->ns_dev = nullptr;
-    c->dirs_ptrs_dev = nullptr;
-    c->counters_dev = nullptr;
-    c->batch_cap = 0;
-    PV_TRY(dev_alloc(&c->batch_dev, sizeof(BatchVolume) * n, "batch descriptors"));
-    PV_TRY(dev_alloc(&c->frames_dev, sizeof(FrameParams) * n, "batch frames"));
-    PV_TRY(dev_alloc(&c->ns_dev, sizeof(int) * n, "batch ray counts"));
-    PV_TRY(dev_alloc(&c->dirs_ptrs_dev, sizeof(float4 *) * n, "batch direction pointers"));
-    PV_TRY(dev_alloc(&c->counters_dev, sizeof(int) * (2 + n), "batch counters"));
-    // a fresh status word
-    HIP_TRY(launch_zero(c->counters_dev, sizeof(int) * (2 + n), c->stream));
+static pv_status ensure_slot(pv_ctx *c, BatchSlot &b, int n) {
+    if (n <= b.cap) return PV_OK;
+    hipFree(b.batch_dev);
+    hipFree(b.frames_dev);
+    hipFree(b.ns_dev);
+    hipFree(b.dirs_ptrs_dev);
+    hipFree(b.counters_dev);
+    if (b.stage_host) hipHostFree(b.stage_host);
+    b.batch_dev = nullptr;
+    b.frames_dev = nullptr;
+    b.ns_dev = nullptr;
+    b.dirs_ptrs_dev = nullptr;
+    b.counters_dev = nullptr;
+    b.stage_host = nullptr;
+    b.cap = 0;
+    PV_TRY(dev_alloc(&b.batch_dev, sizeof(BatchVolume) * n, "batch descriptors"));
+    PV_TRY(dev_alloc(&b.frames_dev, sizeof(FrameParams) * n, "batch frames"));
+    PV_TRY(dev_alloc(&b.ns_dev, sizeof(int) * n, "batch ray counts"));
+    PV_TRY(dev_alloc(&b.dirs_ptrs_dev, sizeof(float4 *) * n, "batch direction pointers"));
+    PV_TRY(dev_alloc(&b.counters_dev, sizeof(int) * (2 + n), "batch counters"));
+    HIP_TRY(launch_zero(b.counters_dev, sizeof(int) * (2 + n), c->stream));  // fresh status word
     HIP_TRY(hipStreamSynchronize(c->stream));
     const size_t bytes = (sizeof(BatchVolume) + sizeof(FrameParams) + sizeof(int) + sizeof(float4 *)) * n + 256;
-    for (int i = 0; i < pv_ctx::kRing; ++i) {
-        if (c->stage_host[i]) {
-            hipEventSynchronize(c->stage_ev[i]);
-            hipHostFree(c->stage_host[i]);
-        }
-        c->stage_host[i] = nullptr;
-        HIP_TRY(hipHostMalloc(&c->stage_host[i], bytes));
-    }
-    c->stage_bytes = bytes;
-    c->batch_cap = n;
+    HIP_TRY(hipHostMalloc(&b.stage_host, bytes));
+    b.cap = n;
     return PV_OK;
 }
 
@@ -703,7 +734,10 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
     }
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t s = pick(c, stream);
-    PV_TRY(ensure_batch(c, n));
+    BatchSlot &slot = c->slots[c->slot_next];
+    c->slot_next = (c->slot_next + 1) % pv_ctx::kRing;
+    HIP_TRY(hipEventSynchronize(slot.done));  // the slot's previous launch has finished
+    PV_TRY(ensure_slot(c, slot, n));
     std::vector<BatchVolume> bv(n);
     std::vector<FrameParams> fps(n);
     std::vector<int> ns(n);
@@ -736,11 +770,8 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
         ns[i] = v->n;
         dps[i] = v->dirs;
     }
-    // stage descriptors through pinned memory (ring; wait for the slot's last copy)
-    const int k = c->stage_next;
-    c->stage_next = (k + 1) % pv_ctx::kRing;
-    HIP_TRY(hipEventSynchronize(c->stage_ev[k]));
-    char *h = (char *)c->stage_host[k];
+    // stage descriptors through the slot's pinned memory
+    char *h = (char *)slot.stage_host;
     size_t off = 0;
     auto put = [&](const void *src, size_t bytes) {
         std::memcpy(h + off, src, bytes);
@@ -752,19 +783,20 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
     const size_t o_f = put(fps.data(), sizeof(FrameParams) * n);
     const size_t o_n = put(ns.data(), sizeof(int) * n);
     const size_t o_d = put(dps.data(), sizeof(float4 *) * n);
-    HIP_TRY(hipMemcpyAsync(c->batch_dev, h + o_b, sizeof(BatchVolume) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(c->frames_dev, h + o_f, sizeof(FrameParams) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(c->ns_dev, h + o_n, sizeof(int) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(c->dirs_ptrs_dev, h + o_d, sizeof(float4 *) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipEventRecord(c->stage_ev[k], s));
+    HIP_TRY(hipMemcpyAsync(slot.batch_dev, h + o_b, sizeof(BatchVolume) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(slot.frames_dev, h + o_f, sizeof(FrameParams) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(slot.ns_dev, h + o_n, sizeof(int) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(slot.dirs_ptrs_dev, h + o_d, sizeof(float4 *) * n, hipMemcpyHostToDevice, s));
     // queue counter and per-volume done counters start at zero (status word kept)
-    HIP_TRY(launch_zero(c->counters_dev, sizeof(int), s));
-    HIP_TRY(launch_zero(c->counters_dev + 2, sizeof(int) * n, s));
-    HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s, [&] { return launch_raydirs_batched(c->frames_dev, c->ns_dev, c->dirs_ptrs_dev, n, s); }));
+    HIP_TRY(launch_zero(slot.counters_dev, sizeof(int), s));
+    HIP_TRY(launch_zero(slot.counters_dev + 2, sizeof(int) * n, s));
+    HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s,
+                  [&] { return launch_raydirs_batched(slot.frames_dev, slot.ns_dev, slot.dirs_ptrs_dev, n, s); }));
     HIP_TRY(timed(c, PV_STAGE_BATCHED, s, [&] {
-        return launch_batched(c->batch_dev, n, waves, blend, c->frames_dev, c->counters_dev, c->counters_dev + 2,
-                              c->counters_dev + 1, s);
+        return launch_batched(slot.batch_dev, n, waves, blend, slot.frames_dev, slot.counters_dev,
+                              slot.counters_dev + 2, slot.counters_dev + 1, s);
     }));
+    HIP_TRY(hipEventRecord(slot.done, s));
     for (int i = 0; i < n; ++i) {
         PV_TRY(note_scene_use(vols[i]->scene, s));
         vols[i]->frame++;
@@ -932,11 +964,13 @@ extern "C" pv_status pv_ctx_check(pv_ctx *c, int *status) {
     // status word of the batched work queue (1 = a bounded wait expired)
     if (!c || !status) return fail(PV_ERR_ARG, "NULL argument");
     *status = 0;
-    if (!c->counters_dev) return PV_OK;
     HIP_TRY(hipSetDevice(c->device));
     HIP_TRY(hipDeviceSynchronize());
-    int st = 0;
-    HIP_TRY(hipMemcpy(&st, c->counters_dev + 1, sizeof(int), hipMemcpyDeviceToHost));
-    *status = st;
+    for (int i = 0; i < pv_ctx::kRing; ++i) {
+        if (!c->slots[i].counters_dev) continue;
+        int st = 0;
+        HIP_TRY(hipMemcpy(&st, c->slots[i].counters_dev + 1, sizeof(int), hipMemcpyDeviceToHost));
+        *status |= st;
+    }
     return PV_OK;
 }

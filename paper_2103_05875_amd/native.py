@@ -31,7 +31,7 @@ EXPORTED_SYMBOLS = [
     "pv_client_create", "pv_client_destroy", "pv_client_reset", "pv_client_footprint",
     "pv_pack_delta", "pv_packet_device", "pv_packet_download", "pv_get_masks", "pv_sync",
     "pv_ctx_check", "pv_trace_counts", "pv_ctx_set_timing", "pv_ctx_stage_times",
-    "pv_client_read_state", "pv_client_set_state",
+    "pv_client_read_state", "pv_client_set_state", "pv_volume_set_trace_config", "pv_volume_get_trace_config",
 ]
 
 STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched"]
@@ -62,6 +62,11 @@ class SceneDesc(ctypes.Structure):
                 ("albedo", ctypes.c_void_p), ("emission", ctypes.c_void_p),
                 ("n_dynamic_triangles", ctypes.c_int), ("n_lights", ctypes.c_int),
                 ("lights", ctypes.c_void_p)]
+
+
+class TraceConfig(ctypes.Structure):
+    _fields_ = [("brick", ctypes.c_int * 3), ("persistent", ctypes.c_int), ("top_nodes", ctypes.c_int),
+                ("block_threads", ctypes.c_int)]
 
 
 class Frame(ctypes.Structure):
@@ -124,6 +129,8 @@ def lib():
         "pv_trace_counts": ([vp, P(Frame), P(u64)], i32),
         "pv_ctx_set_timing": ([vp, i32], i32),
         "pv_client_read_state": ([vp, vp, vp, P(u32)], i32),
+        "pv_volume_set_trace_config": ([vp, P(TraceConfig)], i32),
+        "pv_volume_get_trace_config": ([vp, P(TraceConfig)], i32),
         "pv_client_set_state": ([vp, vp, vp, u32], i32),
         "pv_ctx_stage_times": ([vp, P(ctypes.c_double), P(u64)], i32),
     }
@@ -345,6 +352,20 @@ class Volume:
         f, keep = make_frame(rotation, lights)
         _check(lib().pv_update_probes(self.h, ctypes.byref(f), _stream_handle(stream)))
         del keep
+
+    def set_trace_config(self, brick=(4, 4, 4), persistent=False, top_nodes=0, block_threads=128):
+        c = TraceConfig()
+        c.brick[:] = [int(b) for b in brick]
+        c.persistent = 1 if persistent else 0
+        c.top_nodes = int(top_nodes)
+        c.block_threads = int(block_threads)
+        _check(lib().pv_volume_set_trace_config(self.h, ctypes.byref(c)))
+
+    def get_trace_config(self) -> dict:
+        c = TraceConfig()
+        _check(lib().pv_volume_get_trace_config(self.h, ctypes.byref(c)))
+        return {"brick": tuple(c.brick), "persistent": bool(c.persistent), "top_nodes": c.top_nodes,
+                "block_threads": c.block_threads}
 
     def trace_counts(self, rotation, lights=None):
         f, keep = make_frame(rotation, lights)

@@ -169,6 +169,7 @@ class Server:
                         break
                     if self._make_resident(s, now):
                         batch.append(s.queue.popleft())
+                        s.busy = True          # reserved: not evictable while the batch forms
                 if batch:
                     self._launch(k, batch, now)
                     progressed = True

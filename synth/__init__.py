@@ -354,6 +354,35 @@ def config(name: str) -> VolumeConfig:
     return CONFIGS[name]()
 
 
+def served_clients(n_clients: int = 64, seed: int = 30) -> List[VolumeConfig]:
+    """The served workload's clients: probes log-uniform in [512, 16384]
+    (multiple of 256, grid 16 x P/256 x 16) and rays/probe uniform in
+    {64, 128, 256}, over one shared 64 x 64 scene."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_clients):
+        p = int(round(math.exp(rng.uniform(math.log(512), math.log(16384))) / 256)) * 256
+        p = min(max(p, 512), 16384)
+        n = int(rng.choice([64, 128, 256]))
+        ny = p // 256
+        out.append(VolumeConfig(16, ny, 16, (2.0, 0.25, 2.0), (4.0, 14.0 / max(ny - 1, 1), 4.0), n,
+                                max_distance=6.0, fp16=True, sky=(0.10, 0.15, 0.25)))
+    return out
+
+
+def poisson_arrivals(rate_hz: float, duration_s: float, n_clients: int, seed: int = 30):
+    """Arrival times (s) and uniformly chosen client ids of a Poisson
+    request stream."""
+    rng = np.random.default_rng([seed, 1])
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t >= duration_s:
+            break
+        out.append((t, int(rng.integers(0, n_clients))))
+    return out
+
+
 def batched_volumes(n_volumes: int = 32, seed: int = 20) -> List[dict]:
     """The batched workload: per volume a probe count log-uniform in
     [256, 8192] (multiple of 256, grid 16 x P/256 x 16), rays/probe uniform in
