@@ -51,6 +51,9 @@ def parse():
                     help="extra workloads reported in the same line (comma list, or 'none')")
     ap.add_argument("--served-seconds", type=float, default=1.0)
     ap.add_argument("--encode-frames", type=int, default=120)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default trace launch shape")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB device copy (reference kernel for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -267,10 +270,28 @@ def main():
           f"{scene.n_triangles} triangles; warmup {W}, steps {K}", file=sys.stderr, flush=True)
     ctx = ps.Context(0)
     sc = ps.Scene.from_synth(ctx, scene)
+    tuned = None
+    if not args.no_autotune:
+        from paper_2103_05875_amd import autotune
+        scratch = ps.Volume(ctx, cfg)
+        scratch.set_scene(sc)
+        tuned = autotune.tune(scratch, *frames[0], n_triangles=scene.n_triangles, cache=None)
+        scratch.close()
+        print(f"bench: autotuned trace launch {tuned['config']} ({tuned['ms']:.3f} ms)", file=sys.stderr, flush=True)
     vol = ps.Volume(ctx, cfg)
     vol.set_scene(sc)
+    if tuned:
+        c = tuned["config"]
+        vol.set_trace_config(c["brick"], c["persistent"], c["top_nodes"], c["block_threads"], c["split_shadows"])
     cl = ps.Client(vol, client_id=0)
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(i):
         R, l = frames[i]
@@ -316,7 +337,8 @@ def main():
         tri_tests += c["tri_tests"]
         shadow += c["shadow_rays"]
     flop_per_launch = (node_visits * FLOP_PER_NODE_VISIT + tri_tests * FLOP_PER_TRI_TEST) / K
-    trace_s = stage_ms["trace"] / 1e3
+    # the traversal is k_trace, plus k_shadow and k_shade when shadow rays are split out
+    trace_s = (stage_ms["trace"] + stage_ms["shadow"] + stage_ms["shade"]) / 1e3
     achieved = flop_per_launch / trace_s if trace_s > 0 else 0.0
 
     # HBM figures of the blend and pack kernels (algorithmic bytes)
@@ -345,6 +367,9 @@ def main():
                                "moving light; step = full update + delta pack for one client (tau = 0)",
                    "probes": P, "rays_per_probe": n, "triangles": scene.n_triangles},
         "probes_per_s": P * 1e3 / ms_per_step,
+        "trace_config": vol.get_trace_config(),
+        "autotune": None if tuned is None else {"tried": tuned["tried"], "best_ms": tuned["ms"],
+                                                 "top5": tuned.get("ranking")},
         "stage_ms": stage_ms,
         "roofline": {"bound": "alu", "kernel": "k_trace", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,

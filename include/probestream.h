@@ -25,9 +25,9 @@
  *   - Every call returns a pv_status; outputs are written only on PV_OK and
  *     pv_last_error() (thread-local) describes the last failure.
  *   - Work is enqueued asynchronously on the given HIP stream (a
- *     hipStream_t passed as void*; NULL means the context's own stream).
- *     Device faults surface as PV_ERR_DEVICE at the next pv_sync or
- *     blocking call.
+ *     hipStream_t passed as void*; NULL is HIP's default stream, as in HIP
+ *     itself). Device faults surface as PV_ERR_DEVICE at the next pv_sync
+ *     or blocking call.
  *   - The library owns every handle and all device memory (maps, client
  *     references, BVHs, ray buffers, packets). Host arrays passed in are
  *     copied before the call returns and never retained. Device pointers
@@ -249,14 +249,18 @@ pv_status pv_ctx_check(pv_ctx *ctx, int *status);
  * identical results): probes per wavefront packet as a brick
  * brick[0] x brick[1] x brick[2] = 64 of one ray direction, a persistent grid
  * with per-XCD work queues (1) or one wavefront per packet (0), the number of
- * top BVH nodes staged in LDS (0, 21 or 85: one, three or four levels), and
- * threads per block (128 or 256). Defaults: 4x4x4, 0, 0, 128.
+ * top BVH nodes staged in LDS (0, 21 or 85: one, three or four levels),
+ * threads per block (128 or 256), and whether shadow rays are traced inside
+ * the primary kernel (0) or appended to a compacted queue and traced by a
+ * dense second kernel, then applied by a shade kernel (1). Defaults:
+ * 4x4x4, 0, 0, 128, 0.
  */
 typedef struct {
     int brick[3];
     int persistent;
     int top_nodes;
     int block_threads;
+    int split_shadows;
 } pv_trace_config;
 
 pv_status pv_volume_set_trace_config(pv_volume *vol, const pv_trace_config *cfg);
@@ -271,7 +275,9 @@ typedef enum {
     PV_STAGE_PACK_SCAN = 4,
     PV_STAGE_PACK_COMPACT = 5,
     PV_STAGE_BATCHED = 6,
-    PV_STAGE_COUNT = 7
+    PV_STAGE_SHADOW = 7,
+    PV_STAGE_SHADE = 8,
+    PV_STAGE_COUNT = 9
 } pv_stage;
 
 /* When enabled, every kernel launch of the context is bracketed by a pair

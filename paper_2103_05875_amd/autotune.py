@@ -1,0 +1,100 @@
+"""Autotuner for the trace launch shape.
+
+Every launch shape computes bit-identical results; only speed differs. The
+tuner times each candidate (probe brick of a wavefront packet, persistent
+grid with per-XCD work queues or not, BVH nodes staged in LDS, block size)
+on the caller's own volume, scene and frame, with HIP events around the trace
+kernel (the library's stage timing), and keeps the fastest. Results are
+cached in a JSON file keyed by grid shape, rays per probe and scene size, so
+later volumes of the same shape reuse the choice without measuring.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+from typing import Dict, List, Optional
+
+BRICKS = [(4, 4, 4), (8, 8, 1), (8, 4, 2), (16, 4, 1), (2, 4, 8)]
+PERSISTENT = [False, True]
+TOP_NODES = [0, 21, 85]
+BLOCKS = [128, 256]
+SPLIT = [False, True]
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "probestream", "autotune.json")
+
+
+def candidates() -> List[dict]:
+    return [{"brick": b, "persistent": p, "top_nodes": t, "block_threads": w, "split_shadows": s}
+            for b, p, t, w, s in itertools.product(BRICKS, PERSISTENT, TOP_NODES, BLOCKS, SPLIT)]
+
+
+def _apply(volume, c):
+    volume.set_trace_config(tuple(c["brick"]), c["persistent"], c["top_nodes"], c["block_threads"],
+                            c.get("split_shadows", False))
+
+
+def key(cfg, n_triangles: int) -> str:
+    bucket = 1 << max(0, int(n_triangles).bit_length() - 1)
+    return f"{cfg.nx}x{cfg.ny}x{cfg.nz}:n{cfg.rays_per_probe}:t{bucket}"
+
+
+def _load(path: str) -> Dict[str, dict]:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(path: str, data: Dict[str, dict]):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(volume, rotation, lights=None, n_triangles: int = 0, reps: int = 3,
+         cache: Optional[str] = DEFAULT_CACHE, force: bool = False, verbose: bool = False) -> dict:
+    """Pick and set the fastest trace launch shape for ``volume``.
+
+    The volume's maps are updated by the trial runs (callers tune before
+    their real frames, or on a scratch volume of the same shape). Returns
+    {"config": ..., "ms": ..., "tried": n, "cached": bool}.
+    """
+    k = key(volume.cfg, n_triangles)
+    data = _load(cache) if cache else {}
+    if not force and k in data:
+        c = data[k]["config"]
+        _apply(volume, c)
+        return {"config": c, "ms": data[k]["ms"], "tried": 0, "cached": True}
+    ctx = volume.ctx
+    ctx.set_timing(True)
+    results = []
+    try:
+        for c in candidates():
+            _apply(volume, c)
+            volume.update_probes(rotation, lights)          # warm-up
+            ctx.stage_times()
+            for _ in range(reps):
+                volume.update_probes(rotation, lights)
+            st = ctx.stage_times()
+            ms = sum(st[s][0] for s in ("trace", "shadow", "shade")) / max(st["trace"][1], 1)
+            results.append((ms, c))
+            if verbose:
+                print(f"autotune {c} -> {ms:.4f} ms", flush=True)
+    finally:
+        ctx.set_timing(False)
+    results.sort(key=lambda r: r[0])
+    best_ms, best = results[0]
+    _apply(volume, best)
+    if cache:
+        data = _load(cache)
+        data[k] = {"config": {**best, "brick": list(best["brick"])}, "ms": best_ms,
+                   "default_ms": next(ms for ms, c in results if c["brick"] == (4, 4, 4) and not c["persistent"]
+                                      and c["top_nodes"] == 0 and c["block_threads"] == 128
+                                      and not c["split_shadows"])}
+        _save(cache, data)
+    return {"config": best, "ms": best_ms, "tried": len(results), "cached": False,
+            "ranking": [(round(ms, 4), c) for ms, c in results[:5]]}

@@ -137,6 +137,22 @@ struct TraceConfig {
     int persistent = 0;
     int top_nodes = 0;
     int block = 128;
+    int split_shadows = 0;  // 1: shadow rays in a compacted second pass
+};
+
+// Buffers of the split-shadow trace (per volume): hit record per ray
+// (leaf-order triangle index with bit 31 set for the dynamic BVH, distance),
+// occlusion bits per ray (bit l = light l occluded), shadow-ray queue.
+struct ShadowEntry {
+    float4 o_tmax;   // origin, tmax
+    float4 d_ray;    // direction, (ray index * 8 + light) as int bits
+};
+struct SplitBuffers {
+    int2 *hitrec = nullptr;
+    uint32_t *occ = nullptr;
+    ShadowEntry *queue = nullptr;
+    int *count = nullptr;      // queue length (zeroed by the ray-direction kernel)
+    long long capacity = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -146,7 +162,11 @@ struct TraceConfig {
 hipError_t launch_raydirs(const FrameParams &fp, int n, float4 *dirs, int *queue, hipStream_t s);
 hipError_t launch_trace(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp, const float4 *dirs,
                         float4 *rays, int32_t *hits, unsigned long long *counts, const TraceConfig &tc,
-                        int *queue, hipStream_t s);
+                        int *queue, const SplitBuffers &split, hipStream_t s);
+hipError_t launch_shadow(const SceneView &sv, const SplitBuffers &split, const TraceConfig &tc,
+                         unsigned long long *counts, hipStream_t s);
+hipError_t launch_shade(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp, const float4 *dirs,
+                        float4 *rays, const SplitBuffers &split, hipStream_t s);
 hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4 *rays, void *irr, void *vis,
                         int fp16, float h, hipStream_t s);
 hipError_t launch_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, int total_blend,

@@ -59,7 +59,7 @@ __device__ void raydir_one(const FrameParams &fp, int n, int i, float4 *dirs) {
 }
 
 __global__ void k_raydirs(FrameParams fp, int n, float4 *dirs, int *queue) {
-    if (queue && blockIdx.x == 0 && threadIdx.x < 8) queue[threadIdx.x] = 0;
+    if (queue && blockIdx.x == 0 && threadIdx.x < 16) queue[threadIdx.x] = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += blockDim.x * gridDim.x) raydir_one(fp, n, i, dirs);
 }
 
@@ -215,6 +215,32 @@ __device__ __forceinline__ NodeSrc global_nodes(const DeviceBvh &bvh) {
     return NodeSrc{reinterpret_cast<const uint4 *>(bvh.nodes), 0};
 }
 
+// The hit inner children in slot order (any-hit traversal needs no order).
+__device__ __forceinline__ int collect_inner(const Node4Hits &h, int ids[4]) {
+    int m = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const bool inner = h.hit[c] && h.count[c] == 0;
+        ids[c] = h.child[c];
+        m += inner ? 1 : 0;
+    }
+    // move the hit inner ones to the front without dynamic indexing
+    int out[4] = {-1, -1, -1, -1};
+    int w = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const bool inner = h.hit[c] && h.count[c] == 0;
+        out[0] = (inner && w == 0) ? ids[c] : out[0];
+        out[1] = (inner && w == 1) ? ids[c] : out[1];
+        out[2] = (inner && w == 2) ? ids[c] : out[2];
+        out[3] = (inner && w == 3) ? ids[c] : out[3];
+        w += inner ? 1 : 0;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ids[c] = out[c];
+    return m;
+}
+
 // Closest hit in one BVH; updates (tbest, best tri index, best array) when a
 // nearer hit is found; equal distances go to the smaller original id.
 // Leaves are tested where they are met; hit inner children are visited
@@ -286,7 +312,7 @@ __device__ bool any_hit(const DeviceBvh &bvh, const NodeSrc &src, const Ray &r, 
             }
         }
         int ids[4];
-        const int m = sort_inner(h, ids);
+        const int m = collect_inner(h, ids);
         if (m > 0) {
             // constant indices keep ids[] in registers
             if (m > 3) stk.push(sp, ids[3]);
@@ -300,11 +326,51 @@ __device__ bool any_hit(const DeviceBvh &bvh, const NodeSrc &src, const Ray &r, 
     }
 }
 
+// Geometry of a hit: unit normal facing the ray origin and the hit point.
+__device__ __forceinline__ void hit_frame(const GpuTri &T, const Ray &ray, float3 o, float t, float3 &nrm,
+                                          float3 &xh) {
+    nrm = cross3(xyz(T.e1), xyz(T.e2));
+    const float il = rsqrtf(dot3(nrm, nrm));
+    nrm = make_float3(nrm.x * il, nrm.y * il, nrm.z * il);
+    if (dot3(nrm, ray.d) > 0.f) nrm = make_float3(-nrm.x, -nrm.y, -nrm.z);
+    xh = make_float3(fmaf(t, ray.d.x, o.x), fmaf(t, ray.d.y, o.y), fmaf(t, ray.d.z, o.z));
+}
+
+// Light li at a hit: cosine, squared distance, and the shadow ray from the
+// offset point towards the light. Returns false when the light is behind.
+__device__ __forceinline__ bool light_setup(const FrameParams &fp, int li, float eps, float3 nrm, float3 xh,
+                                            float &cosv, float &d2, float3 &so, float3 &sd, float &smax) {
+    const float3 lp = make_float3(fp.light_pos[li][0], fp.light_pos[li][1], fp.light_pos[li][2]);
+    const float3 lv = lp - xh;
+    d2 = dot3(lv, lv);
+    const float dl = sqrtf(d2);
+    cosv = dot3(nrm, lv) / dl;
+    if (!(cosv > 0.f)) return false;
+    so = make_float3(fmaf(eps, nrm.x, xh.x), fmaf(eps, nrm.y, xh.y), fmaf(eps, nrm.z, xh.z));
+    sd = lp - so;
+    const float slen = sqrtf(dot3(sd, sd));
+    const float isl = 1.0f / slen;
+    sd = make_float3(sd.x * isl, sd.y * isl, sd.z * isl);
+    smax = slen - eps;
+    return true;
+}
+
+// Adds light li's direct contribution (the light is visible).
+__device__ __forceinline__ void light_add(const FrameParams &fp, int li, float4 alb, float cosv, float d2, float3 &L) {
+    const float g = cosv / d2 * 0.31830988618379067f;  // 1/pi
+    L.x = fmaf(alb.x * fp.light_int[li][0], g, L.x);
+    L.y = fmaf(alb.y * fp.light_int[li][1], g, L.y);
+    L.z = fmaf(alb.z * fp.light_int[li][2], g, L.z);
+}
+
 // Trace and shade the ray of probe (x, y, z), direction j; writes its record.
-template <bool COUNT, int W>
+// SPLIT: instead of tracing shadow rays here, record the hit and append the
+// shadow rays to the volume's queue (one atomic per wavefront and light).
+template <bool COUNT, int W, bool SPLIT>
 __device__ void trace_shade_one(const VolumeParams &vp, const SceneView &sv, const NodeSrc &stat_src,
                                 const FrameParams &fp, const float4 *dirs, float4 *rays, int32_t *hits, int x, int y,
-                                int z, int j, Stack<W> stk, Counts &cnt, uint32_t &shadow_rays) {
+                                int z, int j, Stack<W> stk, Counts &cnt, uint32_t &shadow_rays,
+                                const SplitBuffers &split) {
     const NodeSrc dyn_src = global_nodes(sv.dyn);
     const float3 o = make_float3(fmaf(vp.sx, (float)x, vp.ox), fmaf(vp.sy, (float)y, vp.oy),
                                  fmaf(vp.sz, (float)z, vp.oz));
@@ -315,48 +381,59 @@ __device__ void trace_shade_one(const VolumeParams &vp, const SceneView &sv, con
     const GpuTri *arr = nullptr;
     closest<COUNT, W>(sv.stat, stat_src, ray, 0.f, tbest, best, best_id, arr, stk, cnt);
     closest<COUNT, W>(sv.dyn, dyn_src, ray, 0.f, tbest, best, best_id, arr, stk, cnt);
+    const size_t p = (size_t)x + (size_t)vp.nx * ((size_t)y + (size_t)vp.ny * z);
+    const size_t q = p * vp.n + j;
     float3 L;
     float dist;
+    float3 nrm, xh;
+    float4 alb = make_float4(0.f, 0.f, 0.f, 0.f);
     if (best >= 0) {
         const GpuTri T = arr[best];
-        float3 nrm = cross3(xyz(T.e1), xyz(T.e2));
-        const float il = rsqrtf(dot3(nrm, nrm));
-        nrm = make_float3(nrm.x * il, nrm.y * il, nrm.z * il);
-        if (dot3(nrm, ray.d) > 0.f) nrm = make_float3(-nrm.x, -nrm.y, -nrm.z);
-        const float3 xh = make_float3(fmaf(tbest, ray.d.x, o.x), fmaf(tbest, ray.d.y, o.y), fmaf(tbest, ray.d.z, o.z));
-        const float4 alb = sv.mats[2 * best_id], emi = sv.mats[2 * best_id + 1];
+        hit_frame(T, ray, o, tbest, nrm, xh);
+        alb = sv.mats[2 * best_id];
+        const float4 emi = sv.mats[2 * best_id + 1];
         L = make_float3(emi.x, emi.y, emi.z);
-        for (int li = 0; li < fp.n_lights; ++li) {
-            const float3 lp = make_float3(fp.light_pos[li][0], fp.light_pos[li][1], fp.light_pos[li][2]);
-            const float3 lv = lp - xh;
-            const float d2 = dot3(lv, lv);
-            const float dl = sqrtf(d2);
-            const float cosv = dot3(nrm, lv) / dl;
-            if (!(cosv > 0.f)) continue;
-            const float3 so = make_float3(fmaf(sv.eps, nrm.x, xh.x), fmaf(sv.eps, nrm.y, xh.y), fmaf(sv.eps, nrm.z, xh.z));
-            float3 sd = lp - so;
-            const float slen = sqrtf(dot3(sd, sd));
-            const float isl = 1.0f / slen;
-            sd = make_float3(sd.x * isl, sd.y * isl, sd.z * isl);
-            const Ray sr = make_ray(so, sd);
-            const float smax = slen - sv.eps;
-            if (COUNT) shadow_rays++;
-            bool occ = any_hit<COUNT, W>(sv.stat, stat_src, sr, 0.f, smax, stk, cnt);
-            if (!occ) occ = any_hit<COUNT, W>(sv.dyn, dyn_src, sr, 0.f, smax, stk, cnt);
-            if (!occ) {
-                const float g = cosv / d2 * 0.31830988618379067f;  // 1/pi
-                L.x = fmaf(alb.x * fp.light_int[li][0], g, L.x);
-                L.y = fmaf(alb.y * fp.light_int[li][1], g, L.y);
-                L.z = fmaf(alb.z * fp.light_int[li][2], g, L.z);
-            }
-        }
         dist = fminf(tbest, vp.max_distance);
     } else {
         L = make_float3(vp.sky[0], vp.sky[1], vp.sky[2]);
         dist = vp.max_distance;
     }
-    const size_t p = (size_t)x + (size_t)vp.nx * ((size_t)y + (size_t)vp.ny * z);
-    const size_t q = p * vp.n + j;
+    if (!SPLIT) {
+        if (best >= 0) {
+            for (int li = 0; li < fp.n_lights; ++li) {
+                float cosv, d2, smax;
+                float3 so, sd;
+                if (!light_setup(fp, li, sv.eps, nrm, xh, cosv, d2, so, sd, smax)) continue;
+                const Ray sr = make_ray(so, sd);
+                if (COUNT) shadow_rays++;
+                bool occ = any_hit<COUNT, W>(sv.stat, stat_src, sr, 0.f, smax, stk, cnt);
+                if (!occ) occ = any_hit<COUNT, W>(sv.dyn, dyn_src, sr, 0.f, smax, stk, cnt);
+                if (!occ) light_add(fp, li, alb, cosv, d2, L);
+            }
+        }
+    } else {
+        split.hitrec[q] = make_int2(best < 0 ? -1 : (best | (arr == sv.dyn.tris ? (int)0x80000000 : 0)),
+                                    __float_as_int(tbest));
+        split.occ[q] = 0u;
+        const int lane = threadIdx.x & 63;
+        for (int li = 0; li < fp.n_lights; ++li) {
+            float cosv = 0.f, d2 = 0.f, smax = 0.f;
+            float3 so = make_float3(0.f, 0.f, 0.f), sd = so;
+            const bool need = best >= 0 && light_setup(fp, li, sv.eps, nrm, xh, cosv, d2, so, sd, smax);
+            const unsigned long long m = __ballot(need);
+            if (m == 0) continue;
+            const int leader = __ffsll((long long)m) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(split.count, __popcll(m));
+            base = __shfl(base, leader);
+            if (need) {
+                const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
+                split.queue[slot].o_tmax = make_float4(so.x, so.y, so.z, smax);
+                split.queue[slot].d_ray = make_float4(sd.x, sd.y, sd.z, __int_as_float((int)(q * 8 + li)));
+                if (COUNT) shadow_rays++;
+            }
+        }
+    }
     rays[q] = make_float4(L.x, L.y, L.z, dist);
     if (hits) hits[q] = best_id;
 }
@@ -370,10 +447,11 @@ struct TraceGrid {
 };
 
 // One wavefront = one ray direction j over one brick of probes.
-template <bool COUNT, int W>
+template <bool COUNT, int W, bool SPLIT>
 __device__ __forceinline__ void trace_wave(const VolumeParams &vp, const SceneView &sv, const NodeSrc &src,
                                            const FrameParams &fp, const float4 *dirs, float4 *rays, int32_t *hits,
-                                           const TraceGrid &g, int w, Stack<W> stk, Counts &cnt, uint32_t &shadow) {
+                                           const TraceGrid &g, int w, Stack<W> stk, Counts &cnt, uint32_t &shadow,
+                                           const SplitBuffers &split) {
     const int lane = threadIdx.x & 63;
     const int j = w / g.n_bricks, brick = w - j * g.n_bricks;
     const int bxi = brick % g.nbx, byi = (brick / g.nbx) % g.nby, bzi = brick / (g.nbx * g.nby);
@@ -381,13 +459,13 @@ __device__ __forceinline__ void trace_wave(const VolumeParams &vp, const SceneVi
     const int y = byi * g.by + (lane / g.bx) % g.by;
     const int z = bzi * g.bz + lane / (g.bx * g.by);
     if (x < vp.nx && y < vp.ny && z < vp.nz)
-        trace_shade_one<COUNT, W>(vp, sv, src, fp, dirs, rays, hits, x, y, z, j, stk, cnt, shadow);
+        trace_shade_one<COUNT, W, SPLIT>(vp, sv, src, fp, dirs, rays, hits, x, y, z, j, stk, cnt, shadow, split);
 }
 
-template <bool COUNT, int W, int TOP>
+template <bool COUNT, int W, int TOP, bool SPLIT>
 __global__ __launch_bounds__(W) void k_trace(VolumeParams vp, SceneView sv, FrameParams fp, const float4 *dirs,
                                              float4 *rays, int32_t *hits, unsigned long long *counts, TraceGrid g,
-                                             int *queue) {
+                                             int *queue, SplitBuffers split) {
     __shared__ int stk[kStack * W];
     NodeSrc src = global_nodes(sv.stat);
     if (TOP > 0) {
@@ -402,7 +480,7 @@ __global__ __launch_bounds__(W) void k_trace(VolumeParams vp, SceneView sv, Fram
     uint32_t shadow = 0;
     if (!g.persistent) {
         const int w = xcd_logical_block() * (W / 64) + (threadIdx.x >> 6);
-        if (w < g.n_waves) trace_wave<COUNT, W>(vp, sv, src, fp, dirs, rays, hits, g, w, st, cnt, shadow);
+        if (w < g.n_waves) trace_wave<COUNT, W, SPLIT>(vp, sv, src, fp, dirs, rays, hits, g, w, st, cnt, shadow, split);
     } else {
         // each wave takes packets from its XCD's range, then from the others
         const int home = blockIdx.x & 7;
@@ -414,7 +492,7 @@ __global__ __launch_bounds__(W) void k_trace(VolumeParams vp, SceneView sv, Fram
                 if ((threadIdx.x & 63) == 0) t = atomicAdd(&queue[k], 1);
                 t = __shfl(t, 0);
                 if (lo + t >= hi) break;
-                trace_wave<COUNT, W>(vp, sv, src, fp, dirs, rays, hits, g, lo + t, st, cnt, shadow);
+                trace_wave<COUNT, W, SPLIT>(vp, sv, src, fp, dirs, rays, hits, g, lo + t, st, cnt, shadow, split);
             }
         }
     }
@@ -423,6 +501,74 @@ __global__ __launch_bounds__(W) void k_trace(VolumeParams vp, SceneView sv, Fram
         atomicAdd(&counts[1], (unsigned long long)cnt.tris);
         atomicAdd(&counts[2], (unsigned long long)shadow);
     }
+}
+
+// Shadow rays of the split trace: dense any-hit over the compacted queue.
+template <bool COUNT, int W, int TOP>
+__global__ __launch_bounds__(W) void k_shadow(SceneView sv, SplitBuffers split, unsigned long long *counts) {
+    __shared__ int stk[kStack * W];
+    NodeSrc src = global_nodes(sv.stat);
+    if (TOP > 0) {
+        const int nt = min(TOP, sv.stat.n_nodes);
+        const uint4 *gn = reinterpret_cast<const uint4 *>(sv.stat.nodes);
+        for (int i = threadIdx.x; i < nt * 4; i += W) pv_top_nodes[i] = gn[i];
+        __syncthreads();
+        src.top = nt;
+    }
+    const NodeSrc dyn_src = global_nodes(sv.dyn);
+    Stack<W> st{stk + threadIdx.x};
+    Counts cnt = {0, 0};
+    const int n = *split.count;
+    // whole wavefronts step together through the queue
+    const int nwaves_grid = gridDim.x * (W / 64);
+    const int wave = blockIdx.x * (W / 64) + (threadIdx.x >> 6);
+    for (int base = wave * 64; base < n; base += nwaves_grid * 64) {
+        const int i = base + (threadIdx.x & 63);
+        if (i < n) {
+            const ShadowEntry e = split.queue[i];
+            const Ray sr = make_ray(xyz(e.o_tmax), xyz(e.d_ray));
+            bool occ = any_hit<COUNT, W>(sv.stat, src, sr, 0.f, e.o_tmax.w, st, cnt);
+            if (!occ) occ = any_hit<COUNT, W>(sv.dyn, dyn_src, sr, 0.f, e.o_tmax.w, st, cnt);
+            if (occ) {
+                const int code = __float_as_int(e.d_ray.w);
+                atomicOr(&split.occ[code >> 3], 1u << (code & 7));
+            }
+        }
+    }
+    if (COUNT) {
+        atomicAdd(&counts[0], (unsigned long long)cnt.nodes);
+        atomicAdd(&counts[1], (unsigned long long)cnt.tris);
+    }
+}
+
+// Shade pass of the split trace: the same light loop as the fused trace, with
+// each light's visibility read from the occlusion bits.
+__global__ __launch_bounds__(256) void k_shade(VolumeParams vp, SceneView sv, FrameParams fp, const float4 *dirs,
+                                               float4 *rays, SplitBuffers split) {
+    const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (size_t)vp.P * vp.n) return;
+    const int2 hr = split.hitrec[q];
+    if (hr.x < 0 || fp.n_lights == 0) return;
+    const int p = (int)(q / vp.n), j = (int)(q - (size_t)p * vp.n);
+    const int x = p % vp.nx, y = (p / vp.nx) % vp.ny, z = p / (vp.nx * vp.ny);
+    const float3 o = make_float3(fmaf(vp.sx, (float)x, vp.ox), fmaf(vp.sy, (float)y, vp.oy),
+                                 fmaf(vp.sz, (float)z, vp.oz));
+    const Ray ray = make_ray(o, xyz(dirs[j]));
+    const GpuTri *arr = (hr.x & 0x80000000) ? sv.dyn.tris : sv.stat.tris;
+    const GpuTri T = arr[hr.x & 0x7fffffff];
+    float3 nrm, xh;
+    hit_frame(T, ray, o, __int_as_float(hr.y), nrm, xh);
+    const float4 alb = sv.mats[2 * tri_id(T)];
+    const uint32_t occ = split.occ[q];
+    float4 rec = rays[q];
+    float3 L = make_float3(rec.x, rec.y, rec.z);
+    for (int li = 0; li < fp.n_lights; ++li) {
+        float cosv, d2, smax;
+        float3 so, sd;
+        if (!light_setup(fp, li, sv.eps, nrm, xh, cosv, d2, so, sd, smax)) continue;
+        if (!((occ >> li) & 1u)) light_add(fp, li, alb, cosv, d2, L);
+    }
+    rays[q] = make_float4(L.x, L.y, L.z, rec.w);
 }
 
 // ---------------------------------------------------------------------------
@@ -637,9 +783,10 @@ __global__ __launch_bounds__(kBatchBlock) void k_batched(const BatchVolume *vols
                 Counts cnt = {0, 0};
                 uint32_t sh = 0;
                 if (x < bv.vp.nx && y < bv.vp.ny && z < bv.vp.nz)
-                    trace_shade_one<false, kBatchBlock>(bv.vp, bv.sv, global_nodes(bv.sv.stat), frames[v], bv.dirs,
-                                                        bv.rays, bv.hits, x, y, z, j,
-                                                        Stack<kBatchBlock>{sm.stk + threadIdx.x}, cnt, sh);
+                    trace_shade_one<false, kBatchBlock, false>(bv.vp, bv.sv, global_nodes(bv.sv.stat), frames[v],
+                                                               bv.dirs, bv.rays, bv.hits, x, y, z, j,
+                                                               Stack<kBatchBlock>{sm.stk + threadIdx.x}, cnt, sh,
+                                                               SplitBuffers());
             }
             __threadfence();
             __syncthreads();
@@ -712,91 +859,188 @@ __device__ __forceinline__ bool texel_changed(uint16_t a, uint16_t b, float tau)
     return fabs(da - db) > (double)tau;
 }
 
-// One wavefront per probe: any interior texel changed -> mask = 1.
-__global__ __launch_bounds__(256) void k_pack_mask(PackBuffers b, int P, float tau_irr, float tau_vis) {
-    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (p >= P) return;
-    const int lane = threadIdx.x & 63;
-    const uint16_t *ci = b.cur_irr + (size_t)p * 300;
-    const uint16_t *ri = b.ref_irr + (size_t)p * 192;
-    bool ch_i = false;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const int t = lane;  // interior texel, row-major 8x8
-        const uint16_t a = ci[c * 100 + ((t >> 3) + 1) * 10 + (t & 7) + 1];
-        ch_i |= texel_changed(a, ri[c * 64 + t], tau_irr);
+// The pack works on tiles of kPackQ consecutive probes. Their FP16 tiles are
+// contiguous in HBM (600 B and 1,296 B per probe) and start on 16-byte
+// boundaries (kPackQ * 600 and kPackQ * 1,296 are multiples of 16), so a block
+// stages them into LDS with aligned 16-byte loads (map allocations carry 256
+// bytes of slack, so the last vector of a ragged tail stays in bounds). Work
+// is then split into row units of 8 interior texels of one channel:
+// irradiance 3 x 8 rows per probe, visibility 2 x 16 rows x 2 halves.
+constexpr int kPackQ = 16;
+constexpr int kPackThreads = 256;
+constexpr int kIrrUnits = 3 * 8;       // per probe
+constexpr int kVisUnits = 2 * 16 * 2;  // per probe
+
+struct PackSmem {
+    uint4 irr[kPackQ * 600 / 16];
+    uint4 vis[kPackQ * 1296 / 16];
+    int changed[kPackQ][2];
+    uint32_t part[kPackThreads / 64];
+};
+
+__device__ __forceinline__ void stage_tiles(const PackBuffers &b, int p0, int P, PackSmem &sm) {
+    const int n = min(kPackQ, P - p0);
+    const uint4 *gi = reinterpret_cast<const uint4 *>(b.cur_irr + (size_t)p0 * 300);
+    const uint4 *gv = reinterpret_cast<const uint4 *>(b.cur_vis + (size_t)p0 * 648);
+    const int vi = (n * 600 + 15) / 16, vv = (n * 1296 + 15) / 16;
+    for (int i = threadIdx.x; i < vi; i += kPackThreads) sm.irr[i] = gi[i];
+    for (int i = threadIdx.x; i < vv; i += kPackThreads) sm.vis[i] = gv[i];
+}
+
+// Unit u of the tile (irradiance units first): probe q, texture (0 irr,
+// 1 vis), channel c, first interior texel t0 (multiple of 8).
+struct Unit {
+    int q, tex, c, t0, N;
+};
+
+__device__ __forceinline__ Unit unit_of(int u) {
+    Unit r;
+    if (u < kPackQ * kIrrUnits) {
+        r.q = u / kIrrUnits;
+        const int w = u - r.q * kIrrUnits;
+        r.tex = 0;
+        r.c = w / 8;
+        r.t0 = (w % 8) * 8;
+        r.N = 8;
+    } else {
+        const int v = u - kPackQ * kIrrUnits;
+        r.q = v / kVisUnits;
+        const int w = v - r.q * kVisUnits;
+        r.tex = 1;
+        r.c = w / 32;
+        r.t0 = (w % 32) * 8;
+        r.N = 16;
     }
-    const uint16_t *cv = b.cur_vis + (size_t)p * 648;
-    const uint16_t *rv = b.ref_vis + (size_t)p * 512;
-    bool ch_v = false;
+    return r;
+}
+
+// The 8 current texels of a unit from the staged tiles.
+__device__ __forceinline__ void unit_cur(const PackSmem &sm, const Unit &u, uint16_t cur[8]) {
+    const uint16_t *base = u.tex == 0 ? reinterpret_cast<const uint16_t *>(sm.irr) + u.q * 300 + u.c * 100
+                                      : reinterpret_cast<const uint16_t *>(sm.vis) + u.q * 648 + u.c * 324;
+    const int S = u.N + 2, row = u.t0 / u.N, col = u.t0 - row * u.N;
+    const uint16_t *src = base + (row + 1) * S + col + 1;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int c = k >> 2, t = lane + 64 * (k & 3);
-        const uint16_t a = cv[c * 324 + ((t >> 4) + 1) * 18 + (t & 15) + 1];
-        ch_v |= texel_changed(a, rv[c * 256 + t], tau_vis);
+    for (int i = 0; i < 8; ++i) cur[i] = src[i];
+}
+
+__device__ __forceinline__ uint16_t *unit_ref(const PackBuffers &b, int p, const Unit &u) {
+    return u.tex == 0 ? b.ref_irr + (size_t)p * 192 + u.c * 64 + u.t0 : b.ref_vis + (size_t)p * 512 + u.c * 256 + u.t0;
+}
+
+__device__ __forceinline__ void unpack8(uint4 v, uint16_t r[8]) {
+    r[0] = v.x & 0xffff;
+    r[1] = v.x >> 16;
+    r[2] = v.y & 0xffff;
+    r[3] = v.y >> 16;
+    r[4] = v.z & 0xffff;
+    r[5] = v.z >> 16;
+    r[6] = v.w & 0xffff;
+    r[7] = v.w >> 16;
+}
+
+// Change mask of every probe: any interior texel differs (tau = 0) or
+// |cur - ref| > tau.
+__global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P, float tau_irr, float tau_vis) {
+    __shared__ PackSmem sm;
+    const int p0 = blockIdx.x * kPackQ;
+    if (p0 >= P) return;
+    if (threadIdx.x < kPackQ * 2) sm.changed[threadIdx.x >> 1][threadIdx.x & 1] = 0;
+    stage_tiles(b, p0, P, sm);
+    __syncthreads();
+    const int n = min(kPackQ, P - p0);
+    const int units = kPackQ * (kIrrUnits + kVisUnits);
+    for (int u = threadIdx.x; u < units; u += kPackThreads) {
+        const Unit un = unit_of(u);
+        if (un.q >= n) continue;
+        uint16_t cur[8], ref[8];
+        unit_cur(sm, un, cur);
+        unpack8(*reinterpret_cast<const uint4 *>(unit_ref(b, p0 + un.q, un)), ref);
+        const float tau = un.tex == 0 ? tau_irr : tau_vis;
+        bool ch = false;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) ch |= texel_changed(cur[i], ref[i], tau);
+        if (ch) atomicOr(&sm.changed[un.q][un.tex], 1);
     }
-    const bool any_i = __any(ch_i), any_v = __any(ch_v);
-    if (lane == 0) {
-        b.mask_irr[p] = any_i ? 1 : 0;
-        b.mask_vis[p] = any_v ? 1 : 0;
+    __syncthreads();
+    if (threadIdx.x < n) {
+        b.mask_irr[p0 + threadIdx.x] = (uint8_t)sm.changed[threadIdx.x][0];
+        b.mask_vis[p0 + threadIdx.x] = (uint8_t)sm.changed[threadIdx.x][1];
     }
 }
 
 constexpr int kScanBlock = 1024;
 
-__device__ int block_exclusive_sum(int v, int *sh, int &total) {
-    const int tid = threadIdx.x;
-    sh[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < kScanBlock; off <<= 1) {
-        const int add = tid >= off ? sh[tid - off] : 0;
-        __syncthreads();
-        sh[tid] += add;
-        __syncthreads();
+// Inclusive scans across the block with wavefront shuffles and one LDS step.
+__device__ __forceinline__ void block_scan2(int &a, int &m, int *sh_a, int *sh_m, int &total_a) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int ya = __shfl_up(a, off), ym = __shfl_up(m, off);
+        if (lane >= off) {
+            a += ya;
+            m = max(m, ym);
+        }
     }
-    total = sh[kScanBlock - 1];
-    const int excl = sh[tid] - v;
-    __syncthreads();
-    return excl;
-}
-
-__device__ int block_exclusive_max(int v, int *sh) {
-    const int tid = threadIdx.x;
-    sh[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < kScanBlock; off <<= 1) {
-        const int o = tid >= off ? sh[tid - off] : -1;
-        __syncthreads();
-        sh[tid] = max(sh[tid], o);
-        __syncthreads();
+    if (lane == 63) {
+        sh_a[wv] = a;
+        sh_m[wv] = m;
     }
-    const int excl = tid > 0 ? sh[tid - 1] : -1;
     __syncthreads();
-    return excl;
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kScanBlock / 64; ++w) {
+            sh_a[w] += sh_a[w - 1];
+            sh_m[w] = max(sh_m[w], sh_m[w - 1]);
+        }
+    }
+    __syncthreads();
+    if (wv > 0) {
+        a += sh_a[wv - 1];
+        m = max(m, sh_m[wv - 1]);
+    }
+    total_a = sh_a[kScanBlock / 64 - 1];
+    __syncthreads();
 }
 
 // One block: ordered ranks of the changed probes, delta-coded index buffers,
 // the header, and the checksum share of the index section.
 __global__ __launch_bounds__(kScanBlock) void k_pack_scan(PackBuffers b, int P, uint32_t client, uint32_t seq) {
-    __shared__ int sh[kScanBlock];
+    __shared__ int sh_a[kScanBlock / 64], sh_m[kScanBlock / 64];
     __shared__ uint32_t shu[kScanBlock / 64];
     const int tid = threadIdx.x;
     const int per = (P + kScanBlock - 1) / kScanBlock;
     const int lo = min(P, tid * per), hi = min(P, lo + per);
     int ki = 0, kv = 0, last_i = -1, last_v = -1;
     for (int p = lo; p < hi; ++p) {
-        if (b.mask_irr[p]) { ++ki; last_i = p; }
-        if (b.mask_vis[p]) { ++kv; last_v = p; }
+        if (b.mask_irr[p]) {
+            ++ki;
+            last_i = p;
+        }
+        if (b.mask_vis[p]) {
+            ++kv;
+            last_v = p;
+        }
     }
-    int K_irr, K_vis;
-    const int base_i = block_exclusive_sum(ki, sh, K_irr);
-    const int base_v = block_exclusive_sum(kv, sh, K_vis);
-    int prev_i = block_exclusive_max(last_i, sh);
-    int prev_v = block_exclusive_max(last_v, sh);
+    // inclusive scans; exclusive values are the inclusive ones minus this thread's
+    int ai = ki, mi = last_i, av = kv, mv = last_v, K_irr, K_vis;
+    block_scan2(ai, mi, sh_a, sh_m, K_irr);
+    block_scan2(av, mv, sh_a, sh_m, K_vis);
+    // exclusive max: the previous threads' last changed probe
+    int prev_i = __shfl_up(mi, 1), prev_v = __shfl_up(mv, 1);
+    __shared__ int wlast_i[kScanBlock / 64], wlast_v[kScanBlock / 64];
+    if ((tid & 63) == 63) {
+        wlast_i[tid >> 6] = mi;
+        wlast_v[tid >> 6] = mv;
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) {
+        prev_i = (tid >> 6) > 0 ? wlast_i[(tid >> 6) - 1] : -1;
+        prev_v = (tid >> 6) > 0 ? wlast_v[(tid >> 6) - 1] : -1;
+    }
     uint8_t *pk = b.packet;
     uint16_t *idx_i = reinterpret_cast<uint16_t *>(pk + 32);
     uint16_t *idx_v = idx_i + K_irr;
-    int k_i = base_i, k_v = base_v;
+    int k_i = ai - ki, k_v = av - kv;
     for (int p = lo; p < hi; ++p) {
         if (b.mask_irr[p]) {
             b.rank_irr[p] = k_i;
@@ -839,72 +1083,62 @@ __global__ __launch_bounds__(kScanBlock) void k_pack_scan(PackBuffers b, int P, 
     }
 }
 
-// One block of 192 threads per probe: XOR byte planes of the sent probes,
-// reference update, checksum share. Threads 0..47 take irradiance (3
-// channels x 16 groups of 4 texels), 48..175 visibility (2 x 64 groups).
-__global__ __launch_bounds__(192) void k_pack_compact(PackBuffers b, int P) {
-    __shared__ uint32_t shu[3];
-    const int p = blockIdx.x;
-    if (p >= P) return;
-    const bool si = b.mask_irr[p] != 0, svv = b.mask_vis[p] != 0;
-    if (!si && !svv) return;
-    const int tid = threadIdx.x;
+// XOR byte planes of the sent probes, reference update, checksum share.
+__global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, int P) {
+    __shared__ PackSmem sm;
+    const int p0 = blockIdx.x * kPackQ;
+    if (p0 >= P) return;
+    const int n = min(kPackQ, P - p0);
+    // skip the tile when none of its probes is sent (uniform per block)
+    bool any = false;
+    for (int q = 0; q < n; ++q) any |= (b.mask_irr[p0 + q] | b.mask_vis[p0 + q]) != 0;
+    if (!any) return;
+    stage_tiles(b, p0, P, sm);
+    __syncthreads();
     const uint32_t *h = reinterpret_cast<const uint32_t *>(b.packet);
     const int K_irr = (int)h[5], K_vis = (int)h[6];
     const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
     uint8_t *planes_i = b.packet + 32 + idx_bytes;
     uint8_t *planes_v = planes_i + (size_t)K_irr * 6 * 64;
     uint32_t part = 0;
-    int N = 0, c = 0, m = 0, K = 0, k = 0;
-    const uint16_t *tile = nullptr;
-    uint16_t *ref = nullptr;
-    uint8_t *planes = nullptr;
-    bool act = false;
-    if (tid < 48 && si) {
-        N = 8;
-        c = tid >> 4;
-        m = tid & 15;
-        K = K_irr;
-        k = (int)b.rank_irr[p];
-        tile = b.cur_irr + (size_t)p * 300 + c * 100;
-        ref = b.ref_irr + (size_t)p * 192 + c * 64;
-        planes = planes_i;
-        act = true;
-    } else if (tid >= 48 && tid < 176 && svv) {
-        const int u = tid - 48;
-        N = 16;
-        c = u >> 6;
-        m = u & 63;
-        K = K_vis;
-        k = (int)b.rank_vis[p];
-        tile = b.cur_vis + (size_t)p * 648 + c * 324;
-        ref = b.ref_vis + (size_t)p * 512 + c * 256;
-        planes = planes_v;
-        act = true;
-    }
-    if (act) {
-        const int t0 = 4 * m, row = t0 / N, col = t0 - row * N;
-        const uint16_t *src = tile + (row + 1) * (N + 2) + col + 1;
-        const uint16_t a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3];
-        const uint2 rf = *reinterpret_cast<const uint2 *>(ref + t0);
-        const uint16_t x0 = a0 ^ (uint16_t)(rf.x & 0xffff), x1 = a1 ^ (uint16_t)(rf.x >> 16);
-        const uint16_t x2 = a2 ^ (uint16_t)(rf.y & 0xffff), x3 = a3 ^ (uint16_t)(rf.y >> 16);
-        const uint32_t lo = (x0 & 0xffu) | ((x1 & 0xffu) << 8) | ((x2 & 0xffu) << 16) | ((uint32_t)(x3 & 0xffu) << 24);
-        const uint32_t hi = (x0 >> 8) | ((x1 >> 8) << 8) | ((x2 >> 8) << 16) | ((uint32_t)(x3 >> 8) << 24);
-        const size_t plane_bytes = (size_t)K * N * N;
-        uint8_t *dlo = planes + (size_t)(2 * c) * plane_bytes + (size_t)k * N * N + t0;
+    const int units = kPackQ * (kIrrUnits + kVisUnits);
+    for (int u = threadIdx.x; u < units; u += kPackThreads) {
+        const Unit un = unit_of(u);
+        if (un.q >= n) continue;
+        const int p = p0 + un.q;
+        if (!(un.tex == 0 ? b.mask_irr[p] : b.mask_vis[p])) continue;
+        uint16_t cur[8], ref[8];
+        unit_cur(sm, un, cur);
+        uint16_t *rp = unit_ref(b, p, un);
+        unpack8(*reinterpret_cast<const uint4 *>(rp), ref);
+        uint32_t lo[2] = {0, 0}, hi[2] = {0, 0};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint16_t x = cur[i] ^ ref[i];
+            lo[i >> 2] |= (uint32_t)(x & 0xff) << (8 * (i & 3));
+            hi[i >> 2] |= (uint32_t)(x >> 8) << (8 * (i & 3));
+        }
+        const int K = un.tex == 0 ? K_irr : K_vis;
+        const int k = un.tex == 0 ? (int)b.rank_irr[p] : (int)b.rank_vis[p];
+        const size_t NN = (size_t)un.N * un.N, plane_bytes = (size_t)K * NN;
+        uint8_t *dlo = (un.tex == 0 ? planes_i : planes_v) + (size_t)(2 * un.c) * plane_bytes + (size_t)k * NN + un.t0;
         uint8_t *dhi = dlo + plane_bytes;
-        *reinterpret_cast<uint32_t *>(dlo) = lo;
-        *reinterpret_cast<uint32_t *>(dhi) = hi;
-        *reinterpret_cast<uint2 *>(ref + t0) =
-            make_uint2((uint32_t)a0 | ((uint32_t)a1 << 16), (uint32_t)a2 | ((uint32_t)a3 << 16));
-        part = word_hash(lo, (uint32_t)((dlo - (b.packet + 32)) >> 2)) +
-               word_hash(hi, (uint32_t)((dhi - (b.packet + 32)) >> 2));
+        *reinterpret_cast<uint2 *>(dlo) = make_uint2(lo[0], lo[1]);
+        *reinterpret_cast<uint2 *>(dhi) = make_uint2(hi[0], hi[1]);
+        *reinterpret_cast<uint4 *>(rp) =
+            make_uint4((uint32_t)cur[0] | ((uint32_t)cur[1] << 16), (uint32_t)cur[2] | ((uint32_t)cur[3] << 16),
+                       (uint32_t)cur[4] | ((uint32_t)cur[5] << 16), (uint32_t)cur[6] | ((uint32_t)cur[7] << 16));
+        const uint32_t wlo = (uint32_t)((dlo - (b.packet + 32)) >> 2), whi = (uint32_t)((dhi - (b.packet + 32)) >> 2);
+        part += word_hash(lo[0], wlo) + word_hash(lo[1], wlo + 1) + word_hash(hi[0], whi) + word_hash(hi[1], whi + 1);
     }
     for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-    if ((tid & 63) == 0) shu[tid >> 6] = part;
+    if ((threadIdx.x & 63) == 0) sm.part[threadIdx.x >> 6] = part;
     __syncthreads();
-    if (tid == 0) atomicAdd(reinterpret_cast<uint32_t *>(b.packet) + 7, shu[0] + shu[1] + shu[2]);
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int w = 0; w < kPackThreads / 64; ++w) s += sm.part[w];
+        atomicAdd(reinterpret_cast<uint32_t *>(b.packet) + 7, s);
+    }
 }
 
 __global__ void k_zero(uint32_t *p, size_t words) {
@@ -926,16 +1160,16 @@ hipError_t launch_raydirs_batched(const FrameParams *frames_dev, const int *ns_d
     return hipGetLastError();
 }
 
-template <bool COUNT, int W, int TOP>
+template <bool COUNT, int W, int TOP, bool SPLIT>
 static hipError_t launch_trace_t(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp,
                                  const float4 *dirs, float4 *rays, int32_t *hits, unsigned long long *counts,
-                                 const TraceGrid &g, int *queue, hipStream_t s) {
+                                 const TraceGrid &g, int *queue, const SplitBuffers &split, hipStream_t s) {
     unsigned blocks;
     if (g.persistent) {
         int dev = 0, cus = 256, per_cu = 1;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<COUNT, W, TOP>, W,
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<COUNT, W, TOP, SPLIT>, W,
                                                            (size_t)TOP * sizeof(GpuNode4));
         const long long need = ((long long)g.n_waves * 64 + W - 1) / W;
         blocks = (unsigned)std::max(1ll, std::min<long long>((long long)cus * std::max(per_cu, 1), need));
@@ -943,18 +1177,19 @@ static hipError_t launch_trace_t(const VolumeParams &vp, const SceneView &sv, co
         blocks = (unsigned)(((long long)g.n_waves * 64 + W - 1) / W);
     }
     const size_t smem = (size_t)TOP * sizeof(GpuNode4);
-    hipLaunchKernelGGL((k_trace<COUNT, W, TOP>), dim3(blocks), dim3(W), smem, s, vp, sv, fp, dirs, rays, hits, counts,
-                       g, queue);
+    hipLaunchKernelGGL((k_trace<COUNT, W, TOP, SPLIT>), dim3(blocks), dim3(W), smem, s, vp, sv, fp, dirs, rays, hits,
+                       counts, g, queue, split);
     return hipGetLastError();
 }
 
-template <bool COUNT>
+template <bool COUNT, bool SPLIT>
 static hipError_t launch_trace_c(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp,
                                  const float4 *dirs, float4 *rays, int32_t *hits, unsigned long long *counts,
-                                 const TraceConfig &tc, const TraceGrid &g, int *queue, hipStream_t s) {
+                                 const TraceConfig &tc, const TraceGrid &g, int *queue, const SplitBuffers &split,
+                                 hipStream_t s) {
 #define PV_TRACE_CASE(Wv, Tv)                                                                                   \
     if (tc.block == Wv && tc.top_nodes == Tv)                                                                  \
-        return launch_trace_t<COUNT, Wv, Tv>(vp, sv, fp, dirs, rays, hits, counts, g, queue, s);
+        return launch_trace_t<COUNT, Wv, Tv, SPLIT>(vp, sv, fp, dirs, rays, hits, counts, g, queue, split, s);
     PV_TRACE_CASE(128, 0)
     PV_TRACE_CASE(128, 21)
     PV_TRACE_CASE(128, 85)
@@ -967,7 +1202,7 @@ static hipError_t launch_trace_c(const VolumeParams &vp, const SceneView &sv, co
 
 hipError_t launch_trace(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp, const float4 *dirs,
                         float4 *rays, int32_t *hits, unsigned long long *counts, const TraceConfig &tc, int *queue,
-                        hipStream_t s) {
+                        const SplitBuffers &split, hipStream_t s) {
     TraceGrid g;
     g.bx = tc.bx;
     g.by = tc.by;
@@ -979,8 +1214,51 @@ hipError_t launch_trace(const VolumeParams &vp, const SceneView &sv, const Frame
     g.n_waves = g.n_bricks * vp.n;
     g.persistent = tc.persistent && queue != nullptr;
     g.chunk = (g.n_waves + 7) / 8;
-    if (counts) return launch_trace_c<true>(vp, sv, fp, dirs, rays, hits, counts, tc, g, queue, s);
-    return launch_trace_c<false>(vp, sv, fp, dirs, rays, hits, counts, tc, g, queue, s);
+    const bool split_mode = tc.split_shadows && split.queue != nullptr;
+    if (counts) {
+        if (split_mode) return launch_trace_c<true, true>(vp, sv, fp, dirs, rays, hits, counts, tc, g, queue, split, s);
+        return launch_trace_c<true, false>(vp, sv, fp, dirs, rays, hits, counts, tc, g, queue, split, s);
+    }
+    if (split_mode) return launch_trace_c<false, true>(vp, sv, fp, dirs, rays, hits, counts, tc, g, queue, split, s);
+    return launch_trace_c<false, false>(vp, sv, fp, dirs, rays, hits, counts, tc, g, queue, split, s);
+}
+
+template <bool COUNT, int W, int TOP>
+static hipError_t launch_shadow_t(const SceneView &sv, const SplitBuffers &split, unsigned long long *counts,
+                                  hipStream_t s) {
+    int dev = 0, cus = 256, per_cu = 1;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_shadow<COUNT, W, TOP>, W,
+                                                       (size_t)TOP * sizeof(GpuNode4));
+    const long long cap_blocks = (split.capacity + W - 1) / W;
+    const unsigned blocks = (unsigned)std::max(1ll, std::min<long long>((long long)cus * std::max(per_cu, 1), cap_blocks));
+    hipLaunchKernelGGL((k_shadow<COUNT, W, TOP>), dim3(blocks), dim3(W), (size_t)TOP * sizeof(GpuNode4), s, sv, split,
+                       counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_shadow(const SceneView &sv, const SplitBuffers &split, const TraceConfig &tc,
+                         unsigned long long *counts, hipStream_t s) {
+#define PV_SHADOW_CASE(Wv, Tv)                                                           \
+    if (tc.block == Wv && tc.top_nodes == Tv)                                            \
+        return counts ? launch_shadow_t<true, Wv, Tv>(sv, split, counts, s)              \
+                      : launch_shadow_t<false, Wv, Tv>(sv, split, counts, s);
+    PV_SHADOW_CASE(128, 0)
+    PV_SHADOW_CASE(128, 21)
+    PV_SHADOW_CASE(128, 85)
+    PV_SHADOW_CASE(256, 0)
+    PV_SHADOW_CASE(256, 21)
+    PV_SHADOW_CASE(256, 85)
+#undef PV_SHADOW_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_shade(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp, const float4 *dirs,
+                        float4 *rays, const SplitBuffers &split, hipStream_t s) {
+    const long long n = (long long)vp.P * vp.n;
+    hipLaunchKernelGGL(k_shade, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vp, sv, fp, dirs, rays, split);
+    return hipGetLastError();
 }
 
 hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4 *rays, void *irr, void *vis,
@@ -1019,7 +1297,7 @@ hipError_t launch_batched(const BatchVolume *vols_dev, int n_vols, int total_wav
 }
 
 hipError_t launch_pack_mask(const PackBuffers &b, int P, float tau_irr, float tau_vis, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_mask, dim3((P + 3) / 4), dim3(256), 0, s, b, P, tau_irr, tau_vis);
+    hipLaunchKernelGGL(k_pack_mask, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P, tau_irr, tau_vis);
     return hipGetLastError();
 }
 
@@ -1029,7 +1307,7 @@ hipError_t launch_pack_scan(const PackBuffers &b, int P, uint32_t client, uint32
 }
 
 hipError_t launch_pack_compact(const PackBuffers &b, int P, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_compact, dim3(P), dim3(192), 0, s, b, P);
+    hipLaunchKernelGGL(k_pack_compact, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P);
     return hipGetLastError();
 }
 

@@ -115,10 +115,11 @@ struct pv_volume {
     void *irr = nullptr, *vis = nullptr;
     float4 *rays = nullptr, *dirs = nullptr;
     int32_t *hits = nullptr;
-    int *queue = nullptr;  // 8 work-queue counters of the persistent trace
+    int *queue = nullptr;  // [0..7] work queues of the persistent trace, [8] shadow-queue length
     int64_t frame = 0;
     pv_scene *scene = nullptr;
     TraceConfig tc;
+    SplitBuffers split;    // allocated on first use of the split-shadow trace
 };
 
 struct pv_client {
@@ -132,7 +133,8 @@ struct pv_client {
     uint32_t *hdr_host = nullptr;  // pinned, 32 bytes
 };
 
-static hipStream_t pick(pv_ctx *ctx, void *s) { return s ? (hipStream_t)s : ctx->stream; }
+// NULL is HIP's default stream, as in the HIP API itself.
+static hipStream_t pick(pv_ctx *, void *s) { return (hipStream_t)s; }
 
 static uint64_t irr_bytes(int P, size_t elem) { return (uint64_t)P * 3 * 100 * elem; }
 static uint64_t vis_bytes(int P, size_t elem) { return (uint64_t)P * 2 * 324 * elem; }
@@ -456,7 +458,7 @@ static pv_status validate_desc(const pv_volume_desc *d) {
 static uint64_t volume_bytes(const pv_volume_desc *d) {
     const int P = d->nx * d->ny * d->nz, n = d->rays_per_probe;
     const size_t elem = d->format == PV_MAP_FP16 ? 2 : 4;
-    uint64_t b = irr_bytes(P, elem) + vis_bytes(P, elem) + (uint64_t)P * n * 16 + (uint64_t)n * 16 + 32;
+    uint64_t b = irr_bytes(P, elem) + vis_bytes(P, elem) + 512 + (uint64_t)P * n * 16 + (uint64_t)n * 16 + 64;
     if (d->flags & PV_KEEP_HITS) b += (uint64_t)P * n * 4;
     return b;
 }
@@ -475,6 +477,9 @@ static void free_volume(pv_volume *v) {
     hipFree(v->dirs);
     hipFree(v->hits);
     hipFree(v->queue);
+    hipFree(v->split.hitrec);
+    hipFree(v->split.occ);
+    hipFree(v->split.queue);
     delete v;
 }
 
@@ -488,12 +493,13 @@ extern "C" pv_status pv_create_volume(pv_ctx *ctx, const pv_volume_desc *d, pv_v
     v->P = d->nx * d->ny * d->nz;
     v->n = d->rays_per_probe;
     v->elem = d->format == PV_MAP_FP16 ? 2 : 4;
-    pv_status st = dev_alloc(&v->irr, irr_bytes(v->P, v->elem), "irradiance maps");
-    if (st == PV_OK) st = dev_alloc(&v->vis, vis_bytes(v->P, v->elem), "visibility maps");
+    // 256 bytes of slack: vector loads of a ragged last tile stay in bounds
+    pv_status st = dev_alloc(&v->irr, irr_bytes(v->P, v->elem) + 256, "irradiance maps");
+    if (st == PV_OK) st = dev_alloc(&v->vis, vis_bytes(v->P, v->elem) + 256, "visibility maps");
     if (st == PV_OK) st = dev_alloc(&v->rays, (size_t)v->P * v->n * 16, "ray buffer");
     if (st == PV_OK) st = dev_alloc(&v->dirs, (size_t)v->n * 16, "directions");
     if (st == PV_OK && (d->flags & PV_KEEP_HITS)) st = dev_alloc(&v->hits, (size_t)v->P * v->n * 4, "hit ids");
-    if (st == PV_OK) st = dev_alloc(&v->queue, 8 * sizeof(int), "work queues");
+    if (st == PV_OK) st = dev_alloc(&v->queue, 16 * sizeof(int), "work queues");
     if (st == PV_OK && launch_zero(v->irr, irr_bytes(v->P, v->elem), ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "zero fill");
     if (st == PV_OK && launch_zero(v->vis, vis_bytes(v->P, v->elem), ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "zero fill");
     if (st == PV_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "sync after zero fill");
@@ -571,6 +577,41 @@ static float effective_h(const pv_volume *v) {
     return (v->frame == 0 && (v->desc.flags & PV_FIRST_FRAME_NO_HISTORY)) ? 0.f : v->desc.hysteresis;
 }
 
+// Split-shadow buffers sized for this frame's lights (grown when needed).
+static pv_status ensure_split(pv_volume *v, int n_lights, hipStream_t s) {
+    const long long need = (long long)v->P * v->n * std::max(n_lights, 1);
+    if (v->split.hitrec && v->split.capacity >= need) return PV_OK;
+    HIP_TRY(hipStreamSynchronize(s));
+    hipFree(v->split.hitrec);
+    hipFree(v->split.occ);
+    hipFree(v->split.queue);
+    v->split = SplitBuffers();
+    PV_TRY(dev_alloc(&v->split.hitrec, (size_t)v->P * v->n * sizeof(int2), "hit records"));
+    PV_TRY(dev_alloc(&v->split.occ, (size_t)v->P * v->n * sizeof(uint32_t), "occlusion bits"));
+    PV_TRY(dev_alloc(&v->split.queue, (size_t)need * sizeof(ShadowEntry), "shadow queue"));
+    v->split.count = v->queue + 8;
+    v->split.capacity = need;
+    return PV_OK;
+}
+
+// Enqueues ray directions + trace (+ shadow + shade passes in split mode).
+static pv_status enqueue_trace(pv_volume *v, const FrameParams &fp, const SceneView &sv, unsigned long long *counts,
+                               hipStream_t s) {
+    pv_ctx *c = v->ctx;
+    const VolumeParams vp = volume_params(v);
+    const bool split = v->tc.split_shadows != 0;
+    if (split) PV_TRY(ensure_split(v, fp.n_lights, s));
+    const SplitBuffers sb = split ? v->split : SplitBuffers();
+    HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s, [&] { return launch_raydirs(fp, v->n, v->dirs, v->queue, s); }));
+    HIP_TRY(timed(c, PV_STAGE_TRACE, s,
+                  [&] { return launch_trace(vp, sv, fp, v->dirs, v->rays, v->hits, counts, v->tc, v->queue, sb, s); }));
+    if (split && fp.n_lights > 0) {
+        HIP_TRY(timed(c, PV_STAGE_SHADOW, s, [&] { return launch_shadow(sv, sb, v->tc, counts, s); }));
+        HIP_TRY(timed(c, PV_STAGE_SHADE, s, [&] { return launch_shade(vp, sv, fp, v->dirs, v->rays, sb, s); }));
+    }
+    return PV_OK;
+}
+
 extern "C" pv_status pv_update_probes(pv_volume *v, const pv_frame *f, void *stream) {
     if (!v) return fail(PV_ERR_ARG, "volume is NULL");
     if (!v->scene) return fail(PV_ERR_STATE, "no scene set on the volume");
@@ -583,9 +624,7 @@ extern "C" pv_status pv_update_probes(pv_volume *v, const pv_frame *f, void *str
     const SceneView sv = scene_view(v->scene);
     const int fp16 = v->desc.format == PV_MAP_FP16;
     const float h = effective_h(v);
-    HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s, [&] { return launch_raydirs(fp, v->n, v->dirs, v->queue, s); }));
-    HIP_TRY(timed(c, PV_STAGE_TRACE, s,
-                  [&] { return launch_trace(vp, sv, fp, v->dirs, v->rays, v->hits, nullptr, v->tc, v->queue, s); }));
+    PV_TRY(enqueue_trace(v, fp, sv, nullptr, s));
     HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend(vp, v->dirs, v->rays, v->irr, v->vis, fp16, h, s); }));
     PV_TRY(note_scene_use(v->scene, s));
     v->frame++;
@@ -602,9 +641,11 @@ extern "C" pv_status pv_trace_counts(pv_volume *v, const pv_frame *f, uint64_t c
     if (!c->counts_dev) PV_TRY(dev_alloc(&c->counts_dev, 4 * sizeof(unsigned long long), "counters"));
     hipStream_t s = c->stream;
     HIP_TRY(launch_zero(c->counts_dev, 4 * sizeof(unsigned long long), s));
-    const VolumeParams vp = volume_params(v);
-    HIP_TRY(launch_raydirs(fp, v->n, v->dirs, v->queue, s));
-    HIP_TRY(launch_trace(vp, scene_view(v->scene), fp, v->dirs, v->rays, v->hits, c->counts_dev, v->tc, v->queue, s));
+    const bool timing = c->timing;
+    c->timing = false;
+    const pv_status st = enqueue_trace(v, fp, scene_view(v->scene), c->counts_dev, s);
+    c->timing = timing;
+    PV_TRY(st);
     PV_TRY(note_scene_use(v->scene, s));
     unsigned long long host[4];
     HIP_TRY(hipMemcpyAsync(host, c->counts_dev, sizeof(host), hipMemcpyDeviceToHost, s));
@@ -634,12 +675,14 @@ extern "C" pv_status pv_volume_set_trace_config(pv_volume *v, const pv_trace_con
     if (c->persistent != 0 && c->persistent != 1) return fail(PV_ERR_ARG, "persistent must be 0 or 1");
     if (c->top_nodes != 0 && c->top_nodes != 21 && c->top_nodes != 85) return fail(PV_ERR_ARG, "top_nodes must be 0, 21 or 85");
     if (c->block_threads != 128 && c->block_threads != 256) return fail(PV_ERR_ARG, "block_threads must be 128 or 256");
+    if (c->split_shadows != 0 && c->split_shadows != 1) return fail(PV_ERR_ARG, "split_shadows must be 0 or 1");
     v->tc.bx = c->brick[0];
     v->tc.by = c->brick[1];
     v->tc.bz = c->brick[2];
     v->tc.persistent = c->persistent;
     v->tc.top_nodes = c->top_nodes;
     v->tc.block = c->block_threads;
+    v->tc.split_shadows = c->split_shadows;
     return PV_OK;
 }
 
@@ -651,6 +694,7 @@ extern "C" pv_status pv_volume_get_trace_config(pv_volume *v, pv_trace_config *c
     c->persistent = v->tc.persistent;
     c->top_nodes = v->tc.top_nodes;
     c->block_threads = v->tc.block;
+    c->split_shadows = v->tc.split_shadows;
     return PV_OK;
 }
 

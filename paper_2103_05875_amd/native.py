@@ -34,7 +34,7 @@ EXPORTED_SYMBOLS = [
     "pv_client_read_state", "pv_client_set_state", "pv_volume_set_trace_config", "pv_volume_get_trace_config",
 ]
 
-STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched"]
+STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched", "shadow", "shade"]
 
 
 class NativeError(RuntimeError):
@@ -66,7 +66,7 @@ class SceneDesc(ctypes.Structure):
 
 class TraceConfig(ctypes.Structure):
     _fields_ = [("brick", ctypes.c_int * 3), ("persistent", ctypes.c_int), ("top_nodes", ctypes.c_int),
-                ("block_threads", ctypes.c_int)]
+                ("block_threads", ctypes.c_int), ("split_shadows", ctypes.c_int)]
 
 
 class Frame(ctypes.Structure):
@@ -148,12 +148,13 @@ def _check(st: int):
 
 
 def _stream_handle(stream) -> Optional[int]:
-    """None -> the library's stream; torch.cuda.Stream or raw int accepted."""
+    """None or 0 -> HIP's default stream; a torch.cuda.Stream or a raw
+    hipStream_t value is passed through."""
     if stream is None:
         return None
     if isinstance(stream, int):
-        return stream
-    return int(stream.cuda_stream)
+        return stream or None
+    return int(stream.cuda_stream) or None
 
 
 # --------------------------------------------------------------------------
@@ -353,19 +354,21 @@ class Volume:
         _check(lib().pv_update_probes(self.h, ctypes.byref(f), _stream_handle(stream)))
         del keep
 
-    def set_trace_config(self, brick=(4, 4, 4), persistent=False, top_nodes=0, block_threads=128):
+    def set_trace_config(self, brick=(4, 4, 4), persistent=False, top_nodes=0, block_threads=128,
+                         split_shadows=False):
         c = TraceConfig()
         c.brick[:] = [int(b) for b in brick]
         c.persistent = 1 if persistent else 0
         c.top_nodes = int(top_nodes)
         c.block_threads = int(block_threads)
+        c.split_shadows = 1 if split_shadows else 0
         _check(lib().pv_volume_set_trace_config(self.h, ctypes.byref(c)))
 
     def get_trace_config(self) -> dict:
         c = TraceConfig()
         _check(lib().pv_volume_get_trace_config(self.h, ctypes.byref(c)))
         return {"brick": tuple(c.brick), "persistent": bool(c.persistent), "top_nodes": c.top_nodes,
-                "block_threads": c.block_threads}
+                "block_threads": c.block_threads, "split_shadows": bool(c.split_shadows)}
 
     def trace_counts(self, rotation, lights=None):
         f, keep = make_frame(rotation, lights)

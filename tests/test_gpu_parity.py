@@ -467,3 +467,28 @@ def test_served_results_equal_alone_results(ps, ctx, O):
     _say(f"  evictions {srv.evictions}, largest batch {max(r.batch_size for r in served)}, "
          f"latency {serve.latency_stats(served)}")
     scene.close()
+
+
+def test_trace_launch_shapes_are_bit_identical(ps, ctx, O):
+    """Every trace launch shape the autotuner may pick (brick, persistent
+    queues, LDS-staged top nodes, block size) gives the same bits."""
+    from paper_2103_05875_amd import autotune
+    _say("trace launch shapes: identical bits")
+    scene = ps.Scene.from_synth(ctx, synth.box_city(n_tris=12000, extent=32.0))
+    cfg = synth.VolumeConfig(7, 5, 9, (2.0, 0.25, 2.0), (4.0, 1.5, 3.5), 96, fp16=True, max_distance=6.0,
+                             sky=(0.1, 0.15, 0.25))
+    ref = None
+    for c in autotune.candidates()[::7] + [autotune.candidates()[-1]]:
+        v = ps.Volume(ctx, cfg, keep_hits=True)
+        v.set_scene(scene)
+        v.set_trace_config(c["brick"], c["persistent"], c["top_nodes"], c["block_threads"], c["split_shadows"])
+        for f in range(2):
+            v.update_probes(synth.rotation(77, f))
+        irr, vis, _ = v.read_maps()
+        rays, hits, _ = v.read_rays()
+        got = (irr.tobytes(), vis.tobytes(), rays.tobytes(), hits.tobytes())
+        if ref is None:
+            ref = got
+        assert got == ref, f"launch shape {c} differs"
+        v.close()
+    scene.close()
