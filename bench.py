@@ -47,9 +47,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--legs", default="batched,served,encode",
+    ap.add_argument("--legs", default="batched,served,served_below_capacity,served_tight_memory,encode",
                     help="extra workloads reported in the same line (comma list, or 'none')")
     ap.add_argument("--served-seconds", type=float, default=1.0)
+    ap.add_argument("--served-low-rate", type=float, default=300.0,
+                    help="arrival rate of the second served run, below the measured capacity")
+    ap.add_argument("--tune-cache", default=None, help="autotune cache file (tuned once, then reused)")
     ap.add_argument("--encode-frames", type=int, default=120)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default trace launch shape")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -143,7 +146,7 @@ def leg_batched(ps, torch, reps: int):
     return out
 
 
-def leg_served(ps, duration_s: float):
+def leg_served(ps, duration_s: float, rate_hz: float = 2000.0, budget_frac: float = 1.0, with_plain: bool = True):
     """Served workload: 64 clients (probes log-uniform 512-16384, rays from
     {64,128,256}) over one shared 200k-triangle scene, Poisson requests at
     2000/s, continuous batching with HBM admission; against the same trace
@@ -152,7 +155,7 @@ def leg_served(ps, duration_s: float):
     from paper_2103_05875_amd import serve
     cfgs = synth.served_clients(64, seed=30)
     scene_syn = synth.box_field(200_000, seed=31)
-    arrivals = synth.poisson_arrivals(2000.0, duration_s, len(cfgs), seed=30)
+    arrivals = synth.poisson_arrivals(rate_hz, duration_s, len(cfgs), seed=30)
     path = synth.light_path(12, 240)
 
     def make():
@@ -167,24 +170,25 @@ def leg_served(ps, duration_s: float):
     ctx = ps.Context(0)
     scene = ps.Scene.from_synth(ctx, scene_syn)
     total_fp = sum(ps.volume_footprint(c) + ps.client_footprint(c) for c in cfgs)
-    budget = int(0.75 * total_fp)
+    budget = int(budget_frac * total_fp) + (1 << 20)
     srv = serve.Server(ctx, scene, cfgs, hbm_budget=budget, n_streams=3, max_batch=32)
     t0 = time.perf_counter()
     served = srv.run(make(), timeout_s=120.0)
     span = max(r.done for r in served)
     srv.close()
-    plain = serve.serve_plain(ctx, scene, cfgs, make(), timeout_s=240.0)
-    span_p = max(r.done for r in plain)
+    plain = serve.serve_plain(ctx, scene, cfgs, make(), timeout_s=240.0) if with_plain else None
+    span_p = max(r.done for r in plain) if plain else None
     probes = sum(cfgs[r.client].n_probes for r in served)
     rays = sum(cfgs[r.client].n_probes * cfgs[r.client].rays_per_probe for r in served)
-    same = all(a.packet == b.packet for a, b in zip(sorted(served, key=lambda r: r.arrival),
-                                                     sorted(plain, key=lambda r: r.arrival)))
-    out = {"clients": len(cfgs), "requests": len(served), "arrival_rate_hz": 2000.0, "duration_s": duration_s,
+    same = plain is None or all(a.packet == b.packet for a, b in zip(sorted(served, key=lambda r: r.arrival),
+                                                                     sorted(plain, key=lambda r: r.arrival)))
+    out = {"clients": len(cfgs), "requests": len(served), "arrival_rate_hz": rate_hz, "duration_s": duration_s,
            "offered_probes_per_s": probes / duration_s, "hbm_budget_bytes": budget, "footprint_all_bytes": total_fp,
            "served": dict(serve.latency_stats(served), probes_per_s=probes / span, probe_rays_per_s=rays / span,
                           mean_batch=float(np.mean([r.batch_size for r in served])),
                           evictions=srv.evictions, admissions=srv.admissions),
-           "plain": dict(serve.latency_stats(plain), probes_per_s=probes / span_p, probe_rays_per_s=rays / span_p),
+           "plain": None if plain is None else dict(serve.latency_stats(plain), probes_per_s=probes / span_p,
+                                                    probe_rays_per_s=rays / span_p),
            "packets_identical": bool(same)}
     scene.close()
     ctx.close()
@@ -233,7 +237,9 @@ def leg_encode(ps, torch, frames: int):
     kv = np.mean([c[1] for c in changed])
     pack_bytes = P * 1408 * 2 + (ki * 384 + kv * 1024) * 2 + P * 2
     upd_ms = (st["raydirs"][0] + st["trace"][0] + st["blend"][0]) / frames
+    per_kernel = {k: st[k][0] / max(st[k][1], 1) for k in ("pack_mask", "pack_scan", "pack_compact", "trace", "blend")}
     out = {"probes": P, "frames": frames, "round_trip_bit_exact": bool(ok), "mean_changed_irr": ki,
+           "kernel_ms": per_kernel,
            "mean_changed_vis": kv, "packet_bytes_per_frame": sent_bytes / frames,
            "Mbps_at_10Hz": sent_bytes / frames * 8 * 10 / 1e6,
            "update_ms": upd_ms, "probe_rays_per_s": P * cfg.rays_per_probe / (upd_ms / 1e3),
@@ -275,7 +281,7 @@ def main():
         from paper_2103_05875_amd import autotune
         scratch = ps.Volume(ctx, cfg)
         scratch.set_scene(sc)
-        tuned = autotune.tune(scratch, *frames[0], n_triangles=scene.n_triangles, cache=None)
+        tuned = autotune.tune(scratch, *frames[0], n_triangles=scene.n_triangles, cache=args.tune_cache)
         scratch.close()
         print(f"bench: autotuned trace launch {tuned['config']} ({tuned['ms']:.3f} ms)", file=sys.stderr, flush=True)
     vol = ps.Volume(ctx, cfg)
@@ -390,6 +396,9 @@ def main():
         h.close()
     runners = {"batched": lambda: leg_batched(ps, torch, reps=5),
                "served": lambda: leg_served(ps, args.served_seconds),
+               "served_below_capacity": lambda: leg_served(ps, 2.0, rate_hz=args.served_low_rate),
+               "served_tight_memory": lambda: leg_served(ps, 2.0, rate_hz=args.served_low_rate, budget_frac=0.6,
+                                                         with_plain=False),
                "encode": lambda: leg_encode(ps, torch, args.encode_frames)}
     for name in legs:
         print(f"bench: {name} leg", file=sys.stderr, flush=True)

@@ -85,7 +85,7 @@ __device__ __forceinline__ Ray make_ray(float3 o, float3 d) {
     float dx = fabsf(d.x) < 1e-20f ? copysignf(1e-20f, d.x) : d.x;
     float dy = fabsf(d.y) < 1e-20f ? copysignf(1e-20f, d.y) : d.y;
     float dz = fabsf(d.z) < 1e-20f ? copysignf(1e-20f, d.z) : d.z;
-    r.inv = make_float3(1.0f / dx, 1.0f / dy, 1.0f / dz);
+    r.inv = make_float3(__builtin_amdgcn_rcpf(dx), __builtin_amdgcn_rcpf(dy), __builtin_amdgcn_rcpf(dz));
     r.oinv = make_float3(o.x * r.inv.x, o.y * r.inv.y, o.z * r.inv.z);
     return r;
 }
@@ -641,9 +641,11 @@ struct BlendSmem {
     float2 sR[kBlendProbes][kBlendChunk];
 };
 
-// One block: 4 probes; thread t owns visibility texel t of all 4 probes and
-// irradiance texel (t mod 64) of probe t/64.
-template <typename T, int S>
+// One block: Q probes (Q = 1, 2 or 4); thread t owns visibility texel t of
+// all Q probes and irradiance texel (t mod 64) of probe t/64 (threads with
+// t/64 >= Q skip the irradiance). Each sum runs over the rays in the same
+// order whatever Q is, so every Q gives identical bits.
+template <typename T, int S, int Q = kBlendProbes>
 __device__ void blend_group(const VolumeParams &vp, const float4 *dirs, const float4 *rays, T *irr, T *vis,
                             float h, int p0, BlendSmem &sm) {
     float4 *sd = sm.sd;
@@ -662,7 +664,7 @@ __device__ void blend_group(const VolumeParams &vp, const float4 *dirs, const fl
         const int m = min(kBlendChunk, n - j0);
         __syncthreads();
         for (int k = tid; k < m; k += kBlendBlock) sd[k] = dirs[j0 + k];
-        for (int k = tid; k < kBlendProbes * m; k += kBlendBlock) {
+        for (int k = tid; k < Q * m; k += kBlendBlock) {
             const int q = k / m, jj = k - q * m, p = p0 + q;
             const float4 rec = p < P ? rays[(size_t)p * n + j0 + jj] : make_float4(0.f, 0.f, 0.f, 0.f);
             sL[q][jj] = rec;
@@ -675,13 +677,13 @@ __device__ void blend_group(const VolumeParams &vp, const float4 *dirs, const fl
             const float v = pow_int<S>(cv, vp.vis_sharpness);
             sv += v;
 #pragma unroll
-            for (int q = 0; q < kBlendProbes; ++q) {
+            for (int q = 0; q < Q; ++q) {
                 const float2 rr = sR[q][jj];
                 a1[q] = fmaf(v, rr.x, a1[q]);
                 a2[q] = fmaf(v, rr.y, a2[q]);
             }
             const float ci = fmaxf(dot3(wi, d), 0.f);
-            const float4 L = sL[qi][jj];
+            const float4 L = sL[qi < Q ? qi : 0][jj];
             sw += ci;
             ar = fmaf(ci, L.x, ar);
             ag = fmaf(ci, L.y, ag);
@@ -694,7 +696,7 @@ __device__ void blend_group(const VolumeParams &vp, const float4 *dirs, const fl
         const float isv = 1.0f / sv;
         const int i = tid & 15, jr = tid >> 4;
 #pragma unroll
-        for (int q = 0; q < kBlendProbes; ++q) {
+        for (int q = 0; q < Q; ++q) {
             const int p = p0 + q;
             if (p >= P) break;
             T *base = vis + (size_t)p * 2 * 324;
@@ -709,7 +711,7 @@ __device__ void blend_group(const VolumeParams &vp, const float4 *dirs, const fl
     }
     // irradiance: 3 channels, 10x10 tiles
     const int p = p0 + qi;
-    if (p < P && sw > kWeightFloor) {
+    if (qi < Q && p < P && sw > kWeightFloor) {
         const float isw = 1.0f / sw;
         const int i = ti & 7, jr = ti >> 3;
         T *base = irr + (size_t)p * 3 * 100;
@@ -723,13 +725,13 @@ __device__ void blend_group(const VolumeParams &vp, const float4 *dirs, const fl
     }
 }
 
-template <typename T, int S>
+template <typename T, int S, int Q>
 __global__ __launch_bounds__(kBlendBlock) void k_blend(VolumeParams vp, const float4 *dirs, const float4 *rays,
                                                       T *irr, T *vis, float h) {
     __shared__ BlendSmem sm;
-    const int p0 = xcd_logical_block() * kBlendProbes;
+    const int p0 = xcd_logical_block() * Q;
     if (p0 >= vp.P) return;
-    blend_group<T, S>(vp, dirs, rays, irr, vis, h, p0, sm);
+    blend_group<T, S, Q>(vp, dirs, rays, irr, vis, h, p0, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1008,17 +1010,26 @@ __global__ __launch_bounds__(kScanBlock) void k_pack_scan(PackBuffers b, int P, 
     __shared__ int sh_a[kScanBlock / 64], sh_m[kScanBlock / 64];
     __shared__ uint32_t shu[kScanBlock / 64];
     const int tid = threadIdx.x;
-    const int per = (P + kScanBlock - 1) / kScanBlock;
+    // per-thread ranges of a multiple of 16 probes, read as 16-byte vectors
+    // (mask arrays are padded to 65,536 zero bytes)
+    const int per = 16 * ((P + kScanBlock * 16 - 1) / (kScanBlock * 16));
     const int lo = min(P, tid * per), hi = min(P, lo + per);
     int ki = 0, kv = 0, last_i = -1, last_v = -1;
-    for (int p = lo; p < hi; ++p) {
-        if (b.mask_irr[p]) {
-            ++ki;
-            last_i = p;
-        }
-        if (b.mask_vis[p]) {
-            ++kv;
-            last_v = p;
+    for (int p = lo; p < hi; p += 16) {
+        const uint4 mi = *reinterpret_cast<const uint4 *>(b.mask_irr + p);
+        const uint4 mv = *reinterpret_cast<const uint4 *>(b.mask_vis + p);
+        const uint32_t wi[4] = {mi.x, mi.y, mi.z, mi.w}, wv[4] = {mv.x, mv.y, mv.z, mv.w};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const bool ci = (wi[i >> 2] >> (8 * (i & 3))) & 0xffu, cv = (wv[i >> 2] >> (8 * (i & 3))) & 0xffu;
+            if (ci && p + i < hi) {
+                ++ki;
+                last_i = p + i;
+            }
+            if (cv && p + i < hi) {
+                ++kv;
+                last_v = p + i;
+            }
         }
     }
     // inclusive scans; exclusive values are the inclusive ones minus this thread's
@@ -1041,18 +1052,26 @@ __global__ __launch_bounds__(kScanBlock) void k_pack_scan(PackBuffers b, int P, 
     uint16_t *idx_i = reinterpret_cast<uint16_t *>(pk + 32);
     uint16_t *idx_v = idx_i + K_irr;
     int k_i = ai - ki, k_v = av - kv;
-    for (int p = lo; p < hi; ++p) {
-        if (b.mask_irr[p]) {
-            b.rank_irr[p] = k_i;
-            idx_i[k_i] = (uint16_t)(k_i == 0 ? p : p - prev_i);
-            prev_i = p;
-            ++k_i;
-        }
-        if (b.mask_vis[p]) {
-            b.rank_vis[p] = k_v;
-            idx_v[k_v] = (uint16_t)(k_v == 0 ? p : p - prev_v);
-            prev_v = p;
-            ++k_v;
+    for (int p0 = lo; p0 < hi; p0 += 16) {
+        const uint4 mi = *reinterpret_cast<const uint4 *>(b.mask_irr + p0);
+        const uint4 mv = *reinterpret_cast<const uint4 *>(b.mask_vis + p0);
+        const uint32_t wi[4] = {mi.x, mi.y, mi.z, mi.w}, wv[4] = {mv.x, mv.y, mv.z, mv.w};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int p = p0 + i;
+            if (p >= hi) break;
+            if ((wi[i >> 2] >> (8 * (i & 3))) & 0xffu) {
+                b.rank_irr[p] = k_i;
+                idx_i[k_i] = (uint16_t)(k_i == 0 ? p : p - prev_i);
+                prev_i = p;
+                ++k_i;
+            }
+            if ((wv[i >> 2] >> (8 * (i & 3))) & 0xffu) {
+                b.rank_vis[p] = k_v;
+                idx_v[k_v] = (uint16_t)(k_v == 0 ? p : p - prev_v);
+                prev_v = p;
+                ++k_v;
+            }
         }
     }
     const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
@@ -1261,26 +1280,31 @@ hipError_t launch_shade(const VolumeParams &vp, const SceneView &sv, const Frame
     return hipGetLastError();
 }
 
+template <typename T, int S>
+static hipError_t launch_blend_t(const VolumeParams &vp, const float4 *dirs, const float4 *rays, void *irr, void *vis,
+                                 float h, hipStream_t s) {
+    // probes per block: enough blocks to give every CU several
+    const int Q = vp.P >= 4096 ? 4 : (vp.P >= 2048 ? 2 : 1);
+#define PV_BLEND_Q(Qv)                                                                                      \
+    if (Q == Qv) {                                                                                         \
+        hipLaunchKernelGGL((k_blend<T, S, Qv>), dim3((vp.P + Qv - 1) / Qv), dim3(kBlendBlock), 0, s, vp, dirs, \
+                           rays, (T *)irr, (T *)vis, h);                                                   \
+        return hipGetLastError();                                                                          \
+    }
+    PV_BLEND_Q(4)
+    PV_BLEND_Q(2)
+    PV_BLEND_Q(1)
+#undef PV_BLEND_Q
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4 *rays, void *irr, void *vis,
                         int fp16, float h, hipStream_t s) {
-    const int blocks = (vp.P + kBlendProbes - 1) / kBlendProbes;
     const bool s50 = vp.vis_sharpness == 50;
-    if (fp16) {
-        if (s50)
-            hipLaunchKernelGGL((k_blend<__half, 50>), dim3(blocks), dim3(kBlendBlock), 0, s, vp, dirs, rays,
-                               (__half *)irr, (__half *)vis, h);
-        else
-            hipLaunchKernelGGL((k_blend<__half, 0>), dim3(blocks), dim3(kBlendBlock), 0, s, vp, dirs, rays,
-                               (__half *)irr, (__half *)vis, h);
-    } else {
-        if (s50)
-            hipLaunchKernelGGL((k_blend<float, 50>), dim3(blocks), dim3(kBlendBlock), 0, s, vp, dirs, rays,
-                               (float *)irr, (float *)vis, h);
-        else
-            hipLaunchKernelGGL((k_blend<float, 0>), dim3(blocks), dim3(kBlendBlock), 0, s, vp, dirs, rays,
-                               (float *)irr, (float *)vis, h);
-    }
-    return hipGetLastError();
+    if (fp16) return s50 ? launch_blend_t<__half, 50>(vp, dirs, rays, irr, vis, h, s)
+                         : launch_blend_t<__half, 0>(vp, dirs, rays, irr, vis, h, s);
+    return s50 ? launch_blend_t<float, 50>(vp, dirs, rays, irr, vis, h, s)
+               : launch_blend_t<float, 0>(vp, dirs, rays, irr, vis, h, s);
 }
 
 hipError_t launch_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, int total_blend,

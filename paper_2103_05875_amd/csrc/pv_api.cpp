@@ -855,7 +855,7 @@ extern "C" pv_status pv_client_footprint(const pv_volume_desc *d, uint64_t *byte
     PV_TRY(validate_desc(d));
     if (!bytes) return fail(PV_ERR_ARG, "bytes is NULL");
     const uint64_t P = (uint64_t)d->nx * d->ny * d->nz;
-    *bytes = P * (192 + 512) * 2 + P * 2 + P * 8 + packet_capacity((int)P);
+    *bytes = P * (192 + 512) * 2 + 2 * (PV_MAX_PROBES + 16) + P * 8 + packet_capacity((int)P);
     return PV_OK;
 }
 
@@ -883,8 +883,10 @@ extern "C" pv_status pv_client_create(pv_volume *v, uint32_t id, pv_client **out
     c->packet_cap = packet_capacity(P);
     pv_status st = dev_alloc(&c->ref_irr, (size_t)P * 192 * 2, "irradiance reference");
     if (st == PV_OK) st = dev_alloc(&c->ref_vis, (size_t)P * 512 * 2, "visibility reference");
-    if (st == PV_OK) st = dev_alloc(&c->mask_irr, (size_t)P, "mask");
-    if (st == PV_OK) st = dev_alloc(&c->mask_vis, (size_t)P, "mask");
+    // masks padded to the index limit and zeroed: the scan reads them in
+    // 16-byte vectors past P
+    if (st == PV_OK) st = dev_alloc(&c->mask_irr, (size_t)PV_MAX_PROBES + 16, "mask");
+    if (st == PV_OK) st = dev_alloc(&c->mask_vis, (size_t)PV_MAX_PROBES + 16, "mask");
     if (st == PV_OK) st = dev_alloc(&c->rank_irr, (size_t)P * 4, "ranks");
     if (st == PV_OK) st = dev_alloc(&c->rank_vis, (size_t)P * 4, "ranks");
     if (st == PV_OK) st = dev_alloc(&c->packet, c->packet_cap, "packet");
@@ -892,6 +894,8 @@ extern "C" pv_status pv_client_create(pv_volume *v, uint32_t id, pv_client **out
     hipStream_t s = v->ctx->stream;
     if (st == PV_OK && (launch_zero(c->ref_irr, (size_t)P * 192 * 2, s) != hipSuccess ||
                         launch_zero(c->ref_vis, (size_t)P * 512 * 2, s) != hipSuccess ||
+                        launch_zero(c->mask_irr, (size_t)PV_MAX_PROBES + 16, s) != hipSuccess ||
+                        launch_zero(c->mask_vis, (size_t)PV_MAX_PROBES + 16, s) != hipSuccess ||
                         launch_zero(c->packet, 32, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess))
         st = fail(PV_ERR_DEVICE, "client initialisation");
     if (st != PV_OK) {

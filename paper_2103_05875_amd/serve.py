@@ -52,7 +52,8 @@ class _ClientSlot:
 
 class Server:
     def __init__(self, ctx: native.Context, scene: native.Scene, configs: List, hbm_budget: int,
-                 n_streams: int = 3, max_batch: int = 32, tau_irr: float = 0.0, tau_vis: float = 0.0):
+                 n_streams: int = 3, max_batch: int = 32, tau_irr: float = 0.0, tau_vis: float = 0.0,
+                 max_wait_s: float = 0.05):
         import torch
         self.ctx = ctx
         self.scene = scene
@@ -70,6 +71,9 @@ class Server:
         self.inflight: List[Optional[tuple]] = [None] * n_streams
         self.evictions = 0
         self.admissions = 0
+        # a request whose client is not resident waits at most this long before
+        # it may evict others; until then resident clients go first
+        self.max_wait_s = max_wait_s
 
     # -------------------------------------------------------------- memory
     def _make_resident(self, slot: _ClientSlot, now: float) -> bool:
@@ -160,13 +164,18 @@ class Server:
             for k in range(len(self.streams)):
                 if self.inflight[k] is not None:
                     continue
-                # oldest head-of-queue request first, one per client
+                # one head-of-queue request per client: resident clients and
+                # requests past their wait bound first, then by age
                 heads = [s for s in self.slots.values() if s.queue and not s.busy]
-                heads.sort(key=lambda s: s.queue[0].arrival)
+                heads.sort(key=lambda s: (not (s.volume is not None or now - s.queue[0].arrival > self.max_wait_s),
+                                          s.queue[0].arrival))
                 batch = []
                 for s in heads:
                     if len(batch) >= self.max_batch:
                         break
+                    if s.volume is None and now - s.queue[0].arrival <= self.max_wait_s and \
+                            self.used + s.footprint > self.budget:
+                        continue              # would evict: wait for its bound or for free memory
                     if self._make_resident(s, now):
                         batch.append(s.queue.popleft())
                         s.busy = True          # reserved: not evictable while the batch forms
