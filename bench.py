@@ -123,23 +123,31 @@ def leg_batched(ps, torch, reps: int):
         else:
             ps.update_probes_batched(batched, rots, stream=stream)
 
+    graph = ps.BatchGraph(batched)
+
+    def run_graph(f):
+        graph.launch([synth.rotation(20 + i, f) for i in range(len(specs))], stream=stream)
+
     out = {}
-    for which in ("plain", "batched"):
+    for which in ("plain", "batched", "graph"):
+        step = run_graph if which == "graph" else (lambda f, w=which: run(f, w))
         for f in range(2):
-            run(f, which)
+            step(f)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for f in range(2, 2 + reps):
-            run(f, which)
+            step(f)
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         out[which] = {"ms_per_frame": ms, "probe_rays_per_s": rays / (ms / 1e3), "probes_per_s": probes / (ms / 1e3)}
+    graph.close()
     same = all(np.array_equal(a.read_maps()[0], b.read_maps()[0]) for a, b in zip(plain, batched))
     assert ctx.check() == 0
     out.update({"volumes": len(specs), "probes": probes, "probe_rays": rays, "bit_identical_to_plain": bool(same),
-                "speedup": out["plain"]["ms_per_frame"] / out["batched"]["ms_per_frame"]})
+                "speedup": out["plain"]["ms_per_frame"] / out["batched"]["ms_per_frame"],
+                "graph_speedup": out["plain"]["ms_per_frame"] / out["graph"]["ms_per_frame"]})
     for h in plain + batched + scenes:
         h.close()
     ctx.close()

@@ -172,6 +172,21 @@ pv_status pv_update_probes(pv_volume *vol, const pv_frame *frame, void *stream);
 pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_frame *frames, int n, void *stream);
 
 /*
+ * A captured HIP graph of the batched update of a fixed set of volumes:
+ * a copy node refreshing the device-resident descriptors and frame
+ * parameters from pinned host memory, a zero-fill kernel for the work-queue
+ * counters, the ray-direction kernel and the persistent batched kernel.
+ * pv_batch_graph_launch writes the frames into the pinned buffer (waiting for
+ * the graph's previous launch to finish first) and launches the graph on
+ * 'stream'; results equal pv_update_probes_batched. The volumes must outlive
+ * the graph.
+ */
+typedef struct pv_batch_graph pv_batch_graph;
+pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_batch_graph **out);
+pv_status pv_batch_graph_launch(pv_batch_graph *graph, const pv_frame *frames, void *stream);
+pv_status pv_batch_graph_destroy(pv_batch_graph *graph);
+
+/*
  * Blend + hysteresis + guard bands from externally supplied ray records
  * (device pointer, [P][rays_per_probe] x float4 {L.r, L.g, L.b, distance}),
  * with the directions of 'frame'. Advances the frame counter like an update.

@@ -14,6 +14,6 @@ from __future__ import annotations
 
 from .native import (  # noqa: F401
     PV_FIRST_FRAME_NO_HISTORY, PV_KEEP_HITS, PV_MAP_FP16, PV_MAP_FP32,
-    Client, Context, NativeError, Scene, Volume, build, lib, lib_path, update_probes_batched,
+    BatchGraph, Client, Context, NativeError, Scene, Volume, build, lib, lib_path, update_probes_batched,
     volume_footprint, client_footprint, EXPORTED_SYMBOLS,
 )

@@ -765,31 +765,35 @@ static pv_status ensure_slot(pv_ctx *c, BatchSlot &b, int n) {
     return PV_OK;
 }
 
-extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_frame *frames, int n, void *stream) {
-    if (!vols || !frames || n < 1) return fail(PV_ERR_ARG, "need at least one volume and frame");
-    pv_ctx *c = vols[0] ? vols[0]->ctx : nullptr;
-    if (!c) return fail(PV_ERR_ARG, "volume 0 is NULL");
-    for (int i = 0; i < n; ++i) {
-        if (!vols[i]) return fail(PV_ERR_ARG, "volume " + std::to_string(i) + " is NULL");
-        if (vols[i]->ctx != c) return fail(PV_ERR_ARG, "volumes belong to different contexts");
-        if (!vols[i]->scene) return fail(PV_ERR_STATE, "volume " + std::to_string(i) + " has no scene");
-        for (int k = 0; k < i; ++k)
-            if (vols[k] == vols[i]) return fail(PV_ERR_ARG, "a volume appears twice in one batch");
-    }
-    HIP_TRY(hipSetDevice(c->device));
-    hipStream_t s = pick(c, stream);
-    BatchSlot &slot = c->slots[c->slot_next];
-    c->slot_next = (c->slot_next + 1) % pv_ctx::kRing;
-    HIP_TRY(hipEventSynchronize(slot.done));  // the slot's previous launch has finished
-    PV_TRY(ensure_slot(c, slot, n));
+// ---------------------------------------------------------------------------
+// captured batched frame
+// ---------------------------------------------------------------------------
+struct pv_batch_graph {
+    pv_ctx *ctx = nullptr;
+    std::vector<pv_volume *> vols;
+    BatchSlot slot;           // device descriptors + pinned staging owned by the graph
+    size_t o_b = 0, o_f = 0, o_n = 0, o_d = 0, bytes = 0;
+    int waves = 0, blend = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool launched = false;
+};
+
+// Fills the pinned staging of a batch: descriptors, frames, ray counts and
+// direction pointers; returns the wave and blend-group totals.
+static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int n, char *h, size_t *offs, int &waves,
+                            int &blend) {
     std::vector<BatchVolume> bv(n);
     std::vector<FrameParams> fps(n);
+    std::memset(fps.data(), 0, sizeof(FrameParams) * n);
     std::vector<int> ns(n);
     std::vector<float4 *> dps(n);
-    int waves = 0, blend = 0;
+    waves = 0;
+    blend = 0;
     for (int i = 0; i < n; ++i) {
         pv_volume *v = vols[i];
-        PV_TRY(frame_params(&frames[i], v->scene, fps[i]));
+        if (frames) PV_TRY(frame_params(&frames[i], v->scene, fps[i]));
         BatchVolume &b = bv[i];
         b.vp = volume_params(v);
         b.sv = scene_view(v->scene);
@@ -804,8 +808,7 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
         b.bricks_y = (v->desc.ny + 3) / 4;
         b.bricks_z = (v->desc.nz + 3) / 4;
         b.n_waves = b.bricks_x * b.bricks_y * b.bricks_z * v->n;
-        // trace items hold 4 waves; each volume starts on an item boundary
-        waves = (waves + 3) / 4 * 4;
+        waves = (waves + 3) / 4 * 4;  // trace items hold 4 waves; each volume starts on an item boundary
         b.first_wave = waves;
         waves += b.n_waves;
         b.n_blend = (v->P + 3) / 4;
@@ -814,8 +817,6 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
         ns[i] = v->n;
         dps[i] = v->dirs;
     }
-    // stage descriptors through the slot's pinned memory
-    char *h = (char *)slot.stage_host;
     size_t off = 0;
     auto put = [&](const void *src, size_t bytes) {
         std::memcpy(h + off, src, bytes);
@@ -823,14 +824,47 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
         off += (bytes + 15) / 16 * 16;
         return o;
     };
-    const size_t o_b = put(bv.data(), sizeof(BatchVolume) * n);
-    const size_t o_f = put(fps.data(), sizeof(FrameParams) * n);
-    const size_t o_n = put(ns.data(), sizeof(int) * n);
-    const size_t o_d = put(dps.data(), sizeof(float4 *) * n);
-    HIP_TRY(hipMemcpyAsync(slot.batch_dev, h + o_b, sizeof(BatchVolume) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(slot.frames_dev, h + o_f, sizeof(FrameParams) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(slot.ns_dev, h + o_n, sizeof(int) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(slot.dirs_ptrs_dev, h + o_d, sizeof(float4 *) * n, hipMemcpyHostToDevice, s));
+    offs[0] = put(bv.data(), sizeof(BatchVolume) * n);
+    offs[1] = put(fps.data(), sizeof(FrameParams) * n);  // zeros when no frames are given yet
+    offs[2] = put(ns.data(), sizeof(int) * n);
+    offs[3] = put(dps.data(), sizeof(float4 *) * n);
+    offs[4] = off;
+    return PV_OK;
+}
+
+static pv_status check_batch(pv_volume *const *vols, int n, pv_ctx **ctx) {
+    if (!vols || n < 1) return fail(PV_ERR_ARG, "need at least one volume");
+    pv_ctx *c = vols[0] ? vols[0]->ctx : nullptr;
+    if (!c) return fail(PV_ERR_ARG, "volume 0 is NULL");
+    for (int i = 0; i < n; ++i) {
+        if (!vols[i]) return fail(PV_ERR_ARG, "volume " + std::to_string(i) + " is NULL");
+        if (vols[i]->ctx != c) return fail(PV_ERR_ARG, "volumes belong to different contexts");
+        if (!vols[i]->scene) return fail(PV_ERR_STATE, "volume " + std::to_string(i) + " has no scene");
+        for (int k = 0; k < i; ++k)
+            if (vols[k] == vols[i]) return fail(PV_ERR_ARG, "a volume appears twice in one batch");
+    }
+    *ctx = c;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_frame *frames, int n, void *stream) {
+    if (!frames) return fail(PV_ERR_ARG, "frames is NULL");
+    pv_ctx *c = nullptr;
+    PV_TRY(check_batch(vols, n, &c));
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = pick(c, stream);
+    BatchSlot &slot = c->slots[c->slot_next];
+    c->slot_next = (c->slot_next + 1) % pv_ctx::kRing;
+    HIP_TRY(hipEventSynchronize(slot.done));  // the slot's previous launch has finished
+    PV_TRY(ensure_slot(c, slot, n));
+    size_t offs[5];
+    int waves, blend;
+    char *h = (char *)slot.stage_host;
+    PV_TRY(fill_batch(vols, frames, n, h, offs, waves, blend));
+    HIP_TRY(hipMemcpyAsync(slot.batch_dev, h + offs[0], sizeof(BatchVolume) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(slot.frames_dev, h + offs[1], sizeof(FrameParams) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(slot.ns_dev, h + offs[2], sizeof(int) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(slot.dirs_ptrs_dev, h + offs[3], sizeof(float4 *) * n, hipMemcpyHostToDevice, s));
     // queue counter and per-volume done counters start at zero (status word kept)
     HIP_TRY(launch_zero(slot.counters_dev, sizeof(int), s));
     HIP_TRY(launch_zero(slot.counters_dev + 2, sizeof(int) * n, s));
@@ -845,6 +879,108 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
         PV_TRY(note_scene_use(vols[i]->scene, s));
         vols[i]->frame++;
     }
+    return PV_OK;
+}
+
+static void free_graph(pv_batch_graph *g) {
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    if (g->done) hipEventDestroy(g->done);
+    BatchSlot &b = g->slot;
+    hipFree(b.batch_dev);
+    hipFree(b.frames_dev);
+    hipFree(b.ns_dev);
+    hipFree(b.dirs_ptrs_dev);
+    hipFree(b.counters_dev);
+    if (b.stage_host) hipHostFree(b.stage_host);
+    delete g;
+}
+
+extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_batch_graph **out) {
+    if (!out) return fail(PV_ERR_ARG, "out is NULL");
+    pv_ctx *c = nullptr;
+    PV_TRY(check_batch(vols, n, &c));
+    HIP_TRY(hipSetDevice(c->device));
+    pv_batch_graph *g = new pv_batch_graph();
+    g->ctx = c;
+    g->vols.assign(vols, vols + n);
+    pv_status st = ensure_slot(c, g->slot, n);
+    if (st == PV_OK && hipEventCreateWithFlags(&g->done, hipEventDisableTiming) != hipSuccess)
+        st = fail(PV_ERR_DEVICE, "event");
+    size_t offs[5];
+    if (st == PV_OK) st = fill_batch(vols, nullptr, n, (char *)g->slot.stage_host, offs, g->waves, g->blend);
+    if (st != PV_OK) {
+        free_graph(g);
+        return st;
+    }
+    g->o_b = offs[0];
+    g->o_f = offs[1];
+    g->o_n = offs[2];
+    g->o_d = offs[3];
+    g->bytes = offs[4];
+    // capture on a private stream: copy node, zero fill, ray directions, batched kernel
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    BatchSlot &b = g->slot;
+    char *h = (char *)b.stage_host;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.batch_dev, h + g->o_b, sizeof(BatchVolume) * n, hipMemcpyHostToDevice, cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.frames_dev, h + g->o_f, sizeof(FrameParams) * n, hipMemcpyHostToDevice, cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.ns_dev, h + g->o_n, sizeof(int) * n, hipMemcpyHostToDevice, cs);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.dirs_ptrs_dev, h + g->o_d, sizeof(float4 *) * n, hipMemcpyHostToDevice, cs);
+    if (e == hipSuccess) e = launch_zero(b.counters_dev, sizeof(int), cs);
+    if (e == hipSuccess) e = launch_zero(b.counters_dev + 2, sizeof(int) * n, cs);
+    if (e == hipSuccess) e = launch_raydirs_batched(b.frames_dev, b.ns_dev, b.dirs_ptrs_dev, n, cs);
+    if (e == hipSuccess)
+        e = launch_batched(b.batch_dev, n, g->waves, g->blend, b.frames_dev, b.counters_dev, b.counters_dev + 2,
+                           b.counters_dev + 1, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) {
+        g->graph = graph;
+        e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    } else if (graph) {
+        hipGraphDestroy(graph);
+    }
+    hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        free_graph(g);
+        return fail(PV_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_batch_graph_launch(pv_batch_graph *g, const pv_frame *frames, void *stream) {
+    if (!g || !frames) return fail(PV_ERR_ARG, "NULL argument");
+    pv_ctx *c = g->ctx;
+    HIP_TRY(hipSetDevice(c->device));
+    const int n = (int)g->vols.size();
+    for (int i = 0; i < n; ++i)
+        if (!g->vols[i]->scene) return fail(PV_ERR_STATE, "a volume of the graph has no scene");
+    // the copy node reads the pinned buffer when the graph runs: the previous
+    // launch must have finished before it is rewritten
+    if (g->launched) HIP_TRY(hipEventSynchronize(g->done));
+    size_t offs[5];
+    int waves, blend;
+    PV_TRY(fill_batch(g->vols.data(), frames, n, (char *)g->slot.stage_host, offs, waves, blend));
+    hipStream_t s = pick(c, stream);
+    HIP_TRY(timed(c, PV_STAGE_BATCHED, s, [&] { return hipGraphLaunch(g->exec, s); }));
+    HIP_TRY(hipEventRecord(g->done, s));
+    g->launched = true;
+    for (int i = 0; i < n; ++i) {
+        PV_TRY(note_scene_use(g->vols[i]->scene, s));
+        g->vols[i]->frame++;
+    }
+    return PV_OK;
+}
+
+extern "C" pv_status pv_batch_graph_destroy(pv_batch_graph *g) {
+    if (!g) return PV_OK;
+    hipSetDevice(g->ctx->device);
+    if (g->launched) hipEventSynchronize(g->done);
+    free_graph(g);
     return PV_OK;
 }
 

@@ -32,6 +32,7 @@ EXPORTED_SYMBOLS = [
     "pv_pack_delta", "pv_packet_device", "pv_packet_download", "pv_get_masks", "pv_sync",
     "pv_ctx_check", "pv_trace_counts", "pv_ctx_set_timing", "pv_ctx_stage_times",
     "pv_client_read_state", "pv_client_set_state", "pv_volume_set_trace_config", "pv_volume_get_trace_config",
+    "pv_batch_graph_create", "pv_batch_graph_launch", "pv_batch_graph_destroy",
 ]
 
 STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched", "shadow", "shade"]
@@ -130,6 +131,9 @@ def lib():
         "pv_ctx_set_timing": ([vp, i32], i32),
         "pv_client_read_state": ([vp, vp, vp, P(u32)], i32),
         "pv_volume_set_trace_config": ([vp, P(TraceConfig)], i32),
+        "pv_batch_graph_create": ([P(vp), i32, P(vp)], i32),
+        "pv_batch_graph_launch": ([vp, P(Frame), vp], i32),
+        "pv_batch_graph_destroy": ([vp], i32),
         "pv_volume_get_trace_config": ([vp, P(TraceConfig)], i32),
         "pv_client_set_state": ([vp, vp, vp, u32], i32),
         "pv_ctx_stage_times": ([vp, P(ctypes.c_double), P(u64)], i32),
@@ -439,6 +443,38 @@ def update_probes_batched(volumes: Sequence[Volume], rotations, lights=None, str
         frames[i] = f
         keeps.append(keep)
     _check(lib().pv_update_probes_batched(arr, frames, n, _stream_handle(stream)))
+
+
+class BatchGraph:
+    """Captured HIP graph of the batched update of a fixed set of volumes."""
+
+    def __init__(self, volumes: Sequence[Volume]):
+        self.volumes = list(volumes)
+        arr = (ctypes.c_void_p * len(volumes))(*[v.h.value for v in volumes])
+        h = ctypes.c_void_p()
+        _check(lib().pv_batch_graph_create(arr, len(volumes), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self, rotations, lights=None, stream=None):
+        n = len(self.volumes)
+        frames = (Frame * n)()
+        keeps = []
+        for i in range(n):
+            f, keep = make_frame(rotations[i], None if lights is None else lights[i])
+            frames[i] = f
+            keeps.append(keep)
+        _check(lib().pv_batch_graph_launch(self.h, frames, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pv_batch_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Client:
