@@ -53,11 +53,94 @@ def parse():
     ap.add_argument("--served-low-rate", type=float, default=300.0,
                     help="arrival rate of the second served run, below the measured capacity")
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (tuned once, then reused)")
+    ap.add_argument("--retune", action="store_true", help="measure every launch shape, ignoring caches")
+    ap.add_argument("--trace-config", default=None,
+                    help="pin the trace launch shape: bx,by,bz,persistent,top_nodes,block_threads,split_shadows")
+    ap.add_argument("--counters", default=os.path.join(ROOT, "profiles", "k_trace_city_counters.txt"),
+                    help="HBM byte counters of the trace kernel (rocprofv3 --pmc), used for roofline.traffic "
+                         "when they were taken on the current kernel source and launch shape")
+    ap.add_argument("--write-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT"), default=None,
+                    help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, "
+                         "WRITE_SIZE) of this bench run with --calibrate-copy into the counters file")
     ap.add_argument("--encode-frames", type=int, default=120)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default trace launch shape")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (reference kernel for HBM byte counters)")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ("kernels.hip", "internal.h", "bvh.cpp")
+COPY_BYTES = 256 << 20             # the --calibrate-copy kernel reads and writes this many bytes
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2103_05875_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def config_string(c) -> str:
+    return ",".join(str(int(v)) for v in (*c["brick"], c["persistent"], c["top_nodes"], c["block_threads"],
+                                          c["split_shadows"]))
+
+
+def read_counters(path, trace_config):
+    """roofline.traffic from the committed counters file: HBM bytes per
+    trace launch, or None unless the file was made from the current kernel
+    sources with the same launch shape."""
+    try:
+        kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None, "no counters file"
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None, "kernel sources changed since the counters were taken"
+    if kv.get("trace_config") != config_string(trace_config):
+        return None, "counters were taken with another launch shape"
+    return float(kv["traffic_bytes_per_launch"]), path
+
+
+def write_counters(fetch_csv, write_csv, out, trace_config):
+    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the trace kernel by
+    what the same counters read for the 256 MiB device copy, and write the
+    counters file that read_counters() accepts."""
+    import csv
+
+    def load(path, counter):
+        rows = []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        return rows
+
+    res = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = load(path, counter)
+        copy = max(v for k, v in rows if "copyBuffer" in k or "copy" in k.lower())
+        trace = [v for k, v in rows if k.startswith("pv::k_trace<false") or k.startswith("void pv::k_trace<false")]
+        res[counter] = {"copy_kib": copy, "scale": COPY_BYTES / (copy * 1024.0),
+                        "trace_kib": sum(trace) / len(trace), "n": len(trace)}
+    fetch = res["FETCH_SIZE"]["trace_kib"] * 1024 * res["FETCH_SIZE"]["scale"]
+    write = res["WRITE_SIZE"]["trace_kib"] * 1024 * res["WRITE_SIZE"]["scale"]
+    with open(out, "w") as f:
+        f.write("# HBM traffic of the trace kernel (k_trace, uninstrumented) on the city workload\n")
+        f.write("# counters per dispatch from rocprofv3 --pmc, one counter per run; each scaled by what the\n")
+        f.write("# same counter reads for a 256 MiB device-to-device copy (reads and writes 268435456 bytes)\n")
+        for c, r in res.items():
+            f.write(f"{c.lower()}_copy_kib: {r['copy_kib']:.1f}\n")
+            f.write(f"{c.lower()}_scale: {r['scale']:.4f}\n")
+            f.write(f"{c.lower()}_trace_kib_mean: {r['trace_kib']:.1f}\n")
+            f.write(f"{c.lower()}_trace_dispatches: {r['n']}\n")
+        f.write(f"fetch_bytes_per_launch: {fetch:.0f}\n")
+        f.write(f"write_bytes_per_launch: {write:.0f}\n")
+        f.write(f"traffic_bytes_per_launch: {fetch + write:.0f}\n")
+        f.write(f"trace_config: {trace_config}\n")
+        f.write(f"source_sha256: {kernel_source_hash()}\n")
+    return fetch + write
 
 
 def cpu_baseline(cfg, scene, path, budget_s: float):
@@ -263,8 +346,14 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(the hot path has no cross-GPU exchange; see DESIGN.md for how it shards)", file=sys.stderr)
+              "(this build runs the hot path on a single GPU and has no cross-GPU exchange)", file=sys.stderr)
         sys.exit(2)
+    if args.write_counters:
+        if not args.trace_config:
+            sys.exit("--write-counters needs the --trace-config the counters were taken with")
+        t = write_counters(*args.write_counters, trace_config=args.trace_config)
+        print(f"trace kernel HBM traffic {t / 1e6:.2f} MB per launch -> {args.write_counters[2]}")
+        return
     import numpy as np
     import torch
 
@@ -286,13 +375,20 @@ def main():
     ctx = ps.Context(0)
     sc = ps.Scene.from_synth(ctx, scene)
     tuned = None
-    if not args.no_autotune:
+    if args.trace_config:
+        v = [int(x) for x in args.trace_config.split(",")]
+        tuned = {"config": {"brick": tuple(v[0:3]), "persistent": bool(v[3]), "top_nodes": v[4],
+                            "block_threads": v[5], "split_shadows": bool(v[6])},
+                 "ms": float("nan"), "tried": 0, "source": "pinned"}
+    elif not args.no_autotune:
         from paper_2103_05875_amd import autotune
         scratch = ps.Volume(ctx, cfg)
         scratch.set_scene(sc)
-        tuned = autotune.tune(scratch, *frames[0], n_triangles=scene.n_triangles, cache=args.tune_cache)
+        tuned = autotune.tune(scratch, *frames[0], n_triangles=scene.n_triangles, cache=args.tune_cache,
+                              force=args.retune)
         scratch.close()
-        print(f"bench: autotuned trace launch {tuned['config']} ({tuned['ms']:.3f} ms)", file=sys.stderr, flush=True)
+        print(f"bench: trace launch {tuned['config']} ({tuned['source']}, {tuned['ms']:.3f} ms)",
+              file=sys.stderr, flush=True)
     vol = ps.Volume(ctx, cfg)
     vol.set_scene(sc)
     if tuned:
@@ -356,6 +452,8 @@ def main():
     trace_s = (stage_ms["trace"] + stage_ms["shadow"] + stage_ms["shade"]) / 1e3
     achieved = flop_per_launch / trace_s if trace_s > 0 else 0.0
 
+    traffic, traffic_src = read_counters(args.counters, vol.get_trace_config())
+
     # HBM figures of the blend and pack kernels (algorithmic bytes)
     P, n = cfg.n_probes, cfg.rays_per_probe
     blend_bytes = P * (16 * n + (192 + 512) * 2 + (300 + 648) * 2)
@@ -383,11 +481,13 @@ def main():
                    "probes": P, "rays_per_probe": n, "triangles": scene.n_triangles},
         "probes_per_s": P * 1e3 / ms_per_step,
         "trace_config": vol.get_trace_config(),
-        "autotune": None if tuned is None else {"tried": tuned["tried"], "best_ms": tuned["ms"],
-                                                 "top5": tuned.get("ranking")},
+        "autotune": None if tuned is None else {"source": tuned["source"], "tried": tuned["tried"],
+                                                 "best_ms": tuned["ms"], "top5": tuned.get("ranking")},
         "stage_ms": stage_ms,
         "roofline": {"bound": "alu", "kernel": "k_trace", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
+                     "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
+                     "trace_ms": trace_s * 1e3,
                      "flop_per_launch": flop_per_launch, "node_visits_per_ray": node_visits / (K * rays),
                      "tri_tests_per_ray": tri_tests / (K * rays), "shadow_rays_per_ray": shadow / (K * rays)},
         "blend": {"ms": stage_ms["blend"], "hbm_GBps": blend_bytes / (stage_ms["blend"] / 1e3) / 1e9 if stage_ms["blend"] else None,

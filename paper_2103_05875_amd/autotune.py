@@ -4,9 +4,12 @@ Every launch shape computes bit-identical results; only speed differs. The
 tuner times each candidate (probe brick of a wavefront packet, persistent
 grid with per-XCD work queues or not, BVH nodes staged in LDS, block size)
 on the caller's own volume, scene and frame, with HIP events around the trace
-kernel (the library's stage timing), and keeps the fastest. Results are
+kernels (the library's stage timing), and keeps the fastest. Results are
 cached in a JSON file keyed by grid shape, rays per probe and scene size, so
-later volumes of the same shape reuse the choice without measuring.
+later volumes of the same shape reuse the choice without measuring. The
+package also ships a small table of launch shapes measured on MI355X for the
+workloads it is benchmarked on (``tuning_gfx950.json``, same keys); it is
+consulted after the caller's cache and before measuring.
 """
 from __future__ import annotations
 
@@ -22,11 +25,14 @@ BLOCKS = [128, 256]
 SPLIT = [False, True]
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "probestream", "autotune.json")
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
 
 
 def candidates() -> List[dict]:
+    # the split-shadow trace always runs one wave per packet: no persistent variant
     return [{"brick": b, "persistent": p, "top_nodes": t, "block_threads": w, "split_shadows": s}
-            for b, p, t, w, s in itertools.product(BRICKS, PERSISTENT, TOP_NODES, BLOCKS, SPLIT)]
+            for b, p, t, w, s in itertools.product(BRICKS, PERSISTENT, TOP_NODES, BLOCKS, SPLIT)
+            if not (p and s)]
 
 
 def _apply(volume, c):
@@ -56,19 +62,25 @@ def _save(path: str, data: Dict[str, dict]):
 
 
 def tune(volume, rotation, lights=None, n_triangles: int = 0, reps: int = 3,
-         cache: Optional[str] = DEFAULT_CACHE, force: bool = False, verbose: bool = False) -> dict:
+         cache: Optional[str] = DEFAULT_CACHE, force: bool = False, verbose: bool = False,
+         shipped: bool = True) -> dict:
     """Pick and set the fastest trace launch shape for ``volume``.
 
-    The volume's maps are updated by the trial runs (callers tune before
-    their real frames, or on a scratch volume of the same shape). Returns
-    {"config": ..., "ms": ..., "tried": n, "cached": bool}.
+    Looks the shape up in ``cache``, then (if ``shipped``) in the shipped
+    table, and measures every candidate only when neither has it or when
+    ``force`` is set. The volume's maps are updated by the trial runs
+    (callers tune before their real frames, or on a scratch volume of the
+    same shape). Returns {"config": ..., "ms": ..., "tried": n, "cached":
+    bool, "source": "cache" | "shipped" | "measured"}.
     """
     k = key(volume.cfg, n_triangles)
-    data = _load(cache) if cache else {}
-    if not force and k in data:
-        c = data[k]["config"]
-        _apply(volume, c)
-        return {"config": c, "ms": data[k]["ms"], "tried": 0, "cached": True}
+    if not force:
+        for source, path in (("cache", cache), ("shipped", SHIPPED if shipped else None)):
+            entry = _load(path).get(k) if path else None
+            if entry:
+                c = {**entry["config"], "brick": tuple(entry["config"]["brick"])}
+                _apply(volume, c)
+                return {"config": c, "ms": entry["ms"], "tried": 0, "cached": True, "source": source}
     ctx = volume.ctx
     ctx.set_timing(True)
     results = []
@@ -94,7 +106,8 @@ def tune(volume, rotation, lights=None, n_triangles: int = 0, reps: int = 3,
         data[k] = {"config": {**best, "brick": list(best["brick"])}, "ms": best_ms,
                    "default_ms": next(ms for ms, c in results if c["brick"] == (4, 4, 4) and not c["persistent"]
                                       and c["top_nodes"] == 0 and c["block_threads"] == 128
-                                      and not c["split_shadows"])}
+                                      and not c["split_shadows"]),
+                   "all": [[round(ms, 4), {**c, "brick": list(c["brick"])}] for ms, c in results]}
         _save(cache, data)
-    return {"config": best, "ms": best_ms, "tried": len(results), "cached": False,
+    return {"config": best, "ms": best_ms, "tried": len(results), "cached": False, "source": "measured",
             "ranking": [(round(ms, 4), c) for ms, c in results[:5]]}

@@ -333,6 +333,7 @@ struct Collapse {
     };
     std::vector<N4> tree;
     std::vector<GpuNode4> out;
+    std::vector<int> leaf_order;  // output triangle slot -> builder reference index
     Collapse(const std::vector<BNode> &b) : bn(b) {}
 
     // children of a 4-wide node: expand the largest inner child until 4
@@ -384,7 +385,9 @@ struct Collapse {
         return me;
     }
 
-    // nodes numbered breadth first, so the top levels are a prefix
+    // nodes numbered breadth first, so the top levels are a prefix; the
+    // triangles of a node's leaf children are stored back to back in slot
+    // order, so one node's leaf triangles span at most 4 * kLeafMax slots
     void emit(int root) {
         std::vector<int> order, index(tree.size(), -1);
         order.push_back(root);
@@ -401,8 +404,9 @@ struct Collapse {
                 const BNode &k = bn[t.kid_bnode[c]];
                 box[c] = k.box;
                 if (k.count > 0) {
-                    child[c] = k.first;
+                    child[c] = (int)leaf_order.size();
                     count[c] = k.count;
+                    for (int r = k.first; r < k.first + k.count; ++r) leaf_order.push_back(r);
                 } else {
                     child[c] = index[t.kid_n4[c]];
                 }
@@ -505,11 +509,16 @@ bool build_bvh4(const float *tri9, int n, int id_base, HostBvh4 &out, std::strin
         out.nodes = std::move(col.out);
         out.depth = depth;
         out.stack_need = need;
+        if ((int)col.leaf_order.size() != n) {
+            err = "internal: leaf triangles do not cover the scene";
+            return false;
+        }
         out.tris.resize(n);
         for (int i = 0; i < n; ++i) {
-            const float *t = tri9 + 9 * (size_t)refs[i].tri;
+            const int src = refs[col.leaf_order[i]].tri;
+            const float *t = tri9 + 9 * (size_t)src;
             GpuTri g;
-            g.v0 = make_float4(t[0], t[1], t[2], bits_as_float(id_base + refs[i].tri));
+            g.v0 = make_float4(t[0], t[1], t[2], bits_as_float(id_base + src));
             g.e1 = make_float4(t[3] - t[0], t[4] - t[1], t[5] - t[2], 0.f);
             g.e2 = make_float4(t[6] - t[0], t[7] - t[1], t[8] - t[2], 0.f);
             out.tris[i] = g;

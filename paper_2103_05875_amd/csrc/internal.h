@@ -129,7 +129,8 @@ struct BatchVolume {
 };
 
 // Launch shape of the trace: probe brick per wavefront (bx*by*bz = 64),
-// persistent grid with per-XCD work queues or one wave per packet, number of
+// persistent grid with per-lane ray refill from per-XCD work queues or one
+// wave per packet, number of
 // top BVH nodes staged in LDS (0, 21 or 85 = the top 1, 3 or 4 levels), and
 // threads per block (128 or 256).
 struct TraceConfig {
