@@ -69,7 +69,8 @@ def parse():
     return ap.parse_args()
 
 
-KERNEL_SOURCES = ("kernels.hip", "internal.h", "bvh.cpp")
+# sources of the trace kernel (its BVH layout included): the counters stay valid while these are unchanged
+KERNEL_SOURCES = ("trace.hip", "trace_device.h", "device_common.h", "internal.h", "bvh.cpp")
 COPY_BYTES = 256 << 20             # the --calibrate-copy kernel reads and writes this many bytes
 
 

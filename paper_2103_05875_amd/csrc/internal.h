@@ -110,11 +110,32 @@ struct SceneView {
     float eps;            // shadow-ray offset
 };
 
+// Blend weight tables of one volume-frame, written by the ray-direction
+// kernel (rows: 64 irradiance texels, then 256 visibility texels):
+//   w[((j / 4) * kTexRows + t) * 4 + j % 4]  weight of ray j for texel row t;
+//                                            rays n .. (n rounded up to a
+//                                            multiple of 128) - 1 weigh 0
+//   part[b * kTexRows + t]                   sum of row t over rays
+//                                            kRaysPerPart*b .. +kRaysPerPart-1
+// The blend sums the parts in order b = 0, 1, ... for the row totals.
+constexpr int kTexRows = 64 + 256;
+constexpr int kRaysPerPart = 64;
+constexpr int kBlendTile = 8;  // probes per blend block
+struct WeightTables {
+    float *w = nullptr;
+    float *part = nullptr;
+    int k4 = 0;
+    int nparts = 0;
+};
+inline size_t weight_table_floats(int n) { return (size_t)((n + 127) / 128) * 128 * kTexRows; }
+inline size_t weight_part_floats(int n) { return (size_t)((n + kRaysPerPart - 1) / kRaysPerPart) * kTexRows; }
+
 // Work description of one volume for the batched launch.
 struct BatchVolume {
     VolumeParams vp;
     SceneView sv;
     const float4 *dirs;
+    WeightTables wt;
     float4 *rays;
     int32_t *hits;
     void *irr;
@@ -157,10 +178,11 @@ struct SplitBuffers {
 };
 
 // ---------------------------------------------------------------------------
-// Launchers (kernels.hip)
+// Launchers (trace.hip, blend.hip, batched.hip, pack.hip)
 // ---------------------------------------------------------------------------
-// queue: 8 ints zeroed by this kernel for the persistent trace that follows
-hipError_t launch_raydirs(const FrameParams &fp, int n, float4 *dirs, int *queue, hipStream_t s);
+// Directions and weight tables; queue: 16 ints zeroed for the trace that follows
+hipError_t launch_raydirs(const FrameParams &fp, const VolumeParams &vp, float4 *dirs, const WeightTables &wt,
+                          int *queue, hipStream_t s);
 hipError_t launch_trace(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp, const float4 *dirs,
                         float4 *rays, int32_t *hits, unsigned long long *counts, const TraceConfig &tc,
                         int *queue, const SplitBuffers &split, hipStream_t s);
@@ -168,13 +190,13 @@ hipError_t launch_shadow(const SceneView &sv, const SplitBuffers &split, const T
                          unsigned long long *counts, hipStream_t s);
 hipError_t launch_shade(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp, const float4 *dirs,
                         float4 *rays, const SplitBuffers &split, hipStream_t s);
-hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4 *rays, void *irr, void *vis,
+hipError_t launch_blend(const VolumeParams &vp, const WeightTables &wt, const float4 *rays, void *irr, void *vis,
                         int fp16, float h, hipStream_t s);
 hipError_t launch_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, int total_blend,
                           const FrameParams *frames_dev, int *queue_dev, int *done_dev, int *status_dev,
                           hipStream_t s);
-hipError_t launch_raydirs_batched(const FrameParams *frames_dev, const int *ns_dev, float4 *const *dirs_dev,
-                                  int n_vols, hipStream_t s);
+hipError_t launch_raydirs_batched(const BatchVolume *vols_dev, const FrameParams *frames_dev, int n_vols,
+                                  int max_parts, hipStream_t s);
 
 struct PackBuffers {
     const uint16_t *cur_irr, *cur_vis;   // tiles

@@ -1,0 +1,359 @@
+// Lossless delta pack of FP16 probe tiles for one client: change masks,
+// ordered compaction with a delta-coded index buffer, XOR byte planes against
+// the client's last-transmitted state, reference update, checksum.
+#include "device_common.h"
+
+namespace pv {
+
+// ---------------------------------------------------------------------------
+// pack
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ __forceinline__ uint32_t word_hash(uint32_t w, uint32_t word_index) {
+    return fmix32(w ^ (word_index * 0x9E3779B9u));
+}
+
+__device__ __forceinline__ bool texel_changed(uint16_t a, uint16_t b, float tau) {
+    if (tau == 0.f) return a != b;
+    // binary16 values are exact in double and so is their difference
+    const double da = (double)__half2float(__ushort_as_half(a));
+    const double db = (double)__half2float(__ushort_as_half(b));
+    return fabs(da - db) > (double)tau;
+}
+
+// The pack works on tiles of kPackQ consecutive probes. Their FP16 tiles are
+// contiguous in HBM (600 B and 1,296 B per probe) and start on 16-byte
+// boundaries (kPackQ * 600 and kPackQ * 1,296 are multiples of 16), so a block
+// stages them into LDS with aligned 16-byte loads (map allocations carry 256
+// bytes of slack, so the last vector of a ragged tail stays in bounds). Work
+// is then split into row units of 8 interior texels of one channel:
+// irradiance 3 x 8 rows per probe, visibility 2 x 16 rows x 2 halves.
+constexpr int kPackQ = 16;
+constexpr int kPackThreads = 256;
+constexpr int kIrrUnits = 3 * 8;       // per probe
+constexpr int kVisUnits = 2 * 16 * 2;  // per probe
+
+struct PackSmem {
+    uint4 irr[kPackQ * 600 / 16];
+    uint4 vis[kPackQ * 1296 / 16];
+    int changed[kPackQ][2];
+    uint32_t part[kPackThreads / 64];
+};
+
+__device__ __forceinline__ void stage_tiles(const PackBuffers &b, int p0, int P, PackSmem &sm) {
+    const int n = min(kPackQ, P - p0);
+    const uint4 *gi = reinterpret_cast<const uint4 *>(b.cur_irr + (size_t)p0 * 300);
+    const uint4 *gv = reinterpret_cast<const uint4 *>(b.cur_vis + (size_t)p0 * 648);
+    const int vi = (n * 600 + 15) / 16, vv = (n * 1296 + 15) / 16;
+    for (int i = threadIdx.x; i < vi; i += kPackThreads) sm.irr[i] = gi[i];
+    for (int i = threadIdx.x; i < vv; i += kPackThreads) sm.vis[i] = gv[i];
+}
+
+// Unit u of the tile (irradiance units first): probe q, texture (0 irr,
+// 1 vis), channel c, first interior texel t0 (multiple of 8).
+struct Unit {
+    int q, tex, c, t0, N;
+};
+
+__device__ __forceinline__ Unit unit_of(int u) {
+    Unit r;
+    if (u < kPackQ * kIrrUnits) {
+        r.q = u / kIrrUnits;
+        const int w = u - r.q * kIrrUnits;
+        r.tex = 0;
+        r.c = w / 8;
+        r.t0 = (w % 8) * 8;
+        r.N = 8;
+    } else {
+        const int v = u - kPackQ * kIrrUnits;
+        r.q = v / kVisUnits;
+        const int w = v - r.q * kVisUnits;
+        r.tex = 1;
+        r.c = w / 32;
+        r.t0 = (w % 32) * 8;
+        r.N = 16;
+    }
+    return r;
+}
+
+// The 8 current texels of a unit from the staged tiles.
+__device__ __forceinline__ void unit_cur(const PackSmem &sm, const Unit &u, uint16_t cur[8]) {
+    const uint16_t *base = u.tex == 0 ? reinterpret_cast<const uint16_t *>(sm.irr) + u.q * 300 + u.c * 100
+                                      : reinterpret_cast<const uint16_t *>(sm.vis) + u.q * 648 + u.c * 324;
+    const int S = u.N + 2, row = u.t0 / u.N, col = u.t0 - row * u.N;
+    const uint16_t *src = base + (row + 1) * S + col + 1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) cur[i] = src[i];
+}
+
+__device__ __forceinline__ uint16_t *unit_ref(const PackBuffers &b, int p, const Unit &u) {
+    return u.tex == 0 ? b.ref_irr + (size_t)p * 192 + u.c * 64 + u.t0 : b.ref_vis + (size_t)p * 512 + u.c * 256 + u.t0;
+}
+
+__device__ __forceinline__ void unpack8(uint4 v, uint16_t r[8]) {
+    r[0] = v.x & 0xffff;
+    r[1] = v.x >> 16;
+    r[2] = v.y & 0xffff;
+    r[3] = v.y >> 16;
+    r[4] = v.z & 0xffff;
+    r[5] = v.z >> 16;
+    r[6] = v.w & 0xffff;
+    r[7] = v.w >> 16;
+}
+
+// Change mask of every probe: any interior texel differs (tau = 0) or
+// |cur - ref| > tau.
+__global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P, float tau_irr, float tau_vis) {
+    __shared__ PackSmem sm;
+    const int p0 = blockIdx.x * kPackQ;
+    if (p0 >= P) return;
+    if (threadIdx.x < kPackQ * 2) sm.changed[threadIdx.x >> 1][threadIdx.x & 1] = 0;
+    stage_tiles(b, p0, P, sm);
+    __syncthreads();
+    const int n = min(kPackQ, P - p0);
+    const int units = kPackQ * (kIrrUnits + kVisUnits);
+    for (int u = threadIdx.x; u < units; u += kPackThreads) {
+        const Unit un = unit_of(u);
+        if (un.q >= n) continue;
+        uint16_t cur[8], ref[8];
+        unit_cur(sm, un, cur);
+        unpack8(*reinterpret_cast<const uint4 *>(unit_ref(b, p0 + un.q, un)), ref);
+        const float tau = un.tex == 0 ? tau_irr : tau_vis;
+        bool ch = false;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) ch |= texel_changed(cur[i], ref[i], tau);
+        if (ch) atomicOr(&sm.changed[un.q][un.tex], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < n) {
+        b.mask_irr[p0 + threadIdx.x] = (uint8_t)sm.changed[threadIdx.x][0];
+        b.mask_vis[p0 + threadIdx.x] = (uint8_t)sm.changed[threadIdx.x][1];
+    }
+}
+
+constexpr int kScanBlock = 1024;
+
+// Inclusive scans across the block with wavefront shuffles and one LDS step.
+__device__ __forceinline__ void block_scan2(int &a, int &m, int *sh_a, int *sh_m, int &total_a) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int ya = __shfl_up(a, off), ym = __shfl_up(m, off);
+        if (lane >= off) {
+            a += ya;
+            m = max(m, ym);
+        }
+    }
+    if (lane == 63) {
+        sh_a[wv] = a;
+        sh_m[wv] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kScanBlock / 64; ++w) {
+            sh_a[w] += sh_a[w - 1];
+            sh_m[w] = max(sh_m[w], sh_m[w - 1]);
+        }
+    }
+    __syncthreads();
+    if (wv > 0) {
+        a += sh_a[wv - 1];
+        m = max(m, sh_m[wv - 1]);
+    }
+    total_a = sh_a[kScanBlock / 64 - 1];
+    __syncthreads();
+}
+
+// One block: ordered ranks of the changed probes, delta-coded index buffers,
+// the header, and the checksum share of the index section.
+__global__ __launch_bounds__(kScanBlock) void k_pack_scan(PackBuffers b, int P, uint32_t client, uint32_t seq) {
+    __shared__ int sh_a[kScanBlock / 64], sh_m[kScanBlock / 64];
+    __shared__ uint32_t shu[kScanBlock / 64];
+    const int tid = threadIdx.x;
+    // per-thread ranges of a multiple of 16 probes, read as 16-byte vectors
+    // (mask arrays are padded to 65,536 zero bytes)
+    const int per = 16 * ((P + kScanBlock * 16 - 1) / (kScanBlock * 16));
+    const int lo = min(P, tid * per), hi = min(P, lo + per);
+    int ki = 0, kv = 0, last_i = -1, last_v = -1;
+    for (int p = lo; p < hi; p += 16) {
+        const uint4 mi = *reinterpret_cast<const uint4 *>(b.mask_irr + p);
+        const uint4 mv = *reinterpret_cast<const uint4 *>(b.mask_vis + p);
+        const uint32_t wi[4] = {mi.x, mi.y, mi.z, mi.w}, wv[4] = {mv.x, mv.y, mv.z, mv.w};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const bool ci = (wi[i >> 2] >> (8 * (i & 3))) & 0xffu, cv = (wv[i >> 2] >> (8 * (i & 3))) & 0xffu;
+            if (ci && p + i < hi) {
+                ++ki;
+                last_i = p + i;
+            }
+            if (cv && p + i < hi) {
+                ++kv;
+                last_v = p + i;
+            }
+        }
+    }
+    // inclusive scans; exclusive values are the inclusive ones minus this thread's
+    int ai = ki, mi = last_i, av = kv, mv = last_v, K_irr, K_vis;
+    block_scan2(ai, mi, sh_a, sh_m, K_irr);
+    block_scan2(av, mv, sh_a, sh_m, K_vis);
+    // exclusive max: the previous threads' last changed probe
+    int prev_i = __shfl_up(mi, 1), prev_v = __shfl_up(mv, 1);
+    __shared__ int wlast_i[kScanBlock / 64], wlast_v[kScanBlock / 64];
+    if ((tid & 63) == 63) {
+        wlast_i[tid >> 6] = mi;
+        wlast_v[tid >> 6] = mv;
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) {
+        prev_i = (tid >> 6) > 0 ? wlast_i[(tid >> 6) - 1] : -1;
+        prev_v = (tid >> 6) > 0 ? wlast_v[(tid >> 6) - 1] : -1;
+    }
+    uint8_t *pk = b.packet;
+    uint16_t *idx_i = reinterpret_cast<uint16_t *>(pk + 32);
+    uint16_t *idx_v = idx_i + K_irr;
+    int k_i = ai - ki, k_v = av - kv;
+    for (int p0 = lo; p0 < hi; p0 += 16) {
+        const uint4 mi = *reinterpret_cast<const uint4 *>(b.mask_irr + p0);
+        const uint4 mv = *reinterpret_cast<const uint4 *>(b.mask_vis + p0);
+        const uint32_t wi[4] = {mi.x, mi.y, mi.z, mi.w}, wv[4] = {mv.x, mv.y, mv.z, mv.w};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int p = p0 + i;
+            if (p >= hi) break;
+            if ((wi[i >> 2] >> (8 * (i & 3))) & 0xffu) {
+                b.rank_irr[p] = k_i;
+                idx_i[k_i] = (uint16_t)(k_i == 0 ? p : p - prev_i);
+                prev_i = p;
+                ++k_i;
+            }
+            if ((wv[i >> 2] >> (8 * (i & 3))) & 0xffu) {
+                b.rank_vis[p] = k_v;
+                idx_v[k_v] = (uint16_t)(k_v == 0 ? p : p - prev_v);
+                prev_v = p;
+                ++k_v;
+            }
+        }
+    }
+    const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
+    if (tid < 16) {  // zero the padding after the entries
+        const int pos = 2 * (K_irr + K_vis) + tid;
+        if (pos < idx_bytes) pk[32 + pos] = 0;
+    }
+    __syncthreads();
+    // checksum of the index section (payload words 0 .. idx_bytes/4 - 1)
+    uint32_t part = 0;
+    const uint32_t *words = reinterpret_cast<const uint32_t *>(pk + 32);
+    for (int wi = tid; wi < idx_bytes / 4; wi += kScanBlock) part += word_hash(words[wi], (uint32_t)wi);
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if ((tid & 63) == 0) shu[tid >> 6] = part;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t sum = 0;
+        for (int k = 0; k < kScanBlock / 64; ++k) sum += shu[k];
+        uint32_t *h = reinterpret_cast<uint32_t *>(pk);
+        h[0] = 0x4B505650u;
+        h[1] = 1u | (32u << 16);
+        h[2] = client;
+        h[3] = seq;
+        h[4] = (uint32_t)P;
+        h[5] = (uint32_t)K_irr;
+        h[6] = (uint32_t)K_vis;
+        h[7] = sum;
+    }
+}
+
+// XOR byte planes of the sent probes, reference update, checksum share.
+__global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, int P) {
+    __shared__ PackSmem sm;
+    const int p0 = blockIdx.x * kPackQ;
+    if (p0 >= P) return;
+    const int n = min(kPackQ, P - p0);
+    // skip the tile when none of its probes is sent (uniform per block)
+    bool any = false;
+    for (int q = 0; q < n; ++q) any |= (b.mask_irr[p0 + q] | b.mask_vis[p0 + q]) != 0;
+    if (!any) return;
+    stage_tiles(b, p0, P, sm);
+    __syncthreads();
+    const uint32_t *h = reinterpret_cast<const uint32_t *>(b.packet);
+    const int K_irr = (int)h[5], K_vis = (int)h[6];
+    const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
+    uint8_t *planes_i = b.packet + 32 + idx_bytes;
+    uint8_t *planes_v = planes_i + (size_t)K_irr * 6 * 64;
+    uint32_t part = 0;
+    const int units = kPackQ * (kIrrUnits + kVisUnits);
+    for (int u = threadIdx.x; u < units; u += kPackThreads) {
+        const Unit un = unit_of(u);
+        if (un.q >= n) continue;
+        const int p = p0 + un.q;
+        if (!(un.tex == 0 ? b.mask_irr[p] : b.mask_vis[p])) continue;
+        uint16_t cur[8], ref[8];
+        unit_cur(sm, un, cur);
+        uint16_t *rp = unit_ref(b, p, un);
+        unpack8(*reinterpret_cast<const uint4 *>(rp), ref);
+        uint32_t lo[2] = {0, 0}, hi[2] = {0, 0};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint16_t x = cur[i] ^ ref[i];
+            lo[i >> 2] |= (uint32_t)(x & 0xff) << (8 * (i & 3));
+            hi[i >> 2] |= (uint32_t)(x >> 8) << (8 * (i & 3));
+        }
+        const int K = un.tex == 0 ? K_irr : K_vis;
+        const int k = un.tex == 0 ? (int)b.rank_irr[p] : (int)b.rank_vis[p];
+        const size_t NN = (size_t)un.N * un.N, plane_bytes = (size_t)K * NN;
+        uint8_t *dlo = (un.tex == 0 ? planes_i : planes_v) + (size_t)(2 * un.c) * plane_bytes + (size_t)k * NN + un.t0;
+        uint8_t *dhi = dlo + plane_bytes;
+        *reinterpret_cast<uint2 *>(dlo) = make_uint2(lo[0], lo[1]);
+        *reinterpret_cast<uint2 *>(dhi) = make_uint2(hi[0], hi[1]);
+        *reinterpret_cast<uint4 *>(rp) =
+            make_uint4((uint32_t)cur[0] | ((uint32_t)cur[1] << 16), (uint32_t)cur[2] | ((uint32_t)cur[3] << 16),
+                       (uint32_t)cur[4] | ((uint32_t)cur[5] << 16), (uint32_t)cur[6] | ((uint32_t)cur[7] << 16));
+        const uint32_t wlo = (uint32_t)((dlo - (b.packet + 32)) >> 2), whi = (uint32_t)((dhi - (b.packet + 32)) >> 2);
+        part += word_hash(lo[0], wlo) + word_hash(lo[1], wlo + 1) + word_hash(hi[0], whi) + word_hash(hi[1], whi + 1);
+    }
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if ((threadIdx.x & 63) == 0) sm.part[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int w = 0; w < kPackThreads / 64; ++w) s += sm.part[w];
+        atomicAdd(reinterpret_cast<uint32_t *>(b.packet) + 7, s);
+    }
+}
+
+__global__ void k_zero(uint32_t *p, size_t words) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)blockDim.x * gridDim.x)
+        p[i] = 0u;
+}
+
+hipError_t launch_pack_mask(const PackBuffers &b, int P, float tau_irr, float tau_vis, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_mask, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P, tau_irr, tau_vis);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_scan(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_scan, dim3(1), dim3(kScanBlock), 0, s, b, P, client, seq);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_compact(const PackBuffers &b, int P, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_compact, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
+    const size_t words = bytes / 4;
+    if (words == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)p, words);
+    return hipGetLastError();
+}
+
+}  // namespace pv

@@ -1,5 +1,6 @@
 // C ABI of the probe-volume library: handles, validation, device memory,
-// launch sequencing. Kernels live in kernels.hip, the BVH builder in bvh.cpp.
+// launch sequencing. Kernels live in trace.hip, blend.hip, batched.hip and
+// pack.hip, the BVH builder in bvh.cpp.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -40,8 +41,6 @@ extern "C" const char *pv_version(void) { return "probestream 1.0 gfx950"; }
 struct BatchSlot {
     BatchVolume *batch_dev = nullptr;
     FrameParams *frames_dev = nullptr;
-    int *ns_dev = nullptr;
-    float4 **dirs_ptrs_dev = nullptr;
     int *counters_dev = nullptr;  // [0] queue, [1] status, [2..] done per volume
     int cap = 0;
     void *stage_host = nullptr;
@@ -114,6 +113,7 @@ struct pv_volume {
     size_t elem = 4;
     void *irr = nullptr, *vis = nullptr;
     float4 *rays = nullptr, *dirs = nullptr;
+    WeightTables wt;  // blend weights of the current frame
     int32_t *hits = nullptr;
     int *queue = nullptr;  // [0..7] work queues of the persistent trace, [8] shadow-queue length
     int64_t frame = 0;
@@ -198,8 +198,6 @@ extern "C" pv_status pv_ctx_destroy(pv_ctx *c) {
         BatchSlot &b = c->slots[i];
         hipFree(b.batch_dev);
         hipFree(b.frames_dev);
-        hipFree(b.ns_dev);
-        hipFree(b.dirs_ptrs_dev);
         hipFree(b.counters_dev);
         if (b.stage_host) hipHostFree(b.stage_host);
         if (b.done) hipEventDestroy(b.done);
@@ -458,7 +456,8 @@ static pv_status validate_desc(const pv_volume_desc *d) {
 static uint64_t volume_bytes(const pv_volume_desc *d) {
     const int P = d->nx * d->ny * d->nz, n = d->rays_per_probe;
     const size_t elem = d->format == PV_MAP_FP16 ? 2 : 4;
-    uint64_t b = irr_bytes(P, elem) + vis_bytes(P, elem) + 512 + (uint64_t)P * n * 16 + (uint64_t)n * 16 + 64;
+    uint64_t b = irr_bytes(P, elem) + vis_bytes(P, elem) + 512 + (uint64_t)P * n * 16 + (uint64_t)n * 16 + 64 +
+                 (uint64_t)(weight_table_floats(n) + weight_part_floats(n)) * 4;
     if (d->flags & PV_KEEP_HITS) b += (uint64_t)P * n * 4;
     return b;
 }
@@ -475,6 +474,8 @@ static void free_volume(pv_volume *v) {
     hipFree(v->vis);
     hipFree(v->rays);
     hipFree(v->dirs);
+    hipFree(v->wt.w);
+    hipFree(v->wt.part);
     hipFree(v->hits);
     hipFree(v->queue);
     hipFree(v->split.hitrec);
@@ -498,8 +499,14 @@ extern "C" pv_status pv_create_volume(pv_ctx *ctx, const pv_volume_desc *d, pv_v
     if (st == PV_OK) st = dev_alloc(&v->vis, vis_bytes(v->P, v->elem) + 256, "visibility maps");
     if (st == PV_OK) st = dev_alloc(&v->rays, (size_t)v->P * v->n * 16, "ray buffer");
     if (st == PV_OK) st = dev_alloc(&v->dirs, (size_t)v->n * 16, "directions");
+    v->wt.k4 = (v->n + 3) / 4;
+    v->wt.nparts = (v->n + kRaysPerPart - 1) / kRaysPerPart;
+    if (st == PV_OK) st = dev_alloc(&v->wt.w, weight_table_floats(v->n) * 4, "blend weight table");
+    if (st == PV_OK) st = dev_alloc(&v->wt.part, weight_part_floats(v->n) * 4, "blend weight sums");
     if (st == PV_OK && (d->flags & PV_KEEP_HITS)) st = dev_alloc(&v->hits, (size_t)v->P * v->n * 4, "hit ids");
     if (st == PV_OK) st = dev_alloc(&v->queue, 16 * sizeof(int), "work queues");
+    if (st == PV_OK && launch_zero(v->wt.w, weight_table_floats(v->n) * 4, ctx->stream) != hipSuccess)
+        st = fail(PV_ERR_DEVICE, "zero fill");  // the padding past n stays zero
     if (st == PV_OK && launch_zero(v->irr, irr_bytes(v->P, v->elem), ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "zero fill");
     if (st == PV_OK && launch_zero(v->vis, vis_bytes(v->P, v->elem), ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "zero fill");
     if (st == PV_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "sync after zero fill");
@@ -602,7 +609,7 @@ static pv_status enqueue_trace(pv_volume *v, const FrameParams &fp, const SceneV
     const bool split = v->tc.split_shadows != 0;
     if (split) PV_TRY(ensure_split(v, fp.n_lights, s));
     const SplitBuffers sb = split ? v->split : SplitBuffers();
-    HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s, [&] { return launch_raydirs(fp, v->n, v->dirs, v->queue, s); }));
+    HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s, [&] { return launch_raydirs(fp, vp, v->dirs, v->wt, v->queue, s); }));
     HIP_TRY(timed(c, PV_STAGE_TRACE, s,
                   [&] { return launch_trace(vp, sv, fp, v->dirs, v->rays, v->hits, counts, v->tc, v->queue, sb, s); }));
     if (split && fp.n_lights > 0) {
@@ -625,7 +632,7 @@ extern "C" pv_status pv_update_probes(pv_volume *v, const pv_frame *f, void *str
     const int fp16 = v->desc.format == PV_MAP_FP16;
     const float h = effective_h(v);
     PV_TRY(enqueue_trace(v, fp, sv, nullptr, s));
-    HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend(vp, v->dirs, v->rays, v->irr, v->vis, fp16, h, s); }));
+    HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend(vp, v->wt, v->rays, v->irr, v->vis, fp16, h, s); }));
     PV_TRY(note_scene_use(v->scene, s));
     v->frame++;
     return PV_OK;
@@ -661,8 +668,8 @@ extern "C" pv_status pv_blend_rays(pv_volume *v, const pv_frame *f, const void *
     HIP_TRY(hipSetDevice(v->ctx->device));
     hipStream_t s = pick(v->ctx, stream);
     const VolumeParams vp = volume_params(v);
-    HIP_TRY(launch_raydirs(fp, v->n, v->dirs, nullptr, s));
-    HIP_TRY(launch_blend(vp, v->dirs, (const float4 *)rays_dev, v->irr, v->vis, v->desc.format == PV_MAP_FP16,
+    HIP_TRY(launch_raydirs(fp, vp, v->dirs, v->wt, nullptr, s));
+    HIP_TRY(launch_blend(vp, v->wt, (const float4 *)rays_dev, v->irr, v->vis, v->desc.format == PV_MAP_FP16,
                          effective_h(v), s));
     v->frame++;
     return PV_OK;
@@ -741,25 +748,19 @@ static pv_status ensure_slot(pv_ctx *c, BatchSlot &b, int n) {
     if (n <= b.cap) return PV_OK;
     hipFree(b.batch_dev);
     hipFree(b.frames_dev);
-    hipFree(b.ns_dev);
-    hipFree(b.dirs_ptrs_dev);
     hipFree(b.counters_dev);
     if (b.stage_host) hipHostFree(b.stage_host);
     b.batch_dev = nullptr;
     b.frames_dev = nullptr;
-    b.ns_dev = nullptr;
-    b.dirs_ptrs_dev = nullptr;
     b.counters_dev = nullptr;
     b.stage_host = nullptr;
     b.cap = 0;
     PV_TRY(dev_alloc(&b.batch_dev, sizeof(BatchVolume) * n, "batch descriptors"));
     PV_TRY(dev_alloc(&b.frames_dev, sizeof(FrameParams) * n, "batch frames"));
-    PV_TRY(dev_alloc(&b.ns_dev, sizeof(int) * n, "batch ray counts"));
-    PV_TRY(dev_alloc(&b.dirs_ptrs_dev, sizeof(float4 *) * n, "batch direction pointers"));
     PV_TRY(dev_alloc(&b.counters_dev, sizeof(int) * (2 + n), "batch counters"));
     HIP_TRY(launch_zero(b.counters_dev, sizeof(int) * (2 + n), c->stream));  // fresh status word
     HIP_TRY(hipStreamSynchronize(c->stream));
-    const size_t bytes = (sizeof(BatchVolume) + sizeof(FrameParams) + sizeof(int) + sizeof(float4 *)) * n + 256;
+    const size_t bytes = (sizeof(BatchVolume) + sizeof(FrameParams)) * n + 256;
     HIP_TRY(hipHostMalloc(&b.stage_host, bytes));
     b.cap = n;
     return PV_OK;
@@ -772,25 +773,24 @@ struct pv_batch_graph {
     pv_ctx *ctx = nullptr;
     std::vector<pv_volume *> vols;
     BatchSlot slot;           // device descriptors + pinned staging owned by the graph
-    size_t o_b = 0, o_f = 0, o_n = 0, o_d = 0, bytes = 0;
-    int waves = 0, blend = 0;
+    size_t o_b = 0, o_f = 0, bytes = 0;
+    int waves = 0, blend = 0, max_parts = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
     bool launched = false;
 };
 
-// Fills the pinned staging of a batch: descriptors, frames, ray counts and
-// direction pointers; returns the wave and blend-group totals.
+// Fills the pinned staging of a batch: descriptors and frames; returns the
+// wave and blend-group totals and the most ray-direction blocks of a volume.
 static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int n, char *h, size_t *offs, int &waves,
-                            int &blend) {
+                            int &blend, int &max_parts) {
     std::vector<BatchVolume> bv(n);
     std::vector<FrameParams> fps(n);
     std::memset(fps.data(), 0, sizeof(FrameParams) * n);
-    std::vector<int> ns(n);
-    std::vector<float4 *> dps(n);
     waves = 0;
     blend = 0;
+    max_parts = 0;
     for (int i = 0; i < n; ++i) {
         pv_volume *v = vols[i];
         if (frames) PV_TRY(frame_params(&frames[i], v->scene, fps[i]));
@@ -798,6 +798,8 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
         b.vp = volume_params(v);
         b.sv = scene_view(v->scene);
         b.dirs = v->dirs;
+        b.wt = v->wt;
+        max_parts = std::max(max_parts, v->wt.nparts);
         b.rays = v->rays;
         b.hits = v->hits;
         b.irr = v->irr;
@@ -811,11 +813,9 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
         waves = (waves + 3) / 4 * 4;  // trace items hold 4 waves; each volume starts on an item boundary
         b.first_wave = waves;
         waves += b.n_waves;
-        b.n_blend = (v->P + 3) / 4;
+        b.n_blend = (v->P + kBlendTile - 1) / kBlendTile;
         b.first_blend = blend;
         blend += b.n_blend;
-        ns[i] = v->n;
-        dps[i] = v->dirs;
     }
     size_t off = 0;
     auto put = [&](const void *src, size_t bytes) {
@@ -826,9 +826,7 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
     };
     offs[0] = put(bv.data(), sizeof(BatchVolume) * n);
     offs[1] = put(fps.data(), sizeof(FrameParams) * n);  // zeros when no frames are given yet
-    offs[2] = put(ns.data(), sizeof(int) * n);
-    offs[3] = put(dps.data(), sizeof(float4 *) * n);
-    offs[4] = off;
+    offs[2] = off;
     return PV_OK;
 }
 
@@ -857,19 +855,17 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
     c->slot_next = (c->slot_next + 1) % pv_ctx::kRing;
     HIP_TRY(hipEventSynchronize(slot.done));  // the slot's previous launch has finished
     PV_TRY(ensure_slot(c, slot, n));
-    size_t offs[5];
-    int waves, blend;
+    size_t offs[3];
+    int waves, blend, max_parts;
     char *h = (char *)slot.stage_host;
-    PV_TRY(fill_batch(vols, frames, n, h, offs, waves, blend));
+    PV_TRY(fill_batch(vols, frames, n, h, offs, waves, blend, max_parts));
     HIP_TRY(hipMemcpyAsync(slot.batch_dev, h + offs[0], sizeof(BatchVolume) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(slot.frames_dev, h + offs[1], sizeof(FrameParams) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(slot.ns_dev, h + offs[2], sizeof(int) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(slot.dirs_ptrs_dev, h + offs[3], sizeof(float4 *) * n, hipMemcpyHostToDevice, s));
     // queue counter and per-volume done counters start at zero (status word kept)
     HIP_TRY(launch_zero(slot.counters_dev, sizeof(int), s));
     HIP_TRY(launch_zero(slot.counters_dev + 2, sizeof(int) * n, s));
     HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s,
-                  [&] { return launch_raydirs_batched(slot.frames_dev, slot.ns_dev, slot.dirs_ptrs_dev, n, s); }));
+                  [&] { return launch_raydirs_batched(slot.batch_dev, slot.frames_dev, n, max_parts, s); }));
     HIP_TRY(timed(c, PV_STAGE_BATCHED, s, [&] {
         return launch_batched(slot.batch_dev, n, waves, blend, slot.frames_dev, slot.counters_dev,
                               slot.counters_dev + 2, slot.counters_dev + 1, s);
@@ -889,8 +885,6 @@ static void free_graph(pv_batch_graph *g) {
     BatchSlot &b = g->slot;
     hipFree(b.batch_dev);
     hipFree(b.frames_dev);
-    hipFree(b.ns_dev);
-    hipFree(b.dirs_ptrs_dev);
     hipFree(b.counters_dev);
     if (b.stage_host) hipHostFree(b.stage_host);
     delete g;
@@ -907,17 +901,16 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
     pv_status st = ensure_slot(c, g->slot, n);
     if (st == PV_OK && hipEventCreateWithFlags(&g->done, hipEventDisableTiming) != hipSuccess)
         st = fail(PV_ERR_DEVICE, "event");
-    size_t offs[5];
-    if (st == PV_OK) st = fill_batch(vols, nullptr, n, (char *)g->slot.stage_host, offs, g->waves, g->blend);
+    size_t offs[3];
+    if (st == PV_OK)
+        st = fill_batch(vols, nullptr, n, (char *)g->slot.stage_host, offs, g->waves, g->blend, g->max_parts);
     if (st != PV_OK) {
         free_graph(g);
         return st;
     }
     g->o_b = offs[0];
     g->o_f = offs[1];
-    g->o_n = offs[2];
-    g->o_d = offs[3];
-    g->bytes = offs[4];
+    g->bytes = offs[2];
     // capture on a private stream: copy node, zero fill, ray directions, batched kernel
     hipStream_t cs = nullptr;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -926,11 +919,9 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) e = hipMemcpyAsync(b.batch_dev, h + g->o_b, sizeof(BatchVolume) * n, hipMemcpyHostToDevice, cs);
     if (e == hipSuccess) e = hipMemcpyAsync(b.frames_dev, h + g->o_f, sizeof(FrameParams) * n, hipMemcpyHostToDevice, cs);
-    if (e == hipSuccess) e = hipMemcpyAsync(b.ns_dev, h + g->o_n, sizeof(int) * n, hipMemcpyHostToDevice, cs);
-    if (e == hipSuccess) e = hipMemcpyAsync(b.dirs_ptrs_dev, h + g->o_d, sizeof(float4 *) * n, hipMemcpyHostToDevice, cs);
     if (e == hipSuccess) e = launch_zero(b.counters_dev, sizeof(int), cs);
     if (e == hipSuccess) e = launch_zero(b.counters_dev + 2, sizeof(int) * n, cs);
-    if (e == hipSuccess) e = launch_raydirs_batched(b.frames_dev, b.ns_dev, b.dirs_ptrs_dev, n, cs);
+    if (e == hipSuccess) e = launch_raydirs_batched(b.batch_dev, b.frames_dev, n, g->max_parts, cs);
     if (e == hipSuccess)
         e = launch_batched(b.batch_dev, n, g->waves, g->blend, b.frames_dev, b.counters_dev, b.counters_dev + 2,
                            b.counters_dev + 1, cs);
@@ -962,9 +953,9 @@ extern "C" pv_status pv_batch_graph_launch(pv_batch_graph *g, const pv_frame *fr
     // the copy node reads the pinned buffer when the graph runs: the previous
     // launch must have finished before it is rewritten
     if (g->launched) HIP_TRY(hipEventSynchronize(g->done));
-    size_t offs[5];
-    int waves, blend;
-    PV_TRY(fill_batch(g->vols.data(), frames, n, (char *)g->slot.stage_host, offs, waves, blend));
+    size_t offs[3];
+    int waves, blend, max_parts;
+    PV_TRY(fill_batch(g->vols.data(), frames, n, (char *)g->slot.stage_host, offs, waves, blend, max_parts));
     hipStream_t s = pick(c, stream);
     HIP_TRY(timed(c, PV_STAGE_BATCHED, s, [&] { return hipGraphLaunch(g->exec, s); }));
     HIP_TRY(hipEventRecord(g->done, s));

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libprobestream.so")
-SOURCES = ["kernels.hip", "bvh.cpp", "pv_api.cpp"]
+SOURCES = ["trace.hip", "blend.hip", "batched.hip", "pack.hip", "bvh.cpp", "pv_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -20,15 +20,37 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = SO + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), file=sys.stderr)
-    subprocess.check_call(cmd)
-    os.replace(tmp, SO)
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compiles every source to an object (in parallel), then links."""
+    import concurrent.futures
+    import tempfile
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    with tempfile.TemporaryDirectory(prefix="pvbuild") as tmpd:
+        objs, cmds = [], []
+        for s in SOURCES:
+            obj = os.path.join(tmpd, s + ".o")
+            objs.append(obj)
+            cmds.append([HIPCC, *[f for f in FLAGS if f != "-shared"], *inc, "-c", os.path.join(CSRC, s), "-o", obj])
+        workers = jobs or min(len(cmds), os.cpu_count() or 1)
+        with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+            for cmd, rc in zip(cmds, ex.map(_run(verbose), cmds)):
+                if rc != 0:
+                    raise subprocess.CalledProcessError(rc, cmd)
+        tmp = SO + ".tmp"
+        link = [HIPCC, *FLAGS, *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(link), file=sys.stderr)
+        subprocess.check_call(link)
+        os.replace(tmp, SO)
     return SO
+
+
+def _run(verbose):
+    def go(cmd):
+        if verbose:
+            print(" ".join(cmd), file=sys.stderr)
+        return subprocess.call(cmd)
+    return go
 
 
 if __name__ == "__main__":

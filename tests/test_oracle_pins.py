@@ -238,6 +238,73 @@ def test_convex_room_direct_light_closed_form(O):
             assert np.isclose(rays["r"][p, j], min(t, 4.0), rtol=1e-12)
 
 
+def test_square_occluder_shadow_closed_form(O):
+    """A floor, a floating two-sided square and a light above it: a floor
+    point is lit exactly when its segment to the light misses the square
+    (checked where that segment crosses the square's plane); points on the
+    square's underside face away from the light; misses see the sky."""
+    f32 = lambda v: np.float32(v)
+    floor = np.array([[[-60, 0, -60], [60, 0, -60], [60, 0, 60]], [[-60, 0, -60], [60, 0, 60], [-60, 0, 60]]],
+                     np.float32)
+    a0, a1, hy = 0.0, 1.5, 2.0                               # square [a0,a1]^2 at height hy
+    square = np.array([[[a0, hy, a0], [a1, hy, a0], [a1, hy, a1]], [[a0, hy, a0], [a1, hy, a1], [a0, hy, a1]]],
+                      np.float32)
+    tris = np.concatenate([floor, square])
+    alb = np.array([[0.5, 0.6, 0.7]] * 2 + [[0.3, 0.3, 0.3]] * 2, np.float32)
+    Lp = np.array([0.7, 6.0, 0.8])
+    I = np.array([40.0, 30.0, 20.0])
+    light = np.array([[*Lp, *I]], np.float32)
+    sky = (0.05, 0.1, 0.2)
+    cfg = _cfg(nx=3, ny=1, nz=3, origin=(-0.5, 1.0, -0.5), spacing=(1.0, 1.0, 1.0), rays_per_probe=256,
+               max_distance=8.0, sky=sky)
+    osc = O.OracleScene(tris, alb)
+    R = synth.rotation(21, 0)
+    rays = O.trace_shade(osc, cfg, R, light)
+    d = O.ray_dirs(256, R)
+    Lp64, I64 = Lp.astype(np.float32).astype(np.float64), I.astype(np.float32).astype(np.float64)
+    n_lit = n_shadow = n_under = 0
+    for p in range(cfg.n_probes):
+        x, z = p % 3, p // 3
+        o = np.array([f32(-0.5) + f32(1.0) * x, f32(1.0), f32(-0.5) + f32(1.0) * z], np.float64)
+        for j in range(256):
+            dj = d[j]
+            L = rays["L"][p, j]
+            t_sq = (hy - o[1]) / dj[1] if dj[1] > 0 else np.inf
+            if np.isfinite(t_sq):
+                h = o + t_sq * dj
+                if a0 < h[0] < a1 and a0 < h[2] < a1:
+                    if min(h[0] - a0, a1 - h[0], h[2] - a0, a1 - h[2]) < 1e-6:
+                        continue                              # grazing an edge: a tie
+                    assert np.allclose(L, 0.0, atol=1e-15), (p, j)   # underside faces away from the light
+                    n_under += 1
+                    continue
+            if dj[1] >= 0:
+                assert np.allclose(L, sky, rtol=1e-12), (p, j)
+                continue
+            t = -o[1] / dj[1]
+            xh = o + t * dj
+            if max(abs(xh[0]), abs(xh[2])) > 60.0 - 1e-6:
+                if max(abs(xh[0]), abs(xh[2])) > 60.0 + 1e-6:
+                    assert np.allclose(L, sky, rtol=1e-12), (p, j)   # beyond the floor's edge
+                continue
+            lv = Lp64 - xh
+            s = (hy - xh[1]) / lv[1]                          # where the segment to the light crosses y = hy
+            c = xh + s * lv
+            m = min(c[0] - a0, a1 - c[0], c[2] - a0, a1 - c[2])
+            if abs(m) < 1e-6:
+                continue                                      # shadow-ray edge tie
+            dist = np.linalg.norm(lv)
+            lit = rays["L"][p, j]
+            expect = alb[0].astype(np.float64) / math.pi * I64 * (lv[1] / dist) / dist ** 2
+            if m > 0:
+                assert np.allclose(lit, 0.0, atol=1e-15), (p, j)
+                n_shadow += 1
+            else:
+                assert np.allclose(lit, expect, rtol=1e-9), (p, j)
+                n_lit += 1
+    assert n_lit > 100 and n_shadow > 20 and n_under > 20, (n_lit, n_shadow, n_under)
+
+
 def test_box_room_invariants_and_bounds(O):
     cfg = synth.config("box_room")
     sc = synth.box_room()
