@@ -164,18 +164,19 @@ pv_status pv_set_scene(pv_volume *vol, pv_scene *scene);
 pv_status pv_update_probes(pv_volume *vol, const pv_frame *frame, void *stream);
 
 /*
- * The same update for n volumes in one go: one ray-direction launch, one
- * persistent trace-and-blend launch whose work queue covers every volume
- * (each volume's blend starts when its own rays are done), enqueued on
- * 'stream'. Results are bit-identical to n pv_update_probes calls.
+ * The same update for n volumes in one go, enqueued on 'stream': three
+ * launches whatever n is -- ray directions and blend weights of every
+ * volume, the trace of every wavefront packet of every volume, the blend of
+ * every probe group of every volume -- so small volumes share the device
+ * instead of each filling it alone. Results are bit-identical to n
+ * pv_update_probes calls with the default trace launch shape.
  */
 pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_frame *frames, int n, void *stream);
 
 /*
  * A captured HIP graph of the batched update of a fixed set of volumes:
- * a copy node refreshing the device-resident descriptors and frame
- * parameters from pinned host memory, a zero-fill kernel for the work-queue
- * counters, the ray-direction kernel and the persistent batched kernel.
+ * copy nodes refreshing the device-resident descriptors and frame
+ * parameters from pinned host memory, then the three batched kernels.
  * pv_batch_graph_launch writes the frames into the pinned buffer (waiting for
  * the graph's previous launch to finish first) and launches the graph on
  * 'stream'; results equal pv_update_probes_batched. The volumes must outlive
@@ -254,10 +255,6 @@ pv_status pv_get_masks(pv_client *client, void **mask_irr_dev, void **mask_vis_d
 /* Wait for the stream (NULL: the whole device); report asynchronous device
  * errors. */
 pv_status pv_sync(void *stream);
-/* Synchronous: status word of the batched work queue, 0 when every bounded
- * wait of the persistent launch completed, 1 when one expired (its result
- * is then invalid). */
-pv_status pv_ctx_check(pv_ctx *ctx, int *status);
 
 /*
  * Launch shape of the trace kernel (a tuning choice; every shape computes
@@ -291,7 +288,7 @@ typedef enum {
     PV_STAGE_TRACE = 1,
     PV_STAGE_BLEND = 2,
     PV_STAGE_PACK_MASK = 3,
-    PV_STAGE_PACK_SCAN = 4,
+    PV_STAGE_PACK_SCAN = 4,     /* reserved: the prefix is taken inside the compaction */
     PV_STAGE_PACK_COMPACT = 5,
     PV_STAGE_BATCHED = 6,
     PV_STAGE_SHADOW = 7,

@@ -1,119 +1,90 @@
-// Batched update: one persistent launch traces and blends many volumes.
+// Batched update of many volumes: after the ray-direction kernel of every
+// volume (blend.hip), one trace launch covers every packet of every volume
+// and one blend launch every probe group of every volume. Each block belongs
+// to one volume and finds it by binary search over the per-volume prefix
+// counts, so volumes of different sizes, ray counts, scenes and map formats
+// share the device without a launch per volume. Results are bit-identical
+// to the per-volume launches: each ray and each probe group runs the same
+// device code on the same inputs.
 #include "blend_device.h"
 #include "trace_device.h"
 
 namespace pv {
 
-// ---------------------------------------------------------------------------
-// batched persistent launch
-// ---------------------------------------------------------------------------
-// Work queue over all volumes: first every trace item (4 waves), then every
-// blend group (8 probes). A blend group of volume v waits until all
-// trace items of v have completed; every item it waits on was dequeued
-// earlier by a running block that never waits on later items, so the
-// queue drains. The wait is bounded; on expiry the block records an error
-// and skips its item.
-constexpr int kBatchBlock = 256;
-constexpr long long kSpinLimit = 1ll << 26;
+constexpr int kBatchBlock = 256;            // trace: four packets per block
+constexpr int kBatchTop = 21;               // top BVH nodes staged per block
+constexpr int kBatchWaves = kBatchBlock / 64;
 
-union BatchSmem {
-    int stk[kStack * kBatchBlock];
-    BlendSmem blend;
-};
+// Last volume whose first item is at or before 'item' (prefix counts are
+// ascending; every volume has at least one item).
+template <bool BLEND>
+__device__ __forceinline__ int find_volume(const BatchVolume *vols, int n_vols, int item) {
+    int lo = 0, hi = n_vols - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int first = BLEND ? vols[mid].first_blend : vols[mid].first_wave;
+        if (first <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
 
-// Blend group of one volume (a call of its own: its registers are not
-// allocated together with the trace path's).
-__device__ __attribute__((noinline)) void batched_blend_item(const BatchVolume &bv, int p0, BlendSmem &sm) {
+template <typename E>
+__global__ __launch_bounds__(kBatchBlock) void k_trace_batched(const BatchVolume *vols, int n_vols,
+                                                               const FrameParams *frames) {
+    __shared__ E stk[kStack * kBatchBlock];
+    const int wave0 = xcd_logical_block() * kBatchWaves;  // volumes start on a block boundary
+    const int v = __builtin_amdgcn_readfirstlane(find_volume<false>(vols, n_vols, wave0));
+    const BatchVolume &bv = vols[v];
+    NodeSrc src = global_nodes(bv.sv.stat);
+    const int nt = min(kBatchTop, bv.sv.stat.n_nodes);
+    const uint4 *gn = reinterpret_cast<const uint4 *>(bv.sv.stat.nodes);
+    for (int i = threadIdx.x; i < nt * 4; i += kBatchBlock) pv_top_nodes[i] = gn[i];
+    __syncthreads();
+    src.top = nt;
+    const int local = wave0 - bv.first_wave + (threadIdx.x >> 6);
+    if (local >= bv.n_waves) return;
+    const int lane = threadIdx.x & 63;
+    const int n_bricks = bv.bricks_x * bv.bricks_y * bv.bricks_z;
+    const int j = local / n_bricks, brick = local - j * n_bricks;
+    const int bxi = brick % bv.bricks_x, byi = (brick / bv.bricks_x) % bv.bricks_y,
+              bzi = brick / (bv.bricks_x * bv.bricks_y);
+    const int x = bxi * 4 + (lane & 3), y = byi * 4 + ((lane >> 2) & 3), z = bzi * 4 + (lane >> 4);
+    if (x >= bv.vp.nx || y >= bv.vp.ny || z >= bv.vp.nz) return;
+    Counts cnt = {0, 0};
+    uint32_t sh = 0;
+    trace_shade_one<false, false>(bv.vp, bv.sv, src, frames[v], bv.dirs, bv.rays, bv.hits, x, y, z, j,
+                                  Stack<kBatchBlock, E>{stk + threadIdx.x}, cnt, sh, SplitBuffers());
+}
+
+__global__ __launch_bounds__(kBlendThreads) void k_blend_batched(const BatchVolume *vols, int n_vols) {
+    __shared__ BlendSmem sm;
+    const int g = xcd_logical_block();
+    const int v = __builtin_amdgcn_readfirstlane(find_volume<true>(vols, n_vols, g));
+    const BatchVolume &bv = vols[v];
+    const int p0 = (g - bv.first_blend) * kBlendTile;
     if (bv.fp16)
         blend_tile<__half>(bv.vp, bv.wt, bv.rays, (__half *)bv.irr, (__half *)bv.vis, bv.h, p0, sm);
     else
         blend_tile<float>(bv.vp, bv.wt, bv.rays, (float *)bv.irr, (float *)bv.vis, bv.h, p0, sm);
 }
 
-__device__ __forceinline__ int volume_of_wave(const BatchVolume *vols, int n_vols, int wave) {
-    int v = 0;
-    while (v + 1 < n_vols && vols[v + 1].first_wave <= wave) ++v;
-    return v;
+hipError_t launch_trace_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, const FrameParams *frames_dev,
+                                bool short_stack, hipStream_t s) {
+    static_assert(kBatchWaves * 64 == kBatchBlock, "packets per trace block");
+    const dim3 grid((total_waves + kBatchWaves - 1) / kBatchWaves);
+    const size_t smem = (size_t)kBatchTop * sizeof(GpuNode4);
+    if (short_stack)
+        hipLaunchKernelGGL(k_trace_batched<uint16_t>, grid, dim3(kBatchBlock), smem, s, vols_dev, n_vols, frames_dev);
+    else
+        hipLaunchKernelGGL(k_trace_batched<int>, grid, dim3(kBatchBlock), smem, s, vols_dev, n_vols, frames_dev);
+    return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kBatchBlock) void k_batched(const BatchVolume *vols, int n_vols, int wave_items,
-                                                        int total_blend, const FrameParams *frames, int *queue,
-                                                        int *done, int *status) {
-    __shared__ BatchSmem sm;
-    __shared__ int item_s;
-    const int total = wave_items + total_blend;
-    const int wpi = kBatchBlock / 64;  // trace waves per item
-    while (true) {
-        __syncthreads();
-        if (threadIdx.x == 0) item_s = atomicAdd(queue, 1);
-        __syncthreads();
-        // the item is the same for the whole block: keep it (and what is
-        // derived from it) in scalar registers
-        const int item = __builtin_amdgcn_readfirstlane(item_s);
-        if (item >= total) break;
-        if (item < wave_items) {
-            const int wave = item * wpi + (threadIdx.x >> 6);
-            const int v = volume_of_wave(vols, n_vols, wave);
-            const BatchVolume &bv = vols[v];
-            const int local = wave - bv.first_wave;
-            if (local >= 0 && local < bv.n_waves) {
-                const int lane = threadIdx.x & 63;
-                const int n_bricks = bv.n_waves / bv.vp.n;
-                const int j = local / n_bricks, brick = local - j * n_bricks;
-                const int bxi = brick % bv.bricks_x, byi = (brick / bv.bricks_x) % bv.bricks_y,
-                          bzi = brick / (bv.bricks_x * bv.bricks_y);
-                const int x = bxi * 4 + (lane & 3), y = byi * 4 + ((lane >> 2) & 3), z = bzi * 4 + (lane >> 4);
-                Counts cnt = {0, 0};
-                uint32_t sh = 0;
-                if (x < bv.vp.nx && y < bv.vp.ny && z < bv.vp.nz)
-                    trace_shade_one<false, false>(bv.vp, bv.sv, global_nodes(bv.sv.stat), frames[v],
-                                                               bv.dirs, bv.rays, bv.hits, x, y, z, j,
-                                                               Stack<kBatchBlock>{sm.stk + threadIdx.x}, cnt, sh,
-                                                               SplitBuffers());
-            }
-            __threadfence();
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                for (int k = 0; k < wpi; ++k) {
-                    const int wk = item * wpi + k;
-                    const int vk = volume_of_wave(vols, n_vols, wk);
-                    const int lk = wk - vols[vk].first_wave;
-                    if (lk >= 0 && lk < vols[vk].n_waves) atomicAdd(&done[vk], 1);
-                }
-            }
-        } else {
-            const int g = item - wave_items;
-            int v = 0;
-            while (v + 1 < n_vols && vols[v + 1].first_blend <= g) ++v;
-            v = __builtin_amdgcn_readfirstlane(v);
-            const BatchVolume &bv = vols[v];
-            if (threadIdx.x == 0) {
-                long long spins = 0;
-                while (__hip_atomic_load(&done[v], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < bv.n_waves) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++spins > kSpinLimit) {
-                        atomicExch(status, 1);
-                        break;
-                    }
-                }
-                __threadfence();
-            }
-            __syncthreads();
-            batched_blend_item(bv, (g - bv.first_blend) * kBlendTile, sm.blend);
-        }
-    }
-}
-
-hipError_t launch_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, int total_blend,
-                          const FrameParams *frames_dev, int *queue_dev, int *done_dev, int *status_dev,
-                          hipStream_t s) {
-    const int wave_items = (total_waves + kBatchBlock / 64 - 1) / (kBatchBlock / 64);
-    int dev = 0, cus = 256;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int blocks = cus * 4;
-    hipLaunchKernelGGL(k_batched, dim3(blocks), dim3(kBatchBlock), 0, s, vols_dev, n_vols, wave_items, total_blend,
-                       frames_dev, queue_dev, done_dev, status_dev);
+hipError_t launch_blend_batched(const BatchVolume *vols_dev, int n_vols, int total_blend, hipStream_t s) {
+    hipLaunchKernelGGL(k_blend_batched, dim3(total_blend), dim3(kBlendThreads), 0, s, vols_dev, n_vols);
     return hipGetLastError();
 }
 

@@ -142,7 +142,7 @@ struct BatchVolume {
     void *vis;
     float h;          // effective hysteresis of this frame
     int fp16;
-    int first_wave;   // prefix over volumes of trace waves
+    int first_wave;   // prefix over volumes of trace packets (multiple of 4)
     int n_waves;
     int first_blend;  // prefix over volumes of blend groups
     int n_blend;
@@ -192,9 +192,11 @@ hipError_t launch_shade(const VolumeParams &vp, const SceneView &sv, const Frame
                         float4 *rays, const SplitBuffers &split, hipStream_t s);
 hipError_t launch_blend(const VolumeParams &vp, const WeightTables &wt, const float4 *rays, void *irr, void *vis,
                         int fp16, float h, hipStream_t s);
-hipError_t launch_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, int total_blend,
-                          const FrameParams *frames_dev, int *queue_dev, int *done_dev, int *status_dev,
-                          hipStream_t s);
+// Batched trace / blend over every volume of a batch (descriptors on the
+// device; each volume's first_wave a multiple of 4).
+hipError_t launch_trace_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, const FrameParams *frames_dev,
+                                bool short_stack, hipStream_t s);
+hipError_t launch_blend_batched(const BatchVolume *vols_dev, int n_vols, int total_blend, hipStream_t s);
 hipError_t launch_raydirs_batched(const BatchVolume *vols_dev, const FrameParams *frames_dev, int n_vols,
                                   int max_parts, hipStream_t s);
 
@@ -202,12 +204,13 @@ struct PackBuffers {
     const uint16_t *cur_irr, *cur_vis;   // tiles
     uint16_t *ref_irr, *ref_vis;         // interiors
     uint8_t *mask_irr, *mask_vis;
-    uint32_t *rank_irr, *rank_vis;
+    int4 *tiles;      // per tile of 16 probes: changed counts (irr, vis), last changed probe (irr, vis)
+    uint32_t *done;   // compaction blocks finished
     uint8_t *packet;
 };
 hipError_t launch_pack_mask(const PackBuffers &b, int P, float tau_irr, float tau_vis, hipStream_t s);
-hipError_t launch_pack_scan(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s);
-hipError_t launch_pack_compact(const PackBuffers &b, int P, hipStream_t s);
+hipError_t launch_pack_compact(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s);
+constexpr int kPackTile = 16;  // probes per pack block
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 
 }  // namespace pv

@@ -110,11 +110,17 @@ __device__ __forceinline__ void unpack8(uint4 v, uint16_t r[8]) {
 }
 
 // Change mask of every probe: any interior texel differs (tau = 0) or
-// |cur - ref| > tau.
+// |cur - ref| > tau. Each block also leaves a summary of its tile (changed
+// counts and last changed probe per texture) for the compaction; block 0
+// clears the packet checksum and the compaction's block counter.
 __global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P, float tau_irr, float tau_vis) {
     __shared__ PackSmem sm;
     const int p0 = blockIdx.x * kPackQ;
     if (p0 >= P) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        reinterpret_cast<uint32_t *>(b.packet)[7] = 0u;
+        *b.done = 0u;
+    }
     if (threadIdx.x < kPackQ * 2) sm.changed[threadIdx.x >> 1][threadIdx.x & 1] = 0;
     stage_tiles(b, p0, P, sm);
     __syncthreads();
@@ -137,128 +143,163 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P
         b.mask_irr[p0 + threadIdx.x] = (uint8_t)sm.changed[threadIdx.x][0];
         b.mask_vis[p0 + threadIdx.x] = (uint8_t)sm.changed[threadIdx.x][1];
     }
-}
-
-constexpr int kScanBlock = 1024;
-
-// Inclusive scans across the block with wavefront shuffles and one LDS step.
-__device__ __forceinline__ void block_scan2(int &a, int &m, int *sh_a, int *sh_m, int &total_a) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int ya = __shfl_up(a, off), ym = __shfl_up(m, off);
-        if (lane >= off) {
-            a += ya;
-            m = max(m, ym);
-        }
-    }
-    if (lane == 63) {
-        sh_a[wv] = a;
-        sh_m[wv] = m;
-    }
-    __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kScanBlock / 64; ++w) {
-            sh_a[w] += sh_a[w - 1];
-            sh_m[w] = max(sh_m[w], sh_m[w - 1]);
+        int4 s = make_int4(0, 0, -1, -1);
+        for (int q = 0; q < n; ++q) {
+            if (sm.changed[q][0]) {
+                s.x++;
+                s.z = p0 + q;
+            }
+            if (sm.changed[q][1]) {
+                s.y++;
+                s.w = p0 + q;
+            }
         }
+        b.tiles[blockIdx.x] = s;
     }
-    __syncthreads();
-    if (wv > 0) {
-        a += sh_a[wv - 1];
-        m = max(m, sh_m[wv - 1]);
-    }
-    total_a = sh_a[kScanBlock / 64 - 1];
-    __syncthreads();
 }
 
-// One block: ordered ranks of the changed probes, delta-coded index buffers,
-// the header, and the checksum share of the index section.
-__global__ __launch_bounds__(kScanBlock) void k_pack_scan(PackBuffers b, int P, uint32_t client, uint32_t seq) {
-    __shared__ int sh_a[kScanBlock / 64], sh_m[kScanBlock / 64];
-    __shared__ uint32_t shu[kScanBlock / 64];
-    const int tid = threadIdx.x;
-    // per-thread ranges of a multiple of 16 probes, read as 16-byte vectors
-    // (mask arrays are padded to 65,536 zero bytes)
-    const int per = 16 * ((P + kScanBlock * 16 - 1) / (kScanBlock * 16));
-    const int lo = min(P, tid * per), hi = min(P, lo + per);
-    int ki = 0, kv = 0, last_i = -1, last_v = -1;
-    for (int p = lo; p < hi; p += 16) {
-        const uint4 mi = *reinterpret_cast<const uint4 *>(b.mask_irr + p);
-        const uint4 mv = *reinterpret_cast<const uint4 *>(b.mask_vis + p);
-        const uint32_t wi[4] = {mi.x, mi.y, mi.z, mi.w}, wv[4] = {mv.x, mv.y, mv.z, mv.w};
+// Block reduction of (sum, sum, max, max) over the block's threads.
+__device__ __forceinline__ int4 block_reduce_tiles(int4 v, int4 *sh) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const bool ci = (wi[i >> 2] >> (8 * (i & 3))) & 0xffu, cv = (wv[i >> 2] >> (8 * (i & 3))) & 0xffu;
-            if (ci && p + i < hi) {
-                ++ki;
-                last_i = p + i;
-            }
-            if (cv && p + i < hi) {
-                ++kv;
-                last_v = p + i;
-            }
-        }
+    for (int off = 32; off > 0; off >>= 1) {
+        v.x += __shfl_xor(v.x, off);
+        v.y += __shfl_xor(v.y, off);
+        v.z = max(v.z, __shfl_xor(v.z, off));
+        v.w = max(v.w, __shfl_xor(v.w, off));
     }
-    // inclusive scans; exclusive values are the inclusive ones minus this thread's
-    int ai = ki, mi = last_i, av = kv, mv = last_v, K_irr, K_vis;
-    block_scan2(ai, mi, sh_a, sh_m, K_irr);
-    block_scan2(av, mv, sh_a, sh_m, K_vis);
-    // exclusive max: the previous threads' last changed probe
-    int prev_i = __shfl_up(mi, 1), prev_v = __shfl_up(mv, 1);
-    __shared__ int wlast_i[kScanBlock / 64], wlast_v[kScanBlock / 64];
-    if ((tid & 63) == 63) {
-        wlast_i[tid >> 6] = mi;
-        wlast_v[tid >> 6] = mv;
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int4 r = sh[0];
+    for (int w = 1; w < kPackThreads / 64; ++w) {
+        r.x += sh[w].x;
+        r.y += sh[w].y;
+        r.z = max(r.z, sh[w].z);
+        r.w = max(r.w, sh[w].w);
     }
     __syncthreads();
-    if ((tid & 63) == 0) {
-        prev_i = (tid >> 6) > 0 ? wlast_i[(tid >> 6) - 1] : -1;
-        prev_v = (tid >> 6) > 0 ? wlast_v[(tid >> 6) - 1] : -1;
+    return r;
+}
+
+// Compaction of one tile: its changed probes' ranks (the tile summaries of
+// the blocks before it), their delta-coded index entries, XOR byte planes
+// and reference update, and the plane words' checksum share. The last block
+// to finish hashes the index section and writes the header.
+__global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, int P, uint32_t client, uint32_t seq) {
+    __shared__ PackSmem sm;
+    __shared__ int4 red[kPackThreads / 64];
+    __shared__ int rank_s[kPackQ][2];
+    __shared__ int last_s;
+    const int tile = blockIdx.x, p0 = tile * kPackQ;
+    const int n_tiles = gridDim.x;
+    const int n = min(kPackQ, P - p0);
+    // totals and the prefix before this tile
+    int4 before = make_int4(0, 0, -1, -1), all = make_int4(0, 0, -1, -1);
+    for (int t = threadIdx.x; t < n_tiles; t += kPackThreads) {
+        const int4 s = b.tiles[t];
+        all.x += s.x;
+        all.y += s.y;
+        if (t < tile) {
+            before.x += s.x;
+            before.y += s.y;
+            before.z = max(before.z, s.z);
+            before.w = max(before.w, s.w);
+        }
     }
-    uint8_t *pk = b.packet;
-    uint16_t *idx_i = reinterpret_cast<uint16_t *>(pk + 32);
+    all = block_reduce_tiles(all, red);
+    before = block_reduce_tiles(before, red);
+    const int K_irr = all.x, K_vis = all.y;
+    const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
+    uint16_t *idx_i = reinterpret_cast<uint16_t *>(b.packet + 32);
     uint16_t *idx_v = idx_i + K_irr;
-    int k_i = ai - ki, k_v = av - kv;
-    for (int p0 = lo; p0 < hi; p0 += 16) {
-        const uint4 mi = *reinterpret_cast<const uint4 *>(b.mask_irr + p0);
-        const uint4 mv = *reinterpret_cast<const uint4 *>(b.mask_vis + p0);
-        const uint32_t wi[4] = {mi.x, mi.y, mi.z, mi.w}, wv[4] = {mv.x, mv.y, mv.z, mv.w};
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int p = p0 + i;
-            if (p >= hi) break;
-            if ((wi[i >> 2] >> (8 * (i & 3))) & 0xffu) {
-                b.rank_irr[p] = k_i;
-                idx_i[k_i] = (uint16_t)(k_i == 0 ? p : p - prev_i);
+    const int4 mine = b.tiles[tile];
+    if (threadIdx.x == 0) {
+        // ranks and index entries of the tile's changed probes, in order
+        int ki = before.x, kv = before.y, prev_i = before.z, prev_v = before.w;
+        for (int q = 0; q < n; ++q) {
+            const int p = p0 + q;
+            rank_s[q][0] = rank_s[q][1] = -1;
+            if (b.mask_irr[p]) {
+                idx_i[ki] = (uint16_t)(ki == 0 ? p : p - prev_i);
+                rank_s[q][0] = ki++;
                 prev_i = p;
-                ++k_i;
             }
-            if ((wv[i >> 2] >> (8 * (i & 3))) & 0xffu) {
-                b.rank_vis[p] = k_v;
-                idx_v[k_v] = (uint16_t)(k_v == 0 ? p : p - prev_v);
+            if (b.mask_vis[p]) {
+                idx_v[kv] = (uint16_t)(kv == 0 ? p : p - prev_v);
+                rank_s[q][1] = kv++;
                 prev_v = p;
-                ++k_v;
             }
         }
     }
-    const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
-    if (tid < 16) {  // zero the padding after the entries
-        const int pos = 2 * (K_irr + K_vis) + tid;
+    uint32_t part = 0;
+    if (mine.x + mine.y > 0) {
+        stage_tiles(b, p0, P, sm);
+        __syncthreads();
+        uint8_t *planes_i = b.packet + 32 + idx_bytes;
+        uint8_t *planes_v = planes_i + (size_t)K_irr * 6 * 64;
+        const int units = kPackQ * (kIrrUnits + kVisUnits);
+        for (int u = threadIdx.x; u < units; u += kPackThreads) {
+            const Unit un = unit_of(u);
+            if (un.q >= n) continue;
+            const int k = rank_s[un.q][un.tex];
+            if (k < 0) continue;
+            const int p = p0 + un.q;
+            uint16_t cur[8], ref[8];
+            unit_cur(sm, un, cur);
+            uint16_t *rp = unit_ref(b, p, un);
+            unpack8(*reinterpret_cast<const uint4 *>(rp), ref);
+            uint32_t lo[2] = {0, 0}, hi[2] = {0, 0};
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint16_t x = cur[i] ^ ref[i];
+                lo[i >> 2] |= (uint32_t)(x & 0xff) << (8 * (i & 3));
+                hi[i >> 2] |= (uint32_t)(x >> 8) << (8 * (i & 3));
+            }
+            const int K = un.tex == 0 ? K_irr : K_vis;
+            const size_t NN = (size_t)un.N * un.N, plane_bytes = (size_t)K * NN;
+            uint8_t *dlo = (un.tex == 0 ? planes_i : planes_v) + (size_t)(2 * un.c) * plane_bytes + (size_t)k * NN + un.t0;
+            uint8_t *dhi = dlo + plane_bytes;
+            *reinterpret_cast<uint2 *>(dlo) = make_uint2(lo[0], lo[1]);
+            *reinterpret_cast<uint2 *>(dhi) = make_uint2(hi[0], hi[1]);
+            *reinterpret_cast<uint4 *>(rp) =
+                make_uint4((uint32_t)cur[0] | ((uint32_t)cur[1] << 16), (uint32_t)cur[2] | ((uint32_t)cur[3] << 16),
+                           (uint32_t)cur[4] | ((uint32_t)cur[5] << 16), (uint32_t)cur[6] | ((uint32_t)cur[7] << 16));
+            const uint32_t wlo = (uint32_t)((dlo - (b.packet + 32)) >> 2), whi = (uint32_t)((dhi - (b.packet + 32)) >> 2);
+            part += word_hash(lo[0], wlo) + word_hash(lo[1], wlo + 1) + word_hash(hi[0], whi) + word_hash(hi[1], whi + 1);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if ((threadIdx.x & 63) == 0) sm.part[threadIdx.x >> 6] = part;
+    __syncthreads();
+    uint32_t *h = reinterpret_cast<uint32_t *>(b.packet);
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int w = 0; w < kPackThreads / 64; ++w) s += sm.part[w];
+        if (s) atomicAdd(h + 7, s);
+        // publish this block's index entries, planes and share, then count it
+        __threadfence();
+        last_s = atomicAdd(b.done, 1u) == (uint32_t)(n_tiles - 1);
+    }
+    __syncthreads();
+    if (!last_s) return;
+    // last block: every index entry is written; pad, hash, header
+    __threadfence();
+    uint8_t *pk = b.packet;
+    if (threadIdx.x < 16) {
+        const int pos = 2 * (K_irr + K_vis) + threadIdx.x;
         if (pos < idx_bytes) pk[32 + pos] = 0;
     }
     __syncthreads();
-    // checksum of the index section (payload words 0 .. idx_bytes/4 - 1)
-    uint32_t part = 0;
+    uint32_t ih = 0;
     const uint32_t *words = reinterpret_cast<const uint32_t *>(pk + 32);
-    for (int wi = tid; wi < idx_bytes / 4; wi += kScanBlock) part += word_hash(words[wi], (uint32_t)wi);
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-    if ((tid & 63) == 0) shu[tid >> 6] = part;
+    for (int wi = threadIdx.x; wi < idx_bytes / 4; wi += kPackThreads)
+        ih += word_hash(__builtin_nontemporal_load(words + wi), (uint32_t)wi);
+    for (int off = 32; off > 0; off >>= 1) ih += __shfl_xor(ih, off);
+    if ((threadIdx.x & 63) == 0) sm.part[threadIdx.x >> 6] = ih;
     __syncthreads();
-    if (tid == 0) {
-        uint32_t sum = 0;
-        for (int k = 0; k < kScanBlock / 64; ++k) sum += shu[k];
-        uint32_t *h = reinterpret_cast<uint32_t *>(pk);
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int w = 0; w < kPackThreads / 64; ++w) s += sm.part[w];
         h[0] = 0x4B505650u;
         h[1] = 1u | (32u << 16);
         h[2] = client;
@@ -266,65 +307,7 @@ __global__ __launch_bounds__(kScanBlock) void k_pack_scan(PackBuffers b, int P, 
         h[4] = (uint32_t)P;
         h[5] = (uint32_t)K_irr;
         h[6] = (uint32_t)K_vis;
-        h[7] = sum;
-    }
-}
-
-// XOR byte planes of the sent probes, reference update, checksum share.
-__global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, int P) {
-    __shared__ PackSmem sm;
-    const int p0 = blockIdx.x * kPackQ;
-    if (p0 >= P) return;
-    const int n = min(kPackQ, P - p0);
-    // skip the tile when none of its probes is sent (uniform per block)
-    bool any = false;
-    for (int q = 0; q < n; ++q) any |= (b.mask_irr[p0 + q] | b.mask_vis[p0 + q]) != 0;
-    if (!any) return;
-    stage_tiles(b, p0, P, sm);
-    __syncthreads();
-    const uint32_t *h = reinterpret_cast<const uint32_t *>(b.packet);
-    const int K_irr = (int)h[5], K_vis = (int)h[6];
-    const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
-    uint8_t *planes_i = b.packet + 32 + idx_bytes;
-    uint8_t *planes_v = planes_i + (size_t)K_irr * 6 * 64;
-    uint32_t part = 0;
-    const int units = kPackQ * (kIrrUnits + kVisUnits);
-    for (int u = threadIdx.x; u < units; u += kPackThreads) {
-        const Unit un = unit_of(u);
-        if (un.q >= n) continue;
-        const int p = p0 + un.q;
-        if (!(un.tex == 0 ? b.mask_irr[p] : b.mask_vis[p])) continue;
-        uint16_t cur[8], ref[8];
-        unit_cur(sm, un, cur);
-        uint16_t *rp = unit_ref(b, p, un);
-        unpack8(*reinterpret_cast<const uint4 *>(rp), ref);
-        uint32_t lo[2] = {0, 0}, hi[2] = {0, 0};
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const uint16_t x = cur[i] ^ ref[i];
-            lo[i >> 2] |= (uint32_t)(x & 0xff) << (8 * (i & 3));
-            hi[i >> 2] |= (uint32_t)(x >> 8) << (8 * (i & 3));
-        }
-        const int K = un.tex == 0 ? K_irr : K_vis;
-        const int k = un.tex == 0 ? (int)b.rank_irr[p] : (int)b.rank_vis[p];
-        const size_t NN = (size_t)un.N * un.N, plane_bytes = (size_t)K * NN;
-        uint8_t *dlo = (un.tex == 0 ? planes_i : planes_v) + (size_t)(2 * un.c) * plane_bytes + (size_t)k * NN + un.t0;
-        uint8_t *dhi = dlo + plane_bytes;
-        *reinterpret_cast<uint2 *>(dlo) = make_uint2(lo[0], lo[1]);
-        *reinterpret_cast<uint2 *>(dhi) = make_uint2(hi[0], hi[1]);
-        *reinterpret_cast<uint4 *>(rp) =
-            make_uint4((uint32_t)cur[0] | ((uint32_t)cur[1] << 16), (uint32_t)cur[2] | ((uint32_t)cur[3] << 16),
-                       (uint32_t)cur[4] | ((uint32_t)cur[5] << 16), (uint32_t)cur[6] | ((uint32_t)cur[7] << 16));
-        const uint32_t wlo = (uint32_t)((dlo - (b.packet + 32)) >> 2), whi = (uint32_t)((dhi - (b.packet + 32)) >> 2);
-        part += word_hash(lo[0], wlo) + word_hash(lo[1], wlo + 1) + word_hash(hi[0], whi) + word_hash(hi[1], whi + 1);
-    }
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-    if ((threadIdx.x & 63) == 0) sm.part[threadIdx.x >> 6] = part;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t s = 0;
-        for (int w = 0; w < kPackThreads / 64; ++w) s += sm.part[w];
-        atomicAdd(reinterpret_cast<uint32_t *>(b.packet) + 7, s);
+        atomicAdd(h + 7, s);
     }
 }
 
@@ -338,13 +321,8 @@ hipError_t launch_pack_mask(const PackBuffers &b, int P, float tau_irr, float ta
     return hipGetLastError();
 }
 
-hipError_t launch_pack_scan(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_scan, dim3(1), dim3(kScanBlock), 0, s, b, P, client, seq);
-    return hipGetLastError();
-}
-
-hipError_t launch_pack_compact(const PackBuffers &b, int P, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_compact, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P);
+hipError_t launch_pack_compact(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_compact, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P, client, seq);
     return hipGetLastError();
 }
 

@@ -41,7 +41,6 @@ extern "C" const char *pv_version(void) { return "probestream 1.0 gfx950"; }
 struct BatchSlot {
     BatchVolume *batch_dev = nullptr;
     FrameParams *frames_dev = nullptr;
-    int *counters_dev = nullptr;  // [0] queue, [1] status, [2..] done per volume
     int cap = 0;
     void *stage_host = nullptr;
     hipEvent_t done = nullptr;
@@ -127,7 +126,8 @@ struct pv_client {
     uint32_t id = 0, seq = 0;
     uint16_t *ref_irr = nullptr, *ref_vis = nullptr;
     uint8_t *mask_irr = nullptr, *mask_vis = nullptr;
-    uint32_t *rank_irr = nullptr, *rank_vis = nullptr;
+    int4 *tiles = nullptr;         // per-tile summaries of the last mask pass
+    uint32_t *done = nullptr;      // compaction block counter
     uint8_t *packet = nullptr;
     uint64_t packet_cap = 0;
     uint32_t *hdr_host = nullptr;  // pinned, 32 bytes
@@ -198,7 +198,6 @@ extern "C" pv_status pv_ctx_destroy(pv_ctx *c) {
         BatchSlot &b = c->slots[i];
         hipFree(b.batch_dev);
         hipFree(b.frames_dev);
-        hipFree(b.counters_dev);
         if (b.stage_host) hipHostFree(b.stage_host);
         if (b.done) hipEventDestroy(b.done);
     }
@@ -748,18 +747,13 @@ static pv_status ensure_slot(pv_ctx *c, BatchSlot &b, int n) {
     if (n <= b.cap) return PV_OK;
     hipFree(b.batch_dev);
     hipFree(b.frames_dev);
-    hipFree(b.counters_dev);
     if (b.stage_host) hipHostFree(b.stage_host);
     b.batch_dev = nullptr;
     b.frames_dev = nullptr;
-    b.counters_dev = nullptr;
     b.stage_host = nullptr;
     b.cap = 0;
     PV_TRY(dev_alloc(&b.batch_dev, sizeof(BatchVolume) * n, "batch descriptors"));
     PV_TRY(dev_alloc(&b.frames_dev, sizeof(FrameParams) * n, "batch frames"));
-    PV_TRY(dev_alloc(&b.counters_dev, sizeof(int) * (2 + n), "batch counters"));
-    HIP_TRY(launch_zero(b.counters_dev, sizeof(int) * (2 + n), c->stream));  // fresh status word
-    HIP_TRY(hipStreamSynchronize(c->stream));
     const size_t bytes = (sizeof(BatchVolume) + sizeof(FrameParams)) * n + 256;
     HIP_TRY(hipHostMalloc(&b.stage_host, bytes));
     b.cap = n;
@@ -775,6 +769,7 @@ struct pv_batch_graph {
     BatchSlot slot;           // device descriptors + pinned staging owned by the graph
     size_t o_b = 0, o_f = 0, bytes = 0;
     int waves = 0, blend = 0, max_parts = 0;
+    bool short_stack = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -782,21 +777,24 @@ struct pv_batch_graph {
 };
 
 // Fills the pinned staging of a batch: descriptors and frames; returns the
-// wave and blend-group totals and the most ray-direction blocks of a volume.
+// packet and blend-group totals, the most ray-direction blocks of a volume,
+// and whether every BVH of the batch fits 16-bit stack entries.
 static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int n, char *h, size_t *offs, int &waves,
-                            int &blend, int &max_parts) {
+                            int &blend, int &max_parts, bool &short_stack) {
     std::vector<BatchVolume> bv(n);
     std::vector<FrameParams> fps(n);
     std::memset(fps.data(), 0, sizeof(FrameParams) * n);
     waves = 0;
     blend = 0;
     max_parts = 0;
+    short_stack = true;
     for (int i = 0; i < n; ++i) {
         pv_volume *v = vols[i];
         if (frames) PV_TRY(frame_params(&frames[i], v->scene, fps[i]));
         BatchVolume &b = bv[i];
         b.vp = volume_params(v);
         b.sv = scene_view(v->scene);
+        short_stack = short_stack && b.sv.stat.n_nodes <= 65536 && b.sv.dyn.n_nodes <= 65536;
         b.dirs = v->dirs;
         b.wt = v->wt;
         max_parts = std::max(max_parts, v->wt.nparts);
@@ -810,7 +808,7 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
         b.bricks_y = (v->desc.ny + 3) / 4;
         b.bricks_z = (v->desc.nz + 3) / 4;
         b.n_waves = b.bricks_x * b.bricks_y * b.bricks_z * v->n;
-        waves = (waves + 3) / 4 * 4;  // trace items hold 4 waves; each volume starts on an item boundary
+        waves = (waves + 3) / 4 * 4;  // trace blocks hold 4 packets; each volume starts on a block boundary
         b.first_wave = waves;
         waves += b.n_waves;
         b.n_blend = (v->P + kBlendTile - 1) / kBlendTile;
@@ -857,19 +855,16 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
     PV_TRY(ensure_slot(c, slot, n));
     size_t offs[3];
     int waves, blend, max_parts;
+    bool short_stack;
     char *h = (char *)slot.stage_host;
-    PV_TRY(fill_batch(vols, frames, n, h, offs, waves, blend, max_parts));
+    PV_TRY(fill_batch(vols, frames, n, h, offs, waves, blend, max_parts, short_stack));
     HIP_TRY(hipMemcpyAsync(slot.batch_dev, h + offs[0], sizeof(BatchVolume) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(slot.frames_dev, h + offs[1], sizeof(FrameParams) * n, hipMemcpyHostToDevice, s));
-    // queue counter and per-volume done counters start at zero (status word kept)
-    HIP_TRY(launch_zero(slot.counters_dev, sizeof(int), s));
-    HIP_TRY(launch_zero(slot.counters_dev + 2, sizeof(int) * n, s));
     HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s,
                   [&] { return launch_raydirs_batched(slot.batch_dev, slot.frames_dev, n, max_parts, s); }));
-    HIP_TRY(timed(c, PV_STAGE_BATCHED, s, [&] {
-        return launch_batched(slot.batch_dev, n, waves, blend, slot.frames_dev, slot.counters_dev,
-                              slot.counters_dev + 2, slot.counters_dev + 1, s);
-    }));
+    HIP_TRY(timed(c, PV_STAGE_BATCHED, s,
+                  [&] { return launch_trace_batched(slot.batch_dev, n, waves, slot.frames_dev, short_stack, s); }));
+    HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend_batched(slot.batch_dev, n, blend, s); }));
     HIP_TRY(hipEventRecord(slot.done, s));
     for (int i = 0; i < n; ++i) {
         PV_TRY(note_scene_use(vols[i]->scene, s));
@@ -885,7 +880,6 @@ static void free_graph(pv_batch_graph *g) {
     BatchSlot &b = g->slot;
     hipFree(b.batch_dev);
     hipFree(b.frames_dev);
-    hipFree(b.counters_dev);
     if (b.stage_host) hipHostFree(b.stage_host);
     delete g;
 }
@@ -903,7 +897,8 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
         st = fail(PV_ERR_DEVICE, "event");
     size_t offs[3];
     if (st == PV_OK)
-        st = fill_batch(vols, nullptr, n, (char *)g->slot.stage_host, offs, g->waves, g->blend, g->max_parts);
+        st = fill_batch(vols, nullptr, n, (char *)g->slot.stage_host, offs, g->waves, g->blend, g->max_parts,
+                        g->short_stack);
     if (st != PV_OK) {
         free_graph(g);
         return st;
@@ -911,7 +906,7 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
     g->o_b = offs[0];
     g->o_f = offs[1];
     g->bytes = offs[2];
-    // capture on a private stream: copy node, zero fill, ray directions, batched kernel
+    // capture on a private stream: copy nodes, ray directions, trace, blend
     hipStream_t cs = nullptr;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     BatchSlot &b = g->slot;
@@ -919,12 +914,9 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) e = hipMemcpyAsync(b.batch_dev, h + g->o_b, sizeof(BatchVolume) * n, hipMemcpyHostToDevice, cs);
     if (e == hipSuccess) e = hipMemcpyAsync(b.frames_dev, h + g->o_f, sizeof(FrameParams) * n, hipMemcpyHostToDevice, cs);
-    if (e == hipSuccess) e = launch_zero(b.counters_dev, sizeof(int), cs);
-    if (e == hipSuccess) e = launch_zero(b.counters_dev + 2, sizeof(int) * n, cs);
     if (e == hipSuccess) e = launch_raydirs_batched(b.batch_dev, b.frames_dev, n, g->max_parts, cs);
-    if (e == hipSuccess)
-        e = launch_batched(b.batch_dev, n, g->waves, g->blend, b.frames_dev, b.counters_dev, b.counters_dev + 2,
-                           b.counters_dev + 1, cs);
+    if (e == hipSuccess) e = launch_trace_batched(b.batch_dev, n, g->waves, b.frames_dev, g->short_stack, cs);
+    if (e == hipSuccess) e = launch_blend_batched(b.batch_dev, n, g->blend, cs);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &graph);
     if (e == hipSuccess) e = e2;
@@ -955,7 +947,11 @@ extern "C" pv_status pv_batch_graph_launch(pv_batch_graph *g, const pv_frame *fr
     if (g->launched) HIP_TRY(hipEventSynchronize(g->done));
     size_t offs[3];
     int waves, blend, max_parts;
-    PV_TRY(fill_batch(g->vols.data(), frames, n, (char *)g->slot.stage_host, offs, waves, blend, max_parts));
+    bool short_stack;
+    PV_TRY(fill_batch(g->vols.data(), frames, n, (char *)g->slot.stage_host, offs, waves, blend, max_parts,
+                      short_stack));
+    if (waves != g->waves || blend != g->blend || short_stack != g->short_stack)
+        return fail(PV_ERR_STATE, "a volume of the graph changed scene since the graph was captured");
     hipStream_t s = pick(c, stream);
     HIP_TRY(timed(c, PV_STAGE_BATCHED, s, [&] { return hipGraphLaunch(g->exec, s); }));
     HIP_TRY(hipEventRecord(g->done, s));
@@ -982,7 +978,7 @@ extern "C" pv_status pv_client_footprint(const pv_volume_desc *d, uint64_t *byte
     PV_TRY(validate_desc(d));
     if (!bytes) return fail(PV_ERR_ARG, "bytes is NULL");
     const uint64_t P = (uint64_t)d->nx * d->ny * d->nz;
-    *bytes = P * (192 + 512) * 2 + 2 * (PV_MAX_PROBES + 16) + P * 8 + packet_capacity((int)P);
+    *bytes = P * (192 + 512) * 2 + 2 * P + (P + kPackTile - 1) / kPackTile * 16 + 4 + packet_capacity((int)P);
     return PV_OK;
 }
 
@@ -991,8 +987,8 @@ static void free_client(pv_client *c) {
     hipFree(c->ref_vis);
     hipFree(c->mask_irr);
     hipFree(c->mask_vis);
-    hipFree(c->rank_irr);
-    hipFree(c->rank_vis);
+    hipFree(c->tiles);
+    hipFree(c->done);
     hipFree(c->packet);
     if (c->hdr_host) hipHostFree(c->hdr_host);
     delete c;
@@ -1010,19 +1006,17 @@ extern "C" pv_status pv_client_create(pv_volume *v, uint32_t id, pv_client **out
     c->packet_cap = packet_capacity(P);
     pv_status st = dev_alloc(&c->ref_irr, (size_t)P * 192 * 2, "irradiance reference");
     if (st == PV_OK) st = dev_alloc(&c->ref_vis, (size_t)P * 512 * 2, "visibility reference");
-    // masks padded to the index limit and zeroed: the scan reads them in
-    // 16-byte vectors past P
-    if (st == PV_OK) st = dev_alloc(&c->mask_irr, (size_t)PV_MAX_PROBES + 16, "mask");
-    if (st == PV_OK) st = dev_alloc(&c->mask_vis, (size_t)PV_MAX_PROBES + 16, "mask");
-    if (st == PV_OK) st = dev_alloc(&c->rank_irr, (size_t)P * 4, "ranks");
-    if (st == PV_OK) st = dev_alloc(&c->rank_vis, (size_t)P * 4, "ranks");
+    if (st == PV_OK) st = dev_alloc(&c->mask_irr, (size_t)P, "mask");
+    if (st == PV_OK) st = dev_alloc(&c->mask_vis, (size_t)P, "mask");
+    if (st == PV_OK) st = dev_alloc(&c->tiles, (size_t)(P + kPackTile - 1) / kPackTile * sizeof(int4), "tile summaries");
+    if (st == PV_OK) st = dev_alloc(&c->done, sizeof(uint32_t), "pack counter");
     if (st == PV_OK) st = dev_alloc(&c->packet, c->packet_cap, "packet");
     if (st == PV_OK && hipHostMalloc((void **)&c->hdr_host, 32) != hipSuccess) st = fail(PV_ERR_OOM, "pinned header");
     hipStream_t s = v->ctx->stream;
     if (st == PV_OK && (launch_zero(c->ref_irr, (size_t)P * 192 * 2, s) != hipSuccess ||
                         launch_zero(c->ref_vis, (size_t)P * 512 * 2, s) != hipSuccess ||
-                        launch_zero(c->mask_irr, (size_t)PV_MAX_PROBES + 16, s) != hipSuccess ||
-                        launch_zero(c->mask_vis, (size_t)PV_MAX_PROBES + 16, s) != hipSuccess ||
+                        launch_zero(c->mask_irr, (size_t)P, s) != hipSuccess ||
+                        launch_zero(c->mask_vis, (size_t)P, s) != hipSuccess ||
                         launch_zero(c->packet, 32, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess))
         st = fail(PV_ERR_DEVICE, "client initialisation");
     if (st != PV_OK) {
@@ -1064,15 +1058,14 @@ extern "C" pv_status pv_pack_delta(pv_client *c, float tau_irr, float tau_vis, v
     b.ref_vis = c->ref_vis;
     b.mask_irr = c->mask_irr;
     b.mask_vis = c->mask_vis;
-    b.rank_irr = c->rank_irr;
-    b.rank_vis = c->rank_vis;
+    b.tiles = c->tiles;
+    b.done = c->done;
     b.packet = c->packet;
     pv_ctx *cx = v->ctx;
     const int P = v->P;
     const uint32_t id = c->id, seq = c->seq;
     HIP_TRY(timed(cx, PV_STAGE_PACK_MASK, s, [&] { return launch_pack_mask(b, P, tau_irr, tau_vis, s); }));
-    HIP_TRY(timed(cx, PV_STAGE_PACK_SCAN, s, [&] { return launch_pack_scan(b, P, id, seq, s); }));
-    HIP_TRY(timed(cx, PV_STAGE_PACK_COMPACT, s, [&] { return launch_pack_compact(b, P, s); }));
+    HIP_TRY(timed(cx, PV_STAGE_PACK_COMPACT, s, [&] { return launch_pack_compact(b, P, id, seq, s); }));
     c->seq++;
     return PV_OK;
 }
@@ -1135,17 +1128,3 @@ extern "C" pv_status pv_sync(void *stream) {
     return PV_OK;
 }
 
-extern "C" pv_status pv_ctx_check(pv_ctx *c, int *status) {
-    // status word of the batched work queue (1 = a bounded wait expired)
-    if (!c || !status) return fail(PV_ERR_ARG, "NULL argument");
-    *status = 0;
-    HIP_TRY(hipSetDevice(c->device));
-    HIP_TRY(hipDeviceSynchronize());
-    for (int i = 0; i < pv_ctx::kRing; ++i) {
-        if (!c->slots[i].counters_dev) continue;
-        int st = 0;
-        HIP_TRY(hipMemcpy(&st, c->slots[i].counters_dev + 1, sizeof(int), hipMemcpyDeviceToHost));
-        *status |= st;
-    }
-    return PV_OK;
-}

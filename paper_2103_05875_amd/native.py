@@ -30,7 +30,7 @@ EXPORTED_SYMBOLS = [
     "pv_blend_rays", "pv_get_maps", "pv_get_rays", "pv_set_maps", "pv_read_maps",
     "pv_client_create", "pv_client_destroy", "pv_client_reset", "pv_client_footprint",
     "pv_pack_delta", "pv_packet_device", "pv_packet_download", "pv_get_masks", "pv_sync",
-    "pv_ctx_check", "pv_trace_counts", "pv_ctx_set_timing", "pv_ctx_stage_times",
+    "pv_trace_counts", "pv_ctx_set_timing", "pv_ctx_stage_times",
     "pv_client_read_state", "pv_client_set_state", "pv_volume_set_trace_config", "pv_volume_get_trace_config",
     "pv_batch_graph_create", "pv_batch_graph_launch", "pv_batch_graph_destroy",
 ]
@@ -126,7 +126,6 @@ def lib():
         "pv_packet_download": ([vp, vp, u64, P(u64), vp], i32),
         "pv_get_masks": ([vp, P(vp), P(vp)], i32),
         "pv_sync": ([vp], i32),
-        "pv_ctx_check": ([vp, P(i32)], i32),
         "pv_trace_counts": ([vp, P(Frame), P(u64)], i32),
         "pv_ctx_set_timing": ([vp, i32], i32),
         "pv_client_read_state": ([vp, vp, vp, P(u32)], i32),
@@ -216,11 +215,6 @@ class Context:
         cnt = (ctypes.c_uint64 * len(STAGES))()
         _check(lib().pv_ctx_stage_times(self.h, ms, cnt))
         return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
-
-    def check(self) -> int:
-        st = ctypes.c_int(0)
-        _check(lib().pv_ctx_check(self.h, ctypes.byref(st)))
-        return st.value
 
     def close(self):
         if getattr(self, "h", None):

