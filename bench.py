@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--counters", default=os.path.join(ROOT, "profiles", "k_trace_city_counters.txt"),
                     help="HBM byte counters of the trace kernel (rocprofv3 --pmc), used for roofline.traffic "
                          "when they were taken on the current kernel source and launch shape")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="CSV", default=None,
+                    help="no GPU work: print the mean per dispatch of every counter in rocprofv3 --pmc "
+                         "counter_collection.csv files, per kernel")
     ap.add_argument("--write-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT"), default=None,
                     help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, "
                          "WRITE_SIZE) of this bench run with --calibrate-copy into the counters file")
@@ -142,6 +145,26 @@ def write_counters(fetch_csv, write_csv, out, trace_config):
         f.write(f"trace_config: {trace_config}\n")
         f.write(f"source_sha256: {kernel_source_hash()}\n")
     return fetch + write
+
+
+def summarize_counters(paths):
+    """Mean per dispatch of each counter, per kernel (template arguments
+    kept, parameters dropped), from rocprofv3 --pmc CSV files."""
+    import csv
+    import collections
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = []
+    for k in sorted(acc):
+        lines.append(k)
+        for c in sorted(acc[k]):
+            v = acc[k][c]
+            lines.append(f"    {c:28s} dispatches {len(v):4d}  mean {sum(v) / len(v):.6g}")
+    return "\n".join(lines)
 
 
 def cpu_baseline(cfg, scene, path, budget_s: float):
@@ -349,6 +372,9 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(this build runs the hot path on a single GPU and has no cross-GPU exchange)", file=sys.stderr)
         sys.exit(2)
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters))
+        return
     if args.write_counters:
         if not args.trace_config:
             sys.exit("--write-counters needs the --trace-config the counters were taken with")

@@ -103,9 +103,10 @@ template <typename T>
 __global__ __launch_bounds__(kBlendThreads) void k_blend(VolumeParams vp, WeightTables wt, const float4 *rays, T *irr,
                                                          T *vis, float h) {
     __shared__ BlendSmem sm;
-    const int p0 = xcd_logical_block() * kBlendTile;
+    const int blk = xcd_logical_block();
+    const int p0 = (blk / kBlendSplit) * kBlendTile;
     if (p0 >= vp.P) return;
-    blend_tile<T>(vp, wt, rays, irr, vis, h, p0, sm);
+    blend_tile<T>(vp, wt, rays, irr, vis, h, p0, blk % kBlendSplit, sm);
 }
 
 hipError_t launch_raydirs(const FrameParams &fp, const VolumeParams &vp, float4 *dirs, const WeightTables &wt,
@@ -124,7 +125,7 @@ hipError_t launch_raydirs_batched(const BatchVolume *vols_dev, const FrameParams
 
 hipError_t launch_blend(const VolumeParams &vp, const WeightTables &wt, const float4 *rays, void *irr, void *vis,
                         int fp16, float h, hipStream_t s) {
-    const dim3 grid((vp.P + kBlendTile - 1) / kBlendTile);
+    const dim3 grid((vp.P + kBlendTile - 1) / kBlendTile * kBlendSplit);
     if (fp16)
         hipLaunchKernelGGL(k_blend<__half>, grid, dim3(kBlendThreads), 0, s, vp, wt, rays, (__half *)irr,
                            (__half *)vis, h);

@@ -15,6 +15,7 @@
 #pragma once
 
 #include "device_common.h"
+#include "blend_layout.h"
 
 namespace pv {
 
@@ -24,6 +25,7 @@ constexpr int kIrrRows = 64;          // irradiance interior texels
 constexpr int kBlendThreads = 256;    // four wavefronts
 constexpr int kBlendK = 128;          // rays staged in LDS per step
 static_assert(kBlendK == 128, "the weight tables are zero-padded to a multiple of 128 rays");
+static_assert(kBlendSplit == 2 && kBlendThreads == 256, "blend_tile maps 2 x 4 waves onto the texel rows");
 
 // Centre direction of interior texel (i, j) of an N x N octahedral map.
 __device__ __forceinline__ float3 oct_texel_dir(int N, int i, int j) {
@@ -106,32 +108,36 @@ __device__ __forceinline__ void blend_store(T *tile, int N, int t, float sum, fl
     store_with_guard<T>(tile, N, i, jr, to_map<T>(nv));
 }
 
-// Blend of probes p0 .. p0+7 by one block of four wavefronts.
+// Blend of probes p0 .. p0+7, rows half 'part' (0 or 1), by one block of
+// four wavefronts; the two halves of a tile are independent blocks.
 //
 // 16x16x4 FP32 MFMA operand layout (lane l of the wave): A[m][k] with
 // m = l % 16, k = l / 16; B[k][n] with k = l / 16, n = l % 16; result
 // D[m][n] in register r with m = 4 (l / 16) + r, n = l % 16.
 // Columns n of B: visibility n = 8 c + q (channel c = r or r^2, probe q);
 // irradiance tile 0 n = 8 c + q (c = red, green), tile 1 n = q (blue; the
-// upper eight columns are zero). Wave w owns irradiance rows 16w .. 16w+15
-// (both tiles) and visibility rows 64w .. 64w+63 (four tiles).
+// upper eight columns are zero). The 8 waves of a tile (g = 4 part + wave)
+// each own three 16-row MFMA tiles: visibility rows 32g .. 32g+31 and
+// irradiance rows 16 (g / 2) .. +15 of colour tile g % 2.
 template <typename T>
 __device__ void blend_tile(const VolumeParams &vp, const WeightTables &wt, const float4 *rays, T *irr, T *vis,
-                           float h, int p0, BlendSmem &sm) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+                           float h, int p0, int part, BlendSmem &sm) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int g = part * 4 + (tid >> 6);
     const int n = vp.n, P = vp.P;
     const int col = lane & 15, krow = lane >> 4;
     const int q = col & 7, half = col >> 3;
+    const int ctile = g & 1;  // irradiance colour tile: 0 = red/green, 1 = blue
 
     for (int t = tid; t < kTexRows; t += kBlendThreads) {
         float s = 0.f;
         for (int b = 0; b < wt.nparts; ++b) s += wt.part[b * kTexRows + t];
         sm.rows[t] = s;
     }
-    v4f acc_i0 = {0.f, 0.f, 0.f, 0.f}, acc_i1 = acc_i0;
-    v4f acc_v[4] = {acc_i0, acc_i0, acc_i0, acc_i0};
-    const int row_i = 16 * wave + col;
-    const int row_v = kIrrRows + 64 * wave + col;
+    v4f acc_i = {0.f, 0.f, 0.f, 0.f};
+    v4f acc_v0 = acc_i, acc_v1 = acc_i;
+    const int row_i = 16 * (g >> 1) + col;
+    const int row_v = kIrrRows + 32 * g + col;
 
     for (int j0 = 0; j0 < n; j0 += kBlendK) {
         const int m = min(kBlendK, n - j0);
@@ -147,38 +153,32 @@ __device__ void blend_tile(const VolumeParams &vp, const WeightTables &wt, const
         // runs on the matrix cores.
         const int steps = ((m + 15) >> 4) << 2;
         const float *wg = wt.w + (size_t)(j0 >> 2) * (4 * kTexRows) + krow;
-        float nxt[4][5];
-        auto load_group = [&](int k0, float a[4][5]) {
+        float nxt[4][3];
+        auto load_group = [&](int k0, float a[4][3]) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const float *w = wg + (size_t)(k0 + u) * (4 * kTexRows);
                 a[u][0] = w[4 * row_i];
                 a[u][1] = w[4 * row_v];
                 a[u][2] = w[4 * (row_v + 16)];
-                a[u][3] = w[4 * (row_v + 32)];
-                a[u][4] = w[4 * (row_v + 48)];
             }
         };
         load_group(0, nxt);
         for (int k0 = 0; k0 < steps; k0 += 4) {
-            float cur[4][5];
+            float cur[4][3];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int x = 0; x < 5; ++x) cur[u][x] = nxt[u][x];
+                for (int x = 0; x < 3; ++x) cur[u][x] = nxt[u][x];
             if (k0 + 4 < steps) load_group(k0 + 4, nxt);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const float4 r4 = sm.rec[4 * (k0 + u) + krow][q];
                 const float bv = half ? r4.w * r4.w : r4.w;
-                const float bi0 = half ? r4.y : r4.x;
-                const float bi1 = half ? 0.f : r4.z;
-                acc_i0 = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u][0], bi0, acc_i0, 0, 0, 0);
-                acc_i1 = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u][0], bi1, acc_i1, 0, 0, 0);
-                acc_v[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u][1], bv, acc_v[0], 0, 0, 0);
-                acc_v[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u][2], bv, acc_v[1], 0, 0, 0);
-                acc_v[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u][3], bv, acc_v[2], 0, 0, 0);
-                acc_v[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u][4], bv, acc_v[3], 0, 0, 0);
+                const float bi = ctile ? (half ? 0.f : r4.z) : (half ? r4.y : r4.x);
+                acc_i = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u][0], bi, acc_i, 0, 0, 0);
+                acc_v0 = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u][1], bv, acc_v0, 0, 0, 0);
+                acc_v1 = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u][2], bv, acc_v1, 0, 0, 0);
             }
         }
     }
@@ -187,20 +187,15 @@ __device__ void blend_tile(const VolumeParams &vp, const WeightTables &wt, const
     if (p >= P) return;
     T *itile = irr + (size_t)p * 3 * 100;
     T *vtile = vis + (size_t)p * 2 * 324;
+    const int ch = ctile ? 2 : half;  // irradiance channel of this lane's column
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int ti = 16 * wave + 4 * krow + r;
-        const float tot = sm.rows[ti];
-        blend_store<T>(itile + half * 100, 8, ti, acc_i0[r], tot, h);
-        if (half == 0) blend_store<T>(itile + 2 * 100, 8, ti, acc_i1[r], tot, h);
+        const int ti = 16 * (g >> 1) + 4 * krow + r;
+        if (!(ctile && half)) blend_store<T>(itile + ch * 100, 8, ti, acc_i[r], sm.rows[ti], h);
+        const int tv0 = 32 * g + 4 * krow + r, tv1 = tv0 + 16;
+        blend_store<T>(vtile + half * 324, 16, tv0, acc_v0[r], sm.rows[kIrrRows + tv0], h);
+        blend_store<T>(vtile + half * 324, 16, tv1, acc_v1[r], sm.rows[kIrrRows + tv1], h);
     }
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int tv = 64 * wave + 16 * b + 4 * krow + r;
-            blend_store<T>(vtile + half * 324, 16, tv, acc_v[b][r], sm.rows[kIrrRows + tv], h);
-        }
 }
 
 }  // namespace pv

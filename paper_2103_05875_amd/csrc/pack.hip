@@ -213,21 +213,27 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
     uint16_t *idx_i = reinterpret_cast<uint16_t *>(b.packet + 32);
     uint16_t *idx_v = idx_i + K_irr;
     const int4 mine = b.tiles[tile];
-    if (threadIdx.x == 0) {
-        // ranks and index entries of the tile's changed probes, in order
-        int ki = before.x, kv = before.y, prev_i = before.z, prev_v = before.w;
-        for (int q = 0; q < n; ++q) {
-            const int p = p0 + q;
+    if (threadIdx.x < 64) {
+        // ranks and index entries of the tile's changed probes: lane q owns
+        // probe p0 + q; its rank counts the changed lanes below it, its
+        // predecessor is the highest of them (or the last one before the tile)
+        const int q = threadIdx.x, p = p0 + q;
+        const bool ci = q < n && b.mask_irr[p] != 0, cv = q < n && b.mask_vis[p] != 0;
+        const unsigned long long below = (1ull << q) - 1ull;
+        const unsigned long long mi = __ballot(ci) & below, mv = __ballot(cv) & below;
+        if (q < kPackQ) {
             rank_s[q][0] = rank_s[q][1] = -1;
-            if (b.mask_irr[p]) {
-                idx_i[ki] = (uint16_t)(ki == 0 ? p : p - prev_i);
-                rank_s[q][0] = ki++;
-                prev_i = p;
+            if (ci) {
+                const int k = before.x + __popcll(mi);
+                const int prev = mi ? p0 + 63 - __clzll((long long)mi) : before.z;
+                idx_i[k] = (uint16_t)(k == 0 ? p : p - prev);
+                rank_s[q][0] = k;
             }
-            if (b.mask_vis[p]) {
-                idx_v[kv] = (uint16_t)(kv == 0 ? p : p - prev_v);
-                rank_s[q][1] = kv++;
-                prev_v = p;
+            if (cv) {
+                const int k = before.y + __popcll(mv);
+                const int prev = mv ? p0 + 63 - __clzll((long long)mv) : before.w;
+                idx_v[k] = (uint16_t)(k == 0 ? p : p - prev);
+                rank_s[q][1] = k;
             }
         }
     }

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "blend_layout.h"
 
 using namespace pv;
 
@@ -811,7 +812,7 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
         waves = (waves + 3) / 4 * 4;  // trace blocks hold 4 packets; each volume starts on a block boundary
         b.first_wave = waves;
         waves += b.n_waves;
-        b.n_blend = (v->P + kBlendTile - 1) / kBlendTile;
+        b.n_blend = (v->P + kBlendTile - 1) / kBlendTile * kBlendSplit;
         b.first_blend = blend;
         blend += b.n_blend;
     }
