@@ -260,16 +260,18 @@ pv_status pv_sync(void *stream);
  * Launch shape of the trace kernel (a tuning choice; every shape computes
  * identical results): probes per wavefront packet as a brick
  * brick[0] x brick[1] x brick[2] = 64 of one ray direction (this also fixes
- * the order in which rays are dealt out), the grid: one wavefront per packet
- * (persistent 0) or a persistent grid whose lanes each take a new ray from
- * per-XCD work queues as soon as theirs ends, with node visits and leaf
- * triangle tests scheduled as separate wave steps (persistent 1), the number
+ * the order in which rays are dealt out), the grid and schedule: one
+ * wavefront per packet (persistent 0); a persistent grid whose lanes each take
+ * a new ray from per-XCD work queues as soon as theirs ends, with node visits
+ * and leaf triangle tests scheduled as separate wave steps (persistent 1); one
+ * wavefront per packet with those separate steps and each lane's shadow rays
+ * started as soon as its primary ray ends (persistent 2), the number
  * of top BVH nodes staged in LDS (0, 21 or 85: one, three or four levels),
  * threads per block (128 or 256), and whether shadow rays are traced inside
  * the primary kernel (0) or appended to a compacted queue and traced by a
  * dense second kernel, then applied by a shade kernel (1; the primary kernel
  * then runs one wavefront per packet whatever 'persistent' says). Defaults:
- * 4x4x4, 0, 0, 128, 0.
+ * 4x4x4, 2, 21, 256, 0.
  */
 typedef struct {
     int brick[3];

@@ -19,7 +19,7 @@ import os
 from typing import Dict, List, Optional
 
 BRICKS = [(4, 4, 4), (8, 8, 1), (8, 4, 2), (16, 4, 1), (2, 4, 8)]
-PERSISTENT = [False, True]
+PERSISTENT = [0, 1, 2]   # packet / persistent with ray refill / packet with node and triangle steps
 TOP_NODES = [0, 21, 85]
 BLOCKS = [128, 256]
 SPLIT = [False, True]
@@ -29,7 +29,7 @@ SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx95
 
 
 def candidates() -> List[dict]:
-    # the split-shadow trace always runs one wave per packet: no persistent variant
+    # the split-shadow trace always runs the plain packet kernel: no other schedule
     return [{"brick": b, "persistent": p, "top_nodes": t, "block_threads": w, "split_shadows": s}
             for b, p, t, w, s in itertools.product(BRICKS, PERSISTENT, TOP_NODES, BLOCKS, SPLIT)
             if not (p and s)]
@@ -104,8 +104,8 @@ def tune(volume, rotation, lights=None, n_triangles: int = 0, reps: int = 3,
     if cache:
         data = _load(cache)
         data[k] = {"config": {**best, "brick": list(best["brick"])}, "ms": best_ms,
-                   "default_ms": next(ms for ms, c in results if c["brick"] == (4, 4, 4) and not c["persistent"]
-                                      and c["top_nodes"] == 0 and c["block_threads"] == 128
+                   "default_ms": next(ms for ms, c in results if c["brick"] == (4, 4, 4) and c["persistent"] == 2
+                                      and c["top_nodes"] == 21 and c["block_threads"] == 256
                                       and not c["split_shadows"]),
                    "all": [[round(ms, 4), {**c, "brick": list(c["brick"])}] for ms, c in results]}
         _save(cache, data)

@@ -3,7 +3,8 @@
 // and one blend launch every probe group of every volume. Each block belongs
 // to one volume and finds it by binary search over the per-volume prefix
 // counts, so volumes of different sizes, ray counts, scenes and map formats
-// share the device without a launch per volume. Results are bit-identical
+// share the device without a launch per volume. The trace runs the stepped
+// lane loop (separate node and triangle steps) on 4x4x4 probe packets. Results are bit-identical
 // to the per-volume launches: each ray and each probe group runs the same
 // device code on the same inputs.
 #include "blend_device.h"
@@ -44,19 +45,25 @@ __global__ __launch_bounds__(kBatchBlock) void k_trace_batched(const BatchVolume
     for (int i = threadIdx.x; i < nt * 4; i += kBatchBlock) pv_top_nodes[i] = gn[i];
     __syncthreads();
     src.top = nt;
+    // the packet of this wave in the volume's packet order (4x4x4 bricks),
+    // traced with the stepped lane loop
+    TraceGrid g;
+    g.bx = g.by = g.bz = 4;
+    g.nbx = bv.bricks_x;
+    g.nby = bv.bricks_y;
+    g.nbz = bv.bricks_z;
+    g.n_bricks = g.nbx * g.nby * g.nbz;
+    g.n_waves = bv.n_waves;
+    g.persistent = 2;
+    g.chunk = 0;
     const int local = wave0 - bv.first_wave + (threadIdx.x >> 6);
-    if (local >= bv.n_waves) return;
-    const int lane = threadIdx.x & 63;
-    const int n_bricks = bv.bricks_x * bv.bricks_y * bv.bricks_z;
-    const int j = local / n_bricks, brick = local - j * n_bricks;
-    const int bxi = brick % bv.bricks_x, byi = (brick / bv.bricks_x) % bv.bricks_y,
-              bzi = brick / (bv.bricks_x * bv.bricks_y);
-    const int x = bxi * 4 + (lane & 3), y = byi * 4 + ((lane >> 2) & 3), z = bzi * 4 + (lane >> 4);
-    if (x >= bv.vp.nx || y >= bv.vp.ny || z >= bv.vp.nz) return;
+    const int q = local < bv.n_waves ? ray_record(bv.vp, g, local * 64 + (threadIdx.x & 63)) : -1;
+    LaneState s;
+    lane_start(s, bv.vp, bv.sv, bv.dirs, q);
     Counts cnt = {0, 0};
     uint32_t sh = 0;
-    trace_shade_one<false, false>(bv.vp, bv.sv, src, frames[v], bv.dirs, bv.rays, bv.hits, x, y, z, j,
-                                  Stack<kBatchBlock, E>{stk + threadIdx.x}, cnt, sh, SplitBuffers());
+    lane_loop<false, false>(s, bv.vp, bv.sv, src, frames[v], bv.dirs, bv.rays, bv.hits, g, nullptr,
+                            Stack<kBatchBlock, E>{stk + threadIdx.x}, cnt, sh);
 }
 
 __global__ __launch_bounds__(kBlendThreads) void k_blend_batched(const BatchVolume *vols, int n_vols) {

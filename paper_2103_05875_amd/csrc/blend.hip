@@ -81,10 +81,10 @@ __device__ __forceinline__ void raydirs_any(const FrameParams &fp, int n, int sh
         raydirs_part<0>(fp, n, sharp, dirs, wt, b, c);
 }
 
-// queue: 16 work-queue counters of the trace that follows, zeroed here
+// queue: the work counters of the trace that follows, zeroed here
 __global__ __launch_bounds__(256) void k_raydirs(FrameParams fp, int n, int sharp, float4 *dirs, WeightTables wt,
                                                  int *queue) {
-    if (queue && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 16) queue[threadIdx.x] = 0;
+    if (queue && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 9) queue[threadIdx.x * kQueueStride] = 0;
     raydirs_any(fp, n, sharp, dirs, wt, blockIdx.x, blockIdx.y);
 }
 

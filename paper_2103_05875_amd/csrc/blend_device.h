@@ -142,8 +142,11 @@ __device__ void blend_tile(const VolumeParams &vp, const WeightTables &wt, const
     for (int j0 = 0; j0 < n; j0 += kBlendK) {
         const int m = min(kBlendK, n - j0);
         __syncthreads();
+        // consecutive threads fill consecutive LDS records (8 probes of one
+        // ray, then the next ray): conflict-free stores, 128-byte runs of
+        // each probe's rays in global memory
         for (int e = tid; e < kBlendK * kBlendTile; e += kBlendThreads) {
-            const int pq = e / kBlendK, jj = e - pq * kBlendK, p = p0 + pq;
+            const int jj = e / kBlendTile, pq = e - jj * kBlendTile, p = p0 + pq;
             sm.rec[jj][pq] = (p < P && jj < m) ? rays[(size_t)p * n + j0 + jj] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();

@@ -398,7 +398,8 @@ struct Collapse {
         out.resize(order.size());
         for (size_t i = 0; i < order.size(); ++i) {
             const N4 &t = tree[order[i]];
-            int child[4] = {-1, -1, -1, -1}, count[4] = {0, 0, 0, 0};
+            int child[4] = {-1, -1, -1, -1}, count[4] = {0, 0, 0, 0}, offset[4] = {0, 0, 0, 0};
+            int base = -1;
             Box box[4];
             for (int c = 0; c < t.nk; ++c) {
                 const BNode &k = bn[t.kid_bnode[c]];
@@ -406,16 +407,19 @@ struct Collapse {
                 if (k.count > 0) {
                     child[c] = (int)leaf_order.size();
                     count[c] = k.count;
+                    if (base < 0) base = child[c];
+                    offset[c] = child[c] - base;
                     for (int r = k.first; r < k.first + k.count; ++r) leaf_order.push_back(r);
                 } else {
                     child[c] = index[t.kid_n4[c]];
                 }
             }
-            quantize(out[i], (size_t)t.nk, box, child, count);
+            quantize(out[i], (size_t)t.nk, box, child, count, offset, base);
         }
     }
 
-    void quantize(GpuNode4 &g, size_t nk, const Box *box, const int *child, const int *count) const {
+    void quantize(GpuNode4 &g, size_t nk, const Box *box, const int *child, const int *count, const int *offset,
+                  int base) const {
         float L[3], H[3];
         for (int a = 0; a < 3; ++a) {
             L[a] = INFINITY;
@@ -457,9 +461,11 @@ struct Collapse {
         std::memcpy(fb, L, 12);
         g.w0 = make_uint4(fb[0], fb[1], fb[2], (uint32_t)eb[0] | ((uint32_t)eb[1] << 8) | ((uint32_t)eb[2] << 16));
         g.w1 = make_uint4(pack(q[0]), pack(q[1]), pack(q[2]), pack(q[3]));
+        // leaf byte: triangle count (bits 0-2) and the leaf's first slot
+        // relative to the node's first leaf slot (bits 3-6); 0 = inner / empty
         uint8_t cnt[4];
-        for (int c = 0; c < 4; ++c) cnt[c] = (uint8_t)count[c];
-        g.w2 = make_uint4(pack(q[4]), pack(q[5]), pack(cnt), 0u);
+        for (int c = 0; c < 4; ++c) cnt[c] = (uint8_t)(count[c] | (count[c] > 0 ? offset[c] << 3 : 0));
+        g.w2 = make_uint4(pack(q[4]), pack(q[5]), pack(cnt), (uint32_t)(base < 0 ? 0 : base));
         g.w3 = make_uint4((uint32_t)child[0], (uint32_t)child[1], (uint32_t)child[2], (uint32_t)child[3]);
     }
 };

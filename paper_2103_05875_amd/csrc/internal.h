@@ -62,9 +62,13 @@ bool build_bvh(const float *tri9, int n, int id_base, HostBvh &out, std::string 
 //   w0 = origin.x, origin.y, origin.z (float bits), exps = ex | ey<<8 | ez<<16
 //        (biased exponents: scale_a = 2^(e_a - 127), so lo = origin + q*scale)
 //   w1 = bytes qlo_x[4] | qhi_x[4] | qlo_y[4] | qhi_y[4]  (byte c = child c)
-//   w2 = bytes qlo_z[4] | qhi_z[4] | count[4] | 0
-//   w3 = child[4]: inner node index (count 0), first triangle of a leaf
-//        (count > 0), or -1 for an empty slot
+//   w2 = bytes qlo_z[4] | qhi_z[4] | leaf[4] | leaf_base
+//        leaf byte c = count | offset << 3: count (1..4) triangles of a leaf
+//        child starting at triangle slot leaf_base + offset; 0 for an inner
+//        or empty slot. The leaf children's triangles are consecutive slots
+//        in child order, so offsets stay below 16.
+//   w3 = child[4]: inner node index (leaf byte 0), first triangle of a leaf,
+//        or -1 for an empty slot
 // Quantization rounds outward (floor / ceil), so decoded boxes contain the
 // exact ones.
 struct alignas(16) GpuNode4 {
@@ -156,9 +160,9 @@ struct BatchVolume {
 // threads per block (128 or 256).
 struct TraceConfig {
     int bx = 4, by = 4, bz = 4;
-    int persistent = 0;
-    int top_nodes = 0;
-    int block = 128;
+    int persistent = 2;     // 0 packet, 1 persistent with ray refill, 2 packet with stepped lanes
+    int top_nodes = 21;
+    int block = 256;
     int split_shadows = 0;  // 1: shadow rays in a compacted second pass
 };
 
@@ -180,7 +184,14 @@ struct SplitBuffers {
 // ---------------------------------------------------------------------------
 // Launchers (trace.hip, blend.hip, batched.hip, pack.hip)
 // ---------------------------------------------------------------------------
-// Directions and weight tables; queue: 16 ints zeroed for the trace that follows
+// Work counters of one volume's trace: one per XCD, each on its own 128-byte
+// line (the XCDs do not share a contended line), then the split-shadow queue
+// length.
+constexpr int kQueueStride = 32;                       // ints between counters
+constexpr int kQueueInts = 9 * kQueueStride;           // 8 counters + shadow count
+inline int *queue_counter(int *q, int k) { return q + k * kQueueStride; }
+
+// Directions and weight tables; the 9 work counters are zeroed for the trace that follows
 hipError_t launch_raydirs(const FrameParams &fp, const VolumeParams &vp, float4 *dirs, const WeightTables &wt,
                           int *queue, hipStream_t s);
 hipError_t launch_trace(const VolumeParams &vp, const SceneView &sv, const FrameParams &fp, const float4 *dirs,
@@ -204,8 +215,10 @@ struct PackBuffers {
     const uint16_t *cur_irr, *cur_vis;   // tiles
     uint16_t *ref_irr, *ref_vis;         // interiors
     uint8_t *mask_irr, *mask_vis;
-    int4 *tiles;      // per tile of 16 probes: changed counts (irr, vis), last changed probe (irr, vis)
-    uint32_t *done;   // compaction blocks finished
+    int4 *tiles;      // per tile of 16 probes: changed counts (irr, vis) and last changed probe
+                      // (irr, vis), replaced by their exclusive prefix by the mask kernel
+    uint32_t *done;   // [0] mask blocks finished, [1] compaction blocks finished (both left 0),
+                      // [2] K_irr, [3] K_vis
     uint8_t *packet;
 };
 hipError_t launch_pack_mask(const PackBuffers &b, int P, float tau_irr, float tau_vis, hipStream_t s);

@@ -109,18 +109,69 @@ __device__ __forceinline__ void unpack8(uint4 v, uint16_t r[8]) {
     r[7] = v.w >> 16;
 }
 
+// A tile summary written by another block of the same kernel, read past
+// this CU's L1.
+__device__ __forceinline__ int4 load_summary(const int4 *tiles, int t) {
+    const int *p = reinterpret_cast<const int *>(tiles + t);
+    return make_int4(__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1), __builtin_nontemporal_load(p + 2),
+                     __builtin_nontemporal_load(p + 3));
+}
+
+// Run by the mask kernel's last block once every tile summary is written:
+// replaces each summary by the exclusive prefix of the tiles before it
+// (changed counts, last changed probe) and stores the totals K_irr, K_vis in
+// done[2], done[3]; resets the block counter for the next pack.
+__device__ void scan_tiles(PackBuffers &b, int n_tiles) {
+    __shared__ int4 part[kPackThreads];
+    __threadfence();
+    const int per = (n_tiles + kPackThreads - 1) / kPackThreads;
+    const int lo = min(n_tiles, (int)threadIdx.x * per), hi = min(n_tiles, lo + per);
+    int4 acc = make_int4(0, 0, -1, -1);
+    for (int t = lo; t < hi; ++t) {
+        const int4 s = load_summary(b.tiles, t);
+        acc.x += s.x;
+        acc.y += s.y;
+        acc.z = max(acc.z, s.z);
+        acc.w = max(acc.w, s.w);
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int4 run = make_int4(0, 0, -1, -1);
+        for (int i = 0; i < kPackThreads; ++i) {
+            const int4 a = part[i];
+            part[i] = run;
+            run.x += a.x;
+            run.y += a.y;
+            run.z = max(run.z, a.z);
+            run.w = max(run.w, a.w);
+        }
+        b.done[2] = (uint32_t)run.x;
+        b.done[3] = (uint32_t)run.y;
+        b.done[0] = 0u;
+    }
+    __syncthreads();
+    int4 run = part[threadIdx.x];
+    for (int t = lo; t < hi; ++t) {
+        const int4 s = load_summary(b.tiles, t);
+        b.tiles[t] = run;
+        run.x += s.x;
+        run.y += s.y;
+        run.z = max(run.z, s.z);
+        run.w = max(run.w, s.w);
+    }
+}
+
 // Change mask of every probe: any interior texel differs (tau = 0) or
 // |cur - ref| > tau. Each block also leaves a summary of its tile (changed
-// counts and last changed probe per texture) for the compaction; block 0
-// clears the packet checksum and the compaction's block counter.
+// counts and last changed probe per texture); the last block to finish turns
+// the summaries into prefixes for the compaction. Block 0 clears the packet
+// checksum.
 __global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P, float tau_irr, float tau_vis) {
     __shared__ PackSmem sm;
     const int p0 = blockIdx.x * kPackQ;
     if (p0 >= P) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        reinterpret_cast<uint32_t *>(b.packet)[7] = 0u;
-        *b.done = 0u;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) reinterpret_cast<uint32_t *>(b.packet)[7] = 0u;
     if (threadIdx.x < kPackQ * 2) sm.changed[threadIdx.x >> 1][threadIdx.x & 1] = 0;
     stage_tiles(b, p0, P, sm);
     __syncthreads();
@@ -156,63 +207,31 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P
             }
         }
         b.tiles[blockIdx.x] = s;
-    }
-}
-
-// Block reduction of (sum, sum, max, max) over the block's threads.
-__device__ __forceinline__ int4 block_reduce_tiles(int4 v, int4 *sh) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        v.x += __shfl_xor(v.x, off);
-        v.y += __shfl_xor(v.y, off);
-        v.z = max(v.z, __shfl_xor(v.z, off));
-        v.w = max(v.w, __shfl_xor(v.w, off));
-    }
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    int4 r = sh[0];
-    for (int w = 1; w < kPackThreads / 64; ++w) {
-        r.x += sh[w].x;
-        r.y += sh[w].y;
-        r.z = max(r.z, sh[w].z);
-        r.w = max(r.w, sh[w].w);
+        __threadfence();
+        sm.part[0] = atomicAdd(b.done, 1u) == gridDim.x - 1;
     }
     __syncthreads();
-    return r;
+    if (sm.part[0]) scan_tiles(b, gridDim.x);
 }
 
-// Compaction of one tile: its changed probes' ranks (the tile summaries of
-// the blocks before it), their delta-coded index entries, XOR byte planes
-// and reference update, and the plane words' checksum share. The last block
-// to finish hashes the index section and writes the header.
+// Compaction of one tile: its changed probes' ranks (the prefix the mask
+// kernel left for the tile plus the changed lanes below), their delta-coded
+// index entries, XOR byte planes and reference update, and the plane words'
+// checksum share. The last block to finish hashes the index section and
+// writes the header.
 __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, int P, uint32_t client, uint32_t seq) {
     __shared__ PackSmem sm;
-    __shared__ int4 red[kPackThreads / 64];
     __shared__ int rank_s[kPackQ][2];
-    __shared__ int last_s;
+    __shared__ int any_s, last_s;
     const int tile = blockIdx.x, p0 = tile * kPackQ;
     const int n_tiles = gridDim.x;
     const int n = min(kPackQ, P - p0);
-    // totals and the prefix before this tile
-    int4 before = make_int4(0, 0, -1, -1), all = make_int4(0, 0, -1, -1);
-    for (int t = threadIdx.x; t < n_tiles; t += kPackThreads) {
-        const int4 s = b.tiles[t];
-        all.x += s.x;
-        all.y += s.y;
-        if (t < tile) {
-            before.x += s.x;
-            before.y += s.y;
-            before.z = max(before.z, s.z);
-            before.w = max(before.w, s.w);
-        }
-    }
-    all = block_reduce_tiles(all, red);
-    before = block_reduce_tiles(before, red);
-    const int K_irr = all.x, K_vis = all.y;
+    // the prefix before this tile and the totals (from the mask kernel)
+    const int4 before = b.tiles[tile];
+    const int K_irr = (int)b.done[2], K_vis = (int)b.done[3];
     const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
     uint16_t *idx_i = reinterpret_cast<uint16_t *>(b.packet + 32);
     uint16_t *idx_v = idx_i + K_irr;
-    const int4 mine = b.tiles[tile];
     if (threadIdx.x < 64) {
         // ranks and index entries of the tile's changed probes: lane q owns
         // probe p0 + q; its rank counts the changed lanes below it, its
@@ -220,7 +239,9 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
         const int q = threadIdx.x, p = p0 + q;
         const bool ci = q < n && b.mask_irr[p] != 0, cv = q < n && b.mask_vis[p] != 0;
         const unsigned long long below = (1ull << q) - 1ull;
-        const unsigned long long mi = __ballot(ci) & below, mv = __ballot(cv) & below;
+        const unsigned long long bi = __ballot(ci), bvv = __ballot(cv);
+        const unsigned long long mi = bi & below, mv = bvv & below;
+        if (q == 0) any_s = (bi | bvv) != 0ull;
         if (q < kPackQ) {
             rank_s[q][0] = rank_s[q][1] = -1;
             if (ci) {
@@ -237,8 +258,9 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
             }
         }
     }
+    __syncthreads();
     uint32_t part = 0;
-    if (mine.x + mine.y > 0) {
+    if (any_s) {
         stage_tiles(b, p0, P, sm);
         __syncthreads();
         uint8_t *planes_i = b.packet + 32 + idx_bytes;
@@ -284,7 +306,7 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
         if (s) atomicAdd(h + 7, s);
         // publish this block's index entries, planes and share, then count it
         __threadfence();
-        last_s = atomicAdd(b.done, 1u) == (uint32_t)(n_tiles - 1);
+        last_s = atomicAdd(b.done + 1, 1u) == (uint32_t)(n_tiles - 1);
     }
     __syncthreads();
     if (!last_s) return;
@@ -314,6 +336,7 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
         h[5] = (uint32_t)K_irr;
         h[6] = (uint32_t)K_vis;
         atomicAdd(h + 7, s);
+        b.done[1] = 0u;  // ready for the next pack
     }
 }
 

@@ -115,7 +115,7 @@ struct pv_volume {
     float4 *rays = nullptr, *dirs = nullptr;
     WeightTables wt;  // blend weights of the current frame
     int32_t *hits = nullptr;
-    int *queue = nullptr;  // [0..7] work queues of the persistent trace, [8] shadow-queue length
+    int *queue = nullptr;  // work counters (queue_counter: 0..7 per XCD, 8 shadow-queue length)
     int64_t frame = 0;
     pv_scene *scene = nullptr;
     TraceConfig tc;
@@ -456,7 +456,8 @@ static pv_status validate_desc(const pv_volume_desc *d) {
 static uint64_t volume_bytes(const pv_volume_desc *d) {
     const int P = d->nx * d->ny * d->nz, n = d->rays_per_probe;
     const size_t elem = d->format == PV_MAP_FP16 ? 2 : 4;
-    uint64_t b = irr_bytes(P, elem) + vis_bytes(P, elem) + 512 + (uint64_t)P * n * 16 + (uint64_t)n * 16 + 64 +
+    uint64_t b = irr_bytes(P, elem) + vis_bytes(P, elem) + 512 + (uint64_t)P * n * 16 + (uint64_t)n * 16 +
+                 (uint64_t)kQueueInts * 4 +
                  (uint64_t)(weight_table_floats(n) + weight_part_floats(n)) * 4;
     if (d->flags & PV_KEEP_HITS) b += (uint64_t)P * n * 4;
     return b;
@@ -504,7 +505,7 @@ extern "C" pv_status pv_create_volume(pv_ctx *ctx, const pv_volume_desc *d, pv_v
     if (st == PV_OK) st = dev_alloc(&v->wt.w, weight_table_floats(v->n) * 4, "blend weight table");
     if (st == PV_OK) st = dev_alloc(&v->wt.part, weight_part_floats(v->n) * 4, "blend weight sums");
     if (st == PV_OK && (d->flags & PV_KEEP_HITS)) st = dev_alloc(&v->hits, (size_t)v->P * v->n * 4, "hit ids");
-    if (st == PV_OK) st = dev_alloc(&v->queue, 16 * sizeof(int), "work queues");
+    if (st == PV_OK) st = dev_alloc(&v->queue, kQueueInts * sizeof(int), "work queues");
     if (st == PV_OK && launch_zero(v->wt.w, weight_table_floats(v->n) * 4, ctx->stream) != hipSuccess)
         st = fail(PV_ERR_DEVICE, "zero fill");  // the padding past n stays zero
     if (st == PV_OK && launch_zero(v->irr, irr_bytes(v->P, v->elem), ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "zero fill");
@@ -596,7 +597,7 @@ static pv_status ensure_split(pv_volume *v, int n_lights, hipStream_t s) {
     PV_TRY(dev_alloc(&v->split.hitrec, (size_t)v->P * v->n * sizeof(int2), "hit records"));
     PV_TRY(dev_alloc(&v->split.occ, (size_t)v->P * v->n * sizeof(uint32_t), "occlusion bits"));
     PV_TRY(dev_alloc(&v->split.queue, (size_t)need * sizeof(ShadowEntry), "shadow queue"));
-    v->split.count = v->queue + 8;
+    v->split.count = queue_counter(v->queue, 8);
     v->split.capacity = need;
     return PV_OK;
 }
@@ -679,7 +680,7 @@ extern "C" pv_status pv_volume_set_trace_config(pv_volume *v, const pv_trace_con
     if (!v || !c) return fail(PV_ERR_ARG, "NULL argument");
     if (c->brick[0] < 1 || c->brick[1] < 1 || c->brick[2] < 1 || c->brick[0] * c->brick[1] * c->brick[2] != 64)
         return fail(PV_ERR_ARG, "brick must hold 64 probes");
-    if (c->persistent != 0 && c->persistent != 1) return fail(PV_ERR_ARG, "persistent must be 0 or 1");
+    if (c->persistent < 0 || c->persistent > 2) return fail(PV_ERR_ARG, "persistent must be 0, 1 or 2");
     if (c->top_nodes != 0 && c->top_nodes != 21 && c->top_nodes != 85) return fail(PV_ERR_ARG, "top_nodes must be 0, 21 or 85");
     if (c->block_threads != 128 && c->block_threads != 256) return fail(PV_ERR_ARG, "block_threads must be 128 or 256");
     if (c->split_shadows != 0 && c->split_shadows != 1) return fail(PV_ERR_ARG, "split_shadows must be 0 or 1");
@@ -979,7 +980,7 @@ extern "C" pv_status pv_client_footprint(const pv_volume_desc *d, uint64_t *byte
     PV_TRY(validate_desc(d));
     if (!bytes) return fail(PV_ERR_ARG, "bytes is NULL");
     const uint64_t P = (uint64_t)d->nx * d->ny * d->nz;
-    *bytes = P * (192 + 512) * 2 + 2 * P + (P + kPackTile - 1) / kPackTile * 16 + 4 + packet_capacity((int)P);
+    *bytes = P * (192 + 512) * 2 + 2 * P + (P + kPackTile - 1) / kPackTile * 16 + 16 + packet_capacity((int)P);
     return PV_OK;
 }
 
@@ -1010,7 +1011,7 @@ extern "C" pv_status pv_client_create(pv_volume *v, uint32_t id, pv_client **out
     if (st == PV_OK) st = dev_alloc(&c->mask_irr, (size_t)P, "mask");
     if (st == PV_OK) st = dev_alloc(&c->mask_vis, (size_t)P, "mask");
     if (st == PV_OK) st = dev_alloc(&c->tiles, (size_t)(P + kPackTile - 1) / kPackTile * sizeof(int4), "tile summaries");
-    if (st == PV_OK) st = dev_alloc(&c->done, sizeof(uint32_t), "pack counter");
+    if (st == PV_OK) st = dev_alloc(&c->done, 4 * sizeof(uint32_t), "pack counters");
     if (st == PV_OK) st = dev_alloc(&c->packet, c->packet_cap, "packet");
     if (st == PV_OK && hipHostMalloc((void **)&c->hdr_host, 32) != hipSuccess) st = fail(PV_ERR_OOM, "pinned header");
     hipStream_t s = v->ctx->stream;
@@ -1018,7 +1019,9 @@ extern "C" pv_status pv_client_create(pv_volume *v, uint32_t id, pv_client **out
                         launch_zero(c->ref_vis, (size_t)P * 512 * 2, s) != hipSuccess ||
                         launch_zero(c->mask_irr, (size_t)P, s) != hipSuccess ||
                         launch_zero(c->mask_vis, (size_t)P, s) != hipSuccess ||
-                        launch_zero(c->packet, 32, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess))
+                        launch_zero(c->packet, 32, s) != hipSuccess ||
+                        launch_zero(c->done, 4 * sizeof(uint32_t), s) != hipSuccess ||
+                        hipStreamSynchronize(s) != hipSuccess))
         st = fail(PV_ERR_DEVICE, "client initialisation");
     if (st != PV_OK) {
         free_client(c);

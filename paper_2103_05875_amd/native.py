@@ -352,11 +352,11 @@ class Volume:
         _check(lib().pv_update_probes(self.h, ctypes.byref(f), _stream_handle(stream)))
         del keep
 
-    def set_trace_config(self, brick=(4, 4, 4), persistent=False, top_nodes=0, block_threads=128,
+    def set_trace_config(self, brick=(4, 4, 4), persistent=2, top_nodes=21, block_threads=256,
                          split_shadows=False):
         c = TraceConfig()
         c.brick[:] = [int(b) for b in brick]
-        c.persistent = 1 if persistent else 0
+        c.persistent = int(persistent)
         c.top_nodes = int(top_nodes)
         c.block_threads = int(block_threads)
         c.split_shadows = 1 if split_shadows else 0
@@ -365,7 +365,7 @@ class Volume:
     def get_trace_config(self) -> dict:
         c = TraceConfig()
         _check(lib().pv_volume_get_trace_config(self.h, ctypes.byref(c)))
-        return {"brick": tuple(c.brick), "persistent": bool(c.persistent), "top_nodes": c.top_nodes,
+        return {"brick": tuple(c.brick), "persistent": int(c.persistent), "top_nodes": c.top_nodes,
                 "block_threads": c.block_threads, "split_shadows": bool(c.split_shadows)}
 
     def trace_counts(self, rotation, lights=None):

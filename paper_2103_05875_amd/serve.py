@@ -115,7 +115,10 @@ class Server:
     def _launch(self, k: int, reqs: List[Request], now: float):
         stream = self.streams[k]
         vols = [self.slots[r.client].volume for r in reqs]
-        native.update_probes_batched(vols, [r.rotation for r in reqs], [r.lights for r in reqs], stream=stream)
+        if len(reqs) == 1:   # a batch of one: the plain launches, no descriptor upload
+            vols[0].update_probes(reqs[0].rotation, reqs[0].lights, stream=stream)
+        else:
+            native.update_probes_batched(vols, [r.rotation for r in reqs], [r.lights for r in reqs], stream=stream)
         for r in reqs:
             self.slots[r.client].client.pack_delta(*self.tau, stream=stream)
             self.slots[r.client].busy = True

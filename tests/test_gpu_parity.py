@@ -501,9 +501,10 @@ def _three_lights(extent):
 
 @pytest.mark.parametrize("case", ["dynamic_3_lights", "one_triangle", "empty", "emissive"])
 def test_refill_trace_equals_packet_trace(ps, ctx, case):
-    """The persistent trace (per-lane ray refill, separate node and triangle
-    steps) writes the same bits as the one-wave-per-packet trace: static and
-    moving triangles, several lights, a ragged grid, degenerate scenes."""
+    """The stepped traces (separate node and triangle steps; with and without
+    per-lane ray refill) write the same bits as the one-wave-per-packet
+    trace: static and moving triangles, several lights, a ragged grid,
+    degenerate scenes."""
     _say(f"refill trace vs packet trace: {case}")
     cfg = synth.VolumeConfig(7, 5, 9, (1.0, 0.3, 1.0), (3.0, 1.7, 2.5), 80, fp16=True, max_distance=6.0,
                              sky=(0.1, 0.15, 0.25))
@@ -522,7 +523,8 @@ def test_refill_trace_equals_packet_trace(ps, ctx, case):
         scene = synth.emissive_box(half_width=3.0, center=(10.0, 4.0, 10.0))
     sc = ps.Scene.from_synth(ctx, scene)
     out = {}
-    for persistent, brick in ((False, (4, 4, 4)), (True, (4, 4, 4)), (True, (8, 4, 2)), (True, (16, 4, 1))):
+    for persistent, brick in ((0, (4, 4, 4)), (1, (4, 4, 4)), (1, (8, 4, 2)), (1, (16, 4, 1)), (2, (4, 4, 4)),
+                              (2, (8, 8, 1))):
         v = ps.Volume(ctx, cfg, keep_hits=True)
         v.set_scene(sc)
         v.set_trace_config(brick, persistent, 21 if persistent else 0, 128, False)
@@ -539,7 +541,7 @@ def test_refill_trace_equals_packet_trace(ps, ctx, case):
         c = v.trace_counts(synth.rotation(91, 3), scene.lights)
         _say(f"  persistent={persistent} brick={brick}: counts {c}")
         v.close()
-    ref = out[(False, (4, 4, 4))]
+    ref = out[(0, (4, 4, 4))]
     for k, got in out.items():
         for f, (a, b) in enumerate(zip(got, ref)):
             assert a == b, f"{k} differs from the packet trace at step {f}"
