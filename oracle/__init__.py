@@ -234,7 +234,7 @@ def _volume_struct(cfg) -> _Volume:
     return v
 
 
-def trace_shade(scene: OracleScene, cfg, R, lights, delta_rel: float = 1e-6, maxc: int = 4,
+def trace_shade(scene: OracleScene, cfg, R, lights, delta_rel: float = 1e-6, maxc: int = 8,
                 nthreads: int = 0, bounds: bool = True):
     """Trace and shade every (probe, ray). Returns a dict of arrays shaped
     [P, n(, 3)]: L, r (nominal), L_lo, L_hi, r_lo, r_hi (tie bounds),

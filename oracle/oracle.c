@@ -355,21 +355,29 @@ static double box_enter(const or_node *nd, const double o[3], const double d[3],
  *   nominal: closest exact hit with t > tmin (ties: smaller triangle index);
  *   near:    1 when the answer could change under a perturbation of size m
  *            (a triangle within m of its edges or of tmin/tmax, or two
- *            different triangles within m of the nominal distance). */
+ *            different triangles within m of the nominal distance);
+ *   ties:    the other triangles that are equally valid answers at margin m:
+ *            those within 2m of the nominal distance, and those the ray
+ *            passes within m of (edges or tmin) in front of the first sure
+ *            hit. */
+#define OR_MAX_TIES 8
 typedef struct {
     int tri;
     double t;
     int near;
-    int nties;           /* other triangles within 2m of the nominal distance */
-    int ties[4];
-    double ties_t[4];
+    int nties;
+    int ties[OR_MAX_TIES];
+    double ties_t[OR_MAX_TIES];
 } or_hit;
 
 #define OR_STACK 128
 
 static or_hit closest_hit(const or_scene *s, const double o[3], const double d[3], double tmin, double m)
 {
-    or_hit h = {-1, INFINITY, 0, 0, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    or_hit h;
+    memset(&h, 0, sizeof h);
+    h.tri = -1;
+    h.t = INFINITY;
     if (s->ntri == 0) return h;
     double t_limit = INFINITY;  /* closest 'sure' distance so far + margin */
     int stack[OR_STACK];
@@ -418,12 +426,14 @@ static or_hit closest_hit(const or_scene *s, const double o[3], const double d[3
     if (t_limit < front + m) front = t_limit - m;
     for (int i = 0; i < npos; ++i) {
         if (poss_t[i] > front + 2.0 * m) continue;
-        if (!poss_sure[i]) h.near = 1;
-        if (poss_id[i] != h.tri && fabs(poss_t[i] - h.t) <= 2.0 * m) {
+        const int graze = !poss_sure[i];
+        const int same_depth = fabs(poss_t[i] - h.t) <= 2.0 * m;
+        if (graze) h.near = 1;
+        if (poss_id[i] != h.tri && (graze || same_depth)) {
             h.near = 1;
             int dup = 0;
             for (int k = 0; k < h.nties; ++k) dup |= h.ties[k] == poss_id[i];
-            if (!dup && h.nties < 4) {
+            if (!dup && h.nties < OR_MAX_TIES) {
                 h.ties[h.nties] = poss_id[i];
                 h.ties_t[h.nties] = poss_t[i];
                 h.nties++;
@@ -623,7 +633,8 @@ OR_API int or_trace_shade(const or_scene *s, const or_volume *v, const float R[9
                         }
                     }
                 /* triangles at the same distance (coplanar or crossing
-                 * surfaces) are equally valid answers */
+                 * surfaces), and triangles the ray grazes in front of the
+                 * first sure hit, are equally valid answers */
                 for (int k = 0; k < h.nties; ++k) {
                     int seen = 0;
                     for (int c = 0; c < nc; ++c) seen |= cands[c] == h.ties[k];

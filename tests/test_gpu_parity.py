@@ -203,6 +203,27 @@ def test_city_full_size_frames(ps, ctx, O):
         _fp16_checks(irr, vis, ov, f"city frame {f}")
 
 
+def test_encode_full_size_frames(ps, ctx, O):
+    """The encode workload at full size: 32x16x32 = 16,384 probes, 256 rays,
+    200k-triangle field with 4 moving occluders (dynamic BVH rebuilt per
+    frame) and a moving light; two frames against the oracle."""
+    cfg = synth.config("encode")
+    scene = synth.box_field(200_000, seed=40, n_moving=4)
+    path = synth.light_path(12, 120)
+    frames, lights = [], []
+    for f in range(2):
+        frames.append(synth.rotation(41, f))
+        l = scene.lights.copy()
+        l[0, :3] = path[f]
+        lights.append(l)
+    dyn = lambda f: synth.moving_occluders(40, f, 4)
+    for f, (irr, vis, ov, grays, ghits, rays) in enumerate(
+            _update_both(ps, ctx, O, cfg, scene, frames, dyn=dyn, lights_per_frame=lights)):
+        _say(f"encode frame {f}")
+        _check_rays(grays, ghits, rays)
+        _fp16_checks(irr, vis, ov, f"encode frame {f}")
+
+
 def test_dynamic_occluders(ps, ctx, O):
     """Moving occluder boxes (dynamic triangles) over a small box field."""
     _say("moving occluders, 4 frames")
