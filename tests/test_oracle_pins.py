@@ -153,6 +153,43 @@ def test_tie_flag_on_shared_edge(O):
     assert np.isclose(t[0], np.linalg.norm(target2 - o[0]), rtol=1e-12)
 
 
+def test_ray_on_box_edge_accepts_both_faces(O):
+    """A ray that runs into a box edge (to FP32 rounding of the box data) can
+    hit either face that meets there, or graze past; the accepted set holds a
+    triangle of each face (the reading of the closest-hit margin)."""
+    cfg = synth.VolumeConfig(1, 1, 1, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 64, max_distance=8.0, fp16=False)
+    R = synth.rotation(5, 0)
+    d = O.ray_dirs(64, R)
+    found = 0
+    for j in (0, 17, 40):
+        dj = d[j]
+        X = 2.0 * dj                                   # the ray meets the edge at t = 2
+        # box whose edge along the axis of least |d| passes through X; the
+        # ray comes from outside, towards the two faces that meet there
+        ax = int(np.argmin(np.abs(dj)))
+        a, b_ = [k for k in range(3) if k != ax]
+        lo, hi = X.copy(), X.copy()
+        for k in (a, b_):
+            if dj[k] > 0:
+                hi[k] = X[k] + 1.0                     # the ray enters through the face at X[k]
+            else:
+                lo[k] = X[k] - 1.0
+        lo[ax], hi[ax] = X[ax] - 0.5, X[ax] + 0.5
+        tris = synth._box_triangles(lo, hi).astype(np.float32)
+        osc = O.OracleScene(tris, np.full((12, 3), 0.5, np.float32))
+        rays = O.trace_shade(osc, cfg, R, np.zeros((0, 6), np.float32))
+        cand = [c for c in rays["cand"][0, j][: rays["ncand"][0, j]] if c >= 0]
+        # which face each candidate lies on: the axis its plane is normal to
+        axes = set()
+        for c in cand:
+            t = tris[c].astype(np.float64)
+            nrm = np.cross(t[1] - t[0], t[2] - t[0])
+            axes.add(int(np.argmax(np.abs(nrm))))
+        assert {a, b_} <= axes, (j, cand, axes)
+        found += 1
+    assert found == 3
+
+
 # ---------------------------------------------------------------- trace + shade special cases
 def _cfg(**kw):
     base = dict(nx=2, ny=2, nz=2, origin=(0.0, 0.0, 0.0), spacing=(0.5, 0.5, 0.5), rays_per_probe=256,
