@@ -73,7 +73,7 @@ def parse():
 
 
 # sources of the trace kernel (its BVH layout included): the counters stay valid while these are unchanged
-KERNEL_SOURCES = ("trace.hip", "trace_device.h", "device_common.h", "internal.h", "bvh.cpp")
+KERNEL_SOURCES = ("trace.hip", "trace_device.h", "device_common.h", "trace_layout.h", "bvh.cpp")
 COPY_BYTES = 256 << 20             # the --calibrate-copy kernel reads and writes this many bytes
 
 
@@ -354,12 +354,12 @@ def leg_encode(ps, torch, frames: int):
     st = ctx.stage_times()
     ctx.set_timing(False)
     P = cfg.n_probes
-    pack_ms = sum(st[k][0] for k in ("pack_mask", "pack_scan", "pack_compact")) / frames
+    pack_ms = sum(st[k][0] for k in ("pack_mask", "pack_scan", "pack_compact", "pack_finish")) / frames
     ki = np.mean([c[0] for c in changed])
     kv = np.mean([c[1] for c in changed])
     pack_bytes = P * 1408 * 2 + (ki * 384 + kv * 1024) * 2 + P * 2
     upd_ms = (st["raydirs"][0] + st["trace"][0] + st["blend"][0]) / frames
-    per_kernel = {k: st[k][0] / max(st[k][1], 1) for k in ("pack_mask", "pack_scan", "pack_compact", "trace", "blend")}
+    per_kernel = {k: st[k][0] / max(st[k][1], 1) for k in ("pack_mask", "pack_scan", "pack_compact", "pack_finish", "trace", "blend")}
     out = {"probes": P, "frames": frames, "round_trip_bit_exact": bool(ok), "mean_changed_irr": ki,
            "kernel_ms": per_kernel,
            "mean_changed_vis": kv, "packet_bytes_per_frame": sent_bytes / frames,
@@ -494,7 +494,7 @@ def main():
     mi, mv = cl.read_masks()
     k_changed = (int(mi.sum()) + int(mv.sum())) / 2.0
     pack_bytes = P * 1408 * 2 + (int(mi.sum()) * 384 + int(mv.sum()) * 1024) * 2 + P * 2
-    pack_ms = stage_ms["pack_mask"] + stage_ms["pack_scan"] + stage_ms["pack_compact"]
+    pack_ms = stage_ms["pack_mask"] + stage_ms["pack_scan"] + stage_ms["pack_compact"] + stage_ms["pack_finish"]
 
     out = {
         "metric": METRIC,

@@ -290,12 +290,13 @@ typedef enum {
     PV_STAGE_TRACE = 1,
     PV_STAGE_BLEND = 2,
     PV_STAGE_PACK_MASK = 3,
-    PV_STAGE_PACK_SCAN = 4,     /* reserved: the prefix is taken inside the compaction */
+    PV_STAGE_PACK_SCAN = 4,
     PV_STAGE_PACK_COMPACT = 5,
     PV_STAGE_BATCHED = 6,
     PV_STAGE_SHADOW = 7,
     PV_STAGE_SHADE = 8,
-    PV_STAGE_COUNT = 9
+    PV_STAGE_PACK_FINISH = 9,
+    PV_STAGE_COUNT = 10
 } pv_stage;
 
 /* When enabled, every kernel launch of the context is bracketed by a pair

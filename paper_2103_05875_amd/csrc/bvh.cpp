@@ -1,8 +1,7 @@
-// Host BVH builder: binned surface-area heuristic over triangle centroids,
-// binary tree, flattened into 64-byte two-box nodes for the GPU traversal.
-//
-// Depth is bounded by kMaxDepth (the traversal's stack size): a node whose
-// remaining depth budget is tight switches to balanced median splits.
+// Host BVH builder: binned surface-area heuristic over triangle centroids
+// into a binary tree (a node whose remaining depth budget is tight switches to
+// balanced median splits), collapsed into the 4-wide quantized nodes of the
+// GPU traversal with a proved bound on its stack.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -202,124 +201,6 @@ float bits_as_float(int v) {
 
 }  // namespace
 
-bool build_bvh(const float *tri9, int n, int id_base, HostBvh &out, std::string &err) {
-    out.nodes.clear();
-    out.tris.clear();
-    out.depth = 0;
-    if (n <= 0) return true;
-    std::vector<Ref> refs(n);
-    Box scene;
-    scene.reset();
-    for (int i = 0; i < n; ++i) {
-        const float *t = tri9 + 9 * (size_t)i;
-        for (int k = 0; k < 9; ++k)
-            if (!std::isfinite(t[k])) {
-                err = "triangle " + std::to_string(i) + " has a non-finite coordinate";
-                return false;
-            }
-        refs[i].box.reset();
-        for (int v = 0; v < 3; ++v) refs[i].box.grow(t + 3 * v);
-        for (int k = 0; k < 3; ++k) refs[i].c[k] = (t[k] + t[3 + k] + t[6 + k]) / 3.0f;
-        refs[i].tri = i;
-        scene.grow(refs[i].box);
-    }
-    Builder b(refs);
-    b.build(0, n, 0);
-    out.depth = b.max_depth_;
-    if (out.depth > kMaxDepth) {
-        err = "BVH depth exceeds the traversal stack";
-        return false;
-    }
-    // conservative padding of child boxes (rounding of the slab test)
-    float diag = 0.f;
-    for (int k = 0; k < 3; ++k) diag += (scene.hi[k] - scene.lo[k]) * (scene.hi[k] - scene.lo[k]);
-    diag = std::sqrt(diag);
-    const float pad_abs = diag * 9.5367431640625e-7f;  // 2^-20 of the extent
-
-    // triangles in leaf order
-    out.tris.resize(n);
-    for (int i = 0; i < n; ++i) {
-        const float *t = tri9 + 9 * (size_t)refs[i].tri;
-        GpuTri g;
-        g.v0 = make_float4(t[0], t[1], t[2], bits_as_float(id_base + refs[i].tri));
-        g.e1 = make_float4(t[3] - t[0], t[4] - t[1], t[5] - t[2], 0.f);
-        g.e2 = make_float4(t[6] - t[0], t[7] - t[1], t[8] - t[2], 0.f);
-        out.tris[i] = g;
-    }
-
-    // flatten: GPU nodes are the inner nodes in depth-first preorder
-    const std::vector<BNode> &bn = b.nodes_;
-    std::vector<int> gpu_id(bn.size(), -1);
-    std::vector<int> order;
-    std::vector<int> stack = {0};
-    if (bn[0].count > 0) {
-        // a single leaf: wrap it in one inner node with an empty slot
-        order.push_back(0);
-    } else {
-        while (!stack.empty()) {
-            int id = stack.back();
-            stack.pop_back();
-            if (bn[id].count > 0) continue;
-            gpu_id[id] = (int)order.size();
-            order.push_back(id);
-            stack.push_back(bn[id].right);
-            stack.push_back(bn[id].left);
-        }
-    }
-    auto padded = [&](const Box &bx, int k, bool hi) {
-        float v = hi ? bx.hi[k] : bx.lo[k];
-        float pad = pad_abs + std::fabs(v) * 2.384185791015625e-7f;  // + 2^-22 relative
-        return hi ? v + pad : v - pad;
-    };
-    out.nodes.resize(order.size());
-    for (size_t g = 0; g < order.size(); ++g) {
-        const BNode &nd = bn[order[g]];
-        int ch[2], cnt[2];
-        Box cb[2];
-        if (nd.count > 0) {  // single-leaf root
-            ch[0] = nd.first;
-            cnt[0] = nd.count;
-            cb[0] = nd.box;
-            ch[1] = -1;
-            cnt[1] = 0;
-            cb[1].reset();
-        } else {
-            const int kids[2] = {nd.left, nd.right};
-            for (int c = 0; c < 2; ++c) {
-                const BNode &k = bn[kids[c]];
-                cb[c] = k.box;
-                if (k.count > 0) {
-                    ch[c] = k.first;
-                    cnt[c] = k.count;
-                } else {
-                    ch[c] = gpu_id[kids[c]];
-                    cnt[c] = 0;
-                }
-            }
-        }
-        float lo[2][3], hi[2][3];
-        for (int c = 0; c < 2; ++c)
-            for (int k = 0; k < 3; ++k) {
-                if (cb[c].empty()) {
-                    lo[c][k] = INFINITY;
-                    hi[c][k] = -INFINITY;
-                } else {
-                    lo[c][k] = padded(cb[c], k, false);
-                    hi[c][k] = padded(cb[c], k, true);
-                }
-            }
-        GpuNode &o = out.nodes[g];
-        o.bx = make_float4(lo[0][0], lo[1][0], hi[0][0], hi[1][0]);
-        o.by = make_float4(lo[0][1], lo[1][1], hi[0][1], hi[1][1]);
-        o.bz = make_float4(lo[0][2], lo[1][2], hi[0][2], hi[1][2]);
-        o.meta = make_int4(ch[0], ch[1], cnt[0], cnt[1]);
-    }
-    return true;
-}
-
-// ---------------------------------------------------------------------------
-// 4-wide quantized BVH
-// ---------------------------------------------------------------------------
 namespace {
 
 struct Collapse {

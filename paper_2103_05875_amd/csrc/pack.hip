@@ -109,69 +109,13 @@ __device__ __forceinline__ void unpack8(uint4 v, uint16_t r[8]) {
     r[7] = v.w >> 16;
 }
 
-// A tile summary written by another block of the same kernel, read past
-// this CU's L1.
-__device__ __forceinline__ int4 load_summary(const int4 *tiles, int t) {
-    const int *p = reinterpret_cast<const int *>(tiles + t);
-    return make_int4(__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1), __builtin_nontemporal_load(p + 2),
-                     __builtin_nontemporal_load(p + 3));
-}
-
-// Run by the mask kernel's last block once every tile summary is written:
-// replaces each summary by the exclusive prefix of the tiles before it
-// (changed counts, last changed probe) and stores the totals K_irr, K_vis in
-// done[2], done[3]; resets the block counter for the next pack.
-__device__ void scan_tiles(PackBuffers &b, int n_tiles) {
-    __shared__ int4 part[kPackThreads];
-    __threadfence();
-    const int per = (n_tiles + kPackThreads - 1) / kPackThreads;
-    const int lo = min(n_tiles, (int)threadIdx.x * per), hi = min(n_tiles, lo + per);
-    int4 acc = make_int4(0, 0, -1, -1);
-    for (int t = lo; t < hi; ++t) {
-        const int4 s = load_summary(b.tiles, t);
-        acc.x += s.x;
-        acc.y += s.y;
-        acc.z = max(acc.z, s.z);
-        acc.w = max(acc.w, s.w);
-    }
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int4 run = make_int4(0, 0, -1, -1);
-        for (int i = 0; i < kPackThreads; ++i) {
-            const int4 a = part[i];
-            part[i] = run;
-            run.x += a.x;
-            run.y += a.y;
-            run.z = max(run.z, a.z);
-            run.w = max(run.w, a.w);
-        }
-        b.done[2] = (uint32_t)run.x;
-        b.done[3] = (uint32_t)run.y;
-        b.done[0] = 0u;
-    }
-    __syncthreads();
-    int4 run = part[threadIdx.x];
-    for (int t = lo; t < hi; ++t) {
-        const int4 s = load_summary(b.tiles, t);
-        b.tiles[t] = run;
-        run.x += s.x;
-        run.y += s.y;
-        run.z = max(run.z, s.z);
-        run.w = max(run.w, s.w);
-    }
-}
-
 // Change mask of every probe: any interior texel differs (tau = 0) or
 // |cur - ref| > tau. Each block also leaves a summary of its tile (changed
-// counts and last changed probe per texture); the last block to finish turns
-// the summaries into prefixes for the compaction. Block 0 clears the packet
-// checksum.
+// counts and last changed probe per texture) for the scan.
 __global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P, float tau_irr, float tau_vis) {
     __shared__ PackSmem sm;
     const int p0 = blockIdx.x * kPackQ;
     if (p0 >= P) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) reinterpret_cast<uint32_t *>(b.packet)[7] = 0u;
     if (threadIdx.x < kPackQ * 2) sm.changed[threadIdx.x >> 1][threadIdx.x & 1] = 0;
     stage_tiles(b, p0, P, sm);
     __syncthreads();
@@ -207,28 +151,99 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P
             }
         }
         b.tiles[blockIdx.x] = s;
-        __threadfence();
-        sm.part[0] = atomicAdd(b.done, 1u) == gridDim.x - 1;
     }
-    __syncthreads();
-    if (sm.part[0]) scan_tiles(b, gridDim.x);
 }
 
-// Compaction of one tile: its changed probes' ranks (the prefix the mask
-// kernel left for the tile plus the changed lanes below), their delta-coded
-// index entries, XOR byte planes and reference update, and the plane words'
-// checksum share. The last block to finish hashes the index section and
-// writes the header.
-__global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, int P, uint32_t client, uint32_t seq) {
+constexpr int kScanThreads = 1024;
+
+// Inclusive scan of (sum, sum, max, max) across the block: wavefront
+// shuffles, then the wavefront totals.
+__device__ __forceinline__ int4 block_scan_tiles(int4 v, int4 *sh) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int a = __shfl_up(v.x, off), c = __shfl_up(v.y, off), z = __shfl_up(v.z, off), w = __shfl_up(v.w, off);
+        if (lane >= off) {
+            v.x += a;
+            v.y += c;
+            v.z = max(v.z, z);
+            v.w = max(v.w, w);
+        }
+    }
+    if (lane == 63) sh[wv] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 1; k < kScanThreads / 64; ++k) {
+            sh[k].x += sh[k - 1].x;
+            sh[k].y += sh[k - 1].y;
+            sh[k].z = max(sh[k].z, sh[k - 1].z);
+            sh[k].w = max(sh[k].w, sh[k - 1].w);
+        }
+    __syncthreads();
+    if (wv > 0) {
+        const int4 o = sh[wv - 1];
+        v.x += o.x;
+        v.y += o.y;
+        v.z = max(v.z, o.z);
+        v.w = max(v.w, o.w);
+    }
+    return v;
+}
+
+// One block: replaces every tile summary by the exclusive prefix of the tiles
+// before it (changed counts, last changed probe) and stores the totals
+// K_irr, K_vis in totals[0], totals[1]; clears the packet checksum.
+__global__ __launch_bounds__(kScanThreads) void k_pack_scan(PackBuffers b, int n_tiles) {
+    __shared__ int4 sh[kScanThreads / 64];
+    const int per = (n_tiles + kScanThreads - 1) / kScanThreads;
+    const int lo = min(n_tiles, (int)threadIdx.x * per), hi = min(n_tiles, lo + per);
+    int4 mine = make_int4(0, 0, -1, -1);
+    for (int t = lo; t < hi; ++t) {
+        const int4 s = b.tiles[t];
+        mine.x += s.x;
+        mine.y += s.y;
+        mine.z = max(mine.z, s.z);
+        mine.w = max(mine.w, s.w);
+    }
+    const int4 inc = block_scan_tiles(mine, sh);
+    int4 run = make_int4(inc.x - mine.x, inc.y - mine.y, -1, -1);
+    // exclusive max: the previous thread's inclusive value
+    const int pz = __shfl_up(inc.z, 1), pw = __shfl_up(inc.w, 1);
+    if ((threadIdx.x & 63) != 0) {
+        run.z = pz;
+        run.w = pw;
+    } else if (threadIdx.x > 0) {
+        run.z = sh[(threadIdx.x >> 6) - 1].z;
+        run.w = sh[(threadIdx.x >> 6) - 1].w;
+    }
+    for (int t = lo; t < hi; ++t) {
+        const int4 s = b.tiles[t];
+        b.tiles[t] = run;
+        run.x += s.x;
+        run.y += s.y;
+        run.z = max(run.z, s.z);
+        run.w = max(run.w, s.w);
+    }
+    if (threadIdx.x == kScanThreads - 1) {
+        b.totals[0] = (uint32_t)inc.x;
+        b.totals[1] = (uint32_t)inc.y;
+        reinterpret_cast<uint32_t *>(b.packet)[7] = 0u;
+    }
+}
+
+// Compaction of one tile: its changed probes' ranks (the tile's prefix from
+// the scan plus the changed lanes below), their delta-coded index entries,
+// XOR byte planes and reference update, and the plane words' checksum share
+// (summed by the finish kernel with the index section's).
+__global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, int P) {
     __shared__ PackSmem sm;
     __shared__ int rank_s[kPackQ][2];
-    __shared__ int any_s, last_s;
+    __shared__ int any_s;
     const int tile = blockIdx.x, p0 = tile * kPackQ;
-    const int n_tiles = gridDim.x;
     const int n = min(kPackQ, P - p0);
-    // the prefix before this tile and the totals (from the mask kernel)
+    // the prefix before this tile and the totals (from the scan)
     const int4 before = b.tiles[tile];
-    const int K_irr = (int)b.done[2], K_vis = (int)b.done[3];
+    const int K_irr = (int)b.totals[0], K_vis = (int)b.totals[1];
     const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
     uint16_t *idx_i = reinterpret_cast<uint16_t *>(b.packet + 32);
     uint16_t *idx_v = idx_i + K_irr;
@@ -299,35 +314,37 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
     for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
     if ((threadIdx.x & 63) == 0) sm.part[threadIdx.x >> 6] = part;
     __syncthreads();
-    uint32_t *h = reinterpret_cast<uint32_t *>(b.packet);
     if (threadIdx.x == 0) {
         uint32_t s = 0;
         for (int w = 0; w < kPackThreads / 64; ++w) s += sm.part[w];
-        if (s) atomicAdd(h + 7, s);
-        // publish this block's index entries, planes and share, then count it
-        __threadfence();
-        last_s = atomicAdd(b.done + 1, 1u) == (uint32_t)(n_tiles - 1);
+        b.partial[tile] = s;
     }
-    __syncthreads();
-    if (!last_s) return;
-    // last block: every index entry is written; pad, hash, header
-    __threadfence();
+}
+
+// One block: pads and hashes the index section, adds the compaction blocks'
+// plane hashes, writes the header.
+__global__ __launch_bounds__(kScanThreads) void k_pack_finish(PackBuffers b, int P, int n_tiles, uint32_t client,
+                                                             uint32_t seq) {
+    __shared__ uint32_t sh[kScanThreads / 64];
+    const int K_irr = (int)b.totals[0], K_vis = (int)b.totals[1];
+    const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
     uint8_t *pk = b.packet;
     if (threadIdx.x < 16) {
         const int pos = 2 * (K_irr + K_vis) + threadIdx.x;
         if (pos < idx_bytes) pk[32 + pos] = 0;
     }
     __syncthreads();
-    uint32_t ih = 0;
+    uint32_t s = 0;
     const uint32_t *words = reinterpret_cast<const uint32_t *>(pk + 32);
-    for (int wi = threadIdx.x; wi < idx_bytes / 4; wi += kPackThreads)
-        ih += word_hash(__builtin_nontemporal_load(words + wi), (uint32_t)wi);
-    for (int off = 32; off > 0; off >>= 1) ih += __shfl_xor(ih, off);
-    if ((threadIdx.x & 63) == 0) sm.part[threadIdx.x >> 6] = ih;
+    for (int wi = threadIdx.x; wi < idx_bytes / 4; wi += kScanThreads) s += word_hash(words[wi], (uint32_t)wi);
+    for (int t = threadIdx.x; t < n_tiles; t += kScanThreads) s += b.partial[t];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t s = 0;
-        for (int w = 0; w < kPackThreads / 64; ++w) s += sm.part[w];
+        uint32_t tot = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) tot += sh[w];
+        uint32_t *h = reinterpret_cast<uint32_t *>(pk);
         h[0] = 0x4B505650u;
         h[1] = 1u | (32u << 16);
         h[2] = client;
@@ -335,8 +352,7 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
         h[4] = (uint32_t)P;
         h[5] = (uint32_t)K_irr;
         h[6] = (uint32_t)K_vis;
-        atomicAdd(h + 7, s);
-        b.done[1] = 0u;  // ready for the next pack
+        h[7] = tot;
     }
 }
 
@@ -350,8 +366,18 @@ hipError_t launch_pack_mask(const PackBuffers &b, int P, float tau_irr, float ta
     return hipGetLastError();
 }
 
-hipError_t launch_pack_compact(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_compact, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P, client, seq);
+hipError_t launch_pack_scan(const PackBuffers &b, int P, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_scan, dim3(1), dim3(kScanThreads), 0, s, b, (P + kPackQ - 1) / kPackQ);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_compact(const PackBuffers &b, int P, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_compact, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_finish(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_finish, dim3(1), dim3(kScanThreads), 0, s, b, P, (P + kPackQ - 1) / kPackQ, client, seq);
     return hipGetLastError();
 }
 

@@ -128,7 +128,8 @@ struct pv_client {
     uint16_t *ref_irr = nullptr, *ref_vis = nullptr;
     uint8_t *mask_irr = nullptr, *mask_vis = nullptr;
     int4 *tiles = nullptr;         // per-tile summaries of the last mask pass
-    uint32_t *done = nullptr;      // compaction block counter
+    uint32_t *totals = nullptr;    // changed-probe totals of the last scan
+    uint32_t *partial = nullptr;   // per-tile checksum shares
     uint8_t *packet = nullptr;
     uint64_t packet_cap = 0;
     uint32_t *hdr_host = nullptr;  // pinned, 32 bytes
@@ -980,7 +981,7 @@ extern "C" pv_status pv_client_footprint(const pv_volume_desc *d, uint64_t *byte
     PV_TRY(validate_desc(d));
     if (!bytes) return fail(PV_ERR_ARG, "bytes is NULL");
     const uint64_t P = (uint64_t)d->nx * d->ny * d->nz;
-    *bytes = P * (192 + 512) * 2 + 2 * P + (P + kPackTile - 1) / kPackTile * 16 + 16 + packet_capacity((int)P);
+    *bytes = P * (192 + 512) * 2 + 2 * P + (P + kPackTile - 1) / kPackTile * 20 + 16 + packet_capacity((int)P);
     return PV_OK;
 }
 
@@ -990,7 +991,8 @@ static void free_client(pv_client *c) {
     hipFree(c->mask_irr);
     hipFree(c->mask_vis);
     hipFree(c->tiles);
-    hipFree(c->done);
+    hipFree(c->totals);
+    hipFree(c->partial);
     hipFree(c->packet);
     if (c->hdr_host) hipHostFree(c->hdr_host);
     delete c;
@@ -1011,7 +1013,8 @@ extern "C" pv_status pv_client_create(pv_volume *v, uint32_t id, pv_client **out
     if (st == PV_OK) st = dev_alloc(&c->mask_irr, (size_t)P, "mask");
     if (st == PV_OK) st = dev_alloc(&c->mask_vis, (size_t)P, "mask");
     if (st == PV_OK) st = dev_alloc(&c->tiles, (size_t)(P + kPackTile - 1) / kPackTile * sizeof(int4), "tile summaries");
-    if (st == PV_OK) st = dev_alloc(&c->done, 4 * sizeof(uint32_t), "pack counters");
+    if (st == PV_OK) st = dev_alloc(&c->totals, 4 * sizeof(uint32_t), "pack totals");
+    if (st == PV_OK) st = dev_alloc(&c->partial, (size_t)(P + kPackTile - 1) / kPackTile * 4, "pack checksum shares");
     if (st == PV_OK) st = dev_alloc(&c->packet, c->packet_cap, "packet");
     if (st == PV_OK && hipHostMalloc((void **)&c->hdr_host, 32) != hipSuccess) st = fail(PV_ERR_OOM, "pinned header");
     hipStream_t s = v->ctx->stream;
@@ -1020,7 +1023,6 @@ extern "C" pv_status pv_client_create(pv_volume *v, uint32_t id, pv_client **out
                         launch_zero(c->mask_irr, (size_t)P, s) != hipSuccess ||
                         launch_zero(c->mask_vis, (size_t)P, s) != hipSuccess ||
                         launch_zero(c->packet, 32, s) != hipSuccess ||
-                        launch_zero(c->done, 4 * sizeof(uint32_t), s) != hipSuccess ||
                         hipStreamSynchronize(s) != hipSuccess))
         st = fail(PV_ERR_DEVICE, "client initialisation");
     if (st != PV_OK) {
@@ -1063,13 +1065,16 @@ extern "C" pv_status pv_pack_delta(pv_client *c, float tau_irr, float tau_vis, v
     b.mask_irr = c->mask_irr;
     b.mask_vis = c->mask_vis;
     b.tiles = c->tiles;
-    b.done = c->done;
+    b.totals = c->totals;
+    b.partial = c->partial;
     b.packet = c->packet;
     pv_ctx *cx = v->ctx;
     const int P = v->P;
     const uint32_t id = c->id, seq = c->seq;
     HIP_TRY(timed(cx, PV_STAGE_PACK_MASK, s, [&] { return launch_pack_mask(b, P, tau_irr, tau_vis, s); }));
-    HIP_TRY(timed(cx, PV_STAGE_PACK_COMPACT, s, [&] { return launch_pack_compact(b, P, id, seq, s); }));
+    HIP_TRY(timed(cx, PV_STAGE_PACK_SCAN, s, [&] { return launch_pack_scan(b, P, s); }));
+    HIP_TRY(timed(cx, PV_STAGE_PACK_COMPACT, s, [&] { return launch_pack_compact(b, P, s); }));
+    HIP_TRY(timed(cx, PV_STAGE_PACK_FINISH, s, [&] { return launch_pack_finish(b, P, id, seq, s); }));
     c->seq++;
     return PV_OK;
 }

@@ -35,7 +35,8 @@ EXPORTED_SYMBOLS = [
     "pv_batch_graph_create", "pv_batch_graph_launch", "pv_batch_graph_destroy",
 ]
 
-STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched", "shadow", "shade"]
+STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched", "shadow", "shade",
+          "pack_finish"]
 
 
 class NativeError(RuntimeError):
