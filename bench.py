@@ -86,6 +86,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
+def parse_trace_config(s: str) -> dict:
+    """bx,by,bz,persistent,top_nodes,block_threads,split_shadows -> trace launch config
+    (persistent is the schedule number 0, 1 or 2, not a flag)."""
+    v = [int(x) for x in s.split(",")]
+    if len(v) != 7:
+        raise ValueError(f"--trace-config needs 7 integers, got {s!r}")
+    return {"brick": tuple(v[0:3]), "persistent": v[3], "top_nodes": v[4], "block_threads": v[5],
+            "split_shadows": bool(v[6])}
+
+
 def config_string(c) -> str:
     return ",".join(str(int(v)) for v in (*c["brick"], c["persistent"], c["top_nodes"], c["block_threads"],
                                           c["split_shadows"]))
@@ -409,10 +419,8 @@ def main():
     sc = ps.Scene.from_synth(ctx, scene)
     tuned = None
     if args.trace_config:
-        v = [int(x) for x in args.trace_config.split(",")]
-        tuned = {"config": {"brick": tuple(v[0:3]), "persistent": bool(v[3]), "top_nodes": v[4],
-                            "block_threads": v[5], "split_shadows": bool(v[6])},
-                 "ms": float("nan"), "tried": 0, "source": "pinned"}
+        tuned = {"config": parse_trace_config(args.trace_config), "ms": float("nan"), "tried": 0,
+                 "source": "pinned"}
     elif not args.no_autotune:
         from paper_2103_05875_amd import autotune
         scratch = ps.Volume(ctx, cfg)

@@ -42,3 +42,11 @@ def test_counters_scale_and_staleness(tmp_path):
     v, why = b.read_counters(str(out), cfg)
     assert v is None and "changed" in why
     assert b.read_counters(str(tmp_path / "missing.txt"), cfg)[0] is None
+
+
+def test_trace_config_string_round_trip():
+    b = _bench()
+    for s in ("4,4,4,0,21,256,0", "4,4,4,1,0,128,0", "4,4,4,2,21,256,0", "8,8,1,0,85,256,1"):
+        c = b.parse_trace_config(s)
+        assert b.config_string(c) == s
+    assert b.parse_trace_config("4,4,4,2,21,256,0")["persistent"] == 2
