@@ -84,7 +84,9 @@ def lib():
         L.or_scene_diag.argtypes = [ctypes.c_void_p]
         L.or_trace_shade.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Volume), _F, ctypes.c_int, _F,
                                      ctypes.c_double, _D, _D, _D, _D, _D, _D, _I32, _D, _I32, _I32,
-                                     ctypes.c_int, ctypes.c_int]
+                                     ctypes.c_int, ctypes.c_int, ctypes.POINTER(_D), ctypes.c_double]
+        L.or_probe_lookup.argtypes = [_D, ctypes.c_int, ctypes.c_int, _D, _D]
+        L.or_probe_query.argtypes = [ctypes.POINTER(_Volume), _D, _D, _D, _D, _D]
         L.or_closest_hits.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D, _I32, _D, _I32, ctypes.c_double]
         L.or_closest_hits_brute.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D, _I32, _D]
         L.or_border.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D]
@@ -235,14 +237,22 @@ def _volume_struct(cfg) -> _Volume:
 
 
 def trace_shade(scene: OracleScene, cfg, R, lights, delta_rel: float = 1e-6, maxc: int = 8,
-                nthreads: int = 0, bounds: bool = True):
+                nthreads: int = 0, bounds: bool = True, prev=None, ind_rel: float = 0.0):
     """Trace and shade every (probe, ray). Returns a dict of arrays shaped
     [P, n(, 3)]: L, r (nominal), L_lo, L_hi, r_lo, r_hi (tie bounds),
-    hit, hit_t, cand [P, n, maxc], ncand."""
+    hit, hit_t, cand [P, n, maxc], ncand. With ``prev`` = (irr, vis) maps
+    (float64 tiles), or (irr, vis, irr_lo, vis_lo, irr_hi, vis_hi) with the
+    tie-bound trajectories, every hit also receives the second bounce from
+    them; its lo/hi span the three trajectories, widened by ``ind_rel`` of
+    the term."""
     v = _volume_struct(cfg)
     P, n = cfg.n_probes, cfg.rays_per_probe
     R = _c(R, np.float32).reshape(9)
     lights = _c(lights, np.float32).reshape(-1, 6)
+    prev_ptrs, keep = None, []
+    if prev is not None:
+        keep = [_c(m, np.float64) for m in prev]
+        prev_ptrs = (_D * 6)(*[_p(m, _D) for m in keep], *([None] * (6 - len(keep))))
     L = np.zeros((P, n, 3))
     r = np.zeros((P, n))
     Llo = np.zeros((P, n, 3)) if bounds else None
@@ -255,10 +265,29 @@ def trace_shade(scene: OracleScene, cfg, R, lights, delta_rel: float = 1e-6, max
     ncand = np.zeros((P, n), np.int32)
     lib().or_trace_shade(scene.h, ctypes.byref(v), _p(R, _F), lights.shape[0], _p(lights, _F), delta_rel,
                          _p(L, _D), _p(Llo, _D), _p(Lhi, _D), _p(r, _D), _p(rlo, _D), _p(rhi, _D),
-                         _p(hit, _I32), _p(hit_t, _D), _p(cand, _I32), _p(ncand, _I32), maxc, nthreads)
+                         _p(hit, _I32), _p(hit_t, _D), _p(cand, _I32), _p(ncand, _I32), maxc, nthreads,
+                         prev_ptrs, float(ind_rel))
     out = dict(L=L, r=r, hit=hit, hit_t=hit_t, cand=cand, ncand=ncand)
     if bounds:
         out.update(L_lo=Llo, L_hi=Lhi, r_lo=rlo, r_hi=rhi)
+    return out
+
+
+def probe_lookup(tile: np.ndarray, d) -> np.ndarray:
+    """Bilinear lookup of one probe's tile [C, N+2, N+2] in direction d."""
+    t = _c(tile, np.float64)
+    C, S, _ = t.shape
+    out = np.zeros(C)
+    lib().or_probe_lookup(_p(t, _D), S - 2, C, _p(_c(d, np.float64), _D), _p(out, _D))
+    return out
+
+
+def probe_query(cfg, irr, vis, x, n) -> np.ndarray:
+    """Mean radiance at point x around normal n from the maps (irr, vis)."""
+    v = _volume_struct(cfg)
+    out = np.zeros(3)
+    lib().or_probe_query(ctypes.byref(v), _p(_c(irr, np.float64), _D), _p(_c(vis, np.float64), _D),
+                         _p(_c(x, np.float64), _D), _p(_c(n, np.float64), _D), _p(out, _D))
     return out
 
 
@@ -305,9 +334,14 @@ class OracleVolume:
         self.frame = 0
         self.last = None
 
-    def update(self, scene: OracleScene, R, lights, nthreads: int = 0, delta_rel: float = 1e-6):
+    def update(self, scene: OracleScene, R, lights, nthreads: int = 0, delta_rel: float = 1e-6,
+               ind_rel: float = 0.0):
         cfg = self.cfg
-        rays = trace_shade(scene, cfg, R, lights, delta_rel=delta_rel, nthreads=nthreads)
+        prev = None
+        if getattr(cfg, "multi_bounce", False):
+            prev = tuple(m.copy() for m in (self.irr, self.vis, self.irr_lo, self.vis_lo, self.irr_hi, self.vis_hi))
+        rays = trace_shade(scene, cfg, R, lights, delta_rel=delta_rel, nthreads=nthreads, prev=prev,
+                           ind_rel=ind_rel)
         dirs = ray_dirs(cfg.rays_per_probe, R)
         first = self.frame == 0
         blend_update(cfg, dirs, rays["L"], rays["r"], self.irr, self.vis, first, nthreads=nthreads)

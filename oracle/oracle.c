@@ -17,6 +17,12 @@
  *     one random rotation per frame, closest hit, direct shading, cosine
  *     (irradiance) and cosine-power (visibility) weighted means, hysteresis,
  *     guard-band copy by the octahedral fold.
+ *   - Section 3.2 (streaming probe visibility): the shading-time query of a
+ *     volume -- trilinear over the eight probes around the point, bilinear
+ *     octahedral lookup through the guard bands, and the Chebyshev bound of
+ *     the (mean, mean squared) distances as a per-probe visibility weight --
+ *     used as the second bounce of an update when requested (each hit adds
+ *     its albedo times the query of the maps as they stood before the frame).
  *   - Section 3.3 (visibility encoding): each FP16 value split into its two
  *     bytes.
  *   - Section 3.4 (repacking, update textures, change thresholding): guard
@@ -560,6 +566,134 @@ static void hit_frame(const or_scene *s, int k, const double o[3], const double 
     for (int c = 0; c < 3; ++c) x[c] = o[c] + t * d[c];
 }
 
+/* ======================================================================== */
+/* Probe query (second bounce)                                               */
+/* ======================================================================== */
+/* Bilinear lookup in one probe's tile of C channel maps ([C][(N+2)^2],
+ * channel planes, row-major) in direction d. Interior texel i is centred at
+ * tile coordinate i + 1 (guard texels at 0 and N+1), so the octahedral
+ * coordinate u lands at s = (u + 1) N / 2 + 0.5 and the four texels around s
+ * are always inside the tile: the guard bands carry the fold across the
+ * square's edges. */
+OR_API void or_probe_lookup(const double *tile, int N, int C, const double d[3], double *out)
+{
+    double uv[2];
+    or_oct_encode(d, uv);
+    const int S = N + 2;
+    double sx = (uv[0] + 1.0) * 0.5 * N + 0.5, sy = (uv[1] + 1.0) * 0.5 * N + 0.5;
+    int x0 = (int)floor(sx), y0 = (int)floor(sy);
+    if (x0 > N) x0 = N;
+    if (y0 > N) y0 = N;
+    if (x0 < 0) x0 = 0;
+    if (y0 < 0) y0 = 0;
+    const double fx = sx - x0, fy = sy - y0;
+    for (int c = 0; c < C; ++c) {
+        const double *t = tile + (size_t)c * S * S;
+        const double a = t[y0 * S + x0], b = t[y0 * S + x0 + 1];
+        const double e = t[(y0 + 1) * S + x0], f = t[(y0 + 1) * S + x0 + 1];
+        out[c] = (1.0 - fy) * ((1.0 - fx) * a + fx * b) + fy * ((1.0 - fx) * e + fx * f);
+    }
+}
+
+/* Mean radiance arriving at point x around normal n, from the volume's
+ * stored maps (irr [P][3][(Ni+2)^2], vis [P][2][(Nv+2)^2]): the probes at the
+ * corners of the grid cell holding x (clamped to the grid) weighted
+ * trilinearly and by the Chebyshev bound of their visibility moments in the
+ * direction of x, each looked up in direction n; 0 when every weight
+ * vanishes. */
+OR_API void or_probe_query(const or_volume *v, const double *irr, const double *vis, const double x[3],
+                           const double n[3], double out[3])
+{
+    const int dims[3] = {v->nx, v->ny, v->nz};
+    int c0[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        const double g = (x[a] - v->origin[a]) / v->spacing[a];
+        if (dims[a] == 1) {
+            c0[a] = 0;
+            f[a] = 0.0;
+            continue;
+        }
+        int c = (int)floor(g);
+        if (c < 0) c = 0;
+        if (c > dims[a] - 2) c = dims[a] - 2;
+        double t = g - c;
+        if (t < 0.0) t = 0.0;
+        if (t > 1.0) t = 1.0;
+        c0[a] = c;
+        f[a] = t;
+    }
+    const int Ni = v->irr_res, Nv = v->vis_res;
+    const size_t ti = (size_t)3 * (Ni + 2) * (Ni + 2), tv = (size_t)2 * (Nv + 2) * (Nv + 2);
+    double acc[3] = {0.0, 0.0, 0.0}, wsum = 0.0;
+    for (int corner = 0; corner < 8; ++corner) {
+        int idx[3];
+        double w = 1.0;
+        int skip = 0;
+        for (int a = 0; a < 3; ++a) {
+            const int bit = (corner >> a) & 1;
+            if (bit && dims[a] == 1) skip = 1;
+            idx[a] = c0[a] + bit;
+            w *= bit ? f[a] : 1.0 - f[a];
+        }
+        if (skip) continue;
+        const int p = idx[0] + v->nx * (idx[1] + v->ny * idx[2]);
+        double pp[3];
+        probe_origin(v, p, pp);
+        const double vec[3] = {x[0] - pp[0], x[1] - pp[1], x[2] - pp[2]};
+        const double dist = sqrt(vec[0] * vec[0] + vec[1] * vec[1] + vec[2] * vec[2]);
+        if (dist > 0.0) {
+            const double dir[3] = {vec[0] / dist, vec[1] / dist, vec[2] / dist};
+            double mom[2];
+            or_probe_lookup(vis + (size_t)p * tv, Nv, 2, dir, mom);
+            if (dist > mom[0]) {
+                const double var = fmax(mom[1] - mom[0] * mom[0], 0.0);
+                const double dd = dist - mom[0];
+                w *= var / (var + dd * dd);
+            }
+        }
+        double e[3];
+        or_probe_lookup(irr + (size_t)p * ti, Ni, 3, n, e);
+        for (int c = 0; c < 3; ++c) acc[c] += w * e[c];
+        wsum += w;
+    }
+    for (int c = 0; c < 3; ++c) out[c] = wsum > 1e-20 ? acc[c] / wsum : 0.0;
+}
+
+/* Stored maps a second bounce reads: the nominal trajectory and the lower
+ * and upper tie-bound trajectories ([0] nominal, [1] lower, [2] upper). */
+typedef struct {
+    const double *irr[3], *vis[3];
+} or_prev_maps;
+
+/* Adds the second bounce to a hit's radiance: albedo times the mean
+ * radiance queried at the hit point moved off the surface along its normal
+ * by a tenth of the smallest probe spacing (so that the probes' own
+ * distance record of that surface does not shadow it). The nominal answer
+ * reads the nominal maps; lo/hi span the answers on all three trajectories
+ * (a lower-precision side's maps lie between the bound maps) and widen by
+ * 'rel' of the term (the sides' stored maps also differ by rounding). */
+static void add_indirect(const or_scene *s, const or_volume *v, const or_prev_maps *pm, int k, const double x[3],
+                         const double n[3], double rel, double L[3], double Llo[3], double Lhi[3])
+{
+    const double bias = 0.1 * fmin(v->spacing[0], fmin(v->spacing[1], v->spacing[2]));
+    const double xb[3] = {x[0] + bias * n[0], x[1] + bias * n[1], x[2] + bias * n[2]};
+    double e[3][3];
+    for (int m = 0; m < 3; ++m) or_probe_query(v, pm->irr[m], pm->vis[m], xb, n, e[m]);
+    for (int c = 0; c < 3; ++c) {
+        const double a = s->alb[3 * k + c];
+        const double ind = a * e[0][c];
+        double lo = ind, hi = ind;
+        for (int m = 1; m < 3; ++m) {
+            lo = fmin(lo, a * e[m][c]);
+            hi = fmax(hi, a * e[m][c]);
+        }
+        L[c] += ind;
+        Llo[c] += lo - rel * fabs(lo);
+        Lhi[c] += hi + rel * fabs(hi);
+    }
+}
+
 /* Distance along (o, d) to the plane of triangle k (for a candidate that a
  * perturbed ray found). */
 static double plane_t(const or_scene *s, int k, const double o[3], const double d[3])
@@ -595,8 +729,21 @@ static double plane_t(const or_scene *s, int k, const double o[3], const double 
 OR_API int or_trace_shade(const or_scene *s, const or_volume *v, const float R[9], int nlights,
                           const float *lights, double delta_rel, double *L_nom, double *L_lo, double *L_hi,
                           double *r_nom, double *r_lo, double *r_hi, int32_t *hit, double *hit_t,
-                          int32_t *cand, int32_t *ncand, int maxc, int nthreads)
+                          int32_t *cand, int32_t *ncand, int maxc, int nthreads, const double *const *prev,
+                          double ind_rel)
 {
+    /* prev: NULL (no second bounce) or six maps: irr, vis (nominal), irr_lo,
+     * vis_lo, irr_hi, vis_hi; a NULL bound pair falls back to the nominal */
+    or_prev_maps pm;
+    const or_prev_maps *pmp = NULL;
+    if (prev) {
+        for (int m = 0; m < 3; ++m) {
+            const int have = prev[2 * m] && prev[2 * m + 1];
+            pm.irr[m] = have ? prev[2 * m] : prev[0];
+            pm.vis[m] = have ? prev[2 * m + 1] : prev[1];
+        }
+        pmp = &pm;
+    }
     const int P = v->nx * v->ny * v->nz;
     const int n = v->n;
     double *dirs = (double *)malloc(sizeof(double) * 3 * n);
@@ -663,9 +810,11 @@ OR_API int or_trace_shade(const or_scene *s, const or_volume *v, const float R[9
                     int grazing;
                     hit_frame(s, k, o, d, t, x, nrm, &grazing);
                     shade_hit(s, k, x, nrm, nlights, lights, m, Lc, Lcl, Lch);
+                    if (pmp) add_indirect(s, v, pmp, k, x, nrm, ind_rel, Lc, Lcl, Lch);
                     if (grazing) {  /* the other side is acceptable too */
                         double nf[3] = {-nrm[0], -nrm[1], -nrm[2]}, a[3], b[3], e[3];
                         shade_hit(s, k, x, nf, nlights, lights, m, a, b, e);
+                        if (pmp) add_indirect(s, v, pmp, k, x, nf, ind_rel, a, b, e);
                         for (int ch = 0; ch < 3; ++ch) {
                             Lcl[ch] = fmin(Lcl[ch], b[ch]);
                             Lch[ch] = fmax(Lch[ch], e[ch]);

@@ -296,6 +296,44 @@ def perturb_fp16_maps(irr: np.ndarray, vis: np.ndarray, seed: int,
     return out[0], out[1]
 
 
+def query_maps(cfg, seed: int, var_lo: float = 0.02):
+    """Stored maps for shading-query tests: full tiles (guard texels drawn
+    like the interior) with irradiance in [0, 2] per channel, visibility mean
+    mu in [0.3, 3] and mean square mu^2 + var, var in [var_lo, 0.5]. Float64
+    arrays holding values of the volume's storage format (binary16 values
+    when cfg.fp16): irradiance [P, 3, 10, 10], visibility [P, 2, 18, 18]."""
+    rng = np.random.default_rng(seed)
+    P = cfg.n_probes
+    si, sv = cfg.irr_res + 2, cfg.vis_res + 2
+    irr = rng.uniform(0.0, 2.0, size=(P, 3, si, si))
+    mu = rng.uniform(0.3, 3.0, size=(P, sv, sv))
+    var = rng.uniform(var_lo, 0.5, size=mu.shape)
+    vis = np.stack([mu, mu * mu + var], axis=1)
+    dt = np.float16 if cfg.fp16 else np.float32
+    return irr.astype(dt).astype(np.float64), vis.astype(dt).astype(np.float64)
+
+
+def query_points(cfg, n_points: int, seed: int):
+    """Query points and normals (float32 [m, 3] each): uniform over the probe
+    grid's box grown by one spacing on every side (clamped cells), then every
+    probe position; normals uniform on the sphere, then the six axis
+    directions in turn (octahedral poles and fold lines)."""
+    rng = np.random.default_rng(seed)
+    o = np.asarray(cfg.origin, np.float64)
+    s = np.asarray(cfg.spacing, np.float64)
+    dims = np.array([cfg.nx, cfg.ny, cfg.nz])
+    lo, hi = o - s, o + s * dims
+    pts = rng.uniform(lo, hi, size=(n_points, 3))
+    idx = np.arange(cfg.n_probes)
+    grid = np.stack([idx % cfg.nx, (idx // cfg.nx) % cfg.ny, idx // (cfg.nx * cfg.ny)], axis=1)
+    pts = np.concatenate([pts, o + s * grid])
+    nrm = rng.normal(size=pts.shape)
+    axes = np.concatenate([np.eye(3), -np.eye(3)])
+    nrm[n_points:] = axes[np.arange(len(pts) - n_points) % 6]
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    return pts.astype(np.float32), nrm.astype(np.float32)
+
+
 def synthetic_rays(n_probes: int, n_rays: int, seed: int, max_distance: float = 4.0):
     """Random ray records for blend-only tests: radiance rgb >= 0 (float32
     [P, n, 3]) and distance in [0, max_distance] (float32 [P, n])."""
@@ -325,6 +363,7 @@ class VolumeConfig:
     fp16: bool = True
     sky: tuple = (0.0, 0.0, 0.0)
     first_frame_no_history: bool = True
+    multi_bounce: bool = False
 
     @property
     def n_probes(self) -> int:

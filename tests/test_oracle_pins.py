@@ -482,6 +482,160 @@ def test_border_makes_bilinear_lookup_continuous_across_the_fold(O, N):
         assert np.array_equal(T[1:-1, 1:-1], tiles[p, 0, 1:-1, 1:-1])
 
 
+# ---------------------------------------------------------------- probe query (second bounce)
+def _random_tiles(O, rng, P, C, N, lo=0.0, hi=1.0):
+    t = np.zeros((P, C, N + 2, N + 2))
+    t[:, :, 1:-1, 1:-1] = rng.uniform(lo, hi, size=(P, C, N, N))
+    return O.border(t)
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_probe_lookup_at_texel_centres_returns_the_texel(O, N):
+    """Looking up the direction of an interior texel's centre returns that
+    texel exactly (the lookup's texel convention is the blend's)."""
+    rng = np.random.default_rng(40 + N)
+    tile = _random_tiles(O, rng, 1, 2, N)[0]
+    dirs = O.texel_dirs(N)
+    for t in rng.choice(N * N, 40, replace=False):
+        j, i = divmod(int(t), N)
+        got = O.probe_lookup(tile, dirs[t])
+        assert np.allclose(got, tile[:, j + 1, i + 1], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_probe_lookup_continuous_across_the_fold(O, N):
+    """Directions just either side of the lower hemisphere's fold lines
+    (x = 0 or y = 0 with z < 0) land on opposite edges of the square; with
+    the guard bands the bilinear lookups agree in the limit."""
+    rng = np.random.default_rng(50 + N)
+    tile = _random_tiles(O, rng, 1, 1, N)[0]
+    eps = 1e-10
+    for _ in range(60):
+        a, zc = rng.uniform(-1, 1), -rng.uniform(0.05, 1.0)
+        for d0, d1 in (((a, eps, zc), (a, -eps, zc)), ((eps, a, zc), (-eps, a, zc))):
+            u = O.probe_lookup(tile, np.array(d0) / np.linalg.norm(d0))
+            w = O.probe_lookup(tile, np.array(d1) / np.linalg.norm(d1))
+            assert np.allclose(u, w, atol=1e-7)
+    # the bottom pole (all four corners of the square) is one value
+    poles = [O.probe_lookup(tile, np.array([sx * 1e-9, sy * 1e-9, -1.0])) for sx in (-1, 1) for sy in (-1, 1)]
+    assert np.allclose(poles, poles[0], atol=1e-7)
+
+
+def _query_cfg(nx, ny, nz, spacing=(1.0, 1.0, 1.0)):
+    return _cfg(nx=nx, ny=ny, nz=nz, spacing=spacing, origin=(0.0, 0.0, 0.0))
+
+
+def _const_maps(O, cfg, irr_vals, mean, var):
+    """Maps with probe p's irradiance the constant RGB irr_vals[p] and its
+    visibility moments (mean[p], mean[p]^2 + var[p]) in every texel."""
+    irr, vis = O.empty_maps(cfg)
+    for p in range(cfg.n_probes):
+        irr[p] = np.asarray(irr_vals[p], np.float64)[:, None, None]
+        vis[p, 0] = mean[p]
+        vis[p, 1] = mean[p] ** 2 + var[p]
+    return irr, vis
+
+
+def test_probe_query_at_a_probe_is_that_probes_lookup(O):
+    """At a probe's own position the trilinear weight is 1 for that probe
+    (grid indexing p = x + nx (y + ny z), including the last plane of each
+    axis), so the query is its lookup in the normal's direction."""
+    cfg = _query_cfg(3, 2, 4, spacing=(0.5, 1.25, 0.75))
+    rng = np.random.default_rng(7)
+    irr = _random_tiles(O, rng, cfg.n_probes, 3, cfg.irr_res, 0.1, 2.0)
+    vis = np.zeros((cfg.n_probes, 2, cfg.vis_res + 2, cfg.vis_res + 2))
+    for p in range(cfg.n_probes):
+        x, y, z = p % 3, (p // 3) % 2, p // 6
+        pos = np.array([0.5 * x, 1.25 * y, 0.75 * z])
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        got = O.probe_query(cfg, irr, vis, pos, n)
+        assert np.allclose(got, O.probe_lookup(irr[p], n), rtol=1e-12, atol=0)
+
+
+def test_probe_query_trilinear_without_occlusion(O):
+    """Probes whose recorded distances lie beyond the point: weights are the
+    trilinear ones, so the query of per-probe constants is their trilinear
+    interpolation (exact fractions chosen so the weights are known)."""
+    cfg = _query_cfg(2, 2, 2)
+    vals = [(float(p), 2.0 * p, 1.0) for p in range(8)]
+    irr, vis = _const_maps(O, cfg, vals, [100.0] * 8, [1.0] * 8)
+    fx, fy, fz = 0.25, 0.5, 0.75
+    want = np.zeros(3)
+    for p in range(8):
+        bx, by, bz = p & 1, (p >> 1) & 1, p >> 2
+        w = (fx if bx else 1 - fx) * (fy if by else 1 - fy) * (fz if bz else 1 - fz)
+        want += w * np.array(vals[p])
+    got = O.probe_query(cfg, irr, vis, np.array([fx, fy, fz]), np.array([0.0, 0.0, 1.0]))
+    assert np.allclose(got, want, rtol=1e-12)
+    # outside the grid the edge cell is used with its weights clamped
+    got = O.probe_query(cfg, irr, vis, np.array([-3.0, 0.5, 9.0]), np.array([0.0, 1.0, 0.0]))
+    assert np.allclose(got, 0.5 * (np.array(vals[4]) + np.array(vals[6])), rtol=1e-12)
+
+
+@pytest.mark.parametrize("var, want", [(0.09, 3.0), (0.0, 4.0), (0.01, (0.5 * 0.1 * 1 + 0.5 * 4) / (0.5 * 0.1 + 0.5))])
+def test_probe_query_chebyshev_weight(O, var, want):
+    """Two probes 1 apart, the point halfway. Probe A recorded mean distance
+    0.2 towards it (occluder nearer than the point, 0.3 short), probe B 10.
+    A's weight is 1/2 * var / (var + 0.3^2): with var = 0.09 that is 1/4 and
+    the query (1/4 * 1 + 1/2 * 4) / (3/4) = 3; with var = 0 A is excluded."""
+    cfg = _query_cfg(2, 1, 1)
+    irr, vis = _const_maps(O, cfg, [(1.0, 1.0, 1.0), (4.0, 4.0, 4.0)], [0.2, 10.0], [var, 1.0])
+    got = O.probe_query(cfg, irr, vis, np.array([0.5, 0.0, 0.0]), np.array([0.0, 0.0, 1.0]))
+    assert np.allclose(got, want, rtol=1e-12)
+
+
+def test_probe_query_of_empty_maps_is_zero(O):
+    cfg = _query_cfg(2, 2, 2)
+    irr, vis = O.empty_maps(cfg)
+    assert np.array_equal(O.probe_query(cfg, irr, vis, np.array([0.3, 0.4, 0.5]), np.array([1.0, 0, 0])),
+                          np.zeros(3))
+
+
+@pytest.mark.parametrize("h", [0.0, 0.6])
+def test_second_bounce_in_closed_box_closed_form(O, h):
+    """Closed box, every wall emitting E with albedo rho, no lights. Frame 0
+    reads empty maps, so the map is E. From then on every hit adds rho times
+    the (uniform) stored radiance: m_k = h m_(k-1) + (1 - h)(E + rho m_(k-1)),
+    the geometric series E (1 + rho + ... + rho^k) when h = 0, converging to
+    E / (1 - rho)."""
+    E = np.array([0.7, 0.4, 0.2])
+    rho = np.array([0.5, 0.25, 0.8])
+    tris = synth._box_triangles(np.array([-1.5, -1.0, -1.25]), np.array([2.0, 1.75, 1.5]))
+    sc = O.OracleScene(tris.astype(np.float32), np.tile(rho, (12, 1)).astype(np.float32),
+                       np.tile(E, (12, 1)).astype(np.float32))
+    cfg = _cfg(nx=3, ny=2, nz=2, spacing=(0.5, 0.75, 0.6), origin=(-0.4, -0.3, -0.2), rays_per_probe=128,
+               hysteresis=h, multi_bounce=True)
+    vol = O.OracleVolume(cfg)
+    Ef = E.astype(np.float32).astype(np.float64)
+    rf = rho.astype(np.float32).astype(np.float64)
+    hf = float(np.float32(h))
+    m = Ef.copy()
+    for k in range(5):
+        vol.update(sc, synth.rotation(8, k), np.zeros((0, 6), np.float32))
+        if k > 0:
+            m = hf * m + (1 - hf) * (Ef + rf * m)
+        for c in range(3):
+            assert np.allclose(vol.irr[:, c, 1:-1, 1:-1], m[c], rtol=1e-12), (k, c)
+    if h == 0.0:
+        assert np.allclose(m, Ef * (1 - rf ** 5) / (1 - rf), rtol=1e-12)
+
+
+def test_second_bounce_off_leaves_the_update_unchanged(O):
+    """Without the flag the maps do not depend on the stored ones: a box
+    whose walls reflect gives the emission alone every frame."""
+    E = np.array([0.3, 0.6, 0.9])
+    tris = synth._box_triangles(np.array([-2.0, -2.0, -2.0]), np.array([2.0, 2.0, 2.0]))
+    sc = O.OracleScene(tris.astype(np.float32), np.full((12, 3), 0.5, np.float32),
+                       np.tile(E, (12, 1)).astype(np.float32))
+    cfg = _cfg(rays_per_probe=64, hysteresis=0.0)
+    vol = O.OracleVolume(cfg)
+    for k in range(3):
+        vol.update(sc, synth.rotation(9, k), np.zeros((0, 6), np.float32))
+        for c in range(3):
+            assert np.allclose(vol.irr[:, c, 1:-1, 1:-1], np.float32(E[c]), rtol=1e-12)
+
+
 # ---------------------------------------------------------------- packing
 def _np_masks(cur_irr, cur_vis, ref_irr, ref_vis, tau_irr, tau_vis):
     ci = cur_irr[:, :, 1:-1, 1:-1].reshape(cur_irr.shape[0], 3, -1)
