@@ -70,6 +70,13 @@ typedef enum { PV_MAP_FP32 = 0, PV_MAP_FP16 = 1 } pv_map_format;
 /* pv_volume_desc.flags */
 #define PV_FIRST_FRAME_NO_HISTORY 1u /* first update of a volume uses h = 0 */
 #define PV_KEEP_HITS 2u              /* keep the hit triangle id of every ray */
+/* Second bounce (Sec. 3.2's shading-time query applied during the update):
+ * every hit adds its albedo times the volume's query (pv_probe_query) at the
+ * hit point moved off the surface along its normal by a tenth of the
+ * smallest probe spacing, evaluated on the maps as they stand before the
+ * frame's blend. Repeated frames thus accumulate multiple bounces. Costs an
+ * 8-byte hit record per ray and one more launch per update. */
+#define PV_MULTI_BOUNCE 4u
 
 #define PV_MAX_LIGHTS 8
 #define PV_MAX_PROBES 65536          /* the 2-byte probe index (Section 3.4) */
@@ -94,7 +101,7 @@ typedef struct {
     int vis_sharpness;       /* visibility weight = max(0, cos)^s, s in [1, 128] */
     pv_map_format format;
     float sky[3];            /* radiance of rays that leave the scene */
-    uint32_t flags;          /* PV_FIRST_FRAME_NO_HISTORY | PV_KEEP_HITS */
+    uint32_t flags;          /* PV_FIRST_FRAME_NO_HISTORY | PV_KEEP_HITS | PV_MULTI_BOUNCE */
 } pv_volume_desc;
 
 typedef struct {
@@ -199,6 +206,23 @@ pv_status pv_get_maps(pv_volume *vol, void **irr_dev, void **vis_dev);
 /* Borrowed device pointers: ray records [P][n] float4, hit triangle ids
  * [P][n] int32 (-1 = miss; NULL unless PV_KEEP_HITS), directions [n] float4. */
 pv_status pv_get_rays(pv_volume *vol, void **rays_dev, void **hits_dev, void **dirs_dev);
+/*
+ * Shading query of the volume's current maps (Sec. 3.2: probe visibility by
+ * a Chebyshev test on the stored mean and mean-squared distances), the step
+ * a client runs per shaded point: the mean radiance arriving at point i
+ * around normal i, as the weighted mean over the eight probes at the corners
+ * of the grid cell holding the point (clamped to the grid) of each probe's
+ * irradiance tile filtered bilinearly in the normal's direction. A probe's
+ * weight is its trilinear weight, times var / (var + (d - mu)^2) when the
+ * point's distance d from it exceeds the mean distance mu its visibility
+ * tile records in that direction (var = mu2 - mu^2, floored at 0; var = 0
+ * excludes the probe). 0 when every weight vanishes.
+ * points_dev, normals_dev: device float [n][3] (normals non-zero, any
+ * length); out_dev: device float [n][3], written. Asynchronous on 'stream';
+ * n = 0 does nothing. FP32 arithmetic on FP32 or FP16 maps.
+ */
+pv_status pv_probe_query(pv_volume *vol, const float *points_dev, const float *normals_dev, int64_t n, float *out_dev,
+                         void *stream);
 /* Replace the maps from host memory (checkpoint import) and set the frame
  * counter; synchronous. */
 pv_status pv_set_maps(pv_volume *vol, const void *irr_host, const void *vis_host, int64_t frame);
@@ -296,7 +320,8 @@ typedef enum {
     PV_STAGE_SHADOW = 7,
     PV_STAGE_SHADE = 8,
     PV_STAGE_PACK_FINISH = 9,
-    PV_STAGE_COUNT = 10
+    PV_STAGE_BOUNCE = 10,
+    PV_STAGE_COUNT = 11
 } pv_stage;
 
 /* When enabled, every kernel launch of the context is bracketed by a pair

@@ -49,11 +49,13 @@ struct BatchVolume {
     int n_waves;
     int first_blend;  // prefix over volumes of blend groups
     int n_blend;
+    int first_bounce; // prefix over volumes of second-bounce blocks (0 blocks without it)
+    int n_bounce;
     int bricks_x, bricks_y, bricks_z;
 };
 
 // ---------------------------------------------------------------------------
-// Launchers (trace.hip, blend.hip, batched.hip, pack.hip)
+// Launchers (trace.hip, blend.hip, batched.hip, bounce.hip, pack.hip)
 // ---------------------------------------------------------------------------
 // Directions and weight tables; the 9 work counters are zeroed for the trace that follows
 hipError_t launch_raydirs(const FrameParams &fp, const VolumeParams &vp, float4 *dirs, const WeightTables &wt,
@@ -67,6 +69,15 @@ hipError_t launch_trace_batched(const BatchVolume *vols_dev, int n_vols, int tot
 hipError_t launch_blend_batched(const BatchVolume *vols_dev, int n_vols, int total_blend, hipStream_t s);
 hipError_t launch_raydirs_batched(const BatchVolume *vols_dev, const FrameParams *frames_dev, int n_vols,
                                   int max_parts, hipStream_t s);
+
+// Second bounce (bounce.hip): adds albedo x the stored maps' query to every
+// hit record's radiance (vp.hitrec must be set); the client query.
+int bounce_blocks(int P, int n);
+hipError_t launch_bounce(const VolumeParams &vp, const SceneView &sv, const float4 *dirs, float4 *rays,
+                         const void *irr, const void *vis, int fp16, hipStream_t s);
+hipError_t launch_bounce_batched(const BatchVolume *vols_dev, int n_vols, int total_blocks, hipStream_t s);
+hipError_t launch_probe_query(const VolumeParams &vp, const void *irr, const void *vis, int fp16, const float *pts,
+                              const float *nrms, float *out, long long n, hipStream_t s);
 
 struct PackBuffers {
     const uint16_t *cur_irr, *cur_vis;   // tiles

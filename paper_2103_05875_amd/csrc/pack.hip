@@ -2,24 +2,13 @@
 // ordered compaction with a delta-coded index buffer, XOR byte planes against
 // the client's last-transmitted state, reference update, checksum.
 #include "device_common.h"
+#include "packet_format.h"
 
 namespace pv {
 
 // ---------------------------------------------------------------------------
 // pack
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
-    h ^= h >> 16;
-    h *= 0x85ebca6bu;
-    h ^= h >> 13;
-    h *= 0xc2b2ae35u;
-    h ^= h >> 16;
-    return h;
-}
-
-__device__ __forceinline__ uint32_t word_hash(uint32_t w, uint32_t word_index) {
-    return fmix32(w ^ (word_index * 0x9E3779B9u));
-}
 
 __device__ __forceinline__ bool texel_changed(uint16_t a, uint16_t b, float tau) {
     if (tau == 0.f) return a != b;
@@ -345,14 +334,14 @@ __global__ __launch_bounds__(kScanThreads) void k_pack_finish(PackBuffers b, int
         uint32_t tot = 0;
         for (int w = 0; w < kScanThreads / 64; ++w) tot += sh[w];
         uint32_t *h = reinterpret_cast<uint32_t *>(pk);
-        h[0] = 0x4B505650u;
-        h[1] = 1u | (32u << 16);
-        h[2] = client;
-        h[3] = seq;
-        h[4] = (uint32_t)P;
-        h[5] = (uint32_t)K_irr;
-        h[6] = (uint32_t)K_vis;
-        h[7] = tot;
+        h[kHdrMagic] = kPacketMagic;
+        h[kHdrVersion] = kPacketVersion;
+        h[kHdrClient] = client;
+        h[kHdrSeq] = seq;
+        h[kHdrProbes] = (uint32_t)P;
+        h[kHdrKIrr] = (uint32_t)K_irr;
+        h[kHdrKVis] = (uint32_t)K_vis;
+        h[kHdrChecksum] = tot;
     }
 }
 

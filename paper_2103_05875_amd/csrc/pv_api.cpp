@@ -115,6 +115,7 @@ struct pv_volume {
     float4 *rays = nullptr, *dirs = nullptr;
     WeightTables wt;  // blend weights of the current frame
     int32_t *hits = nullptr;
+    int2 *hitrec = nullptr;  // second-bounce hit records (PV_MULTI_BOUNCE)
     int *queue = nullptr;  // work counters (queue_counter: 0..7 per XCD, 8 shadow-queue length)
     int64_t frame = 0;
     pv_scene *scene = nullptr;
@@ -450,7 +451,9 @@ static pv_status validate_desc(const pv_volume_desc *d) {
         return fail(PV_ERR_ARG, "origin, spacing and sky must be finite");
     if (d->irr_res != 8 || d->vis_res != 16)
         return fail(PV_ERR_UNSUPPORTED, "supported: irr_res = 8 and vis_res = 16");
-    if (d->flags & ~(PV_FIRST_FRAME_NO_HISTORY | PV_KEEP_HITS)) return fail(PV_ERR_ARG, "unknown flags");
+    if (!(d->spacing[0] > 0.f && d->spacing[1] > 0.f && d->spacing[2] > 0.f))
+        return fail(PV_ERR_ARG, "spacing must be > 0 on every axis");
+    if (d->flags & ~(PV_FIRST_FRAME_NO_HISTORY | PV_KEEP_HITS | PV_MULTI_BOUNCE)) return fail(PV_ERR_ARG, "unknown flags");
     return PV_OK;
 }
 
@@ -461,6 +464,7 @@ static uint64_t volume_bytes(const pv_volume_desc *d) {
                  (uint64_t)kQueueInts * 4 +
                  (uint64_t)(weight_table_floats(n) + weight_part_floats(n)) * 4;
     if (d->flags & PV_KEEP_HITS) b += (uint64_t)P * n * 4;
+    if (d->flags & PV_MULTI_BOUNCE) b += (uint64_t)P * n * 8;
     return b;
 }
 
@@ -479,6 +483,7 @@ static void free_volume(pv_volume *v) {
     hipFree(v->wt.w);
     hipFree(v->wt.part);
     hipFree(v->hits);
+    hipFree(v->hitrec);
     hipFree(v->queue);
     hipFree(v->split.hitrec);
     hipFree(v->split.occ);
@@ -506,6 +511,8 @@ extern "C" pv_status pv_create_volume(pv_ctx *ctx, const pv_volume_desc *d, pv_v
     if (st == PV_OK) st = dev_alloc(&v->wt.w, weight_table_floats(v->n) * 4, "blend weight table");
     if (st == PV_OK) st = dev_alloc(&v->wt.part, weight_part_floats(v->n) * 4, "blend weight sums");
     if (st == PV_OK && (d->flags & PV_KEEP_HITS)) st = dev_alloc(&v->hits, (size_t)v->P * v->n * 4, "hit ids");
+    if (st == PV_OK && (d->flags & PV_MULTI_BOUNCE))
+        st = dev_alloc(&v->hitrec, (size_t)v->P * v->n * sizeof(int2), "hit records");
     if (st == PV_OK) st = dev_alloc(&v->queue, kQueueInts * sizeof(int), "work queues");
     if (st == PV_OK && launch_zero(v->wt.w, weight_table_floats(v->n) * 4, ctx->stream) != hipSuccess)
         st = fail(PV_ERR_DEVICE, "zero fill");  // the padding past n stays zero
@@ -579,6 +586,7 @@ static VolumeParams volume_params(const pv_volume *v) {
     p.max_distance = d.max_distance;
     for (int k = 0; k < 3; ++k) p.sky[k] = d.sky[k];
     p.vis_sharpness = d.vis_sharpness;
+    p.hitrec = v->hitrec;
     return p;
 }
 
@@ -634,6 +642,9 @@ extern "C" pv_status pv_update_probes(pv_volume *v, const pv_frame *f, void *str
     const int fp16 = v->desc.format == PV_MAP_FP16;
     const float h = effective_h(v);
     PV_TRY(enqueue_trace(v, fp, sv, nullptr, s));
+    if (v->hitrec)
+        HIP_TRY(timed(c, PV_STAGE_BOUNCE, s,
+                      [&] { return launch_bounce(vp, sv, v->dirs, v->rays, v->irr, v->vis, fp16, s); }));
     HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend(vp, v->wt, v->rays, v->irr, v->vis, fp16, h, s); }));
     PV_TRY(note_scene_use(v->scene, s));
     v->frame++;
@@ -722,6 +733,20 @@ extern "C" pv_status pv_get_rays(pv_volume *v, void **rays, void **hits, void **
     return PV_OK;
 }
 
+extern "C" pv_status pv_probe_query(pv_volume *v, const float *pts, const float *nrms, int64_t n, float *out,
+                                    void *stream) {
+    if (!v) return fail(PV_ERR_ARG, "volume is NULL");
+    if (n < 0) return fail(PV_ERR_ARG, "n must be >= 0");
+    if (n == 0) return PV_OK;
+    if (!pts || !nrms || !out) return fail(PV_ERR_ARG, "NULL buffer");
+    if (n > (int64_t)1 << 31) return fail(PV_ERR_ARG, "at most 2^31 points per call");
+    HIP_TRY(hipSetDevice(v->ctx->device));
+    const int fp16 = v->desc.format == PV_MAP_FP16;
+    HIP_TRY(launch_probe_query(volume_params(v), v->irr, v->vis, fp16, pts, nrms, out, (long long)n,
+                               pick(v->ctx, stream)));
+    return PV_OK;
+}
+
 extern "C" pv_status pv_set_maps(pv_volume *v, const void *irr, const void *vis, int64_t frame) {
     if (!v || !irr || !vis) return fail(PV_ERR_ARG, "NULL argument");
     if (frame < 0) return fail(PV_ERR_ARG, "frame must be >= 0");
@@ -771,7 +796,7 @@ struct pv_batch_graph {
     std::vector<pv_volume *> vols;
     BatchSlot slot;           // device descriptors + pinned staging owned by the graph
     size_t o_b = 0, o_f = 0, bytes = 0;
-    int waves = 0, blend = 0, max_parts = 0;
+    int waves = 0, blend = 0, bounce = 0, max_parts = 0;
     bool short_stack = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -780,15 +805,17 @@ struct pv_batch_graph {
 };
 
 // Fills the pinned staging of a batch: descriptors and frames; returns the
-// packet and blend-group totals, the most ray-direction blocks of a volume,
-// and whether every BVH of the batch fits 16-bit stack entries.
+// packet, blend-group and second-bounce block totals, the most ray-direction
+// blocks of a volume, and whether every BVH of the batch fits 16-bit stack
+// entries.
 static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int n, char *h, size_t *offs, int &waves,
-                            int &blend, int &max_parts, bool &short_stack) {
+                            int &blend, int &bounce, int &max_parts, bool &short_stack) {
     std::vector<BatchVolume> bv(n);
     std::vector<FrameParams> fps(n);
     std::memset(fps.data(), 0, sizeof(FrameParams) * n);
     waves = 0;
     blend = 0;
+    bounce = 0;
     max_parts = 0;
     short_stack = true;
     for (int i = 0; i < n; ++i) {
@@ -817,6 +844,9 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
         b.n_blend = (v->P + kBlendTile - 1) / kBlendTile * kBlendSplit;
         b.first_blend = blend;
         blend += b.n_blend;
+        b.n_bounce = v->hitrec ? bounce_blocks(v->P, v->n) : 0;
+        b.first_bounce = bounce;
+        bounce += b.n_bounce;
     }
     size_t off = 0;
     auto put = [&](const void *src, size_t bytes) {
@@ -857,16 +887,18 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
     HIP_TRY(hipEventSynchronize(slot.done));  // the slot's previous launch has finished
     PV_TRY(ensure_slot(c, slot, n));
     size_t offs[3];
-    int waves, blend, max_parts;
+    int waves, blend, bounce, max_parts;
     bool short_stack;
     char *h = (char *)slot.stage_host;
-    PV_TRY(fill_batch(vols, frames, n, h, offs, waves, blend, max_parts, short_stack));
+    PV_TRY(fill_batch(vols, frames, n, h, offs, waves, blend, bounce, max_parts, short_stack));
     HIP_TRY(hipMemcpyAsync(slot.batch_dev, h + offs[0], sizeof(BatchVolume) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(slot.frames_dev, h + offs[1], sizeof(FrameParams) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s,
                   [&] { return launch_raydirs_batched(slot.batch_dev, slot.frames_dev, n, max_parts, s); }));
     HIP_TRY(timed(c, PV_STAGE_BATCHED, s,
                   [&] { return launch_trace_batched(slot.batch_dev, n, waves, slot.frames_dev, short_stack, s); }));
+    if (bounce > 0)
+        HIP_TRY(timed(c, PV_STAGE_BOUNCE, s, [&] { return launch_bounce_batched(slot.batch_dev, n, bounce, s); }));
     HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend_batched(slot.batch_dev, n, blend, s); }));
     HIP_TRY(hipEventRecord(slot.done, s));
     for (int i = 0; i < n; ++i) {
@@ -900,8 +932,8 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
         st = fail(PV_ERR_DEVICE, "event");
     size_t offs[3];
     if (st == PV_OK)
-        st = fill_batch(vols, nullptr, n, (char *)g->slot.stage_host, offs, g->waves, g->blend, g->max_parts,
-                        g->short_stack);
+        st = fill_batch(vols, nullptr, n, (char *)g->slot.stage_host, offs, g->waves, g->blend, g->bounce,
+                        g->max_parts, g->short_stack);
     if (st != PV_OK) {
         free_graph(g);
         return st;
@@ -919,6 +951,7 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
     if (e == hipSuccess) e = hipMemcpyAsync(b.frames_dev, h + g->o_f, sizeof(FrameParams) * n, hipMemcpyHostToDevice, cs);
     if (e == hipSuccess) e = launch_raydirs_batched(b.batch_dev, b.frames_dev, n, g->max_parts, cs);
     if (e == hipSuccess) e = launch_trace_batched(b.batch_dev, n, g->waves, b.frames_dev, g->short_stack, cs);
+    if (e == hipSuccess && g->bounce > 0) e = launch_bounce_batched(b.batch_dev, n, g->bounce, cs);
     if (e == hipSuccess) e = launch_blend_batched(b.batch_dev, n, g->blend, cs);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &graph);
@@ -949,11 +982,11 @@ extern "C" pv_status pv_batch_graph_launch(pv_batch_graph *g, const pv_frame *fr
     // launch must have finished before it is rewritten
     if (g->launched) HIP_TRY(hipEventSynchronize(g->done));
     size_t offs[3];
-    int waves, blend, max_parts;
+    int waves, blend, bounce, max_parts;
     bool short_stack;
-    PV_TRY(fill_batch(g->vols.data(), frames, n, (char *)g->slot.stage_host, offs, waves, blend, max_parts,
+    PV_TRY(fill_batch(g->vols.data(), frames, n, (char *)g->slot.stage_host, offs, waves, blend, bounce, max_parts,
                       short_stack));
-    if (waves != g->waves || blend != g->blend || short_stack != g->short_stack)
+    if (waves != g->waves || blend != g->blend || bounce != g->bounce || short_stack != g->short_stack)
         return fail(PV_ERR_STATE, "a volume of the graph changed scene since the graph was captured");
     hipStream_t s = pick(c, stream);
     HIP_TRY(timed(c, PV_STAGE_BATCHED, s, [&] { return hipGraphLaunch(g->exec, s); }));

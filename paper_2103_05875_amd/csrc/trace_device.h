@@ -283,6 +283,11 @@ __device__ bool any_hit(const DeviceBvh &bvh, const NodeSrc &src, const Ray &r, 
     }
 }
 
+// Hit record of a ray (layout in VolumeParams::hitrec).
+__device__ __forceinline__ int2 hit_record(int slot, bool dyn, float t) {
+    return make_int2(slot < 0 ? -1 : (slot | (dyn ? (int)0x80000000 : 0)), __float_as_int(t));
+}
+
 // Geometry of a hit: unit normal facing the ray origin and the hit point.
 __device__ __forceinline__ void hit_frame(const GpuTri &T, const Ray &ray, float3 o, float t, float3 &nrm,
                                           float3 &xh) {
@@ -369,8 +374,7 @@ __device__ void trace_shade_one(const VolumeParams &vp, const SceneView &sv, con
             }
         }
     } else {
-        split.hitrec[q] = make_int2(best < 0 ? -1 : (best | (arr == sv.dyn.tris ? (int)0x80000000 : 0)),
-                                    __float_as_int(tbest));
+        split.hitrec[q] = hit_record(best, arr == sv.dyn.tris, tbest);
         split.occ[q] = 0u;
         const int lane = threadIdx.x & 63;
         for (int li = 0; li < fp.n_lights; ++li) {
@@ -393,6 +397,7 @@ __device__ void trace_shade_one(const VolumeParams &vp, const SceneView &sv, con
     }
     rays[q] = make_float4(L.x, L.y, L.z, dist);
     if (hits) hits[q] = best_id;
+    if (vp.hitrec) vp.hitrec[q] = hit_record(best, arr == sv.dyn.tris, tbest);
 }
 
 struct TraceGrid {
@@ -525,6 +530,7 @@ __device__ void lane_transition(LaneState &s, const VolumeParams &vp, const Scen
     if (next_light<COUNT>(s, vp, sv, fp, dirs, shadow_rays)) return;
     rays[s.q] = make_float4(s.L.x, s.L.y, s.L.z, s.dist);
     if (hits) hits[s.q] = s.best_id;
+    if (vp.hitrec) vp.hitrec[s.q] = hit_record(s.best, s.best_dyn, s.tbest);
     s.q = -1;
 }
 

@@ -84,6 +84,10 @@ struct VolumeParams {
     float max_distance;
     float sky[3];
     int vis_sharpness;
+    // When set (second bounce on), the trace also writes every ray's hit
+    // record [P][n]: x = leaf-order triangle slot with bit 31 set for the
+    // dynamic BVH, or -1 for a miss; y = hit distance (float bits).
+    int2 *hitrec;
 };
 
 struct SceneView {

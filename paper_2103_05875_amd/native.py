@@ -20,6 +20,7 @@ PV_MAP_FP32 = 0
 PV_MAP_FP16 = 1
 PV_FIRST_FRAME_NO_HISTORY = 1
 PV_KEEP_HITS = 2
+PV_MULTI_BOUNCE = 4
 PV_MAX_LIGHTS = 8
 
 # every symbol include/probestream.h declares
@@ -32,11 +33,11 @@ EXPORTED_SYMBOLS = [
     "pv_pack_delta", "pv_packet_device", "pv_packet_download", "pv_get_masks", "pv_sync",
     "pv_trace_counts", "pv_ctx_set_timing", "pv_ctx_stage_times",
     "pv_client_read_state", "pv_client_set_state", "pv_volume_set_trace_config", "pv_volume_get_trace_config",
-    "pv_batch_graph_create", "pv_batch_graph_launch", "pv_batch_graph_destroy",
+    "pv_batch_graph_create", "pv_batch_graph_launch", "pv_batch_graph_destroy", "pv_probe_query",
 ]
 
 STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched", "shadow", "shade",
-          "pack_finish"]
+          "pack_finish", "bounce"]
 
 
 class NativeError(RuntimeError):
@@ -117,6 +118,7 @@ def lib():
         "pv_get_maps": ([vp, P(vp), P(vp)], i32),
         "pv_get_rays": ([vp, P(vp), P(vp), P(vp)], i32),
         "pv_set_maps": ([vp, vp, vp, ctypes.c_int64], i32),
+        "pv_probe_query": ([vp, vp, vp, ctypes.c_int64, vp, vp], i32),
         "pv_read_maps": ([vp, vp, vp, P(ctypes.c_int64)], i32),
         "pv_client_create": ([vp, u32, P(vp)], i32),
         "pv_client_destroy": ([vp], i32),
@@ -298,7 +300,7 @@ def make_desc(cfg, flags: Optional[int] = None) -> VolumeDesc:
     d.format = PV_MAP_FP16 if cfg.fp16 else PV_MAP_FP32
     d.sky[:] = [float(v) for v in cfg.sky]
     if flags is None:
-        flags = PV_FIRST_FRAME_NO_HISTORY if cfg.first_frame_no_history else 0
+        flags = desc_flags(cfg)
     d.flags = flags
     return d
 
@@ -329,12 +331,17 @@ def client_footprint(cfg) -> int:
     return b.value
 
 
+def desc_flags(cfg, keep_hits: bool = False) -> int:
+    return ((PV_FIRST_FRAME_NO_HISTORY if cfg.first_frame_no_history else 0) |
+            (PV_KEEP_HITS if keep_hits else 0) |
+            (PV_MULTI_BOUNCE if getattr(cfg, "multi_bounce", False) else 0))
+
+
 class Volume:
     def __init__(self, ctx: Context, cfg, keep_hits: bool = False):
         self.ctx = ctx
         self.cfg = cfg
-        flags = (PV_FIRST_FRAME_NO_HISTORY if cfg.first_frame_no_history else 0) | (PV_KEEP_HITS if keep_hits else 0)
-        self._desc = make_desc(cfg, flags)
+        self._desc = make_desc(cfg, desc_flags(cfg, keep_hits))
         h = ctypes.c_void_p()
         _check(lib().pv_create_volume(ctx.h, ctypes.byref(self._desc), ctypes.byref(h)))
         self.h = h
@@ -405,6 +412,20 @@ class Volume:
         vis = np.ascontiguousarray(vis, dt)
         assert irr.shape == (self.P, 3, 10, 10) and vis.shape == (self.P, 2, 18, 18)
         _check(lib().pv_set_maps(self.h, irr.ctypes.data, vis.ctypes.data, int(frame)))
+
+    def probe_query(self, points, normals, stream=None):
+        """Shading query of the current maps at points [m,3] around normals
+        [m,3] (float32 torch tensors on the device, or arrays copied there);
+        returns the [m,3] float32 device tensor (asynchronous on ``stream``)."""
+        import torch
+        pts = torch.as_tensor(points, dtype=torch.float32, device="cuda").contiguous()
+        nrm = torch.as_tensor(normals, dtype=torch.float32, device="cuda").contiguous()
+        if pts.dim() != 2 or pts.shape[1] != 3 or nrm.shape != pts.shape:
+            raise ValueError("points and normals must both be [m, 3]")
+        out = torch.empty_like(pts)
+        _check(lib().pv_probe_query(self.h, pts.data_ptr(), nrm.data_ptr(), pts.shape[0], out.data_ptr(),
+                                    _stream_handle(stream)))
+        return out
 
     def read_rays(self):
         """Ray records [P,n,4] float32 (L rgb, distance), hit ids [P,n]

@@ -50,6 +50,7 @@ def test_null_handles_and_destroy_null(ps):
         assert getattr(L, fn)(None) == 0
     assert L.pv_update_probes(None, None, None) == -1
     assert L.pv_pack_delta(None, 0.0, 0.0, None) == -1
+    assert L.pv_probe_query(None, None, None, 1, None, None) == -1
 
 
 def _fp(ps, cfg, **kw):
@@ -77,6 +78,11 @@ def test_footprint_and_validation(ps):
     assert _fp(ps, cfg, max_distance=0.0)[0] == -1
     assert _fp(ps, cfg, irr_res=6)[0] == -6
     assert _fp(ps, cfg, flags=0x80)[0] == -1
+    # the second bounce keeps an 8-byte hit record per ray
+    assert _fp(ps, cfg, flags=ps.native.PV_MULTI_BOUNCE) == (0, b + P * n * 8)
+    d = ps.native.make_desc(cfg)
+    d.spacing[1] = 0.0
+    assert ps.lib().pv_volume_footprint(ctypes.byref(d), ctypes.byref(ctypes.c_uint64())) == -1
     assert b"65536" in ps.lib().pv_last_error() or True
     c = ctypes.c_uint64(0)
     assert ps.lib().pv_client_footprint(ctypes.byref(ps.native.make_desc(cfg)), ctypes.byref(c)) == 0
