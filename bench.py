@@ -342,7 +342,10 @@ def leg_served(ps, duration_s: float, rate_hz: float = 2000.0, budget_frac: floa
 def leg_encode(ps, torch, frames: int):
     """Encode path: 32x16x32 = 16,384 probes, 256 rays, 200k-triangle field
     with 4 moving occluders and a moving light; each frame updates and packs
-    with tau = 1/1024 for both textures; pack throughput against HBM."""
+    with tau = 1/1024 for both textures, and a receiver (the client side)
+    applies every packet on the device; the receiver's tiles equal the
+    server's record of what the client holds at every 20th frame. Pack
+    throughput against HBM."""
     import synth
     cfg = synth.config("encode")
     scene_syn = synth.box_field(200_000, seed=40, n_moving=4)
@@ -351,11 +354,12 @@ def leg_encode(ps, torch, frames: int):
     vol = ps.Volume(ctx, cfg)
     vol.set_scene(sc)
     cl = ps.Client(vol, 0)
+    rx = ps.Receiver(ctx, cfg.n_probes)   # the client side: applies each packet on the device
     path = synth.light_path(12, frames)
     stream = torch.cuda.current_stream()
     ctx.set_timing(True)
     ctx.stage_times()
-    sent_bytes, changed = 0, []
+    sent_bytes, changed, ok = 0, [], True
     for f in range(frames):
         sc.set_dynamic(synth.moving_occluders(40, f, 4), stream=stream)
         l = scene_syn.lights.copy()
@@ -364,6 +368,13 @@ def leg_encode(ps, torch, frames: int):
         cl.pack_delta(1.0 / 1024, 1.0 / 1024, stream=stream)
         pkt = cl.packet_download(stream=stream)
         sent_bytes += len(pkt)
+        rx.apply(pkt, stream=stream)
+        if f % 20 == 19 or f == frames - 1:
+            ok &= rx.status() == (0, f)
+            ri, rv, _ = cl.read_state()
+            gi, gv = rx.read_maps()
+            ok &= bool(np.array_equal(gi[:, :, 1:-1, 1:-1].reshape(cfg.n_probes, 3, -1), ri))
+            ok &= bool(np.array_equal(gv[:, :, 1:-1, 1:-1].reshape(cfg.n_probes, 2, -1), rv))
         mi, mv = cl.read_masks()
         changed.append((int(mi.sum()), int(mv.sum())))
     st = ctx.stage_times()
@@ -375,14 +386,15 @@ def leg_encode(ps, torch, frames: int):
     pack_bytes = P * 1408 * 2 + (ki * 384 + kv * 1024) * 2 + P * 2
     upd_ms = (st["raydirs"][0] + st["trace"][0] + st["blend"][0]) / frames
     per_kernel = {k: st[k][0] / max(st[k][1], 1) for k in ("pack_mask", "pack_scan", "pack_compact", "pack_finish", "trace", "blend")}
-    out = {"probes": P, "frames": frames, "mean_changed_irr": ki,
+    out = {"probes": P, "frames": frames, "round_trip_bit_exact": bool(ok),
+           "client_unpack_ms": st["unpack"][0] / frames, "mean_changed_irr": ki,
            "kernel_ms": per_kernel,
            "mean_changed_vis": kv, "packet_bytes_per_frame": sent_bytes / frames,
            "Mbps_at_10Hz": sent_bytes / frames * 8 * 10 / 1e6,
            "update_ms": upd_ms, "probe_rays_per_s": P * cfg.rays_per_probe / (upd_ms / 1e3),
            "pack_ms": pack_ms, "pack_hbm_GBps": pack_bytes / (pack_ms / 1e3) / 1e9,
            "pack_hbm_frac": pack_bytes / (pack_ms / 1e3) / PEAK_HBM}
-    for h in (cl, vol, sc, ctx):
+    for h in (rx, cl, vol, sc, ctx):
         h.close()
     return out
 

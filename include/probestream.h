@@ -281,6 +281,38 @@ pv_status pv_get_masks(pv_client *client, void **mask_irr_dev, void **mask_vis_d
 pv_status pv_sync(void *stream);
 
 /*
+ * Client side (Sec. 3.4: the client keeps its textures, applies index-based
+ * probe updates and rebuilds the guard bands the packets leave out). A
+ * receiver holds FP16 tiles in the layout of pv_volume_desc (irradiance
+ * [P][3][10][10], visibility [P][2][18][18], guard bands included), all-zero
+ * bits at creation -- the state of a new pv_client's reference.
+ */
+typedef struct pv_receiver pv_receiver;
+pv_status pv_receiver_create(pv_ctx *ctx, int n_probes, pv_receiver **out);
+pv_status pv_receiver_destroy(pv_receiver *rcv);
+/*
+ * Apply one packet (host memory, the pv_pack_delta layout) asynchronously
+ * on 'stream': copied through pinned staging, the index decoded, the
+ * payload checksum recomputed, and -- only when the index is valid (every
+ * probe in range, strictly increasing) and the checksum matches -- each
+ * sent probe's byte planes XORed into its interior texels, written with
+ * their guard copies. A packet that fails those checks leaves the tiles
+ * unchanged. Header errors are returned at once: PV_ERR_ARG (magic, probe
+ * count, size), PV_ERR_UNSUPPORTED (version). Consecutive applies are
+ * ordered on the device whatever streams they use.
+ */
+pv_status pv_receiver_apply(pv_receiver *rcv, const void *packet, uint64_t bytes, void *stream);
+/* Waits for the last apply: *result 0 = applied, -2 = checksum mismatch,
+ * -4 = invalid index (both: tiles unchanged); *seq (may be NULL) = sequence
+ * number of the last packet known to be applied. PV_ERR_STATE before the
+ * first apply. */
+pv_status pv_receiver_status(pv_receiver *rcv, int *result, uint32_t *seq);
+/* Borrowed device pointers to the tiles (uint16 binary16 bit patterns). */
+pv_status pv_receiver_get_maps(pv_receiver *rcv, void **irr_dev, void **vis_dev);
+/* Copy the tiles to host memory; synchronous. */
+pv_status pv_receiver_read_maps(pv_receiver *rcv, void *irr_host, void *vis_host);
+
+/*
  * Launch shape of the trace kernel (a tuning choice; every shape computes
  * identical results): probes per wavefront packet as a brick
  * brick[0] x brick[1] x brick[2] = 64 of one ray direction (this also fixes
@@ -321,7 +353,8 @@ typedef enum {
     PV_STAGE_SHADE = 8,
     PV_STAGE_PACK_FINISH = 9,
     PV_STAGE_BOUNCE = 10,
-    PV_STAGE_COUNT = 11
+    PV_STAGE_UNPACK = 11,
+    PV_STAGE_COUNT = 12
 } pv_stage;
 
 /* When enabled, every kernel launch of the context is bracketed by a pair

@@ -96,4 +96,22 @@ hipError_t launch_pack_finish(const PackBuffers &b, int P, uint32_t client, uint
 constexpr int kPackTile = 16;  // probes per pack block
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 
+// Client-side unpack (receive.hip). The packet's header has been checked on
+// the host; the index and the checksum are checked on the device before any
+// texel is written.
+struct RxStatus {
+    uint32_t sum;      // payload checksum accumulated on the device
+    int bad_index;     // 1: an index entry is out of range or not increasing
+};
+struct RxBuffers {
+    const uint8_t *pkt;   // device copy of the packet
+    int P, K_irr, K_vis;
+    uint32_t checksum;    // from the header
+    long long payload_words;
+    uint16_t *irr, *vis;  // the client's tiles (with guard bands)
+    int *idx;             // [K_irr + K_vis] decoded probe numbers
+    RxStatus *status;
+};
+hipError_t launch_receive(const RxBuffers &b, hipStream_t s);
+
 }  // namespace pv

@@ -1,6 +1,6 @@
 // C ABI of the probe-volume library: handles, validation, device memory,
-// launch sequencing. Kernels live in trace.hip, blend.hip, batched.hip and
-// pack.hip, the BVH builder in bvh.cpp.
+// launch sequencing. Kernels live in trace.hip, blend.hip, batched.hip,
+// bounce.hip, pack.hip and receive.hip, the BVH builder in bvh.cpp.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -11,6 +11,7 @@
 
 #include "internal.h"
 #include "blend_layout.h"
+#include "packet_format.h"
 
 using namespace pv;
 
@@ -141,10 +142,7 @@ static hipStream_t pick(pv_ctx *, void *s) { return (hipStream_t)s; }
 
 static uint64_t irr_bytes(int P, size_t elem) { return (uint64_t)P * 3 * 100 * elem; }
 static uint64_t vis_bytes(int P, size_t elem) { return (uint64_t)P * 2 * 324 * elem; }
-static uint64_t packet_capacity(int P) {
-    uint64_t idx = ((2ull * 2 * P + 15) / 16) * 16;
-    return 32 + idx + (uint64_t)P * (6 * 64 + 4 * 256);
-}
+static uint64_t packet_capacity(int P) { return packet_bytes((uint64_t)P, (uint64_t)P); }
 
 template <typename T>
 static pv_status dev_alloc(T **p, size_t bytes, const char *what) {
@@ -1152,10 +1150,9 @@ extern "C" pv_status pv_packet_download(pv_client *c, void *host, uint64_t cap, 
     hipStream_t s = pick(c->vol->ctx, stream);
     HIP_TRY(hipMemcpyAsync(c->hdr_host, c->packet, 32, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    const uint32_t K_irr = c->hdr_host[5], K_vis = c->hdr_host[6];
-    if (c->hdr_host[0] != 0x4B505650u) return fail(PV_ERR_STATE, "no packet has been built");
-    const uint64_t idx = ((2ull * (K_irr + K_vis) + 15) / 16) * 16;
-    const uint64_t total = 32 + idx + (uint64_t)K_irr * 384 + (uint64_t)K_vis * 1024;
+    const uint32_t K_irr = c->hdr_host[kHdrKIrr], K_vis = c->hdr_host[kHdrKVis];
+    if (c->hdr_host[kHdrMagic] != kPacketMagic) return fail(PV_ERR_STATE, "no packet has been built");
+    const uint64_t total = packet_bytes(K_irr, K_vis);
     *bytes = total;
     if (!host || cap < total) return fail(PV_ERR_CAPACITY, "packet needs " + std::to_string(total) + " bytes");
     std::memcpy(host, c->hdr_host, 32);
@@ -1170,3 +1167,145 @@ extern "C" pv_status pv_sync(void *stream) {
     return PV_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// receiver (client-side unpack)
+// ---------------------------------------------------------------------------
+struct pv_receiver {
+    pv_ctx *ctx = nullptr;
+    int P = 0;
+    uint16_t *irr = nullptr, *vis = nullptr;  // tiles with guard bands
+    int *idx = nullptr;
+    RxStatus *status = nullptr;
+    uint8_t *pkt = nullptr;                   // device copy of the packet being applied
+    uint8_t *stage = nullptr;                 // pinned staging of the host packet
+    uint64_t cap = 0;
+    hipEvent_t copied = nullptr, done = nullptr;
+    bool used = false;
+    uint32_t checksum = 0, seq = 0, last_seq = 0;
+    bool pending = false;
+};
+
+static void free_receiver(pv_receiver *r) {
+    hipFree(r->irr);
+    hipFree(r->vis);
+    hipFree(r->idx);
+    hipFree(r->status);
+    hipFree(r->pkt);
+    if (r->stage) hipHostFree(r->stage);
+    if (r->copied) hipEventDestroy(r->copied);
+    if (r->done) hipEventDestroy(r->done);
+    delete r;
+}
+
+extern "C" pv_status pv_receiver_create(pv_ctx *ctx, int n_probes, pv_receiver **out) {
+    if (!ctx || !out) return fail(PV_ERR_ARG, "NULL argument");
+    if (n_probes < 1 || n_probes > PV_MAX_PROBES) return fail(PV_ERR_ARG, "n_probes must be in [1, 65536]");
+    HIP_TRY(hipSetDevice(ctx->device));
+    pv_receiver *r = new pv_receiver();
+    r->ctx = ctx;
+    r->P = n_probes;
+    r->cap = packet_capacity(n_probes);
+    pv_status st = dev_alloc(&r->irr, irr_bytes(r->P, 2), "receiver irradiance tiles");
+    if (st == PV_OK) st = dev_alloc(&r->vis, vis_bytes(r->P, 2), "receiver visibility tiles");
+    if (st == PV_OK) st = dev_alloc(&r->idx, (size_t)2 * r->P * sizeof(int), "receiver index");
+    if (st == PV_OK) st = dev_alloc(&r->status, sizeof(RxStatus), "receiver status");
+    if (st == PV_OK) st = dev_alloc(&r->pkt, r->cap, "receiver packet buffer");
+    if (st == PV_OK && hipHostMalloc((void **)&r->stage, r->cap) != hipSuccess)
+        st = fail(PV_ERR_OOM, "pinned packet staging");
+    if (st == PV_OK && (hipEventCreateWithFlags(&r->copied, hipEventDisableTiming) != hipSuccess ||
+                        hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess))
+        st = fail(PV_ERR_DEVICE, "event");
+    if (st == PV_OK && launch_zero(r->irr, irr_bytes(r->P, 2), ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "zero fill");
+    if (st == PV_OK && launch_zero(r->vis, vis_bytes(r->P, 2), ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "zero fill");
+    if (st == PV_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "sync after zero fill");
+    if (st != PV_OK) {
+        free_receiver(r);
+        return st;
+    }
+    *out = r;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_receiver_destroy(pv_receiver *r) {
+    if (!r) return PV_OK;
+    hipSetDevice(r->ctx->device);
+    if (r->used) hipEventSynchronize(r->done);
+    free_receiver(r);
+    return PV_OK;
+}
+
+static uint32_t get_u32(const uint8_t *p) {
+    return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+
+extern "C" pv_status pv_receiver_apply(pv_receiver *r, const void *packet, uint64_t bytes, void *stream) {
+    if (!r || !packet) return fail(PV_ERR_ARG, "NULL argument");
+    const uint8_t *h = (const uint8_t *)packet;
+    if (bytes < (uint64_t)kPacketHeader) return fail(PV_ERR_ARG, "packet shorter than its header");
+    if (get_u32(h + 4 * kHdrMagic) != kPacketMagic) return fail(PV_ERR_ARG, "not a probe packet (magic)");
+    if (get_u32(h + 4 * kHdrVersion) != kPacketVersion) return fail(PV_ERR_UNSUPPORTED, "packet version");
+    if (get_u32(h + 4 * kHdrProbes) != (uint32_t)r->P) return fail(PV_ERR_ARG, "packet is for another probe count");
+    const uint32_t K_irr = get_u32(h + 4 * kHdrKIrr), K_vis = get_u32(h + 4 * kHdrKVis);
+    if (K_irr > (uint32_t)r->P || K_vis > (uint32_t)r->P) return fail(PV_ERR_ARG, "more sent probes than probes");
+    if (bytes != packet_bytes(K_irr, K_vis)) return fail(PV_ERR_ARG, "packet size does not match its header");
+    HIP_TRY(hipSetDevice(r->ctx->device));
+    hipStream_t s = pick(r->ctx, stream);
+    // the staging buffer is free once the previous copy has run; the device
+    // packet buffer once the previous unpack has (ordered on this stream)
+    if (r->used) {
+        HIP_TRY(hipEventSynchronize(r->copied));
+        HIP_TRY(hipStreamWaitEvent(s, r->done, 0));
+    }
+    std::memcpy(r->stage, packet, bytes);
+    HIP_TRY(hipMemcpyAsync(r->pkt, r->stage, bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(r->copied, s));
+    RxBuffers b;
+    b.pkt = r->pkt;
+    b.P = r->P;
+    b.K_irr = (int)K_irr;
+    b.K_vis = (int)K_vis;
+    b.checksum = get_u32(h + 4 * kHdrChecksum);
+    b.payload_words = (long long)(bytes - kPacketHeader) / 4;
+    b.irr = r->irr;
+    b.vis = r->vis;
+    b.idx = r->idx;
+    b.status = r->status;
+    HIP_TRY(timed(r->ctx, PV_STAGE_UNPACK, s, [&] { return launch_receive(b, s); }));
+    HIP_TRY(hipEventRecord(r->done, s));
+    r->used = true;
+    r->checksum = b.checksum;
+    r->seq = get_u32(h + 4 * kHdrSeq);
+    r->pending = true;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_receiver_status(pv_receiver *r, int *result, uint32_t *seq) {
+    if (!r || !result) return fail(PV_ERR_ARG, "NULL argument");
+    if (!r->used) return fail(PV_ERR_STATE, "no packet has been applied");
+    HIP_TRY(hipSetDevice(r->ctx->device));
+    HIP_TRY(hipEventSynchronize(r->done));
+    RxStatus st;
+    HIP_TRY(hipMemcpy(&st, r->status, sizeof st, hipMemcpyDeviceToHost));
+    *result = st.bad_index ? -4 : (st.sum != r->checksum ? -2 : 0);
+    if (r->pending && *result == 0) r->last_seq = r->seq;
+    r->pending = false;
+    if (seq) *seq = r->last_seq;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_receiver_get_maps(pv_receiver *r, void **irr, void **vis) {
+    if (!r || !irr || !vis) return fail(PV_ERR_ARG, "NULL argument");
+    *irr = r->irr;
+    *vis = r->vis;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_receiver_read_maps(pv_receiver *r, void *irr, void *vis) {
+    if (!r || !irr || !vis) return fail(PV_ERR_ARG, "NULL argument");
+    HIP_TRY(hipSetDevice(r->ctx->device));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(irr, r->irr, irr_bytes(r->P, 2), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(vis, r->vis, vis_bytes(r->P, 2), hipMemcpyDeviceToHost));
+    return PV_OK;
+}

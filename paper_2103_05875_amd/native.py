@@ -34,10 +34,12 @@ EXPORTED_SYMBOLS = [
     "pv_trace_counts", "pv_ctx_set_timing", "pv_ctx_stage_times",
     "pv_client_read_state", "pv_client_set_state", "pv_volume_set_trace_config", "pv_volume_get_trace_config",
     "pv_batch_graph_create", "pv_batch_graph_launch", "pv_batch_graph_destroy", "pv_probe_query",
+    "pv_receiver_create", "pv_receiver_destroy", "pv_receiver_apply", "pv_receiver_status",
+    "pv_receiver_get_maps", "pv_receiver_read_maps",
 ]
 
 STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched", "shadow", "shade",
-          "pack_finish", "bounce"]
+          "pack_finish", "bounce", "unpack"]
 
 
 class NativeError(RuntimeError):
@@ -119,6 +121,12 @@ def lib():
         "pv_get_rays": ([vp, P(vp), P(vp), P(vp)], i32),
         "pv_set_maps": ([vp, vp, vp, ctypes.c_int64], i32),
         "pv_probe_query": ([vp, vp, vp, ctypes.c_int64, vp, vp], i32),
+        "pv_receiver_create": ([vp, i32, P(vp)], i32),
+        "pv_receiver_destroy": ([vp], i32),
+        "pv_receiver_apply": ([vp, vp, u64, vp], i32),
+        "pv_receiver_status": ([vp, P(i32), P(u32)], i32),
+        "pv_receiver_get_maps": ([vp, P(vp), P(vp)], i32),
+        "pv_receiver_read_maps": ([vp, vp, vp], i32),
         "pv_read_maps": ([vp, vp, vp, P(ctypes.c_int64)], i32),
         "pv_client_create": ([vp, u32, P(vp)], i32),
         "pv_client_destroy": ([vp], i32),
@@ -544,6 +552,45 @@ class Client:
     def close(self):
         if getattr(self, "h", None):
             lib().pv_client_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Receiver:
+    """Client-side state of one volume: FP16 tiles (guard bands included)
+    updated from delta packets on the device."""
+
+    def __init__(self, ctx: Context, n_probes: int):
+        self.ctx = ctx
+        self.P = int(n_probes)
+        h = ctypes.c_void_p()
+        _check(lib().pv_receiver_create(ctx.h, self.P, ctypes.byref(h)))
+        self.h = h
+
+    def apply(self, packet: bytes, stream=None):
+        buf = np.frombuffer(packet, np.uint8)
+        _check(lib().pv_receiver_apply(self.h, buf.ctypes.data, buf.size, _stream_handle(stream)))
+
+    def status(self):
+        """(result, seq): 0 applied, -2 checksum mismatch, -4 invalid index."""
+        rc, seq = ctypes.c_int(0), ctypes.c_uint32(0)
+        _check(lib().pv_receiver_status(self.h, ctypes.byref(rc), ctypes.byref(seq)))
+        return rc.value, seq.value
+
+    def read_maps(self):
+        irr = np.zeros((self.P, 3, 10, 10), np.uint16)
+        vis = np.zeros((self.P, 2, 18, 18), np.uint16)
+        _check(lib().pv_receiver_read_maps(self.h, irr.ctypes.data, vis.ctypes.data))
+        return irr, vis
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pv_receiver_destroy(self.h)
             self.h = None
 
     def __del__(self):
