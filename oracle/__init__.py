@@ -86,6 +86,11 @@ def lib():
                                      ctypes.c_double, _D, _D, _D, _D, _D, _D, _I32, _D, _I32, _I32,
                                      ctypes.c_int, ctypes.c_int, ctypes.POINTER(_D), ctypes.c_double]
         L.or_probe_lookup.argtypes = [_D, ctypes.c_int, ctypes.c_int, _D, _D]
+        L.or_yuv_dims.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+        L.or_irr_code.argtypes = [ctypes.c_float, ctypes.c_float]
+        L.or_irr_code.restype = ctypes.c_uint16
+        L.or_yuv_encode.argtypes = [ctypes.c_int, ctypes.c_int, _D, _U16, ctypes.c_float, _U16, _U8]
+        L.or_yuv_decode.argtypes = [ctypes.c_int, ctypes.c_int, _U16, _U8, ctypes.POINTER(ctypes.c_uint32), _U16]
         L.or_probe_query.argtypes = [ctypes.POINTER(_Volume), _D, _D, _D, _D, _D]
         L.or_closest_hits.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D, _I32, _D, _I32, ctypes.c_double]
         L.or_closest_hits_brute.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D, _I32, _D]
@@ -289,6 +294,47 @@ def probe_query(cfg, irr, vis, x, n) -> np.ndarray:
     lib().or_probe_query(ctypes.byref(v), _p(_c(irr, np.float64), _D), _p(_c(vis, np.float64), _D),
                          _p(_c(x, np.float64), _D), _p(_c(n, np.float64), _D), _p(out, _D))
     return out
+
+
+def irr_scale_factor(scale: float) -> np.float32:
+    """k of the irradiance code: the FP32 value nearest 1023 / scale."""
+    return np.float32(1023.0 / float(scale))
+
+
+def yuv_dims(P: int, C: int):
+    """(irradiance plane width, height, visibility plane width x', height)."""
+    out = (ctypes.c_int64 * 4)()
+    lib().or_yuv_dims(P, C, out)
+    return tuple(int(v) for v in out)
+
+
+def irr_code(v: float, scale: float) -> int:
+    return int(lib().or_irr_code(float(np.float32(v)), float(irr_scale_factor(scale))))
+
+
+def yuv_encode(irr_tiles, vis_bits, scale: float, C: int):
+    """Codec surfaces of a volume: irradiance YUV444 planes [3, H, W] uint16
+    and visibility planes [3, Hv, x'] uint8."""
+    irr = _c(irr_tiles, np.float64)
+    vis = _c(vis_bits, np.uint16)
+    P = irr.shape[0]
+    W, H, Wv, Hv = yuv_dims(P, C)
+    ip = np.zeros((3, H, W), np.uint16)
+    vp = np.zeros((3, Hv, Wv), np.uint8)
+    lib().or_yuv_encode(P, C, _p(irr, _D), _p(vis, _U16), float(irr_scale_factor(scale)), _p(ip, _U16), _p(vp, _U8))
+    return ip, vp
+
+
+def yuv_decode(irr_planes, vis_planes, P: int, C: int):
+    """Inverse of yuv_encode: A2RGB10 codes [P, 64] uint32 and visibility
+    binary16 interiors [P, 2, 256] uint16."""
+    ip = _c(irr_planes, np.uint16)
+    vp = _c(vis_planes, np.uint8)
+    codes = np.zeros((P, 64), np.uint32)
+    vis = np.zeros((P, 2, 256), np.uint16)
+    lib().or_yuv_decode(P, C, _p(ip, _U16), _p(vp, _U8), codes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                        _p(vis, _U16))
+    return codes, vis
 
 
 def border(tiles: np.ndarray) -> np.ndarray:

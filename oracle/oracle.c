@@ -1253,3 +1253,104 @@ OR_API int or_max_threads(void)
     return 1;
 #endif
 }
+
+/* ======================================================================== */
+/* Codec surfaces (Sec. 3.3, memory layout figure)                           */
+/* ======================================================================== */
+/*
+ * Probe p occupies atlas tile (p % C, p / C); unused tiles of the last row
+ * are zero. Guard bands are not part of the surfaces (Sec. 3.4 repacking).
+ *
+ * Irradiance: each channel's normalised value becomes a 10-bit unsigned
+ * code, shifted into the top 10 bits of a 16-bit sample (low 6 bits zero);
+ * R, G, B are the Y, U, V planes of a YUV444 surface, each [8 rows][8 C]
+ * per atlas row of tiles. The code is decided in FP32: the FP32 product of
+ * the value and k (the FP32 value nearest 1023 / scale), rounded to the
+ * nearest integer (ties to even), clamped to [0, 1023].
+ *
+ * Visibility: a row of x RG16F texels is 4x bytes (per texel mean lo, mean
+ * hi, mean^2 lo, mean^2 hi); byte m goes to YUV sample m / 3, channel m % 3
+ * (Y, U, V), so three texels fill four YUV samples (YUVY, UVYU, VYUV) and a
+ * plane row holds ceil(4x / 3) samples (x = 16 C), missing bytes zero.
+ */
+static int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+OR_API void or_yuv_dims(int P, int C, int64_t out[4])
+{
+    const int rows = ceil_div(P, C);
+    out[0] = 8 * (int64_t)C;                 /* irradiance plane width */
+    out[1] = 8 * (int64_t)rows;              /* irradiance plane height */
+    out[2] = ceil_div(4 * 16 * C, 3);        /* visibility plane width x' */
+    out[3] = 16 * (int64_t)rows;             /* visibility plane height */
+}
+
+OR_API uint16_t or_irr_code(float v, float k)
+{
+    float x = v * k;
+    x = rintf(x);
+    if (!(x > 0.0f)) return 0;
+    if (x > 1023.0f) return 1023;
+    return (uint16_t)x;
+}
+
+/* irr: FP16-valued tiles as doubles [P][3][10][10]; vis: binary16 bit
+ * patterns [P][2][18][18]. */
+OR_API void or_yuv_encode(int P, int C, const double *irr, const uint16_t *vis, float k, uint16_t *irr_planes,
+                          uint8_t *vis_planes)
+{
+    int64_t d[4];
+    or_yuv_dims(P, C, d);
+    const int64_t W = d[0], H = d[1], Wv = d[2], Hv = d[3];
+    memset(irr_planes, 0, sizeof(uint16_t) * 3 * W * H);
+    memset(vis_planes, 0, 3 * Wv * Hv);
+    for (int p = 0; p < P; ++p) {
+        const int tx = p % C, ty = p / C;
+        for (int c = 0; c < 3; ++c)
+            for (int j = 0; j < 8; ++j)
+                for (int i = 0; i < 8; ++i) {
+                    const float v = (float)irr[(((int64_t)p * 3 + c) * 10 + j + 1) * 10 + i + 1];
+                    irr_planes[((int64_t)c * H + ty * 8 + j) * W + tx * 8 + i] = (uint16_t)(or_irr_code(v, k) << 6);
+                }
+        for (int j = 0; j < 16; ++j)
+            for (int i = 0; i < 16; ++i) {
+                const int64_t row = (int64_t)ty * 16 + j, col = (int64_t)tx * 16 + i;
+                for (int b = 0; b < 4; ++b) {
+                    const uint16_t h = vis[(((int64_t)p * 2 + b / 2) * 18 + j + 1) * 18 + i + 1];
+                    const uint8_t byte = (uint8_t)(b % 2 ? h >> 8 : h & 0xFF);
+                    const int64_t m = 4 * col + b;
+                    vis_planes[((m % 3) * Hv + row) * Wv + m / 3] = byte;
+                }
+            }
+    }
+}
+
+/* Inverse: irr_codes [P][64] = R | G << 10 | B << 20 (A2RGB10, alpha 0),
+ * vis_bits [P][2][256] binary16 interiors. */
+OR_API void or_yuv_decode(int P, int C, const uint16_t *irr_planes, const uint8_t *vis_planes, uint32_t *irr_codes,
+                          uint16_t *vis_bits)
+{
+    int64_t d[4];
+    or_yuv_dims(P, C, d);
+    const int64_t W = d[0], H = d[1], Wv = d[2], Hv = d[3];
+    for (int p = 0; p < P; ++p) {
+        const int tx = p % C, ty = p / C;
+        for (int t = 0; t < 64; ++t) {
+            const int i = t % 8, j = t / 8;
+            uint32_t code = 0;
+            for (int c = 0; c < 3; ++c)
+                code |= (uint32_t)(irr_planes[((int64_t)c * H + ty * 8 + j) * W + tx * 8 + i] >> 6) << (10 * c);
+            irr_codes[(int64_t)p * 64 + t] = code;
+        }
+        for (int t = 0; t < 256; ++t) {
+            const int i = t % 16, j = t / 16;
+            const int64_t row = (int64_t)ty * 16 + j, col = (int64_t)tx * 16 + i;
+            uint8_t by[4];
+            for (int b = 0; b < 4; ++b) {
+                const int64_t m = 4 * col + b;
+                by[b] = vis_planes[((m % 3) * Hv + row) * Wv + m / 3];
+            }
+            vis_bits[((int64_t)p * 2 + 0) * 256 + t] = (uint16_t)(by[0] | (by[1] << 8));
+            vis_bits[((int64_t)p * 2 + 1) * 256 + t] = (uint16_t)(by[2] | (by[3] << 8));
+        }
+    }
+}

@@ -812,3 +812,66 @@ def test_packet_sizes_follow_the_layout(O):
     for Ki, Kv in ((0, 0), (1, 0), (0, 1), (7, 3), (2048, 2048)):
         idx = ((ib * (Ki + Kv) + 15) // 16) * 16
         assert O.packet_bytes(Ki, Kv) == 32 + idx + Ki * 8 * 8 * 3 * 2 + Kv * 16 * 16 * 2 * 2
+
+
+# ---------------------------------------------------------------- codec surfaces (Sec. 3.3)
+def test_visibility_interleave_is_yuvy_uvyu_vyuv(O):
+    """Three RG16F texels (12 bytes) fill four YUV samples in the order the
+    paper gives: YUVY, UVYU, VYUV; a 16-texel row (64 bytes) needs
+    ceil(4 * 16 / 3) = 22 samples, the last holding one byte."""
+    P, C = 1, 1
+    vis = np.zeros((P, 2, 18, 18), np.uint16)
+    b = np.arange(1, 65, dtype=np.uint16)           # bytes 1..64 of the first row, in texel order
+    for i in range(16):
+        vis[0, 0, 1, i + 1] = b[4 * i] | (b[4 * i + 1] << 8)       # mean: lo, hi
+        vis[0, 1, 1, i + 1] = b[4 * i + 2] | (b[4 * i + 3] << 8)   # mean^2: lo, hi
+    irr = np.zeros((P, 3, 10, 10))
+    ip, vp = O.yuv_encode(irr, vis, 1.0, C)
+    assert O.yuv_dims(P, C) == (8, 8, 22, 16) and vp.shape == (3, 16, 22)
+    Y, U, V = vp[0, 0], vp[1, 0], vp[2, 0]
+    # texel 0 -> Y0 U0 V0 Y1, texel 1 -> U1 V1 Y2 U2, texel 2 -> V2 Y3 U3 V3
+    assert [Y[0], U[0], V[0], Y[1]] == [1, 2, 3, 4]
+    assert [U[1], V[1], Y[2], U[2]] == [5, 6, 7, 8]
+    assert [V[2], Y[3], U[3], V[3]] == [9, 10, 11, 12]
+    assert (Y[21], U[21], V[21]) == (64, 0, 0)
+    assert not vp[:, 1:].any()                       # the other rows of the first probe are zero here
+
+
+def test_irradiance_code_examples(O):
+    """10-bit codes of normalised values, shifted into the top of 16 bits:
+    ties go to even, values clamp to [0, 1023]."""
+    assert O.irr_code(0.5, 1.0) == 512                # 511.5 -> 512
+    assert O.irr_code(0.25, 1.0) == 256               # 255.75
+    assert O.irr_code(510.5, 1023.0) == 510           # k = 1: an exact tie, to even
+    assert O.irr_code(511.5, 1023.0) == 512
+    assert O.irr_code(2.0, 1.0) == 1023 and O.irr_code(-1.0, 1.0) == 0 and O.irr_code(0.0, 1.0) == 0
+    irr = np.zeros((1, 3, 10, 10))
+    irr[0, 0, 1, 1], irr[0, 1, 1, 1], irr[0, 2, 1, 1] = 1.0, 0.5, 0.0
+    ip, _ = O.yuv_encode(irr, np.zeros((1, 2, 18, 18), np.uint16), 1.0, 1)
+    assert (ip[0, 0, 0], ip[1, 0, 0], ip[2, 0, 0]) == (0xFFC0, 512 << 6, 0)
+
+
+@pytest.mark.parametrize("P, C", [(1, 1), (7, 3), (48, 16), (100, 7)])
+def test_codec_surfaces_layout_and_round_trip(O, P, C):
+    """Probe p sits in atlas tile (p % C, p / C); decoding the surfaces gives
+    back every visibility bit pattern and the A2RGB10 codes of every texel."""
+    rng = np.random.default_rng(P * 31 + C)
+    irr16, vis = synth.random_fp16_maps(P, 8, 16, seed=P + C, scale=3.0)
+    irr = irr16.view(np.float16).astype(np.float64)
+    scale = 2.5
+    ip, vp = O.yuv_encode(irr, vis, scale, C)
+    W, H, Wv, Hv = O.yuv_dims(P, C)
+    assert (W, H) == (8 * C, 8 * -(-P // C)) and (Wv, Hv) == (-(-64 * C // 3), 16 * -(-P // C))
+    assert not (ip & 0x3F).any()                      # low 6 bits of every sample are zero
+    codes, vback = O.yuv_decode(ip, vp, P, C)
+    assert np.array_equal(vback, vis[:, :, 1:-1, 1:-1].reshape(P, 2, 256))
+    k = np.float32(1023.0 / scale)
+    want = np.clip(np.rint(irr[:, :, 1:-1, 1:-1].astype(np.float32) * k), 0, 1023).astype(np.uint32)
+    want = want.reshape(P, 3, 64)
+    assert np.array_equal(codes, want[:, 0] | (want[:, 1] << 10) | (want[:, 2] << 20))
+    p = int(rng.integers(P))
+    tx, ty = p % C, p // C
+    assert np.array_equal(ip[1, ty * 8:(ty + 1) * 8, tx * 8:(tx + 1) * 8] >> 6, want[p, 1].reshape(8, 8))
+    # tiles past the last probe are zero
+    if P % C:
+        assert not ip[:, -8:, (P % C) * 8:].any()
