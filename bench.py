@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--legs", default="batched,served,served_below_capacity,served_tight_memory,encode,multi_bounce",
+    ap.add_argument("--legs", default="batched,served,served_below_capacity,served_tight_memory,encode,multi_bounce,codec",
                     help="extra workloads reported in the same line (comma list, or 'none')")
     ap.add_argument("--served-seconds", type=float, default=1.0)
     ap.add_argument("--served-low-rate", type=float, default=300.0,
@@ -399,6 +399,49 @@ def leg_encode(ps, torch, frames: int):
     return out
 
 
+def leg_codec(ps, torch, reps: int = 20):
+    """Codec surfaces (Sec. 3.3) of the encode-size volume (16,384 probes,
+    FP16 maps, 128 tiles per atlas row): encode and decode times and their
+    algorithmic bytes (interiors read, planes written; planes read, codes and
+    bit patterns written) against HBM."""
+    import synth
+    P, C = 16384, 128
+    irr, vis = synth.random_fp16_maps(P, 8, 16, seed=60, scale=3.0)
+    cfg = synth.config("encode")
+    ctx = ps.Context(0)
+    vol = ps.Volume(ctx, cfg)
+    vol.set_maps(irr, vis, 0)
+    stream = torch.cuda.current_stream()
+    w, h, wv, hv = ps.yuv_dims(P, C)
+    ip, vp = vol.encode_yuv(2.0, C, stream=stream)
+    codes, vb = ps.decode_yuv(ctx, P, C, ip, vp, stream=stream)
+    torch.cuda.synchronize()
+    ok = bool(np.array_equal(vb.cpu().numpy().view(np.uint16), vis[:, :, 1:-1, 1:-1].reshape(P, 2, 256)))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    for _ in range(reps):
+        vol.encode_yuv(2.0, C, stream=stream)
+    ev[1].record(stream)
+    for _ in range(reps):
+        ps.decode_yuv(ctx, P, C, ip, vp, stream=stream)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    enc_ms = ev[0].elapsed_time(ev[1]) / reps
+    dec_ms = ev[1].elapsed_time(ev[2]) / reps
+    interiors = P * (192 + 512) * 2
+    planes = 3 * w * h * 2 + 3 * wv * hv
+    dec_out = P * 64 * 4 + P * 512 * 2
+    out = {"probes": P, "tiles_per_row": C, "irr_planes": [3, h, w], "vis_planes": [3, hv, wv],
+           "visibility_round_trip_bit_exact": ok,
+           "encode_ms": enc_ms, "encode_GBps": (interiors + planes) / (enc_ms / 1e3) / 1e9,
+           "decode_ms": dec_ms, "decode_GBps": (planes + dec_out) / (dec_ms / 1e3) / 1e9}
+    out["encode_hbm_frac"] = out["encode_GBps"] * 1e9 / PEAK_HBM
+    out["decode_hbm_frac"] = out["decode_GBps"] * 1e9 / PEAK_HBM
+    for hnd in (vol, ctx):
+        hnd.close()
+    return out
+
+
 def leg_multi_bounce(ps, torch, cfg, scene, frames, trace_config):
     """The headline city step with the second bounce on: each hit adds its
     albedo times the query of the stored maps (one more launch per update).
@@ -613,6 +656,7 @@ def main():
                "served_tight_memory": lambda: leg_served(ps, 2.0, rate_hz=args.served_low_rate, budget_frac=0.6,
                                                          with_plain=False),
                "encode": lambda: leg_encode(ps, torch, args.encode_frames),
+               "codec": lambda: leg_codec(ps, torch),
                "multi_bounce": lambda: leg_multi_bounce(ps, torch, cfg, scene, frames,
                                                         tuned["config"] if tuned else None)}
     for name in legs:

@@ -313,6 +313,35 @@ pv_status pv_receiver_get_maps(pv_receiver *rcv, void **irr_dev, void **vis_dev)
 pv_status pv_receiver_read_maps(pv_receiver *rcv, void *irr_host, void *vis_host);
 
 /*
+ * Codec surfaces (Sec. 3.3): a volume's textures as the planes a lossless
+ * video encoder takes, and back. Probe p occupies atlas tile
+ * (p % tiles_per_row, p / tiles_per_row); guard bands are left out; tiles
+ * past the last probe are zero. rows = ceil(n_probes / tiles_per_row).
+ *   irradiance: three planes (Y = R, U = G, V = B) of uint16, each
+ *     [8 rows][8 tiles_per_row]; sample = code << 6 with the 10-bit code
+ *     rint(value * k) clamped to [0, 1023], k the FP32 value nearest
+ *     1023 / irr_scale, the product in FP32 (ties to even);
+ *   visibility: three planes (Y, U, V) of uint8, each
+ *     [16 rows][ceil(64 tiles_per_row / 3)]: the bytes of a texel row
+ *     (per texel mean lo, mean hi, mean^2 lo, mean^2 hi) dealt in order to
+ *     Y, U, V of consecutive samples, so three texels fill four samples;
+ *     missing bytes zero.
+ * pv_yuv_dims: dims = {irradiance width, height, visibility width, height}.
+ * pv_encode_yuv: from an FP16 volume's current maps (PV_ERR_UNSUPPORTED for
+ *   FP32 maps); planes are caller-owned device buffers of 3 x w x h samples
+ *   each, plane after plane; asynchronous on 'stream'.
+ * pv_decode_yuv: planes back to A2RGB10 codes [n_probes][64] (R | G << 10 |
+ *   B << 20, alpha 0; texel t = row * 8 + column) and visibility bit
+ *   patterns [n_probes][2][256]; caller-owned device buffers; asynchronous.
+ * Both: n_probes and tiles_per_row in [1, 65536], else PV_ERR_ARG.
+ */
+pv_status pv_yuv_dims(int n_probes, int tiles_per_row, int64_t dims[4]);
+pv_status pv_encode_yuv(pv_volume *vol, float irr_scale, int tiles_per_row, uint16_t *irr_planes_dev,
+                        uint8_t *vis_planes_dev, void *stream);
+pv_status pv_decode_yuv(pv_ctx *ctx, int n_probes, int tiles_per_row, const uint16_t *irr_planes_dev,
+                        const uint8_t *vis_planes_dev, uint32_t *irr_codes_dev, uint16_t *vis_dev, void *stream);
+
+/*
  * Launch shape of the trace kernel (a tuning choice; every shape computes
  * identical results): probes per wavefront packet as a brick
  * brick[0] x brick[1] x brick[2] = 64 of one ray direction (this also fixes
@@ -354,7 +383,8 @@ typedef enum {
     PV_STAGE_PACK_FINISH = 9,
     PV_STAGE_BOUNCE = 10,
     PV_STAGE_UNPACK = 11,
-    PV_STAGE_COUNT = 12
+    PV_STAGE_CODEC = 12,
+    PV_STAGE_COUNT = 13
 } pv_stage;
 
 /* When enabled, every kernel launch of the context is bracketed by a pair

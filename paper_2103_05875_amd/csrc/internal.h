@@ -114,4 +114,18 @@ struct RxBuffers {
 };
 hipError_t launch_receive(const RxBuffers &b, hipStream_t s);
 
+// Codec surfaces (yuv.hip): plane sizes for P probes, C tiles per atlas row.
+struct YuvDims {
+    long long w, h;    // irradiance planes (samples)
+    long long wv, hv;  // visibility planes
+};
+inline YuvDims yuv_dims(int P, int C) {
+    const long long rows = (P + C - 1) / C;
+    return YuvDims{8ll * C, 8 * rows, (64ll * C + 2) / 3, 16 * rows};
+}
+hipError_t launch_yuv_encode(const uint16_t *irr, const uint16_t *vis, int P, int C, float k, uint16_t *irr_planes,
+                             uint8_t *vis_planes, const YuvDims &d, hipStream_t s);
+hipError_t launch_yuv_decode(const uint16_t *irr_planes, const uint8_t *vis_planes, int P, int C, uint32_t *codes,
+                             uint16_t *vis, const YuvDims &d, hipStream_t s);
+
 }  // namespace pv

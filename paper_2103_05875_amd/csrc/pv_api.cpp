@@ -1,6 +1,6 @@
 // C ABI of the probe-volume library: handles, validation, device memory,
 // launch sequencing. Kernels live in trace.hip, blend.hip, batched.hip,
-// bounce.hip, pack.hip and receive.hip, the BVH builder in bvh.cpp.
+// bounce.hip, pack.hip, receive.hip and yuv.hip, the BVH builder in bvh.cpp.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -1307,5 +1307,55 @@ extern "C" pv_status pv_receiver_read_maps(pv_receiver *r, void *irr, void *vis)
     HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipMemcpy(irr, r->irr, irr_bytes(r->P, 2), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(vis, r->vis, vis_bytes(r->P, 2), hipMemcpyDeviceToHost));
+    return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// codec surfaces
+// ---------------------------------------------------------------------------
+static pv_status check_layout(int P, int C) {
+    if (P < 1 || P > PV_MAX_PROBES) return fail(PV_ERR_ARG, "n_probes must be in [1, 65536]");
+    if (C < 1 || C > PV_MAX_PROBES) return fail(PV_ERR_ARG, "tiles_per_row must be in [1, 65536]");
+    return PV_OK;
+}
+
+extern "C" pv_status pv_yuv_dims(int n_probes, int tiles_per_row, int64_t dims[4]) {
+    if (!dims) return fail(PV_ERR_ARG, "dims is NULL");
+    PV_TRY(check_layout(n_probes, tiles_per_row));
+    const YuvDims d = yuv_dims(n_probes, tiles_per_row);
+    dims[0] = d.w;
+    dims[1] = d.h;
+    dims[2] = d.wv;
+    dims[3] = d.hv;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_encode_yuv(pv_volume *v, float irr_scale, int tiles_per_row, uint16_t *irr_planes,
+                                   uint8_t *vis_planes, void *stream) {
+    if (!v || !irr_planes || !vis_planes) return fail(PV_ERR_ARG, "NULL argument");
+    if (v->desc.format != PV_MAP_FP16) return fail(PV_ERR_UNSUPPORTED, "codec surfaces need FP16 maps");
+    if (!(irr_scale > 0.f) || !std::isfinite(irr_scale)) return fail(PV_ERR_ARG, "irr_scale must be finite and > 0");
+    PV_TRY(check_layout(v->P, tiles_per_row));
+    HIP_TRY(hipSetDevice(v->ctx->device));
+    const float k = (float)(1023.0 / (double)irr_scale);
+    const YuvDims d = yuv_dims(v->P, tiles_per_row);
+    hipStream_t s = pick(v->ctx, stream);
+    HIP_TRY(timed(v->ctx, PV_STAGE_CODEC, s, [&] {
+        return launch_yuv_encode((const uint16_t *)v->irr, (const uint16_t *)v->vis, v->P, tiles_per_row, k,
+                                 irr_planes, vis_planes, d, s);
+    }));
+    return PV_OK;
+}
+
+extern "C" pv_status pv_decode_yuv(pv_ctx *ctx, int n_probes, int tiles_per_row, const uint16_t *irr_planes,
+                                   const uint8_t *vis_planes, uint32_t *irr_codes, uint16_t *vis, void *stream) {
+    if (!ctx || !irr_planes || !vis_planes || !irr_codes || !vis) return fail(PV_ERR_ARG, "NULL argument");
+    PV_TRY(check_layout(n_probes, tiles_per_row));
+    HIP_TRY(hipSetDevice(ctx->device));
+    const YuvDims d = yuv_dims(n_probes, tiles_per_row);
+    hipStream_t s = pick(ctx, stream);
+    HIP_TRY(timed(ctx, PV_STAGE_CODEC, s, [&] {
+        return launch_yuv_decode(irr_planes, vis_planes, n_probes, tiles_per_row, irr_codes, vis, d, s);
+    }));
     return PV_OK;
 }

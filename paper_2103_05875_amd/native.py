@@ -35,11 +35,11 @@ EXPORTED_SYMBOLS = [
     "pv_client_read_state", "pv_client_set_state", "pv_volume_set_trace_config", "pv_volume_get_trace_config",
     "pv_batch_graph_create", "pv_batch_graph_launch", "pv_batch_graph_destroy", "pv_probe_query",
     "pv_receiver_create", "pv_receiver_destroy", "pv_receiver_apply", "pv_receiver_status",
-    "pv_receiver_get_maps", "pv_receiver_read_maps",
+    "pv_receiver_get_maps", "pv_receiver_read_maps", "pv_yuv_dims", "pv_encode_yuv", "pv_decode_yuv",
 ]
 
 STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched", "shadow", "shade",
-          "pack_finish", "bounce", "unpack"]
+          "pack_finish", "bounce", "unpack", "codec"]
 
 
 class NativeError(RuntimeError):
@@ -127,6 +127,9 @@ def lib():
         "pv_receiver_status": ([vp, P(i32), P(u32)], i32),
         "pv_receiver_get_maps": ([vp, P(vp), P(vp)], i32),
         "pv_receiver_read_maps": ([vp, vp, vp], i32),
+        "pv_yuv_dims": ([i32, i32, P(ctypes.c_int64)], i32),
+        "pv_encode_yuv": ([vp, f32, i32, vp, vp, vp], i32),
+        "pv_decode_yuv": ([vp, i32, i32, vp, vp, vp, vp, vp], i32),
         "pv_read_maps": ([vp, vp, vp, P(ctypes.c_int64)], i32),
         "pv_client_create": ([vp, u32, P(vp)], i32),
         "pv_client_destroy": ([vp], i32),
@@ -435,6 +438,18 @@ class Volume:
                                     _stream_handle(stream)))
         return out
 
+    def encode_yuv(self, irr_scale: float, tiles_per_row: int, stream=None):
+        """Codec surfaces of the current maps: (irradiance planes [3, h, w]
+        uint16 as int16 bits, visibility planes [3, hv, wv] uint8), torch
+        device tensors (asynchronous on ``stream``)."""
+        import torch
+        w, h, wv, hv = yuv_dims(self.P, tiles_per_row)
+        ip = torch.empty((3, h, w), dtype=torch.int16, device="cuda")
+        vp = torch.empty((3, hv, wv), dtype=torch.uint8, device="cuda")
+        _check(lib().pv_encode_yuv(self.h, float(irr_scale), int(tiles_per_row), ip.data_ptr(), vp.data_ptr(),
+                                   _stream_handle(stream)))
+        return ip, vp
+
     def read_rays(self):
         """Ray records [P,n,4] float32 (L rgb, distance), hit ids [P,n]
         (None unless keep_hits) and directions [n,4], copied to the host."""
@@ -559,6 +574,30 @@ class Client:
             self.close()
         except Exception:
             pass
+
+
+def yuv_dims(n_probes: int, tiles_per_row: int):
+    """(irradiance plane width, height, visibility plane width, height)."""
+    d = (ctypes.c_int64 * 4)()
+    _check(lib().pv_yuv_dims(int(n_probes), int(tiles_per_row), d))
+    return tuple(int(x) for x in d)
+
+
+def decode_yuv(ctx: "Context", n_probes: int, tiles_per_row: int, irr_planes, vis_planes, stream=None):
+    """Codec surfaces (torch device tensors) back to A2RGB10 codes [P, 64]
+    (int32 bits) and visibility binary16 patterns [P, 2, 256] (int16 bits)."""
+    import torch
+    w, h, wv, hv = yuv_dims(n_probes, tiles_per_row)
+    if tuple(irr_planes.shape) != (3, h, w) or tuple(vis_planes.shape) != (3, hv, wv):
+        raise ValueError("plane shapes do not match the layout")
+    if irr_planes.element_size() != 2 or vis_planes.element_size() != 1:
+        raise ValueError("irradiance planes are 16-bit, visibility planes 8-bit")
+    ip, vp = irr_planes.contiguous(), vis_planes.contiguous()
+    codes = torch.empty((n_probes, 64), dtype=torch.int32, device="cuda")
+    vis = torch.empty((n_probes, 2, 256), dtype=torch.int16, device="cuda")
+    _check(lib().pv_decode_yuv(ctx.h, int(n_probes), int(tiles_per_row), ip.data_ptr(), vp.data_ptr(),
+                               codes.data_ptr(), vis.data_ptr(), _stream_handle(stream)))
+    return codes, vis
 
 
 class Receiver:

@@ -97,3 +97,13 @@ def test_no_device_is_reported_not_faked(ps):
         pytest.skip("a GPU is present")
     with pytest.raises(ps.NativeError):
         ps.Context(0)
+
+
+def test_codec_surface_dims_match_the_oracle(ps, oracle_lib):
+    """pv_yuv_dims (host logic, no device) against the oracle's layout."""
+    for P, C in ((1, 1), (7, 3), (2048, 32), (65536, 256), (5, 65536)):
+        assert ps.yuv_dims(P, C) == oracle_lib.yuv_dims(P, C)
+    d = (ctypes.c_int64 * 4)()
+    assert ps.lib().pv_yuv_dims(0, 1, d) == -1
+    assert ps.lib().pv_yuv_dims(10, 0, d) == -1
+    assert ps.lib().pv_yuv_dims(65537, 1, d) == -1
