@@ -104,7 +104,7 @@ def lib():
         L.or_pack.restype = ctypes.c_int64
         L.or_pack.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _U16, _U16, _U16, _U16,
                               ctypes.c_double, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32,
-                              _U8, ctypes.c_int64, _U8, _U8]
+                              _U8, ctypes.c_int64, _U8, _U8, _U8]
         L.or_client_apply.restype = ctypes.c_int
         L.or_client_apply.argtypes = [_U8, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       _U16, _U16, ctypes.POINTER(ctypes.c_uint32)]
@@ -337,6 +337,128 @@ def yuv_decode(irr_planes, vis_planes, P: int, C: int):
     return codes, vis
 
 
+# --------------------------------------------------------------------------
+# probe selection (Sec. 3.4): active probes, the client's visible set
+# --------------------------------------------------------------------------
+def _unit_normals(scene: "OracleScene") -> np.ndarray:
+    t = scene._tris.reshape(-1, 3, 3).astype(np.float64)
+    n = np.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0])
+    return n / np.linalg.norm(n, axis=1, keepdims=True)
+
+
+def probe_activity(scene: "OracleScene", cfg, R, rays, graze: float = 1e-6, tol: float = 1e-5):
+    """Which probes are active after a frame whose trace gave ``rays``
+    (trace_shade output). A probe is inactive when more than a quarter of
+    its rays hit a triangle from behind (the side its normal (v1 - v0) x
+    (v2 - v0) points away from: the probe sits inside a solid), or when none
+    of its rays hits anything closer than the cell diagonal |spacing| (no
+    surface near enough to be shaded by it). Returns (nominal, lo, hi) bool
+    [P]: lo = active whatever the accepted hits and rounding, hi = active for
+    some of them (a ray with a grazing hit counts both ways, a hit within
+    ``tol`` relative of the diagonal both ways)."""
+    P, n = cfg.n_probes, cfg.rays_per_probe
+    d = ray_dirs(n, R)
+    un = _unit_normals(scene) if scene.ntri else np.zeros((0, 3))
+    sp = np.array([float(np.float32(s)) for s in cfg.spacing])
+    diag = float(np.sqrt((sp * sp).sum()))
+    cand, ncand, hit, t = rays["cand"], rays["ncand"], rays["hit"], rays["hit_t"]
+    maxc = cand.shape[2]
+    valid = np.arange(maxc)[None, None, :] < ncand[..., None]
+    cc = np.where(valid, cand, -2)                     # -2: no candidate in this slot
+    is_hit = cc >= 0
+    cosv = np.where(is_hit, np.einsum("pnck,nk->pnc", un[np.clip(cc, 0, None)] if scene.ntri else
+                                      np.zeros(cc.shape + (3,)), d), 0.0)
+    back_c = is_hit & (cosv > graze)
+    front_c = (cc == -1) | (is_hit & (cosv < -graze))
+    back_nom = (hit >= 0) & (np.where(hit >= 0, np.einsum("pnk,nk->pn", un[np.clip(hit, 0, None)] if scene.ntri
+                                                          else np.zeros(hit.shape + (3,)), d), 0.0) > 0)
+    back_lo = (back_c | ~valid).all(axis=2) & back_c.any(axis=2)     # every candidate surely from behind
+    back_hi = (~(front_c | ~valid)).any(axis=2)                        # some candidate possibly from behind
+    near_nom = (hit >= 0) & (t < diag)
+    all_hit = (is_hit | ~valid).all(axis=2)
+    near_lo = all_hit & (hit >= 0) & (t < diag * (1 - tol))
+    near_hi = (is_hit.any(axis=2) & ((hit < 0) | (t < diag * (1 + tol))))
+
+    nom = (4 * back_nom.sum(axis=1) <= n) & near_nom.any(axis=1)
+    lo = (4 * back_hi.sum(axis=1) <= n) & near_lo.any(axis=1)
+    hi = (4 * back_lo.sum(axis=1) <= n) & near_hi.any(axis=1)
+    return nom, lo, hi
+
+
+def _cell_range(g, dim, tol):
+    """Cells an axis coordinate g (grid units) may fall in: the clamped
+    floor, and its neighbour when g lies within tol of a cell plane."""
+    if dim == 1:
+        return {0}
+    out = set()
+    for x in (g - tol, g, g + tol):
+        out.add(int(min(max(np.floor(x), 0), dim - 2)))
+    return out
+
+
+def client_pvs(scene: "OracleScene", cfg, eye, n_rays: int, tol: float = 1e-5, delta_rel: float = 1e-6):
+    """The client's potentially visible set (Sec. 3.4: a spherical view from
+    the client's position): n_rays spherical-Fibonacci directions (no
+    rotation) from ``eye``; every probe at a corner of the grid cell (clamped
+    to the grid) holding a hit point. Returns (nominal, lo, hi) bool [P]: hi
+    adds, for rays near a tie, every corner of the cells around the hit and,
+    for points within tol of a cell plane, both cells; lo keeps only the rays
+    whose cell is certain. For a ray near a tie the hits of the ray started
+    +-delta along each axis are taken as well (as the trace's accepted set
+    does)."""
+    P = cfg.n_probes
+    dims = (cfg.nx, cfg.ny, cfg.nz)
+    o = np.array([float(np.float32(v)) for v in cfg.origin])
+    s = np.array([float(np.float32(v)) for v in cfg.spacing])
+    eye = np.array([float(np.float32(v)) for v in eye])
+    d = ray_dirs(n_rays, np.eye(3, dtype=np.float32))
+    m = 2.0 * delta_rel * scene.diag
+    tri, t, near = scene.closest_hits(np.repeat(eye[None], n_rays, 0), d, margin=m)
+    nom = np.zeros(P, bool)
+    lo = np.zeros(P, bool)
+    hi = np.zeros(P, bool)
+
+    def mark(mask, cells):
+        for cx in cells[0]:
+            for cy in cells[1]:
+                for cz in cells[2]:
+                    for bz in range(2 if dims[2] > 1 else 1):
+                        for by in range(2 if dims[1] > 1 else 1):
+                            for bx in range(2 if dims[0] > 1 else 1):
+                                mask[(cx + bx) + dims[0] * ((cy + by) + dims[1] * (cz + bz))] = True
+    def cells(x, widen):
+        g = (x - o) / s
+        w = [_cell_range(g[a], dims[a], tol) for a in range(3)]
+        if widen:
+            w = [set(range(max(min(c) - 1, 0), min(max(c) + 1, max(dims[a] - 2, 0)) + 1)) for a, c in enumerate(w)]
+        return w
+
+    near_rays = np.nonzero(near)[0]
+    alt = {}
+    if near_rays.size:
+        delta = delta_rel * scene.diag
+        for a in range(3):
+            for sg in (-1.0, 1.0):
+                e2 = eye.copy()
+                e2[a] += sg * delta
+                tr, tt, _ = scene.closest_hits(np.repeat(e2[None], near_rays.size, 0), d[near_rays])
+                for k, r in enumerate(near_rays):
+                    if tr[k] >= 0:
+                        alt.setdefault(r, []).append(e2 + tt[k] * d[r])
+    for r in range(n_rays):
+        if tri[r] >= 0:
+            x = eye + t[r] * d[r]
+            g = (x - o) / s
+            mark(nom, [_cell_range(g[a], dims[a], 0.0) for a in range(3)])
+            w = cells(x, near[r])
+            if not near[r] and all(len(c) == 1 for c in w):
+                mark(lo, w)
+            mark(hi, w)
+        for x in alt.get(r, []):
+            mark(hi, cells(x, True))
+    return nom, lo, hi
+
+
 def border(tiles: np.ndarray) -> np.ndarray:
     """Guard-band copy of a float tile set [P, C, N+2, N+2] (returns a copy)."""
     t = _c(tiles, np.float64).copy()
@@ -420,8 +542,10 @@ class OracleClientState:
         self.client = client
         self.seq = 0
 
-    def pack(self, cur_irr: np.ndarray, cur_vis: np.ndarray, tau_irr: float = 0.0, tau_vis: float = 0.0):
-        """Pack FP16 tiles (uint16 [P,3,Ni+2,Ni+2] / [P,2,Nv+2,Nv+2]).
+    def pack(self, cur_irr: np.ndarray, cur_vis: np.ndarray, tau_irr: float = 0.0, tau_vis: float = 0.0,
+             eligible=None):
+        """Pack FP16 tiles (uint16 [P,3,Ni+2,Ni+2] / [P,2,Nv+2,Nv+2]); only
+        ``eligible`` probes (bool [P], None = all) may be sent.
         Returns (packet bytes, mask_irr, mask_vis)."""
         cur_irr = _c(cur_irr, np.uint16)
         cur_vis = _c(cur_vis, np.uint16)
@@ -433,7 +557,8 @@ class OracleClientState:
         mv = np.zeros(self.P, np.uint8)
         n = lib().or_pack(self.P, self.Ni, self.Nv, _p(cur_irr, _U16), _p(cur_vis, _U16),
                           _p(self.ref_irr, _U16), _p(self.ref_vis, _U16), float(tau_irr), float(tau_vis),
-                          self.client, self.seq, _p(out, _U8), cap, _p(mi, _U8), _p(mv, _U8))
+                          self.client, self.seq, _p(out, _U8), cap, _p(mi, _U8), _p(mv, _U8),
+                          None if eligible is None else _p(_c(eligible, np.uint8), _U8))
         assert n > 0
         self.seq += 1
         return out[:n].tobytes(), mi.astype(bool), mv.astype(bool)

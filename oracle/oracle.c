@@ -1091,13 +1091,16 @@ OR_API int64_t or_packet_bytes(int K_irr, int K_vis, int Ni, int Nv)
  */
 OR_API int64_t or_pack(int P, int Ni, int Nv, const uint16_t *cur_irr, const uint16_t *cur_vis, uint16_t *ref_irr,
                        uint16_t *ref_vis, double tau_irr, double tau_vis, uint32_t client, uint32_t seq,
-                       uint8_t *out, int64_t cap, uint8_t *mask_irr, uint8_t *mask_vis)
+                       uint8_t *out, int64_t cap, uint8_t *mask_irr, uint8_t *mask_vis, const uint8_t *eligible)
 {
+    /* eligible (NULL: every probe): the probes that may be sent at all
+     * (active, and in the client's view when one is set, Sec. 3.4) */
     uint8_t *mi = (uint8_t *)malloc(P > 0 ? P : 1), *mv = (uint8_t *)malloc(P > 0 ? P : 1);
     int K_irr = 0, K_vis = 0;
     for (int p = 0; p < P; ++p) {
-        mi[p] = (uint8_t)probe_changed(cur_irr, ref_irr, 3, Ni, p, tau_irr);
-        mv[p] = (uint8_t)probe_changed(cur_vis, ref_vis, 2, Nv, p, tau_vis);
+        const int ok = eligible ? eligible[p] != 0 : 1;
+        mi[p] = (uint8_t)(ok && probe_changed(cur_irr, ref_irr, 3, Ni, p, tau_irr));
+        mv[p] = (uint8_t)(ok && probe_changed(cur_vis, ref_vis, 2, Nv, p, tau_vis));
         K_irr += mi[p];
         K_vis += mv[p];
     }

@@ -79,8 +79,10 @@ _BOX_FACES = (
 )
 
 
-def _box_triangles(lo, hi) -> np.ndarray:
-    """12 triangles (2 per face) of an axis-aligned box, float64 [12,3,3]."""
+def _box_triangles(lo, hi, inward: bool = False) -> np.ndarray:
+    """12 triangles (2 per face) of an axis-aligned box, float64 [12,3,3].
+    Wound so that (v1 - v0) x (v2 - v0) points out of the box (a solid), or
+    into it with ``inward`` (a room whose inside is open space)."""
     lo = np.asarray(lo, np.float64)
     hi = np.asarray(hi, np.float64)
     corners = np.array([[hi[0] if (c & 1) else lo[0],
@@ -88,8 +90,12 @@ def _box_triangles(lo, hi) -> np.ndarray:
                          hi[2] if (c & 4) else lo[2]] for c in range(8)])
     out = []
     for a, b, c, d in _BOX_FACES:
-        out.append([corners[a], corners[b], corners[c]])
-        out.append([corners[a], corners[c], corners[d]])
+        if inward:
+            out.append([corners[a], corners[b], corners[c]])
+            out.append([corners[a], corners[c], corners[d]])
+        else:
+            out.append([corners[a], corners[c], corners[b]])
+            out.append([corners[a], corners[d], corners[c]])
     return np.array(out)
 
 
@@ -105,7 +111,7 @@ def box_room(seed: int = 1) -> Scene:
     quads = 24 triangles, per-quad albedo U(0.2,0.8)^3, one point light at
     (0.4, 3.6, 0.4) with intensity (20, 20, 20)."""
     rng = np.random.default_rng(seed)
-    room = _box_triangles([-1, -1, -1], [4, 4, 4])
+    room = _box_triangles([-1, -1, -1], [4, 4, 4], inward=True)
     cube = _box_triangles([1.25, 1.25, 1.25], [1.75, 1.75, 1.75])
     tris = np.concatenate([room, cube])
     quad_alb = rng.uniform(0.2, 0.8, size=(12, 3))
@@ -119,7 +125,7 @@ def emissive_box(half_width: float = 1.0, center=(0.0, 0.0, 0.0),
                  emission=(0.7, 0.4, 0.2)) -> Scene:
     """Closed box whose walls all emit the same radiance and reflect nothing."""
     c = np.asarray(center, np.float64)
-    tris = _box_triangles(c - half_width, c + half_width)
+    tris = _box_triangles(c - half_width, c + half_width, inward=True)
     e = np.tile(np.asarray(emission, np.float64), (12, 1))
     return soup_scene(tris, np.zeros((12, 3)), e, np.zeros((0, 6)))
 
@@ -127,7 +133,7 @@ def emissive_box(half_width: float = 1.0, center=(0.0, 0.0, 0.0),
 def cube_shell(half_width: float, center=(0.0, 0.0, 0.0), albedo=0.5,
                lights=None) -> Scene:
     c = np.asarray(center, np.float64)
-    tris = _box_triangles(c - half_width, c + half_width)
+    tris = _box_triangles(c - half_width, c + half_width, inward=True)
     lights = np.zeros((0, 6)) if lights is None else lights
     return soup_scene(tris, np.full((12, 3), albedo), np.zeros((12, 3)), lights)
 
@@ -164,8 +170,9 @@ def box_city(n_tris: int = 50_000, seed_layout: int = 10,
     heights = np.exp(math.log(3.0) + 0.6 * hrng.standard_normal(n_boxes))
     x0 = cx * cell + ox
     z0 = cz * cell + oz
-    tris = [np.array([[[-1.0, 0.0, -1.0], [extent + 1, 0.0, -1.0], [extent + 1, 0.0, extent + 1]],
-                      [[-1.0, 0.0, -1.0], [extent + 1, 0.0, extent + 1], [-1.0, 0.0, extent + 1]]])]
+    # the ground faces up (+y)
+    tris = [np.array([[[-1.0, 0.0, -1.0], [extent + 1, 0.0, extent + 1], [extent + 1, 0.0, -1.0]],
+                      [[-1.0, 0.0, -1.0], [-1.0, 0.0, extent + 1], [extent + 1, 0.0, extent + 1]]])]
     # box bottoms sit just below the ground plane, so no face is coplanar
     # with the ground (no overlapping surfaces)
     for b in range(n_boxes):

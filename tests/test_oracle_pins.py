@@ -875,3 +875,67 @@ def test_codec_surfaces_layout_and_round_trip(O, P, C):
     # tiles past the last probe are zero
     if P % C:
         assert not ip[:, -8:, (P % C) * 8:].any()
+
+
+# ---------------------------------------------------------------- probe selection (Sec. 3.4)
+def test_pack_sends_only_eligible_probes(O):
+    """With an eligibility mask (active probes in the client's view) the sent
+    set is changed AND eligible; ineligible probes keep their reference."""
+    P = 200
+    cur_i, cur_v = synth.random_fp16_maps(P, 8, 16, seed=13)
+    st = O.OracleClientState(P)
+    elig = np.random.default_rng(5).uniform(size=P) < 0.6
+    pkt, mi, mv = st.pack(cur_i, cur_v, eligible=elig)
+    full_i, full_v = _np_masks(cur_i, cur_v, np.zeros((P, 3, 64), np.uint16), np.zeros((P, 2, 256), np.uint16), 0, 0)
+    assert np.array_equal(mi, full_i & elig) and np.array_equal(mv, full_v & elig)
+    d = _parse(pkt)
+    assert np.array_equal(d["idx_irr"], np.nonzero(full_i & elig)[0])
+    assert not st.ref_irr[~elig].any() and not st.ref_vis[~elig].any()
+    # the same probes become sendable once eligible
+    pkt2, mi2, _ = st.pack(cur_i, cur_v)
+    assert np.array_equal(mi2, full_i & ~elig)
+
+
+def _solid_box_scene(O):
+    tris = synth._box_triangles([-0.5, -0.5, -0.5], [0.5, 0.5, 0.5]).astype(np.float32)   # outward: a solid
+    return O.OracleScene(tris, np.full((12, 3), 0.5, np.float32))
+
+
+def test_activity_inside_near_and_far(O):
+    """Probes 1 apart on a line from the centre of a solid unit box: inside
+    it (every ray hits a face from behind) inactive; at 1 and 2 (the face
+    within the cell diagonal sqrt 3) active; at 3 (nothing within sqrt 3)
+    inactive."""
+    cfg = _cfg(nx=4, ny=1, nz=1, spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), rays_per_probe=256)
+    sc = _solid_box_scene(O)
+    R = synth.rotation(3, 0)
+    rays = O.trace_shade(sc, cfg, R, np.zeros((0, 6), np.float32))
+    nom, lo, hi = O.probe_activity(sc, cfg, R, rays)
+    assert nom.tolist() == [False, True, True, False]
+    assert np.array_equal(lo, nom) and np.array_equal(hi, nom)
+
+
+def test_activity_below_a_ground_plane(O):
+    """Half the rays of a probe below an upward-facing ground hit it from
+    behind (> 1/4): inactive; above it: active."""
+    ground = synth.box_city(n_tris=14).triangles()[:2].astype(np.float32)
+    sc = O.OracleScene(ground, np.full((2, 3), 0.5, np.float32))
+    cfg = _cfg(nx=2, ny=2, nz=1, spacing=(1.0, 1.0, 1.0), origin=(10.0, -0.5, 10.0), rays_per_probe=256)
+    R = synth.rotation(3, 0)
+    nom, lo, hi = O.probe_activity(sc, cfg, R, O.trace_shade(sc, cfg, R, np.zeros((0, 6), np.float32)))
+    assert nom.tolist() == [False, False, True, True] and np.array_equal(lo, hi)
+
+
+def test_client_view_marks_the_cells_of_visible_points(O):
+    """A wall at z = 2.5 in front of the eye, nothing else: the visible
+    points all lie in cells with z index 2, so exactly the probes with
+    z in {2, 3} are in the view; an empty scene marks nothing."""
+    cfg = _cfg(nx=4, ny=4, nz=4, spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0))
+    wall = np.array([[[-5, -5, 2.5], [5, 5, 2.5], [5, -5, 2.5]], [[-5, -5, 2.5], [-5, 5, 2.5], [5, 5, 2.5]]],
+                    np.float32)
+    sc = O.OracleScene(wall, np.full((2, 3), 0.5, np.float32))
+    nom, lo, hi = O.client_pvs(sc, cfg, (1.5, 1.5, 0.2), 4096)
+    z = np.arange(64) // 16
+    assert np.array_equal(nom, z >= 2) and np.array_equal(lo, nom) and np.array_equal(hi, nom)
+    empty = O.OracleScene(np.zeros((0, 3, 3), np.float32), np.zeros((0, 3), np.float32))
+    assert not any(m.any() for m in O.client_pvs(empty, cfg, (1.5, 1.5, 0.2), 512))
