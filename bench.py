@@ -47,7 +47,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--legs", default="batched,served,served_below_capacity,served_tight_memory,encode,multi_bounce,codec",
+    ap.add_argument("--legs", default="batched,served,served_below_capacity,served_tight_memory,encode,multi_bounce,codec,"
+                                      "selection",
                     help="extra workloads reported in the same line (comma list, or 'none')")
     ap.add_argument("--served-seconds", type=float, default=1.0)
     ap.add_argument("--served-low-rate", type=float, default=300.0,
@@ -442,6 +443,69 @@ def leg_codec(ps, torch, reps: int = 20):
     return out
 
 
+def street_eye(scene, height: float = 1.7):
+    """A client position at street level in the box city: the first point of a
+    coarse grid over the city that lies outside every box (boxes are the
+    12-triangle groups after the 2 ground triangles)."""
+    tris = scene.triangles()
+    boxes = tris[2:].reshape(-1, 12, 3, 3)
+    lo, hi = boxes.min(axis=(1, 2)), boxes.max(axis=(1, 2))
+    for x in np.linspace(5.3, 58.7, 24):
+        for z in np.linspace(5.1, 58.9, 24):
+            pt = np.array([x, height, z])
+            if not np.any(np.all((pt > lo - 0.5) & (pt < hi + 0.5), axis=1)):
+                return tuple(float(v) for v in pt)
+    return (32.0, 12.0, 32.0)
+
+
+def leg_selection(ps, torch, cfg, scene, frames, trace_config):
+    """Probe selection on the city workload (Sec. 3.4): the volume classifies
+    its probes every update; client A culls to a spherical view from a street
+    position, client B sends every active changed probe; per-frame sent
+    probes of both (tau = 0) and the cost of classification and view."""
+    import dataclasses
+    scfg = dataclasses.replace(cfg, classify=True)
+    ctx = ps.Context(0)
+    sc = ps.Scene.from_synth(ctx, scene)
+    vol = ps.Volume(ctx, scfg)
+    vol.set_scene(sc)
+    if trace_config:
+        c = trace_config
+        vol.set_trace_config(c["brick"], c["persistent"], c["top_nodes"], c["block_threads"], c["split_shadows"])
+    a, bcl = ps.Client(vol, client_id=1), ps.Client(vol, client_id=2)
+    stream = torch.cuda.current_stream()
+    eye = street_eye(scene)
+    ctx.set_timing(True)
+    ctx.stage_times()
+    a.set_view(eye, 16384, stream=stream)
+    view_ms = ctx.stage_times()["select"][0]
+    sent_a, sent_b = [], []
+    for i, (R, l) in enumerate(frames):
+        vol.update_probes(R, l, stream=stream)
+        a.pack_delta(0.0, 0.0, stream=stream)
+        ma = [m.sum() for m in a.read_masks()]
+        bcl.pack_delta(0.0, 0.0, stream=stream)
+        mb = [m.sum() for m in bcl.read_masks()]
+        if i > 0:   # frame 0 sends the initial state
+            sent_a.append(ma)
+            sent_b.append(mb)
+    st = ctx.stage_times()
+    ctx.set_timing(False)
+    P = scfg.n_probes
+    active = vol.read_active()
+    view = a.read_view()
+    sa, sb = np.mean(sent_a, axis=0), np.mean(sent_b, axis=0)
+    out = {"eye": eye, "view_rays": 16384, "view_ms": view_ms, "probes": P,
+           "active": int(active.sum()), "in_view": int(view.sum()), "active_in_view": int((active & view).sum()),
+           "classify_ms": st["select"][0] / max(st["select"][1], 1),
+           "sent_per_frame_view": {"irr": float(sa[0]), "vis": float(sa[1])},
+           "sent_per_frame_all_active": {"irr": float(sb[0]), "vis": float(sb[1])},
+           "reduction_vs_active": 1.0 - float((sa[0] + sa[1]) / max(2 * active.sum(), 1))}
+    for h in (a, bcl, vol, sc, ctx):
+        h.close()
+    return out
+
+
 def leg_multi_bounce(ps, torch, cfg, scene, frames, trace_config):
     """The headline city step with the second bounce on: each hit adds its
     albedo times the query of the stored maps (one more launch per update).
@@ -657,6 +721,7 @@ def main():
                                                          with_plain=False),
                "encode": lambda: leg_encode(ps, torch, args.encode_frames),
                "codec": lambda: leg_codec(ps, torch),
+               "selection": lambda: leg_selection(ps, torch, cfg, scene, frames, tuned["config"] if tuned else None),
                "multi_bounce": lambda: leg_multi_bounce(ps, torch, cfg, scene, frames,
                                                         tuned["config"] if tuned else None)}
     for name in legs:

@@ -77,6 +77,16 @@ typedef enum { PV_MAP_FP32 = 0, PV_MAP_FP16 = 1 } pv_map_format;
  * frame's blend. Repeated frames thus accumulate multiple bounces. Costs an
  * 8-byte hit record per ray and one more launch per update. */
 #define PV_MULTI_BOUNCE 4u
+/* Probe activity (Sec. 3.4: only active probes are worth sending): every
+ * update classifies each probe from its rays -- inactive when more than a
+ * quarter of them hit a triangle from behind (the side its normal
+ * (v1 - v0) x (v2 - v0) points away from, i.e. the probe sits inside a
+ * solid; scenes wind triangles with normals out of solids) or when none
+ * hits anything closer than the cell diagonal |spacing| -- and the pack
+ * sends active probes only. Costs an 8-byte hit record per ray, P bytes
+ * and one launch per update. Before the first update every probe counts as
+ * active. */
+#define PV_CLASSIFY 8u
 
 #define PV_MAX_LIGHTS 8
 #define PV_MAX_PROBES 65536          /* the 2-byte probe index (Section 3.4) */
@@ -101,7 +111,7 @@ typedef struct {
     int vis_sharpness;       /* visibility weight = max(0, cos)^s, s in [1, 128] */
     pv_map_format format;
     float sky[3];            /* radiance of rays that leave the scene */
-    uint32_t flags;          /* PV_FIRST_FRAME_NO_HISTORY | PV_KEEP_HITS | PV_MULTI_BOUNCE */
+    uint32_t flags;          /* PV_FIRST_FRAME_NO_HISTORY | PV_KEEP_HITS | PV_MULTI_BOUNCE | PV_CLASSIFY */
 } pv_volume_desc;
 
 typedef struct {
@@ -276,6 +286,25 @@ pv_status pv_client_set_state(pv_client *client, const void *ref_irr_host, const
 /* Changed-probe masks of the last pack (device, [P] uint8 each). */
 pv_status pv_get_masks(pv_client *client, void **mask_irr_dev, void **mask_vis_dev);
 
+/* Activity of the last update, [P] uint8 (1 = active), device memory owned
+ * by the volume; PV_ERR_STATE without PV_CLASSIFY. */
+pv_status pv_get_active(pv_volume *vol, const void **active_dev);
+/*
+ * Server-side client-view culling (Sec. 3.4: the probes that may shade
+ * points visible from the client, estimated by a spherical view from its
+ * position): n_rays spherical-Fibonacci directions (no rotation) are traced
+ * from eye against the volume's scene; every probe at a corner of the grid
+ * cell (clamped to the grid) holding a hit point joins the client's view.
+ * From then on pv_pack_delta sends only probes in the view (and active,
+ * with PV_CLASSIFY); probes outside keep their reference. Asynchronous on
+ * 'stream'. n_rays in [1, 2^22]; eye finite.
+ */
+pv_status pv_client_set_view(pv_client *client, const float eye[3], int n_rays, void *stream);
+/* Back to no view culling. */
+pv_status pv_client_clear_view(pv_client *client);
+/* The client's view mask [P] uint8, or NULL when no view is set. */
+pv_status pv_client_get_view(pv_client *client, const void **view_dev);
+
 /* Wait for the stream (NULL: the whole device); report asynchronous device
  * errors. */
 pv_status pv_sync(void *stream);
@@ -384,7 +413,8 @@ typedef enum {
     PV_STAGE_BOUNCE = 10,
     PV_STAGE_UNPACK = 11,
     PV_STAGE_CODEC = 12,
-    PV_STAGE_COUNT = 13
+    PV_STAGE_SELECT = 13,
+    PV_STAGE_COUNT = 14
 } pv_stage;
 
 /* When enabled, every kernel launch of the context is bracketed by a pair

@@ -27,6 +27,20 @@ constexpr int kBlendK = 128;          // rays staged in LDS per step
 static_assert(kBlendK == 128, "the weight tables are zero-padded to a multiple of 128 rays");
 static_assert(kBlendSplit == 2 && kBlendThreads == 256, "blend_tile maps 2 x 4 waves onto the texel rows");
 
+// Direction i of the n-ray spherical-Fibonacci set, rotated by the frame's
+// rotation (FP64 arithmetic, rounded to FP32 once).
+__device__ __forceinline__ float4 raydir(const FrameParams &fp, int n, int i) {
+    // z evenly spaced in (-1, 1); azimuth steps by the golden angle
+    const double z = 1.0 - (2.0 * i + 1.0) / n;
+    const double a = (double)i * 0.61803398874989484820;  // frac(i * (phi - 1))
+    const double az = 6.28318530717958647692 * (a - floor(a));
+    const double rr = sqrt(fmax(0.0, 1.0 - z * z));
+    const double sx = rr * cos(az), sy = rr * sin(az);
+    const float *R = fp.rot;
+    return make_float4((float)(R[0] * sx + R[1] * sy + R[2] * z), (float)(R[3] * sx + R[4] * sy + R[5] * z),
+                       (float)(R[6] * sx + R[7] * sy + R[8] * z), 0.f);
+}
+
 // Centre direction of interior texel (i, j) of an N x N octahedral map.
 __device__ __forceinline__ float3 oct_texel_dir(int N, int i, int j) {
     const float u = (2.0f * i + 1.0f) / N - 1.0f;

@@ -51,6 +51,9 @@ struct BatchVolume {
     int n_blend;
     int first_bounce; // prefix over volumes of second-bounce blocks (0 blocks without it)
     int n_bounce;
+    uint8_t *active;  // probe activity (classifying volumes), else null
+    int first_classify; // prefix over volumes of classification blocks (0 blocks without it)
+    int n_classify;
     int bricks_x, bricks_y, bricks_z;
 };
 
@@ -88,6 +91,8 @@ struct PackBuffers {
     uint32_t *totals;   // K_irr, K_vis (written by the scan)
     uint32_t *partial;  // per tile: checksum share of its plane words (written by the compaction)
     uint8_t *packet;
+    const uint8_t *active;  // [P] volume's active probes, or null (all)
+    const uint8_t *view;    // [P] client's visible set, or null (all)
 };
 hipError_t launch_pack_mask(const PackBuffers &b, int P, float tau_irr, float tau_vis, hipStream_t s);
 hipError_t launch_pack_scan(const PackBuffers &b, int P, hipStream_t s);
@@ -113,6 +118,16 @@ struct RxBuffers {
     RxStatus *status;
 };
 hipError_t launch_receive(const RxBuffers &b, hipStream_t s);
+
+// Probe selection (select.hip): activity from the frame's hit records, and
+// a client's visible set from a spherical view at its position.
+hipError_t launch_classify(const VolumeParams &vp, const SceneView &sv, const float4 *dirs, uint8_t *active,
+                           hipStream_t s);
+hipError_t launch_client_view(const VolumeParams &vp, const SceneView &sv, float ex, float ey, float ez, int n_rays,
+                              uint8_t *view, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t s);
+int classify_blocks(int P);
+hipError_t launch_classify_batched(const BatchVolume *vols_dev, int n_vols, int total_blocks, hipStream_t s);
 
 // Codec surfaces (yuv.hip): plane sizes for P probes, C tiles per atlas row.
 struct YuvDims {

@@ -124,9 +124,16 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P
     }
     __syncthreads();
     if (threadIdx.x < n) {
-        b.mask_irr[p0 + threadIdx.x] = (uint8_t)sm.changed[threadIdx.x][0];
-        b.mask_vis[p0 + threadIdx.x] = (uint8_t)sm.changed[threadIdx.x][1];
+        // only eligible probes are sent: active, and in the client's view
+        const int p = p0 + threadIdx.x;
+        if ((b.active && !b.active[p]) || (b.view && !b.view[p])) {
+            sm.changed[threadIdx.x][0] = 0;
+            sm.changed[threadIdx.x][1] = 0;
+        }
+        b.mask_irr[p] = (uint8_t)sm.changed[threadIdx.x][0];
+        b.mask_vis[p] = (uint8_t)sm.changed[threadIdx.x][1];
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
         int4 s = make_int4(0, 0, -1, -1);
         for (int q = 0; q < n; ++q) {

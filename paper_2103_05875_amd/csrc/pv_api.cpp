@@ -1,6 +1,7 @@
 // C ABI of the probe-volume library: handles, validation, device memory,
 // launch sequencing. Kernels live in trace.hip, blend.hip, batched.hip,
-// bounce.hip, pack.hip, receive.hip and yuv.hip, the BVH builder in bvh.cpp.
+// bounce.hip, select.hip, pack.hip, receive.hip and yuv.hip, the BVH builder
+// in bvh.cpp.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -116,7 +117,8 @@ struct pv_volume {
     float4 *rays = nullptr, *dirs = nullptr;
     WeightTables wt;  // blend weights of the current frame
     int32_t *hits = nullptr;
-    int2 *hitrec = nullptr;  // second-bounce hit records (PV_MULTI_BOUNCE)
+    int2 *hitrec = nullptr;  // hit records (PV_MULTI_BOUNCE or PV_CLASSIFY)
+    uint8_t *active = nullptr;  // [P] probe activity of the last update (PV_CLASSIFY)
     int *queue = nullptr;  // work counters (queue_counter: 0..7 per XCD, 8 shadow-queue length)
     int64_t frame = 0;
     pv_scene *scene = nullptr;
@@ -135,6 +137,8 @@ struct pv_client {
     uint8_t *packet = nullptr;
     uint64_t packet_cap = 0;
     uint32_t *hdr_host = nullptr;  // pinned, 32 bytes
+    uint8_t *view = nullptr;       // [P] visible set of the last pv_client_set_view
+    bool view_on = false;
 };
 
 // NULL is HIP's default stream, as in the HIP API itself.
@@ -451,7 +455,8 @@ static pv_status validate_desc(const pv_volume_desc *d) {
         return fail(PV_ERR_UNSUPPORTED, "supported: irr_res = 8 and vis_res = 16");
     if (!(d->spacing[0] > 0.f && d->spacing[1] > 0.f && d->spacing[2] > 0.f))
         return fail(PV_ERR_ARG, "spacing must be > 0 on every axis");
-    if (d->flags & ~(PV_FIRST_FRAME_NO_HISTORY | PV_KEEP_HITS | PV_MULTI_BOUNCE)) return fail(PV_ERR_ARG, "unknown flags");
+    if (d->flags & ~(PV_FIRST_FRAME_NO_HISTORY | PV_KEEP_HITS | PV_MULTI_BOUNCE | PV_CLASSIFY))
+        return fail(PV_ERR_ARG, "unknown flags");
     return PV_OK;
 }
 
@@ -462,7 +467,8 @@ static uint64_t volume_bytes(const pv_volume_desc *d) {
                  (uint64_t)kQueueInts * 4 +
                  (uint64_t)(weight_table_floats(n) + weight_part_floats(n)) * 4;
     if (d->flags & PV_KEEP_HITS) b += (uint64_t)P * n * 4;
-    if (d->flags & PV_MULTI_BOUNCE) b += (uint64_t)P * n * 8;
+    if (d->flags & (PV_MULTI_BOUNCE | PV_CLASSIFY)) b += (uint64_t)P * n * 8;
+    if (d->flags & PV_CLASSIFY) b += (uint64_t)P;
     return b;
 }
 
@@ -482,6 +488,7 @@ static void free_volume(pv_volume *v) {
     hipFree(v->wt.part);
     hipFree(v->hits);
     hipFree(v->hitrec);
+    hipFree(v->active);
     hipFree(v->queue);
     hipFree(v->split.hitrec);
     hipFree(v->split.occ);
@@ -509,8 +516,14 @@ extern "C" pv_status pv_create_volume(pv_ctx *ctx, const pv_volume_desc *d, pv_v
     if (st == PV_OK) st = dev_alloc(&v->wt.w, weight_table_floats(v->n) * 4, "blend weight table");
     if (st == PV_OK) st = dev_alloc(&v->wt.part, weight_part_floats(v->n) * 4, "blend weight sums");
     if (st == PV_OK && (d->flags & PV_KEEP_HITS)) st = dev_alloc(&v->hits, (size_t)v->P * v->n * 4, "hit ids");
-    if (st == PV_OK && (d->flags & PV_MULTI_BOUNCE))
+    if (st == PV_OK && (d->flags & (PV_MULTI_BOUNCE | PV_CLASSIFY)))
         st = dev_alloc(&v->hitrec, (size_t)v->P * v->n * sizeof(int2), "hit records");
+    if (st == PV_OK && (d->flags & PV_CLASSIFY)) {
+        st = dev_alloc(&v->active, (size_t)v->P, "probe activity");
+        // every probe counts as active until the first update classifies it
+        if (st == PV_OK && launch_fill_u8(v->active, (size_t)v->P, 1, ctx->stream) != hipSuccess)
+            st = fail(PV_ERR_DEVICE, "fill");
+    }
     if (st == PV_OK) st = dev_alloc(&v->queue, kQueueInts * sizeof(int), "work queues");
     if (st == PV_OK && launch_zero(v->wt.w, weight_table_floats(v->n) * 4, ctx->stream) != hipSuccess)
         st = fail(PV_ERR_DEVICE, "zero fill");  // the padding past n stays zero
@@ -640,7 +653,9 @@ extern "C" pv_status pv_update_probes(pv_volume *v, const pv_frame *f, void *str
     const int fp16 = v->desc.format == PV_MAP_FP16;
     const float h = effective_h(v);
     PV_TRY(enqueue_trace(v, fp, sv, nullptr, s));
-    if (v->hitrec)
+    if (v->active)
+        HIP_TRY(timed(c, PV_STAGE_SELECT, s, [&] { return launch_classify(vp, sv, v->dirs, v->active, s); }));
+    if (v->desc.flags & PV_MULTI_BOUNCE)
         HIP_TRY(timed(c, PV_STAGE_BOUNCE, s,
                       [&] { return launch_bounce(vp, sv, v->dirs, v->rays, v->irr, v->vis, fp16, s); }));
     HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend(vp, v->wt, v->rays, v->irr, v->vis, fp16, h, s); }));
@@ -794,7 +809,7 @@ struct pv_batch_graph {
     std::vector<pv_volume *> vols;
     BatchSlot slot;           // device descriptors + pinned staging owned by the graph
     size_t o_b = 0, o_f = 0, bytes = 0;
-    int waves = 0, blend = 0, bounce = 0, max_parts = 0;
+    int waves = 0, blend = 0, bounce = 0, classify = 0, max_parts = 0;
     bool short_stack = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -807,13 +822,14 @@ struct pv_batch_graph {
 // blocks of a volume, and whether every BVH of the batch fits 16-bit stack
 // entries.
 static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int n, char *h, size_t *offs, int &waves,
-                            int &blend, int &bounce, int &max_parts, bool &short_stack) {
+                            int &blend, int &bounce, int &classify, int &max_parts, bool &short_stack) {
     std::vector<BatchVolume> bv(n);
     std::vector<FrameParams> fps(n);
     std::memset(fps.data(), 0, sizeof(FrameParams) * n);
     waves = 0;
     blend = 0;
     bounce = 0;
+    classify = 0;
     max_parts = 0;
     short_stack = true;
     for (int i = 0; i < n; ++i) {
@@ -842,9 +858,13 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
         b.n_blend = (v->P + kBlendTile - 1) / kBlendTile * kBlendSplit;
         b.first_blend = blend;
         blend += b.n_blend;
-        b.n_bounce = v->hitrec ? bounce_blocks(v->P, v->n) : 0;
+        b.n_bounce = (v->desc.flags & PV_MULTI_BOUNCE) ? bounce_blocks(v->P, v->n) : 0;
         b.first_bounce = bounce;
         bounce += b.n_bounce;
+        b.active = v->active;
+        b.n_classify = v->active ? classify_blocks(v->P) : 0;
+        b.first_classify = classify;
+        classify += b.n_classify;
     }
     size_t off = 0;
     auto put = [&](const void *src, size_t bytes) {
@@ -885,16 +905,18 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
     HIP_TRY(hipEventSynchronize(slot.done));  // the slot's previous launch has finished
     PV_TRY(ensure_slot(c, slot, n));
     size_t offs[3];
-    int waves, blend, bounce, max_parts;
+    int waves, blend, bounce, classify, max_parts;
     bool short_stack;
     char *h = (char *)slot.stage_host;
-    PV_TRY(fill_batch(vols, frames, n, h, offs, waves, blend, bounce, max_parts, short_stack));
+    PV_TRY(fill_batch(vols, frames, n, h, offs, waves, blend, bounce, classify, max_parts, short_stack));
     HIP_TRY(hipMemcpyAsync(slot.batch_dev, h + offs[0], sizeof(BatchVolume) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(slot.frames_dev, h + offs[1], sizeof(FrameParams) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s,
                   [&] { return launch_raydirs_batched(slot.batch_dev, slot.frames_dev, n, max_parts, s); }));
     HIP_TRY(timed(c, PV_STAGE_BATCHED, s,
                   [&] { return launch_trace_batched(slot.batch_dev, n, waves, slot.frames_dev, short_stack, s); }));
+    if (classify > 0)
+        HIP_TRY(timed(c, PV_STAGE_SELECT, s, [&] { return launch_classify_batched(slot.batch_dev, n, classify, s); }));
     if (bounce > 0)
         HIP_TRY(timed(c, PV_STAGE_BOUNCE, s, [&] { return launch_bounce_batched(slot.batch_dev, n, bounce, s); }));
     HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend_batched(slot.batch_dev, n, blend, s); }));
@@ -931,7 +953,7 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
     size_t offs[3];
     if (st == PV_OK)
         st = fill_batch(vols, nullptr, n, (char *)g->slot.stage_host, offs, g->waves, g->blend, g->bounce,
-                        g->max_parts, g->short_stack);
+                        g->classify, g->max_parts, g->short_stack);
     if (st != PV_OK) {
         free_graph(g);
         return st;
@@ -949,6 +971,7 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
     if (e == hipSuccess) e = hipMemcpyAsync(b.frames_dev, h + g->o_f, sizeof(FrameParams) * n, hipMemcpyHostToDevice, cs);
     if (e == hipSuccess) e = launch_raydirs_batched(b.batch_dev, b.frames_dev, n, g->max_parts, cs);
     if (e == hipSuccess) e = launch_trace_batched(b.batch_dev, n, g->waves, b.frames_dev, g->short_stack, cs);
+    if (e == hipSuccess && g->classify > 0) e = launch_classify_batched(b.batch_dev, n, g->classify, cs);
     if (e == hipSuccess && g->bounce > 0) e = launch_bounce_batched(b.batch_dev, n, g->bounce, cs);
     if (e == hipSuccess) e = launch_blend_batched(b.batch_dev, n, g->blend, cs);
     hipGraph_t graph = nullptr;
@@ -980,11 +1003,12 @@ extern "C" pv_status pv_batch_graph_launch(pv_batch_graph *g, const pv_frame *fr
     // launch must have finished before it is rewritten
     if (g->launched) HIP_TRY(hipEventSynchronize(g->done));
     size_t offs[3];
-    int waves, blend, bounce, max_parts;
+    int waves, blend, bounce, classify, max_parts;
     bool short_stack;
-    PV_TRY(fill_batch(g->vols.data(), frames, n, (char *)g->slot.stage_host, offs, waves, blend, bounce, max_parts,
-                      short_stack));
-    if (waves != g->waves || blend != g->blend || bounce != g->bounce || short_stack != g->short_stack)
+    PV_TRY(fill_batch(g->vols.data(), frames, n, (char *)g->slot.stage_host, offs, waves, blend, bounce, classify,
+                      max_parts, short_stack));
+    if (waves != g->waves || blend != g->blend || bounce != g->bounce || classify != g->classify ||
+        short_stack != g->short_stack)
         return fail(PV_ERR_STATE, "a volume of the graph changed scene since the graph was captured");
     hipStream_t s = pick(c, stream);
     HIP_TRY(timed(c, PV_STAGE_BATCHED, s, [&] { return hipGraphLaunch(g->exec, s); }));
@@ -1012,7 +1036,7 @@ extern "C" pv_status pv_client_footprint(const pv_volume_desc *d, uint64_t *byte
     PV_TRY(validate_desc(d));
     if (!bytes) return fail(PV_ERR_ARG, "bytes is NULL");
     const uint64_t P = (uint64_t)d->nx * d->ny * d->nz;
-    *bytes = P * (192 + 512) * 2 + 2 * P + (P + kPackTile - 1) / kPackTile * 20 + 16 + packet_capacity((int)P);
+    *bytes = P * (192 + 512) * 2 + 3 * P + (P + kPackTile - 1) / kPackTile * 20 + 16 + packet_capacity((int)P);
     return PV_OK;
 }
 
@@ -1025,6 +1049,7 @@ static void free_client(pv_client *c) {
     hipFree(c->totals);
     hipFree(c->partial);
     hipFree(c->packet);
+    hipFree(c->view);
     if (c->hdr_host) hipHostFree(c->hdr_host);
     delete c;
 }
@@ -1047,6 +1072,7 @@ extern "C" pv_status pv_client_create(pv_volume *v, uint32_t id, pv_client **out
     if (st == PV_OK) st = dev_alloc(&c->totals, 4 * sizeof(uint32_t), "pack totals");
     if (st == PV_OK) st = dev_alloc(&c->partial, (size_t)(P + kPackTile - 1) / kPackTile * 4, "pack checksum shares");
     if (st == PV_OK) st = dev_alloc(&c->packet, c->packet_cap, "packet");
+    if (st == PV_OK) st = dev_alloc(&c->view, (size_t)P, "client view");
     if (st == PV_OK && hipHostMalloc((void **)&c->hdr_host, 32) != hipSuccess) st = fail(PV_ERR_OOM, "pinned header");
     hipStream_t s = v->ctx->stream;
     if (st == PV_OK && (launch_zero(c->ref_irr, (size_t)P * 192 * 2, s) != hipSuccess ||
@@ -1099,6 +1125,8 @@ extern "C" pv_status pv_pack_delta(pv_client *c, float tau_irr, float tau_vis, v
     b.totals = c->totals;
     b.partial = c->partial;
     b.packet = c->packet;
+    b.active = v->active;
+    b.view = c->view_on ? c->view : nullptr;
     pv_ctx *cx = v->ctx;
     const int P = v->P;
     const uint32_t id = c->id, seq = c->seq;
@@ -1357,5 +1385,45 @@ extern "C" pv_status pv_decode_yuv(pv_ctx *ctx, int n_probes, int tiles_per_row,
     HIP_TRY(timed(ctx, PV_STAGE_CODEC, s, [&] {
         return launch_yuv_decode(irr_planes, vis_planes, n_probes, tiles_per_row, irr_codes, vis, d, s);
     }));
+    return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// probe selection
+// ---------------------------------------------------------------------------
+extern "C" pv_status pv_get_active(pv_volume *v, const void **active_dev) {
+    if (!v || !active_dev) return fail(PV_ERR_ARG, "NULL argument");
+    if (!v->active) return fail(PV_ERR_STATE, "volume was created without PV_CLASSIFY");
+    *active_dev = v->active;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_client_set_view(pv_client *c, const float eye[3], int n_rays, void *stream) {
+    if (!c || !eye) return fail(PV_ERR_ARG, "NULL argument");
+    if (!finite_all(eye, 3)) return fail(PV_ERR_ARG, "eye must be finite");
+    if (n_rays < 1 || n_rays > (1 << 22)) return fail(PV_ERR_ARG, "n_rays must be in [1, 4194304]");
+    pv_volume *v = c->vol;
+    if (!v->scene) return fail(PV_ERR_STATE, "no scene set on the client's volume");
+    HIP_TRY(hipSetDevice(v->ctx->device));
+    hipStream_t s = pick(v->ctx, stream);
+    const VolumeParams vp = volume_params(v);
+    const SceneView sv = scene_view(v->scene);
+    HIP_TRY(launch_fill_u8(c->view, (size_t)v->P, 0, s));
+    HIP_TRY(timed(v->ctx, PV_STAGE_SELECT, s,
+                  [&] { return launch_client_view(vp, sv, eye[0], eye[1], eye[2], n_rays, c->view, s); }));
+    PV_TRY(note_scene_use(v->scene, s));
+    c->view_on = true;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_client_clear_view(pv_client *c) {
+    if (!c) return fail(PV_ERR_ARG, "NULL argument");
+    c->view_on = false;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_client_get_view(pv_client *c, const void **view_dev) {
+    if (!c || !view_dev) return fail(PV_ERR_ARG, "NULL argument");
+    *view_dev = c->view_on ? c->view : nullptr;
     return PV_OK;
 }

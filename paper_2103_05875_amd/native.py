@@ -21,6 +21,7 @@ PV_MAP_FP16 = 1
 PV_FIRST_FRAME_NO_HISTORY = 1
 PV_KEEP_HITS = 2
 PV_MULTI_BOUNCE = 4
+PV_CLASSIFY = 8
 PV_MAX_LIGHTS = 8
 
 # every symbol include/probestream.h declares
@@ -36,10 +37,11 @@ EXPORTED_SYMBOLS = [
     "pv_batch_graph_create", "pv_batch_graph_launch", "pv_batch_graph_destroy", "pv_probe_query",
     "pv_receiver_create", "pv_receiver_destroy", "pv_receiver_apply", "pv_receiver_status",
     "pv_receiver_get_maps", "pv_receiver_read_maps", "pv_yuv_dims", "pv_encode_yuv", "pv_decode_yuv",
+    "pv_get_active", "pv_client_set_view", "pv_client_clear_view", "pv_client_get_view",
 ]
 
 STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched", "shadow", "shade",
-          "pack_finish", "bounce", "unpack", "codec"]
+          "pack_finish", "bounce", "unpack", "codec", "select"]
 
 
 class NativeError(RuntimeError):
@@ -128,6 +130,10 @@ def lib():
         "pv_receiver_get_maps": ([vp, P(vp), P(vp)], i32),
         "pv_receiver_read_maps": ([vp, vp, vp], i32),
         "pv_yuv_dims": ([i32, i32, P(ctypes.c_int64)], i32),
+        "pv_get_active": ([vp, P(vp)], i32),
+        "pv_client_set_view": ([vp, P(f32), i32, vp], i32),
+        "pv_client_clear_view": ([vp], i32),
+        "pv_client_get_view": ([vp, P(vp)], i32),
         "pv_encode_yuv": ([vp, f32, i32, vp, vp, vp], i32),
         "pv_decode_yuv": ([vp, i32, i32, vp, vp, vp, vp, vp], i32),
         "pv_read_maps": ([vp, vp, vp, P(ctypes.c_int64)], i32),
@@ -345,7 +351,8 @@ def client_footprint(cfg) -> int:
 def desc_flags(cfg, keep_hits: bool = False) -> int:
     return ((PV_FIRST_FRAME_NO_HISTORY if cfg.first_frame_no_history else 0) |
             (PV_KEEP_HITS if keep_hits else 0) |
-            (PV_MULTI_BOUNCE if getattr(cfg, "multi_bounce", False) else 0))
+            (PV_MULTI_BOUNCE if getattr(cfg, "multi_bounce", False) else 0) |
+            (PV_CLASSIFY if getattr(cfg, "classify", False) else 0))
 
 
 class Volume:
@@ -437,6 +444,14 @@ class Volume:
         _check(lib().pv_probe_query(self.h, pts.data_ptr(), nrm.data_ptr(), pts.shape[0], out.data_ptr(),
                                     _stream_handle(stream)))
         return out
+
+    def read_active(self) -> np.ndarray:
+        """Probe activity of the last update, bool [P] (volumes created with
+        cfg.classify)."""
+        sync()
+        a = ctypes.c_void_p()
+        _check(lib().pv_get_active(self.h, ctypes.byref(a)))
+        return device_to_host(a.value, (self.P,), "uint8").astype(bool)
 
     def encode_yuv(self, irr_scale: float, tiles_per_row: int, stream=None):
         """Codec surfaces of the current maps: (irradiance planes [3, h, w]
@@ -555,6 +570,21 @@ class Client:
         rv = np.ascontiguousarray(ref_vis, np.uint16)
         assert ri.size == self.volume.P * 192 and rv.size == self.volume.P * 512
         _check(lib().pv_client_set_state(self.h, ri.ctypes.data, rv.ctypes.data, int(seq)))
+
+    def set_view(self, eye, n_rays: int = 4096, stream=None):
+        """Cull to the probes a spherical view from ``eye`` can see."""
+        e = (ctypes.c_float * 3)(*[float(v) for v in eye])
+        _check(lib().pv_client_set_view(self.h, e, int(n_rays), _stream_handle(stream)))
+
+    def clear_view(self):
+        _check(lib().pv_client_clear_view(self.h))
+
+    def read_view(self):
+        """The view mask, bool [P], or None when no view is set."""
+        sync()
+        a = ctypes.c_void_p()
+        _check(lib().pv_client_get_view(self.h, ctypes.byref(a)))
+        return None if not a.value else device_to_host(a.value, (self.volume.P,), "uint8").astype(bool)
 
     def read_masks(self):
         sync()

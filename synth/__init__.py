@@ -371,6 +371,7 @@ class VolumeConfig:
     sky: tuple = (0.0, 0.0, 0.0)
     first_frame_no_history: bool = True
     multi_bounce: bool = False
+    classify: bool = False
 
     @property
     def n_probes(self) -> int:
