@@ -87,6 +87,12 @@ def lib():
                                      ctypes.c_int, ctypes.c_int, ctypes.POINTER(_D), ctypes.c_double]
         L.or_probe_lookup.argtypes = [_D, ctypes.c_int, ctypes.c_int, _D, _D]
         L.or_yuv_dims.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+        L.or_huf_lengths.argtypes = [ctypes.POINTER(ctypes.c_uint64), _U8]
+        L.or_huf_codes.argtypes = [_U8, ctypes.POINTER(ctypes.c_uint32)]
+        L.or_huf_encode.argtypes = [_U8, _U8, ctypes.c_int64]
+        L.or_huf_encode.restype = ctypes.c_int64
+        L.or_huf_decode.argtypes = [_U8, ctypes.c_int64, _U8, ctypes.c_int64]
+        L.or_huf_decode.restype = ctypes.c_int64
         L.or_irr_code.argtypes = [ctypes.c_float, ctypes.c_float]
         L.or_irr_code.restype = ctypes.c_uint16
         L.or_yuv_encode.argtypes = [ctypes.c_int, ctypes.c_int, _D, _U16, ctypes.c_float, _U16, _U8]
@@ -457,6 +463,46 @@ def client_pvs(scene: "OracleScene", cfg, eye, n_rays: int, tol: float = 1e-5, d
         for x in alt.get(r, []):
             mark(hi, cells(x, True))
     return nom, lo, hi
+
+
+# --------------------------------------------------------------------------
+# entropy stage
+# --------------------------------------------------------------------------
+HUF_MAX_BITS = 12
+HUF_CHUNK = 4096
+
+
+def huf_lengths(hist) -> np.ndarray:
+    h = _c(hist, np.uint64)
+    assert h.size == 256
+    out = np.zeros(256, np.uint8)
+    lib().or_huf_lengths(h.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _p(out, _U8))
+    return out
+
+
+def huf_codes(lengths) -> np.ndarray:
+    ln = _c(lengths, np.uint8)
+    out = np.zeros(256, np.uint32)
+    lib().or_huf_codes(_p(ln, _U8), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    return out
+
+
+def huf_encode(packet: bytes) -> bytes:
+    a = np.frombuffer(packet, np.uint8).copy()
+    cap = 64 + 2 * len(packet) + 11 * (132 + 4 * (len(packet) // HUF_CHUNK + 2))
+    out = np.zeros(cap, np.uint8)
+    n = lib().or_huf_encode(_p(a, _U8), _p(out, _U8), cap)
+    assert n > 0
+    return out[:n].tobytes()
+
+
+def huf_decode(container: bytes, cap: int) -> bytes:
+    a = np.frombuffer(container, np.uint8).copy()
+    out = np.zeros(cap, np.uint8)
+    n = lib().or_huf_decode(_p(a, _U8), a.size, _p(out, _U8), cap)
+    if n < 0:
+        raise ValueError("malformed container")
+    return out[:n].tobytes()
 
 
 def border(tiles: np.ndarray) -> np.ndarray:

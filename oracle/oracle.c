@@ -1374,3 +1374,241 @@ OR_API void or_yuv_decode(int P, int C, const uint16_t *irr_planes, const uint8_
         }
     }
 }
+
+/* ======================================================================== */
+/* Entropy stage: canonical Huffman coding of the packet's byte streams      */
+/* ======================================================================== */
+/*
+ * Streams of a packet: 0 = the index section (2 (K_irr + K_vis) bytes, no
+ * padding), 1..6 = the irradiance planes (K_irr * 64 bytes each), 7..10 =
+ * the visibility planes (K_vis * 256 bytes each). Each stream gets its own
+ * code over byte symbols:
+ *   - code lengths by Huffman's algorithm over the symbols that occur,
+ *     merging the two lightest nodes first, leaves before internal nodes
+ *     on equal weight, leaves ordered by (count, symbol); a single symbol
+ *     gets length 1; if the longest code exceeds OR_HUF_MAX bits, every
+ *     count is halved (rounded up) and the lengths rebuilt;
+ *   - canonical codes: symbols sorted by (length, symbol), each code the
+ *     previous plus one, shifted left by the length difference;
+ *   - the stream is cut into chunks of OR_HUF_CHUNK symbols, each coded
+ *     most significant bit first and padded to a multiple of 32 bits.
+ * Container: u32 magic 0x43485650 ("PVHC"), u32 version 1, the 32-byte
+ * packet header, then per stream: u8 lengths[256] as 128 bytes of nibbles
+ * (symbol 2i in the low nibble), u32 n_chunks, u32 bits[n_chunks], then the
+ * chunks' 32-bit words, chunk after chunk (each word's bytes in big-endian
+ * order, i.e. the bit stream's byte order).
+ */
+#define OR_HUF_MAX 12
+#define OR_HUF_CHUNK 4096
+#define OR_HUF_STREAMS 11
+
+typedef struct {
+    int64_t w;
+    int sym;   /* leaf symbol, or -1 */
+    int a, b;  /* children (internal) */
+} or_hnode;
+
+static int cmp_leaf(const void *x, const void *y)
+{
+    const or_hnode *p = (const or_hnode *)x, *q = (const or_hnode *)y;
+    if (p->w != q->w) return p->w < q->w ? -1 : 1;
+    return p->sym - q->sym;
+}
+
+static void huf_depths(const or_hnode *nd, int i, int d, uint8_t *len)
+{
+    if (nd[i].sym >= 0) {
+        len[nd[i].sym] = (uint8_t)(d > 0 ? d : 1);
+        return;
+    }
+    huf_depths(nd, nd[i].a, d + 1, len);
+    huf_depths(nd, nd[i].b, d + 1, len);
+}
+
+/* Code lengths of a histogram (0 for absent symbols). */
+OR_API void or_huf_lengths(const uint64_t hist[256], uint8_t len[256])
+{
+    int64_t h[256];
+    for (int s = 0; s < 256; ++s) h[s] = (int64_t)hist[s];
+    for (;;) {
+        or_hnode nd[512];
+        int nl = 0;
+        for (int s = 0; s < 256; ++s)
+            if (h[s] > 0) {
+                nd[nl].w = h[s];
+                nd[nl].sym = s;
+                nd[nl].a = nd[nl].b = -1;
+                ++nl;
+            }
+        memset(len, 0, 256);
+        if (nl == 0) return;
+        qsort(nd, nl, sizeof(or_hnode), cmp_leaf);
+        /* two queues: leaves nd[0..nl), internal nodes appended after them */
+        int li = 0, ii = nl, ie = nl;
+        while ((nl - li) + (ie - ii) > 1) {
+            int pick[2];
+            for (int k = 0; k < 2; ++k) {
+                if (li < nl && (ii >= ie || nd[li].w <= nd[ii].w))
+                    pick[k] = li++;
+                else
+                    pick[k] = ii++;
+            }
+            nd[ie].w = nd[pick[0]].w + nd[pick[1]].w;
+            nd[ie].sym = -1;
+            nd[ie].a = pick[0];
+            nd[ie].b = pick[1];
+            ++ie;
+        }
+        huf_depths(nd, ie - 1, 0, len);
+        int mx = 0;
+        for (int s = 0; s < 256; ++s) mx = len[s] > mx ? len[s] : mx;
+        if (mx <= OR_HUF_MAX) return;
+        for (int s = 0; s < 256; ++s) h[s] = (h[s] + 1) / 2;
+    }
+}
+
+/* Canonical codes of a length table. */
+OR_API void or_huf_codes(const uint8_t len[256], uint32_t code[256])
+{
+    uint32_t c = 0;
+    int prev = 0, first = 1;
+    for (int L = 1; L <= OR_HUF_MAX; ++L)
+        for (int s = 0; s < 256; ++s)
+            if (len[s] == L) {
+                if (first) {
+                    c = 0;
+                    first = 0;
+                } else {
+                    c = (c + 1) << (L - prev);
+                }
+                prev = L;
+                code[s] = c;
+            }
+    for (int s = 0; s < 256; ++s)
+        if (!len[s]) code[s] = 0;
+}
+
+static void stream_span(const uint8_t *pkt, int k, const uint8_t **p, int64_t *n)
+{
+    const int64_t Ki = get_u32(pkt + 20), Kv = get_u32(pkt + 24);
+    const int64_t idx = (2 * (Ki + Kv) + 15) / 16 * 16;
+    if (k == 0) {
+        *p = pkt + 32;
+        *n = 2 * (Ki + Kv);
+    } else if (k <= 6) {
+        *p = pkt + 32 + idx + (int64_t)(k - 1) * Ki * 64;
+        *n = Ki * 64;
+    } else {
+        *p = pkt + 32 + idx + 6 * Ki * 64 + (int64_t)(k - 7) * Kv * 256;
+        *n = Kv * 256;
+    }
+}
+
+/* Encodes a packet; returns the container size (or -size needed when cap is
+ * too small). */
+OR_API int64_t or_huf_encode(const uint8_t *pkt, uint8_t *out, int64_t cap)
+{
+    int64_t total = 8 + 32;
+    uint8_t lens[OR_HUF_STREAMS][256];
+    uint32_t codes[OR_HUF_STREAMS][256];
+    for (int k = 0; k < OR_HUF_STREAMS; ++k) {
+        const uint8_t *p;
+        int64_t n;
+        stream_span(pkt, k, &p, &n);
+        uint64_t hist[256] = {0};
+        for (int64_t i = 0; i < n; ++i) hist[p[i]]++;
+        or_huf_lengths(hist, lens[k]);
+        or_huf_codes(lens[k], codes[k]);
+        const int64_t nch = (n + OR_HUF_CHUNK - 1) / OR_HUF_CHUNK;
+        total += 128 + 4 + 4 * nch;
+        for (int64_t c = 0; c < nch; ++c) {
+            int64_t bits = 0;
+            for (int64_t i = c * OR_HUF_CHUNK; i < n && i < (c + 1) * OR_HUF_CHUNK; ++i) bits += lens[k][p[i]];
+            total += (bits + 31) / 32 * 4;
+        }
+    }
+    if (total > cap) return -total;
+    memset(out, 0, total);
+    put_u32(out, 0x43485650u);
+    put_u32(out + 4, 1u);
+    memcpy(out + 8, pkt, 32);
+    uint8_t *w = out + 40;
+    for (int k = 0; k < OR_HUF_STREAMS; ++k) {
+        const uint8_t *p;
+        int64_t n;
+        stream_span(pkt, k, &p, &n);
+        for (int i = 0; i < 128; ++i) w[i] = (uint8_t)(lens[k][2 * i] | (lens[k][2 * i + 1] << 4));
+        w += 128;
+        const int64_t nch = (n + OR_HUF_CHUNK - 1) / OR_HUF_CHUNK;
+        put_u32(w, (uint32_t)nch);
+        uint8_t *bits_tab = w + 4;
+        w += 4 + 4 * nch;
+        for (int64_t c = 0; c < nch; ++c) {
+            int64_t bit = 0;
+            for (int64_t i = c * OR_HUF_CHUNK; i < n && i < (c + 1) * OR_HUF_CHUNK; ++i) {
+                const int L = lens[k][p[i]];
+                const uint32_t cd = codes[k][p[i]];
+                for (int b = L - 1; b >= 0; --b, ++bit)
+                    if ((cd >> b) & 1u) w[bit >> 3] |= (uint8_t)(0x80u >> (bit & 7));
+            }
+            put_u32(bits_tab + 4 * c, (uint32_t)bit);
+            w += (bit + 31) / 32 * 4;
+        }
+    }
+    return total;
+}
+
+/* Decodes a container back into the packet (its size from the header);
+ * returns the packet size, or -1 on a malformed container. */
+OR_API int64_t or_huf_decode(const uint8_t *in, int64_t bytes, uint8_t *pkt, int64_t cap)
+{
+    if (bytes < 40 || get_u32(in) != 0x43485650u || get_u32(in + 4) != 1u) return -1;
+    const uint8_t *hdr = in + 8;
+    const int64_t Ki = get_u32(hdr + 20), Kv = get_u32(hdr + 24);
+    const int64_t size = or_packet_bytes((int)Ki, (int)Kv, 8, 16);
+    if (size > cap) return -1;
+    memset(pkt, 0, size);
+    memcpy(pkt, hdr, 32);
+    const uint8_t *r = in + 40, *end = in + bytes;
+    for (int k = 0; k < OR_HUF_STREAMS; ++k) {
+        const uint8_t *p;
+        int64_t n;
+        stream_span(pkt, k, &p, &n);
+        uint8_t *dst = (uint8_t *)p;
+        if (r + 132 > end) return -1;
+        uint8_t len[256];
+        uint32_t code[256];
+        for (int i = 0; i < 128; ++i) {
+            len[2 * i] = r[i] & 15;
+            len[2 * i + 1] = r[i] >> 4;
+        }
+        or_huf_codes(len, code);
+        r += 128;
+        const int64_t nch = get_u32(r);
+        if (nch != (n + OR_HUF_CHUNK - 1) / OR_HUF_CHUNK) return -1;
+        const uint8_t *bits_tab = r + 4;
+        r += 4 + 4 * nch;
+        for (int64_t c = 0; c < nch; ++c) {
+            const int64_t nbits = get_u32(bits_tab + 4 * c);
+            if (r + (nbits + 31) / 32 * 4 > end) return -1;
+            int64_t bit = 0;
+            for (int64_t i = c * OR_HUF_CHUNK; i < n && i < (c + 1) * OR_HUF_CHUNK; ++i) {
+                /* read bit by bit until a code matches (plain prefix decoding) */
+                uint32_t acc = 0;
+                int L = 0, found = -1;
+                while (found < 0) {
+                    if (L >= OR_HUF_MAX || bit >= nbits) return -1;
+                    acc = (acc << 1) | ((r[bit >> 3] >> (7 - (bit & 7))) & 1u);
+                    ++bit;
+                    ++L;
+                    for (int s = 0; s < 256 && found < 0; ++s)
+                        if (len[s] == L && code[s] == acc) found = s;
+                }
+                dst[i] = (uint8_t)found;
+            }
+            r += (nbits + 31) / 32 * 4;
+        }
+    }
+    /* the index section's padding is zero by the packet format */
+    return size;
+}

@@ -939,3 +939,80 @@ def test_client_view_marks_the_cells_of_visible_points(O):
     assert np.array_equal(nom, z >= 2) and np.array_equal(lo, nom) and np.array_equal(hi, nom)
     empty = O.OracleScene(np.zeros((0, 3, 3), np.float32), np.zeros((0, 3), np.float32))
     assert not any(m.any() for m in O.client_pvs(empty, cfg, (1.5, 1.5, 0.2), 512))
+
+
+# ---------------------------------------------------------------- entropy stage
+def test_huffman_lengths_textbook_example(O):
+    """Frequencies 45, 13, 12, 16, 9, 5 (a-f) give the textbook optimal
+    code lengths 1, 3, 3, 3, 4, 4 (224 bits in all)."""
+    h = np.zeros(256, np.uint64)
+    h[[0, 1, 2, 3, 4, 5]] = [45, 13, 12, 16, 9, 5]
+    ln = O.huf_lengths(h)
+    assert ln[:6].tolist() == [1, 3, 3, 3, 4, 4] and not ln[6:].any()
+    assert int((ln.astype(np.int64) * h.astype(np.int64)).sum()) == 224
+
+
+def test_huffman_codes_are_canonical_and_prefix_free(O):
+    rng = np.random.default_rng(8)
+    h = np.zeros(256, np.uint64)
+    h[rng.choice(256, 40, replace=False)] = rng.integers(1, 10_000, 40)
+    ln = O.huf_lengths(h)
+    cd = O.huf_codes(ln)
+    used = np.nonzero(ln)[0]
+    assert abs(sum(2.0 ** -int(ln[s]) for s in used) - 1.0) < 1e-12      # complete code (Kraft equality)
+    words = [format(int(cd[s]), f"0{int(ln[s])}b") for s in used]
+    for i, a in enumerate(words):
+        for j, c in enumerate(words):
+            assert i == j or not c.startswith(a)
+    order = sorted(used, key=lambda s: (ln[s], s))                        # canonical: consecutive in (length, symbol)
+    for a, c in zip(order, order[1:]):
+        assert int(cd[c]) == (int(cd[a]) + 1) << (int(ln[c]) - int(ln[a]))
+    one = np.zeros(256, np.uint64)
+    one[7] = 3
+    assert O.huf_lengths(one)[7] == 1
+
+
+def test_huffman_length_limit(O):
+    """Fibonacci frequencies force a 30-level tree; the counts are halved
+    until the longest code fits 12 bits, and the code stays complete."""
+    h = np.zeros(256, np.uint64)
+    f = [1, 1]
+    while len(f) < 30:
+        f.append(f[-1] + f[-2])
+    h[:30] = f
+    ln = O.huf_lengths(h)
+    assert ln.max() == 12 and (ln[:30] > 0).all()
+    assert abs(sum(2.0 ** -int(ln[s]) for s in range(30)) - 1.0) < 1e-12
+
+
+def test_entropy_round_trip_and_size(O):
+    """A real packet: decode(encode) gives it back byte for byte, and the
+    container size follows the layout: 40 bytes + per stream 132 bytes + 4
+    per chunk + each chunk's sum of code lengths rounded up to 32 bits."""
+    P = 300
+    cur_i, cur_v = synth.random_fp16_maps(P, 8, 16, seed=3)
+    ref_i, ref_v = synth.perturb_fp16_maps(cur_i, cur_v, seed=4, p_probe=0.5, p_texel=0.1, rel=2e-3)
+    st = O.OracleClientState(P)
+    st.ref_irr[:] = ref_i[:, :, 1:-1, 1:-1].reshape(P, 3, -1)
+    st.ref_vis[:] = ref_v[:, :, 1:-1, 1:-1].reshape(P, 2, -1)
+    pkt, mi, mv = st.pack(cur_i, cur_v)
+    enc = O.huf_encode(pkt)
+    assert O.huf_decode(enc, len(pkt) + 64) == pkt
+    d = _parse(pkt)
+    Ki, Kv = int(d["Ki"]), int(d["Kv"])
+    buf = np.frombuffer(pkt, np.uint8)
+    idx_pad = -(-2 * (Ki + Kv) // 16) * 16
+    streams = [buf[32:32 + 2 * (Ki + Kv)]]
+    off = 32 + idx_pad
+    streams += [buf[off + k * Ki * 64: off + (k + 1) * Ki * 64] for k in range(6)]
+    off += 6 * Ki * 64
+    streams += [buf[off + k * Kv * 256: off + (k + 1) * Kv * 256] for k in range(4)]
+    size = 40
+    for s in streams:
+        ln = O.huf_lengths(np.bincount(s, minlength=256).astype(np.uint64)).astype(np.int64)
+        nch = -(-s.size // 4096)
+        size += 132 + 4 * nch
+        for c in range(nch):
+            size += -(-int(ln[s[c * 4096:(c + 1) * 4096]].sum()) // 32) * 4
+    assert len(enc) == size
+    assert len(enc) < len(pkt)            # XOR planes of small changes are mostly zero bytes
