@@ -343,10 +343,11 @@ def leg_served(ps, duration_s: float, rate_hz: float = 2000.0, budget_frac: floa
 def leg_encode(ps, torch, frames: int):
     """Encode path: 32x16x32 = 16,384 probes, 256 rays, 200k-triangle field
     with 4 moving occluders and a moving light; each frame updates and packs
-    with tau = 1/1024 for both textures, and a receiver (the client side)
-    applies every packet on the device; the receiver's tiles equal the
-    server's record of what the client holds at every 20th frame. Pack
-    throughput against HBM."""
+    with tau = 1/1024 for both textures, entropy-codes the packet on the
+    device, and a receiver (the client side) decodes and applies every
+    container on the device; the receiver's tiles equal the server's record
+    of what the client holds at every 20th frame. Pack throughput against
+    HBM; packet and coded sizes."""
     import synth
     cfg = synth.config("encode")
     scene_syn = synth.box_field(200_000, seed=40, n_moving=4)
@@ -360,7 +361,7 @@ def leg_encode(ps, torch, frames: int):
     stream = torch.cuda.current_stream()
     ctx.set_timing(True)
     ctx.stage_times()
-    sent_bytes, changed, ok = 0, [], True
+    sent_bytes, coded_bytes, changed, ok = 0, 0, [], True
     for f in range(frames):
         sc.set_dynamic(synth.moving_occluders(40, f, 4), stream=stream)
         l = scene_syn.lights.copy()
@@ -369,7 +370,10 @@ def leg_encode(ps, torch, frames: int):
         cl.pack_delta(1.0 / 1024, 1.0 / 1024, stream=stream)
         pkt = cl.packet_download(stream=stream)
         sent_bytes += len(pkt)
-        rx.apply(pkt, stream=stream)
+        cl.entropy_encode(stream=stream)
+        coded = cl.entropy_download(stream=stream)
+        coded_bytes += len(coded)
+        rx.apply_compressed(coded, stream=stream)
         if f % 20 == 19 or f == frames - 1:
             ok &= rx.status() == (0, f)
             ri, rv, _ = cl.read_state()
@@ -388,7 +392,11 @@ def leg_encode(ps, torch, frames: int):
     upd_ms = (st["raydirs"][0] + st["trace"][0] + st["blend"][0]) / frames
     per_kernel = {k: st[k][0] / max(st[k][1], 1) for k in ("pack_mask", "pack_scan", "pack_compact", "pack_finish", "trace", "blend")}
     out = {"probes": P, "frames": frames, "round_trip_bit_exact": bool(ok),
-           "client_unpack_ms": st["unpack"][0] / frames, "mean_changed_irr": ki,
+           "entropy_encode_ms": st["entropy"][0] / frames,
+           "client_decode_and_unpack_ms": st["unpack"][0] / frames,
+           "coded_bytes_per_frame": coded_bytes / frames,
+           "coded_Mbps_at_10Hz": coded_bytes / frames * 8 * 10 / 1e6,
+           "entropy_ratio": sent_bytes / max(coded_bytes, 1), "mean_changed_irr": ki,
            "kernel_ms": per_kernel,
            "mean_changed_vis": kv, "packet_bytes_per_frame": sent_bytes / frames,
            "Mbps_at_10Hz": sent_bytes / frames * 8 * 10 / 1e6,
@@ -479,11 +487,15 @@ def leg_selection(ps, torch, cfg, scene, frames, trace_config):
     ctx.stage_times()
     a.set_view(eye, 16384, stream=stream)
     view_ms = ctx.stage_times()["select"][0]
-    sent_a, sent_b = [], []
+    sent_a, sent_b, bytes_a, coded_a = [], [], [], []
     for i, (R, l) in enumerate(frames):
         vol.update_probes(R, l, stream=stream)
         a.pack_delta(0.0, 0.0, stream=stream)
         ma = [m.sum() for m in a.read_masks()]
+        if i > 0:
+            bytes_a.append(len(a.packet_download(stream=stream)))
+            a.entropy_encode(stream=stream)
+            coded_a.append(len(a.entropy_download(stream=stream)))
         bcl.pack_delta(0.0, 0.0, stream=stream)
         mb = [m.sum() for m in bcl.read_masks()]
         if i > 0:   # frame 0 sends the initial state
@@ -500,7 +512,10 @@ def leg_selection(ps, torch, cfg, scene, frames, trace_config):
            "classify_ms": st["select"][0] / max(st["select"][1], 1),
            "sent_per_frame_view": {"irr": float(sa[0]), "vis": float(sa[1])},
            "sent_per_frame_all_active": {"irr": float(sb[0]), "vis": float(sb[1])},
-           "reduction_vs_active": 1.0 - float((sa[0] + sa[1]) / max(2 * active.sum(), 1))}
+           "reduction_vs_active": 1.0 - float((sa[0] + sa[1]) / max(2 * active.sum(), 1)),
+           "view_packet_Mbps_at_10Hz": float(np.mean(bytes_a)) * 8 * 10 / 1e6,
+           "view_coded_Mbps_at_10Hz": float(np.mean(coded_a)) * 8 * 10 / 1e6,
+           "view_coded_Mbps_at_60Hz": float(np.mean(coded_a)) * 8 * 60 / 1e6}
     for h in (a, bcl, vol, sc, ctx):
         h.close()
     return out

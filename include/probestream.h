@@ -342,6 +342,34 @@ pv_status pv_receiver_get_maps(pv_receiver *rcv, void **irr_dev, void **vis_dev)
 pv_status pv_receiver_read_maps(pv_receiver *rcv, void *irr_host, void *vis_host);
 
 /*
+ * Entropy stage (lossless; the paper's own stage is HEVC, not built here):
+ * the client's last packet coded on the device with a canonical Huffman
+ * code per byte stream -- stream 0 the index section (2 (K_irr + K_vis)
+ * bytes, no padding), 1..6 the irradiance planes, 7..10 the visibility
+ * planes. Per stream: code lengths by Huffman's algorithm over the byte
+ * values that occur (the two lightest nodes merged first, leaves before
+ * internal nodes on equal weight, leaves ordered by (count, value)), limited
+ * to 12 bits by halving every count (rounded up) and rebuilding; canonical
+ * codes in (length, value) order; the stream cut into chunks of 1,024 bytes,
+ * each coded most significant bit first and padded to 32 bits.
+ * Container (little endian): u32 0x43485650 ("PVHC"), u32 version 1, the
+ * 32-byte packet header, then per stream 128 bytes of code lengths (value
+ * 2i in the low nibble of byte i), u32 n_chunks, u32 bits[n_chunks], and
+ * the chunks' bytes.
+ * pv_entropy_encode: after pv_pack_delta, on 'stream'; returns once the
+ *   histograms are on the host (it waits for the stream up to that point;
+ *   the code tables are built on the host) with the coding kernels queued.
+ * pv_entropy_download: synchronous; PV_ERR_CAPACITY (with *bytes set) when
+ *   cap is too small; PV_ERR_STATE before the first encode.
+ * pv_receiver_apply_compressed: decodes a container on the device and
+ *   applies the packet as pv_receiver_apply does (same checks and status);
+ *   container structure errors: PV_ERR_ARG at once.
+ */
+pv_status pv_entropy_encode(pv_client *client, void *stream);
+pv_status pv_entropy_download(pv_client *client, void *host_buf, uint64_t cap, uint64_t *bytes, void *stream);
+pv_status pv_receiver_apply_compressed(pv_receiver *rcv, const void *container, uint64_t bytes, void *stream);
+
+/*
  * Codec surfaces (Sec. 3.3): a volume's textures as the planes a lossless
  * video encoder takes, and back. Probe p occupies atlas tile
  * (p % tiles_per_row, p / tiles_per_row); guard bands are left out; tiles
@@ -414,7 +442,8 @@ typedef enum {
     PV_STAGE_UNPACK = 11,
     PV_STAGE_CODEC = 12,
     PV_STAGE_SELECT = 13,
-    PV_STAGE_COUNT = 14
+    PV_STAGE_ENTROPY = 14,
+    PV_STAGE_COUNT = 15
 } pv_stage;
 
 /* When enabled, every kernel launch of the context is bracketed by a pair

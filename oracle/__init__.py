@@ -469,7 +469,7 @@ def client_pvs(scene: "OracleScene", cfg, eye, n_rays: int, tol: float = 1e-5, d
 # entropy stage
 # --------------------------------------------------------------------------
 HUF_MAX_BITS = 12
-HUF_CHUNK = 4096
+HUF_CHUNK = 1024
 
 
 def huf_lengths(hist) -> np.ndarray:

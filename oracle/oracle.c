@@ -1399,7 +1399,7 @@ OR_API void or_yuv_decode(int P, int C, const uint16_t *irr_planes, const uint8_
  * order, i.e. the bit stream's byte order).
  */
 #define OR_HUF_MAX 12
-#define OR_HUF_CHUNK 4096
+#define OR_HUF_CHUNK 1024
 #define OR_HUF_STREAMS 11
 
 typedef struct {

@@ -129,6 +129,39 @@ hipError_t launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t s);
 int classify_blocks(int P);
 hipError_t launch_classify_batched(const BatchVolume *vols_dev, int n_vols, int total_blocks, hipStream_t s);
 
+// Entropy stage (entropy.hip).
+constexpr int kEntStreams = 11;  // index section, 6 irradiance planes, 4 visibility planes
+struct EntBuffers {
+    const uint8_t *pkt;      // the packet (its header gives the stream sizes)
+    uint32_t *hist;          // [11][256], zeroed before the histogram
+    uint8_t *lens;           // [11][256]
+    uint32_t *codes;         // [11][256]
+    uint32_t *chunk_bits;    // [11][max_chunks]
+    unsigned long long *chunk_off;  // [11][max_chunks] byte offsets in the container
+    unsigned long long *total;      // container bytes
+    uint8_t *out;            // the container
+    int max_chunks;          // chunks of the longest possible stream
+};
+struct EntChunk {
+    int stream, n_sym;
+    unsigned int bits;
+    unsigned long long in_off, out_off;  // container / packet byte offsets
+};
+struct EntBlock {
+    int stream, first, n;    // up to 64 consecutive chunks of one stream
+};
+struct EntDecode {
+    const uint8_t *in;       // the container
+    unsigned long long stream_base[kEntStreams];  // offsets of the streams' tables
+    const EntChunk *chunks;
+    const EntBlock *blocks;
+    int n_blocks;
+    uint8_t *pkt;            // decoded packet (index padding cleared by the host)
+};
+hipError_t launch_entropy_hist(const EntBuffers &e, int max_chunks, hipStream_t s);
+hipError_t launch_entropy_encode(const EntBuffers &e, int max_chunks, hipStream_t s);  // after the tables
+hipError_t launch_entropy_decode(const EntDecode &d, hipStream_t s);
+
 // Codec surfaces (yuv.hip): plane sizes for P probes, C tiles per atlas row.
 struct YuvDims {
     long long w, h;    // irradiance planes (samples)

@@ -1,7 +1,7 @@
 // C ABI of the probe-volume library: handles, validation, device memory,
 // launch sequencing. Kernels live in trace.hip, blend.hip, batched.hip,
-// bounce.hip, select.hip, pack.hip, receive.hip and yuv.hip, the BVH builder
-// in bvh.cpp.
+// bounce.hip, select.hip, pack.hip, entropy.hip, receive.hip and yuv.hip,
+// the BVH builder in bvh.cpp.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -139,6 +139,11 @@ struct pv_client {
     uint32_t *hdr_host = nullptr;  // pinned, 32 bytes
     uint8_t *view = nullptr;       // [P] visible set of the last pv_client_set_view
     bool view_on = false;
+    // entropy stage (allocated on first use)
+    EntBuffers ent = {};
+    uint64_t ent_cap = 0;
+    unsigned long long *ent_total_host = nullptr;  // pinned
+    uint8_t *ent_tables_host = nullptr;            // pinned: histograms, then lengths and codes
 };
 
 // NULL is HIP's default stream, as in the HIP API itself.
@@ -1050,6 +1055,15 @@ static void free_client(pv_client *c) {
     hipFree(c->partial);
     hipFree(c->packet);
     hipFree(c->view);
+    hipFree(c->ent.hist);
+    hipFree(c->ent.lens);
+    hipFree(c->ent.codes);
+    hipFree(c->ent.chunk_bits);
+    hipFree(c->ent.chunk_off);
+    hipFree(c->ent.total);
+    hipFree(c->ent.out);
+    if (c->ent_total_host) hipHostFree(c->ent_total_host);
+    if (c->ent_tables_host) hipHostFree(c->ent_tables_host);
     if (c->hdr_host) hipHostFree(c->hdr_host);
     delete c;
 }
@@ -1212,6 +1226,14 @@ struct pv_receiver {
     bool used = false;
     uint32_t checksum = 0, seq = 0, last_seq = 0;
     bool pending = false;
+    // compressed packets: device container, chunk list and decode tables;
+    // pinned staging of the container and chunk list
+    uint8_t *ent_in = nullptr;
+    EntChunk *ent_chunks = nullptr;
+    EntBlock *ent_blocks = nullptr;
+    uint64_t ent_in_cap = 0, ent_chunk_cap = 0, ent_block_cap = 0;
+    uint8_t *ent_stage = nullptr;
+    uint64_t ent_stage_cap = 0;
 };
 
 static void free_receiver(pv_receiver *r) {
@@ -1220,6 +1242,10 @@ static void free_receiver(pv_receiver *r) {
     hipFree(r->idx);
     hipFree(r->status);
     hipFree(r->pkt);
+    hipFree(r->ent_in);
+    hipFree(r->ent_chunks);
+    hipFree(r->ent_blocks);
+    if (r->ent_stage) hipHostFree(r->ent_stage);
     if (r->stage) hipHostFree(r->stage);
     if (r->copied) hipEventDestroy(r->copied);
     if (r->done) hipEventDestroy(r->done);
@@ -1267,27 +1293,22 @@ static uint32_t get_u32(const uint8_t *p) {
     return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
 }
 
-extern "C" pv_status pv_receiver_apply(pv_receiver *r, const void *packet, uint64_t bytes, void *stream) {
-    if (!r || !packet) return fail(PV_ERR_ARG, "NULL argument");
-    const uint8_t *h = (const uint8_t *)packet;
-    if (bytes < (uint64_t)kPacketHeader) return fail(PV_ERR_ARG, "packet shorter than its header");
+// Header of a packet for receiver r: magic, version, probe count, sent
+// counts; returns the packet size in *size.
+static pv_status check_packet_header(const pv_receiver *r, const uint8_t *h, uint64_t *size) {
     if (get_u32(h + 4 * kHdrMagic) != kPacketMagic) return fail(PV_ERR_ARG, "not a probe packet (magic)");
     if (get_u32(h + 4 * kHdrVersion) != kPacketVersion) return fail(PV_ERR_UNSUPPORTED, "packet version");
     if (get_u32(h + 4 * kHdrProbes) != (uint32_t)r->P) return fail(PV_ERR_ARG, "packet is for another probe count");
     const uint32_t K_irr = get_u32(h + 4 * kHdrKIrr), K_vis = get_u32(h + 4 * kHdrKVis);
     if (K_irr > (uint32_t)r->P || K_vis > (uint32_t)r->P) return fail(PV_ERR_ARG, "more sent probes than probes");
-    if (bytes != packet_bytes(K_irr, K_vis)) return fail(PV_ERR_ARG, "packet size does not match its header");
-    HIP_TRY(hipSetDevice(r->ctx->device));
-    hipStream_t s = pick(r->ctx, stream);
-    // the staging buffer is free once the previous copy has run; the device
-    // packet buffer once the previous unpack has (ordered on this stream)
-    if (r->used) {
-        HIP_TRY(hipEventSynchronize(r->copied));
-        HIP_TRY(hipStreamWaitEvent(s, r->done, 0));
-    }
-    std::memcpy(r->stage, packet, bytes);
-    HIP_TRY(hipMemcpyAsync(r->pkt, r->stage, bytes, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipEventRecord(r->copied, s));
+    *size = packet_bytes(K_irr, K_vis);
+    return PV_OK;
+}
+
+// Verifies and applies the packet now in r->pkt (ordered on s), header h.
+static pv_status receive_on_device(pv_receiver *r, const uint8_t *h, hipStream_t s) {
+    const uint32_t K_irr = get_u32(h + 4 * kHdrKIrr), K_vis = get_u32(h + 4 * kHdrKVis);
+    const uint64_t bytes = packet_bytes(K_irr, K_vis);
     RxBuffers b;
     b.pkt = r->pkt;
     b.P = r->P;
@@ -1306,6 +1327,27 @@ extern "C" pv_status pv_receiver_apply(pv_receiver *r, const void *packet, uint6
     r->seq = get_u32(h + 4 * kHdrSeq);
     r->pending = true;
     return PV_OK;
+}
+
+extern "C" pv_status pv_receiver_apply(pv_receiver *r, const void *packet, uint64_t bytes, void *stream) {
+    if (!r || !packet) return fail(PV_ERR_ARG, "NULL argument");
+    const uint8_t *h = (const uint8_t *)packet;
+    if (bytes < (uint64_t)kPacketHeader) return fail(PV_ERR_ARG, "packet shorter than its header");
+    uint64_t size = 0;
+    PV_TRY(check_packet_header(r, h, &size));
+    if (bytes != size) return fail(PV_ERR_ARG, "packet size does not match its header");
+    HIP_TRY(hipSetDevice(r->ctx->device));
+    hipStream_t s = pick(r->ctx, stream);
+    // the staging buffer is free once the previous copy has run; the device
+    // packet buffer once the previous unpack has (ordered on this stream)
+    if (r->used) {
+        HIP_TRY(hipEventSynchronize(r->copied));
+        HIP_TRY(hipStreamWaitEvent(s, r->done, 0));
+    }
+    std::memcpy(r->stage, packet, bytes);
+    HIP_TRY(hipMemcpyAsync(r->pkt, r->stage, bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(r->copied, s));
+    return receive_on_device(r, h, s);
 }
 
 extern "C" pv_status pv_receiver_status(pv_receiver *r, int *result, uint32_t *seq) {
@@ -1426,4 +1468,230 @@ extern "C" pv_status pv_client_get_view(pv_client *c, const void **view_dev) {
     if (!c || !view_dev) return fail(PV_ERR_ARG, "NULL argument");
     *view_dev = c->view_on ? c->view : nullptr;
     return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// entropy stage
+// ---------------------------------------------------------------------------
+static constexpr int kHufChunk = 1024;
+static constexpr uint32_t kContainerMagic = 0x43485650u;  // "PVHC"
+
+static int max_chunks_of(int P) { return (int)(((int64_t)P * kVisPlaneBytes + kHufChunk - 1) / kHufChunk); }
+
+// Huffman code lengths of one histogram: the two lightest nodes merged
+// first, a leaf before an internal node of equal weight, leaves in (count,
+// value) order; a lone symbol gets length 1; while the longest code exceeds
+// 12 bits every count is halved (rounded up) and the lengths rebuilt.
+static void huffman_lengths(const uint32_t *hist, uint8_t *len) {
+    std::vector<uint64_t> cnt(hist, hist + 256);
+    for (;;) {
+        std::vector<std::pair<uint64_t, int>> leaves;
+        for (int v = 0; v < 256; ++v)
+            if (cnt[v]) leaves.push_back({cnt[v], v});
+        std::memset(len, 0, 256);
+        const int n = (int)leaves.size();
+        if (n == 0) return;
+        if (n == 1) {
+            len[leaves[0].second] = 1;
+            return;
+        }
+        std::sort(leaves.begin(), leaves.end());
+        // nodes 0..n-1 are the leaves, n.. the merged nodes in creation order
+        std::vector<uint64_t> w(2 * n);
+        std::vector<int> parent(2 * n, -1);
+        for (int i = 0; i < n; ++i) w[i] = leaves[i].first;
+        int li = 0, mi = n, me = n;
+        while ((n - li) + (me - mi) > 1) {
+            int pick[2];
+            for (int &pk : pick) pk = (li < n && (mi >= me || w[li] <= w[mi])) ? li++ : mi++;
+            w[me] = w[pick[0]] + w[pick[1]];
+            parent[pick[0]] = parent[pick[1]] = me;
+            ++me;
+        }
+        std::vector<int> depth(me, 0);
+        for (int i = me - 2; i >= 0; --i) depth[i] = depth[parent[i]] + 1;
+        int longest = 0;
+        for (int i = 0; i < n; ++i) {
+            len[leaves[i].second] = (uint8_t)depth[i];
+            longest = std::max(longest, depth[i]);
+        }
+        if (longest <= 12) return;
+        for (auto &x : cnt) x = (x + 1) / 2;
+    }
+}
+
+// Canonical codes: in (length, value) order, each code the previous one plus
+// one, shifted left by the length difference.
+static void canonical_codes_host(const uint8_t *len, uint32_t *code) {
+    uint32_t c = 0;
+    int prev = 0;
+    bool first = true;
+    for (int L = 1; L <= 12; ++L)
+        for (int v = 0; v < 256; ++v)
+            if (len[v] == L) {
+                c = first ? 0u : (c + 1u) << (L - prev);
+                first = false;
+                prev = L;
+                code[v] = c;
+            }
+    for (int v = 0; v < 256; ++v)
+        if (!len[v]) code[v] = 0;
+}
+
+extern "C" pv_status pv_entropy_encode(pv_client *c, void *stream) {
+    if (!c) return fail(PV_ERR_ARG, "client is NULL");
+    pv_volume *v = c->vol;
+    HIP_TRY(hipSetDevice(v->ctx->device));
+    hipStream_t s = pick(v->ctx, stream);
+    const int mc = max_chunks_of(v->P);
+    if (!c->ent.out) {
+        c->ent.max_chunks = mc;
+        // worst case: 12 bits per byte, plus tables and per-chunk padding
+        c->ent_cap = 8 + kPacketHeader + (uint64_t)kEntStreams * (132 + 8ull * mc) + c->packet_cap * 3 / 2 + 64;
+        PV_TRY(dev_alloc(&c->ent.hist, kEntStreams * 256 * sizeof(uint32_t), "entropy histograms"));
+        PV_TRY(dev_alloc(&c->ent.lens, kEntStreams * 256, "code lengths"));
+        PV_TRY(dev_alloc(&c->ent.codes, kEntStreams * 256 * sizeof(uint32_t), "codes"));
+        PV_TRY(dev_alloc(&c->ent.chunk_bits, (size_t)kEntStreams * mc * sizeof(uint32_t), "chunk bits"));
+        PV_TRY(dev_alloc(&c->ent.chunk_off, (size_t)kEntStreams * mc * sizeof(unsigned long long), "chunk offsets"));
+        PV_TRY(dev_alloc(&c->ent.total, sizeof(unsigned long long), "container size"));
+        PV_TRY(dev_alloc(&c->ent.out, c->ent_cap, "container"));
+        if (hipHostMalloc((void **)&c->ent_total_host, sizeof(unsigned long long)) != hipSuccess)
+            return fail(PV_ERR_OOM, "pinned container size");
+        if (hipHostMalloc((void **)&c->ent_tables_host, kEntStreams * 256 * (4 + 1 + 4)) != hipSuccess)
+            return fail(PV_ERR_OOM, "pinned code tables");
+    }
+    c->ent.pkt = c->packet;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(c->ent_tables_host);
+    uint8_t *lens = c->ent_tables_host + kEntStreams * 256 * 4;
+    uint32_t *codes = reinterpret_cast<uint32_t *>(lens + kEntStreams * 256);
+    HIP_TRY(launch_zero(c->ent.hist, kEntStreams * 256 * sizeof(uint32_t), s));
+    HIP_TRY(timed(v->ctx, PV_STAGE_ENTROPY, s, [&] { return launch_entropy_hist(c->ent, mc, s); }));
+    HIP_TRY(hipMemcpyAsync(hist, c->ent.hist, kEntStreams * 256 * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < kEntStreams; ++k) {
+        huffman_lengths(hist + 256 * k, lens + 256 * k);
+        canonical_codes_host(lens + 256 * k, codes + 256 * k);
+    }
+    HIP_TRY(hipMemcpyAsync(c->ent.lens, lens, kEntStreams * 256, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c->ent.codes, codes, kEntStreams * 256 * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(timed(v->ctx, PV_STAGE_ENTROPY, s, [&] { return launch_entropy_encode(c->ent, mc, s); }));
+    return PV_OK;
+}
+
+extern "C" pv_status pv_entropy_download(pv_client *c, void *host, uint64_t cap, uint64_t *bytes, void *stream) {
+    if (!c || !bytes) return fail(PV_ERR_ARG, "NULL argument");
+    if (!c->ent.out) return fail(PV_ERR_STATE, "no packet has been entropy coded");
+    HIP_TRY(hipSetDevice(c->vol->ctx->device));
+    hipStream_t s = pick(c->vol->ctx, stream);
+    HIP_TRY(hipMemcpyAsync(c->ent_total_host, c->ent.total, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t total = *c->ent_total_host;
+    *bytes = total;
+    if (!host || cap < total) return fail(PV_ERR_CAPACITY, "container needs " + std::to_string(total) + " bytes");
+    HIP_TRY(hipMemcpyAsync(host, c->ent.out, total, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PV_OK;
+}
+
+template <typename T>
+static pv_status grow(T **p, uint64_t &cap, uint64_t need, const char *what) {
+    if (need <= cap) return PV_OK;
+    hipFree(*p);
+    *p = nullptr;
+    cap = 0;
+    PV_TRY(dev_alloc(p, need * sizeof(T), what));
+    cap = need;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_receiver_apply_compressed(pv_receiver *r, const void *container, uint64_t bytes, void *stream) {
+    if (!r || !container) return fail(PV_ERR_ARG, "NULL argument");
+    const uint8_t *in = (const uint8_t *)container;
+    if (bytes < 8 + (uint64_t)kPacketHeader) return fail(PV_ERR_ARG, "container shorter than its header");
+    if (get_u32(in) != kContainerMagic) return fail(PV_ERR_ARG, "not a compressed probe packet (magic)");
+    if (get_u32(in + 4) != 1u) return fail(PV_ERR_UNSUPPORTED, "container version");
+    const uint8_t *h = in + 8;
+    uint64_t size = 0;
+    PV_TRY(check_packet_header(r, h, &size));
+    const uint64_t Ki = get_u32(h + 4 * kHdrKIrr), Kv = get_u32(h + 4 * kHdrKVis);
+    const uint64_t idx = packet_index_bytes(Ki, Kv);
+    // the container's structure, from its tables
+    std::vector<EntChunk> chunks;
+    std::vector<EntBlock> blocks;
+    EntDecode d;
+    uint64_t off = 8 + kPacketHeader;
+    for (int k = 0; k < kEntStreams; ++k) {
+        uint64_t start, n;
+        if (k == 0) {
+            start = kPacketHeader;
+            n = 2 * (Ki + Kv);
+        } else if (k <= kIrrPlanes) {
+            start = kPacketHeader + idx + (k - 1) * Ki * kIrrPlaneBytes;
+            n = Ki * kIrrPlaneBytes;
+        } else {
+            start = kPacketHeader + idx + kIrrPlanes * Ki * kIrrPlaneBytes + (k - 1 - kIrrPlanes) * Kv * kVisPlaneBytes;
+            n = Kv * kVisPlaneBytes;
+        }
+        const uint64_t nch = (n + kHufChunk - 1) / kHufChunk;
+        if (off + 132 + 4 * nch > bytes) return fail(PV_ERR_ARG, "container truncated (tables)");
+        d.stream_base[k] = off;
+        for (int i = 0; i < 128; ++i)
+            if ((in[off + i] & 15) > 12 || (in[off + i] >> 4) > 12) return fail(PV_ERR_ARG, "code length above 12 bits");
+        if (get_u32(in + off + 128) != nch) return fail(PV_ERR_ARG, "chunk count does not match the header");
+        const uint8_t *bits_tab = in + off + 132;
+        off += 132 + 4 * nch;
+        for (uint64_t c = 0; c < nch; c += 64)
+            blocks.push_back(EntBlock{k, (int)(chunks.size() + c), (int)std::min<uint64_t>(64, nch - c)});
+        for (uint64_t c = 0; c < nch; ++c) {
+            const uint32_t bits = get_u32(bits_tab + 4 * c);
+            const uint64_t n_sym = std::min<uint64_t>(kHufChunk, n - c * kHufChunk);
+            if (bits < n_sym || bits > 12 * n_sym) return fail(PV_ERR_ARG, "chunk bit count out of range");
+            EntChunk e;
+            e.stream = k;
+            e.n_sym = (int)n_sym;
+            e.bits = bits;
+            e.in_off = off;
+            e.out_off = start + c * kHufChunk;
+            chunks.push_back(e);
+            off += (bits + 31) / 32 * 4;
+        }
+    }
+    if (off != bytes) return fail(PV_ERR_ARG, "container size does not match its tables");
+    HIP_TRY(hipSetDevice(r->ctx->device));
+    hipStream_t s = pick(r->ctx, stream);
+    if (r->used) {
+        HIP_TRY(hipEventSynchronize(r->copied));
+        HIP_TRY(hipStreamWaitEvent(s, r->done, 0));
+    }
+    const uint64_t chunk_bytes = chunks.size() * sizeof(EntChunk);
+    const uint64_t block_bytes = blocks.size() * sizeof(EntBlock);
+    const uint64_t stage_need = (bytes + 15) / 16 * 16 + (chunk_bytes + 15) / 16 * 16 + block_bytes;
+    if (stage_need > r->ent_stage_cap) {
+        if (r->ent_stage) hipHostFree(r->ent_stage);
+        r->ent_stage = nullptr;
+        r->ent_stage_cap = 0;
+        if (hipHostMalloc((void **)&r->ent_stage, stage_need) != hipSuccess) return fail(PV_ERR_OOM, "pinned staging");
+        r->ent_stage_cap = stage_need;
+    }
+    PV_TRY(grow(&r->ent_in, r->ent_in_cap, bytes, "container buffer"));
+    PV_TRY(grow(&r->ent_chunks, r->ent_chunk_cap, std::max<uint64_t>(chunks.size(), 1), "chunk list"));
+    PV_TRY(grow(&r->ent_blocks, r->ent_block_cap, std::max<uint64_t>(blocks.size(), 1), "decode blocks"));
+    const uint64_t cpos = (bytes + 15) / 16 * 16, bpos = cpos + (chunk_bytes + 15) / 16 * 16;
+    std::memcpy(r->ent_stage, in, bytes);
+    if (chunk_bytes) std::memcpy(r->ent_stage + cpos, chunks.data(), chunk_bytes);
+    if (block_bytes) std::memcpy(r->ent_stage + bpos, blocks.data(), block_bytes);
+    HIP_TRY(hipMemcpyAsync(r->ent_in, r->ent_stage, bytes, hipMemcpyHostToDevice, s));
+    if (chunk_bytes) HIP_TRY(hipMemcpyAsync(r->ent_chunks, r->ent_stage + cpos, chunk_bytes, hipMemcpyHostToDevice, s));
+    if (block_bytes) HIP_TRY(hipMemcpyAsync(r->ent_blocks, r->ent_stage + bpos, block_bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(r->copied, s));
+    // the index section's zero padding is not coded: clear its last 16 bytes
+    // before the decode writes the entries among them
+    if (idx >= 16) HIP_TRY(launch_zero(r->pkt + kPacketHeader + idx - 16, 16, s));
+    d.in = r->ent_in;
+    d.chunks = r->ent_chunks;
+    d.blocks = r->ent_blocks;
+    d.n_blocks = (int)blocks.size();
+    d.pkt = r->pkt;
+    HIP_TRY(timed(r->ctx, PV_STAGE_UNPACK, s, [&] { return launch_entropy_decode(d, s); }));
+    return receive_on_device(r, h, s);
 }

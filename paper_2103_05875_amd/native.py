@@ -38,10 +38,11 @@ EXPORTED_SYMBOLS = [
     "pv_receiver_create", "pv_receiver_destroy", "pv_receiver_apply", "pv_receiver_status",
     "pv_receiver_get_maps", "pv_receiver_read_maps", "pv_yuv_dims", "pv_encode_yuv", "pv_decode_yuv",
     "pv_get_active", "pv_client_set_view", "pv_client_clear_view", "pv_client_get_view",
+    "pv_entropy_encode", "pv_entropy_download", "pv_receiver_apply_compressed",
 ]
 
 STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched", "shadow", "shade",
-          "pack_finish", "bounce", "unpack", "codec", "select"]
+          "pack_finish", "bounce", "unpack", "codec", "select", "entropy"]
 
 
 class NativeError(RuntimeError):
@@ -134,6 +135,9 @@ def lib():
         "pv_client_set_view": ([vp, P(f32), i32, vp], i32),
         "pv_client_clear_view": ([vp], i32),
         "pv_client_get_view": ([vp, P(vp)], i32),
+        "pv_entropy_encode": ([vp, vp], i32),
+        "pv_entropy_download": ([vp, vp, u64, P(u64), vp], i32),
+        "pv_receiver_apply_compressed": ([vp, vp, u64, vp], i32),
         "pv_encode_yuv": ([vp, f32, i32, vp, vp, vp], i32),
         "pv_decode_yuv": ([vp, i32, i32, vp, vp, vp, vp, vp], i32),
         "pv_read_maps": ([vp, vp, vp, P(ctypes.c_int64)], i32),
@@ -571,6 +575,19 @@ class Client:
         assert ri.size == self.volume.P * 192 and rv.size == self.volume.P * 512
         _check(lib().pv_client_set_state(self.h, ri.ctypes.data, rv.ctypes.data, int(seq)))
 
+    def entropy_encode(self, stream=None):
+        """Entropy-code the last packet on the device (asynchronous)."""
+        _check(lib().pv_entropy_encode(self.h, _stream_handle(stream)))
+
+    def entropy_download(self, stream=None) -> bytes:
+        nb = ctypes.c_uint64(0)
+        st = lib().pv_entropy_download(self.h, None, 0, ctypes.byref(nb), _stream_handle(stream))
+        if st not in (0, -5):
+            _check(st)
+        buf = np.zeros(max(nb.value, 1), np.uint8)
+        _check(lib().pv_entropy_download(self.h, buf.ctypes.data, buf.size, ctypes.byref(nb), _stream_handle(stream)))
+        return buf[:nb.value].tobytes()
+
     def set_view(self, eye, n_rays: int = 4096, stream=None):
         """Cull to the probes a spherical view from ``eye`` can see."""
         e = (ctypes.c_float * 3)(*[float(v) for v in eye])
@@ -644,6 +661,10 @@ class Receiver:
     def apply(self, packet: bytes, stream=None):
         buf = np.frombuffer(packet, np.uint8)
         _check(lib().pv_receiver_apply(self.h, buf.ctypes.data, buf.size, _stream_handle(stream)))
+
+    def apply_compressed(self, container: bytes, stream=None):
+        buf = np.frombuffer(container, np.uint8)
+        _check(lib().pv_receiver_apply_compressed(self.h, buf.ctypes.data, buf.size, _stream_handle(stream)))
 
     def status(self):
         """(result, seq): 0 applied, -2 checksum mismatch, -4 invalid index."""

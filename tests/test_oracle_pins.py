@@ -988,7 +988,8 @@ def test_huffman_length_limit(O):
 def test_entropy_round_trip_and_size(O):
     """A real packet: decode(encode) gives it back byte for byte, and the
     container size follows the layout: 40 bytes + per stream 132 bytes + 4
-    per chunk + each chunk's sum of code lengths rounded up to 32 bits."""
+    per 1,024-byte chunk + each chunk's sum of code lengths rounded up to 32
+    bits."""
     P = 300
     cur_i, cur_v = synth.random_fp16_maps(P, 8, 16, seed=3)
     ref_i, ref_v = synth.perturb_fp16_maps(cur_i, cur_v, seed=4, p_probe=0.5, p_texel=0.1, rel=2e-3)
@@ -1010,9 +1011,9 @@ def test_entropy_round_trip_and_size(O):
     size = 40
     for s in streams:
         ln = O.huf_lengths(np.bincount(s, minlength=256).astype(np.uint64)).astype(np.int64)
-        nch = -(-s.size // 4096)
+        nch = -(-s.size // 1024)
         size += 132 + 4 * nch
         for c in range(nch):
-            size += -(-int(ln[s[c * 4096:(c + 1) * 4096]].sum()) // 32) * 4
+            size += -(-int(ln[s[c * 1024:(c + 1) * 1024]].sum()) // 32) * 4
     assert len(enc) == size
     assert len(enc) < len(pkt)            # XOR planes of small changes are mostly zero bytes
