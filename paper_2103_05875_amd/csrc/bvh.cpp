@@ -1,7 +1,13 @@
-// Host BVH builder: binned surface-area heuristic over triangle centroids
-// into a binary tree (a node whose remaining depth budget is tight switches to
-// balanced median splits), collapsed into the 4-wide quantized nodes of the
-// GPU traversal with a proved bound on its stack.
+// Host BVH builder: triangles whose boxes are large against the scene's
+// average are first split into several references with clipped boxes (early
+// split clipping: a ground plane spanning the scene would otherwise put a
+// scene-sized box under the root that every ray enters); then a binned
+// surface-area heuristic over reference centroids builds a binary tree (a
+// node whose remaining depth budget is tight switches to balanced median
+// splits), collapsed into the 4-wide quantized nodes of the GPU traversal
+// with a proved bound on its stack. A split triangle appears in several
+// leaves; every copy carries the same id, so closest and any hit are
+// unchanged.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -44,6 +50,87 @@ struct Ref {
     float c[3];
     int tri;
 };
+
+// Box of the part of triangle t (9 floats) inside box clip: the triangle
+// clipped against the six planes (Sutherland-Hodgman), then bounded.
+Box clipped_box(const float *t, const Box &clip) {
+    float poly[2][12][3];
+    int n = 3, cur = 0;
+    for (int v = 0; v < 3; ++v)
+        for (int k = 0; k < 3; ++k) poly[0][v][k] = t[3 * v + k];
+    for (int axis = 0; axis < 3 && n > 0; ++axis)
+        for (int side = 0; side < 2 && n > 0; ++side) {
+            const float bound = side ? clip.hi[axis] : clip.lo[axis];
+            auto inside = [&](const float *p) { return side ? p[axis] <= bound : p[axis] >= bound; };
+            int m = 0;
+            for (int i = 0; i < n; ++i) {
+                const float *a = poly[cur][i], *c = poly[cur][(i + 1) % n];
+                const bool ia = inside(a), ic = inside(c);
+                if (ia && m < 12) {
+                    for (int k = 0; k < 3; ++k) poly[cur ^ 1][m][k] = a[k];
+                    ++m;
+                }
+                if (ia != ic && m < 12) {
+                    const float s = (bound - a[axis]) / (c[axis] - a[axis]);
+                    for (int k = 0; k < 3; ++k) poly[cur ^ 1][m][k] = a[k] + s * (c[k] - a[k]);
+                    poly[cur ^ 1][m][axis] = bound;
+                    ++m;
+                }
+            }
+            n = m;
+            cur ^= 1;
+        }
+    Box out;
+    out.reset();
+    for (int i = 0; i < n; ++i) out.grow(poly[cur][i]);
+    // clipping rounds: never let the box leave the triangle's own box
+    Box own;
+    own.reset();
+    for (int v = 0; v < 3; ++v) own.grow(t + 3 * v);
+    for (int k = 0; k < 3 && !out.empty(); ++k) {
+        out.lo[k] = std::max(out.lo[k], own.lo[k]);
+        out.hi[k] = std::min(out.hi[k], own.hi[k]);
+    }
+    return out;
+}
+
+// Splits the references whose box half-area exceeds 16 times the mean (and
+// 1/4096 of the scene's) at the middle of their longest axis, clipping the
+// triangle to each half, until every box is small enough or the references
+// number 2n. Deterministic (first-in, first-out).
+void split_large(const float *tri9, int n, const Box &scene, std::vector<Ref> &refs) {
+    double mean = 0.0;
+    for (const Ref &r : refs) mean += r.box.half_area();
+    mean /= std::max(n, 1);
+    const float limit = std::max((float)(16.0 * mean), scene.half_area() / 4096.f);
+    const size_t budget = bvh_max_refs(n);
+    std::vector<Ref> out, queue;
+    out.reserve(budget);
+    for (const Ref &r : refs) (r.box.half_area() > limit ? queue : out).push_back(r);
+    for (size_t qi = 0; qi < queue.size(); ++qi) {
+        const Ref r = queue[qi];
+        const size_t pending = queue.size() - qi - 1;
+        if (r.box.half_area() <= limit || out.size() + pending + 2 > budget) {
+            out.push_back(r);
+            continue;
+        }
+        int axis = 0;
+        for (int k = 1; k < 3; ++k)
+            if (r.box.hi[k] - r.box.lo[k] > r.box.hi[axis] - r.box.lo[axis]) axis = k;
+        const float mid = 0.5f * (r.box.lo[axis] + r.box.hi[axis]);
+        for (int half = 0; half < 2; ++half) {
+            Box h = r.box;
+            (half ? h.lo : h.hi)[axis] = mid;
+            Ref c;
+            c.tri = r.tri;
+            c.box = clipped_box(tri9 + 9 * (size_t)r.tri, h);
+            if (c.box.empty()) continue;
+            for (int k = 0; k < 3; ++k) c.c[k] = 0.5f * (c.box.lo[k] + c.box.hi[k]);
+            queue.push_back(c);
+        }
+    }
+    refs.swap(out);
+}
 
 struct BNode {
     Box box;
@@ -378,9 +465,11 @@ bool build_bvh4(const float *tri9, int n, int id_base, HostBvh4 &out, std::strin
             refs[i].tri = i;
             scene.grow(refs[i].box);
         }
-        if (levels_needed(n) + 2 > limit) break;
+        split_large(tri9, n, scene, refs);
+        const int m = (int)refs.size();
+        if (levels_needed(m) + 2 > limit) break;
         Builder b(refs, limit);
-        b.build(0, n, 0);
+        b.build(0, m, 0);
         // conservative padding of every box (rounding of the slab test)
         float diag = 0.f;
         for (int k = 0; k < 3; ++k) diag += (scene.hi[k] - scene.lo[k]) * (scene.hi[k] - scene.lo[k]);
@@ -399,12 +488,12 @@ bool build_bvh4(const float *tri9, int n, int id_base, HostBvh4 &out, std::strin
         out.nodes = std::move(col.out);
         out.depth = depth;
         out.stack_need = need;
-        if ((int)col.leaf_order.size() != n) {
+        if ((int)col.leaf_order.size() != m) {
             err = "internal: leaf triangles do not cover the scene";
             return false;
         }
-        out.tris.resize(n);
-        for (int i = 0; i < n; ++i) {
+        out.tris.resize(m);
+        for (int i = 0; i < m; ++i) {
             const int src = refs[col.leaf_order[i]].tri;
             const float *t = tri9 + 9 * (size_t)src;
             GpuTri g;

@@ -104,8 +104,9 @@ struct pv_scene {
     hipEvent_t dyn_use[kRing] = {};
     bool dyn_used[kRing] = {};
     int dyn_nodes_n[kRing] = {};
+    int dyn_tris_n[kRing] = {};
     int dyn_slot = 0;
-    size_t dyn_node_cap = 0;
+    size_t dyn_node_cap = 0, dyn_tri_cap = 0;
 };
 
 struct pv_volume {
@@ -359,11 +360,13 @@ extern "C" pv_status pv_scene_create(pv_ctx *ctx, const pv_scene_desc *d, pv_sce
         return fail(PV_ERR_DEVICE, std::string("materials upload: ") + hipGetErrorString(e));
     }
     if (s->n_dyn > 0) {
-        s->dyn_node_cap = (size_t)s->n_dyn;  // a tree over n leaves has fewer than n inner nodes
+        // a tree over m leaf slots has fewer than m inner nodes
+        s->dyn_node_cap = bvh_max_refs(s->n_dyn);
+        s->dyn_tri_cap = bvh_max_refs(s->n_dyn);
         for (int i = 0; i < pv_scene::kRing; ++i) {
             st = dev_alloc(&s->dyn_nodes[i], s->dyn_node_cap * sizeof(GpuNode4), "dynamic BVH nodes");
-            if (st == PV_OK) st = dev_alloc(&s->dyn_tris[i], (size_t)s->n_dyn * sizeof(GpuTri), "dynamic triangles");
-            if (st == PV_OK && hipHostMalloc(&s->dyn_stage[i], s->dyn_node_cap * sizeof(GpuNode4) + (size_t)s->n_dyn * sizeof(GpuTri)) != hipSuccess)
+            if (st == PV_OK) st = dev_alloc(&s->dyn_tris[i], s->dyn_tri_cap * sizeof(GpuTri), "dynamic triangles");
+            if (st == PV_OK && hipHostMalloc(&s->dyn_stage[i], s->dyn_node_cap * sizeof(GpuNode4) + s->dyn_tri_cap * sizeof(GpuTri)) != hipSuccess)
                 st = fail(PV_ERR_OOM, "pinned staging for dynamic triangles");
             if (st == PV_OK && hipEventCreateWithFlags(&s->dyn_use[i], hipEventDisableTiming) != hipSuccess)
                 st = fail(PV_ERR_DEVICE, "event");
@@ -389,7 +392,8 @@ static pv_status set_dynamic_impl(pv_scene *s, const float *pos, hipStream_t st)
     HostBvh4 hb;
     std::string err;
     if (!build_bvh4(pos, s->n_dyn, s->n_static, hb, err)) return fail(PV_ERR_ARG, err);
-    if (hb.nodes.size() > s->dyn_node_cap) return fail(PV_ERR_STATE, "dynamic BVH larger than its slot");
+    if (hb.nodes.size() > s->dyn_node_cap || hb.tris.size() > s->dyn_tri_cap)
+        return fail(PV_ERR_STATE, "dynamic BVH larger than its slot");
     const int k = (s->dyn_slot + 1) % pv_scene::kRing;
     // the slot may still be read by earlier work: wait for its last use
     if (s->dyn_used[k]) HIP_TRY(hipEventSynchronize(s->dyn_use[k]));
@@ -402,6 +406,7 @@ static pv_status set_dynamic_impl(pv_scene *s, const float *pos, hipStream_t st)
     HIP_TRY(hipEventRecord(s->dyn_use[k], st));
     s->dyn_used[k] = true;
     s->dyn_nodes_n[k] = (int)hb.nodes.size();
+    s->dyn_tris_n[k] = (int)hb.tris.size();
     s->dyn_slot = k;
     return PV_OK;
 }
@@ -429,7 +434,7 @@ static SceneView scene_view(pv_scene *s) {
         v.dyn.nodes = s->dyn_nodes[s->dyn_slot];
         v.dyn.tris = s->dyn_tris[s->dyn_slot];
         v.dyn.n_nodes = s->dyn_nodes_n[s->dyn_slot];
-        v.dyn.n_tris = s->n_dyn;
+        v.dyn.n_tris = s->dyn_tris_n[s->dyn_slot];
     }
     v.mats = s->mats;
     v.eps = s->eps;

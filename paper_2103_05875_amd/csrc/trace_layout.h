@@ -64,6 +64,10 @@ struct HostBvh4 {
 // Stack entries the 4-wide traversal may hold at once.
 constexpr int kStack4 = 32;
 
+// Leaf triangle slots a BVH over n triangles may hold (large triangles are
+// split into several references, at most doubling the count).
+inline size_t bvh_max_refs(int n) { return 2 * (size_t)(n > 0 ? n : 0); }
+
 // Builds the 4-wide quantized BVH (collapsed from the binary SAH tree, with
 // the binary depth limit lowered until the worst-case stack fits kStack4).
 bool build_bvh4(const float *tri9, int n, int id_base, HostBvh4 &out, std::string &err);
