@@ -74,9 +74,9 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_batched(const BatchVolu
     const int local = g - bv.first_blend;
     const int p0 = (local / kBlendSplit) * kBlendTile, part = local % kBlendSplit;
     if (bv.fp16)
-        blend_tile<__half>(bv.vp, bv.wt, bv.rays, (__half *)bv.irr, (__half *)bv.vis, bv.h, p0, part, sm);
+        blend_tile_any<__half>(bv.vp, bv.dirs, bv.rays, (__half *)bv.irr, (__half *)bv.vis, bv.h, p0, part, sm);
     else
-        blend_tile<float>(bv.vp, bv.wt, bv.rays, (float *)bv.irr, (float *)bv.vis, bv.h, p0, part, sm);
+        blend_tile_any<float>(bv.vp, bv.dirs, bv.rays, (float *)bv.irr, (float *)bv.vis, bv.h, p0, part, sm);
 }
 
 hipError_t launch_trace_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, const FrameParams *frames_dev,

@@ -23,8 +23,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kIrrRows = 64;          // irradiance interior texels
 constexpr int kBlendThreads = 256;    // four wavefronts
-constexpr int kBlendK = 128;          // rays staged in LDS per step
-static_assert(kBlendK == 128, "the weight tables are zero-padded to a multiple of 128 rays");
+constexpr int kBlendK = 128;          // rays staged in LDS per chunk
+static_assert(kBlendK <= kBlendThreads && kBlendK * kBlendTile % kBlendThreads == 0, "chunk staging");
 static_assert(kBlendSplit == 2 && kBlendThreads == 256, "blend_tile maps 2 x 4 waves onto the texel rows");
 
 // Direction i of the n-ray spherical-Fibonacci set, rotated by the frame's
@@ -105,22 +105,26 @@ __device__ __forceinline__ void store_with_guard(T *tile, int N, int i, int j, T
 
 struct BlendSmem {
     float4 rec[kBlendK][kBlendTile];  // ray records of the tile's probes
+    float4 dir[kBlendK];              // the chunk's ray directions (zero past n)
     float rows[kTexRows];             // weight row totals
 };
 
 // New value of one texel-channel: estimate = sum / total, lerped with the
-// stored value by h (h = 0: no history), rounded to the map format, written
-// with its guard copies. A texel whose total is at most the floor keeps its
-// value.
+// stored value 'old' by h (h = 0: no history), rounded to the map format,
+// written with its guard copies. A texel whose total is at most the floor
+// keeps its value.
 template <typename T>
-__device__ __forceinline__ void blend_store(T *tile, int N, int t, float sum, float total, float h) {
+__device__ __forceinline__ void blend_store(T *tile, int N, int t, float sum, float total, float h, float old) {
     if (!(total > kWeightFloor)) return;
     const int i = t % N, jr = t / N;
     const float est = sum * (1.0f / total);
     float nv = est;
-    if (h > 0.f) nv = fmaf(h, load_map<T>(tile + (jr + 1) * (N + 2) + (i + 1)), (1.0f - h) * est);
+    if (h > 0.f) nv = fmaf(h, old, (1.0f - h) * est);
     store_with_guard<T>(tile, N, i, jr, to_map<T>(nv));
 }
+
+// Interior texel t of an N x N map in its (N+2)^2 tile.
+__device__ __forceinline__ int interior(int N, int t) { return (t / N + 1) * (N + 2) + t % N + 1; }
 
 // Blend of probes p0 .. p0+7, rows half 'part' (0 or 1), by one block of
 // four wavefronts; the two halves of a tile are independent blocks.
@@ -133,86 +137,136 @@ __device__ __forceinline__ void blend_store(T *tile, int N, int t, float sum, fl
 // upper eight columns are zero). The 8 waves of a tile (g = 4 part + wave)
 // each own three 16-row MFMA tiles: visibility rows 32g .. 32g+31 and
 // irradiance rows 16 (g / 2) .. +15 of colour tile g % 2.
-template <typename T>
-__device__ void blend_tile(const VolumeParams &vp, const WeightTables &wt, const float4 *rays, T *irr, T *vis,
-                           float h, int p0, int part, BlendSmem &sm) {
+//
+// The A operand (the weights) is computed in registers: lane l evaluates
+// its three rows' weights for ray 4 step + l / 16 from the ray direction
+// staged in LDS, and also sums them, so a wave holds the weight row totals
+// of its own rows with no weight table in memory. Ray records arrive in
+// 128-ray chunks through LDS; the next chunk is loaded into registers while
+// the current one runs on the matrix cores, and the stored values the
+// hysteresis needs are loaded before the products.
+template <typename T, int S>
+__device__ void blend_tile(const VolumeParams &vp, const float4 *dirs, const float4 *rays, T *irr, T *vis, float h,
+                           int p0, int part, BlendSmem &sm) {
+    constexpr int kStage = kBlendK * kBlendTile / kBlendThreads;  // records each thread stages per chunk
     const int tid = threadIdx.x, lane = tid & 63;
     const int g = part * 4 + (tid >> 6);
-    const int n = vp.n, P = vp.P;
+    const int n = vp.n, P = vp.P, sharp = vp.vis_sharpness;
     const int col = lane & 15, krow = lane >> 4;
     const int q = col & 7, half = col >> 3;
     const int ctile = g & 1;  // irradiance colour tile: 0 = red/green, 1 = blue
+    const int p = p0 + q;
+    const bool has_i = !(ctile && half);  // the blue tile's upper columns are zero
 
-    for (int t = tid; t < kTexRows; t += kBlendThreads) {
-        float s = 0.f;
-        for (int b = 0; b < wt.nparts; ++b) s += wt.part[b * kTexRows + t];
-        sm.rows[t] = s;
+    // texel directions of this lane's A rows (irradiance ti_a; visibility tv_a, tv_a + 16)
+    const int ti_a = 16 * (g >> 1) + col, tv_a = 32 * g + col;
+    const float3 om_i = oct_texel_dir(8, ti_a & 7, ti_a >> 3);
+    const float3 om_v0 = oct_texel_dir(16, tv_a & 15, tv_a >> 4);
+    const float3 om_v1 = oct_texel_dir(16, (tv_a + 16) & 15, (tv_a + 16) >> 4);
+
+    // the lane's output tiles (irradiance channel: red/green by column
+    // half, or blue) and their stored values (rows 4 krow + r)
+    T *itile = irr + ((size_t)min(p, P - 1) * 3 + (ctile ? 2 : half)) * 100;
+    T *vtile = vis + ((size_t)min(p, P - 1) * 2 + half) * 324;
+    float old_i[4] = {0.f, 0.f, 0.f, 0.f}, old_v0[4] = {0.f, 0.f, 0.f, 0.f}, old_v1[4] = {0.f, 0.f, 0.f, 0.f};
+    if (h > 0.f && p < P) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ti = 16 * (g >> 1) + 4 * krow + r, tv0 = 32 * g + 4 * krow + r;
+            if (has_i) old_i[r] = load_map<T>(itile + interior(8, ti));
+            old_v0[r] = load_map<T>(vtile + interior(16, tv0));
+            old_v1[r] = load_map<T>(vtile + interior(16, tv0 + 16));
+        }
     }
+
+    // chunk staging: consecutive threads take consecutive LDS records (8
+    // probes of one ray, then the next ray): conflict-free stores, 128-byte
+    // runs of each probe's rays in global memory
+    float4 rr[kStage], dr;
+    auto fetch = [&](int j0) {
+        const int m = min(kBlendK, n - j0);
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int e = tid + u * kBlendThreads, jj = e / kBlendTile, pp = p0 + e % kBlendTile;
+            rr[u] = (pp < P && jj < m) ? rays[(size_t)pp * n + j0 + jj] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        dr = (tid < m) ? dirs[j0 + tid] : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    fetch(0);
+
     v4f acc_i = {0.f, 0.f, 0.f, 0.f};
     v4f acc_v0 = acc_i, acc_v1 = acc_i;
-    const int row_i = 16 * (g >> 1) + col;
-    const int row_v = kIrrRows + 32 * g + col;
-
+    float s_i = 0.f, s_v0 = 0.f, s_v1 = 0.f;
     for (int j0 = 0; j0 < n; j0 += kBlendK) {
         const int m = min(kBlendK, n - j0);
-        __syncthreads();
-        // consecutive threads fill consecutive LDS records (8 probes of one
-        // ray, then the next ray): conflict-free stores, 128-byte runs of
-        // each probe's rays in global memory
-        for (int e = tid; e < kBlendK * kBlendTile; e += kBlendThreads) {
-            const int jj = e / kBlendTile, pq = e - jj * kBlendTile, p = p0 + pq;
-            sm.rec[jj][pq] = (p < P && jj < m) ? rays[(size_t)p * n + j0 + jj] : make_float4(0.f, 0.f, 0.f, 0.f);
+        __syncthreads();  // every wave is done with the previous chunk
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int e = tid + u * kBlendThreads;
+            sm.rec[e / kBlendTile][e % kBlendTile] = rr[u];
         }
+        if (tid < kBlendK) sm.dir[tid] = dr;
         __syncthreads();
-        // steps of 4 rays, in groups of 4 steps: the records past m are
-        // staged as zeros and the table is zero past n (padded to kBlendK).
-        // The weights of the next group are loaded while the current one
-        // runs on the matrix cores.
+        if (j0 + kBlendK < n) fetch(j0 + kBlendK);
+        // steps of 4 rays, unrolled by 4: past m the staged directions and
+        // records are zero, so the weights and products add exact zeros
         const int steps = ((m + 15) >> 4) << 2;
-        const float *wg = wt.w + (size_t)(j0 >> 2) * (4 * kTexRows) + krow;
-        float nxt[4][3];
-        auto load_group = [&](int k0, float a[4][3]) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const float *w = wg + (size_t)(k0 + u) * (4 * kTexRows);
-                a[u][0] = w[4 * row_i];
-                a[u][1] = w[4 * row_v];
-                a[u][2] = w[4 * (row_v + 16)];
-            }
-        };
-        load_group(0, nxt);
         for (int k0 = 0; k0 < steps; k0 += 4) {
-            float cur[4][3];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int x = 0; x < 3; ++x) cur[u][x] = nxt[u][x];
-            if (k0 + 4 < steps) load_group(k0 + 4, nxt);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const float4 r4 = sm.rec[4 * (k0 + u) + krow][q];
+                const int j = 4 * (k0 + u) + krow;
+                const float4 r4 = sm.rec[j][q];
+                const float3 d = xyz(sm.dir[j]);
+                const float w_i = fmaxf(dot3(om_i, d), 0.f);
+                const float w_v0 = pow_int<S>(fmaxf(dot3(om_v0, d), 0.f), sharp);
+                const float w_v1 = pow_int<S>(fmaxf(dot3(om_v1, d), 0.f), sharp);
+                s_i += w_i;
+                s_v0 += w_v0;
+                s_v1 += w_v1;
                 const float bv = half ? r4.w * r4.w : r4.w;
                 const float bi = ctile ? (half ? 0.f : r4.z) : (half ? r4.y : r4.x);
-                acc_i = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u][0], bi, acc_i, 0, 0, 0);
-                acc_v0 = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u][1], bv, acc_v0, 0, 0, 0);
-                acc_v1 = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u][2], bv, acc_v1, 0, 0, 0);
+                acc_i = __builtin_amdgcn_mfma_f32_16x16x4f32(w_i, bi, acc_i, 0, 0, 0);
+                acc_v0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w_v0, bv, acc_v0, 0, 0, 0);
+                acc_v1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w_v1, bv, acc_v1, 0, 0, 0);
             }
         }
     }
 
-    const int p = p0 + q;
+    // row totals: the four lanes of a row (l / 16 = 0 .. 3) hold partial
+    // sums; after the two exchanges all four hold the same total
+    s_i += __shfl_xor(s_i, 16);
+    s_i += __shfl_xor(s_i, 32);
+    s_v0 += __shfl_xor(s_v0, 16);
+    s_v0 += __shfl_xor(s_v0, 32);
+    s_v1 += __shfl_xor(s_v1, 16);
+    s_v1 += __shfl_xor(s_v1, 32);
+    if (krow == 0) {
+        if (ctile == 0) sm.rows[ti_a] = s_i;  // both colour tiles compute the same irradiance rows
+        sm.rows[kIrrRows + tv_a] = s_v0;
+        sm.rows[kIrrRows + tv_a + 16] = s_v1;
+    }
+    __syncthreads();
+
     if (p >= P) return;
-    T *itile = irr + (size_t)p * 3 * 100;
-    T *vtile = vis + (size_t)p * 2 * 324;
-    const int ch = ctile ? 2 : half;  // irradiance channel of this lane's column
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int ti = 16 * (g >> 1) + 4 * krow + r;
-        if (!(ctile && half)) blend_store<T>(itile + ch * 100, 8, ti, acc_i[r], sm.rows[ti], h);
+        if (has_i) blend_store<T>(itile, 8, ti, acc_i[r], sm.rows[ti], h, old_i[r]);
         const int tv0 = 32 * g + 4 * krow + r, tv1 = tv0 + 16;
-        blend_store<T>(vtile + half * 324, 16, tv0, acc_v0[r], sm.rows[kIrrRows + tv0], h);
-        blend_store<T>(vtile + half * 324, 16, tv1, acc_v1[r], sm.rows[kIrrRows + tv1], h);
+        blend_store<T>(vtile, 16, tv0, acc_v0[r], sm.rows[kIrrRows + tv0], h, old_v0[r]);
+        blend_store<T>(vtile, 16, tv1, acc_v1[r], sm.rows[kIrrRows + tv1], h, old_v1[r]);
     }
+}
+
+// Both sharpness forms of the blend (s = 50 is unrolled; every path that
+// blends a volume dispatches the same way, so their results are identical).
+template <typename T>
+__device__ __forceinline__ void blend_tile_any(const VolumeParams &vp, const float4 *dirs, const float4 *rays, T *irr,
+                                               T *vis, float h, int p0, int part, BlendSmem &sm) {
+    if (vp.vis_sharpness == 50)
+        blend_tile<T, 50>(vp, dirs, rays, irr, vis, h, p0, part, sm);
+    else
+        blend_tile<T, 0>(vp, dirs, rays, irr, vis, h, p0, part, sm);
 }
 
 }  // namespace pv

@@ -13,32 +13,14 @@
 
 namespace pv {
 
-// Blend weight tables of one volume-frame, written by the ray-direction
-// kernel (rows: 64 irradiance texels, then 256 visibility texels):
-//   w[((j / 4) * kTexRows + t) * 4 + j % 4]  weight of ray j for texel row t;
-//                                            rays n .. (n rounded up to a
-//                                            multiple of 128) - 1 weigh 0
-//   part[b * kTexRows + t]                   sum of row t over rays
-//                                            kRaysPerPart*b .. +kRaysPerPart-1
-// The blend sums the parts in order b = 0, 1, ... for the row totals.
-constexpr int kTexRows = 64 + 256;
-constexpr int kRaysPerPart = 64;
-constexpr int kBlendTile = 8;  // probes per blend block
-struct WeightTables {
-    float *w = nullptr;
-    float *part = nullptr;
-    int k4 = 0;
-    int nparts = 0;
-};
-inline size_t weight_table_floats(int n) { return (size_t)((n + 127) / 128) * 128 * kTexRows; }
-inline size_t weight_part_floats(int n) { return (size_t)((n + kRaysPerPart - 1) / kRaysPerPart) * kTexRows; }
+constexpr int kTexRows = 64 + 256;  // texel rows of the blend: 64 irradiance, then 256 visibility
+constexpr int kBlendTile = 8;       // probes per blend block
 
 // Work description of one volume for the batched launch.
 struct BatchVolume {
     VolumeParams vp;
     SceneView sv;
     const float4 *dirs;
-    WeightTables wt;
     float4 *rays;
     int32_t *hits;
     void *irr;
@@ -61,9 +43,9 @@ struct BatchVolume {
 // Launchers (trace.hip, blend.hip, batched.hip, bounce.hip, pack.hip)
 // ---------------------------------------------------------------------------
 // Directions and weight tables; the 9 work counters are zeroed for the trace that follows
-hipError_t launch_raydirs(const FrameParams &fp, const VolumeParams &vp, float4 *dirs, const WeightTables &wt,
-                          int *queue, hipStream_t s);
-hipError_t launch_blend(const VolumeParams &vp, const WeightTables &wt, const float4 *rays, void *irr, void *vis,
+hipError_t launch_raydirs(const FrameParams &fp, const VolumeParams &vp, float4 *dirs, int *queue, hipStream_t s);
+int raydir_blocks(int n);
+hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4 *rays, void *irr, void *vis,
                         int fp16, float h, hipStream_t s);
 // Batched trace / blend over every volume of a batch (descriptors on the
 // device; each volume's first_wave a multiple of 4).
@@ -71,7 +53,7 @@ hipError_t launch_trace_batched(const BatchVolume *vols_dev, int n_vols, int tot
                                 bool short_stack, hipStream_t s);
 hipError_t launch_blend_batched(const BatchVolume *vols_dev, int n_vols, int total_blend, hipStream_t s);
 hipError_t launch_raydirs_batched(const BatchVolume *vols_dev, const FrameParams *frames_dev, int n_vols,
-                                  int max_parts, hipStream_t s);
+                                  int dir_blocks, hipStream_t s);
 
 // Second bounce (bounce.hip): adds albedo x the stored maps' query to every
 // hit record's radiance (vp.hitrec must be set); the client query.

@@ -116,7 +116,6 @@ struct pv_volume {
     size_t elem = 4;
     void *irr = nullptr, *vis = nullptr;
     float4 *rays = nullptr, *dirs = nullptr;
-    WeightTables wt;  // blend weights of the current frame
     int32_t *hits = nullptr;
     int2 *hitrec = nullptr;  // hit records (PV_MULTI_BOUNCE or PV_CLASSIFY)
     uint8_t *active = nullptr;  // [P] probe activity of the last update (PV_CLASSIFY)
@@ -474,8 +473,7 @@ static uint64_t volume_bytes(const pv_volume_desc *d) {
     const int P = d->nx * d->ny * d->nz, n = d->rays_per_probe;
     const size_t elem = d->format == PV_MAP_FP16 ? 2 : 4;
     uint64_t b = irr_bytes(P, elem) + vis_bytes(P, elem) + 512 + (uint64_t)P * n * 16 + (uint64_t)n * 16 +
-                 (uint64_t)kQueueInts * 4 +
-                 (uint64_t)(weight_table_floats(n) + weight_part_floats(n)) * 4;
+                 (uint64_t)kQueueInts * 4;
     if (d->flags & PV_KEEP_HITS) b += (uint64_t)P * n * 4;
     if (d->flags & (PV_MULTI_BOUNCE | PV_CLASSIFY)) b += (uint64_t)P * n * 8;
     if (d->flags & PV_CLASSIFY) b += (uint64_t)P;
@@ -494,8 +492,6 @@ static void free_volume(pv_volume *v) {
     hipFree(v->vis);
     hipFree(v->rays);
     hipFree(v->dirs);
-    hipFree(v->wt.w);
-    hipFree(v->wt.part);
     hipFree(v->hits);
     hipFree(v->hitrec);
     hipFree(v->active);
@@ -521,10 +517,6 @@ extern "C" pv_status pv_create_volume(pv_ctx *ctx, const pv_volume_desc *d, pv_v
     if (st == PV_OK) st = dev_alloc(&v->vis, vis_bytes(v->P, v->elem) + 256, "visibility maps");
     if (st == PV_OK) st = dev_alloc(&v->rays, (size_t)v->P * v->n * 16, "ray buffer");
     if (st == PV_OK) st = dev_alloc(&v->dirs, (size_t)v->n * 16, "directions");
-    v->wt.k4 = (v->n + 3) / 4;
-    v->wt.nparts = (v->n + kRaysPerPart - 1) / kRaysPerPart;
-    if (st == PV_OK) st = dev_alloc(&v->wt.w, weight_table_floats(v->n) * 4, "blend weight table");
-    if (st == PV_OK) st = dev_alloc(&v->wt.part, weight_part_floats(v->n) * 4, "blend weight sums");
     if (st == PV_OK && (d->flags & PV_KEEP_HITS)) st = dev_alloc(&v->hits, (size_t)v->P * v->n * 4, "hit ids");
     if (st == PV_OK && (d->flags & (PV_MULTI_BOUNCE | PV_CLASSIFY)))
         st = dev_alloc(&v->hitrec, (size_t)v->P * v->n * sizeof(int2), "hit records");
@@ -535,8 +527,6 @@ extern "C" pv_status pv_create_volume(pv_ctx *ctx, const pv_volume_desc *d, pv_v
             st = fail(PV_ERR_DEVICE, "fill");
     }
     if (st == PV_OK) st = dev_alloc(&v->queue, kQueueInts * sizeof(int), "work queues");
-    if (st == PV_OK && launch_zero(v->wt.w, weight_table_floats(v->n) * 4, ctx->stream) != hipSuccess)
-        st = fail(PV_ERR_DEVICE, "zero fill");  // the padding past n stays zero
     if (st == PV_OK && launch_zero(v->irr, irr_bytes(v->P, v->elem), ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "zero fill");
     if (st == PV_OK && launch_zero(v->vis, vis_bytes(v->P, v->elem), ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "zero fill");
     if (st == PV_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(PV_ERR_DEVICE, "sync after zero fill");
@@ -640,7 +630,7 @@ static pv_status enqueue_trace(pv_volume *v, const FrameParams &fp, const SceneV
     const bool split = v->tc.split_shadows != 0;
     if (split) PV_TRY(ensure_split(v, fp.n_lights, s));
     const SplitBuffers sb = split ? v->split : SplitBuffers();
-    HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s, [&] { return launch_raydirs(fp, vp, v->dirs, v->wt, v->queue, s); }));
+    HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s, [&] { return launch_raydirs(fp, vp, v->dirs, v->queue, s); }));
     HIP_TRY(timed(c, PV_STAGE_TRACE, s,
                   [&] { return launch_trace(vp, sv, fp, v->dirs, v->rays, v->hits, counts, v->tc, v->queue, sb, s); }));
     if (split && fp.n_lights > 0) {
@@ -668,7 +658,7 @@ extern "C" pv_status pv_update_probes(pv_volume *v, const pv_frame *f, void *str
     if (v->desc.flags & PV_MULTI_BOUNCE)
         HIP_TRY(timed(c, PV_STAGE_BOUNCE, s,
                       [&] { return launch_bounce(vp, sv, v->dirs, v->rays, v->irr, v->vis, fp16, s); }));
-    HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend(vp, v->wt, v->rays, v->irr, v->vis, fp16, h, s); }));
+    HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend(vp, v->dirs, v->rays, v->irr, v->vis, fp16, h, s); }));
     PV_TRY(note_scene_use(v->scene, s));
     v->frame++;
     return PV_OK;
@@ -704,8 +694,8 @@ extern "C" pv_status pv_blend_rays(pv_volume *v, const pv_frame *f, const void *
     HIP_TRY(hipSetDevice(v->ctx->device));
     hipStream_t s = pick(v->ctx, stream);
     const VolumeParams vp = volume_params(v);
-    HIP_TRY(launch_raydirs(fp, vp, v->dirs, v->wt, nullptr, s));
-    HIP_TRY(launch_blend(vp, v->wt, (const float4 *)rays_dev, v->irr, v->vis, v->desc.format == PV_MAP_FP16,
+    HIP_TRY(launch_raydirs(fp, vp, v->dirs, nullptr, s));
+    HIP_TRY(launch_blend(vp, v->dirs, (const float4 *)rays_dev, v->irr, v->vis, v->desc.format == PV_MAP_FP16,
                          effective_h(v), s));
     v->frame++;
     return PV_OK;
@@ -819,7 +809,7 @@ struct pv_batch_graph {
     std::vector<pv_volume *> vols;
     BatchSlot slot;           // device descriptors + pinned staging owned by the graph
     size_t o_b = 0, o_f = 0, bytes = 0;
-    int waves = 0, blend = 0, bounce = 0, classify = 0, max_parts = 0;
+    int waves = 0, blend = 0, bounce = 0, classify = 0, dir_blocks = 0;
     bool short_stack = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -832,7 +822,7 @@ struct pv_batch_graph {
 // blocks of a volume, and whether every BVH of the batch fits 16-bit stack
 // entries.
 static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int n, char *h, size_t *offs, int &waves,
-                            int &blend, int &bounce, int &classify, int &max_parts, bool &short_stack) {
+                            int &blend, int &bounce, int &classify, int &dir_blocks, bool &short_stack) {
     std::vector<BatchVolume> bv(n);
     std::vector<FrameParams> fps(n);
     std::memset(fps.data(), 0, sizeof(FrameParams) * n);
@@ -840,7 +830,7 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
     blend = 0;
     bounce = 0;
     classify = 0;
-    max_parts = 0;
+    dir_blocks = 0;
     short_stack = true;
     for (int i = 0; i < n; ++i) {
         pv_volume *v = vols[i];
@@ -850,8 +840,7 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
         b.sv = scene_view(v->scene);
         short_stack = short_stack && b.sv.stat.n_nodes <= 65536 && b.sv.dyn.n_nodes <= 65536;
         b.dirs = v->dirs;
-        b.wt = v->wt;
-        max_parts = std::max(max_parts, v->wt.nparts);
+        dir_blocks = std::max(dir_blocks, raydir_blocks(v->n));
         b.rays = v->rays;
         b.hits = v->hits;
         b.irr = v->irr;
@@ -915,14 +904,14 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
     HIP_TRY(hipEventSynchronize(slot.done));  // the slot's previous launch has finished
     PV_TRY(ensure_slot(c, slot, n));
     size_t offs[3];
-    int waves, blend, bounce, classify, max_parts;
+    int waves, blend, bounce, classify, dir_blocks;
     bool short_stack;
     char *h = (char *)slot.stage_host;
-    PV_TRY(fill_batch(vols, frames, n, h, offs, waves, blend, bounce, classify, max_parts, short_stack));
+    PV_TRY(fill_batch(vols, frames, n, h, offs, waves, blend, bounce, classify, dir_blocks, short_stack));
     HIP_TRY(hipMemcpyAsync(slot.batch_dev, h + offs[0], sizeof(BatchVolume) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(slot.frames_dev, h + offs[1], sizeof(FrameParams) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s,
-                  [&] { return launch_raydirs_batched(slot.batch_dev, slot.frames_dev, n, max_parts, s); }));
+                  [&] { return launch_raydirs_batched(slot.batch_dev, slot.frames_dev, n, dir_blocks, s); }));
     HIP_TRY(timed(c, PV_STAGE_BATCHED, s,
                   [&] { return launch_trace_batched(slot.batch_dev, n, waves, slot.frames_dev, short_stack, s); }));
     if (classify > 0)
@@ -963,7 +952,7 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
     size_t offs[3];
     if (st == PV_OK)
         st = fill_batch(vols, nullptr, n, (char *)g->slot.stage_host, offs, g->waves, g->blend, g->bounce,
-                        g->classify, g->max_parts, g->short_stack);
+                        g->classify, g->dir_blocks, g->short_stack);
     if (st != PV_OK) {
         free_graph(g);
         return st;
@@ -979,7 +968,7 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) e = hipMemcpyAsync(b.batch_dev, h + g->o_b, sizeof(BatchVolume) * n, hipMemcpyHostToDevice, cs);
     if (e == hipSuccess) e = hipMemcpyAsync(b.frames_dev, h + g->o_f, sizeof(FrameParams) * n, hipMemcpyHostToDevice, cs);
-    if (e == hipSuccess) e = launch_raydirs_batched(b.batch_dev, b.frames_dev, n, g->max_parts, cs);
+    if (e == hipSuccess) e = launch_raydirs_batched(b.batch_dev, b.frames_dev, n, g->dir_blocks, cs);
     if (e == hipSuccess) e = launch_trace_batched(b.batch_dev, n, g->waves, b.frames_dev, g->short_stack, cs);
     if (e == hipSuccess && g->classify > 0) e = launch_classify_batched(b.batch_dev, n, g->classify, cs);
     if (e == hipSuccess && g->bounce > 0) e = launch_bounce_batched(b.batch_dev, n, g->bounce, cs);
@@ -1013,10 +1002,10 @@ extern "C" pv_status pv_batch_graph_launch(pv_batch_graph *g, const pv_frame *fr
     // launch must have finished before it is rewritten
     if (g->launched) HIP_TRY(hipEventSynchronize(g->done));
     size_t offs[3];
-    int waves, blend, bounce, classify, max_parts;
+    int waves, blend, bounce, classify, dir_blocks;
     bool short_stack;
     PV_TRY(fill_batch(g->vols.data(), frames, n, (char *)g->slot.stage_host, offs, waves, blend, bounce, classify,
-                      max_parts, short_stack));
+                      dir_blocks, short_stack));
     if (waves != g->waves || blend != g->blend || bounce != g->bounce || classify != g->classify ||
         short_stack != g->short_stack)
         return fail(PV_ERR_STATE, "a volume of the graph changed scene since the graph was captured");
