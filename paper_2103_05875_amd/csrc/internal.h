@@ -68,7 +68,7 @@ struct PackBuffers {
     const uint16_t *cur_irr, *cur_vis;   // tiles
     uint16_t *ref_irr, *ref_vis;         // interiors
     uint8_t *mask_irr, *mask_vis;
-    int4 *tiles;      // per tile of 16 probes: changed counts (irr, vis) and last changed probe
+    int4 *tiles;      // per tile of kPackTile probes: changed counts (irr, vis) and last changed probe
                       // (irr, vis), replaced by their exclusive prefix by the scan
     uint32_t *totals;   // K_irr, K_vis (written by the scan)
     uint32_t *partial;  // per tile: checksum share of its plane words (written by the compaction)
@@ -80,7 +80,7 @@ hipError_t launch_pack_mask(const PackBuffers &b, int P, float tau_irr, float ta
 hipError_t launch_pack_scan(const PackBuffers &b, int P, hipStream_t s);
 hipError_t launch_pack_compact(const PackBuffers &b, int P, hipStream_t s);
 hipError_t launch_pack_finish(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s);
-constexpr int kPackTile = 16;  // probes per pack block
+constexpr int kPackTile = 8;   // probes per pack block
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 
 // Client-side unpack (receive.hip). The packet's header has been checked on

@@ -25,7 +25,8 @@ __device__ __forceinline__ bool texel_changed(uint16_t a, uint16_t b, float tau)
 // bytes of slack, so the last vector of a ragged tail stays in bounds). Work
 // is then split into row units of 8 interior texels of one channel:
 // irradiance 3 x 8 rows per probe, visibility 2 x 16 rows x 2 halves.
-constexpr int kPackQ = 16;
+constexpr int kPackQ = kPackTile;
+static_assert(kPackQ * 600 % 16 == 0 && kPackQ * 1296 % 16 == 0 && kPackQ <= 64, "aligned staging, one ballot");
 constexpr int kPackThreads = 256;
 constexpr int kIrrUnits = 3 * 8;       // per probe
 constexpr int kVisUnits = 2 * 16 * 2;  // per probe
