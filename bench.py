@@ -666,6 +666,20 @@ def main():
     ctx.set_timing(False)
     stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
 
+    # the same steps with the packet handed to the host each step (the
+    # boundary's host buffer: header, then payload over PCIe); reported
+    # beside the value, never as it
+    torch.cuda.synchronize()
+    pkt_bytes = 0
+    wall0 = time.perf_counter()
+    for i in range(W, W + K):
+        step(i)
+        pkt_bytes += len(cl.packet_download(stream=stream))
+    torch.cuda.synchronize()
+    pcie_ms = (time.perf_counter() - wall0) * 1e3 / K
+    pcie = {"ms_per_step": pcie_ms, "probe_rays_per_s": cfg.n_probes * cfg.rays_per_probe / (pcie_ms / 1e3),
+            "packet_bytes_mean": pkt_bytes / K}
+
     # algorithmic traversal work of the same frames (instrumented trace)
     node_visits = tri_tests = shadow = 0
     for i in range(W, W + K):
@@ -716,6 +730,7 @@ def main():
                      "trace_ms": trace_s * 1e3,
                      "flop_per_launch": flop_per_launch, "node_visits_per_ray": node_visits / (K * rays),
                      "tri_tests_per_ray": tri_tests / (K * rays), "shadow_rays_per_ray": shadow / (K * rays)},
+        "pcie_inclusive": pcie,
         "blend": {"ms": stage_ms["blend"], "hbm_GBps": blend_bytes / (stage_ms["blend"] / 1e3) / 1e9 if stage_ms["blend"] else None,
                   "hbm_frac": blend_bytes / (stage_ms["blend"] / 1e3) / PEAK_HBM if stage_ms["blend"] else None,
                   "alu_frac": blend_flop / (stage_ms["blend"] / 1e3) / PEAK_FP32_VECTOR if stage_ms["blend"] else None},

@@ -42,7 +42,7 @@ struct BatchVolume {
 // ---------------------------------------------------------------------------
 // Launchers (trace.hip, blend.hip, batched.hip, bounce.hip, pack.hip)
 // ---------------------------------------------------------------------------
-// Directions and weight tables; the 9 work counters are zeroed for the trace that follows
+// Ray directions; the 9 work counters are zeroed for the trace that follows
 hipError_t launch_raydirs(const FrameParams &fp, const VolumeParams &vp, float4 *dirs, int *queue, hipStream_t s);
 int raydir_blocks(int n);
 hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4 *rays, void *irr, void *vis,

@@ -11,10 +11,11 @@
 //     mean^2 hi); byte m of a texel row goes to sample m / 3 of plane m % 3,
 //     so three texels fill four YUV samples; a row of x = 16 C texels is
 //     ceil(4 x / 3) samples, the missing bytes zero
-// One thread per output sample (encode) or texel (decode): the writes of a
-// wavefront are contiguous, the reads gather short runs from the tiles. All
-// of it is a pure permutation of bytes plus one rounding per irradiance
-// value, so the kernels are bound by HBM.
+// Irradiance: one thread per output sample (encode) or texel (decode);
+// visibility encode: one thread per three texels (four samples per plane);
+// the writes of a wavefront are contiguous, the reads gather short runs
+// from the tiles. All of it is a pure permutation of bytes plus one rounding
+// per irradiance value, so the kernels are bound by HBM.
 #include "device_common.h"
 
 namespace pv {
@@ -45,26 +46,34 @@ __global__ __launch_bounds__(kYuvThreads) void k_yuv_irr_encode(const uint16_t *
     }
 }
 
+// One thread per group of three texels of a row (twelve bytes): it reads
+// each texel's two 16-bit values once and writes four consecutive samples
+// of each plane (byte 3k + c of the group is sample k of plane c).
 __global__ __launch_bounds__(kYuvThreads) void k_yuv_vis_encode(const uint16_t *vis, int P, int C, uint8_t *planes,
                                                                 int Wv, int Hv) {
+    const int x = 16 * C, G = (x + 2) / 3;
     const long long idx = (long long)blockIdx.x * kYuvThreads + threadIdx.x;
-    if (idx >= (long long)Wv * Hv) return;
-    const int row = (int)(idx / Wv), u = (int)(idx - (long long)row * Wv);
-    const int x = 16 * C, ty = row >> 4, j = row & 15;
-    const size_t plane = (size_t)Wv * Hv;
+    if (idx >= (long long)G * Hv) return;
+    const int row = (int)(idx / G), g = (int)(idx - (long long)row * G);
+    const int ty = row >> 4, j = row & 15;
+    uint32_t tex[3];
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        const int m = 3 * u + ch, col = m >> 2, b = m & 3;
-        uint8_t byte = 0;
-        if (col < x) {
-            const int p = ty * C + (col >> 4), i = col & 15;
-            if (p < P) {
-                const uint16_t h = vis[(((size_t)p * 2 + (b >> 1)) * 18 + j + 1) * 18 + i + 1];
-                byte = (uint8_t)((b & 1) ? h >> 8 : h & 0xFF);
-            }
+    for (int t = 0; t < 3; ++t) {
+        const int col = 3 * g + t, p = ty * C + (col >> 4), i = col & 15;
+        tex[t] = 0u;
+        if (col < x && p < P) {
+            const size_t at = (((size_t)p * 2) * 18 + j + 1) * 18 + i + 1;
+            tex[t] = (uint32_t)vis[at] | ((uint32_t)vis[at + 18 * 18] << 16);
         }
-        planes[ch * plane + idx] = byte;
     }
+    const size_t plane = (size_t)Wv * Hv, base = (size_t)row * Wv;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int m = 3 * k + c, u = 4 * g + k;
+            if (u < Wv) planes[c * plane + base + u] = (uint8_t)(tex[m >> 2] >> (8 * (m & 3)));
+        }
 }
 
 __global__ __launch_bounds__(kYuvThreads) void k_yuv_irr_decode(const uint16_t *planes, int P, int C, int W, int H,
@@ -103,8 +112,8 @@ hipError_t launch_yuv_encode(const uint16_t *irr, const uint16_t *vis, int P, in
                              uint8_t *vis_planes, const YuvDims &d, hipStream_t s) {
     hipLaunchKernelGGL(k_yuv_irr_encode, yuv_grid(d.w * d.h), dim3(kYuvThreads), 0, s, irr, P, C, k, irr_planes,
                        (int)d.w, (int)d.h);
-    hipLaunchKernelGGL(k_yuv_vis_encode, yuv_grid(d.wv * d.hv), dim3(kYuvThreads), 0, s, vis, P, C, vis_planes,
-                       (int)d.wv, (int)d.hv);
+    hipLaunchKernelGGL(k_yuv_vis_encode, yuv_grid((16ll * C + 2) / 3 * d.hv), dim3(kYuvThreads), 0, s, vis, P, C,
+                       vis_planes, (int)d.wv, (int)d.hv);
     return hipGetLastError();
 }
 

@@ -241,14 +241,17 @@ def test_dynamic_occluders(ps, ctx, O):
 
 
 # ------------------------------------------------------------------ blend from given rays
-@pytest.mark.parametrize("fp16,n,grid", [(False, 64, (37, 1, 1)), (False, 300, (3, 2, 2)),
-                                         (True, 256, (9, 5, 3)), (True, 513, (2, 1, 3))])
-def test_blend_from_given_rays(ps, ctx, O, fp16, n, grid):
+@pytest.mark.parametrize("fp16,n,grid,sharp", [(False, 64, (37, 1, 1), 50), (False, 300, (3, 2, 2), 50),
+                                               (True, 256, (9, 5, 3), 50), (True, 513, (2, 1, 3), 50),
+                                               (False, 96, (3, 1, 2), 7), (True, 4096, (2, 1, 1), 1),
+                                               (False, 130, (11, 1, 1), 128)])
+def test_blend_from_given_rays(ps, ctx, O, fp16, n, grid, sharp):
     """a4-a6 alone: both sides blend the same seeded ray records over five
-    frames of hysteresis."""
+    frames of hysteresis; visibility exponents other than 50 take the
+    blend's generic power, 4,096 rays its longest chunk loop."""
     import torch
-    _say(f"blend from given rays fp16={fp16} n={n} grid={grid}")
-    cfg = synth.VolumeConfig(*grid, (0, 0, 0), (1, 1, 1), n, fp16=fp16, max_distance=4.0)
+    _say(f"blend from given rays fp16={fp16} n={n} grid={grid} sharpness={sharp}")
+    cfg = synth.VolumeConfig(*grid, (0, 0, 0), (1, 1, 1), n, fp16=fp16, max_distance=4.0, vis_sharpness=sharp)
     vol = ps.Volume(ctx, cfg)
     irr_o, vis_o = O.empty_maps(cfg)
     for f in range(5):
@@ -266,8 +269,10 @@ def test_blend_from_given_rays(ps, ctx, O, fp16, n, grid):
                 d = ulps_from(g, o)
                 assert d.max() <= 2.0 and (d <= 1.0).mean() >= 0.999
         else:
+            # x^s carries about s times the FP32 rounding of its base, so the
+            # visibility bound grows with s up to the FP32 map bound (1e-4)
             assert excess_fp32(irr, irr_o, irr_o)[0] <= 1e-5
-            assert excess_fp32(vis, vis_o, vis_o)[0] <= 1e-5
+            assert excess_fp32(vis, vis_o, vis_o)[0] <= (1e-5 if sharp <= 50 else 1e-4)
         assert fold_consistent(irr) and fold_consistent(vis)
         del dev
     vol.close()
