@@ -182,8 +182,8 @@ pv_status pv_update_probes(pv_volume *vol, const pv_frame *frame, void *stream);
 
 /*
  * The same update for n volumes in one go, enqueued on 'stream': three
- * launches whatever n is -- ray directions and blend weights of every
- * volume, the trace of every wavefront packet of every volume, the blend of
+ * launches whatever n is -- ray directions of every volume, the trace of
+ * every wavefront packet of every volume, the blend of
  * every probe group of every volume -- so small volumes share the device
  * instead of each filling it alone. Results are bit-identical to n
  * pv_update_probes calls with the default trace launch shape.
