@@ -129,8 +129,12 @@ struct EntChunk {
     unsigned int bits;
     unsigned long long in_off, out_off;  // container / packet byte offsets
 };
+// Chunks per decode block (one wavefront, one chunk per lane; the decode of a
+// chunk is a serial chain of LDS lookups, so fewer chunks per wavefront
+// spread the chains over more SIMDs).
+constexpr int kEntDecodeChunks = 8;
 struct EntBlock {
-    int stream, first, n;    // up to 64 consecutive chunks of one stream
+    int stream, first, n;    // up to kEntDecodeChunks consecutive chunks of one stream
 };
 struct EntDecode {
     const uint8_t *in;       // the container

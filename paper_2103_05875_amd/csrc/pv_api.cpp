@@ -1634,8 +1634,8 @@ extern "C" pv_status pv_receiver_apply_compressed(pv_receiver *r, const void *co
         if (get_u32(in + off + 128) != nch) return fail(PV_ERR_ARG, "chunk count does not match the header");
         const uint8_t *bits_tab = in + off + 132;
         off += 132 + 4 * nch;
-        for (uint64_t c = 0; c < nch; c += 64)
-            blocks.push_back(EntBlock{k, (int)(chunks.size() + c), (int)std::min<uint64_t>(64, nch - c)});
+        for (uint64_t c = 0; c < nch; c += kEntDecodeChunks)
+            blocks.push_back(EntBlock{k, (int)(chunks.size() + c), (int)std::min<uint64_t>(kEntDecodeChunks, nch - c)});
         for (uint64_t c = 0; c < nch; ++c) {
             const uint32_t bits = get_u32(bits_tab + 4 * c);
             const uint64_t n_sym = std::min<uint64_t>(kHufChunk, n - c * kHufChunk);
