@@ -196,6 +196,17 @@ def summarize_counters(paths):
     return "\n".join(lines)
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, scene, path, budget_s: float):
     """The oracle as it stands on the host cores: full frames of the same
     workload (trace + shade, blend, pack), as many as fit the budget
@@ -219,12 +230,12 @@ def cpu_baseline(cfg, scene, path, budget_s: float):
         bv = vis.astype(np.float16).view(np.uint16)
         st.pack(bi, bv)
         frames += 1
-        if time.perf_counter() - t0 > budget_s or frames >= 50:
+        if time.perf_counter() - t0 > budget_s or frames >= 200:
             break
     dt = time.perf_counter() - t0
     rays_total = frames * cfg.n_probes * cfg.rays_per_probe
     return {"value": rays_total / dt, "unit": "probe-rays/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "probes_per_s": frames * cfg.n_probes / dt,
+            "cpu_model": _cpu_model(), "probes_per_s": frames * cfg.n_probes / dt,
             "sample": f"{frames} full frame(s) of the same workload (trace + shade, blend, pack), "
                       f"{dt:.1f} s wall, OpenMP over probes"}
 
@@ -668,6 +679,18 @@ def main():
     value = rays * K / (ms_per_step * K / 1e3)
     print(f"bench: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # per-step distribution: each step of the same frames bracketed by
+    # events on the launch stream
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for i, (a, b) in zip(range(W, W + K), evs):
+        a.record(stream)
+        step(i)
+        b.record(stream)
+    torch.cuda.synchronize()
+    per_step = np.array([a.elapsed_time(b) for a, b in evs])
+    step_dist = {"p50_ms": float(np.percentile(per_step, 50)), "p90_ms": float(np.percentile(per_step, 90)),
+                 "min_ms": float(per_step.min()), "max_ms": float(per_step.max())}
+
     # same steps again with every kernel bracketed by HIP events on its stream
     ctx.set_timing(True)
     ctx.stage_times()
@@ -706,6 +729,12 @@ def main():
 
     traffic, traffic_src = read_counters(args.counters, vol.get_trace_config())
 
+    # attainable ceilings of plain kernels on this device, beside the
+    # data-sheet peaks the fractions are quoted against
+    ceil = {"hbm_copy_GBps": ctx.measure_ceiling(ps.native.PV_CEIL_COPY) / 1e9,
+            "fma_f32_TFLOPs": ctx.measure_ceiling(ps.native.PV_CEIL_FMA_F32) / 1e12,
+            "mfma_f32_TFLOPs": ctx.measure_ceiling(ps.native.PV_CEIL_MFMA_F32) / 1e12}
+
     # HBM figures of the blend and pack kernels (algorithmic bytes)
     P, n = cfg.n_probes, cfg.rays_per_probe
     blend_bytes = P * (16 * n + (192 + 512) * 2 + (300 + 648) * 2)
@@ -741,8 +770,11 @@ def main():
                      "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
                      "trace_ms": trace_s * 1e3,
                      "flop_per_launch": flop_per_launch, "node_visits_per_ray": node_visits / (K * rays),
-                     "tri_tests_per_ray": tri_tests / (K * rays), "shadow_rays_per_ray": shadow / (K * rays)},
+                     "tri_tests_per_ray": tri_tests / (K * rays), "shadow_rays_per_ray": shadow / (K * rays),
+                     "frac_of_attainable_fma": achieved / (ceil["fma_f32_TFLOPs"] * 1e12)},
+        "ceilings": ceil,
         "pcie_inclusive": pcie,
+        "step_ms_distribution": step_dist,
         "blend": {"ms": stage_ms["blend"], "hbm_GBps": blend_bytes / (stage_ms["blend"] / 1e3) / 1e9 if stage_ms["blend"] else None,
                   "hbm_frac": blend_bytes / (stage_ms["blend"] / 1e3) / PEAK_HBM if stage_ms["blend"] else None,
                   "alu_frac": blend_flop / (stage_ms["blend"] / 1e3) / PEAK_FP32_VECTOR if stage_ms["blend"] else None},

@@ -454,10 +454,24 @@ pv_status pv_ctx_set_timing(pv_ctx *ctx, int enable);
 pv_status pv_ctx_stage_times(pv_ctx *ctx, double *ms, uint64_t *launches);
 
 /* Instrumented trace of one frame (for measurement): the same work as
- * pv_update_probes with per-ray counts of box-pair and triangle tests,
- * summed into counts[0] (node visits, two boxes each), counts[1] (triangle
+ * pv_update_probes with per-ray counts of node and triangle tests,
+ * summed into counts[0] (node visits, four child boxes each), counts[1] (triangle
  * tests), counts[2] (shadow rays). Synchronous. */
 pv_status pv_trace_counts(pv_volume *vol, const pv_frame *frame, uint64_t counts[3]);
+
+/* Attainable ceilings of the context's device (for measurement: what a plain
+ * kernel reaches, beside the data-sheet peaks):
+ *   PV_CEIL_COPY      float4 copy of 1 GiB; rate in bytes/s, read + write
+ *   PV_CEIL_FMA_F32   eight independent FP32 FMA chains per thread, no
+ *                     packed FP32; rate in FLOP/s (FMA = 2)
+ *   PV_CEIL_MFMA_F32  four independent 16x16x4 FP32 MFMA chains per
+ *                     wavefront; rate in FLOP/s
+ * 32 wavefronts per compute unit; one untimed warm-up, then the fastest of
+ * 'reps' launches (HIP events on the context's stream). Allocates and frees
+ * its own buffers (2 GiB for the copy). Synchronous. PV_ERR_ARG for an
+ * unknown kind or reps < 1. */
+enum { PV_CEIL_COPY = 0, PV_CEIL_FMA_F32 = 1, PV_CEIL_MFMA_F32 = 2 };
+pv_status pv_measure_ceiling(pv_ctx *ctx, int kind, int reps, double *rate);
 
 #pragma GCC visibility pop
 

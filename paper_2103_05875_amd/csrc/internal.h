@@ -55,6 +55,12 @@ hipError_t launch_blend_batched(const BatchVolume *vols_dev, int n_vols, int tot
 hipError_t launch_raydirs_batched(const BatchVolume *vols_dev, const FrameParams *frames_dev, int n_vols,
                                   int dir_blocks, hipStream_t s);
 
+// Attainable ceilings (ceilings.hip): stream copy, FP32 FMA chains, FP32
+// MFMA chains; 'out' holds blocks * 256 floats.
+hipError_t launch_ceil_copy(const void *src, void *dst, size_t bytes, int blocks, hipStream_t s);
+hipError_t launch_ceil_fma(float *out, int blocks, int iters, hipStream_t s);
+hipError_t launch_ceil_mfma(float *out, int blocks, int iters, hipStream_t s);
+
 // Second bounce (bounce.hip): adds albedo x the stored maps' query to every
 // hit record's radiance (vp.hitrec must be set); the client query.
 int bounce_blocks(int P, int n);

@@ -687,6 +687,58 @@ extern "C" pv_status pv_trace_counts(pv_volume *v, const pv_frame *f, uint64_t c
     return PV_OK;
 }
 
+extern "C" pv_status pv_measure_ceiling(pv_ctx *c, int kind, int reps, double *rate) {
+    if (!c || !rate) return fail(PV_ERR_ARG, "NULL argument");
+    if (kind < PV_CEIL_COPY || kind > PV_CEIL_MFMA_F32) return fail(PV_ERR_ARG, "unknown ceiling kind");
+    if (reps < 1) return fail(PV_ERR_ARG, "reps must be >= 1");
+    HIP_TRY(hipSetDevice(c->device));
+    int cus = 256;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    const int blocks = cus * 8;  // 32 wavefronts per CU
+    const size_t copy_bytes = (size_t)1 << 30;
+    const int fma_iters = 4096, mfma_iters = 1024;
+    void *a = nullptr, *b = nullptr;
+    pv_status st = PV_OK;
+    if (kind == PV_CEIL_COPY) {
+        st = dev_alloc(&a, copy_bytes, "ceiling copy source");
+        if (st == PV_OK) st = dev_alloc(&b, copy_bytes, "ceiling copy destination");
+    } else {
+        st = dev_alloc(&a, (size_t)blocks * 256 * sizeof(float), "ceiling output");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == PV_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        st = fail(PV_ERR_DEVICE, "event create");
+    hipStream_t s = c->stream;
+    auto run = [&]() -> hipError_t {
+        if (kind == PV_CEIL_COPY) return launch_ceil_copy(a, b, copy_bytes, blocks, s);
+        if (kind == PV_CEIL_FMA_F32) return launch_ceil_fma((float *)a, blocks, fma_iters, s);
+        return launch_ceil_mfma((float *)a, blocks, mfma_iters, s);
+    };
+    double best_ms = 0.0;
+    for (int r = -1; st == PV_OK && r < reps; ++r) {  // one untimed warm-up
+        if (hipEventRecord(e0, s) != hipSuccess || run() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess) {
+            st = fail(PV_ERR_DEVICE, "ceiling kernel");
+            break;
+        }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = fail(PV_ERR_DEVICE, "event time");
+        if (r >= 0 && (best_ms == 0.0 || ms < best_ms)) best_ms = ms;
+    }
+    if (st == PV_OK) {
+        const double threads = (double)blocks * 256;
+        const double work = kind == PV_CEIL_COPY    ? 2.0 * (double)copy_bytes
+                            : kind == PV_CEIL_FMA_F32 ? threads * fma_iters * 8 * 2
+                                                      : threads / 64 * mfma_iters * 4 * 2048.0;
+        *rate = work / (best_ms * 1e-3);
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(a);
+    hipFree(b);
+    return st;
+}
+
 extern "C" pv_status pv_blend_rays(pv_volume *v, const pv_frame *f, const void *rays_dev, void *stream) {
     if (!v || !rays_dev) return fail(PV_ERR_ARG, "NULL argument");
     FrameParams fp;

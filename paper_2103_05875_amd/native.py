@@ -22,6 +22,8 @@ PV_FIRST_FRAME_NO_HISTORY = 1
 PV_KEEP_HITS = 2
 PV_MULTI_BOUNCE = 4
 PV_CLASSIFY = 8
+# pv_measure_ceiling kinds
+PV_CEIL_COPY, PV_CEIL_FMA_F32, PV_CEIL_MFMA_F32 = 0, 1, 2
 PV_MAX_LIGHTS = 8
 
 # every symbol include/probestream.h declares
@@ -32,7 +34,7 @@ EXPORTED_SYMBOLS = [
     "pv_blend_rays", "pv_get_maps", "pv_get_rays", "pv_set_maps", "pv_read_maps",
     "pv_client_create", "pv_client_destroy", "pv_client_reset", "pv_client_footprint",
     "pv_pack_delta", "pv_packet_device", "pv_packet_download", "pv_get_masks", "pv_sync",
-    "pv_trace_counts", "pv_ctx_set_timing", "pv_ctx_stage_times",
+    "pv_trace_counts", "pv_measure_ceiling", "pv_ctx_set_timing", "pv_ctx_stage_times",
     "pv_client_read_state", "pv_client_set_state", "pv_volume_set_trace_config", "pv_volume_get_trace_config",
     "pv_batch_graph_create", "pv_batch_graph_launch", "pv_batch_graph_destroy", "pv_probe_query",
     "pv_receiver_create", "pv_receiver_destroy", "pv_receiver_apply", "pv_receiver_status",
@@ -151,6 +153,7 @@ def lib():
         "pv_get_masks": ([vp, P(vp), P(vp)], i32),
         "pv_sync": ([vp], i32),
         "pv_trace_counts": ([vp, P(Frame), P(u64)], i32),
+        "pv_measure_ceiling": ([vp, i32, i32, P(ctypes.c_double)], i32),
         "pv_ctx_set_timing": ([vp, i32], i32),
         "pv_client_read_state": ([vp, vp, vp, P(u32)], i32),
         "pv_volume_set_trace_config": ([vp, P(TraceConfig)], i32),
@@ -239,6 +242,13 @@ class Context:
         cnt = (ctypes.c_uint64 * len(STAGES))()
         _check(lib().pv_ctx_stage_times(self.h, ms, cnt))
         return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
+
+    def measure_ceiling(self, kind: int, reps: int = 5) -> float:
+        """Attainable rate of a plain kernel on this device: bytes/s for
+        PV_CEIL_COPY, FLOP/s for PV_CEIL_FMA_F32 and PV_CEIL_MFMA_F32."""
+        r = ctypes.c_double(0.0)
+        _check(lib().pv_measure_ceiling(self.h, int(kind), int(reps), ctypes.byref(r)))
+        return r.value
 
     def close(self):
         if getattr(self, "h", None):

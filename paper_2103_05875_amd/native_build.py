@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libprobestream.so")
-SOURCES = ["trace.hip", "blend.hip", "batched.hip", "bounce.hip", "select.hip", "pack.hip", "entropy.hip", "receive.hip", "yuv.hip", "bvh.cpp", "pv_api.cpp"]
+SOURCES = ["trace.hip", "blend.hip", "batched.hip", "bounce.hip", "select.hip", "pack.hip", "entropy.hip", "receive.hip", "yuv.hip", "ceilings.hip", "bvh.cpp", "pv_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
