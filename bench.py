@@ -389,6 +389,8 @@ def leg_encode(ps, torch, frames: int):
         l = scene_syn.lights.copy()
         l[0, :3] = path[f]
         vol.update_probes(synth.rotation(41, f), l, stream=stream)
+        if f == frames - 1:
+            saved = cl.read_state()   # the client before the last pack (timed again below)
         cl.pack_delta(1.0 / 1024, 1.0 / 1024, stream=stream)
         pkt = cl.packet_download(stream=stream)
         sent_bytes += len(pkt)
@@ -407,7 +409,35 @@ def leg_encode(ps, torch, frames: int):
     st = ctx.stage_times()
     ctx.set_timing(False)
     P = cfg.n_probes
-    pack_ms = sum(st[k][0] for k in ("pack_mask", "pack_scan", "pack_compact", "pack_finish")) / frames
+    pack_keys = ("pack_mask", "pack_scan", "pack_compact", "pack_finish")
+    pack_ms = sum(st[k][0] for k in pack_keys) / frames
+
+    # the last frame's pack again, warm and cold (1 GiB streamed through the
+    # caches first; the maps, reference and packet, about 80 MB, would
+    # otherwise sit in the 256 MB last-level cache): the client's state before
+    # that pack is restored before every repetition
+    flush_a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    flush_b = torch.empty_like(flush_a)
+
+    def pack_again(cold: bool) -> float:
+        times = []
+        for _ in range(6):
+            cl.set_state(*saved)
+            if cold:
+                flush_b.copy_(flush_a)
+            torch.cuda.synchronize()
+            ctx.set_timing(True)
+            ctx.stage_times()
+            cl.pack_delta(1.0 / 1024, 1.0 / 1024, stream=stream)
+            s2 = ctx.stage_times()
+            ctx.set_timing(False)
+            times.append(sum(s2[k][0] for k in pack_keys))
+        return float(np.median(times[1:]))
+
+    warm_ms, cold_ms = pack_again(False), pack_again(True)
+    del flush_a, flush_b
+    ci, cv = changed[-1]
+    last_bytes = P * 1408 * 2 + (ci * 384 + cv * 1024) * 2 + P * 2
     ki = np.mean([c[0] for c in changed])
     kv = np.mean([c[1] for c in changed])
     pack_bytes = P * 1408 * 2 + (ki * 384 + kv * 1024) * 2 + P * 2
@@ -424,6 +454,9 @@ def leg_encode(ps, torch, frames: int):
            "mean_changed_vis": kv, "packet_bytes_per_frame": sent_bytes / frames,
            "Mbps_at_10Hz": sent_bytes / frames * 8 * 10 / 1e6,
            "update_ms": upd_ms, "probe_rays_per_s": P * cfg.rays_per_probe / (upd_ms / 1e3),
+           "pack_last_frame": {"bytes": last_bytes, "warm_ms": warm_ms, "cold_ms": cold_ms,
+                               "warm_hbm_frac": last_bytes / (warm_ms / 1e3) / PEAK_HBM,
+                               "cold_hbm_frac": last_bytes / (cold_ms / 1e3) / PEAK_HBM},
            "pack_ms": pack_ms, "pack_hbm_GBps": pack_bytes / (pack_ms / 1e3) / 1e9,
            "pack_hbm_frac": pack_bytes / (pack_ms / 1e3) / PEAK_HBM}
     for h in (rx, cl, vol, sc, ctx):
