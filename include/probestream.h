@@ -278,6 +278,13 @@ pv_status pv_packet_device(pv_client *client, const void **packet_dev, uint64_t 
  * bytes to host_buf. PV_ERR_CAPACITY with *bytes = needed size when cap is
  * too small. */
 pv_status pv_packet_download(pv_client *client, void *host_buf, uint64_t cap, uint64_t *bytes, void *stream);
+/* Synchronous: wait for the last pack on 'stream' and copy the packet into
+ * the client's own pinned host staging (allocated, or grown, on first use
+ * to the packet's size); *host_ptr receives that borrowed pointer, valid
+ * until the next pv_packet_stage or pv_packet_download on the client or its
+ * destruction, and *bytes the packet's size. For callers that copy the
+ * bytes out themselves: one device-to-host transfer at pinned rate. */
+pv_status pv_packet_stage(pv_client *client, const void **host_ptr, uint64_t *bytes, void *stream);
 /* Client reference export / import (host buffers [P][3][64] and
  * [P][2][256] uint16, plus the sequence counter); synchronous. Lets a
  * server evict a client's state from HBM and bring it back later. */

@@ -137,6 +137,8 @@ struct pv_client {
     uint8_t *packet = nullptr;
     uint64_t packet_cap = 0;
     uint32_t *hdr_host = nullptr;  // pinned, 32 bytes
+    uint8_t *stage_host = nullptr; // pinned packet staging (grown on demand)
+    uint64_t stage_cap = 0;
     uint8_t *view = nullptr;       // [P] visible set of the last pv_client_set_view
     bool view_on = false;
     // entropy stage (allocated on first use)
@@ -1111,6 +1113,7 @@ static void free_client(pv_client *c) {
     if (c->ent_total_host) hipHostFree(c->ent_total_host);
     if (c->ent_tables_host) hipHostFree(c->ent_tables_host);
     if (c->hdr_host) hipHostFree(c->hdr_host);
+    if (c->stage_host) hipHostFree(c->stage_host);
     delete c;
 }
 
@@ -1232,20 +1235,48 @@ extern "C" pv_status pv_get_masks(pv_client *c, void **mi, void **mv) {
     return PV_OK;
 }
 
+// Waits for the last pack on s and copies the whole packet into the
+// client's pinned staging (D2H at full PCIe rate, no pageable bounce).
+static pv_status stage_packet(pv_client *c, hipStream_t s, uint64_t *bytes) {
+    HIP_TRY(hipMemcpyAsync(c->hdr_host, c->packet, 32, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t K_irr = c->hdr_host[kHdrKIrr], K_vis = c->hdr_host[kHdrKVis];
+    if (c->hdr_host[kHdrMagic] != kPacketMagic) return fail(PV_ERR_STATE, "no packet has been built");
+    const uint64_t total = packet_bytes(K_irr, K_vis);
+    if (total > c->stage_cap) {
+        if (c->stage_host) hipHostFree(c->stage_host);
+        c->stage_host = nullptr;
+        c->stage_cap = 0;
+        if (hipHostMalloc((void **)&c->stage_host, total) != hipSuccess) return fail(PV_ERR_OOM, "pinned packet staging");
+        c->stage_cap = total;
+    }
+    std::memcpy(c->stage_host, c->hdr_host, 32);
+    if (total > 32) HIP_TRY(hipMemcpyAsync(c->stage_host + 32, c->packet + 32, total - 32, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *bytes = total;
+    return PV_OK;
+}
+
 extern "C" pv_status pv_packet_download(pv_client *c, void *host, uint64_t cap, uint64_t *bytes, void *stream) {
     if (!c || !bytes) return fail(PV_ERR_ARG, "NULL argument");
     HIP_TRY(hipSetDevice(c->vol->ctx->device));
     hipStream_t s = pick(c->vol->ctx, stream);
     HIP_TRY(hipMemcpyAsync(c->hdr_host, c->packet, 32, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    const uint32_t K_irr = c->hdr_host[kHdrKIrr], K_vis = c->hdr_host[kHdrKVis];
     if (c->hdr_host[kHdrMagic] != kPacketMagic) return fail(PV_ERR_STATE, "no packet has been built");
-    const uint64_t total = packet_bytes(K_irr, K_vis);
+    const uint64_t total = packet_bytes(c->hdr_host[kHdrKIrr], c->hdr_host[kHdrKVis]);
     *bytes = total;
     if (!host || cap < total) return fail(PV_ERR_CAPACITY, "packet needs " + std::to_string(total) + " bytes");
-    std::memcpy(host, c->hdr_host, 32);
-    if (total > 32) HIP_TRY(hipMemcpyAsync((char *)host + 32, c->packet + 32, total - 32, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    PV_TRY(stage_packet(c, s, bytes));
+    std::memcpy(host, c->stage_host, total);
+    return PV_OK;
+}
+
+extern "C" pv_status pv_packet_stage(pv_client *c, const void **host_ptr, uint64_t *bytes, void *stream) {
+    if (!c || !host_ptr || !bytes) return fail(PV_ERR_ARG, "NULL argument");
+    HIP_TRY(hipSetDevice(c->vol->ctx->device));
+    PV_TRY(stage_packet(c, pick(c->vol->ctx, stream), bytes));
+    *host_ptr = c->stage_host;
     return PV_OK;
 }
 

@@ -34,7 +34,7 @@ EXPORTED_SYMBOLS = [
     "pv_blend_rays", "pv_get_maps", "pv_get_rays", "pv_set_maps", "pv_read_maps",
     "pv_client_create", "pv_client_destroy", "pv_client_reset", "pv_client_footprint",
     "pv_pack_delta", "pv_packet_device", "pv_packet_download", "pv_get_masks", "pv_sync",
-    "pv_trace_counts", "pv_measure_ceiling", "pv_ctx_set_timing", "pv_ctx_stage_times",
+    "pv_trace_counts", "pv_measure_ceiling", "pv_packet_stage", "pv_ctx_set_timing", "pv_ctx_stage_times",
     "pv_client_read_state", "pv_client_set_state", "pv_volume_set_trace_config", "pv_volume_get_trace_config",
     "pv_batch_graph_create", "pv_batch_graph_launch", "pv_batch_graph_destroy", "pv_probe_query",
     "pv_receiver_create", "pv_receiver_destroy", "pv_receiver_apply", "pv_receiver_status",
@@ -154,6 +154,7 @@ def lib():
         "pv_sync": ([vp], i32),
         "pv_trace_counts": ([vp, P(Frame), P(u64)], i32),
         "pv_measure_ceiling": ([vp, i32, i32, P(ctypes.c_double)], i32),
+        "pv_packet_stage": ([vp, P(ctypes.c_void_p), P(u64), vp], i32),
         "pv_ctx_set_timing": ([vp, i32], i32),
         "pv_client_read_state": ([vp, vp, vp, P(u32)], i32),
         "pv_volume_set_trace_config": ([vp, P(TraceConfig)], i32),
@@ -564,12 +565,21 @@ class Client:
         _check(lib().pv_packet_device(self.h, ctypes.byref(p), ctypes.byref(cap)))
         return p.value, cap.value
 
+    def packet_stage(self, stream=None):
+        """Waits for the pack on 'stream' and stages the packet in the
+        client's pinned host buffer: (address, size), borrowed until the next
+        stage or download on this client."""
+        ptr, nb = ctypes.c_void_p(), ctypes.c_uint64(0)
+        _check(lib().pv_packet_stage(self.h, ctypes.byref(ptr), ctypes.byref(nb), _stream_handle(stream)))
+        return ptr.value, nb.value
+
     def packet_download(self, stream=None) -> bytes:
-        _, cap = self.packet_device()
-        buf = np.zeros(cap, np.uint8)
-        nb = ctypes.c_uint64(0)
-        _check(lib().pv_packet_download(self.h, buf.ctypes.data, cap, ctypes.byref(nb), _stream_handle(stream)))
-        return buf[:nb.value].tobytes()
+        """The last packet as bytes (waits for the pack on 'stream'): staged
+        in the client's pinned host buffer, then copied once into the
+        returned object."""
+        ptr, nb = ctypes.c_void_p(), ctypes.c_uint64(0)
+        _check(lib().pv_packet_stage(self.h, ctypes.byref(ptr), ctypes.byref(nb), _stream_handle(stream)))
+        return ctypes.string_at(ptr.value, nb.value)
 
     def read_state(self):
         P = self.volume.P

@@ -12,11 +12,12 @@ memory are free. Admission is by device footprint against a budget; idle
 clients are evicted to host memory (bit-exact) and brought back on demand.
 
 All GPU work goes through the C ABI (``pv_update_probes_batched``,
-``pv_pack_delta``, ``pv_packet_download``); this module only schedules.
+``pv_pack_delta``, ``pv_packet_stage``); this module only schedules.
 """
 from __future__ import annotations
 
 import collections
+import ctypes
 import dataclasses
 import time
 from typing import Dict, List, Optional
@@ -33,7 +34,9 @@ class Request:
     lights: np.ndarray
     arrival: float                 # seconds on the server clock
     done: Optional[float] = None
-    packet: Optional[bytes] = None
+    packet: Optional[bytes] = None   # the packet (keep_packets), else None
+    header: Optional[bytes] = None   # its 32-byte header (sizes, sequence, payload checksum)
+    nbytes: int = 0
     batch_size: int = 0
 
 
@@ -53,7 +56,7 @@ class _ClientSlot:
 class Server:
     def __init__(self, ctx: native.Context, scene: native.Scene, configs: List, hbm_budget: int,
                  n_streams: int = 3, max_batch: int = 32, tau_irr: float = 0.0, tau_vis: float = 0.0,
-                 max_wait_s: float = 0.05):
+                 max_wait_s: float = 0.05, keep_packets: bool = True):
         import torch
         self.ctx = ctx
         self.scene = scene
@@ -74,6 +77,9 @@ class Server:
         # a request whose client is not resident waits at most this long before
         # it may evict others; until then resident clients go first
         self.max_wait_s = max_wait_s
+        # False: a request completes when its packet is in (pinned) host
+        # memory, and only its header is kept (a server hands the bytes on)
+        self.keep_packets = keep_packets
 
     # -------------------------------------------------------------- memory
     def _make_resident(self, slot: _ClientSlot, now: float) -> bool:
@@ -134,7 +140,7 @@ class Server:
             return []
         out = []
         for r in reqs:
-            r.packet = self.slots[r.client].client.packet_download(stream=self.streams[k])
+            _deliver(r, self.slots[r.client].client, self.streams[k], self.keep_packets)
             r.done = clock()
             r.batch_size = len(reqs)
             self.slots[r.client].busy = False
@@ -199,8 +205,18 @@ class Server:
             s.client = s.volume = None
 
 
+def _deliver(r: Request, client: native.Client, stream, keep: bool):
+    if keep:
+        r.packet = client.packet_download(stream=stream)
+        r.header, r.nbytes = r.packet[:32], len(r.packet)
+    else:
+        ptr, r.nbytes = client.packet_stage(stream=stream)
+        r.header = ctypes.string_at(ptr, 32)
+
+
 def serve_plain(ctx: native.Context, scene: native.Scene, configs: List, requests: List[Request],
-                tau_irr: float = 0.0, tau_vis: float = 0.0, timeout_s: float = 600.0) -> List[Request]:
+                tau_irr: float = 0.0, tau_vis: float = 0.0, timeout_s: float = 600.0,
+                keep_packets: bool = True) -> List[Request]:
     """The same trace served one request at a time (update, pack, download),
     with every client's state resident: the per-request path that the
     batched server is compared against."""
@@ -223,7 +239,7 @@ def serve_plain(ctx: native.Context, scene: native.Scene, configs: List, request
                 raise TimeoutError("plain path exceeded its time limit")
             vols[r.client].update_probes(r.rotation, r.lights)
             cls[r.client].pack_delta(tau_irr, tau_vis)
-            r.packet = cls[r.client].packet_download()
+            _deliver(r, cls[r.client], None, keep_packets)
             r.done = time.perf_counter() - t0
             r.batch_size = 1
             out.append(r)

@@ -52,6 +52,7 @@ def test_null_handles_and_destroy_null(ps):
     assert L.pv_pack_delta(None, 0.0, 0.0, None) == -1
     assert L.pv_probe_query(None, None, None, 1, None, None) == -1
     assert L.pv_measure_ceiling(None, 0, 1, None) == -1
+    assert L.pv_packet_stage(None, None, None, None) == -1
 
 
 def _fp(ps, cfg, **kw):

@@ -162,3 +162,26 @@ def test_receiver_full_size_volume(ps, ctx, O):
         assert np.array_equal(gi, dec.irr) and np.array_equal(gv, dec.vis)
     for h in (rx, cl, vol):
         h.close()
+
+
+def test_packet_download_entry_points_agree(ps, ctx):
+    """pv_packet_download into a caller buffer and pv_packet_stage (the
+    binding's path) return the same bytes; a short buffer is refused with
+    the needed size."""
+    import ctypes
+    _say("packet download vs pinned staging")
+    scene, cfg, sc, vol = _server(ps, ctx, nx=4, ny=4, nz=4, n=64, tris=3000)
+    cl = ps.Client(vol, client_id=3)
+    L = ps.lib()
+    for f in range(3):
+        vol.update_probes(synth.rotation(31, f))
+        cl.pack_delta(0.0, 1.0 / 1024)
+        staged = cl.packet_download()
+        nb = ctypes.c_uint64(0)
+        assert L.pv_packet_download(cl.h, None, 0, ctypes.byref(nb), None) == -5   # PV_ERR_CAPACITY
+        assert nb.value == len(staged)
+        buf = (ctypes.c_uint8 * nb.value)()
+        assert L.pv_packet_download(cl.h, buf, nb.value, ctypes.byref(nb), None) == 0
+        assert bytes(buf) == staged
+    for h in (cl, vol, sc):
+        h.close()
