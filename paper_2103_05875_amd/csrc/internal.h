@@ -87,6 +87,11 @@ hipError_t launch_pack_scan(const PackBuffers &b, int P, hipStream_t s);
 hipError_t launch_pack_compact(const PackBuffers &b, int P, hipStream_t s);
 hipError_t launch_pack_finish(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s);
 constexpr int kPackTile = 8;   // probes per pack block
+// Up to this many tiles every compaction block reduces the tile summaries
+// itself and the scan launch is skipped (its few microseconds of launch
+// latency exceed the redundant reads); above it the one-block scan runs.
+constexpr int kPackFusedTiles = 2048;
+bool pack_fused(int P);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 
 // Client-side unpack (receive.hip). The packet's header has been checked on

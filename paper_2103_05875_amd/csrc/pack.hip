@@ -228,19 +228,79 @@ __global__ __launch_bounds__(kScanThreads) void k_pack_scan(PackBuffers b, int n
     }
 }
 
-// Compaction of one tile: its changed probes' ranks (the tile's prefix from
-// the scan plus the changed lanes below), their delta-coded index entries,
-// XOR byte planes and reference update, and the plane words' checksum share
-// (summed by the finish kernel with the index section's).
+// Sums (x, y) and maxima (z, w) of the mask pass's tile summaries over
+// tiles [0, upto) and the totals over all n_tiles, reduced by the whole
+// block (every thread must call it).
+template <int T>
+__device__ __forceinline__ void reduce_tiles(const int4 *tiles, int n_tiles, int upto, int4 &before, int2 &total,
+                                             int4 *sh) {
+    int4 pre = make_int4(0, 0, -1, -1);
+    int2 tot = make_int2(0, 0);
+    for (int t = threadIdx.x; t < n_tiles; t += T) {
+        const int4 v = tiles[t];
+        tot.x += v.x;
+        tot.y += v.y;
+        if (t < upto) {
+            pre.x += v.x;
+            pre.y += v.y;
+            pre.z = max(pre.z, v.z);
+            pre.w = max(pre.w, v.w);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        pre.x += __shfl_xor(pre.x, off);
+        pre.y += __shfl_xor(pre.y, off);
+        pre.z = max(pre.z, __shfl_xor(pre.z, off));
+        pre.w = max(pre.w, __shfl_xor(pre.w, off));
+        tot.x += __shfl_xor(tot.x, off);
+        tot.y += __shfl_xor(tot.y, off);
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[2 * wv] = pre;
+        sh[2 * wv + 1] = make_int4(tot.x, tot.y, 0, 0);
+    }
+    __syncthreads();
+    before = make_int4(0, 0, -1, -1);
+    total = make_int2(0, 0);
+    for (int w = 0; w < T / 64; ++w) {
+        const int4 a = sh[2 * w], c = sh[2 * w + 1];
+        before.x += a.x;
+        before.y += a.y;
+        before.z = max(before.z, a.z);
+        before.w = max(before.w, a.w);
+        total.x += c.x;
+        total.y += c.y;
+    }
+    __syncthreads();
+}
+
+// Compaction of one tile: its changed probes' ranks (the tile's prefix plus
+// the changed lanes below), their delta-coded index entries, XOR byte planes
+// and reference update, and the plane words' checksum share (summed by the
+// finish kernel with the index section's). FUSED: the block reduces the
+// tile summaries itself (small tile counts, no scan launch); otherwise the
+// scan left the prefix in the tile's summary and the totals.
+template <bool FUSED>
 __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, int P) {
     __shared__ PackSmem sm;
     __shared__ int rank_s[kPackQ][2];
     __shared__ int any_s;
+    __shared__ int4 red[2 * kPackThreads / 64];
     const int tile = blockIdx.x, p0 = tile * kPackQ;
     const int n = min(kPackQ, P - p0);
-    // the prefix before this tile and the totals (from the scan)
-    const int4 before = b.tiles[tile];
-    const int K_irr = (int)b.totals[0], K_vis = (int)b.totals[1];
+    int4 before;
+    int K_irr, K_vis;
+    if (FUSED) {
+        int2 tot;
+        reduce_tiles<kPackThreads>(b.tiles, (P + kPackQ - 1) / kPackQ, tile, before, tot, red);
+        K_irr = tot.x;
+        K_vis = tot.y;
+    } else {
+        before = b.tiles[tile];
+        K_irr = (int)b.totals[0];
+        K_vis = (int)b.totals[1];
+    }
     const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
     uint16_t *idx_i = reinterpret_cast<uint16_t *>(b.packet + 32);
     uint16_t *idx_v = idx_i + K_irr;
@@ -319,11 +379,23 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
 }
 
 // One block: pads and hashes the index section, adds the compaction blocks'
-// plane hashes, writes the header.
+// plane hashes, writes the header (FUSED: the totals from the tile summaries).
+template <bool FUSED>
 __global__ __launch_bounds__(kScanThreads) void k_pack_finish(PackBuffers b, int P, int n_tiles, uint32_t client,
                                                              uint32_t seq) {
     __shared__ uint32_t sh[kScanThreads / 64];
-    const int K_irr = (int)b.totals[0], K_vis = (int)b.totals[1];
+    __shared__ int4 red[2 * kScanThreads / 64];
+    int K_irr, K_vis;
+    if (FUSED) {
+        int4 none;
+        int2 tot;
+        reduce_tiles<kScanThreads>(b.tiles, n_tiles, 0, none, tot, red);
+        K_irr = tot.x;
+        K_vis = tot.y;
+    } else {
+        K_irr = (int)b.totals[0];
+        K_vis = (int)b.totals[1];
+    }
     const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
     uint8_t *pk = b.packet;
     if (threadIdx.x < 16) {
@@ -368,13 +440,22 @@ hipError_t launch_pack_scan(const PackBuffers &b, int P, hipStream_t s) {
     return hipGetLastError();
 }
 
+bool pack_fused(int P) { return (P + kPackQ - 1) / kPackQ <= kPackFusedTiles; }
+
 hipError_t launch_pack_compact(const PackBuffers &b, int P, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_compact, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P);
+    if (pack_fused(P))
+        hipLaunchKernelGGL(k_pack_compact<true>, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P);
+    else
+        hipLaunchKernelGGL(k_pack_compact<false>, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P);
     return hipGetLastError();
 }
 
 hipError_t launch_pack_finish(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_finish, dim3(1), dim3(kScanThreads), 0, s, b, P, (P + kPackQ - 1) / kPackQ, client, seq);
+    const int n_tiles = (P + kPackQ - 1) / kPackQ;
+    if (pack_fused(P))
+        hipLaunchKernelGGL(k_pack_finish<true>, dim3(1), dim3(kScanThreads), 0, s, b, P, n_tiles, client, seq);
+    else
+        hipLaunchKernelGGL(k_pack_finish<false>, dim3(1), dim3(kScanThreads), 0, s, b, P, n_tiles, client, seq);
     return hipGetLastError();
 }
 

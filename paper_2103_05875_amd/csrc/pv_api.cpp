@@ -1194,7 +1194,7 @@ extern "C" pv_status pv_pack_delta(pv_client *c, float tau_irr, float tau_vis, v
     const int P = v->P;
     const uint32_t id = c->id, seq = c->seq;
     HIP_TRY(timed(cx, PV_STAGE_PACK_MASK, s, [&] { return launch_pack_mask(b, P, tau_irr, tau_vis, s); }));
-    HIP_TRY(timed(cx, PV_STAGE_PACK_SCAN, s, [&] { return launch_pack_scan(b, P, s); }));
+    if (!pack_fused(P)) HIP_TRY(timed(cx, PV_STAGE_PACK_SCAN, s, [&] { return launch_pack_scan(b, P, s); }));
     HIP_TRY(timed(cx, PV_STAGE_PACK_COMPACT, s, [&] { return launch_pack_compact(b, P, s); }));
     HIP_TRY(timed(cx, PV_STAGE_PACK_FINISH, s, [&] { return launch_pack_finish(b, P, id, seq, s); }));
     c->seq++;
