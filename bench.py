@@ -147,7 +147,9 @@ def write_counters(fetch_csv, write_csv, out, trace_config):
     res = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = load(path, counter)
-        copy = max(v for k, v in rows if "copyBuffer" in k or "copy" in k.lower())
+        # the calibration copy is the runtime's blit kernel (the ceiling
+        # kernels' own 1 GiB copy is not it)
+        copy = max(v for k, v in rows if "copyBuffer" in k)
         trace = [v for k, v in rows if is_trace_kernel(k)]
         res[counter] = {"copy_kib": copy, "scale": COPY_BYTES / (copy * 1024.0),
                         "trace_kib": sum(trace) / len(trace), "n": len(trace)}
