@@ -275,15 +275,18 @@ pv_status pv_pack_delta(pv_client *client, float tau_irr, float tau_vis, void *s
 /* Borrowed device pointer to the packet buffer and its capacity. */
 pv_status pv_packet_device(pv_client *client, const void **packet_dev, uint64_t *capacity);
 /* Synchronous: wait for the last pack on 'stream', copy only the packet's
- * bytes to host_buf. PV_ERR_CAPACITY with *bytes = needed size when cap is
- * too small. */
+ * bytes to host_buf (Sec. 4: only the compressed data crosses to the host).
+ * PV_ERR_CAPACITY with *bytes = needed size when cap is too small;
+ * PV_ERR_STATE before the first pack. */
 pv_status pv_packet_download(pv_client *client, void *host_buf, uint64_t cap, uint64_t *bytes, void *stream);
 /* Synchronous: wait for the last pack on 'stream' and copy the packet into
  * the client's own pinned host staging (allocated, or grown, on first use
  * to the packet's size); *host_ptr receives that borrowed pointer, valid
  * until the next pv_packet_stage or pv_packet_download on the client or its
  * destruction, and *bytes the packet's size. For callers that copy the
- * bytes out themselves: one device-to-host transfer at pinned rate. */
+ * bytes out themselves: one device-to-host transfer at pinned rate (Sec. 4:
+ * only the packet crosses to the host). PV_ERR_STATE before the first pack,
+ * PV_ERR_OOM when the staging cannot be allocated. */
 pv_status pv_packet_stage(pv_client *client, const void **host_ptr, uint64_t *bytes, void *stream);
 /* Client reference export / import (host buffers [P][3][64] and
  * [P][2][256] uint16, plus the sequence counter); synchronous. Lets a
@@ -476,7 +479,8 @@ pv_status pv_trace_counts(pv_volume *vol, const pv_frame *frame, uint64_t counts
  * 32 wavefronts per compute unit; one untimed warm-up, then the fastest of
  * 'reps' launches (HIP events on the context's stream). Allocates and frees
  * its own buffers (2 GiB for the copy). Synchronous. PV_ERR_ARG for an
- * unknown kind or reps < 1. */
+ * unknown kind or reps < 1, PV_ERR_OOM when the buffers cannot be allocated.
+ * Measurement support only; no part of the paper's method. */
 enum { PV_CEIL_COPY = 0, PV_CEIL_FMA_F32 = 1, PV_CEIL_MFMA_F32 = 2 };
 pv_status pv_measure_ceiling(pv_ctx *ctx, int kind, int reps, double *rate);
 
