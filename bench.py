@@ -160,12 +160,12 @@ def write_counters(fetch_csv, write_csv, out, trace_config):
                 "city workload\n")
         f.write("# counters per dispatch from rocprofv3 --pmc, one counter per run; each scaled by what the\n")
         f.write("# same counter reads for a 256 MiB device-to-device copy (reads and writes 268435456 bytes)\n")
-        f.write("# commands (GPU box, repository root, TMPDIR=/tmp), then on any host:\n")
+        f.write("# commands (MI355X host, repository root, TMPDIR=/tmp), then on any host:\n")
         for c in ("FETCH_SIZE", "WRITE_SIZE"):
-            f.write(f"#   rocprofv3 --pmc {c} -f csv -d gpurun_out/pmc_{c} -o pmc -- python3 bench.py --steps 3 "
+            f.write(f"#   rocprofv3 --pmc {c} -f csv -d OUT_DIR/pmc_{c} -o pmc -- python3 bench.py --steps 3 "
                     f"--warmup 1 --legs none --no-cpu-baseline --calibrate-copy --trace-config {trace_config}\n")
-        f.write("#   python3 bench.py --write-counters gpurun_out/pmc_FETCH_SIZE/pmc_counter_collection.csv "
-                f"gpurun_out/pmc_WRITE_SIZE/pmc_counter_collection.csv OUT --trace-config {trace_config}\n")
+        f.write("#   python3 bench.py --write-counters OUT_DIR/pmc_FETCH_SIZE/pmc_counter_collection.csv "
+                f"OUT_DIR/pmc_WRITE_SIZE/pmc_counter_collection.csv OUT --trace-config {trace_config}\n")
         for c, r in res.items():
             f.write(f"{c.lower()}_copy_kib: {r['copy_kib']:.1f}\n")
             f.write(f"{c.lower()}_scale: {r['scale']:.4f}\n")
@@ -645,7 +645,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(this build runs the hot path on a single GPU and has no cross-GPU exchange)", file=sys.stderr)
+              "(the library runs the update and pack on a single GPU and has no cross-GPU exchange)", file=sys.stderr)
         sys.exit(2)
     if args.summarize_counters:
         print(summarize_counters(args.summarize_counters))

@@ -103,7 +103,7 @@ def lib():
         return _lib
     if not os.path.exists(_SO):
         raise ImportError(f"native library {_SO} is missing: build it first "
-                          "(python -c 'import __graft_entry__ as g; g.build()')")
+                          "(paper_2103_05875_amd.native_build.build())")
     L = ctypes.CDLL(_SO)
     vp, i32, u32, u64, f32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float
     P = ctypes.POINTER
