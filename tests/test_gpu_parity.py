@@ -286,8 +286,11 @@ def _grid_for(P):
     return P, 1, 1
 
 
+# 16,377 probes: 2,048 tiles, the last with one probe (the largest scan-free
+# pack); 16,392 probes: 2,049 tiles (the one-block scan runs)
 @pytest.mark.parametrize("P,taus", [(1, (0.0, 0.0)), (37, (1.0 / 1024, 0.0)), (2048, (0.0, 1.0 / 1024)),
-                                    (16384, (1.0 / 1024, 1.0 / 1024)), (1000, (0.01, 0.003))])
+                                    (16384, (1.0 / 1024, 1.0 / 1024)), (1000, (0.01, 0.003)),
+                                    (16377, (0.0, 1.0 / 1024)), (16392, (1.0 / 1024, 0.0))])
 def test_pack_bit_exact(ps, ctx, O, P, taus):
     _say(f"pack P={P} taus={taus}")
     nx, ny, nz = _grid_for(P)
