@@ -494,6 +494,16 @@ def test_served_results_equal_alone_results(ps, ctx, O):
         assert a[c] == b[c], f"client {c} differs"
     _say(f"  evictions {srv.evictions}, largest batch {max(r.batch_size for r in served)}, "
          f"latency {serve.latency_stats(served)}")
+    # delivery at the pinned staging, headers kept: the same headers and sizes
+    srv2 = serve.Server(ctx, scene, cfgs, hbm_budget=budget, n_streams=3, max_batch=8, keep_packets=False)
+    staged = srv2.run(make())
+    srv2.close()
+    hdr = lambda rs: {c: [(r.header, r.nbytes) for r in sorted((r for r in rs if r.client == c),
+                                                              key=lambda r: r.arrival)] for c in range(8)}
+    h2 = hdr(staged)
+    for c in range(8):
+        assert all(r.packet is None for r in staged)
+        assert h2[c] == [(p[:32], len(p)) for p in b[c]], f"client {c}: staged headers differ"
     scene.close()
 
 
