@@ -12,7 +12,8 @@
 //     so three texels fill four YUV samples; a row of x = 16 C texels is
 //     ceil(4 x / 3) samples, the missing bytes zero
 // Irradiance: one thread per output sample (encode) or texel (decode);
-// visibility encode: one thread per three texels (four samples per plane);
+// visibility encode: one thread per three texels (four samples per plane),
+// written out through LDS as 32-bit words;
 // the writes of a wavefront are contiguous, the reads gather short runs
 // from the tiles. All of it is a pure permutation of bytes plus one rounding
 // per irradiance value, so the kernels are bound by HBM.
@@ -47,33 +48,56 @@ __global__ __launch_bounds__(kYuvThreads) void k_yuv_irr_encode(const uint16_t *
 }
 
 // One thread per group of three texels of a row (twelve bytes): it reads
-// each texel's two 16-bit values once and writes four consecutive samples
-// of each plane (byte 3k + c of the group is sample k of plane c).
+// each texel's two 16-bit values once and puts byte 3k + c of the group,
+// sample k of plane c, into LDS; the block then writes its run of each
+// plane's row (up to 1,024 samples) as aligned 32-bit words, bytes only at
+// the run's two ends (words aligned in memory, whatever the planes' base).
+// Block (x, y): row x, groups 256y ..
 __global__ __launch_bounds__(kYuvThreads) void k_yuv_vis_encode(const uint16_t *vis, int P, int C, uint8_t *planes,
                                                                 int Wv, int Hv) {
+    __shared__ uint8_t sm[3][4 * kYuvThreads];
     const int x = 16 * C, G = (x + 2) / 3;
-    const long long idx = (long long)blockIdx.x * kYuvThreads + threadIdx.x;
-    if (idx >= (long long)G * Hv) return;
-    const int row = (int)(idx / G), g = (int)(idx - (long long)row * G);
+    const int row = blockIdx.x, g0 = blockIdx.y * kYuvThreads, g = g0 + threadIdx.x;
     const int ty = row >> 4, j = row & 15;
     uint32_t tex[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
         const int col = 3 * g + t, p = ty * C + (col >> 4), i = col & 15;
         tex[t] = 0u;
-        if (col < x && p < P) {
+        if (g < G && col < x && p < P) {
             const size_t at = (((size_t)p * 2) * 18 + j + 1) * 18 + i + 1;
             tex[t] = (uint32_t)vis[at] | ((uint32_t)vis[at + 18 * 18] << 16);
         }
     }
-    const size_t plane = (size_t)Wv * Hv, base = (size_t)row * Wv;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int m = 3 * k + c, u = 4 * g + k;
-            if (u < Wv) planes[c * plane + base + u] = (uint8_t)(tex[m >> 2] >> (8 * (m & 3)));
+            const int m = 3 * k + c;
+            sm[c][4 * threadIdx.x + k] = (uint8_t)(tex[m >> 2] >> (8 * (m & 3)));
         }
+    __syncthreads();
+    const int u0 = 4 * g0, len = min(4 * kYuvThreads, Wv - u0);
+    const size_t plane = (size_t)Wv * Hv;
+    const long long mis = (long long)((uintptr_t)planes & 3);  // the base's offset from a word boundary
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const long long a0 = (long long)(c * plane + (size_t)row * Wv + u0);
+        const long long A = ((a0 + mis) & ~3ll) - mis;  // index of the aligned word holding a0
+        const int nwords = (int)((a0 + len - A + 3) >> 2);
+        for (int w = threadIdx.x; w < nwords; w += kYuvThreads) {
+            const long long at = A + 4ll * w;
+            if (at >= a0 && at + 4 <= a0 + len) {
+                const int o = (int)(at - a0);
+                *reinterpret_cast<uint32_t *>(planes + at) = (uint32_t)sm[c][o] | ((uint32_t)sm[c][o + 1] << 8) |
+                                                             ((uint32_t)sm[c][o + 2] << 16) |
+                                                             ((uint32_t)sm[c][o + 3] << 24);
+            } else {
+                for (int bb = 0; bb < 4; ++bb)
+                    if (at + bb >= a0 && at + bb < a0 + len) planes[at + bb] = sm[c][at + bb - a0];
+            }
+        }
+    }
 }
 
 __global__ __launch_bounds__(kYuvThreads) void k_yuv_irr_decode(const uint16_t *planes, int P, int C, int W, int H,
@@ -112,8 +136,9 @@ hipError_t launch_yuv_encode(const uint16_t *irr, const uint16_t *vis, int P, in
                              uint8_t *vis_planes, const YuvDims &d, hipStream_t s) {
     hipLaunchKernelGGL(k_yuv_irr_encode, yuv_grid(d.w * d.h), dim3(kYuvThreads), 0, s, irr, P, C, k, irr_planes,
                        (int)d.w, (int)d.h);
-    hipLaunchKernelGGL(k_yuv_vis_encode, yuv_grid((16ll * C + 2) / 3 * d.hv), dim3(kYuvThreads), 0, s, vis, P, C,
-                       vis_planes, (int)d.wv, (int)d.hv);
+    const int groups = (16 * C + 2) / 3;
+    hipLaunchKernelGGL(k_yuv_vis_encode, dim3((unsigned)d.hv, (groups + kYuvThreads - 1) / kYuvThreads),
+                       dim3(kYuvThreads), 0, s, vis, P, C, vis_planes, (int)d.wv, (int)d.hv);
     return hipGetLastError();
 }
 
