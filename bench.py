@@ -500,13 +500,14 @@ def leg_codec(ps, torch, reps: int = 20):
     codes, vb = ps.decode_yuv(ctx, P, C, ip, vp, stream=stream)
     torch.cuda.synchronize()
     ok = bool(np.array_equal(vb.cpu().numpy().view(np.uint16), vis[:, :, 1:-1, 1:-1].reshape(P, 2, 256)))
+    # outputs reused, so that the loops time the kernels, not allocation
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     ev[0].record(stream)
     for _ in range(reps):
-        vol.encode_yuv(2.0, C, stream=stream)
+        vol.encode_yuv(2.0, C, stream=stream, out=(ip, vp))
     ev[1].record(stream)
     for _ in range(reps):
-        ps.decode_yuv(ctx, P, C, ip, vp, stream=stream)
+        ps.decode_yuv(ctx, P, C, ip, vp, stream=stream, out=(codes, vb))
     ev[2].record(stream)
     torch.cuda.synchronize()
     enc_ms = ev[0].elapsed_time(ev[1]) / reps

@@ -468,14 +468,21 @@ class Volume:
         _check(lib().pv_get_active(self.h, ctypes.byref(a)))
         return device_to_host(a.value, (self.P,), "uint8").astype(bool)
 
-    def encode_yuv(self, irr_scale: float, tiles_per_row: int, stream=None):
+    def encode_yuv(self, irr_scale: float, tiles_per_row: int, stream=None, out=None):
         """Codec surfaces of the current maps: (irradiance planes [3, h, w]
         uint16 as int16 bits, visibility planes [3, hv, wv] uint8), torch
-        device tensors (asynchronous on ``stream``)."""
+        device tensors (asynchronous on ``stream``); ``out`` may hold two
+        contiguous tensors of those shapes and sizes to write into."""
         import torch
         w, h, wv, hv = yuv_dims(self.P, tiles_per_row)
-        ip = torch.empty((3, h, w), dtype=torch.int16, device="cuda")
-        vp = torch.empty((3, hv, wv), dtype=torch.uint8, device="cuda")
+        if out is None:
+            ip = torch.empty((3, h, w), dtype=torch.int16, device="cuda")
+            vp = torch.empty((3, hv, wv), dtype=torch.uint8, device="cuda")
+        else:
+            ip, vp = out
+            if tuple(ip.shape) != (3, h, w) or tuple(vp.shape) != (3, hv, wv) or ip.element_size() != 2 \
+                    or vp.element_size() != 1 or not (ip.is_contiguous() and vp.is_contiguous()):
+                raise ValueError("output planes do not match the layout")
         _check(lib().pv_encode_yuv(self.h, float(irr_scale), int(tiles_per_row), ip.data_ptr(), vp.data_ptr(),
                                    _stream_handle(stream)))
         return ip, vp
@@ -650,9 +657,10 @@ def yuv_dims(n_probes: int, tiles_per_row: int):
     return tuple(int(x) for x in d)
 
 
-def decode_yuv(ctx: "Context", n_probes: int, tiles_per_row: int, irr_planes, vis_planes, stream=None):
+def decode_yuv(ctx: "Context", n_probes: int, tiles_per_row: int, irr_planes, vis_planes, stream=None, out=None):
     """Codec surfaces (torch device tensors) back to A2RGB10 codes [P, 64]
-    (int32 bits) and visibility binary16 patterns [P, 2, 256] (int16 bits)."""
+    (int32 bits) and visibility binary16 patterns [P, 2, 256] (int16 bits);
+    ``out`` may hold two contiguous tensors of those shapes to write into."""
     import torch
     w, h, wv, hv = yuv_dims(n_probes, tiles_per_row)
     if tuple(irr_planes.shape) != (3, h, w) or tuple(vis_planes.shape) != (3, hv, wv):
@@ -660,8 +668,14 @@ def decode_yuv(ctx: "Context", n_probes: int, tiles_per_row: int, irr_planes, vi
     if irr_planes.element_size() != 2 or vis_planes.element_size() != 1:
         raise ValueError("irradiance planes are 16-bit, visibility planes 8-bit")
     ip, vp = irr_planes.contiguous(), vis_planes.contiguous()
-    codes = torch.empty((n_probes, 64), dtype=torch.int32, device="cuda")
-    vis = torch.empty((n_probes, 2, 256), dtype=torch.int16, device="cuda")
+    if out is None:
+        codes = torch.empty((n_probes, 64), dtype=torch.int32, device="cuda")
+        vis = torch.empty((n_probes, 2, 256), dtype=torch.int16, device="cuda")
+    else:
+        codes, vis = out
+        if tuple(codes.shape) != (n_probes, 64) or codes.element_size() != 4 or tuple(vis.shape) != (n_probes, 2, 256) \
+                or vis.element_size() != 2 or not (codes.is_contiguous() and vis.is_contiguous()):
+            raise ValueError("output buffers do not match the layout")
     _check(lib().pv_decode_yuv(ctx.h, int(n_probes), int(tiles_per_row), ip.data_ptr(), vp.data_ptr(),
                                codes.data_ptr(), vis.data_ptr(), _stream_handle(stream)))
     return codes, vis

@@ -81,6 +81,16 @@ def test_codec_surfaces_after_an_update_and_errors(ps, ctx, O):
     assert np.array_equal(ip.cpu().numpy().view(np.uint16), wi) and np.array_equal(vp.cpu().numpy(), wvp)
     _, vback = ps.decode_yuv(ctx, cfg.n_probes, 20, ip, vp)
     assert np.array_equal(vback.cpu().numpy().view(np.uint16), vis[:, :, 1:-1, 1:-1].reshape(-1, 2, 256))
+    # caller-provided outputs (filled with garbage first) give the same bytes
+    import torch
+    ip2, vp2 = torch.full_like(ip, -1), torch.full_like(vp, 0xAB)
+    codes2, vis2 = torch.full((cfg.n_probes, 64), -1, dtype=torch.int32, device="cuda"), \
+        torch.full((cfg.n_probes, 2, 256), -1, dtype=torch.int16, device="cuda")
+    vol.encode_yuv(4.0, 20, out=(ip2, vp2))
+    ps.decode_yuv(ctx, cfg.n_probes, 20, ip2, vp2, out=(codes2, vis2))
+    assert torch.equal(ip2, ip) and torch.equal(vp2, vp) and torch.equal(vis2, vback)
+    with pytest.raises(ValueError):
+        vol.encode_yuv(4.0, 21, out=(ip2, vp2))
     for bad in ((0.0, 20), (float("inf"), 20), (1.0, 0), (1.0, 70000)):
         with pytest.raises(ps.NativeError):
             vol.encode_yuv(*bad)
