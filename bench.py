@@ -352,8 +352,9 @@ def leg_served(ps, duration_s: float, rate_hz: float = 2000.0, budget_frac: floa
            "plain": None if plain is None else dict(serve.latency_stats(plain), probes_per_s=probes / span_p,
                                                     probe_rays_per_s=rays / span_p),
            "packets_identical": bool(same)}
-    if plain is not None:
-        # offered load against what the plain path sustains on the same trace
+    if plain is not None and span_p > 1.1 * duration_s:
+        # the plain path fell behind, so its rate is its capacity: offered
+        # load as a fraction of it
         out["offered_over_plain_capacity"] = out["offered_probes_per_s"] / out["plain"]["probes_per_s"]
     scene.close()
     ctx.close()
