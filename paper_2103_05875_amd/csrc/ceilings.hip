@@ -40,7 +40,6 @@ __global__ __launch_bounds__(kCeilThreads) void k_ceil_mfma(float *out, int iter
     v4f_c acc[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[k] = v4f_c{0.f, 0.f, 0.f, (float)k};
-#pragma unroll 4
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[k], 0, 0, 0);
