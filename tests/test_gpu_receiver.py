@@ -173,6 +173,10 @@ def test_packet_download_entry_points_agree(ps, ctx):
     scene, cfg, sc, vol = _server(ps, ctx, nx=4, ny=4, nz=4, n=64, tris=3000)
     cl = ps.Client(vol, client_id=3)
     L = ps.lib()
+    # before the first pack there is no packet to hand out
+    ptr, nb = ctypes.c_void_p(), ctypes.c_uint64(0)
+    assert L.pv_packet_stage(cl.h, ctypes.byref(ptr), ctypes.byref(nb), None) == -4   # PV_ERR_STATE
+    assert L.pv_packet_download(cl.h, None, 0, ctypes.byref(nb), None) == -4
     for f in range(3):
         vol.update_probes(synth.rotation(31, f))
         cl.pack_delta(0.0, 1.0 / 1024)
