@@ -293,6 +293,28 @@ pv_status pv_packet_stage(pv_client *client, const void **host_ptr, uint64_t *by
  * server evict a client's state from HBM and bring it back later. */
 pv_status pv_client_read_state(pv_client *client, void *ref_irr_host, void *ref_vis_host, uint32_t *seq);
 pv_status pv_client_set_state(pv_client *client, const void *ref_irr_host, const void *ref_vis_host, uint32_t seq);
+/* pv_pack_delta without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops that may not
+ * call hipMalloc). Same computation, kernels and packet layout as
+ * pv_pack_delta, on caller-owned device buffers:
+ *   cur_irr, cur_vis  the current FP16 tiles, [P][3][10][10] and
+ *                     [P][2][18][18] binary16 (the volume map layout);
+ *   ref_irr, ref_vis  the client's reference interiors, [P][3][64] and
+ *                     [P][2][256] binary16 (all zero = nothing sent yet);
+ *                     read, and sent probes written (in place);
+ *   packet            receives the packet; packet_cap must hold a full
+ *                     resend (the size of a packet with K_irr = K_vis = P),
+ *                     else PV_ERR_CAPACITY. The header gives its size.
+ * client_id and seq go into the header. Every pointer 16-byte aligned.
+ * Changed masks, tile summaries, totals and checksum shares live in one
+ * static device array per GPU of 288.25 KiB (held until the process ends),
+ * which limits n_probes to 65,536 (PV_ERR_ARG beyond). All calls on one GPU
+ * share that array: calls that overlap on a GPU (different streams, or
+ * threads) race and must be ordered by the caller. Asynchronous on 'stream';
+ * calls no allocating routine. Not timed by pv_ctx_set_timing. */
+pv_status pv_pack_delta_noalloc(pv_ctx *ctx, const uint16_t *cur_irr, const uint16_t *cur_vis, uint16_t *ref_irr,
+                                uint16_t *ref_vis, int n_probes, float tau_irr, float tau_vis, uint32_t client_id,
+                                uint32_t seq, uint8_t *packet, uint64_t packet_cap, void *stream);
 /* Changed-probe masks of the last pack (device, [P] uint8 each). */
 pv_status pv_get_masks(pv_client *client, void **mask_irr_dev, void **mask_vis_dev);
 

@@ -15,5 +15,6 @@ from __future__ import annotations
 from .native import (  # noqa: F401
     PV_FIRST_FRAME_NO_HISTORY, PV_KEEP_HITS, PV_MAP_FP16, PV_MAP_FP32,
     BatchGraph, Client, Context, NativeError, Receiver, Scene, Volume, build, lib, lib_path, update_probes_batched,
-    volume_footprint, client_footprint, decode_yuv, yuv_dims, EXPORTED_SYMBOLS,
+    volume_footprint, client_footprint, decode_yuv, yuv_dims, EXPORTED_SYMBOLS, pack_delta_noalloc,
+    packet_capacity,
 )

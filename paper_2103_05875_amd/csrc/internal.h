@@ -93,6 +93,16 @@ constexpr int kPackTile = 8;   // probes per pack block
 constexpr int kPackFusedTiles = 2048;
 bool pack_fused(int P);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+// Pack without allocation (pack.hip): intermediates live in a static device
+// array sized for kNoAllocMaxProbes probes; its address on a device is taken
+// once with that device current (noalloc_scratch_init, from pv_ctx_create).
+constexpr int kNoAllocMaxProbes = PV_MAX_PROBES;
+constexpr size_t kNoAllocScratchBytes = 8192 * 16 + 32768 + 256 + 65536 + 65536;
+hipError_t noalloc_scratch_init(int device);
+unsigned char *noalloc_scratch(int device);  // null before noalloc_scratch_init on that device
+hipError_t launch_pack_noalloc(unsigned char *scratch_dev, const uint16_t *cur_irr, const uint16_t *cur_vis,
+                               uint16_t *ref_irr, uint16_t *ref_vis, int P, float tau_irr, float tau_vis,
+                               uint32_t client, uint32_t seq, uint8_t *packet, hipStream_t s);
 
 // Client-side unpack (receive.hip). The packet's header has been checked on
 // the host; the index and the checksum are checked on the device before any

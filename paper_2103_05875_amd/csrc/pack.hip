@@ -1,6 +1,9 @@
 // Lossless delta pack of FP16 probe tiles for one client: change masks,
 // ordered compaction with a delta-coded index buffer, XOR byte planes against
 // the client's last-transmitted state, reference update, checksum.
+#include <mutex>
+#include <vector>
+
 #include "device_common.h"
 #include "packet_format.h"
 
@@ -21,8 +24,9 @@ __device__ __forceinline__ bool texel_changed(uint16_t a, uint16_t b, float tau)
 // The pack works on tiles of kPackQ consecutive probes. Their FP16 tiles are
 // contiguous in HBM (600 B and 1,296 B per probe) and start on 16-byte
 // boundaries (kPackQ * 600 and kPackQ * 1,296 are multiples of 16), so a block
-// stages them into LDS with aligned 16-byte loads (map allocations carry 256
-// bytes of slack, so the last vector of a ragged tail stays in bounds). Work
+// stages them into LDS with aligned 16-byte loads; a ragged last tile of odd
+// length ends its irradiance run with one 8-byte load, so no load reads past
+// the maps (which may be caller-owned buffers of exactly P tiles). Work
 // is then split into row units of 8 interior texels of one channel:
 // irradiance 3 x 8 rows per probe, visibility 2 x 16 rows x 2 halves.
 constexpr int kPackQ = kPackTile;
@@ -42,9 +46,12 @@ __device__ __forceinline__ void stage_tiles(const PackBuffers &b, int p0, int P,
     const int n = min(kPackQ, P - p0);
     const uint4 *gi = reinterpret_cast<const uint4 *>(b.cur_irr + (size_t)p0 * 300);
     const uint4 *gv = reinterpret_cast<const uint4 *>(b.cur_vis + (size_t)p0 * 648);
-    const int vi = (n * 600 + 15) / 16, vv = (n * 1296 + 15) / 16;
+    // n * 1296 is a multiple of 16; n * 600 leaves 8 bytes when n is odd
+    const int vi = n * 600 / 16, vv = n * 1296 / 16;
     for (int i = threadIdx.x; i < vi; i += kPackThreads) sm.irr[i] = gi[i];
     for (int i = threadIdx.x; i < vv; i += kPackThreads) sm.vis[i] = gv[i];
+    if ((n & 1) && threadIdx.x == 0)
+        reinterpret_cast<uint2 *>(sm.irr)[2 * vi] = reinterpret_cast<const uint2 *>(gi)[2 * vi];
 }
 
 // Unit u of the tile (irradiance units first): probe q, texture (0 irr,
@@ -465,6 +472,77 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
     const size_t blocks = std::min<size_t>((words + 255) / 256, 4096);
     hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)p, words);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// pack without allocation: the per-call intermediates (masks, tile
+// summaries, totals, checksum shares) in one static device array
+// ---------------------------------------------------------------------------
+// Layout of the array for up to kNoAllocMaxProbes probes (offsets in bytes,
+// each section 256-byte aligned).
+constexpr int kNoAllocTiles = (kNoAllocMaxProbes + kPackTile - 1) / kPackTile;
+constexpr size_t kScrTiles = 0;
+constexpr size_t kScrPartial = kScrTiles + (size_t)kNoAllocTiles * sizeof(int4);
+constexpr size_t kScrTotals = kScrPartial + ((size_t)kNoAllocTiles * 4 + 255) / 256 * 256;
+constexpr size_t kScrMaskIrr = kScrTotals + 256;
+constexpr size_t kScrMaskVis = kScrMaskIrr + ((size_t)kNoAllocMaxProbes + 255) / 256 * 256;
+constexpr size_t kScrEnd = kScrMaskVis + ((size_t)kNoAllocMaxProbes + 255) / 256 * 256;
+static_assert(kScrEnd == kNoAllocScratchBytes, "scratch layout and its stated size agree");
+
+// One copy per device; each GPU the library runs on holds it until the
+// process ends. Host code never passes this name to a kernel: it uses the
+// device address that hipGetSymbolAddress returned for the current device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<unsigned char *> g_scratch_ptr;  // per device, null until set up
+
+hipError_t noalloc_scratch_init(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = (unsigned char *)ptr;
+    return hipSuccess;
+}
+
+unsigned char *noalloc_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return device >= 0 && device < (int)g_scratch_ptr.size() ? g_scratch_ptr[device] : nullptr;
+}
+
+// The pack's launch sequence over caller-owned maps, reference and packet,
+// with every intermediate in the device's scratch array (ptr from
+// noalloc_scratch). Every intermediate is written before it is read, so
+// nothing is cleared between calls.
+hipError_t launch_pack_noalloc(unsigned char *scr, const uint16_t *cur_irr, const uint16_t *cur_vis, uint16_t *ref_irr,
+                               uint16_t *ref_vis, int P, float tau_irr, float tau_vis, uint32_t client, uint32_t seq,
+                               uint8_t *packet, hipStream_t s) {
+    PackBuffers b;
+    b.cur_irr = cur_irr;
+    b.cur_vis = cur_vis;
+    b.ref_irr = ref_irr;
+    b.ref_vis = ref_vis;
+    b.mask_irr = scr + kScrMaskIrr;
+    b.mask_vis = scr + kScrMaskVis;
+    b.tiles = reinterpret_cast<int4 *>(scr + kScrTiles);
+    b.totals = reinterpret_cast<uint32_t *>(scr + kScrTotals);
+    b.partial = reinterpret_cast<uint32_t *>(scr + kScrPartial);
+    b.packet = packet;
+    b.active = nullptr;
+    b.view = nullptr;
+    hipError_t e = launch_pack_mask(b, P, tau_irr, tau_vis, s);
+    if (e == hipSuccess && !pack_fused(P)) e = launch_pack_scan(b, P, s);
+    if (e == hipSuccess) e = launch_pack_compact(b, P, s);
+    if (e == hipSuccess) e = launch_pack_finish(b, P, client, seq, s);
+    return e;
 }
 
 }  // namespace pv

@@ -188,6 +188,8 @@ extern "C" pv_status pv_ctx_create(int hip_device, pv_ctx **out) {
     HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(PV_ERR_UNSUPPORTED, std::string("built for gfx950, device is ") + prop.gcnArchName);
+    // the no-allocation pack's scratch array: its address on this device
+    HIP_TRY(noalloc_scratch_init(hip_device));
     pv_ctx *c = new pv_ctx();
     c->device = hip_device;
     hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
@@ -1198,6 +1200,30 @@ extern "C" pv_status pv_pack_delta(pv_client *c, float tau_irr, float tau_vis, v
     HIP_TRY(timed(cx, PV_STAGE_PACK_COMPACT, s, [&] { return launch_pack_compact(b, P, s); }));
     HIP_TRY(timed(cx, PV_STAGE_PACK_FINISH, s, [&] { return launch_pack_finish(b, P, id, seq, s); }));
     c->seq++;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_pack_delta_noalloc(pv_ctx *cx, const uint16_t *cur_irr, const uint16_t *cur_vis,
+                                           uint16_t *ref_irr, uint16_t *ref_vis, int n_probes, float tau_irr,
+                                           float tau_vis, uint32_t client_id, uint32_t seq, uint8_t *packet,
+                                           uint64_t packet_cap, void *stream) {
+    if (!cx || !cur_irr || !cur_vis || !ref_irr || !ref_vis || !packet) return fail(PV_ERR_ARG, "NULL argument");
+    if (n_probes < 1 || n_probes > kNoAllocMaxProbes)
+        return fail(PV_ERR_ARG, "n_probes " + std::to_string(n_probes) + " outside [1, " +
+                                    std::to_string(kNoAllocMaxProbes) + "] (the scratch array's limit)");
+    if (!(tau_irr >= 0.f) || !(tau_vis >= 0.f) || !std::isfinite(tau_irr) || !std::isfinite(tau_vis))
+        return fail(PV_ERR_ARG, "thresholds must be finite and >= 0");
+    const uintptr_t align = (uintptr_t)cur_irr | (uintptr_t)cur_vis | (uintptr_t)ref_irr | (uintptr_t)ref_vis |
+                            (uintptr_t)packet;
+    if (align & 15u) return fail(PV_ERR_ARG, "maps, references and packet must be 16-byte aligned");
+    if (packet_cap < packet_capacity(n_probes))
+        return fail(PV_ERR_CAPACITY, "packet buffer needs " + std::to_string(packet_capacity(n_probes)) +
+                                         " bytes (a full resend)");
+    HIP_TRY(hipSetDevice(cx->device));
+    unsigned char *scr = noalloc_scratch(cx->device);
+    if (!scr) return fail(PV_ERR_STATE, "scratch array not set up on this device");
+    HIP_TRY(launch_pack_noalloc(scr, cur_irr, cur_vis, ref_irr, ref_vis, n_probes, tau_irr, tau_vis, client_id, seq,
+                                packet, pick(cx, stream)));
     return PV_OK;
 }
 

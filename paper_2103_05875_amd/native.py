@@ -40,7 +40,7 @@ EXPORTED_SYMBOLS = [
     "pv_receiver_create", "pv_receiver_destroy", "pv_receiver_apply", "pv_receiver_status",
     "pv_receiver_get_maps", "pv_receiver_read_maps", "pv_yuv_dims", "pv_encode_yuv", "pv_decode_yuv",
     "pv_get_active", "pv_client_set_view", "pv_client_clear_view", "pv_client_get_view",
-    "pv_entropy_encode", "pv_entropy_download", "pv_receiver_apply_compressed",
+    "pv_entropy_encode", "pv_entropy_download", "pv_receiver_apply_compressed", "pv_pack_delta_noalloc",
 ]
 
 STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched", "shadow", "shade",
@@ -148,6 +148,7 @@ def lib():
         "pv_client_reset": ([vp, vp], i32),
         "pv_client_footprint": ([P(VolumeDesc), P(u64)], i32),
         "pv_pack_delta": ([vp, f32, f32, vp], i32),
+        "pv_pack_delta_noalloc": ([vp, vp, vp, vp, vp, i32, f32, f32, u32, u32, vp, u64, vp], i32),
         "pv_packet_device": ([vp, P(vp), P(u64)], i32),
         "pv_packet_download": ([vp, vp, u64, P(u64), vp], i32),
         "pv_get_masks": ([vp, P(vp), P(vp)], i32),
@@ -648,6 +649,22 @@ class Client:
             self.close()
         except Exception:
             pass
+
+
+def packet_capacity(n_probes: int) -> int:
+    """Bytes of a full-resend packet of n_probes probes."""
+    idx = (2 * 2 * n_probes + 15) // 16 * 16
+    return 32 + idx + n_probes * 6 * 64 + n_probes * 4 * 256
+
+
+def pack_delta_noalloc(ctx: Context, cur_irr: int, cur_vis: int, ref_irr: int, ref_vis: int, n_probes: int,
+                       tau_irr: float, tau_vis: float, client_id: int, seq: int, packet: int, packet_cap: int,
+                       stream=None):
+    """pv_pack_delta_noalloc on device addresses (caller-owned buffers)."""
+    _check(lib().pv_pack_delta_noalloc(ctx.h, ctypes.c_void_p(cur_irr), ctypes.c_void_p(cur_vis),
+                                       ctypes.c_void_p(ref_irr), ctypes.c_void_p(ref_vis), int(n_probes),
+                                       float(tau_irr), float(tau_vis), int(client_id), int(seq),
+                                       ctypes.c_void_p(packet), int(packet_cap), _stream_handle(stream)))
 
 
 def yuv_dims(n_probes: int, tiles_per_row: int):
