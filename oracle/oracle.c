@@ -392,9 +392,6 @@ static or_hit closest_hit(const or_scene *s, const double o[3], const double d[3
     /* Possible hits close to the front are kept to decide 'near' at the end. */
     double poss_t[64];
     int poss_id[64], poss_sure[64], npos = 0, overflow = 0;
-    int h_sure = 0;                       /* the nominal hit is a sure one */
-    double sure_t = INFINITY;             /* the first sure hit */
-    int sure_k = -1;
     while (sp) {
         const or_node *nd = &s->nodes[stack[--sp]];
         if (box_enter(nd, o, d, m, t_limit) == INFINITY) continue;
@@ -410,11 +407,6 @@ static or_hit closest_hit(const or_scene *s, const double o[3], const double d[3
                 if (exact && (t < h.t || (t == h.t && k < h.tri))) {
                     h.t = t;
                     h.tri = k;
-                    h_sure = sure;
-                }
-                if (sure && (t < sure_t || (t == sure_t && k < sure_k))) {
-                    sure_t = t;
-                    sure_k = k;
                 }
                 if (sure && t + m < t_limit) t_limit = t + m;
                 if (possible) {
@@ -433,15 +425,6 @@ static or_hit closest_hit(const or_scene *s, const double o[3], const double d[3
             stack[sp++] = nd->left;
             stack[sp++] = nd->right;
         }
-    }
-    /* A nominal hit that is itself a graze may be missed altogether; the ray
-     * then goes on to the first sure hit behind it (or leaves the scene):
-     * that outcome is accepted too. */
-    if (h.tri >= 0 && !h_sure) {
-        h.near = 1;
-        h.ties[h.nties] = sure_k;
-        h.ties_t[h.nties] = sure_t;
-        h.nties++;
     }
     /* near: any possible-but-not-sure triangle in front of the sure front, or
      * another triangle within 2m of the nominal distance. */

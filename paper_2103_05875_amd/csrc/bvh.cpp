@@ -498,8 +498,8 @@ bool build_bvh4(const float *tri9, int n, int id_base, HostBvh4 &out, std::strin
             const float *t = tri9 + 9 * (size_t)src;
             GpuTri g;
             g.v0 = make_float4(t[0], t[1], t[2], bits_as_float(id_base + src));
-            g.e1 = make_float4(t[3] - t[0], t[4] - t[1], t[5] - t[2], 0.f);
-            g.e2 = make_float4(t[6] - t[0], t[7] - t[1], t[8] - t[2], 0.f);
+            g.v1 = make_float4(t[3], t[4], t[5], 0.f);
+            g.v2 = make_float4(t[6], t[7], t[8], 0.f);
             out.tris[i] = g;
         }
         return true;

@@ -28,7 +28,7 @@ __device__ __forceinline__ void classify_probe(const VolumeParams &vp, const Sce
         const int2 rec = vp.hitrec[(size_t)p * vp.n + j];
         if (rec.x == -1) continue;
         const GpuTri tri = (rec.x < 0 ? sv.dyn.tris : sv.stat.tris)[rec.x & 0x7fffffff];
-        const float3 nrm = cross3(xyz(tri.e1), xyz(tri.e2));
+        const float3 nrm = cross3(xyz(tri.v1) - xyz(tri.v0), xyz(tri.v2) - xyz(tri.v0));
         back += dot3(nrm, xyz(dirs[j])) > 0.f ? 1 : 0;
         near |= __int_as_float(rec.y) < diag;
     }
@@ -79,6 +79,7 @@ __global__ __launch_bounds__(kViewThreads) void k_client_view(VolumeParams vp, S
     closest<false>(sv.stat, global_nodes(sv.stat), ray, 0.f, tbest, best, best_id, arr, stk_l, cnt);
     closest<false>(sv.dyn, global_nodes(sv.dyn), ray, 0.f, tbest, best, best_id, arr, stk_l, cnt);
     if (best < 0) return;
+    tbest = plane_t(arr[best], eye, ray.d);
     const float3 x = make_float3(fmaf(tbest, ray.d.x, ex), fmaf(tbest, ray.d.y, ey), fmaf(tbest, ray.d.z, ez));
     int cx, cy, cz;
     float fx, fy, fz;

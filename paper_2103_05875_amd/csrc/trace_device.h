@@ -1,5 +1,5 @@
 // Ray traversal and direct shading, device side: quantized 4-wide BVH
-// nodes, Moller-Trumbore triangles, per-lane LDS stack, closest / any hit,
+// nodes, watertight triangle tests, per-lane LDS stack, closest / any hit,
 // and the shading of one probe ray (emission, point lights with shadow rays,
 // sky). Used by the trace kernels and by the batched kernel.
 #pragma once
@@ -13,7 +13,33 @@ namespace pv {
 // ---------------------------------------------------------------------------
 struct Ray {
     float3 o, d, inv;
+    // The ray's shear (Woop, Benthin and Wald 2013, "Watertight ray/triangle
+    // intersection"): kz is the axis of the largest |d| and (kx, ky, kz) the
+    // cyclic order ending in it; a point p relative to the origin maps to
+    // (p_kx - sx p_kz, p_ky - sy p_kz, sz p_kz) with sx = d_kx / d_kz,
+    // sy = d_ky / d_kz, sz = 1 / d_kz: the ray becomes the +z axis and the
+    // third coordinate the ray parameter.
+    float3 shear;  // sx, sy, sz
+    int kz;
 };
+
+// Per-lane choice between a and b as one bitfield insert (no branch).
+__device__ __forceinline__ float pick(bool c, float a, float b) {
+    const uint32_t m = c ? 0xffffffffu : 0u;
+    return __uint_as_float((m & __float_as_uint(a)) | (~m & __float_as_uint(b)));
+}
+
+// v with its axes rotated cyclically so that axis kz comes last; K = 0, 1, 2
+// is that axis known at compile time, K = -1 takes it from kz.
+template <int K = -1>
+__device__ __forceinline__ float3 rotate_to_z(float3 v, int kz) {
+    if (K == 0) return make_float3(v.y, v.z, v.x);
+    if (K == 1) return make_float3(v.z, v.x, v.y);
+    if (K == 2) return v;
+    const bool k0 = kz == 0, k1 = kz == 1;
+    return make_float3(pick(k0, v.y, pick(k1, v.z, v.x)), pick(k0, v.z, pick(k1, v.x, v.y)),
+                       pick(k0, v.x, pick(k1, v.y, v.z)));
+}
 
 __device__ __forceinline__ Ray make_ray(float3 o, float3 d) {
     Ray r;
@@ -24,23 +50,72 @@ __device__ __forceinline__ Ray make_ray(float3 o, float3 d) {
     float dy = fabsf(d.y) < 1e-20f ? copysignf(1e-20f, d.y) : d.y;
     float dz = fabsf(d.z) < 1e-20f ? copysignf(1e-20f, d.z) : d.z;
     r.inv = make_float3(__builtin_amdgcn_rcpf(dx), __builtin_amdgcn_rcpf(dy), __builtin_amdgcn_rcpf(dz));
+    const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    r.kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+    const float3 dr = rotate_to_z(d, r.kz);
+    const float sz = __builtin_amdgcn_rcpf(dr.z);
+    r.shear = make_float3(dr.x * sz, dr.y * sz, sz);
     return r;
 }
 
-// Two-sided Moller-Trumbore: true when the ray line crosses the triangle
-// (barycentrics inside, det != 0); t receives the distance along the ray.
+// Signed double areas of the projected triangle's edges, products rounded
+// separately (no fused multiply-add), so that the edge (P, Q) gives exactly
+// the negated value of (Q, P): two triangles sharing an edge then agree on
+// which side of it a ray passes.
+__device__ __forceinline__ void edge_areas(float ax, float ay, float bx, float by, float cx, float cy, float &u,
+                                           float &v, float &w) {
+#pragma clang fp contract(off)
+    u = cx * by - cy * bx;
+    v = ax * cy - ay * cx;
+    w = bx * ay - by * ax;
+}
+
+// Two-sided watertight ray/triangle test (Woop, Benthin and Wald 2013): each
+// vertex relative to the origin is sheared into the ray's frame by one fixed
+// function of that vertex, and the ray crosses the triangle when the three
+// edge areas do not have mixed signs (a ray through a shared edge or vertex
+// is inside at least one of the triangles there, never neither). True when
+// the ray line crosses the triangle; t receives the ray parameter of the
+// crossing as the barycentric mean of the vertices' parameters (within
+// about 1e-6 of the scene's extent, enough to order hits; the hit a ray
+// keeps gets its distance again from plane_t).
+template <int K>
+__device__ __forceinline__ bool tri_cross_k(const GpuTri &T, const Ray &r, float &t) {
+    const float3 A = rotate_to_z<K>(xyz(T.v0) - r.o, r.kz);
+    const float3 B = rotate_to_z<K>(xyz(T.v1) - r.o, r.kz);
+    const float3 C = rotate_to_z<K>(xyz(T.v2) - r.o, r.kz);
+    const float sx = r.shear.x, sy = r.shear.y, sz = r.shear.z;
+    float u, v, w;
+    edge_areas(fmaf(-sx, A.z, A.x), fmaf(-sy, A.z, A.y), fmaf(-sx, B.z, B.x), fmaf(-sy, B.z, B.y),
+               fmaf(-sx, C.z, C.x), fmaf(-sy, C.z, C.y), u, v, w);
+    const float lo = fminf(u, fminf(v, w)), hi = fmaxf(u, fmaxf(v, w));
+    const float det = u + v + w;
+    t = sz * fmaf(u, A.z, fmaf(v, B.z, w * C.z)) * __builtin_amdgcn_rcpf(det);
+    // written so that NaN (det == 0: a ray in the plane) fails
+    return !(lo < 0.f && hi > 0.f) && det != 0.f && (t == t);
+}
+
+// The rays of a packet share one direction and so one projection axis:
+// when every testing lane has the same, the rotation is resolved at compile
+// time (a wave-uniform branch); otherwise per lane.
 __device__ __forceinline__ bool tri_cross(const GpuTri &T, const Ray &r, float &t) {
-    const float3 e1 = xyz(T.e1), e2 = xyz(T.e2);
-    const float3 p = cross3(r.d, e2);
-    const float det = dot3(e1, p);
-    const float inv = __builtin_amdgcn_rcpf(det);
-    const float3 s = r.o - xyz(T.v0);
-    const float u = dot3(s, p) * inv;
-    const float3 q = cross3(s, e1);
-    const float v = dot3(r.d, q) * inv;
-    t = dot3(e2, q) * inv;
-    // written so that NaN (det == 0) fails every test
-    return (u >= 0.f) && (v >= 0.f) && (u + v <= 1.f) && (t == t);
+    const int k0 = __builtin_amdgcn_readfirstlane(r.kz);
+    if (__all(r.kz == k0)) {
+        if (k0 == 0) return tri_cross_k<0>(T, r, t);
+        if (k0 == 1) return tri_cross_k<1>(T, r, t);
+        return tri_cross_k<2>(T, r, t);
+    }
+    return tri_cross_k<-1>(T, r, t);
+}
+
+// Ray parameter where (o, d) meets the plane of T: n . (v0 - o) / n . d with
+// n = (v1 - v0) x (v2 - v0). A few ulps even on a large triangle met close to
+// the origin, where the barycentric mean of far vertices' parameters loses
+// up to 1e-3 of a short distance to cancellation.
+__device__ __forceinline__ float plane_t(const GpuTri &T, float3 o, float3 d) {
+    const float3 v0 = xyz(T.v0);
+    const float3 n = cross3(xyz(T.v1) - v0, xyz(T.v2) - v0);
+    return dot3(n, v0 - o) * __builtin_amdgcn_rcpf(dot3(n, d));
 }
 
 __device__ __forceinline__ int tri_id(const GpuTri &T) { return __float_as_int(T.v0.w); }
@@ -291,7 +366,7 @@ __device__ __forceinline__ int2 hit_record(int slot, bool dyn, float t) {
 // Geometry of a hit: unit normal facing the ray origin and the hit point.
 __device__ __forceinline__ void hit_frame(const GpuTri &T, const Ray &ray, float3 o, float t, float3 &nrm,
                                           float3 &xh) {
-    nrm = cross3(xyz(T.e1), xyz(T.e2));
+    nrm = cross3(xyz(T.v1) - xyz(T.v0), xyz(T.v2) - xyz(T.v0));
     const float il = rsqrtf(dot3(nrm, nrm));
     nrm = make_float3(nrm.x * il, nrm.y * il, nrm.z * il);
     if (dot3(nrm, ray.d) > 0.f) nrm = make_float3(-nrm.x, -nrm.y, -nrm.z);
@@ -343,6 +418,7 @@ __device__ void trace_shade_one(const VolumeParams &vp, const SceneView &sv, con
     const GpuTri *arr = nullptr;
     closest<COUNT>(sv.stat, stat_src, ray, 0.f, tbest, best, best_id, arr, stk, cnt);
     closest<COUNT>(sv.dyn, dyn_src, ray, 0.f, tbest, best, best_id, arr, stk, cnt);
+    if (best >= 0) tbest = plane_t(arr[best], o, ray.d);
     const size_t p = (size_t)x + (size_t)vp.nx * ((size_t)y + (size_t)vp.ny * z);
     const size_t q = p * vp.n + j;
     float3 L;
@@ -514,9 +590,12 @@ __device__ void lane_transition(LaneState &s, const VolumeParams &vp, const Scen
         return;
     }
     if (s.stage <= kPrimDyn) {
-        // primary ray done: emission or sky, then the lights
+        // primary ray done: its distance from the hit triangle's plane, then
+        // emission or sky, then the lights
         s.tbest = s.tmax;
         if (s.best >= 0) {
+            const int p = s.q / vp.n, j = s.q - p * vp.n;
+            s.tbest = plane_t((s.best_dyn ? sv.dyn.tris : sv.stat.tris)[s.best], probe_origin(vp, p), xyz(dirs[j]));
             const float4 emi = sv.mats[2 * s.best_id + 1];
             s.L = make_float3(emi.x, emi.y, emi.z);
             s.dist = fminf(s.tbest, vp.max_distance);

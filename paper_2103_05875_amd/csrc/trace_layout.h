@@ -18,10 +18,12 @@ namespace pv {
 // Device data layouts
 // ---------------------------------------------------------------------------
 
-// Triangle in leaf order: v0 (w = original triangle id as int bits),
-// e1 = v1 - v0, e2 = v2 - v0 (w unused).
+// Triangle in leaf order: its three vertices exactly as given (v0.w = the
+// original triangle id as int bits; v1.w, v2.w unused). Vertices shared by
+// neighbouring triangles are bit-identical, which the watertight triangle
+// test relies on.
 struct alignas(16) GpuTri {
-    float4 v0, e1, e2;
+    float4 v0, v1, v2;
 };
 
 struct GpuNode4;

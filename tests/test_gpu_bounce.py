@@ -124,18 +124,30 @@ def _update_both(ps, ctx, O, cfg, scene, frames, ind_rel):
     vol.set_scene(sc)
     ov = O.OracleVolume(cfg)
     osc = O.OracleScene.from_scene(scene)
+    g_irr, g_vis = O.empty_maps(cfg)   # the oracle's blend of the GPU's own ray records
     for f, R in enumerate(frames):
         vol.update_probes(R, scene.lights)
         rays = ov.update(osc, R, scene.lights, ind_rel=ind_rel)
         irr, vis, fr = vol.read_maps()
         grays, ghits, _ = vol.read_rays()
         assert fr == f + 1
+        O.blend_update(cfg, O.ray_dirs(cfg.rays_per_probe, R), grays[..., :3], grays[..., 3], g_irr, g_vis,
+                       first=(f == 0))
+        for name, g, o in (("irr", irr, g_irr), ("vis", vis, g_vis)):
+            if cfg.fp16:
+                d = ulps_from(g, o)
+                _say(f"  re-blend {name}: max {d.max():.2f} ulp, within 1 ulp {(d <= 1.0).mean():.5f}")
+                assert d.max() <= 2.0 and (d <= 1.0).mean() >= 0.999
+            else:
+                e = excess_fp32(g, o, o)[0]
+                _say(f"  re-blend {name}: max relative difference {e:.2e}")
+                assert e <= 1e-4
         yield irr, vis, ov, grays, ghits, rays
     vol.close()
     sc.close()
 
 
-def _check_rays(grays, ghits, rays, min_equal=0.999):
+def _check_rays(grays, ghits, rays, min_equal=0.9999):
     eq, ok = hit_agreement(ghits, rays)
     assert ok == 1.0, f"hits outside the accepted set: {1 - ok:.2e}"
     assert eq >= min_equal, f"nominal hit agreement {eq:.6f}"
