@@ -30,12 +30,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "probe-rays/s and probes updated/s at 1 GPU (plain vs batched/served); p50/p99 latency"
 
-# Algorithmic FP32 work of the traversal (FMA = 2, add/mul/min/max/compare = 1):
-# one node visit tests four child boxes (per box 6 plane FMAs, 10 min/max, one
-# compare = 23) after 9 ops of per-node decode; one triangle test (two
-# crosses, four dots, a reciprocal, compares) = 52.
-FLOP_PER_NODE_VISIT = 101
-FLOP_PER_TRI_TEST = 52
+# Algorithmic FP32 work of the traversal, the method's own and not this
+# kernel's instruction count: a ray/box slab test is about 20 FLOP (six plane
+# distances, the entry max and exit min, the compare) and a node visit tests
+# four child boxes; a ray/triangle test is about 30 FLOP. Decoding the
+# quantized boxes, the watertight test's vertex rotation and the stack are
+# this implementation's overhead and are not counted.
+FLOP_PER_NODE_VISIT = 4 * 20
+FLOP_PER_TRI_TEST = 30
 PEAK_FP32_VECTOR = 157.3e12        # MI355X published FP32 vector peak (FLOP/s)
 PEAK_HBM = 8.0e12                  # MI355X published HBM3E bandwidth (B/s)
 

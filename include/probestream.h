@@ -164,6 +164,24 @@ pv_status pv_scene_create(pv_ctx *ctx, const pv_scene_desc *desc, pv_scene **out
  * triangles, in effect for work enqueued on 'stream' after this call. */
 pv_status pv_scene_set_dynamic(pv_scene *scene, const float *positions, void *stream);
 pv_status pv_scene_destroy(pv_scene *scene);
+/* Copy of the scene's device BVH (dynamic = 0: the static triangles; 1: the
+ * dynamic ones as of the last pv_scene_set_dynamic), synchronous, for
+ * inspection and for replaying the traversal on the host. counts receives
+ * (nodes, triangle slots) and eps the shadow-ray offset; with NULL buffers
+ * only those are returned. Nodes: 64 bytes each, breadth first from the
+ * root at 0, as four 16-byte words:
+ *   w0: origin x, y, z (float), per-axis exponents e_x | e_y << 8 | e_z << 16
+ *       (a child box coordinate is origin + q * 2^(e - 127), q a byte)
+ *   w1: bytes q_lo_x[4] | q_hi_x[4] | q_lo_y[4] | q_hi_y[4] (byte c = child c)
+ *   w2: bytes q_lo_z[4] | q_hi_z[4] | leaf[4] | first leaf slot (u32);
+ *       leaf byte = count (bits 0-2, 0 for an inner child) | slot offset
+ *       from the first leaf slot (bits 3-6)
+ *   w3: child[4] (int32): inner node index, or -1 for an empty slot
+ * Triangle slots: 48 bytes, vertices v0, v1, v2 as float4 (v0.w = the
+ * triangle's index as int32 bits); a triangle may fill several slots.
+ * PV_ERR_CAPACITY when a buffer is smaller than counts require. */
+pv_status pv_scene_read_bvh(pv_scene *scene, int dynamic, void *nodes_host, uint64_t nodes_cap, void *tris_host,
+                            uint64_t tris_cap, int64_t counts[2], float *eps);
 
 /* Maps zeroed, frame counter 0. */
 pv_status pv_create_volume(pv_ctx *ctx, const pv_volume_desc *desc, pv_volume **out);

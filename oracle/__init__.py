@@ -29,15 +29,18 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = os.path.join(_HERE, "oracle.c")
+# oracle.c: the method in FP64; bvh4_replay.c: the GPU trace's traversal work
+# replayed on the host from the library's exported BVH (counts only)
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "bvh4_replay.c")]
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    """Compile the oracle with gcc (no FMA contraction beyond the explicit
+    fmaf calls, OpenMP)."""
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-Wall", "-o", tmp, _SRC, "-lm"])
+                               "-Wall", "-o", tmp, *_SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -115,6 +118,11 @@ def lib():
         L.or_client_apply.argtypes = [_U8, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       _U16, _U16, ctypes.POINTER(ctypes.c_uint32)]
         L.or_max_threads.restype = ctypes.c_int
+        L.rp_trace_counts.restype = ctypes.c_int
+        L.rp_trace_counts.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                      ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _F, _F,
+                                      ctypes.c_int, _F, ctypes.c_int, _F, ctypes.c_float,
+                                      ctypes.POINTER(ctypes.c_uint64)]
         _lib = L
     return _lib
 
@@ -564,6 +572,28 @@ class OracleVolume:
         self.frame += 1
         self.last = rays
         return rays
+
+
+# --------------------------------------------------------------------------
+# traversal work of the GPU trace, replayed on the host
+# --------------------------------------------------------------------------
+def replay_trace_counts(static_bvh, dynamic_bvh, cfg, dirs, lights, eps: float) -> dict:
+    """Node visits, triangle tests and shadow rays of tracing every (probe,
+    ray) of ``cfg`` through the library's own BVHs (``(nodes, tris)`` as
+    Scene.read_bvh returns them) with directions ``dirs`` [n, 4] float32 as
+    the device computed them; see bvh4_replay.c."""
+    sn, st = (np.ascontiguousarray(a) for a in static_bvh)
+    dn, dt = (np.ascontiguousarray(a) for a in dynamic_bvh)
+    f = lambda v: np.array([float(np.float32(x)) for x in v], np.float32)
+    o, sp = f(cfg.origin), f(cfg.spacing)
+    dirs = _c(dirs, np.float32).reshape(-1, 4)
+    lights = _c(lights, np.float32).reshape(-1, 6)
+    out = (ctypes.c_uint64 * 3)()
+    rc = lib().rp_trace_counts(sn.ctypes.data, sn.shape[0], st.ctypes.data, dn.ctypes.data, dn.shape[0],
+                               dt.ctypes.data, cfg.nx, cfg.ny, cfg.nz, _p(o, _F), _p(sp, _F), dirs.shape[0],
+                               _p(dirs, _F), lights.shape[0], _p(lights, _F), float(eps), out)
+    assert rc == 0, "traversal stack overflow in the replay"
+    return {"node_visits": int(out[0]), "tri_tests": int(out[1]), "shadow_rays": int(out[2])}
 
 
 # --------------------------------------------------------------------------

@@ -444,6 +444,24 @@ static SceneView scene_view(pv_scene *s) {
     return v;
 }
 
+extern "C" pv_status pv_scene_read_bvh(pv_scene *s, int dynamic, void *nodes_host, uint64_t nodes_cap,
+                                       void *tris_host, uint64_t tris_cap, int64_t counts[2], float *eps) {
+    if (!s || !counts) return fail(PV_ERR_ARG, "NULL argument");
+    HIP_TRY(hipSetDevice(s->ctx->device));
+    HIP_TRY(hipDeviceSynchronize());
+    const SceneView v = scene_view(s);
+    const DeviceBvh &b = dynamic ? v.dyn : v.stat;
+    counts[0] = b.n_nodes;
+    counts[1] = b.n_tris;
+    if (eps) *eps = v.eps;
+    const uint64_t nb = (uint64_t)b.n_nodes * sizeof(GpuNode4), tb = (uint64_t)b.n_tris * sizeof(GpuTri);
+    if (!nodes_host || !tris_host) return PV_OK;
+    if (nodes_cap < nb || tris_cap < tb) return fail(PV_ERR_CAPACITY, "buffers smaller than the BVH");
+    if (nb) HIP_TRY(hipMemcpy(nodes_host, b.nodes, nb, hipMemcpyDeviceToHost));
+    if (tb) HIP_TRY(hipMemcpy(tris_host, b.tris, tb, hipMemcpyDeviceToHost));
+    return PV_OK;
+}
+
 static pv_status note_scene_use(pv_scene *s, hipStream_t st) {
     if (s->n_dyn > 0) HIP_TRY(hipEventRecord(s->dyn_use[s->dyn_slot], st));
     return PV_OK;

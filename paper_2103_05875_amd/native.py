@@ -41,6 +41,7 @@ EXPORTED_SYMBOLS = [
     "pv_receiver_get_maps", "pv_receiver_read_maps", "pv_yuv_dims", "pv_encode_yuv", "pv_decode_yuv",
     "pv_get_active", "pv_client_set_view", "pv_client_clear_view", "pv_client_get_view",
     "pv_entropy_encode", "pv_entropy_download", "pv_receiver_apply_compressed", "pv_pack_delta_noalloc",
+    "pv_scene_read_bvh",
 ]
 
 STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched", "shadow", "shade",
@@ -115,6 +116,7 @@ def lib():
         "pv_scene_create": ([vp, P(SceneDesc), P(vp)], i32),
         "pv_scene_set_dynamic": ([vp, vp, vp], i32),
         "pv_scene_destroy": ([vp], i32),
+        "pv_scene_read_bvh": ([vp, i32, vp, u64, vp, u64, P(ctypes.c_int64), P(f32)], i32),
         "pv_create_volume": ([vp, P(VolumeDesc), P(vp)], i32),
         "pv_volume_destroy": ([vp], i32),
         "pv_volume_footprint": ([P(VolumeDesc), P(u64)], i32),
@@ -305,6 +307,18 @@ class Scene:
     def set_dynamic(self, positions, stream=None):
         pos = np.ascontiguousarray(positions, np.float32).reshape(-1)
         _check(lib().pv_scene_set_dynamic(self.h, pos.ctypes.data, _stream_handle(stream)))
+
+    def read_bvh(self, dynamic: bool = False):
+        """(nodes uint32 [N, 16], triangle slots float32 [T, 12], shadow-ray
+        offset) of the device BVH (layout in the header)."""
+        cnt = (ctypes.c_int64 * 2)()
+        eps = ctypes.c_float(0.0)
+        _check(lib().pv_scene_read_bvh(self.h, int(dynamic), None, 0, None, 0, cnt, ctypes.byref(eps)))
+        nodes = np.zeros((cnt[0], 16), np.uint32)
+        tris = np.zeros((cnt[1], 12), np.float32)
+        _check(lib().pv_scene_read_bvh(self.h, int(dynamic), nodes.ctypes.data, nodes.nbytes, tris.ctypes.data,
+                                       tris.nbytes, cnt, ctypes.byref(eps)))
+        return nodes, tris, eps.value
 
     def close(self):
         if getattr(self, "h", None):

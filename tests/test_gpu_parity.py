@@ -276,6 +276,46 @@ def test_dynamic_occluders(ps, ctx, O):
             assert (ghits >= scene.n_triangles - scene.n_dynamic).any()
 
 
+# ------------------------------------------------------------------ traversal work counts
+@pytest.mark.parametrize("workload", ["city", "encode"])
+def test_trace_counts_equal_host_replay(ps, ctx, O, workload):
+    """The device's instrumented counts (node visits, triangle tests, shadow
+    rays: the roofline's FLOP per launch is built from them) against a host
+    replay of the same traversal over the BVH the library built (read back
+    from the device), for every ray of a full-size frame. The replay's
+    reciprocals are correctly rounded where the device's are approximate,
+    so a few boundary decisions may differ: totals within 1e-5 (measured: the
+    city frame equal to one node visit in 9.3 M)."""
+    if workload == "city":
+        cfg, scene = synth.config("city"), synth.box_city()
+        R, dyn = synth.rotation(13, 0), None
+        path = synth.light_path(12, 60)
+    else:
+        cfg, scene = synth.config("encode"), synth.box_field(200_000, seed=40, n_moving=4)
+        R, dyn = synth.rotation(41, 0), synth.moving_occluders(40, 0, 4)
+        path = synth.light_path(12, 120)
+    lights = scene.lights.copy()
+    lights[0, :3] = path[0]
+    _say(f"trace counts vs host replay: {workload}")
+    sc = ps.Scene.from_synth(ctx, scene)
+    if dyn is not None:
+        sc.set_dynamic(dyn)
+    vol = ps.Volume(ctx, cfg)
+    vol.set_scene(sc)
+    vol.update_probes(R, lights)
+    _, _, dirs = vol.read_rays()
+    got = vol.trace_counts(R, lights)
+    rep = O.replay_trace_counts(sc.read_bvh(False)[:2], sc.read_bvh(True)[:2], cfg, dirs, lights, sc.read_bvh()[2])
+    rays = cfg.n_probes * cfg.rays_per_probe
+    _say(f"  device {got}; replay {rep}; per ray {rep['node_visits'] / rays:.3f} nodes, "
+         f"{rep['tri_tests'] / rays:.3f} triangles, {rep['shadow_rays'] / rays:.3f} shadow rays")
+    for k in ("node_visits", "tri_tests", "shadow_rays"):
+        assert abs(got[k] - rep[k]) <= 1e-5 * rep[k], k
+    assert rep["node_visits"] > 10 * rays and rep["shadow_rays"] > 0.1 * rays
+    vol.close()
+    sc.close()
+
+
 # ------------------------------------------------------------------ blend from given rays
 @pytest.mark.parametrize("fp16,n,grid,sharp", [(False, 64, (37, 1, 1), 50), (False, 300, (3, 2, 2), 50),
                                                (True, 256, (9, 5, 3), 50), (True, 513, (2, 1, 3), 50),
