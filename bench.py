@@ -40,6 +40,7 @@ FLOP_PER_NODE_VISIT = 4 * 20
 FLOP_PER_TRI_TEST = 30
 PEAK_FP32_VECTOR = 157.3e12        # MI355X published FP32 vector peak (FLOP/s)
 PEAK_HBM = 8.0e12                  # MI355X published HBM3E bandwidth (B/s)
+PEAK_BF16_MFMA = 2.5e15            # MI355X published dense BF16 matrix peak (FLOP/s)
 
 
 def parse():
@@ -50,7 +51,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--legs", default="batched,served,served_below_capacity,served_tight_memory,served_sweep,encode,"
-                                      "multi_bounce,codec,"
+                                      "multi_bounce,codec,blend_paths,"
                                       "selection",
                     help="extra workloads reported in the same line (comma list, or 'none')")
     ap.add_argument("--served-seconds", type=float, default=1.0)
@@ -532,6 +533,54 @@ def leg_codec(ps, torch, reps: int = 20):
     return out
 
 
+def leg_blend_paths(ps, torch, reps: int = 20):
+    """The blend (weighted means, hysteresis, guard bands) of volumes of
+    2,048 (the city), 4,096, 8,192 and 16,384 (the encode workload) probes,
+    256 rays, FP16 maps, on every blend path, from the same seeded ray
+    records: event time of the blend kernel, its algorithmic bytes (ray
+    records, stored interiors read, tiles written) against HBM and its FLOP
+    (2 per weight x record term) against the peak of its unit (BF16x3
+    counts its three products against the BF16 matrix peak; FP32 matrix
+    and vector FMAs against the FP32 peak)."""
+    import synth
+    out = {}
+    ctx = ps.Context(0)
+    stream = torch.cuda.current_stream()
+    for name, (grid, n) in (("city", ((16, 8, 16), 256)), ("4096", ((16, 16, 16), 256)),
+                            ("8192", ((32, 16, 16), 256)), ("encode", ((32, 16, 32), 256))):
+        cfg = synth.VolumeConfig(*grid, (0, 0, 0), (1, 1, 1), n, fp16=True, max_distance=3.0)
+        P = cfg.n_probes
+        vol = ps.Volume(ctx, cfg)
+        L, r = synth.synthetic_rays(P, n, seed=7, max_distance=3.0)
+        dev = torch.from_numpy(np.concatenate([L, r[..., None]], axis=-1).astype(np.float32)).cuda()
+        torch.cuda.synchronize()
+        R = synth.rotation(8, 0)
+        row = {}
+        for mode in ("tiles", "f32", "bf16x3", "valu"):
+            vol.set_blend_mode(mode)
+            for _ in range(3):
+                vol.blend_rays(R, dev.data_ptr(), stream=stream)
+            torch.cuda.synchronize()
+            ctx.set_timing(True)
+            ctx.stage_times()
+            for _ in range(reps):
+                vol.blend_rays(R, dev.data_ptr(), stream=stream)
+            torch.cuda.synchronize()
+            st = ctx.stage_times()
+            ctx.set_timing(False)
+            ms = st["blend"][0] / max(st["blend"][1], 1)
+            bytes_ = P * (16 * n + (192 + 512) * 2 + (300 + 648) * 2)
+            flop = P * 1408 * n
+            peak = PEAK_BF16_MFMA / 3 if mode == "bf16x3" else PEAK_FP32_VECTOR
+            row[mode] = {"ms": ms, "table_ms": st["raydirs"][0] / max(st["raydirs"][1], 1),
+                         "hbm_frac": bytes_ / (ms / 1e3) / PEAK_HBM, "mfma_frac": flop / (ms / 1e3) / peak}
+        out[name] = {"probes": P, "rays_per_probe": n, "paths": row}
+        del dev
+        vol.close()
+    ctx.close()
+    return out
+
+
 def street_eye(scene, height: float = 1.7):
     """A client position at street level in the box city: the first point of a
     coarse grid over the city that lies outside every box (boxes are the
@@ -854,6 +903,7 @@ def main():
                                                          with_plain=False),
                "encode": lambda: leg_encode(ps, torch, args.encode_frames),
                "codec": lambda: leg_codec(ps, torch),
+               "blend_paths": lambda: leg_blend_paths(ps, torch),
                "selection": lambda: leg_selection(ps, torch, cfg, scene, frames, tuned["config"] if tuned else None),
                "multi_bounce": lambda: leg_multi_bounce(ps, torch, cfg, scene, frames,
                                                         tuned["config"] if tuned else None)}

@@ -473,6 +473,22 @@ typedef struct {
     int split_shadows;
 } pv_trace_config;
 
+/* Numeric path of the blend (Sec. 3.2's weighted means as one matrix
+ * product per texture: weights x ray records). The weights are shared by
+ * every probe of a volume-frame; except for PV_BLEND_TILES they are
+ * evaluated once per frame into a table. PV_BLEND_BF16X3: BF16 matrix cores,
+ * weights and records split into high and low BF16 halves, three products
+ * per term with FP32 accumulation (about 2^-16 relative per term).
+ * PV_BLEND_F32: FP32 matrix cores. PV_BLEND_TILES: FP32 matrix cores with
+ * the weights evaluated again by every 8-probe tile (no table).
+ * PV_BLEND_VALU: the table on FP32 vector FMAs. PV_BLEND_AUTO (the default
+ * of a new volume) resolves to PV_BLEND_TILES below 4,096 probes and to
+ * PV_BLEND_F32 from there. Every path but PV_BLEND_BF16X3 meets the FP32
+ * blend's 1e-5 bound. Takes effect from the next update; the mode is
+ * reported as resolved. */
+enum { PV_BLEND_AUTO = 0, PV_BLEND_BF16X3 = 1, PV_BLEND_F32 = 2, PV_BLEND_TILES = 3, PV_BLEND_VALU = 4 };
+pv_status pv_volume_set_blend_mode(pv_volume *vol, int mode);
+pv_status pv_volume_get_blend_mode(pv_volume *vol, int *mode);
 pv_status pv_volume_set_trace_config(pv_volume *vol, const pv_trace_config *cfg);
 pv_status pv_volume_get_trace_config(pv_volume *vol, pv_trace_config *cfg);
 

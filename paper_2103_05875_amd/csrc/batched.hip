@@ -7,7 +7,7 @@
 // lane loop (separate node and triangle steps) on 4x4x4 probe packets. Results are bit-identical
 // to the per-volume launches: each ray and each probe group runs the same
 // device code on the same inputs.
-#include "blend_device.h"
+#include "blend_gemm.h"
 #include "trace_device.h"
 
 namespace pv {
@@ -66,17 +66,41 @@ __global__ __launch_bounds__(kBatchBlock) void k_trace_batched(const BatchVolume
                             Stack<kBatchBlock, E>{stk + threadIdx.x}, cnt, sh);
 }
 
+// Blocks of a volume follow its blend mode: per-tile blocks (8 probes, half
+// the rows) or column-group blocks of the product with four row groups.
+union BatchedBlendSmem {
+    BlendSmem tiles;
+    BlendSmemGemm<float> gemm32;
+    BlendSmemGemm<__half> gemm16;
+};
+
+template <typename T>
+__device__ __forceinline__ void blend_batched_block(const BatchVolume &bv, int local, BatchedBlendSmem &sm) {
+    const int mode = bv.vp.blend_mode;
+    if (mode == kBlendTiles) {
+        blend_tile_any<T>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, (local / kBlendSplit) * kBlendTile,
+                          local % kBlendSplit, sm.tiles);
+        return;
+    }
+    BlendSmemGemm<T> &g = *reinterpret_cast<BlendSmemGemm<T> *>(&sm);
+    if (mode == kBlendBF16x3)
+        blend_gemm_block<T, kBlendBF16x3, 4>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, local, g);
+    else if (mode == kBlendVALU)
+        blend_gemm_block<T, kBlendVALU, 4>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, local, g);
+    else
+        blend_gemm_block<T, kBlendF32, 4>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, local, g);
+}
+
 __global__ __launch_bounds__(kBlendThreads) void k_blend_batched(const BatchVolume *vols, int n_vols) {
-    __shared__ BlendSmem sm;
+    __shared__ BatchedBlendSmem sm;
     const int g = xcd_logical_block();
     const int v = __builtin_amdgcn_readfirstlane(find_volume<true>(vols, n_vols, g));
     const BatchVolume &bv = vols[v];
     const int local = g - bv.first_blend;
-    const int p0 = (local / kBlendSplit) * kBlendTile, part = local % kBlendSplit;
     if (bv.fp16)
-        blend_tile_any<__half>(bv.vp, bv.dirs, bv.rays, (__half *)bv.irr, (__half *)bv.vis, bv.h, p0, part, sm);
+        blend_batched_block<__half>(bv, local, sm);
     else
-        blend_tile_any<float>(bv.vp, bv.dirs, bv.rays, (float *)bv.irr, (float *)bv.vis, bv.h, p0, part, sm);
+        blend_batched_block<float>(bv, local, sm);
 }
 
 hipError_t launch_trace_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, const FrameParams *frames_dev,

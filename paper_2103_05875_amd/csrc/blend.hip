@@ -3,30 +3,58 @@
 //               thread per ray); also clears the trace's work counters
 //   k_blend     weighted means on the FP32 matrix cores, hysteresis, FP32 or
 //               FP16 store, guard bands
-#include "blend_device.h"
+#include "blend_gemm.h"
 
 namespace pv {
 
 constexpr int kDirThreads = 256;
+static_assert(kDirThreads == 256, "a weight-table block is four wavefronts, one row tile each");
 
-// queue: the work counters of the trace that follows, zeroed here
-__global__ __launch_bounds__(kDirThreads) void k_raydirs(FrameParams fp, int n, float4 *dirs, int *queue) {
+__host__ __device__ inline int dir_blocks(int n) { return (n + kDirThreads - 1) / kDirThreads; }
+__host__ __device__ inline int table_blocks(int mode) {
+    return (mode == kBlendBF16x3 || mode == kBlendF32 || mode == kBlendVALU) ? kMTiles / 4 : 0;
+}
+
+// Blocks [0, dir_blocks): one thread per ray direction; the next
+// table_blocks(mode) blocks: the weight table after the directions (four
+// row tiles each). queue: the work counters of the trace that follows,
+// zeroed here.
+__global__ __launch_bounds__(kDirThreads) void k_raydirs(FrameParams fp, int n, float4 *dirs, int *queue, int mode,
+                                                         int sharp) {
+    __shared__ float3 sdir[PV_MAX_RAYS];
+    const int db = dir_blocks(n);
+    if ((int)blockIdx.x >= db) {
+        weight_table_block(fp, n, sharp, mode, reinterpret_cast<uint8_t *>(dirs) + dirs_span(n), blockIdx.x - db,
+                           sdir);
+        return;
+    }
     if (queue && blockIdx.x == 0 && threadIdx.x < 9) queue[threadIdx.x * kQueueStride] = 0;
     const int j = blockIdx.x * kDirThreads + threadIdx.x;
     if (j < n) dirs[j] = raydir(fp, n, j);
 }
 
-// Batched: block (b, v) covers rays 256b .. of volume v.
+// Batched: block (b, v) covers rays 256b .. of volume v, or one block of its
+// weight table.
 __global__ __launch_bounds__(kDirThreads) void k_raydirs_batched(const BatchVolume *vols, const FrameParams *frames,
                                                                  int n_vols) {
+    __shared__ float3 sdir[PV_MAX_RAYS];
     const int v = blockIdx.y;
     if (v >= n_vols) return;
     const BatchVolume &bv = vols[v];
+    const int n = bv.vp.n, db = dir_blocks(n);
+    if ((int)blockIdx.x >= db) {
+        if ((int)blockIdx.x - db < table_blocks(bv.vp.blend_mode))
+            weight_table_block(frames[v], n, bv.vp.vis_sharpness, bv.vp.blend_mode,
+                               reinterpret_cast<uint8_t *>(const_cast<float4 *>(bv.dirs)) + dirs_span(n),
+                               blockIdx.x - db, sdir);
+        return;
+    }
     const int j = blockIdx.x * kDirThreads + threadIdx.x;
-    if (j < bv.vp.n) const_cast<float4 *>(bv.dirs)[j] = raydir(frames[v], bv.vp.n, j);
+    if (j < n) const_cast<float4 *>(bv.dirs)[j] = raydir(frames[v], n, j);
 }
 
-int raydir_blocks(int n) { return (n + kDirThreads - 1) / kDirThreads; }
+int raydir_blocks(int n) { return dir_blocks(n); }
+int weight_blocks(int mode) { return table_blocks(mode); }
 
 template <typename T>
 __global__ __launch_bounds__(kBlendThreads) void k_blend(VolumeParams vp, const float4 *dirs, const float4 *rays, T *irr,
@@ -38,8 +66,21 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(VolumeParams vp, const 
     blend_tile_any<T>(vp, dirs, rays, irr, vis, h, p0, blk % kBlendSplit, sm);
 }
 
+// One block per 16-probe column group, G row-group wavefronts (one kernel
+// per grouping, so that the small groups are not held to the registers of
+// the large ones).
+template <typename T, int MODE, int G>
+__global__ __launch_bounds__(64 * G) void k_blend_gemm(VolumeParams vp, const float4 *dirs, const float4 *rays, T *irr,
+                                                       T *vis, float h) {
+    __shared__ BlendSmemGemm<T> sm;
+    const int cg = xcd_logical_block();
+    if (cg >= blend_column_groups(vp.P)) return;
+    blend_gemm_block<T, MODE, G>(vp, dirs, rays, irr, vis, h, cg, sm);
+}
+
 hipError_t launch_raydirs(const FrameParams &fp, const VolumeParams &vp, float4 *dirs, int *queue, hipStream_t s) {
-    hipLaunchKernelGGL(k_raydirs, dim3(raydir_blocks(vp.n)), dim3(kDirThreads), 0, s, fp, vp.n, dirs, queue);
+    hipLaunchKernelGGL(k_raydirs, dim3(dir_blocks(vp.n) + table_blocks(vp.blend_mode)), dim3(kDirThreads), 0, s, fp,
+                       vp.n, dirs, queue, vp.blend_mode, vp.vis_sharpness);
     return hipGetLastError();
 }
 
@@ -50,16 +91,45 @@ hipError_t launch_raydirs_batched(const BatchVolume *vols_dev, const FrameParams
     return hipGetLastError();
 }
 
+int blend_blocks(int P, int mode) {
+    if (mode == kBlendTiles) return (P + kBlendTile - 1) / kBlendTile * kBlendSplit;
+    return blend_column_groups(P);
+}
+
+template <typename T>
+static hipError_t launch_blend_t(const VolumeParams &vp, const float4 *dirs, const float4 *rays, T *irr, T *vis,
+                                 float h, hipStream_t s) {
+    const dim3 grid(blend_blocks(vp.P, vp.blend_mode));
+    const bool g4 = blend_row_groups(vp.P) == 4;
+    switch (vp.blend_mode) {
+    case kBlendBF16x3:
+        if (g4)
+            hipLaunchKernelGGL((k_blend_gemm<T, kBlendBF16x3, 4>), grid, dim3(256), 0, s, vp, dirs, rays, irr, vis, h);
+        else
+            hipLaunchKernelGGL((k_blend_gemm<T, kBlendBF16x3, 8>), grid, dim3(512), 0, s, vp, dirs, rays, irr, vis, h);
+        break;
+    case kBlendF32:
+        if (g4)
+            hipLaunchKernelGGL((k_blend_gemm<T, kBlendF32, 4>), grid, dim3(256), 0, s, vp, dirs, rays, irr, vis, h);
+        else
+            hipLaunchKernelGGL((k_blend_gemm<T, kBlendF32, 8>), grid, dim3(512), 0, s, vp, dirs, rays, irr, vis, h);
+        break;
+    case kBlendVALU:
+        if (g4)
+            hipLaunchKernelGGL((k_blend_gemm<T, kBlendVALU, 4>), grid, dim3(256), 0, s, vp, dirs, rays, irr, vis, h);
+        else
+            hipLaunchKernelGGL((k_blend_gemm<T, kBlendVALU, 8>), grid, dim3(512), 0, s, vp, dirs, rays, irr, vis, h);
+        break;
+    default:
+        hipLaunchKernelGGL(k_blend<T>, grid, dim3(kBlendThreads), 0, s, vp, dirs, rays, irr, vis, h);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4 *rays, void *irr, void *vis,
                         int fp16, float h, hipStream_t s) {
-    const dim3 grid((vp.P + kBlendTile - 1) / kBlendTile * kBlendSplit);
-    if (fp16)
-        hipLaunchKernelGGL(k_blend<__half>, grid, dim3(kBlendThreads), 0, s, vp, dirs, rays, (__half *)irr,
-                           (__half *)vis, h);
-    else
-        hipLaunchKernelGGL(k_blend<float>, grid, dim3(kBlendThreads), 0, s, vp, dirs, rays, (float *)irr, (float *)vis,
-                           h);
-    return hipGetLastError();
+    if (fp16) return launch_blend_t<__half>(vp, dirs, rays, (__half *)irr, (__half *)vis, h, s);
+    return launch_blend_t<float>(vp, dirs, rays, (float *)irr, (float *)vis, h, s);
 }
 
 }  // namespace pv

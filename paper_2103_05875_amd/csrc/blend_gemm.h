@@ -1,0 +1,484 @@
+// The blend as a matrix product over a per-frame weight table, device side.
+//
+// The weights W[t][j] (texel row t, ray j: max(0, w_t . d_j), to the power s
+// for visibility rows) are shared by every probe of a volume-frame, so they
+// are evaluated once per frame, by extra blocks of the ray-direction launch,
+// into a table laid out as the matrix cores' A operand: per step of 32 rays,
+// per tile of 16 rows, per lane, 32 bytes. The blend then multiplies that
+// table with the ray records of 16 probes per wavefront:
+//   E_irr[t][q] (channel c) = sum_j W[t][j] L[q][j][c]   t < 64
+//   E_vis[t][q] (channel c) = sum_j W[64 + t][j] R_c[q][j]  (R = r, r^2)
+// A block owns 16 probes (their records staged through LDS, shared by its
+// wavefronts) and each of its wavefronts a group of the 44 output tiles of
+// 16 x 16 (row tiles x channels; four groups of 10 to 12, or eight of four
+// to six), so each weight fragment a wavefront loads feeds two or three
+// products and each ray record up to five.
+//
+// Two numeric paths:
+//   BF16x3: 16x16x32 BF16 MFMA. Weights and records are split into a BF16
+//           high half and a BF16 low half (x = hi + lo + O(2^-18 x)), and
+//           each product is hi*hi + hi*lo + lo*hi with FP32 accumulation:
+//           about 2^-16 of relative error per term, far below the binary16
+//           spacing (2^-11) of the maps it serves.
+//   F32:    16x16x4 FP32 MFMA, eight k-steps per 32 rays.
+// Operand layouts (lane l): 16x16x32 BF16: A[l%16][8(l/16) + i], B[8(l/16)
+// + i][l%16], i < 8; 16x16x4 FP32: A[l%16][l/16], B[l/16][l%16]; both give
+// D[4(l/16) + r][l%16] in accumulator register r.
+#pragma once
+
+#include "blend_device.h"
+
+namespace pv {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_bits(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
+__device__ __forceinline__ float bf16_value(unsigned short b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Weight of texel row m (0-63 irradiance, 64-319 visibility) for direction d.
+template <int S>
+__device__ __forceinline__ float row_weight(float3 om, bool vis_row, int sharp, float3 d) {
+    const float c = fmaxf(dot3(om, d), 0.f);
+    return vis_row ? pow_int<S>(c, sharp) : c;
+}
+
+__device__ __forceinline__ float3 row_dir(int m) {
+    return m < 64 ? oct_texel_dir(8, m & 7, m >> 3) : oct_texel_dir(16, (m - 64) & 15, (m - 64) >> 4);
+}
+
+// Table rows of one 16-row tile by one wavefront of a 256-thread block:
+// the block first puts all n directions of the frame into LDS (the same FP32
+// values as the direction kernel), then every wavefront evaluates its own
+// tile's weights; the row totals are each lane's partial sum, then the sum
+// across the four lanes of a row (a fixed order, so every run gives the
+// same totals).
+template <int S>
+__device__ void weight_tile_block(const FrameParams &fp, int n, int sharp, int mode, uint8_t *tab, int mt,
+                                  float3 *sdir) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) sdir[j] = xyz(raydir(fp, n, j));
+    __syncthreads();
+    if (mt >= kMTiles) return;
+    const int lane = threadIdx.x & 63, q = lane & 15, kq = lane >> 4;
+    const int m = 16 * mt + q;
+    const bool vis_row = m >= 64;
+    const float3 om = row_dir(m);
+    const int steps = (n + kWStep - 1) / kWStep;
+    float sum = 0.f;
+    for (int s = 0; s < steps; ++s) {
+        uint4 *dst = reinterpret_cast<uint4 *>(tab + (((size_t)s * kMTiles + mt) * 64 + lane) * 32);
+        if (mode == kBlendBF16x3) {
+            unsigned short hi[8], lo[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int j = s * kWStep + 8 * kq + i;
+                const float w = j < n ? row_weight<S>(om, vis_row, sharp, sdir[j]) : 0.f;
+                sum += w;
+                hi[i] = bf16_bits(w);
+                lo[i] = bf16_bits(w - bf16_value(hi[i]));
+            }
+            dst[0] = make_uint4(hi[0] | (uint32_t)hi[1] << 16, hi[2] | (uint32_t)hi[3] << 16,
+                                hi[4] | (uint32_t)hi[5] << 16, hi[6] | (uint32_t)hi[7] << 16);
+            dst[1] = make_uint4(lo[0] | (uint32_t)lo[1] << 16, lo[2] | (uint32_t)lo[3] << 16,
+                                lo[4] | (uint32_t)lo[5] << 16, lo[6] | (uint32_t)lo[7] << 16);
+        } else if (mode == kBlendVALU) {
+            // rows 4 r4 .. 4 r4 + 3 of the tile side by side per ray of the
+            // step, so that a lane's four rows are one 16-byte load
+            float *dv = reinterpret_cast<float *>(tab + ((size_t)s * kMTiles + mt) * 64 * 32);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = 4 * i + kq, j = s * kWStep + k;
+                const float w = j < n ? row_weight<S>(om, vis_row, sharp, sdir[j]) : 0.f;
+                sum += w;
+                dv[((q >> 2) * kWStep + k) * 4 + (q & 3)] = w;
+            }
+        } else {
+            float w[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int j = s * kWStep + 4 * i + kq;
+                w[i] = j < n ? row_weight<S>(om, vis_row, sharp, sdir[j]) : 0.f;
+                sum += w[i];
+            }
+            dst[0] = make_uint4(__float_as_uint(w[0]), __float_as_uint(w[1]), __float_as_uint(w[2]),
+                                __float_as_uint(w[3]));
+            dst[1] = make_uint4(__float_as_uint(w[4]), __float_as_uint(w[5]), __float_as_uint(w[6]),
+                                __float_as_uint(w[7]));
+        }
+    }
+    sum += __shfl_xor(sum, 16);
+    sum += __shfl_xor(sum, 32);
+    if (kq == 0) reinterpret_cast<float *>(tab + wtab_steps(n) * kMTiles * 64 * 32)[m] = sum;
+}
+
+// One table block (four row tiles) of the direction launch.
+__device__ __forceinline__ void weight_table_block(const FrameParams &fp, int n, int sharp, int mode, uint8_t *tab,
+                                                   int wblock, float3 *sdir) {
+    const int mt = 4 * wblock + (threadIdx.x >> 6);
+    if (sharp == 50)
+        weight_tile_block<50>(fp, n, sharp, mode, tab, mt, sdir);
+    else
+        weight_tile_block<0>(fp, n, sharp, mode, tab, mt, sdir);
+}
+
+__device__ __forceinline__ const uint8_t *weight_table(const float4 *dirs, int n) {
+    return reinterpret_cast<const uint8_t *>(dirs) + dirs_span(n);
+}
+
+// ---------------------------------------------------------------------------
+// the product
+// ---------------------------------------------------------------------------
+// High and low BF16 halves of eight values.
+__device__ __forceinline__ void split8(const float *x, bf16x8 &hi, bf16x8 &lo) {
+    u16x8 h, l;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        h[i] = bf16_bits(x[i]);
+        l[i] = bf16_bits(x[i] - bf16_value(h[i]));
+    }
+    hi = __builtin_bit_cast(bf16x8, h);
+    lo = __builtin_bit_cast(bf16x8, l);
+}
+
+// Channel c of a ray record: radiance r, g, b (c < 3), distance, distance^2.
+__device__ __forceinline__ float channel(float4 r, int c) {
+    return c == 0 ? r.x : c == 1 ? r.y : c == 2 ? r.z : c == 3 ? r.w : r.w * r.w;
+}
+
+// Output tiles of a wavefront: NI irradiance row tiles (three channels)
+// from irradiance tile I0, NV visibility row tiles (two channels) from
+// visibility tile V0.
+template <int I0, int NI, int V0, int NV>
+struct TileSet {
+    static constexpr int kRowTiles = NI + NV;
+    static constexpr int kTiles = 3 * NI + 2 * NV;
+    static constexpr int kChannels = NI > 0 ? (NV > 0 ? 5 : 3) : 2;  // record channels used
+    static constexpr int kC0 = NI > 0 ? 0 : 3;                        // first of them
+    v4f acc[kTiles];
+    // global row tile (0-3 irradiance, 4-19 visibility) of row tile t
+    __device__ static constexpr int mtile(int t) { return t < NI ? I0 + t : 4 + V0 + (t - NI); }
+};
+
+// A fragment of row tile mt at step s for this lane (32 bytes).
+__device__ __forceinline__ void load_frag(const uint8_t *tab, int s, int mt, uint4 &a0, uint4 &a1) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(tab) + (((size_t)s * kMTiles + mt) * 64 + (threadIdx.x & 63)) * 2;
+    a0 = p[0];
+    a1 = p[1];
+}
+
+// Records of one 32-ray step of a column group, shared through LDS by the
+// group's row-group wavefronts (loaded once, coalesced: consecutive threads
+// take consecutive records of a probe). A probe's row is padded by one
+// record so that the fragment reads of 16 probes spread over the banks.
+struct BlendRecs {
+    float4 r[2][16][kWStep + 1];
+};
+
+// The block's 16 probe tiles in LDS for the epilogue, in the maps' own
+// layout: irradiance [16][3][10][10] then visibility [16][2][18][18] of the
+// map type (30,336 bytes in binary16); shares its LDS with the records.
+template <typename T>
+struct BlendImage {
+    static constexpr int kIrrElems = 16 * 3 * 100, kVisElems = 16 * 2 * 324;
+    static constexpr int kBytes = (kIrrElems + kVisElems) * (int)sizeof(T);
+    static_assert(kIrrElems * sizeof(T) % 16 == 0 && kBytes % 16 == 0, "16-byte chunks");
+    T v[kIrrElems + kVisElems];
+};
+
+template <typename T>
+union BlendSmemGemm {
+    BlendRecs recs;
+    BlendImage<T> img;
+};
+
+// Tile element e of an (N + 2)^2 tile -> the element whose value it holds:
+// itself inside, across an edge the interior texel the octahedral fold puts
+// next to it (rows first, then columns, which also maps the corners to the
+// diagonally opposite interior corner).
+__device__ __forceinline__ int guard_source(int N, int e) {
+    const int S = N + 2;
+    int y = e / S, x = e - y * S;
+    if (y == 0 || y == N + 1) {
+        y = y == 0 ? 1 : N;
+        x = N + 1 - x;
+    }
+    if (x == 0 || x == N + 1) {
+        x = x == 0 ? 1 : N;
+        y = N + 1 - y;
+    }
+    return y * S + x;
+}
+
+// Copies between the maps and the block's LDS image in 16-byte chunks
+// (probes p0 .. p0 + np - 1; to_lds: load the stored tiles, else write the
+// image out with every guard texel taken from its interior source).
+template <typename T>
+__device__ __forceinline__ void image_copy(T *irr, T *vis, int p0, int np, BlendImage<T> &img, bool to_lds) {
+    constexpr int kPer = 16 / (int)sizeof(T);
+    // whole chunks; an odd probe count leaves half a chunk of binary16
+    // irradiance (648 elements per probe are always whole chunks)
+    const int ni = np * 300 / kPer, nv = np * 648 / kPer;
+    const int tail = np * 300 - ni * kPer;
+    if (threadIdx.x < tail) {
+        const int e = ni * kPer + threadIdx.x, tile = e / 100;
+        if (to_lds)
+            img.v[e] = irr[(size_t)p0 * 300 + e];
+        else
+            irr[(size_t)p0 * 300 + e] = img.v[tile * 100 + guard_source(8, e - tile * 100)];
+    }
+    uint4 *gi = reinterpret_cast<uint4 *>(irr + (size_t)p0 * 300), *gv = reinterpret_cast<uint4 *>(vis + (size_t)p0 * 648);
+    uint4 *li = reinterpret_cast<uint4 *>(img.v), *lv = reinterpret_cast<uint4 *>(img.v + BlendImage<T>::kIrrElems);
+    for (int c = threadIdx.x; c < ni + nv; c += blockDim.x) {
+        const bool is_vis = c >= ni;
+        const int cc = is_vis ? c - ni : c;
+        if (to_lds) {
+            (is_vis ? lv : li)[cc] = (is_vis ? gv : gi)[cc];
+            continue;
+        }
+        const int S2 = is_vis ? 324 : 100, N = is_vis ? 16 : 8;
+        const T *base = is_vis ? img.v + BlendImage<T>::kIrrElems : img.v;
+        T out[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = cc * kPer + u, tile = e / S2;
+            out[u] = base[tile * S2 + guard_source(N, e - tile * S2)];
+        }
+        (is_vis ? gv : gi)[cc] = *reinterpret_cast<const uint4 *>(out);
+    }
+}
+
+// Prefetch of step s's records by the block's NT threads into registers.
+template <int NT>
+struct RecPrefetch {
+    static constexpr int kPer = 16 * kWStep / NT;
+    float4 v[kPer];
+    __device__ __forceinline__ void load(const float4 *rays, int n, int P, int cg, int s) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = threadIdx.x + u * NT, qq = e / kWStep, k = e % kWStep;
+            const int p = 16 * cg + qq, j = s * kWStep + k;
+            v[u] = (p < P && j < n) ? rays[(size_t)p * n + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+    __device__ __forceinline__ void store(BlendRecs &sm, int buf) const {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = threadIdx.x + u * NT;
+            sm.r[buf][e / kWStep][e % kWStep] = v[u];
+        }
+    }
+};
+
+// One wavefront of the blend: probes 16 cg .. 16 cg + 15 (the block's column
+// group; NT threads of G row-group wavefronts), its tile set, all steps,
+// then the epilogue (estimate = sum / row total, hysteresis, store with
+// guard copies, through the block's LDS image of its tiles). The next
+// step's records (into LDS, by the whole block) and weight fragments are
+// loaded while the current products run.
+template <typename T, int MODE, int NT, int I0, int NI, int V0, int NV>
+__device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, const float4 *rays, T *irr, T *vis,
+                                 float h, int cg, BlendSmemGemm<T> &smu) {
+    BlendRecs &sm = smu.recs;
+    using TS = TileSet<I0, NI, V0, NV>;
+    constexpr int RT = TS::kRowTiles, NC = TS::kChannels, C0 = TS::kC0;
+    const int lane = threadIdx.x & 63, q = lane & 15, kq = lane >> 4;
+    const int n = vp.n, P = vp.P;
+    const int p = 16 * cg + q;
+    const bool live = p < P;
+    const uint8_t *tab = weight_table(dirs, n);
+    const int steps = (n + kWStep - 1) / kWStep;
+    TS ts;
+#pragma unroll
+    for (int t = 0; t < TS::kTiles; ++t) ts.acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    RecPrefetch<NT> pf;
+    pf.load(rays, n, P, cg, 0);
+    pf.store(sm, 0);
+    __syncthreads();
+    // weight fragments of every row tile of the wavefront: this step's, and
+    // the next step's requested before this step's products
+    uint4 acur[RT][2], anxt[RT][2];
+    if constexpr (MODE != kBlendVALU) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) load_frag(tab, 0, TS::mtile(t), acur[t][0], acur[t][1]);
+    }
+    for (int s = 0; s < steps; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < steps) {
+            pf.load(rays, n, P, cg, s + 1);
+            if constexpr (MODE != kBlendVALU) {
+#pragma unroll
+                for (int t = 0; t < RT; ++t) load_frag(tab, s + 1, TS::mtile(t), anxt[t][0], anxt[t][1]);
+            }
+        }
+        if constexpr (MODE == kBlendVALU) {
+            // vector FMAs: the lane's rows 4 kq .. 4 kq + 3 of every row tile
+            // against its probe's records, four rays at a time
+            const float4 *wt = reinterpret_cast<const float4 *>(tab) + (size_t)s * kMTiles * 128;
+#pragma unroll 1
+            for (int k0 = 0; k0 < kWStep; k0 += 4) {
+                float rc[4][NC];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float4 r = sm.r[buf][q][k0 + i];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) rc[i][c] = channel(r, C0 + c);
+                }
+#pragma unroll
+                for (int t = 0; t < RT; ++t) {
+                    const bool it = t < NI;
+                    const int nch = it ? 3 : 2;
+                    const int acc0 = it ? 3 * t : 3 * NI + 2 * (t - NI);
+                    const int ch0 = it ? 0 : NC - 2;
+                    const float4 *w = wt + TS::mtile(t) * 128 + kq * kWStep + k0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float4 wv = w[i];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            if (c >= nch) continue;
+                            v4f &a = ts.acc[acc0 + c];
+                            const float x = rc[i][ch0 + c];
+                            a[0] = fmaf(wv.x, x, a[0]);
+                            a[1] = fmaf(wv.y, x, a[1]);
+                            a[2] = fmaf(wv.z, x, a[2]);
+                            a[3] = fmaf(wv.w, x, a[3]);
+                        }
+                    }
+                }
+            }
+        } else {
+            // the step's operand fragments: BF16x3 rays 8 kq .. 8 kq + 7, F32
+            // ray 4 i + kq of probe q
+            bf16x8 bh[NC], bl[NC];
+            float bf[NC][8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float4 r = sm.r[buf][q][MODE == kBlendBF16x3 ? 8 * kq + i : 4 * i + kq];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) bf[c][i] = channel(r, C0 + c);
+            }
+            if (MODE == kBlendBF16x3) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) split8(bf[c], bh[c], bl[c]);
+            }
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const uint4 a0 = acur[t][0], a1 = acur[t][1];
+                const bool it = t < NI;
+                const int nch = it ? 3 : 2;
+                const int acc0 = it ? 3 * t : 3 * NI + 2 * (t - NI);
+                const int ch0 = it ? 0 : NC - 2;  // first channel slot of the tile's texture
+                if (MODE == kBlendBF16x3) {
+                    const bf16x8 ah = __builtin_bit_cast(bf16x8, a0), al = __builtin_bit_cast(bf16x8, a1);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        if (c >= nch) continue;
+                        v4f &a = ts.acc[acc0 + c];
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ch0 + c], a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ch0 + c], a, 0, 0, 0);
+                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ch0 + c], a, 0, 0, 0);
+                    }
+                } else {
+                    const float w[8] = {__uint_as_float(a0.x), __uint_as_float(a0.y), __uint_as_float(a0.z),
+                                        __uint_as_float(a0.w), __uint_as_float(a1.x), __uint_as_float(a1.y),
+                                        __uint_as_float(a1.z), __uint_as_float(a1.w)};
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        if (c >= nch) continue;
+                        v4f &a = ts.acc[acc0 + c];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            a = __builtin_amdgcn_mfma_f32_16x16x4f32(w[i], bf[ch0 + c][i], a, 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // every wavefront is done with the other buffer since the last step's barrier
+        if (s + 1 < steps) {
+            pf.store(sm, buf ^ 1);
+            if constexpr (MODE != kBlendVALU) {
+#pragma unroll
+                for (int t = 0; t < RT; ++t) {
+                    acur[t][0] = anxt[t][0];
+                    acur[t][1] = anxt[t][1];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // epilogue, through the block's LDS image of its probes' tiles: the
+    // stored tiles are loaded (coalesced), each wavefront replaces its
+    // interior texels by the new values (estimate = sum / row total,
+    // hysteresis, the map's rounding; a texel whose total is at most the
+    // floor keeps its value), and the tiles are written back whole, guard
+    // texels copied from their interior sources
+    BlendImage<T> &img = smu.img;
+    const int np = min(16, P - 16 * cg);
+    image_copy<T>(irr, vis, 16 * cg, np, img, true);
+    __syncthreads();
+    const float *rows = reinterpret_cast<const float *>(tab + wtab_steps(n) * kMTiles * 64 * 32);
+    if (live) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            const bool it = t < NI;
+            const int N = it ? 8 : 16, nch = it ? 3 : 2;
+            const int mloc = it ? I0 + t : V0 + (t - NI);
+            const int acc0 = it ? 3 * t : 3 * NI + 2 * (t - NI);
+            float total[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) total[r] = rows[(it ? 0 : 64) + 16 * mloc + 4 * kq + r];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (c >= nch) continue;
+                T *tile = it ? img.v + (q * 3 + c) * 100 : img.v + BlendImage<T>::kIrrElems + (q * 2 + c) * 324;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float w = total[r];
+                    if (!(w > kWeightFloor)) continue;
+                    T &dst = tile[interior(N, 16 * mloc + 4 * kq + r)];
+                    const float est = ts.acc[acc0 + c][r] * (1.0f / w);
+                    dst = to_map<T>(h > 0.f ? fmaf(h, load_map<T>(&dst), (1.0f - h) * est) : est);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    image_copy<T>(irr, vis, 16 * cg, np, img, false);
+}
+
+// Row groups of a volume's blend: G row-group wavefronts per 16-probe column
+// group, one block per column group (G = 4 for large volumes and in the
+// batched launch, 8 for small volumes so that enough wavefronts run; which
+// wavefront computes a tile does not change its result).
+__host__ __device__ inline int blend_row_groups(int P) { return (P + 15) / 16 >= 512 ? 4 : 8; }
+__host__ __device__ inline int blend_column_groups(int P) { return (P + 15) / 16; }
+
+template <typename T, int MODE, int G>
+__device__ __forceinline__ void blend_gemm_block(const VolumeParams &vp, const float4 *dirs, const float4 *rays, T *irr,
+                                                 T *vis, float h, int cg, BlendSmemGemm<T> &sm) {
+    constexpr int NT = 64 * G;
+    const int g = threadIdx.x >> 6;
+    if (G == 4) {
+        // irradiance (12 tiles) | visibility rows 0-95 (12) | 96-175 (10) | 176-255 (10)
+        switch (g) {
+        case 0: blend_gemm_tiles<T, MODE, NT, 0, 4, 0, 0>(vp, dirs, rays, irr, vis, h, cg, sm); break;
+        case 1: blend_gemm_tiles<T, MODE, NT, 0, 0, 0, 6>(vp, dirs, rays, irr, vis, h, cg, sm); break;
+        case 2: blend_gemm_tiles<T, MODE, NT, 0, 0, 6, 5>(vp, dirs, rays, irr, vis, h, cg, sm); break;
+        default: blend_gemm_tiles<T, MODE, NT, 0, 0, 11, 5>(vp, dirs, rays, irr, vis, h, cg, sm); break;
+        }
+        return;
+    }
+    // eight groups: two of irradiance (6 tiles each), six of visibility (6, 6, 6, 6, 4, 4)
+    switch (g) {
+    case 0: blend_gemm_tiles<T, MODE, NT, 0, 2, 0, 0>(vp, dirs, rays, irr, vis, h, cg, sm); break;
+    case 1: blend_gemm_tiles<T, MODE, NT, 2, 2, 0, 0>(vp, dirs, rays, irr, vis, h, cg, sm); break;
+    case 2: blend_gemm_tiles<T, MODE, NT, 0, 0, 0, 3>(vp, dirs, rays, irr, vis, h, cg, sm); break;
+    case 3: blend_gemm_tiles<T, MODE, NT, 0, 0, 3, 3>(vp, dirs, rays, irr, vis, h, cg, sm); break;
+    case 4: blend_gemm_tiles<T, MODE, NT, 0, 0, 6, 3>(vp, dirs, rays, irr, vis, h, cg, sm); break;
+    case 5: blend_gemm_tiles<T, MODE, NT, 0, 0, 9, 3>(vp, dirs, rays, irr, vis, h, cg, sm); break;
+    case 6: blend_gemm_tiles<T, MODE, NT, 0, 0, 12, 2>(vp, dirs, rays, irr, vis, h, cg, sm); break;
+    default: blend_gemm_tiles<T, MODE, NT, 0, 0, 14, 2>(vp, dirs, rays, irr, vis, h, cg, sm); break;
+    }
+}
+
+}  // namespace pv

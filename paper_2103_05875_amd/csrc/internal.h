@@ -14,7 +14,32 @@
 namespace pv {
 
 constexpr int kTexRows = 64 + 256;  // texel rows of the blend: 64 irradiance, then 256 visibility
-constexpr int kBlendTile = 8;       // probes per blend block
+constexpr int kBlendTile = 8;       // probes per block of the per-tile blend
+
+// Blend paths (pv_blend_mode values; see blend_device.h):
+//   kBlendBF16x3  weight table, products on the BF16 matrix cores as three
+//                 products of high and low halves (FP32 accumulate)
+//   kBlendF32     weight table, FP32 matrix cores
+//   kBlendTiles   weights evaluated per 8-probe tile in registers, FP32
+//                 matrix cores (no table)
+//   kBlendVALU    weight table, FP32 vector FMAs
+enum BlendMode : int { kBlendAuto = 0, kBlendBF16x3 = 1, kBlendF32 = 2, kBlendTiles = 3, kBlendVALU = 4 };
+// The default path of a volume of P probes: the per-tile weights below
+// kTableMinProbes (a table costs a pass over every weight per frame, which
+// small volumes do not earn back), the FP32 table product from there.
+constexpr int kTableMinProbes = 4096;
+inline int auto_blend_mode(int P) { return P >= kTableMinProbes ? kBlendF32 : kBlendTiles; }
+
+// The per-volume-frame weight table follows the ray directions in their
+// buffer: steps of kWStep rays x kMTiles row tiles of 16 texel rows x 64
+// lanes x 32 bytes (the lane's MFMA A-operand fragment of that step: eight
+// FP32 weights, or eight BF16 high halves then eight low halves), then the
+// kTexRows FP32 row totals.
+constexpr int kWStep = 32;
+constexpr int kMTiles = kTexRows / 16;
+__host__ __device__ inline size_t dirs_span(int n) { return ((size_t)n * 16 + 255) / 256 * 256; }
+__host__ __device__ inline size_t wtab_steps(int n) { return (size_t)(n + kWStep - 1) / kWStep; }
+__host__ __device__ inline size_t wtab_bytes(int n) { return wtab_steps(n) * kMTiles * 64 * 32 + kTexRows * 4; }
 
 // Work description of one volume for the batched launch.
 struct BatchVolume {
@@ -43,8 +68,11 @@ struct BatchVolume {
 // Launchers (trace.hip, blend.hip, batched.hip, bounce.hip, pack.hip)
 // ---------------------------------------------------------------------------
 // Ray directions; the 9 work counters are zeroed for the trace that follows
+// (plus the weight table after the directions when the blend mode uses one)
 hipError_t launch_raydirs(const FrameParams &fp, const VolumeParams &vp, float4 *dirs, int *queue, hipStream_t s);
 int raydir_blocks(int n);
+int weight_blocks(int mode);  // extra blocks of the direction launch that build the table
+int blend_blocks(int P, int mode);  // 256-thread blocks of one volume's blend
 hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4 *rays, void *irr, void *vis,
                         int fp16, float h, hipStream_t s);
 // Batched trace / blend over every volume of a batch (descriptors on the

@@ -124,6 +124,7 @@ struct pv_volume {
     pv_scene *scene = nullptr;
     TraceConfig tc;
     SplitBuffers split;    // allocated on first use of the split-shadow trace
+    int blend_mode = kBlendF32;     // resolved BlendMode
 };
 
 struct pv_client {
@@ -494,8 +495,8 @@ static pv_status validate_desc(const pv_volume_desc *d) {
 static uint64_t volume_bytes(const pv_volume_desc *d) {
     const int P = d->nx * d->ny * d->nz, n = d->rays_per_probe;
     const size_t elem = d->format == PV_MAP_FP16 ? 2 : 4;
-    uint64_t b = irr_bytes(P, elem) + vis_bytes(P, elem) + 512 + (uint64_t)P * n * 16 + (uint64_t)n * 16 +
-                 (uint64_t)kQueueInts * 4;
+    uint64_t b = irr_bytes(P, elem) + vis_bytes(P, elem) + 512 + (uint64_t)P * n * 16 + dirs_span(n) +
+                 wtab_bytes(n) + (uint64_t)kQueueInts * 4;
     if (d->flags & PV_KEEP_HITS) b += (uint64_t)P * n * 4;
     if (d->flags & (PV_MULTI_BOUNCE | PV_CLASSIFY)) b += (uint64_t)P * n * 8;
     if (d->flags & PV_CLASSIFY) b += (uint64_t)P;
@@ -534,11 +535,13 @@ extern "C" pv_status pv_create_volume(pv_ctx *ctx, const pv_volume_desc *d, pv_v
     v->P = d->nx * d->ny * d->nz;
     v->n = d->rays_per_probe;
     v->elem = d->format == PV_MAP_FP16 ? 2 : 4;
+    v->blend_mode = auto_blend_mode(v->P);
     // 256 bytes of slack: vector loads of a ragged last tile stay in bounds
     pv_status st = dev_alloc(&v->irr, irr_bytes(v->P, v->elem) + 256, "irradiance maps");
     if (st == PV_OK) st = dev_alloc(&v->vis, vis_bytes(v->P, v->elem) + 256, "visibility maps");
     if (st == PV_OK) st = dev_alloc(&v->rays, (size_t)v->P * v->n * 16, "ray buffer");
-    if (st == PV_OK) st = dev_alloc(&v->dirs, (size_t)v->n * 16, "directions");
+    // the ray directions, then the blend's weight table
+    if (st == PV_OK) st = dev_alloc(&v->dirs, dirs_span(v->n) + wtab_bytes(v->n), "directions and blend weights");
     if (st == PV_OK && (d->flags & PV_KEEP_HITS)) st = dev_alloc(&v->hits, (size_t)v->P * v->n * 4, "hit ids");
     if (st == PV_OK && (d->flags & (PV_MULTI_BOUNCE | PV_CLASSIFY)))
         st = dev_alloc(&v->hitrec, (size_t)v->P * v->n * sizeof(int2), "hit records");
@@ -619,6 +622,7 @@ static VolumeParams volume_params(const pv_volume *v) {
     p.max_distance = d.max_distance;
     for (int k = 0; k < 3; ++k) p.sky[k] = d.sky[k];
     p.vis_sharpness = d.vis_sharpness;
+    p.blend_mode = v->blend_mode;
     p.hitrec = v->hitrec;
     return p;
 }
@@ -768,10 +772,26 @@ extern "C" pv_status pv_blend_rays(pv_volume *v, const pv_frame *f, const void *
     HIP_TRY(hipSetDevice(v->ctx->device));
     hipStream_t s = pick(v->ctx, stream);
     const VolumeParams vp = volume_params(v);
-    HIP_TRY(launch_raydirs(fp, vp, v->dirs, nullptr, s));
-    HIP_TRY(launch_blend(vp, v->dirs, (const float4 *)rays_dev, v->irr, v->vis, v->desc.format == PV_MAP_FP16,
-                         effective_h(v), s));
+    pv_ctx *c = v->ctx;
+    const float h = effective_h(v);
+    HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s, [&] { return launch_raydirs(fp, vp, v->dirs, nullptr, s); }));
+    HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] {
+        return launch_blend(vp, v->dirs, (const float4 *)rays_dev, v->irr, v->vis, v->desc.format == PV_MAP_FP16, h, s);
+    }));
     v->frame++;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_volume_set_blend_mode(pv_volume *v, int mode) {
+    if (!v) return fail(PV_ERR_ARG, "volume is NULL");
+    if (mode < PV_BLEND_AUTO || mode > PV_BLEND_VALU) return fail(PV_ERR_ARG, "unknown blend mode");
+    v->blend_mode = mode == PV_BLEND_AUTO ? auto_blend_mode(v->P) : mode;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_volume_get_blend_mode(pv_volume *v, int *mode) {
+    if (!v || !mode) return fail(PV_ERR_ARG, "NULL argument");
+    *mode = v->blend_mode;
     return PV_OK;
 }
 
@@ -914,7 +934,7 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
         b.sv = scene_view(v->scene);
         short_stack = short_stack && b.sv.stat.n_nodes <= 65536 && b.sv.dyn.n_nodes <= 65536;
         b.dirs = v->dirs;
-        dir_blocks = std::max(dir_blocks, raydir_blocks(v->n));
+        dir_blocks = std::max(dir_blocks, raydir_blocks(v->n) + weight_blocks(v->blend_mode));
         b.rays = v->rays;
         b.hits = v->hits;
         b.irr = v->irr;
@@ -928,7 +948,7 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
         waves = (waves + 3) / 4 * 4;  // trace blocks hold 4 packets; each volume starts on a block boundary
         b.first_wave = waves;
         waves += b.n_waves;
-        b.n_blend = (v->P + kBlendTile - 1) / kBlendTile * kBlendSplit;
+        b.n_blend = blend_blocks(v->P, v->blend_mode);
         b.first_blend = blend;
         blend += b.n_blend;
         b.n_bounce = (v->desc.flags & PV_MULTI_BOUNCE) ? bounce_blocks(v->P, v->n) : 0;

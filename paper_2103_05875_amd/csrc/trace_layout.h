@@ -90,6 +90,7 @@ struct VolumeParams {
     float max_distance;
     float sky[3];
     int vis_sharpness;
+    int blend_mode;     // BlendMode of the frame's blend (never kBlendAuto)
     // When set (second bounce on), the trace also writes every ray's hit
     // record [P][n]: x = leaf-order triangle slot with bit 31 set for the
     // dynamic BVH, or -1 for a miss; y = hit distance (float bits).

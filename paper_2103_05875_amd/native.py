@@ -22,6 +22,9 @@ PV_FIRST_FRAME_NO_HISTORY = 1
 PV_KEEP_HITS = 2
 PV_MULTI_BOUNCE = 4
 PV_CLASSIFY = 8
+# blend paths (pv_volume_set_blend_mode)
+PV_BLEND_AUTO, PV_BLEND_BF16X3, PV_BLEND_F32, PV_BLEND_TILES, PV_BLEND_VALU = 0, 1, 2, 3, 4
+BLEND_MODES = {"auto": 0, "bf16x3": 1, "f32": 2, "tiles": 3, "valu": 4}
 # pv_measure_ceiling kinds
 PV_CEIL_COPY, PV_CEIL_FMA_F32, PV_CEIL_MFMA_F32 = 0, 1, 2
 PV_MAX_LIGHTS = 8
@@ -41,7 +44,7 @@ EXPORTED_SYMBOLS = [
     "pv_receiver_get_maps", "pv_receiver_read_maps", "pv_yuv_dims", "pv_encode_yuv", "pv_decode_yuv",
     "pv_get_active", "pv_client_set_view", "pv_client_clear_view", "pv_client_get_view",
     "pv_entropy_encode", "pv_entropy_download", "pv_receiver_apply_compressed", "pv_pack_delta_noalloc",
-    "pv_scene_read_bvh",
+    "pv_scene_read_bvh", "pv_volume_set_blend_mode", "pv_volume_get_blend_mode",
 ]
 
 STAGES = ["raydirs", "trace", "blend", "pack_mask", "pack_scan", "pack_compact", "batched", "shadow", "shade",
@@ -165,6 +168,8 @@ def lib():
         "pv_batch_graph_launch": ([vp, P(Frame), vp], i32),
         "pv_batch_graph_destroy": ([vp], i32),
         "pv_volume_get_trace_config": ([vp, P(TraceConfig)], i32),
+        "pv_volume_set_blend_mode": ([vp, i32], i32),
+        "pv_volume_get_blend_mode": ([vp, P(i32)], i32),
         "pv_client_set_state": ([vp, vp, vp, u32], i32),
         "pv_ctx_stage_times": ([vp, P(ctypes.c_double), P(u64)], i32),
     }
@@ -417,6 +422,16 @@ class Volume:
         c.block_threads = int(block_threads)
         c.split_shadows = 1 if split_shadows else 0
         _check(lib().pv_volume_set_trace_config(self.h, ctypes.byref(c)))
+
+    def set_blend_mode(self, mode):
+        """Blend path: "auto", "bf16x3", "f32", "tiles", "valu" or its number."""
+        _check(lib().pv_volume_set_blend_mode(self.h, BLEND_MODES.get(mode, mode) if isinstance(mode, str)
+                                              else int(mode)))
+
+    def get_blend_mode(self) -> str:
+        m = ctypes.c_int(0)
+        _check(lib().pv_volume_get_blend_mode(self.h, ctypes.byref(m)))
+        return {v: k for k, v in BLEND_MODES.items()}[m.value]
 
     def get_trace_config(self) -> dict:
         c = TraceConfig()

@@ -354,6 +354,57 @@ def test_blend_from_given_rays(ps, ctx, O, fp16, n, grid, sharp):
     vol.close()
 
 
+@pytest.mark.parametrize("mode", ["bf16x3", "f32", "tiles", "valu"])
+@pytest.mark.parametrize("fp16,n,grid", [(False, 96, (19, 1, 1)), (True, 256, (9, 5, 3)), (True, 300, (3, 2, 2)),
+                                          (False, 33, (2, 1, 1))])
+def test_blend_paths_against_oracle(ps, ctx, O, mode, fp16, n, grid):
+    """Every blend path (weight table with BF16x3 or FP32 products, or the
+    per-tile weights) on the same seeded ray records over four frames of
+    hysteresis: FP16 maps within 2 ulps (1 ulp for 99.9%) of the oracle's
+    FP16 trajectory; FP32 maps within 1e-5 (the BF16x3 products, whose terms
+    carry about 2^-16 of relative error, within 1e-4)."""
+    import torch
+    _say(f"blend path {mode} fp16={fp16} n={n} grid={grid}")
+    cfg = synth.VolumeConfig(*grid, (0, 0, 0), (1, 1, 1), n, fp16=fp16, max_distance=4.0)
+    vol = ps.Volume(ctx, cfg)
+    vol.set_blend_mode(mode)
+    assert vol.get_blend_mode() == mode
+    irr_o, vis_o = O.empty_maps(cfg)
+    for f in range(4):
+        R = synth.rotation(70 + n, f)
+        L, r = synth.synthetic_rays(cfg.n_probes, n, seed=10 * f + n)
+        rec = np.concatenate([L, r[..., None]], axis=-1).astype(np.float32)
+        dev = torch.from_numpy(rec).cuda()
+        torch.cuda.synchronize()
+        vol.blend_rays(R, dev.data_ptr())
+        ps.native.sync()
+        O.blend_update(cfg, O.ray_dirs(n, R), L, r, irr_o, vis_o, first=(f == 0))
+        irr, vis, _ = vol.read_maps()
+        for name, g, o in (("irr", irr, irr_o), ("vis", vis, vis_o)):
+            if fp16:
+                d = ulps_from(g, o)
+                assert d.max() <= 2.0 and (d <= 1.0).mean() >= 0.999, (name, f, d.max())
+            else:
+                e = excess_fp32(g, o, o)[0]
+                assert e <= (1e-4 if mode == "bf16x3" else 1e-5), (name, f, e)
+        assert fold_consistent(irr) and fold_consistent(vis)
+        del dev
+    vol.close()
+
+
+def test_blend_mode_default_follows_volume_size(ps, ctx):
+    """A new volume takes the per-tile weights below 4,096 probes and the FP32
+    table product from there; AUTO restores that choice."""
+    for grid, want in (((4, 4, 4), "tiles"), ((16, 8, 16), "tiles"), ((16, 16, 16), "f32")):
+        vol = ps.Volume(ctx, synth.VolumeConfig(*grid, (0, 0, 0), (1, 1, 1), 64, fp16=True))
+        assert vol.get_blend_mode() == want
+        vol.set_blend_mode("valu")
+        assert vol.get_blend_mode() == "valu"
+        vol.set_blend_mode("auto")
+        assert vol.get_blend_mode() == want
+        vol.close()
+
+
 # ------------------------------------------------------------------ pack (bit-exact)
 def _grid_for(P):
     for nx in range(min(P, 64), 0, -1):
