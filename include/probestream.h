@@ -325,7 +325,7 @@ pv_status pv_client_set_state(pv_client *client, const void *ref_irr_host, const
  *                     else PV_ERR_CAPACITY. The header gives its size.
  * client_id and seq go into the header. Every pointer 16-byte aligned.
  * Changed masks, tile summaries, totals and checksum shares live in one
- * static device array per GPU of 288.25 KiB (held until the process ends),
+ * static device array per GPU of 384.25 KiB (held until the process ends),
  * which limits n_probes to 65,536 (PV_ERR_ARG beyond). All calls on one GPU
  * share that array: calls that overlap on a GPU (different streams, or
  * threads) race and must be ordered by the caller. Asynchronous on 'stream';
@@ -503,7 +503,7 @@ typedef enum {
     PV_STAGE_BATCHED = 6,
     PV_STAGE_SHADOW = 7,
     PV_STAGE_SHADE = 8,
-    PV_STAGE_PACK_FINISH = 9,
+    PV_STAGE_PACK_FINISH = 9, /* the packet checksum (above 4,096 probes) */
     PV_STAGE_BOUNCE = 10,
     PV_STAGE_UNPACK = 11,
     PV_STAGE_CODEC = 12,

@@ -13,12 +13,16 @@ namespace pv {
 // pack
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool texel_changed(uint16_t a, uint16_t b, float tau) {
+// |a - b| > tau for binary16 a, b, decided exactly. A difference of two
+// binary16 values is a multiple of 2^-24: below 1 it has fewer than 24
+// significant bits and binary32 holds it exactly; at or above 1 its binary32
+// rounding stays at or above 1. So for tau < 1 the binary32 difference gives
+// the exact answer; larger thresholds take the difference in binary64.
+__device__ __forceinline__ bool texel_changed(uint16_t a, uint16_t b, float tau, bool narrow) {
     if (tau == 0.f) return a != b;
-    // binary16 values are exact in double and so is their difference
-    const double da = (double)__half2float(__ushort_as_half(a));
-    const double db = (double)__half2float(__ushort_as_half(b));
-    return fabs(da - db) > (double)tau;
+    const float fa = __half2float(__ushort_as_half(a)), fb = __half2float(__ushort_as_half(b));
+    if (narrow) return fabsf(fa - fb) > tau;
+    return fabs((double)fa - (double)fb) > (double)tau;
 }
 
 // The pack works on tiles of kPackQ consecutive probes. Their FP16 tiles are
@@ -106,29 +110,116 @@ __device__ __forceinline__ void unpack8(uint4 v, uint16_t r[8]) {
     r[7] = v.w >> 16;
 }
 
+// Summary of a run of tiles: changed counts (irradiance, visibility) and the
+// last two changed probes of each texture (-1: none). Index entries are
+// deltas to the previous changed probe, so the entry just before a tile's
+// first one is last - second of the tiles before it.
+struct TileSum {
+    int ci, cv, li, lv, si, sv;
+};
+
+__device__ __forceinline__ TileSum tile_sum_none() { return TileSum{0, 0, -1, -1, -1, -1}; }
+
+// Sums and the top two probes of the union (probes of different tiles are
+// distinct): associative and commutative.
+__device__ __forceinline__ TileSum tile_merge(const TileSum &a, const TileSum &c) {
+    TileSum r;
+    r.ci = a.ci + c.ci;
+    r.cv = a.cv + c.cv;
+    r.li = max(a.li, c.li);
+    r.si = max(min(a.li, c.li), max(a.si, c.si));
+    r.lv = max(a.lv, c.lv);
+    r.sv = max(min(a.lv, c.lv), max(a.sv, c.sv));
+    return r;
+}
+
+// A tile's own summary in 32 bits (the mask pass's output): changed counts
+// (0-8) in bits 0-3 and 4-7, then the offsets in the tile (0-7, 15 = none)
+// of the last irradiance, last visibility, second-last irradiance and
+// second-last visibility changed probe in bits 8-11, 12-15, 16-19, 20-23.
+__device__ __forceinline__ uint32_t pack_tile_sum(const TileSum &v, int p0) {
+    auto off = [p0](int p) { return p < 0 ? 15u : (uint32_t)(p - p0); };
+    return (uint32_t)v.ci | (uint32_t)v.cv << 4 | off(v.li) << 8 | off(v.lv) << 12 | off(v.si) << 16 |
+           off(v.sv) << 20;
+}
+
+__device__ __forceinline__ TileSum unpack_tile_sum(uint32_t x, int p0) {
+    auto at = [x, p0](int sh) { const int o = (int)(x >> sh) & 15; return o == 15 ? -1 : p0 + o; };
+    return TileSum{(int)(x & 15u), (int)(x >> 4 & 15u), at(8), at(12), at(16), at(20)};
+}
+
+__device__ __forceinline__ TileSum own_tile_sum(const PackBuffers &b, int t) {
+    return unpack_tile_sum(b.tsum[t], t * kPackQ);
+}
+
+// The scan's output: the summary of the tiles before tile t.
+__device__ __forceinline__ TileSum load_tile_sum(const PackBuffers &b, int t) {
+    const int4 x = b.tiles[t];
+    const int2 y = b.tiles2[t];
+    return TileSum{x.x, x.y, x.z, x.w, y.x, y.y};
+}
+
+__device__ __forceinline__ void store_tile_sum(const PackBuffers &b, int t, const TileSum &v) {
+    b.tiles[t] = make_int4(v.ci, v.cv, v.li, v.lv);
+    b.tiles2[t] = make_int2(v.si, v.sv);
+}
+
+__device__ __forceinline__ TileSum shfl_tile_sum(const TileSum &v, int src) {
+    return TileSum{__shfl(v.ci, src), __shfl(v.cv, src), __shfl(v.li, src),
+                   __shfl(v.lv, src), __shfl(v.si, src), __shfl(v.sv, src)};
+}
+
+__device__ __forceinline__ TileSum shfl_up_tile_sum(const TileSum &v, int off) {
+    return TileSum{__shfl_up(v.ci, off), __shfl_up(v.cv, off), __shfl_up(v.li, off),
+                   __shfl_up(v.lv, off), __shfl_up(v.si, off), __shfl_up(v.sv, off)};
+}
+
+__device__ __forceinline__ TileSum shfl_xor_tile_sum(const TileSum &v, int off) {
+    return TileSum{__shfl_xor(v.ci, off), __shfl_xor(v.cv, off), __shfl_xor(v.li, off),
+                   __shfl_xor(v.lv, off), __shfl_xor(v.si, off), __shfl_xor(v.sv, off)};
+}
+
 // Change mask of every probe: any interior texel differs (tau = 0) or
 // |cur - ref| > tau. Each block also leaves a summary of its tile (changed
-// counts and last changed probe per texture) for the scan.
+// counts and the last two changed probes per texture) for the prefix.
 __global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P, float tau_irr, float tau_vis) {
     __shared__ PackSmem sm;
     const int p0 = blockIdx.x * kPackQ;
     if (p0 >= P) return;
     if (threadIdx.x < kPackQ * 2) sm.changed[threadIdx.x >> 1][threadIdx.x & 1] = 0;
+    const int n = min(kPackQ, P - p0);
+    constexpr int units = kPackQ * (kIrrUnits + kVisUnits);
+    constexpr int kPer = (units + kPackThreads - 1) / kPackThreads;
+    // the thread's reference rows are requested with the tile staging
+    uint4 refv[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int u = threadIdx.x + i * kPackThreads;
+        refv[i] = make_uint4(0u, 0u, 0u, 0u);
+        if (u < units) {
+            const Unit un = unit_of(u);
+            if (un.q < n) refv[i] = *reinterpret_cast<const uint4 *>(unit_ref(b, p0 + un.q, un));
+        }
+    }
     stage_tiles(b, p0, P, sm);
     __syncthreads();
-    const int n = min(kPackQ, P - p0);
-    const int units = kPackQ * (kIrrUnits + kVisUnits);
-    for (int u = threadIdx.x; u < units; u += kPackThreads) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int u = threadIdx.x + i * kPackThreads;
+        if (u >= units) continue;
         const Unit un = unit_of(u);
         if (un.q >= n) continue;
         uint16_t cur[8], ref[8];
         unit_cur(sm, un, cur);
-        unpack8(*reinterpret_cast<const uint4 *>(unit_ref(b, p0 + un.q, un)), ref);
+        unpack8(refv[i], ref);
         const float tau = un.tex == 0 ? tau_irr : tau_vis;
+        const bool narrow = tau < 1.f;
         bool ch = false;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) ch |= texel_changed(cur[i], ref[i], tau);
-        if (ch) atomicOr(&sm.changed[un.q][un.tex], 1);
+        for (int t = 0; t < 8; ++t) ch |= texel_changed(cur[t], ref[t], tau, narrow);
+        // many units of a probe may set its flag: plain stores of the same
+        // value (LDS atomics on one address serialize)
+        if (ch) __hip_atomic_store(&sm.changed[un.q][un.tex], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
     if (threadIdx.x < n) {
@@ -143,174 +234,146 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int4 s = make_int4(0, 0, -1, -1);
+        TileSum t = tile_sum_none();
         for (int q = 0; q < n; ++q) {
             if (sm.changed[q][0]) {
-                s.x++;
-                s.z = p0 + q;
+                t.ci++;
+                t.si = t.li;
+                t.li = p0 + q;
             }
             if (sm.changed[q][1]) {
-                s.y++;
-                s.w = p0 + q;
+                t.cv++;
+                t.sv = t.lv;
+                t.lv = p0 + q;
             }
         }
-        b.tiles[blockIdx.x] = s;
+        b.tsum[blockIdx.x] = pack_tile_sum(t, p0);
+        // the compaction blocks of small volumes add to the checksum
+        if (blockIdx.x == 0) reinterpret_cast<uint32_t *>(b.packet)[kHdrChecksum] = 0u;
     }
 }
 
 constexpr int kScanThreads = 1024;
 
-// Inclusive scan of (sum, sum, max, max) across the block: wavefront
-// shuffles, then the wavefront totals.
-__device__ __forceinline__ int4 block_scan_tiles(int4 v, int4 *sh) {
+// Exclusive prefix (tile_merge) of every thread's value across the block, and
+// the block's total: wavefront shuffles, then the wavefront totals.
+__device__ __forceinline__ TileSum block_exclusive_scan(const TileSum &v, TileSum *sh, TileSum &total) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    TileSum inc = v;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        const int a = __shfl_up(v.x, off), c = __shfl_up(v.y, off), z = __shfl_up(v.z, off), w = __shfl_up(v.w, off);
-        if (lane >= off) {
-            v.x += a;
-            v.y += c;
-            v.z = max(v.z, z);
-            v.w = max(v.w, w);
-        }
+        const TileSum o = shfl_up_tile_sum(inc, off);
+        if (lane >= off) inc = tile_merge(o, inc);
     }
-    if (lane == 63) sh[wv] = v;
+    if (lane == 63) sh[wv] = inc;
     __syncthreads();
-    if (threadIdx.x == 0)
-        for (int k = 1; k < kScanThreads / 64; ++k) {
-            sh[k].x += sh[k - 1].x;
-            sh[k].y += sh[k - 1].y;
-            sh[k].z = max(sh[k].z, sh[k - 1].z);
-            sh[k].w = max(sh[k].w, sh[k - 1].w);
+    if (threadIdx.x == 0) {
+        TileSum run = tile_sum_none();
+        for (int k = 0; k < kScanThreads / 64; ++k) {
+            const TileSum w = sh[k];
+            sh[k] = run;
+            run = tile_merge(run, w);
         }
-    __syncthreads();
-    if (wv > 0) {
-        const int4 o = sh[wv - 1];
-        v.x += o.x;
-        v.y += o.y;
-        v.z = max(v.z, o.z);
-        v.w = max(v.w, o.w);
+        sh[kScanThreads / 64] = run;
     }
-    return v;
+    __syncthreads();
+    TileSum ex = shfl_up_tile_sum(inc, 1);
+    if (lane == 0) ex = tile_sum_none();
+    total = sh[kScanThreads / 64];
+    return tile_merge(sh[wv], ex);
 }
 
-// One block: replaces every tile summary by the exclusive prefix of the tiles
-// before it (changed counts, last changed probe) and stores the totals
-// K_irr, K_vis in totals[0], totals[1]; clears the packet checksum.
+// One block: writes for every tile the summary of the tiles before it and
+// stores the totals (K_irr, K_vis, and the last two changed
+// irradiance probes) in totals[0..3].
 __global__ __launch_bounds__(kScanThreads) void k_pack_scan(PackBuffers b, int n_tiles) {
-    __shared__ int4 sh[kScanThreads / 64];
+    __shared__ TileSum sh[kScanThreads / 64 + 1];
     const int per = (n_tiles + kScanThreads - 1) / kScanThreads;
     const int lo = min(n_tiles, (int)threadIdx.x * per), hi = min(n_tiles, lo + per);
-    int4 mine = make_int4(0, 0, -1, -1);
+    TileSum mine = tile_sum_none();
+    for (int t = lo; t < hi; ++t) mine = tile_merge(mine, own_tile_sum(b, t));
+    TileSum total;
+    TileSum run = block_exclusive_scan(mine, sh, total);
     for (int t = lo; t < hi; ++t) {
-        const int4 s = b.tiles[t];
-        mine.x += s.x;
-        mine.y += s.y;
-        mine.z = max(mine.z, s.z);
-        mine.w = max(mine.w, s.w);
+        const TileSum v = own_tile_sum(b, t);
+        store_tile_sum(b, t, run);
+        run = tile_merge(run, v);
     }
-    const int4 inc = block_scan_tiles(mine, sh);
-    int4 run = make_int4(inc.x - mine.x, inc.y - mine.y, -1, -1);
-    // exclusive max: the previous thread's inclusive value
-    const int pz = __shfl_up(inc.z, 1), pw = __shfl_up(inc.w, 1);
-    if ((threadIdx.x & 63) != 0) {
-        run.z = pz;
-        run.w = pw;
-    } else if (threadIdx.x > 0) {
-        run.z = sh[(threadIdx.x >> 6) - 1].z;
-        run.w = sh[(threadIdx.x >> 6) - 1].w;
-    }
-    for (int t = lo; t < hi; ++t) {
-        const int4 s = b.tiles[t];
-        b.tiles[t] = run;
-        run.x += s.x;
-        run.y += s.y;
-        run.z = max(run.z, s.z);
-        run.w = max(run.w, s.w);
-    }
-    if (threadIdx.x == kScanThreads - 1) {
-        b.totals[0] = (uint32_t)inc.x;
-        b.totals[1] = (uint32_t)inc.y;
-        reinterpret_cast<uint32_t *>(b.packet)[7] = 0u;
+    if (threadIdx.x == 0) {
+        b.totals[0] = (uint32_t)total.ci;
+        b.totals[1] = (uint32_t)total.cv;
+        b.totals[2] = (uint32_t)total.li;
+        b.totals[3] = (uint32_t)total.si;
     }
 }
 
-// Sums (x, y) and maxima (z, w) of the mask pass's tile summaries over
-// tiles [0, upto) and the totals over all n_tiles, reduced by the whole
-// block (every thread must call it).
+// The summary of tiles [0, upto) and of all n_tiles, reduced by the whole
+// block from the mask pass's tile summaries (every thread must call it).
 template <int T>
-__device__ __forceinline__ void reduce_tiles(const int4 *tiles, int n_tiles, int upto, int4 &before, int2 &total,
-                                             int4 *sh) {
-    int4 pre = make_int4(0, 0, -1, -1);
-    int2 tot = make_int2(0, 0);
+__device__ __forceinline__ void reduce_tiles(const PackBuffers &b, int n_tiles, int upto, TileSum &before,
+                                             TileSum &total, TileSum *sh) {
+    TileSum pre = tile_sum_none(), tot = tile_sum_none();
+#pragma unroll 4
     for (int t = threadIdx.x; t < n_tiles; t += T) {
-        const int4 v = tiles[t];
-        tot.x += v.x;
-        tot.y += v.y;
-        if (t < upto) {
-            pre.x += v.x;
-            pre.y += v.y;
-            pre.z = max(pre.z, v.z);
-            pre.w = max(pre.w, v.w);
-        }
+        const TileSum v = own_tile_sum(b, t);
+        tot = tile_merge(tot, v);
+        if (t < upto) pre = tile_merge(pre, v);
     }
     for (int off = 32; off > 0; off >>= 1) {
-        pre.x += __shfl_xor(pre.x, off);
-        pre.y += __shfl_xor(pre.y, off);
-        pre.z = max(pre.z, __shfl_xor(pre.z, off));
-        pre.w = max(pre.w, __shfl_xor(pre.w, off));
-        tot.x += __shfl_xor(tot.x, off);
-        tot.y += __shfl_xor(tot.y, off);
+        pre = tile_merge(pre, shfl_xor_tile_sum(pre, off));
+        tot = tile_merge(tot, shfl_xor_tile_sum(tot, off));
     }
     const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         sh[2 * wv] = pre;
-        sh[2 * wv + 1] = make_int4(tot.x, tot.y, 0, 0);
+        sh[2 * wv + 1] = tot;
     }
     __syncthreads();
-    before = make_int4(0, 0, -1, -1);
-    total = make_int2(0, 0);
+    before = tile_sum_none();
+    total = tile_sum_none();
     for (int w = 0; w < T / 64; ++w) {
-        const int4 a = sh[2 * w], c = sh[2 * w + 1];
-        before.x += a.x;
-        before.y += a.y;
-        before.z = max(before.z, a.z);
-        before.w = max(before.w, a.w);
-        total.x += c.x;
-        total.y += c.y;
+        before = tile_merge(before, sh[2 * w]);
+        total = tile_merge(total, sh[2 * w + 1]);
     }
     __syncthreads();
 }
 
-// Compaction of one tile: its changed probes' ranks (the tile's prefix plus
-// the changed lanes below), their delta-coded index entries, XOR byte planes
-// and reference update, and the plane words' checksum share (summed by the
-// finish kernel with the index section's). FUSED: the block reduces the
-// tile summaries itself (small tile counts, no scan launch); otherwise the
-// scan left the prefix in the tile's summary and the totals.
+// Compaction of one tile: its changed probes' ranks (the prefix before the
+// tile plus the changed lanes below), their delta-coded index entries, XOR
+// byte planes and reference update. The checksum (the sum of every payload
+// word's hash, an order-free integer sum) is split by word: each block hashes
+// its plane words and the index words whose second entry is its own (the
+// entry before its first comes from the last two changed probes before the
+// tile; the first visibility entry pairs with the last irradiance entry),
+// the block holding the index's last entry also the zero padding, and leaves
+// its share: added to the header's checksum word atomically up to
+// kPackAtomicTiles tiles, else stored for k_pack_checksum. Block 0 writes the
+// rest of the header. FUSED: the block reduces the tile summaries itself
+// (small tile counts, no scan launch); otherwise the scan left the prefix in
+// the tile's summary and the totals.
 template <bool FUSED>
-__global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, int P) {
+__global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, int P, uint32_t client, uint32_t seq) {
     __shared__ PackSmem sm;
     __shared__ int rank_s[kPackQ][2];
     __shared__ int any_s;
-    __shared__ int4 red[2 * kPackThreads / 64];
+    __shared__ TileSum red[2 * kPackThreads / 64];
     const int tile = blockIdx.x, p0 = tile * kPackQ;
     const int n = min(kPackQ, P - p0);
-    int4 before;
-    int K_irr, K_vis;
+    TileSum before, tot;
     if (FUSED) {
-        int2 tot;
-        reduce_tiles<kPackThreads>(b.tiles, (P + kPackQ - 1) / kPackQ, tile, before, tot, red);
-        K_irr = tot.x;
-        K_vis = tot.y;
+        reduce_tiles<kPackThreads>(b, (P + kPackQ - 1) / kPackQ, tile, before, tot, red);
     } else {
-        before = b.tiles[tile];
-        K_irr = (int)b.totals[0];
-        K_vis = (int)b.totals[1];
+        before = load_tile_sum(b, tile);
+        tot = tile_sum_none();
+        tot.ci = (int)b.totals[0];
+        tot.cv = (int)b.totals[1];
+        tot.li = (int)b.totals[2];
+        tot.si = (int)b.totals[3];
     }
-    const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
-    uint16_t *idx_i = reinterpret_cast<uint16_t *>(b.packet + 32);
-    uint16_t *idx_v = idx_i + K_irr;
+    const int K_irr = tot.ci, K_vis = tot.cv, M = K_irr + K_vis;
+    const int idx_bytes = ((2 * M + 15) / 16) * 16;
+    uint16_t *idx = reinterpret_cast<uint16_t *>(b.packet + 32);  // irradiance entries, then visibility
+    uint32_t part = 0;
     if (threadIdx.x < 64) {
         // ranks and index entries of the tile's changed probes: lane q owns
         // probe p0 + q; its rank counts the changed lanes below it, its
@@ -321,24 +384,46 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
         const unsigned long long bi = __ballot(ci), bvv = __ballot(cv);
         const unsigned long long mi = bi & below, mv = bvv & below;
         if (q == 0) any_s = (bi | bvv) != 0ull;
+        const int ki = before.ci + __popcll(mi), kv = before.cv + __popcll(mv);
+        const int prev_i = mi ? p0 + 63 - __clzll((long long)mi) : before.li;
+        const int prev_v = mv ? p0 + 63 - __clzll((long long)mv) : before.lv;
+        const uint32_t ei = (uint16_t)(ki == 0 ? p : p - prev_i), ev = (uint16_t)(kv == 0 ? p : p - prev_v);
+        // the entry before each one: a lane below in the tile, or from the
+        // last two changed probes before the tile (or overall, for the first
+        // visibility entry)
+        const uint32_t ei_lane = __shfl(ei, mi ? 63 - __clzll((long long)mi) : 0);
+        const uint32_t ev_lane = __shfl(ev, mv ? 63 - __clzll((long long)mv) : 0);
         if (q < kPackQ) {
-            rank_s[q][0] = rank_s[q][1] = -1;
-            if (ci) {
-                const int k = before.x + __popcll(mi);
-                const int prev = mi ? p0 + 63 - __clzll((long long)mi) : before.z;
-                idx_i[k] = (uint16_t)(k == 0 ? p : p - prev);
-                rank_s[q][0] = k;
+            rank_s[q][0] = ci ? ki : -1;
+            rank_s[q][1] = cv ? kv : -1;
+        }
+        if (ci) idx[ki] = (uint16_t)ei;
+        if (cv) idx[K_irr + kv] = (uint16_t)ev;
+        for (int tex = 0; tex < 2; ++tex) {
+            if (!(tex == 0 ? ci : cv)) continue;
+            const int c = tex == 0 ? ki : K_irr + kv;
+            const uint32_t e = tex == 0 ? ei : ev;
+            if (c & 1) {
+                uint32_t pe;
+                if (tex == 0)
+                    pe = mi ? ei_lane : (uint16_t)(ki == 1 ? before.li : before.li - before.si);
+                else if (mv)
+                    pe = ev_lane;
+                else if (kv > 0)
+                    pe = (uint16_t)(kv == 1 ? before.lv : before.lv - before.sv);
+                else
+                    pe = (uint16_t)(K_irr == 1 ? tot.li : tot.li - tot.si);
+                part += word_hash(pe | (e << 16), (uint32_t)(c - 1) / 2);
             }
-            if (cv) {
-                const int k = before.y + __popcll(mv);
-                const int prev = mv ? p0 + 63 - __clzll((long long)mv) : before.w;
-                idx_v[k] = (uint16_t)(k == 0 ? p : p - prev);
-                rank_s[q][1] = k;
+            if (c == M - 1) {
+                // the last entry: its word if it opens one, then the zero padding
+                if (!(c & 1)) part += word_hash(e, (uint32_t)c / 2);
+                for (int j = M; j < idx_bytes / 2; ++j) idx[j] = 0;
+                for (int w = (M + 1) / 2; w < idx_bytes / 4; ++w) part += word_hash(0u, (uint32_t)w);
             }
         }
     }
     __syncthreads();
-    uint32_t part = 0;
     if (any_s) {
         stage_tiles(b, p0, P, sm);
         __syncthreads();
@@ -379,40 +464,33 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
     if ((threadIdx.x & 63) == 0) sm.part[threadIdx.x >> 6] = part;
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t s = 0;
-        for (int w = 0; w < kPackThreads / 64; ++w) s += sm.part[w];
-        b.partial[tile] = s;
+        uint32_t sum = 0;
+        for (int w = 0; w < kPackThreads / 64; ++w) sum += sm.part[w];
+        uint32_t *h = reinterpret_cast<uint32_t *>(b.packet);
+        if (pack_atomic_checksum((P + kPackQ - 1) / kPackQ)) {
+            if (sum) atomicAdd(h + kHdrChecksum, sum);
+        } else {
+            b.partial[tile] = sum;
+        }
+        if (tile == 0) {
+            h[kHdrMagic] = kPacketMagic;
+            h[kHdrVersion] = kPacketVersion;
+            h[kHdrClient] = client;
+            h[kHdrSeq] = seq;
+            h[kHdrProbes] = (uint32_t)P;
+            h[kHdrKIrr] = (uint32_t)K_irr;
+            h[kHdrKVis] = (uint32_t)K_vis;
+        }
     }
 }
 
-// One block: pads and hashes the index section, adds the compaction blocks'
-// plane hashes, writes the header (FUSED: the totals from the tile summaries).
-template <bool FUSED>
-__global__ __launch_bounds__(kScanThreads) void k_pack_finish(PackBuffers b, int P, int n_tiles, uint32_t client,
-                                                             uint32_t seq) {
+// One block: the packet checksum, the sum of the compaction blocks' shares,
+// above kPackAtomicTiles tiles (there the same-address atomics of the blocks
+// would serialize for longer than this launch takes).
+__global__ __launch_bounds__(kScanThreads) void k_pack_checksum(PackBuffers b, int n_tiles) {
     __shared__ uint32_t sh[kScanThreads / 64];
-    __shared__ int4 red[2 * kScanThreads / 64];
-    int K_irr, K_vis;
-    if (FUSED) {
-        int4 none;
-        int2 tot;
-        reduce_tiles<kScanThreads>(b.tiles, n_tiles, 0, none, tot, red);
-        K_irr = tot.x;
-        K_vis = tot.y;
-    } else {
-        K_irr = (int)b.totals[0];
-        K_vis = (int)b.totals[1];
-    }
-    const int idx_bytes = ((2 * (K_irr + K_vis) + 15) / 16) * 16;
-    uint8_t *pk = b.packet;
-    if (threadIdx.x < 16) {
-        const int pos = 2 * (K_irr + K_vis) + threadIdx.x;
-        if (pos < idx_bytes) pk[32 + pos] = 0;
-    }
-    __syncthreads();
     uint32_t s = 0;
-    const uint32_t *words = reinterpret_cast<const uint32_t *>(pk + 32);
-    for (int wi = threadIdx.x; wi < idx_bytes / 4; wi += kScanThreads) s += word_hash(words[wi], (uint32_t)wi);
+#pragma unroll 4
     for (int t = threadIdx.x; t < n_tiles; t += kScanThreads) s += b.partial[t];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
@@ -420,15 +498,7 @@ __global__ __launch_bounds__(kScanThreads) void k_pack_finish(PackBuffers b, int
     if (threadIdx.x == 0) {
         uint32_t tot = 0;
         for (int w = 0; w < kScanThreads / 64; ++w) tot += sh[w];
-        uint32_t *h = reinterpret_cast<uint32_t *>(pk);
-        h[kHdrMagic] = kPacketMagic;
-        h[kHdrVersion] = kPacketVersion;
-        h[kHdrClient] = client;
-        h[kHdrSeq] = seq;
-        h[kHdrProbes] = (uint32_t)P;
-        h[kHdrKIrr] = (uint32_t)K_irr;
-        h[kHdrKVis] = (uint32_t)K_vis;
-        h[kHdrChecksum] = tot;
+        reinterpret_cast<uint32_t *>(b.packet)[kHdrChecksum] = tot;
     }
 }
 
@@ -449,20 +519,18 @@ hipError_t launch_pack_scan(const PackBuffers &b, int P, hipStream_t s) {
 
 bool pack_fused(int P) { return (P + kPackQ - 1) / kPackQ <= kPackFusedTiles; }
 
-hipError_t launch_pack_compact(const PackBuffers &b, int P, hipStream_t s) {
+hipError_t launch_pack_compact(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s) {
     if (pack_fused(P))
-        hipLaunchKernelGGL(k_pack_compact<true>, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P);
+        hipLaunchKernelGGL(k_pack_compact<true>, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P,
+                           client, seq);
     else
-        hipLaunchKernelGGL(k_pack_compact<false>, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P);
+        hipLaunchKernelGGL(k_pack_compact<false>, dim3((P + kPackQ - 1) / kPackQ), dim3(kPackThreads), 0, s, b, P,
+                           client, seq);
     return hipGetLastError();
 }
 
-hipError_t launch_pack_finish(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s) {
-    const int n_tiles = (P + kPackQ - 1) / kPackQ;
-    if (pack_fused(P))
-        hipLaunchKernelGGL(k_pack_finish<true>, dim3(1), dim3(kScanThreads), 0, s, b, P, n_tiles, client, seq);
-    else
-        hipLaunchKernelGGL(k_pack_finish<false>, dim3(1), dim3(kScanThreads), 0, s, b, P, n_tiles, client, seq);
+hipError_t launch_pack_checksum(const PackBuffers &b, int P, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_checksum, dim3(1), dim3(kScanThreads), 0, s, b, (P + kPackQ - 1) / kPackQ);
     return hipGetLastError();
 }
 
@@ -482,8 +550,10 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
 // each section 256-byte aligned).
 constexpr int kNoAllocTiles = (kNoAllocMaxProbes + kPackTile - 1) / kPackTile;
 constexpr size_t kScrTiles = 0;
-constexpr size_t kScrPartial = kScrTiles + (size_t)kNoAllocTiles * sizeof(int4);
-constexpr size_t kScrTotals = kScrPartial + ((size_t)kNoAllocTiles * 4 + 255) / 256 * 256;
+constexpr size_t kScrTiles2 = kScrTiles + (size_t)kNoAllocTiles * sizeof(int4);
+constexpr size_t kScrPartial = kScrTiles2 + ((size_t)kNoAllocTiles * sizeof(int2) + 255) / 256 * 256;
+constexpr size_t kScrTsum = kScrPartial + ((size_t)kNoAllocTiles * 4 + 255) / 256 * 256;
+constexpr size_t kScrTotals = kScrTsum + ((size_t)kNoAllocTiles * 4 + 255) / 256 * 256;
 constexpr size_t kScrMaskIrr = kScrTotals + 256;
 constexpr size_t kScrMaskVis = kScrMaskIrr + ((size_t)kNoAllocMaxProbes + 255) / 256 * 256;
 constexpr size_t kScrEnd = kScrMaskVis + ((size_t)kNoAllocMaxProbes + 255) / 256 * 256;
@@ -534,14 +604,16 @@ hipError_t launch_pack_noalloc(unsigned char *scr, const uint16_t *cur_irr, cons
     b.mask_vis = scr + kScrMaskVis;
     b.tiles = reinterpret_cast<int4 *>(scr + kScrTiles);
     b.totals = reinterpret_cast<uint32_t *>(scr + kScrTotals);
+    b.tiles2 = reinterpret_cast<int2 *>(scr + kScrTiles2);
     b.partial = reinterpret_cast<uint32_t *>(scr + kScrPartial);
+    b.tsum = reinterpret_cast<uint32_t *>(scr + kScrTsum);
     b.packet = packet;
     b.active = nullptr;
     b.view = nullptr;
     hipError_t e = launch_pack_mask(b, P, tau_irr, tau_vis, s);
     if (e == hipSuccess && !pack_fused(P)) e = launch_pack_scan(b, P, s);
-    if (e == hipSuccess) e = launch_pack_compact(b, P, s);
-    if (e == hipSuccess) e = launch_pack_finish(b, P, client, seq, s);
+    if (e == hipSuccess) e = launch_pack_compact(b, P, client, seq, s);
+    if (e == hipSuccess && !pack_atomic_checksum((P + kPackTile - 1) / kPackTile)) e = launch_pack_checksum(b, P, s);
     return e;
 }
 

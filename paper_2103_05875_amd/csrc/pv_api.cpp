@@ -134,7 +134,9 @@ struct pv_client {
     uint8_t *mask_irr = nullptr, *mask_vis = nullptr;
     int4 *tiles = nullptr;         // per-tile summaries of the last mask pass
     uint32_t *totals = nullptr;    // changed-probe totals of the last scan
+    int2 *tiles2 = nullptr;        // per-tile second-last changed probes
     uint32_t *partial = nullptr;   // per-tile checksum shares
+    uint32_t *tsum = nullptr;      // per-tile own summaries
     uint8_t *packet = nullptr;
     uint64_t packet_cap = 0;
     uint32_t *hdr_host = nullptr;  // pinned, 32 bytes
@@ -1140,7 +1142,9 @@ static void free_client(pv_client *c) {
     hipFree(c->mask_vis);
     hipFree(c->tiles);
     hipFree(c->totals);
+    hipFree(c->tiles2);
     hipFree(c->partial);
+    hipFree(c->tsum);
     hipFree(c->packet);
     hipFree(c->view);
     hipFree(c->ent.hist);
@@ -1173,7 +1177,9 @@ extern "C" pv_status pv_client_create(pv_volume *v, uint32_t id, pv_client **out
     if (st == PV_OK) st = dev_alloc(&c->mask_vis, (size_t)P, "mask");
     if (st == PV_OK) st = dev_alloc(&c->tiles, (size_t)(P + kPackTile - 1) / kPackTile * sizeof(int4), "tile summaries");
     if (st == PV_OK) st = dev_alloc(&c->totals, 4 * sizeof(uint32_t), "pack totals");
+    if (st == PV_OK) st = dev_alloc(&c->tiles2, (size_t)(P + kPackTile - 1) / kPackTile * sizeof(int2), "tile summaries");
     if (st == PV_OK) st = dev_alloc(&c->partial, (size_t)(P + kPackTile - 1) / kPackTile * 4, "pack checksum shares");
+    if (st == PV_OK) st = dev_alloc(&c->tsum, (size_t)(P + kPackTile - 1) / kPackTile * 4, "tile summaries");
     if (st == PV_OK) st = dev_alloc(&c->packet, c->packet_cap, "packet");
     if (st == PV_OK) st = dev_alloc(&c->view, (size_t)P, "client view");
     if (st == PV_OK && hipHostMalloc((void **)&c->hdr_host, 32) != hipSuccess) st = fail(PV_ERR_OOM, "pinned header");
@@ -1226,7 +1232,9 @@ extern "C" pv_status pv_pack_delta(pv_client *c, float tau_irr, float tau_vis, v
     b.mask_vis = c->mask_vis;
     b.tiles = c->tiles;
     b.totals = c->totals;
+    b.tiles2 = c->tiles2;
     b.partial = c->partial;
+    b.tsum = c->tsum;
     b.packet = c->packet;
     b.active = v->active;
     b.view = c->view_on ? c->view : nullptr;
@@ -1235,8 +1243,9 @@ extern "C" pv_status pv_pack_delta(pv_client *c, float tau_irr, float tau_vis, v
     const uint32_t id = c->id, seq = c->seq;
     HIP_TRY(timed(cx, PV_STAGE_PACK_MASK, s, [&] { return launch_pack_mask(b, P, tau_irr, tau_vis, s); }));
     if (!pack_fused(P)) HIP_TRY(timed(cx, PV_STAGE_PACK_SCAN, s, [&] { return launch_pack_scan(b, P, s); }));
-    HIP_TRY(timed(cx, PV_STAGE_PACK_COMPACT, s, [&] { return launch_pack_compact(b, P, s); }));
-    HIP_TRY(timed(cx, PV_STAGE_PACK_FINISH, s, [&] { return launch_pack_finish(b, P, id, seq, s); }));
+    HIP_TRY(timed(cx, PV_STAGE_PACK_COMPACT, s, [&] { return launch_pack_compact(b, P, id, seq, s); }));
+    if (!pack_atomic_checksum((P + kPackTile - 1) / kPackTile))
+        HIP_TRY(timed(cx, PV_STAGE_PACK_FINISH, s, [&] { return launch_pack_checksum(b, P, s); }));
     c->seq++;
     return PV_OK;
 }

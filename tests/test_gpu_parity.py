@@ -450,6 +450,62 @@ def test_pack_bit_exact(ps, ctx, O, P, taus):
     vol.close()
 
 
+def _straddling_pairs(tau, rng, n):
+    """n pairs of binary16 values (bit patterns) whose difference lies within
+    a few binary16 steps of tau on either side, led by a pair whose binary32
+    difference rounds onto tau although the exact one exceeds it (3 against
+    3 * 2^-24 when tau = 3 - 2^-22)."""
+    pairs = [(np.float16(3.0), np.float16(3 * 2.0 ** -24))]
+    while len(pairs) < n:
+        a = np.float16(rng.uniform(tau, tau + 8.0))
+        b = np.float16(float(a) - tau)
+        for k in range(-2, 3):
+            bb = np.uint16(int(b.view(np.uint16)) + k).view(np.float16)
+            if np.isfinite(bb):
+                pairs.append((a, bb) if rng.uniform() < 0.5 else (bb, a))
+    return [(x.view(np.uint16), y.view(np.uint16)) for x, y in pairs[:n]]
+
+
+@pytest.mark.parametrize("tau", [3.0 - 2.0 ** -22, 1.0 / 1024, 0.75, 1.0, 1.5])
+def test_pack_threshold_boundaries(ps, ctx, O, tau):
+    """The change test |cur - ref| > tau is exact (Sec. 3.4's threshold, strict):
+    one texel per probe steps across a difference within a few binary16 steps
+    of tau; the masks and the packet equal the oracle's, which compares in
+    binary64. A binary32 difference would miss the leading pair."""
+    tau = float(np.float32(tau))
+    P = 512
+    _say(f"pack threshold boundaries tau={tau!r}")
+    cfg = synth.VolumeConfig(8, 8, 8, (0, 0, 0), (1, 1, 1), 1, fp16=True)
+    vol = ps.Volume(ctx, cfg)
+    cl = ps.Client(vol, client_id=9)
+    st = O.OracleClientState(P, client=9)
+    rng = np.random.default_rng(int(tau * 1e6) % 1000)
+    pairs = _straddling_pairs(tau, rng, 2 * P)
+    a_i = np.zeros((P, 3, 10, 10), np.uint16)
+    a_v = np.zeros((P, 2, 18, 18), np.uint16)
+    b_i, b_v = a_i.copy(), a_v.copy()
+    for p in range(P):
+        (x0, y0), (x1, y1) = pairs[p], pairs[P + p]
+        c, r, q = p % 3, 1 + p % 8, 1 + (p // 8) % 8
+        a_i[p, c, r, q], b_i[p, c, r, q] = x0, y0
+        a_v[p, p % 2, 1 + p % 16, 1 + (p // 16) % 16], b_v[p, p % 2, 1 + p % 16, 1 + (p // 16) % 16] = x1, y1
+    for f, (mi_, mv_) in enumerate(((a_i, a_v), (b_i, b_v))):
+        vol.set_maps(mi_, mv_, f)
+        t = 0.0 if f == 0 else tau
+        cl.pack_delta(t, t)
+        got = cl.packet_download()
+        want, mi, mv = st.pack(mi_, mv_, t, t)
+        gmi, gmv = cl.read_masks()
+        assert np.array_equal(gmi, mi) and np.array_equal(gmv, mv), f"frame {f}: masks differ"
+        assert got == want
+    # both outcomes occur, and the leading pair counts as changed
+    assert 0 < mi.sum() < P and 0 < mv.sum() < P
+    if tau == float(np.float32(3.0 - 2.0 ** -22)):
+        assert mi[0] == 1
+    cl.close()
+    vol.close()
+
+
 def test_pack_maximum_probe_count(ps, ctx, O):
     P = 65536
     _say("pack P=65536")
