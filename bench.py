@@ -49,12 +49,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=16.0,
+                    help="oracle baseline budget: half on one thread, half on every core")
     ap.add_argument("--legs", default="batched,served,served_below_capacity,served_tight_memory,served_sweep,encode,"
                                       "multi_bounce,codec,blend_paths,"
                                       "selection",
                     help="extra workloads reported in the same line (comma list, or 'none')")
-    ap.add_argument("--served-seconds", type=float, default=1.0)
+    ap.add_argument("--served-seconds", type=float, default=10.0,
+                    help="arrival window of the served leg (2000 requests/s)")
     ap.add_argument("--served-low-rate", type=float, default=300.0,
                     help="arrival rate of the second served run, below the measured capacity")
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (tuned once, then reused)")
@@ -215,35 +217,43 @@ def _cpu_model() -> str:
 
 def cpu_baseline(cfg, scene, path, budget_s: float):
     """The oracle as it stands on the host cores: full frames of the same
-    workload (trace + shade, blend, pack), as many as fit the budget
-    (at least one)."""
+    workload (trace + shade, blend, pack), as many as fit half the budget
+    (at least one), on one thread and then on every core."""
 
     import oracle
     import synth
     osc = oracle.OracleScene.from_scene(scene)
-    irr, vis = oracle.empty_maps(cfg)
-    st = oracle.OracleClientState(cfg.n_probes)
-    frames = 0
-    t0 = time.perf_counter()
-    while True:
-        R = synth.rotation(13, frames)
-        lights = scene.lights.copy()
-        lights[0, :3] = path[frames % len(path)]
-        rays = oracle.trace_shade(osc, cfg, R, lights, bounds=False)
-        oracle.blend_update(cfg, oracle.ray_dirs(cfg.rays_per_probe, R), rays["L"], rays["r"], irr, vis,
-                            first=(frames == 0))
-        bi = irr.astype(np.float16).view(np.uint16)
-        bv = vis.astype(np.float16).view(np.uint16)
-        st.pack(bi, bv)
-        frames += 1
-        if time.perf_counter() - t0 > budget_s or frames >= 200:
-            break
-    dt = time.perf_counter() - t0
-    rays_total = frames * cfg.n_probes * cfg.rays_per_probe
-    return {"value": rays_total / dt, "unit": "probe-rays/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "cpu_model": _cpu_model(), "probes_per_s": frames * cfg.n_probes / dt,
-            "sample": f"{frames} full frame(s) of the same workload (trace + shade, blend, pack), "
-                      f"{dt:.1f} s wall, OpenMP over probes"}
+
+    def run(threads: int, budget: float):
+        irr, vis = oracle.empty_maps(cfg)
+        st = oracle.OracleClientState(cfg.n_probes)
+        frames = 0
+        t0 = time.perf_counter()
+        while True:
+            R = synth.rotation(13, frames)
+            lights = scene.lights.copy()
+            lights[0, :3] = path[frames % len(path)]
+            rays = oracle.trace_shade(osc, cfg, R, lights, bounds=False, nthreads=threads)
+            oracle.blend_update(cfg, oracle.ray_dirs(cfg.rays_per_probe, R), rays["L"], rays["r"], irr, vis,
+                                first=(frames == 0), nthreads=threads)
+            bi = irr.astype(np.float16).view(np.uint16)
+            bv = vis.astype(np.float16).view(np.uint16)
+            st.pack(bi, bv)
+            frames += 1
+            if time.perf_counter() - t0 > budget or frames >= 200:
+                break
+        dt = time.perf_counter() - t0
+        return frames, dt, frames * cfg.n_probes * cfg.rays_per_probe / dt, frames * cfg.n_probes / dt
+
+    cores = oracle.max_threads()
+    f1, dt1, rays1, probes1 = run(1, budget_s / 2)
+    fn, dtn, raysn, probesn = run(cores, budget_s / 2)
+    return {"value": raysn, "unit": "probe-rays/s", "cores": cores, "kind": "oracle",
+            "cpu_model": _cpu_model(), "probes_per_s": probesn,
+            "sample": f"{fn} full frame(s) of the same workload (trace + shade, blend, pack), "
+                      f"{dtn:.1f} s wall, OpenMP over probes on {cores} threads",
+            "single_thread": {"value": rays1, "unit": "probe-rays/s", "cores": 1, "probes_per_s": probes1,
+                              "sample": f"{f1} full frame(s), {dt1:.1f} s wall, one thread"}}
 
 
 def leg_batched(ps, torch, reps: int):

@@ -28,7 +28,11 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# PV_ORACLE_SANITIZE=1 builds and loads a copy with AddressSanitizer and
+# UndefinedBehaviorSanitizer (for a test run with the ASan runtime preloaded)
+_SANITIZE = os.environ.get("PV_ORACLE_SANITIZE") == "1"
+_SO = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
+_SAN_FLAGS = ["-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"]
 # oracle.c: the method in FP64; bvh4_replay.c: the GPU trace's traversal work
 # replayed on the host from the library's exported BVH (counts only)
 _SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "bvh4_replay.c")]
@@ -40,7 +44,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-Wall", "-o", tmp, *_SRC, "-lm"])
+                               "-Wall", *(_SAN_FLAGS if _SANITIZE else []), "-o", tmp, *_SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
