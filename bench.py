@@ -259,10 +259,18 @@ def cpu_baseline(cfg, scene, path, budget_s: float):
 def leg_batched(ps, torch, reps: int):
     """Batched workload: 32 volumes (probes log-uniform 256-8192, rays from
     {64,128,256,512}, each over its own 5k-100k-triangle box scene), one
-    batched update per frame (three launches for all volumes), eager and as a
-    captured graph, against the same volumes updated one by one on the plain
-    path."""
+    batched update per frame (three launches for all volumes: directions,
+    trace, blend), eager and as a captured graph, against the same volumes
+    updated one by one on the plain path. Trace launch shapes are tuned: each
+    plain volume on its own over every shape, the batched volumes per size
+    bucket on the batched launch itself over the shapes the batched trace
+    takes (probe brick and staged top nodes; stepped lanes in 256-thread
+    blocks). Also timed: both
+    paths at the default shape (4x4x4 bricks, 21 staged nodes), and the idle
+    time between the three launches of a batched frame (what one persistent
+    launch could remove at most)."""
     import synth
+    from paper_2103_05875_amd import autotune
     specs = synth.batched_volumes(32, seed=20)
     ctx = ps.Context(0)
     scenes, plain, batched = [], [], []
@@ -287,14 +295,7 @@ def leg_batched(ps, torch, reps: int):
         else:
             ps.update_probes_batched(batched, rots, stream=stream)
 
-    graph = ps.BatchGraph(batched)
-
-    def run_graph(f):
-        graph.launch([synth.rotation(20 + i, f) for i in range(len(specs))], stream=stream)
-
-    out = {}
-    for which in ("plain", "batched", "graph"):
-        step = run_graph if which == "graph" else (lambda f, w=which: run(f, w))
+    def time_it(step):
         for f in range(2):
             step(f)
         torch.cuda.synchronize()
@@ -305,13 +306,61 @@ def leg_batched(ps, torch, reps: int):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        out[which] = {"ms_per_frame": ms, "probe_rays_per_s": rays / (ms / 1e3), "probes_per_s": probes / (ms / 1e3)}
-        if which == "batched":   # same frames on both sets so far
-            same = all(np.array_equal(a.read_maps()[0], b.read_maps()[0]) for a, b in zip(plain, batched))
+        return {"ms_per_frame": ms, "probe_rays_per_s": rays / (ms / 1e3), "probes_per_s": probes / (ms / 1e3)}
+
+    out = {}
+    # the default shape on both paths (the batched form before per-volume shapes)
+    out["plain_default_shape"] = time_it(lambda f: run(f, "plain"))
+    out["batched_default_shape"] = time_it(lambda f: run(f, "batched"))
+    # per-volume tuned shapes
+    t0 = time.perf_counter()
+    shapes = []
+    for s, a in zip(specs, plain):
+        ta = autotune.tune(a, synth.rotation(99, 0), n_triangles=s["n_tris"], reps=2, cache=None, shipped=False)
+        shapes.append({"probes": s["config"].n_probes, "rays": s["config"].rays_per_probe, "triangles": s["n_tris"],
+                       "plain": {**ta["config"], "brick": list(ta["config"]["brick"])}})
+    tb = autotune.tune_batched(batched, [synth.rotation(98 + i, 0) for i in range(len(specs))])
+    for sh, b in zip(shapes, batched):
+        c = b.get_trace_config()
+        sh["batched"] = {"brick": list(c["brick"]), "top_nodes": c["top_nodes"]}
+    batched_tuning = {"bucket": "log2 of the probe count", "timed_launches": tb["tried"],
+                      "trace_ms_default_shape": tb["default_ms"], "trace_ms_tuned": tb["ms"],
+                      "choices": {str(k): {"brick": list(c["brick"]), "top_nodes": c["top_nodes"]}
+                                  for k, c in sorted(tb["choices"].items())}}
+    tune_s = time.perf_counter() - t0
+    # the trial runs advanced the two sets by different frame counts: start
+    # both from the plain volume's maps
+    for a, b in zip(plain, batched):
+        irr, vis, fr = a.read_maps()
+        b.set_maps(irr, vis, fr)
+    for which in ("plain", "batched"):
+        out[which] = time_it(lambda f, w=which: run(f, w))
+    # same frames on both sets since the tuning
+    same = all(np.array_equal(a.read_maps()[0], b.read_maps()[0]) and np.array_equal(a.read_maps()[1], b.read_maps()[1])
+               for a, b in zip(plain, batched))
+    graph = ps.BatchGraph(batched)
+    out["graph"] = time_it(lambda f: graph.launch([synth.rotation(20 + i, f) for i in range(len(specs))],
+                                                  stream=stream))
     graph.close()
+    # the batched frame's three launches by events: their sum against the
+    # frame (the gaps are what a single persistent launch could remove)
+    ctx.set_timing(True)
+    ctx.stage_times()
+    for f in range(reps):
+        run(100 + f, "batched")
+    torch.cuda.synchronize()
+    st = ctx.stage_times()
+    ctx.set_timing(False)
+    kern = sum(st[k][0] for k in ("raydirs", "batched", "blend")) / reps
     out.update({"volumes": len(specs), "probes": probes, "probe_rays": rays, "bit_identical_to_plain": bool(same),
+                "shapes": shapes, "tuning_s": tune_s, "batched_tuning": batched_tuning,
                 "speedup": out["plain"]["ms_per_frame"] / out["batched"]["ms_per_frame"],
-                "graph_speedup": out["plain"]["ms_per_frame"] / out["graph"]["ms_per_frame"]})
+                "graph_speedup": out["plain"]["ms_per_frame"] / out["graph"]["ms_per_frame"],
+                "tuned_over_default_batched": out["batched_default_shape"]["ms_per_frame"]
+                / out["batched"]["ms_per_frame"],
+                "launches_ms": {"directions": st["raydirs"][0] / reps, "trace": st["batched"][0] / reps,
+                                "blend": st["blend"][0] / reps},
+                "gaps_ms": max(0.0, out["batched"]["ms_per_frame"] - kern)})
     for h in plain + batched + scenes:
         h.close()
     ctx.close()

@@ -4,7 +4,8 @@
 // to one volume and finds it by binary search over the per-volume prefix
 // counts, so volumes of different sizes, ray counts, scenes and map formats
 // share the device without a launch per volume. The trace runs the stepped
-// lane loop (separate node and triangle steps) on 4x4x4 probe packets. Results are bit-identical
+// lane loop (separate node and triangle steps) on each volume's own probe
+// brick and top-node staging (its trace configuration). Results are bit-identical
 // to the per-volume launches: each ray and each probe group runs the same
 // device code on the same inputs.
 #include "blend_gemm.h"
@@ -13,7 +14,6 @@
 namespace pv {
 
 constexpr int kBatchBlock = 256;            // trace: four packets per block
-constexpr int kBatchTop = 21;               // top BVH nodes staged per block
 constexpr int kBatchWaves = kBatchBlock / 64;
 
 // Last volume whose first item is at or before 'item' (prefix counts are
@@ -40,15 +40,17 @@ __global__ __launch_bounds__(kBatchBlock) void k_trace_batched(const BatchVolume
     const int v = __builtin_amdgcn_readfirstlane(find_volume<false>(vols, n_vols, wave0));
     const BatchVolume &bv = vols[v];
     NodeSrc src = global_nodes(bv.sv.stat);
-    const int nt = min(kBatchTop, bv.sv.stat.n_nodes);
+    const int nt = min(bv.top_nodes, bv.sv.stat.n_nodes);
     const uint4 *gn = reinterpret_cast<const uint4 *>(bv.sv.stat.nodes);
     for (int i = threadIdx.x; i < nt * 4; i += kBatchBlock) pv_top_nodes[i] = gn[i];
     __syncthreads();
     src.top = nt;
-    // the packet of this wave in the volume's packet order (4x4x4 bricks),
-    // traced with the stepped lane loop
+    // the packet of this wave in the volume's packet order (its own probe
+    // brick), traced with the stepped lane loop
     TraceGrid g;
-    g.bx = g.by = g.bz = 4;
+    g.bx = bv.bx;
+    g.by = bv.by;
+    g.bz = bv.bz;
     g.nbx = bv.bricks_x;
     g.nby = bv.bricks_y;
     g.nbz = bv.bricks_z;
@@ -104,10 +106,10 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend_batched(const BatchVolu
 }
 
 hipError_t launch_trace_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, const FrameParams *frames_dev,
-                                bool short_stack, hipStream_t s) {
+                                bool short_stack, int max_top, hipStream_t s) {
     static_assert(kBatchWaves * 64 == kBatchBlock, "packets per trace block");
     const dim3 grid((total_waves + kBatchWaves - 1) / kBatchWaves);
-    const size_t smem = (size_t)kBatchTop * sizeof(GpuNode4);
+    const size_t smem = (size_t)max_top * sizeof(GpuNode4);
     if (short_stack)
         hipLaunchKernelGGL(k_trace_batched<uint16_t>, grid, dim3(kBatchBlock), smem, s, vols_dev, n_vols, frames_dev);
     else

@@ -62,6 +62,8 @@ struct BatchVolume {
     int first_classify; // prefix over volumes of classification blocks (0 blocks without it)
     int n_classify;
     int bricks_x, bricks_y, bricks_z;
+    int bx, by, bz;   // the volume's probe brick (64 probes per trace packet)
+    int top_nodes;    // top BVH nodes the volume's trace blocks stage in LDS (0, 21 or 85)
 };
 
 // ---------------------------------------------------------------------------
@@ -78,7 +80,7 @@ hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4
 // Batched trace / blend over every volume of a batch (descriptors on the
 // device; each volume's first_wave a multiple of 4).
 hipError_t launch_trace_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, const FrameParams *frames_dev,
-                                bool short_stack, hipStream_t s);
+                                bool short_stack, int max_top, hipStream_t s);
 hipError_t launch_blend_batched(const BatchVolume *vols_dev, int n_vols, int total_blend, hipStream_t s);
 hipError_t launch_raydirs_batched(const BatchVolume *vols_dev, const FrameParams *frames_dev, int n_vols,
                                   int dir_blocks, hipStream_t s);

@@ -907,6 +907,7 @@ struct pv_batch_graph {
     size_t o_b = 0, o_f = 0, bytes = 0;
     int waves = 0, blend = 0, bounce = 0, classify = 0, dir_blocks = 0;
     bool short_stack = true;
+    int max_top = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -915,10 +916,11 @@ struct pv_batch_graph {
 
 // Fills the pinned staging of a batch: descriptors and frames; returns the
 // packet, blend-group and second-bounce block totals, the most ray-direction
-// blocks of a volume, and whether every BVH of the batch fits 16-bit stack
-// entries.
+// blocks of a volume, whether every BVH of the batch fits 16-bit stack
+// entries, and the most top nodes a volume stages.
 static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int n, char *h, size_t *offs, int &waves,
-                            int &blend, int &bounce, int &classify, int &dir_blocks, bool &short_stack) {
+                            int &blend, int &bounce, int &classify, int &dir_blocks, bool &short_stack,
+                            int &max_top) {
     std::vector<BatchVolume> bv(n);
     std::vector<FrameParams> fps(n);
     std::memset(fps.data(), 0, sizeof(FrameParams) * n);
@@ -928,6 +930,7 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
     classify = 0;
     dir_blocks = 0;
     short_stack = true;
+    max_top = 0;
     for (int i = 0; i < n; ++i) {
         pv_volume *v = vols[i];
         if (frames) PV_TRY(frame_params(&frames[i], v->scene, fps[i]));
@@ -943,9 +946,16 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
         b.vis = v->vis;
         b.h = effective_h(v);
         b.fp16 = v->desc.format == PV_MAP_FP16;
-        b.bricks_x = (v->desc.nx + 3) / 4;
-        b.bricks_y = (v->desc.ny + 3) / 4;
-        b.bricks_z = (v->desc.nz + 3) / 4;
+        // the volume's own trace shape: probe brick and staged top nodes (the
+        // batched trace always runs the stepped lanes in 256-thread blocks)
+        b.bx = v->tc.bx;
+        b.by = v->tc.by;
+        b.bz = v->tc.bz;
+        b.top_nodes = v->tc.top_nodes;
+        max_top = std::max(max_top, b.top_nodes);
+        b.bricks_x = (v->desc.nx + b.bx - 1) / b.bx;
+        b.bricks_y = (v->desc.ny + b.by - 1) / b.by;
+        b.bricks_z = (v->desc.nz + b.bz - 1) / b.bz;
         b.n_waves = b.bricks_x * b.bricks_y * b.bricks_z * v->n;
         waves = (waves + 3) / 4 * 4;  // trace blocks hold 4 packets; each volume starts on a block boundary
         b.first_wave = waves;
@@ -1000,16 +1010,16 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
     HIP_TRY(hipEventSynchronize(slot.done));  // the slot's previous launch has finished
     PV_TRY(ensure_slot(c, slot, n));
     size_t offs[3];
-    int waves, blend, bounce, classify, dir_blocks;
+    int waves, blend, bounce, classify, dir_blocks, max_top;
     bool short_stack;
     char *h = (char *)slot.stage_host;
-    PV_TRY(fill_batch(vols, frames, n, h, offs, waves, blend, bounce, classify, dir_blocks, short_stack));
+    PV_TRY(fill_batch(vols, frames, n, h, offs, waves, blend, bounce, classify, dir_blocks, short_stack, max_top));
     HIP_TRY(hipMemcpyAsync(slot.batch_dev, h + offs[0], sizeof(BatchVolume) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(slot.frames_dev, h + offs[1], sizeof(FrameParams) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(timed(c, PV_STAGE_RAYDIRS, s,
                   [&] { return launch_raydirs_batched(slot.batch_dev, slot.frames_dev, n, dir_blocks, s); }));
     HIP_TRY(timed(c, PV_STAGE_BATCHED, s,
-                  [&] { return launch_trace_batched(slot.batch_dev, n, waves, slot.frames_dev, short_stack, s); }));
+                  [&] { return launch_trace_batched(slot.batch_dev, n, waves, slot.frames_dev, short_stack, max_top, s); }));
     if (classify > 0)
         HIP_TRY(timed(c, PV_STAGE_SELECT, s, [&] { return launch_classify_batched(slot.batch_dev, n, classify, s); }));
     if (bounce > 0)
@@ -1048,7 +1058,7 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
     size_t offs[3];
     if (st == PV_OK)
         st = fill_batch(vols, nullptr, n, (char *)g->slot.stage_host, offs, g->waves, g->blend, g->bounce,
-                        g->classify, g->dir_blocks, g->short_stack);
+                        g->classify, g->dir_blocks, g->short_stack, g->max_top);
     if (st != PV_OK) {
         free_graph(g);
         return st;
@@ -1065,7 +1075,7 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
     if (e == hipSuccess) e = hipMemcpyAsync(b.batch_dev, h + g->o_b, sizeof(BatchVolume) * n, hipMemcpyHostToDevice, cs);
     if (e == hipSuccess) e = hipMemcpyAsync(b.frames_dev, h + g->o_f, sizeof(FrameParams) * n, hipMemcpyHostToDevice, cs);
     if (e == hipSuccess) e = launch_raydirs_batched(b.batch_dev, b.frames_dev, n, g->dir_blocks, cs);
-    if (e == hipSuccess) e = launch_trace_batched(b.batch_dev, n, g->waves, b.frames_dev, g->short_stack, cs);
+    if (e == hipSuccess) e = launch_trace_batched(b.batch_dev, n, g->waves, b.frames_dev, g->short_stack, g->max_top, cs);
     if (e == hipSuccess && g->classify > 0) e = launch_classify_batched(b.batch_dev, n, g->classify, cs);
     if (e == hipSuccess && g->bounce > 0) e = launch_bounce_batched(b.batch_dev, n, g->bounce, cs);
     if (e == hipSuccess) e = launch_blend_batched(b.batch_dev, n, g->blend, cs);
@@ -1098,13 +1108,13 @@ extern "C" pv_status pv_batch_graph_launch(pv_batch_graph *g, const pv_frame *fr
     // launch must have finished before it is rewritten
     if (g->launched) HIP_TRY(hipEventSynchronize(g->done));
     size_t offs[3];
-    int waves, blend, bounce, classify, dir_blocks;
+    int waves, blend, bounce, classify, dir_blocks, max_top;
     bool short_stack;
     PV_TRY(fill_batch(g->vols.data(), frames, n, (char *)g->slot.stage_host, offs, waves, blend, bounce, classify,
-                      dir_blocks, short_stack));
+                      dir_blocks, short_stack, max_top));
     if (waves != g->waves || blend != g->blend || bounce != g->bounce || classify != g->classify ||
-        short_stack != g->short_stack)
-        return fail(PV_ERR_STATE, "a volume of the graph changed scene since the graph was captured");
+        short_stack != g->short_stack || max_top != g->max_top)
+        return fail(PV_ERR_STATE, "a volume of the graph changed scene or trace shape since the graph was captured");
     hipStream_t s = pick(c, stream);
     HIP_TRY(timed(c, PV_STAGE_BATCHED, s, [&] { return hipGraphLaunch(g->exec, s); }));
     HIP_TRY(hipEventRecord(g->done, s));

@@ -557,9 +557,15 @@ def test_update_then_pack_round_trip(ps, ctx, O):
 
 # ------------------------------------------------------------------ batched = plain
 def test_batched_matches_plain_bitwise(ps, ctx, O):
+    """Six uneven volumes, three frames: the batched update equals the
+    per-volume updates bit for bit; the batched volumes take different trace
+    shapes (probe bricks, staged top nodes) of their own, the plain ones
+    other schedules."""
     _say("batched vs plain, 6 uneven volumes, 3 frames")
     specs = [((4, 4, 4), 64, True, 2000), ((5, 3, 7), 128, True, 800), ((16, 2, 16), 256, True, 5000),
              ((1, 1, 1), 512, False, 300), ((8, 8, 4), 64, False, 1200), ((3, 3, 3), 1, True, 100)]
+    shapes_b = [((8, 8, 1), 85), ((2, 4, 8), 0), ((16, 4, 1), 21), ((4, 4, 4), 85), ((8, 4, 2), 0), ((4, 4, 4), 21)]
+    shapes_p = [((4, 4, 4), 1), ((8, 4, 2), 0), ((2, 4, 8), 2), ((8, 8, 1), 1), ((16, 4, 1), 0), ((4, 4, 4), 2)]
     plain, batched, scenes = [], [], []
     for i, (g, n, fp16, nt) in enumerate(specs):
         sc_syn = synth.box_city(n_tris=nt, seed_layout=70 + i, seed_heights=80 + i, extent=16.0)
@@ -570,6 +576,8 @@ def test_batched_matches_plain_bitwise(ps, ctx, O):
         a, b = ps.Volume(ctx, cfg), ps.Volume(ctx, cfg)
         a.set_scene(sc)
         b.set_scene(sc)
+        a.set_trace_config(shapes_p[i][0], shapes_p[i][1], 21, 256, False)
+        b.set_trace_config(shapes_b[i][0], 2, shapes_b[i][1], 256, False)
         plain.append(a)
         batched.append(b)
     for f in range(3):
