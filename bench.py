@@ -43,6 +43,10 @@ PEAK_HBM = 8.0e12                  # MI355X published HBM3E bandwidth (B/s)
 PEAK_BF16_MFMA = 2.5e15            # MI355X published dense BF16 matrix peak (FLOP/s)
 
 
+DEFAULT_LEGS = ("batched,served,served_below_capacity,served_tight_memory,served_sweep,encode,multi_bounce,codec,"
+                "blend_paths,selection")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,9 +55,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=16.0,
                     help="oracle baseline budget: half on one thread, half on every core")
-    ap.add_argument("--legs", default="batched,served,served_below_capacity,served_tight_memory,served_sweep,encode,"
-                                      "multi_bounce,codec,blend_paths,"
-                                      "selection",
+    ap.add_argument("--legs", default=DEFAULT_LEGS,
                     help="extra workloads reported in the same line (comma list, or 'none')")
     ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="arrival window of the served leg (2000 requests/s)")
@@ -69,6 +71,9 @@ def parse():
     ap.add_argument("--summarize-counters", nargs="+", metavar="CSV", default=None,
                     help="no GPU work: print the mean per dispatch of every counter in rocprofv3 --pmc "
                          "counter_collection.csv files, per kernel")
+    ap.add_argument("--write-kernel-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT"), default=None,
+                    help="per-kernel HBM bytes of an encode-leg run, scaled by its 1 GiB cache-flush copy")
+    ap.add_argument("--sq-csv", default=None, help="with --write-counters: the SQ counter run's CSV")
     ap.add_argument("--write-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT"), default=None,
                     help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, "
                          "WRITE_SIZE) of this bench run with --calibrate-copy into the counters file")
@@ -124,21 +129,52 @@ def read_counters(path, trace_config):
     return float(kv["traffic_bytes_per_launch"]), path
 
 
-# the trace kernel of each schedule (0 packet, 1 refill, 2 stepped lanes)
-TRACE_KERNEL_NAME = {0: "k_trace", 1: "k_trace_refill<REFILL=true>", 2: "k_trace_refill<REFILL=false>"}
+def read_lane_utilisation(path, trace_config):
+    """VALU lane utilisation of the trace kernel from the same counters file
+    (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)), or None."""
+    try:
+        kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if (kv.get("source_sha256") != kernel_source_hash() or kv.get("trace_config") != config_string(trace_config)
+            or "valu_lane_utilisation" not in kv):
+        return None
+    return float(kv["valu_lane_utilisation"])
 
 
-def is_trace_kernel(name: str) -> bool:
+def trace_kernel_instance(c) -> str:
+    """The template instance a launch shape runs (16-bit stack entries)."""
+    w, t = c["block_threads"], c["top_nodes"]
+    if c["persistent"] == 0:
+        return f"k_trace<false, {w}, {t}, false, unsigned short>"
+    return f"k_trace_refill<false, {w}, {t}, unsigned short, {'true' if c['persistent'] == 1 else 'false'}>"
+
+
+
+
+def is_trace_kernel(name: str, trace_config=None) -> bool:
     """The uninstrumented trace kernel of any schedule (not the counting
-    variant, not the split-shadow passes)."""
+    variant, not the split-shadow passes); with a launch shape, only the
+    template instance that shape runs (block size, staged nodes, schedule)."""
     k = name.replace("void ", "", 1)
-    return k.startswith("pv::k_trace<false") or k.startswith("pv::k_trace_refill<false")
+    if trace_config is None:
+        return k.startswith("pv::k_trace<false") or k.startswith("pv::k_trace_refill<false")
+    c = parse_trace_config(trace_config) if isinstance(trace_config, str) else trace_config
+    w, t = c["block_threads"], c["top_nodes"]
+    if c["persistent"] == 0:
+        return k.startswith(f"pv::k_trace<false, {w}, {t}, false,")
+    refill = "true" if c["persistent"] == 1 else "false"
+    return k.startswith(f"pv::k_trace_refill<false, {w}, {t},") and k.split("(")[0].endswith(f", {refill}>")
 
 
-def write_counters(fetch_csv, write_csv, out, trace_config):
+def write_counters(fetch_csv, write_csv, out, trace_config, legs: str = "none", sq_csv=None):
     """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the trace kernel by
-    what the same counters read for the 256 MiB device copy, and write the
-    counters file that read_counters() accepts."""
+    what the same counters read for the run's largest device copy (the 256
+    MiB calibration copy, or with the encode leg its 1 GiB cache flush), and
+    write the counters file that read_counters() accepts."""
+    copy_bytes = (1 << 30) if "encode" in legs else COPY_BYTES
+    legs_args = "--legs none" if legs == "none" else f"--legs {legs} --encode-frames 4"
     import csv
 
     def load(path, counter):
@@ -155,8 +191,8 @@ def write_counters(fetch_csv, write_csv, out, trace_config):
         # the calibration copy is the runtime's blit kernel (the ceiling
         # kernels' own 1 GiB copy is not it)
         copy = max(v for k, v in rows if "copyBuffer" in k)
-        trace = [v for k, v in rows if is_trace_kernel(k)]
-        res[counter] = {"copy_kib": copy, "scale": COPY_BYTES / (copy * 1024.0),
+        trace = [v for k, v in rows if is_trace_kernel(k, trace_config)]
+        res[counter] = {"copy_kib": copy, "scale": copy_bytes / (copy * 1024.0),
                         "trace_kib": sum(trace) / len(trace), "n": len(trace)}
     fetch = res["FETCH_SIZE"]["trace_kib"] * 1024 * res["FETCH_SIZE"]["scale"]
     write = res["WRITE_SIZE"]["trace_kib"] * 1024 * res["WRITE_SIZE"]["scale"]
@@ -164,18 +200,32 @@ def write_counters(fetch_csv, write_csv, out, trace_config):
         f.write("# HBM traffic of the trace kernel (uninstrumented; k_trace or k_trace_refill by schedule) on the "
                 "city workload\n")
         f.write("# counters per dispatch from rocprofv3 --pmc, one counter per run; each scaled by what the\n")
-        f.write("# same counter reads for a 256 MiB device-to-device copy (reads and writes 268435456 bytes)\n")
+        f.write(f"# same counter reads for the run's largest device-to-device copy (reads and writes {copy_bytes} bytes)\n")
         f.write("# commands (MI355X host, repository root, TMPDIR=/tmp), then on any host:\n")
         for c in ("FETCH_SIZE", "WRITE_SIZE"):
             f.write(f"#   rocprofv3 --pmc {c} -f csv -d OUT_DIR/pmc_{c} -o pmc -- python3 bench.py --steps 3 "
-                    f"--warmup 1 --legs none --no-cpu-baseline --calibrate-copy --trace-config {trace_config}\n")
+                    f"--warmup 1 {legs_args} --no-cpu-baseline --calibrate-copy --trace-config {trace_config}\n")
         f.write("#   python3 bench.py --write-counters OUT_DIR/pmc_FETCH_SIZE/pmc_counter_collection.csv "
-                f"OUT_DIR/pmc_WRITE_SIZE/pmc_counter_collection.csv OUT --trace-config {trace_config}\n")
+                f"OUT_DIR/pmc_WRITE_SIZE/pmc_counter_collection.csv OUT --trace-config {trace_config}"
+                + ("" if legs == "none" else f" --legs {legs}") + "\n")
         for c, r in res.items():
             f.write(f"{c.lower()}_copy_kib: {r['copy_kib']:.1f}\n")
             f.write(f"{c.lower()}_scale: {r['scale']:.4f}\n")
             f.write(f"{c.lower()}_trace_kib_mean: {r['trace_kib']:.1f}\n")
             f.write(f"{c.lower()}_trace_dispatches: {r['n']}\n")
+        if sq_csv:
+            thr, act = [], []
+            with open(sq_csv) as fs:
+                for r in csv.DictReader(fs):
+                    if is_trace_kernel(r["Kernel_Name"], trace_config):
+                        if r["Counter_Name"] == "SQ_THREAD_CYCLES_VALU":
+                            thr.append(float(r["Counter_Value"]))
+                        elif r["Counter_Name"] == "SQ_ACTIVE_INST_VALU":
+                            act.append(float(r["Counter_Value"]))
+            f.write("#   lane utilisation from the SQ counter run: rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU "
+                    "SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_INSTS_LDS "
+                    "(same command), then --sq-csv OUT_DIR/pmc_SQ_WAVES/pmc_counter_collection.csv\n")
+            f.write(f"valu_lane_utilisation: {sum(thr) / len(thr) / (64 * sum(act) / len(act)):.4f}\n")
         f.write(f"fetch_bytes_per_launch: {fetch:.0f}\n")
         f.write(f"write_bytes_per_launch: {write:.0f}\n")
         f.write(f"traffic_bytes_per_launch: {fetch + write:.0f}\n")
@@ -184,16 +234,59 @@ def write_counters(fetch_csv, write_csv, out, trace_config):
     return fetch + write
 
 
+def write_kernel_counters(fetch_csv, write_csv, out, copy_bytes: int, title: str, commands):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of every kernel, per launch
+    grid, scaled by what the same counters read for the run's largest
+    device copy (copy_bytes read and written), as bytes per launch."""
+    import csv
+    import collections
+    res = {}
+    scale = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        acc = collections.defaultdict(list)
+        copy = 0.0
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"])
+                if "copyBuffer" in r["Kernel_Name"]:
+                    copy = max(copy, v)
+                    continue
+                acc[(r["Kernel_Name"].split("(")[0].replace("void ", ""), int(r["Grid_Size"]))].append(v)
+        scale[counter] = (copy, copy_bytes / (copy * 1024.0))
+        for k, v in acc.items():
+            res.setdefault(k, {})[counter] = (len(v), sum(v) / len(v) * 1024 * scale[counter][1])
+    with open(out, "w") as f:
+        f.write(f"# {title}\n")
+        f.write("# rocprofv3 --pmc, one counter per run, mean per dispatch; each counter scaled by what it\n")
+        f.write(f"# reads for the run's largest device copy ({copy_bytes} bytes read and written)\n")
+        f.write("# commands (MI355X host, repository root, TMPDIR=/tmp), then on any host:\n")
+        for c in commands:
+            f.write(f"#   {c}\n")
+        for c, (kib, sc) in scale.items():
+            f.write(f"# {c}: copy reads {kib:.1f} KiB, scale {sc:.4f}\n")
+        f.write(f"# {'kernel':70s} {'grid':>9s} {'n':>4s} {'fetch_MB':>9s} {'write_MB':>9s} {'total_MB':>9s}\n")
+        for (k, g) in sorted(res, key=lambda kg: -sum(x[1] for x in res[kg].values())):
+            r = res[(k, g)]
+            fe = r.get("FETCH_SIZE", (0, 0.0))
+            wr = r.get("WRITE_SIZE", (0, 0.0))
+            f.write(f"{k[:70]:70s} {g:9d} {max(fe[0], wr[0]):4d} {fe[1] / 1e6:9.2f} {wr[1] / 1e6:9.2f} "
+                    f"{(fe[1] + wr[1]) / 1e6:9.2f}\n")
+    return res
+
+
 def summarize_counters(paths):
     """Mean per dispatch of each counter, per kernel (template arguments
-    kept, parameters dropped), from rocprofv3 --pmc CSV files."""
+    kept, parameters dropped) and launch grid, from rocprofv3 --pmc CSV
+    files."""
     import csv
     import collections
     acc = collections.defaultdict(lambda: collections.defaultdict(list))
     for path in paths:
         with open(path) as f:
             for r in csv.DictReader(f):
-                k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                k = r["Kernel_Name"].split("(")[0].replace("void ", "") + f"  [grid {r['Grid_Size']}]"
                 acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
     lines = []
     for k in sorted(acc):
@@ -762,13 +855,27 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the library runs the update and pack on a single GPU and has no cross-GPU exchange)", file=sys.stderr)
         sys.exit(2)
+    if args.write_kernel_counters:
+        fc, wc, out = args.write_kernel_counters
+        cmd = ("python3 bench.py --steps 3 --warmup 1 --legs encode --encode-frames 4 --no-cpu-baseline "
+               "--calibrate-copy" + (f" --trace-config {args.trace_config}" if args.trace_config else ""))
+        write_kernel_counters(fc, wc, out, 1 << 30,
+                              "HBM traffic per launch of every kernel of the city step and the encode leg (4 frames)",
+                              [f"rocprofv3 --pmc {c} -f csv -d OUT_DIR/pmc_{c} -o pmc -- {cmd}"
+                               for c in ("FETCH_SIZE", "WRITE_SIZE")]
+                              + ["python3 bench.py --write-kernel-counters OUT_DIR/pmc_FETCH_SIZE/pmc_counter_collection.csv "
+                                 "OUT_DIR/pmc_WRITE_SIZE/pmc_counter_collection.csv OUT"
+                                 + (f" --trace-config {args.trace_config}" if args.trace_config else "")])
+        print(f"-> {out}")
+        return
     if args.summarize_counters:
         print(summarize_counters(args.summarize_counters))
         return
     if args.write_counters:
         if not args.trace_config:
             sys.exit("--write-counters needs the --trace-config the counters were taken with")
-        t = write_counters(*args.write_counters, trace_config=args.trace_config)
+        t = write_counters(*args.write_counters, trace_config=args.trace_config,
+                           legs="none" if args.legs == DEFAULT_LEGS else args.legs, sq_csv=args.sq_csv)
         print(f"trace kernel HBM traffic {t / 1e6:.2f} MB per launch -> {args.write_counters[2]}")
         return
     import numpy as np
@@ -931,9 +1038,11 @@ def main():
         "autotune": None if tuned is None else {"source": tuned["source"], "tried": tuned["tried"],
                                                  "best_ms": tuned["ms"], "top5": tuned.get("ranking")},
         "stage_ms": stage_ms,
-        "roofline": {"bound": "alu", "kernel": TRACE_KERNEL_NAME[vol.get_trace_config()["persistent"]], "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+        "roofline": {"bound": "alu", "kernel": trace_kernel_instance(vol.get_trace_config()),
+                     "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
                      "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
+                     "valu_lane_utilisation": read_lane_utilisation(args.counters, vol.get_trace_config()),
                      "trace_ms": trace_s * 1e3,
                      "flop_per_launch": flop_per_launch, "node_visits_per_ray": node_visits / (K * rays),
                      "tri_tests_per_ray": tri_tests / (K * rays), "shadow_rays_per_ray": shadow / (K * rays),

@@ -294,21 +294,16 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
     pf.load(rays, n, P, cg, 0);
     pf.store(sm, 0);
     __syncthreads();
-    // weight fragments of every row tile of the wavefront: this step's, and
-    // the next step's requested before this step's products
-    uint4 acur[RT][2], anxt[RT][2];
-    if constexpr (MODE != kBlendVALU) {
-#pragma unroll
-        for (int t = 0; t < RT; ++t) load_frag(tab, 0, TS::mtile(t), acur[t][0], acur[t][1]);
-    }
+    // weight fragments of every row tile of the wavefront for the current
+    // step, requested at the step's start (a second set for the next step
+    // would cost the registers of a third wavefront per SIMD)
+    uint4 acur[RT][2];
     for (int s = 0; s < steps; ++s) {
         const int buf = s & 1;
-        if (s + 1 < steps) {
-            pf.load(rays, n, P, cg, s + 1);
-            if constexpr (MODE != kBlendVALU) {
+        if (s + 1 < steps) pf.load(rays, n, P, cg, s + 1);
+        if constexpr (MODE != kBlendVALU) {
 #pragma unroll
-                for (int t = 0; t < RT; ++t) load_frag(tab, s + 1, TS::mtile(t), anxt[t][0], anxt[t][1]);
-            }
+            for (int t = 0; t < RT; ++t) load_frag(tab, s, TS::mtile(t), acur[t][0], acur[t][1]);
         }
         if constexpr (MODE == kBlendVALU) {
             // vector FMAs: the lane's rows 4 kq .. 4 kq + 3 of every row tile
@@ -396,13 +391,7 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
         // every wavefront is done with the other buffer since the last step's barrier
         if (s + 1 < steps) {
             pf.store(sm, buf ^ 1);
-            if constexpr (MODE != kBlendVALU) {
-#pragma unroll
-                for (int t = 0; t < RT; ++t) {
-                    acur[t][0] = anxt[t][0];
-                    acur[t][1] = anxt[t][1];
-                }
-            }
+
         }
         __syncthreads();
     }
