@@ -356,34 +356,45 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
 #pragma unroll
                 for (int c = 0; c < NC; ++c) split8(bf[c], bh[c], bl[c]);
             }
+            // the products, ordered so that consecutive matrix instructions
+            // feed different accumulators (each accumulator still takes its
+            // terms in the same order)
+            if (MODE == kBlendBF16x3) {
 #pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                const uint4 a0 = acur[t][0], a1 = acur[t][1];
-                const bool it = t < NI;
-                const int nch = it ? 3 : 2;
-                const int acc0 = it ? 3 * t : 3 * NI + 2 * (t - NI);
-                const int ch0 = it ? 0 : NC - 2;  // first channel slot of the tile's texture
-                if (MODE == kBlendBF16x3) {
-                    const bf16x8 ah = __builtin_bit_cast(bf16x8, a0), al = __builtin_bit_cast(bf16x8, a1);
+                for (int pk = 0; pk < 3; ++pk) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        if (c >= nch) continue;
-                        v4f &a = ts.acc[acc0 + c];
-                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ch0 + c], a, 0, 0, 0);
-                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ch0 + c], a, 0, 0, 0);
-                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ch0 + c], a, 0, 0, 0);
+                    for (int t = 0; t < RT; ++t) {
+                        const bool it = t < NI;
+                        const int nch = it ? 3 : 2;
+                        const int acc0 = it ? 3 * t : 3 * NI + 2 * (t - NI);
+                        const int ch0 = it ? 0 : NC - 2;  // first channel slot of the tile's texture
+                        const bf16x8 aw = __builtin_bit_cast(bf16x8, pk == 2 ? acur[t][1] : acur[t][0]);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            if (c >= nch) continue;
+                            v4f &a = ts.acc[acc0 + c];
+                            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, pk == 1 ? bl[ch0 + c] : bh[ch0 + c], a,
+                                                                        0, 0, 0);
+                        }
                     }
-                } else {
-                    const float w[8] = {__uint_as_float(a0.x), __uint_as_float(a0.y), __uint_as_float(a0.z),
-                                        __uint_as_float(a0.w), __uint_as_float(a1.x), __uint_as_float(a1.y),
-                                        __uint_as_float(a1.z), __uint_as_float(a1.w)};
+                }
+            } else {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        if (c >= nch) continue;
-                        v4f &a = ts.acc[acc0 + c];
+                for (int i = 0; i < 8; ++i) {
 #pragma unroll
-                        for (int i = 0; i < 8; ++i)
-                            a = __builtin_amdgcn_mfma_f32_16x16x4f32(w[i], bf[ch0 + c][i], a, 0, 0, 0);
+                    for (int t = 0; t < RT; ++t) {
+                        const bool it = t < NI;
+                        const int nch = it ? 3 : 2;
+                        const int acc0 = it ? 3 * t : 3 * NI + 2 * (t - NI);
+                        const int ch0 = it ? 0 : NC - 2;
+                        const uint4 aw = acur[t][i >> 2];
+                        const float w = __uint_as_float((i & 3) == 0 ? aw.x : (i & 3) == 1 ? aw.y : (i & 3) == 2 ? aw.z : aw.w);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            if (c >= nch) continue;
+                            v4f &a = ts.acc[acc0 + c];
+                            a = __builtin_amdgcn_mfma_f32_16x16x4f32(w, bf[ch0 + c][i], a, 0, 0, 0);
+                        }
                     }
                 }
             }
