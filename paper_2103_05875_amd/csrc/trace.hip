@@ -14,7 +14,8 @@ __device__ __forceinline__ void trace_wave(const VolumeParams &vp, const SceneVi
                                            const TraceGrid &g, int w, STK stk, Counts &cnt, uint32_t &shadow,
                                            const SplitBuffers &split) {
     const int lane = threadIdx.x & 63;
-    const int j = w / g.n_bricks, brick = w - j * g.n_bricks;
+    int j, brick;
+    packet_of(vp, w, j, brick);
     const int bxi = brick % g.nbx, byi = (brick / g.nbx) % g.nby, bzi = brick / (g.nbx * g.nby);
     const int x = bxi * g.bx + lane % g.bx;
     const int y = byi * g.by + (lane / g.bx) % g.by;

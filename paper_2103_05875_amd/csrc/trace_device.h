@@ -616,11 +616,21 @@ __device__ void lane_transition(LaneState &s, const VolumeParams &vp, const Scen
     s.q = -1;
 }
 
+// Packet w -> (ray direction j, brick): brick-major, every direction of a
+// brick before the next brick, so that each XCD's contiguous share of the
+// packets (its blocks, or its refill queue) covers a contiguous set of bricks
+// and its L2 holds the scene around them rather than around every brick.
+__device__ __forceinline__ void packet_of(const VolumeParams &vp, int w, int &j, int &brick) {
+    brick = w / vp.n;
+    j = w - brick * vp.n;
+}
+
 // Ray number r (packet order) -> record index, or -1 for a lane of a ragged
 // brick that lies outside the grid.
 __device__ __forceinline__ int ray_record(const VolumeParams &vp, const TraceGrid &g, int r) {
     const int w = r >> 6, lane = r & 63;
-    const int j = w / g.n_bricks, brick = w - j * g.n_bricks;
+    int j, brick;
+    packet_of(vp, w, j, brick);
     const int bxi = brick % g.nbx, byi = (brick / g.nbx) % g.nby, bzi = brick / (g.nbx * g.nby);
     const int x = bxi * g.bx + lane % g.bx;
     const int y = byi * g.by + (lane / g.bx) % g.by;
