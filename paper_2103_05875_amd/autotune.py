@@ -126,15 +126,18 @@ def probe_bucket(volume) -> int:
     return max(0, int(volume.P).bit_length() - 1)
 
 
-def tune_batched(volumes, rotations, lights=None, reps: int = 4, bucket=probe_bucket,
-                 verbose: bool = False) -> dict:
+def tune_batched(volumes, rotations, lights=None, reps: int = 6, bucket=probe_bucket,
+                 verbose: bool = False, margin: float = 0.01) -> dict:
     """Pick per size bucket the trace shape (probe brick, staged top nodes)
     that makes the batched trace of ``volumes`` fastest, timed on the batched
     launch itself: in a batch every volume shares the device with the others,
     so a shape chosen on a volume alone (where a small grid is latency-bound)
     need not help. One pass of coordinate descent over the buckets, largest
     first; every other volume keeps its current shape while a bucket is
-    timed, and each bucket starts from a fresh timing of the current shapes. The volumes' maps are updated by the trial frames. Returns
+    timed, and each bucket starts from a fresh timing of the current shapes;
+    a candidate replaces the current shape only when it is faster by more
+    than ``margin`` (a bucket is a small share of the launch, so smaller
+    differences are within the timing noise). The volumes' maps are updated by the trial frames. Returns
     {"choices": {bucket: config}, "ms": trace ms of the last pass' best,
     "default_ms": trace ms at the default shape, "tried": launches timed}."""
     from . import native
@@ -173,7 +176,7 @@ def tune_batched(volumes, rotations, lights=None, reps: int = 4, bucket=probe_bu
                 tried += 1
                 if verbose:
                     print(f"batched autotune bucket {k}: {c} -> {ms:.4f} ms", flush=True)
-                if ms < best[0]:
+                if ms < best[0] * (1.0 - margin):
                     best = (ms, c)
             choices[k] = best[1]
             best_ms = best[0]
