@@ -907,7 +907,7 @@ def main():
         scratch = ps.Volume(ctx, cfg)
         scratch.set_scene(sc)
         tuned = autotune.tune(scratch, *frames[0], n_triangles=scene.n_triangles, cache=args.tune_cache,
-                              force=args.retune)
+                              force=args.retune, frames=frames[:8], reps=2)
         scratch.close()
         print(f"bench: trace launch {tuned['config']} ({tuned['source']}, {tuned['ms']:.3f} ms)",
               file=sys.stderr, flush=True)

@@ -70,7 +70,7 @@ def _save(path: str, data: Dict[str, dict]):
 
 def tune(volume, rotation, lights=None, n_triangles: int = 0, reps: int = 3,
          cache: Optional[str] = DEFAULT_CACHE, force: bool = False, verbose: bool = False,
-         shipped: bool = True, space: str = "full") -> dict:
+         shipped: bool = True, space: str = "full", frames=None) -> dict:
     """Pick and set the fastest trace launch shape for ``volume``.
 
     Looks the shape up in ``cache``, then (if ``shipped``) in the shipped
@@ -80,7 +80,11 @@ def tune(volume, rotation, lights=None, n_triangles: int = 0, reps: int = 3,
     same shape). Returns {"config": ..., "ms": ..., "tried": n, "cached":
     bool, "source": "cache" | "shipped" | "measured"}. ``space`` picks the
     candidate set (see candidates()); its choices are cached apart.
+    ``frames`` (a list of (rotation, lights)) times every candidate over
+    those frames instead of repeating one: a shape that is fastest on one
+    frame need not be over a moving light and changing rotations.
     """
+    seq = list(frames) if frames else [(rotation, lights)]
     k = key(volume.cfg, n_triangles) + ("" if space == "full" else ":" + space)
     if not force:
         for source, path in (("cache", cache), ("shipped", SHIPPED if shipped else None)):
@@ -95,10 +99,11 @@ def tune(volume, rotation, lights=None, n_triangles: int = 0, reps: int = 3,
     try:
         for c in candidates(space):
             _apply(volume, c)
-            volume.update_probes(rotation, lights)          # warm-up
+            volume.update_probes(*seq[0])                    # warm-up
             ctx.stage_times()
             for _ in range(reps):
-                volume.update_probes(rotation, lights)
+                for fr in seq:
+                    volume.update_probes(*fr)
             st = ctx.stage_times()
             ms = sum(st[s][0] for s in ("trace", "shadow", "shade")) / max(st["trace"][1], 1)
             results.append((ms, c))
