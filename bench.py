@@ -619,7 +619,8 @@ def leg_encode(ps, torch, frames: int):
     kv = np.mean([c[1] for c in changed])
     pack_bytes = P * 1408 * 2 + (ki * 384 + kv * 1024) * 2 + P * 2
     upd_ms = (st["raydirs"][0] + st["trace"][0] + st["blend"][0]) / frames
-    per_kernel = {k: st[k][0] / max(st[k][1], 1) for k in ("pack_mask", "pack_scan", "pack_compact", "pack_finish", "trace", "blend")}
+    per_kernel = {k: st[k][0] / max(st[k][1], 1) for k in ("pack_mask", "pack_scan", "pack_compact", "pack_finish",
+                                                            "trace", "blend")}
     out = {"probes": P, "frames": frames, "round_trip_bit_exact": bool(ok),
            "trace_config": {**c, "brick": list(c["brick"])}, "trace_config_source": tuned["source"],
            "entropy_encode_ms": st["entropy"][0] / frames,

@@ -179,13 +179,13 @@ __device__ __forceinline__ TileSum shfl_xor_tile_sum(const TileSum &v, int off) 
                    __shfl_xor(v.lv, off), __shfl_xor(v.si, off), __shfl_xor(v.sv, off)};
 }
 
-// Change mask of every probe: any interior texel differs (tau = 0) or
-// |cur - ref| > tau. Each block also leaves a summary of its tile (changed
-// counts and the last two changed probes per texture) for the prefix.
-__global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P, float tau_irr, float tau_vis) {
-    __shared__ PackSmem sm;
-    const int p0 = blockIdx.x * kPackQ;
-    if (p0 >= P) return;
+// Change mask of one tile (every thread of the block): any interior texel
+// differs (tau = 0) or |cur - ref| > tau. The tile's current texels are
+// staged in sm (and stay there for a compaction in the same block); the
+// masks and the tile's 32-bit summary (changed counts and the last two
+// changed probes per texture) are written for the prefix.
+__device__ void mask_tile(const PackBuffers &b, int P, int tile, float tau_irr, float tau_vis, PackSmem &sm) {
+    const int p0 = tile * kPackQ;
     if (threadIdx.x < kPackQ * 2) sm.changed[threadIdx.x >> 1][threadIdx.x & 1] = 0;
     const int n = min(kPackQ, P - p0);
     constexpr int units = kPackQ * (kIrrUnits + kVisUnits);
@@ -247,10 +247,16 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P
                 t.lv = p0 + q;
             }
         }
-        b.tsum[blockIdx.x] = pack_tile_sum(t, p0);
-        // the compaction blocks of small volumes add to the checksum
-        if (blockIdx.x == 0) reinterpret_cast<uint32_t *>(b.packet)[kHdrChecksum] = 0u;
+        b.tsum[tile] = pack_tile_sum(t, p0);
     }
+}
+
+__global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P, float tau_irr, float tau_vis) {
+    __shared__ PackSmem sm;
+    if ((int)blockIdx.x * kPackQ >= P) return;
+    mask_tile(b, P, blockIdx.x, tau_irr, tau_vis, sm);
+    // the compaction blocks of small volumes add to the checksum
+    if (blockIdx.x == 0 && threadIdx.x == 0) reinterpret_cast<uint32_t *>(b.packet)[kHdrChecksum] = 0u;
 }
 
 constexpr int kScanThreads = 1024;
@@ -338,52 +344,40 @@ __device__ __forceinline__ void reduce_tiles(const PackBuffers &b, int n_tiles, 
     __syncthreads();
 }
 
-// Compaction of one tile: its changed probes' ranks (the prefix before the
-// tile plus the changed lanes below), their delta-coded index entries, XOR
-// byte planes and reference update. The checksum (the sum of every payload
-// word's hash, an order-free integer sum) is split by word: each block hashes
-// its plane words and the index words whose second entry is its own (the
-// entry before its first comes from the last two changed probes before the
-// tile; the first visibility entry pairs with the last irradiance entry),
-// the block holding the index's last entry also the zero padding, and leaves
-// its share: added to the header's checksum word atomically up to
-// kPackAtomicTiles tiles, else stored for k_pack_checksum. Block 0 writes the
-// rest of the header. FUSED: the block reduces the tile summaries itself
-// (small tile counts, no scan launch); otherwise the scan left the prefix in
-// the tile's summary and the totals.
-template <bool FUSED>
-__global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, int P, uint32_t client, uint32_t seq) {
-    __shared__ PackSmem sm;
-    __shared__ int rank_s[kPackQ][2];
-    __shared__ int any_s;
-    __shared__ TileSum red[2 * kPackThreads / 64];
-    const int tile = blockIdx.x, p0 = tile * kPackQ;
+// Per-block scratch of a tile's compaction.
+struct CompactShared {
+    int rank_s[kPackQ][2];
+    int any_s;
+};
+
+// Compaction of one tile (every thread of the block): its changed probes'
+// ranks (the summary before the tile plus the changed lanes below), their
+// delta-coded index entries, XOR byte planes and reference update; returns
+// the thread's share of the checksum. The checksum (the sum of every
+// payload word's hash, an order-free integer sum) is split by word: a tile
+// hashes its plane words and the index words whose second entry is its own
+// (the entry before its first comes from the last two changed probes before
+// the tile; the first visibility entry pairs with the last irradiance
+// entry), and the tile holding the index's last entry also the zero
+// padding. staged: the tile's current texels are already in sm.
+__device__ uint32_t compact_tile(const PackBuffers &b, int P, int tile, const TileSum &before, const TileSum &tot,
+                                 PackSmem &sm, bool staged, CompactShared &cs) {
+    const int p0 = tile * kPackQ;
     const int n = min(kPackQ, P - p0);
-    TileSum before, tot;
-    if (FUSED) {
-        reduce_tiles<kPackThreads>(b, (P + kPackQ - 1) / kPackQ, tile, before, tot, red);
-    } else {
-        before = load_tile_sum(b, tile);
-        tot = tile_sum_none();
-        tot.ci = (int)b.totals[0];
-        tot.cv = (int)b.totals[1];
-        tot.li = (int)b.totals[2];
-        tot.si = (int)b.totals[3];
-    }
     const int K_irr = tot.ci, K_vis = tot.cv, M = K_irr + K_vis;
     const int idx_bytes = ((2 * M + 15) / 16) * 16;
     uint16_t *idx = reinterpret_cast<uint16_t *>(b.packet + 32);  // irradiance entries, then visibility
     uint32_t part = 0;
     if (threadIdx.x < 64) {
-        // ranks and index entries of the tile's changed probes: lane q owns
-        // probe p0 + q; its rank counts the changed lanes below it, its
-        // predecessor is the highest of them (or the last one before the tile)
+        // lane q owns probe p0 + q; its rank counts the changed lanes below
+        // it, its predecessor is the highest of them (or the last one before
+        // the tile)
         const int q = threadIdx.x, p = p0 + q;
         const bool ci = q < n && b.mask_irr[p] != 0, cv = q < n && b.mask_vis[p] != 0;
         const unsigned long long below = (1ull << q) - 1ull;
         const unsigned long long bi = __ballot(ci), bvv = __ballot(cv);
         const unsigned long long mi = bi & below, mv = bvv & below;
-        if (q == 0) any_s = (bi | bvv) != 0ull;
+        if (q == 0) cs.any_s = (bi | bvv) != 0ull;
         const int ki = before.ci + __popcll(mi), kv = before.cv + __popcll(mv);
         const int prev_i = mi ? p0 + 63 - __clzll((long long)mi) : before.li;
         const int prev_v = mv ? p0 + 63 - __clzll((long long)mv) : before.lv;
@@ -394,8 +388,8 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
         const uint32_t ei_lane = __shfl(ei, mi ? 63 - __clzll((long long)mi) : 0);
         const uint32_t ev_lane = __shfl(ev, mv ? 63 - __clzll((long long)mv) : 0);
         if (q < kPackQ) {
-            rank_s[q][0] = ci ? ki : -1;
-            rank_s[q][1] = cv ? kv : -1;
+            cs.rank_s[q][0] = ci ? ki : -1;
+            cs.rank_s[q][1] = cv ? kv : -1;
         }
         if (ci) idx[ki] = (uint16_t)ei;
         if (cv) idx[K_irr + kv] = (uint16_t)ev;
@@ -424,16 +418,18 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
         }
     }
     __syncthreads();
-    if (any_s) {
-        stage_tiles(b, p0, P, sm);
-        __syncthreads();
+    if (cs.any_s) {
+        if (!staged) {
+            stage_tiles(b, p0, P, sm);
+            __syncthreads();
+        }
         uint8_t *planes_i = b.packet + 32 + idx_bytes;
         uint8_t *planes_v = planes_i + (size_t)K_irr * 6 * 64;
         const int units = kPackQ * (kIrrUnits + kVisUnits);
         for (int u = threadIdx.x; u < units; u += kPackThreads) {
             const Unit un = unit_of(u);
             if (un.q >= n) continue;
-            const int k = rank_s[un.q][un.tex];
+            const int k = cs.rank_s[un.q][un.tex];
             if (k < 0) continue;
             const int p = p0 + un.q;
             uint16_t cur[8], ref[8];
@@ -460,27 +456,66 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
             part += word_hash(lo[0], wlo) + word_hash(lo[1], wlo + 1) + word_hash(hi[0], whi) + word_hash(hi[1], whi + 1);
         }
     }
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-    if ((threadIdx.x & 63) == 0) sm.part[threadIdx.x >> 6] = part;
+    // the block's scratch is reused by its next tile
     __syncthreads();
+    return part;
+}
+
+// The block's sum of its threads' shares (every thread must call it; thread
+// 0 receives the sum).
+__device__ __forceinline__ uint32_t block_sum(uint32_t part, uint32_t *sh) {
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = part;
+    __syncthreads();
+    uint32_t sum = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kPackThreads / 64; ++w) sum += sh[w];
+    return sum;
+}
+
+__device__ __forceinline__ void write_header(const PackBuffers &b, int P, int K_irr, int K_vis, uint32_t client,
+                                             uint32_t seq) {
+    uint32_t *h = reinterpret_cast<uint32_t *>(b.packet);
+    h[kHdrMagic] = kPacketMagic;
+    h[kHdrVersion] = kPacketVersion;
+    h[kHdrClient] = client;
+    h[kHdrSeq] = seq;
+    h[kHdrProbes] = (uint32_t)P;
+    h[kHdrKIrr] = (uint32_t)K_irr;
+    h[kHdrKVis] = (uint32_t)K_vis;
+}
+
+// Compaction, one block per tile. FUSED: the block reduces the tile
+// summaries itself (small tile counts, no scan launch); otherwise the scan
+// left the summary before the tile and the totals. Each block adds its
+// checksum share to the header atomically up to kPackAtomicTiles tiles, else
+// stores it for k_pack_checksum; block 0 writes the rest of the header.
+template <bool FUSED>
+__global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, int P, uint32_t client, uint32_t seq) {
+    __shared__ PackSmem sm;
+    __shared__ CompactShared cs;
+    __shared__ TileSum red[2 * kPackThreads / 64];
+    const int tile = blockIdx.x;
+    TileSum before, tot;
+    if (FUSED) {
+        reduce_tiles<kPackThreads>(b, (P + kPackQ - 1) / kPackQ, tile, before, tot, red);
+    } else {
+        before = load_tile_sum(b, tile);
+        tot = tile_sum_none();
+        tot.ci = (int)b.totals[0];
+        tot.cv = (int)b.totals[1];
+        tot.li = (int)b.totals[2];
+        tot.si = (int)b.totals[3];
+    }
+    const uint32_t part = compact_tile(b, P, tile, before, tot, sm, false, cs);
+    const uint32_t sum = block_sum(part, sm.part);
     if (threadIdx.x == 0) {
-        uint32_t sum = 0;
-        for (int w = 0; w < kPackThreads / 64; ++w) sum += sm.part[w];
-        uint32_t *h = reinterpret_cast<uint32_t *>(b.packet);
         if (pack_atomic_checksum((P + kPackQ - 1) / kPackQ)) {
-            if (sum) atomicAdd(h + kHdrChecksum, sum);
+            if (sum) atomicAdd(reinterpret_cast<uint32_t *>(b.packet) + kHdrChecksum, sum);
         } else {
             b.partial[tile] = sum;
         }
-        if (tile == 0) {
-            h[kHdrMagic] = kPacketMagic;
-            h[kHdrVersion] = kPacketVersion;
-            h[kHdrClient] = client;
-            h[kHdrSeq] = seq;
-            h[kHdrProbes] = (uint32_t)P;
-            h[kHdrKIrr] = (uint32_t)K_irr;
-            h[kHdrKVis] = (uint32_t)K_vis;
-        }
+        if (tile == 0) write_header(b, P, tot.ci, tot.cv, client, seq);
     }
 }
 
