@@ -392,6 +392,56 @@ def test_blend_paths_against_oracle(ps, ctx, O, mode, fp16, n, grid):
     vol.close()
 
 
+def test_tuner_over_frames_and_batched_buckets(ps, ctx):
+    """The autotuner timed over several frames leaves a candidate shape on
+    the volume; the batched tuner leaves one shape per probe-count bucket,
+    and the batched update at the tuned shapes equals the per-volume
+    updates bit for bit."""
+    from paper_2103_05875_amd import autotune
+    scene = synth.box_field(3000, seed=12, extent=24.0)
+    sc = ps.Scene.from_synth(ctx, scene)
+    cfgs = [synth.VolumeConfig(4, 4, 4, (1.0, 0.3, 1.0), (3.0, 2.0, 3.0), 32, fp16=True, max_distance=5.0),
+            synth.VolumeConfig(8, 4, 8, (1.0, 0.3, 1.0), (1.5, 2.0, 1.5), 32, fp16=True, max_distance=5.0),
+            synth.VolumeConfig(8, 8, 8, (1.0, 0.3, 1.0), (1.5, 1.0, 1.5), 16, fp16=True, max_distance=5.0)]
+    frames = [(synth.rotation(5, f), None) for f in range(3)]
+    v = ps.Volume(ctx, cfgs[0])
+    v.set_scene(sc)
+    r = autotune.tune(v, *frames[0], n_triangles=scene.n_triangles, reps=1, cache=None, shipped=False,
+                      frames=frames, space="batched")
+    got = v.get_trace_config()
+    assert r["tried"] == len(autotune.candidates("batched"))
+    assert tuple(got["brick"]) == tuple(r["config"]["brick"]) and got["top_nodes"] == r["config"]["top_nodes"]
+    v.close()
+    plain, batched = [], []
+    for c in cfgs:
+        a, b = ps.Volume(ctx, c), ps.Volume(ctx, c)
+        a.set_scene(sc)
+        b.set_scene(sc)
+        plain.append(a)
+        batched.append(b)
+    rots = [synth.rotation(6 + i, 0) for i in range(len(cfgs))]
+    tb = autotune.tune_batched(batched, rots, reps=1)
+    assert set(tb["choices"]) == {autotune.probe_bucket(b) for b in batched}
+    for b in batched:
+        c = tb["choices"][autotune.probe_bucket(b)]
+        got = b.get_trace_config()
+        assert tuple(got["brick"]) == tuple(c["brick"]) and got["top_nodes"] == c["top_nodes"]
+    for a, b in zip(plain, batched):
+        a.set_maps(*b.read_maps()[:2], b.read_maps()[2])
+    for f in range(2):
+        rots = [synth.rotation(9 + i, f) for i in range(len(cfgs))]
+        for a, R in zip(plain, rots):
+            a.update_probes(R)
+        ps.update_probes_batched(batched, rots)
+        ps.native.sync()
+        for a, b in zip(plain, batched):
+            ia, va, _ = a.read_maps()
+            ib, vb, _ = b.read_maps()
+            assert np.array_equal(ia, ib) and np.array_equal(va, vb)
+    for h in plain + batched + [sc]:
+        h.close()
+
+
 def test_blend_mode_default_follows_volume_size(ps, ctx):
     """A new volume takes the per-tile weights below 4,096 probes and the FP32
     table product from there; AUTO restores that choice."""
