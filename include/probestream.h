@@ -324,8 +324,10 @@ pv_status pv_client_set_state(pv_client *client, const void *ref_irr_host, const
  *                     resend (the size of a packet with K_irr = K_vis = P),
  *                     else PV_ERR_CAPACITY. The header gives its size.
  * client_id and seq go into the header. Every pointer 16-byte aligned.
- * Changed masks, tile summaries, totals and checksum shares live in one
- * static device array per GPU of 384.25 KiB (held until the process ends),
+ * Changed masks, tile summaries, totals and checksum counters live in one
+ * static device array per GPU of 356.5 KiB (held until the process ends;
+ * the counters are cleared once when the context takes its address and
+ * every call leaves them at zero),
  * which limits n_probes to 65,536 (PV_ERR_ARG beyond). All calls on one GPU
  * share that array: calls that overlap on a GPU (different streams, or
  * threads) race and must be ordered by the caller. Asynchronous on 'stream';

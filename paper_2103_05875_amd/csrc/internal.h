@@ -110,7 +110,8 @@ struct PackBuffers {
                       // probe (irr, vis) of the tiles before it
     int2 *tiles2;     // per tile, likewise: the changed probe before the last one (irr, vis)
     uint32_t *totals; // K_irr, K_vis, last and second-last changed irradiance probe (written by the scan)
-    uint32_t *partial; // per tile: checksum share of its plane and index words (written by the compaction)
+    unsigned long long *cks; // checksum counters: kCksGroups group words and one final word, 128 bytes
+                             // apart; zero between packs (the last adder of each word resets it)
     uint8_t *packet;
     const uint8_t *active;  // [P] volume's active probes, or null (all)
     const uint8_t *view;    // [P] client's visible set, or null (all)
@@ -118,23 +119,28 @@ struct PackBuffers {
 hipError_t launch_pack_mask(const PackBuffers &b, int P, float tau_irr, float tau_vis, hipStream_t s);
 hipError_t launch_pack_scan(const PackBuffers &b, int P, hipStream_t s);
 hipError_t launch_pack_compact(const PackBuffers &b, int P, uint32_t client, uint32_t seq, hipStream_t s);
-hipError_t launch_pack_checksum(const PackBuffers &b, int P, hipStream_t s);
 constexpr int kPackTile = 8;   // probes per pack block
 // Up to this many tiles every compaction block reduces the tile summaries
 // itself and the scan launch is skipped (its few microseconds of launch
 // latency exceed the redundant reads); above it the one-block scan runs.
 constexpr int kPackFusedTiles = 2048;
 bool pack_fused(int P);
-// Up to this many tiles the compaction blocks add their checksum shares to
-// the header atomically; above it k_pack_checksum sums them (one launch).
-constexpr int kPackAtomicTiles = 512;
-__host__ __device__ inline bool pack_atomic_checksum(int n_tiles) { return n_tiles <= kPackAtomicTiles; }
+// The packet checksum is summed by the compaction blocks themselves: each
+// adds its share to one of kCksGroups group words (tile % kCksGroups), the
+// last block of a group adds the group's sum to the final word, the last of
+// those writes the header. A word holds its adders' count in bits 48-63 and
+// their sum in bits 0-47 (at most 256 shares of 32 bits per group at 8,192
+// tiles), so one 64-bit atomic add both adds and tells a block whether it is
+// the last; no fence or second launch is needed.
+constexpr int kCksGroups = 32;
+constexpr int kCksStride = 16;  // 64-bit words between counters (128 bytes)
+constexpr size_t kCksBytes = (size_t)(kCksGroups + 1) * kCksStride * 8;
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 // Pack without allocation (pack.hip): intermediates live in a static device
 // array sized for kNoAllocMaxProbes probes; its address on a device is taken
 // once with that device current (noalloc_scratch_init, from pv_ctx_create).
 constexpr int kNoAllocMaxProbes = PV_MAX_PROBES;
-constexpr size_t kNoAllocScratchBytes = 8192 * 16 + 8192 * 8 + 8192 * 4 + 8192 * 4 + 256 + 65536 + 65536;
+constexpr size_t kNoAllocScratchBytes = 8192 * 16 + 8192 * 8 + 4352 + 8192 * 4 + 256 + 65536 + 65536;
 hipError_t noalloc_scratch_init(int device);
 unsigned char *noalloc_scratch(int device);  // null before noalloc_scratch_init on that device
 hipError_t launch_pack_noalloc(unsigned char *scratch_dev, const uint16_t *cur_irr, const uint16_t *cur_vis,

@@ -255,8 +255,6 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_mask(PackBuffers b, int P
     __shared__ PackSmem sm;
     if ((int)blockIdx.x * kPackQ >= P) return;
     mask_tile(b, P, blockIdx.x, tau_irr, tau_vis, sm);
-    // the compaction blocks of small volumes add to the checksum
-    if (blockIdx.x == 0 && threadIdx.x == 0) reinterpret_cast<uint32_t *>(b.packet)[kHdrChecksum] = 0u;
 }
 
 constexpr int kScanThreads = 1024;
@@ -485,20 +483,41 @@ __device__ __forceinline__ void write_header(const PackBuffers &b, int P, int K_
     h[kHdrKVis] = (uint32_t)K_vis;
 }
 
+// The checksum share of tile 'tile' (thread 0): added to its group's word;
+// the group's last adder resets that word and adds the group's sum to the
+// final word, whose last adder resets it and writes the header checksum.
+// Sums are modulo 2^32 (the checksum is a sum of word hashes, so shares add
+// in any order); a word's low 48 bits hold at most 256 shares.
+__device__ __forceinline__ void add_checksum_share(const PackBuffers &b, int n_tiles, int tile, uint32_t share) {
+    constexpr unsigned long long kOne = 1ull << 48;
+    const int g = tile % kCksGroups;
+    const int members = (n_tiles - g + kCksGroups - 1) / kCksGroups;
+    unsigned long long *gw = b.cks + (size_t)g * kCksStride;
+    const unsigned long long old = atomicAdd(gw, kOne | share);
+    if ((int)(old >> 48) != members - 1) return;
+    atomicExch(gw, 0ull);
+    const uint32_t gsum = (uint32_t)(old + share);
+    unsigned long long *fw = b.cks + (size_t)kCksGroups * kCksStride;
+    const unsigned long long fold = atomicAdd(fw, kOne | gsum);
+    if ((int)(fold >> 48) != min(kCksGroups, n_tiles) - 1) return;
+    atomicExch(fw, 0ull);
+    reinterpret_cast<uint32_t *>(b.packet)[kHdrChecksum] = (uint32_t)(fold + gsum);
+}
+
 // Compaction, one block per tile. FUSED: the block reduces the tile
 // summaries itself (small tile counts, no scan launch); otherwise the scan
 // left the summary before the tile and the totals. Each block adds its
-// checksum share to the header atomically up to kPackAtomicTiles tiles, else
-// stores it for k_pack_checksum; block 0 writes the rest of the header.
+// checksum share (add_checksum_share); block 0 writes the rest of the header.
 template <bool FUSED>
 __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, int P, uint32_t client, uint32_t seq) {
     __shared__ PackSmem sm;
     __shared__ CompactShared cs;
     __shared__ TileSum red[2 * kPackThreads / 64];
     const int tile = blockIdx.x;
+    const int n_tiles = (P + kPackQ - 1) / kPackQ;
     TileSum before, tot;
     if (FUSED) {
-        reduce_tiles<kPackThreads>(b, (P + kPackQ - 1) / kPackQ, tile, before, tot, red);
+        reduce_tiles<kPackThreads>(b, n_tiles, tile, before, tot, red);
     } else {
         before = load_tile_sum(b, tile);
         tot = tile_sum_none();
@@ -510,30 +529,8 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_compact(PackBuffers b, in
     const uint32_t part = compact_tile(b, P, tile, before, tot, sm, false, cs);
     const uint32_t sum = block_sum(part, sm.part);
     if (threadIdx.x == 0) {
-        if (pack_atomic_checksum((P + kPackQ - 1) / kPackQ)) {
-            if (sum) atomicAdd(reinterpret_cast<uint32_t *>(b.packet) + kHdrChecksum, sum);
-        } else {
-            b.partial[tile] = sum;
-        }
         if (tile == 0) write_header(b, P, tot.ci, tot.cv, client, seq);
-    }
-}
-
-// One block: the packet checksum, the sum of the compaction blocks' shares,
-// above kPackAtomicTiles tiles (there the same-address atomics of the blocks
-// would serialize for longer than this launch takes).
-__global__ __launch_bounds__(kScanThreads) void k_pack_checksum(PackBuffers b, int n_tiles) {
-    __shared__ uint32_t sh[kScanThreads / 64];
-    uint32_t s = 0;
-#pragma unroll 4
-    for (int t = threadIdx.x; t < n_tiles; t += kScanThreads) s += b.partial[t];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t tot = 0;
-        for (int w = 0; w < kScanThreads / 64; ++w) tot += sh[w];
-        reinterpret_cast<uint32_t *>(b.packet)[kHdrChecksum] = tot;
+        add_checksum_share(b, n_tiles, tile, sum);
     }
 }
 
@@ -564,11 +561,6 @@ hipError_t launch_pack_compact(const PackBuffers &b, int P, uint32_t client, uin
     return hipGetLastError();
 }
 
-hipError_t launch_pack_checksum(const PackBuffers &b, int P, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_checksum, dim3(1), dim3(kScanThreads), 0, s, b, (P + kPackQ - 1) / kPackQ);
-    return hipGetLastError();
-}
-
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
     const size_t words = bytes / 4;
     if (words == 0) return hipSuccess;
@@ -579,15 +571,15 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // pack without allocation: the per-call intermediates (masks, tile
-// summaries, totals, checksum shares) in one static device array
+// summaries, totals, checksum counters) in one static device array
 // ---------------------------------------------------------------------------
 // Layout of the array for up to kNoAllocMaxProbes probes (offsets in bytes,
 // each section 256-byte aligned).
 constexpr int kNoAllocTiles = (kNoAllocMaxProbes + kPackTile - 1) / kPackTile;
 constexpr size_t kScrTiles = 0;
 constexpr size_t kScrTiles2 = kScrTiles + (size_t)kNoAllocTiles * sizeof(int4);
-constexpr size_t kScrPartial = kScrTiles2 + ((size_t)kNoAllocTiles * sizeof(int2) + 255) / 256 * 256;
-constexpr size_t kScrTsum = kScrPartial + ((size_t)kNoAllocTiles * 4 + 255) / 256 * 256;
+constexpr size_t kScrCks = kScrTiles2 + ((size_t)kNoAllocTiles * sizeof(int2) + 255) / 256 * 256;
+constexpr size_t kScrTsum = kScrCks + (kCksBytes + 255) / 256 * 256;
 constexpr size_t kScrTotals = kScrTsum + ((size_t)kNoAllocTiles * 4 + 255) / 256 * 256;
 constexpr size_t kScrMaskIrr = kScrTotals + 256;
 constexpr size_t kScrMaskVis = kScrMaskIrr + ((size_t)kNoAllocMaxProbes + 255) / 256 * 256;
@@ -614,6 +606,10 @@ hipError_t noalloc_scratch_init(int device) {
     e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
     if (e != hipSuccess) return e;
     if (!ptr) return hipErrorInvalidSymbol;
+    // the checksum counters start at zero; every pack leaves them at zero
+    e = hipMemset((unsigned char *)ptr + kScrCks, 0, kCksBytes);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
     g_scratch_ptr[device] = (unsigned char *)ptr;
     return hipSuccess;
 }
@@ -625,8 +621,9 @@ unsigned char *noalloc_scratch(int device) {
 
 // The pack's launch sequence over caller-owned maps, reference and packet,
 // with every intermediate in the device's scratch array (ptr from
-// noalloc_scratch). Every intermediate is written before it is read, so
-// nothing is cleared between calls.
+// noalloc_scratch). Every intermediate is written before it is read, and
+// the checksum counters are back at zero when a call ends, so nothing is
+// cleared between calls.
 hipError_t launch_pack_noalloc(unsigned char *scr, const uint16_t *cur_irr, const uint16_t *cur_vis, uint16_t *ref_irr,
                                uint16_t *ref_vis, int P, float tau_irr, float tau_vis, uint32_t client, uint32_t seq,
                                uint8_t *packet, hipStream_t s) {
@@ -640,7 +637,7 @@ hipError_t launch_pack_noalloc(unsigned char *scr, const uint16_t *cur_irr, cons
     b.tiles = reinterpret_cast<int4 *>(scr + kScrTiles);
     b.totals = reinterpret_cast<uint32_t *>(scr + kScrTotals);
     b.tiles2 = reinterpret_cast<int2 *>(scr + kScrTiles2);
-    b.partial = reinterpret_cast<uint32_t *>(scr + kScrPartial);
+    b.cks = reinterpret_cast<unsigned long long *>(scr + kScrCks);
     b.tsum = reinterpret_cast<uint32_t *>(scr + kScrTsum);
     b.packet = packet;
     b.active = nullptr;
@@ -648,7 +645,6 @@ hipError_t launch_pack_noalloc(unsigned char *scr, const uint16_t *cur_irr, cons
     hipError_t e = launch_pack_mask(b, P, tau_irr, tau_vis, s);
     if (e == hipSuccess && !pack_fused(P)) e = launch_pack_scan(b, P, s);
     if (e == hipSuccess) e = launch_pack_compact(b, P, client, seq, s);
-    if (e == hipSuccess && !pack_atomic_checksum((P + kPackTile - 1) / kPackTile)) e = launch_pack_checksum(b, P, s);
     return e;
 }
 

@@ -135,7 +135,7 @@ struct pv_client {
     int4 *tiles = nullptr;         // per-tile summaries of the last mask pass
     uint32_t *totals = nullptr;    // changed-probe totals of the last scan
     int2 *tiles2 = nullptr;        // per-tile second-last changed probes
-    uint32_t *partial = nullptr;   // per-tile checksum shares
+    unsigned long long *cks = nullptr;  // checksum counters (zero between packs)
     uint32_t *tsum = nullptr;      // per-tile own summaries
     uint8_t *packet = nullptr;
     uint64_t packet_cap = 0;
@@ -1153,7 +1153,7 @@ static void free_client(pv_client *c) {
     hipFree(c->tiles);
     hipFree(c->totals);
     hipFree(c->tiles2);
-    hipFree(c->partial);
+    hipFree(c->cks);
     hipFree(c->tsum);
     hipFree(c->packet);
     hipFree(c->view);
@@ -1188,7 +1188,7 @@ extern "C" pv_status pv_client_create(pv_volume *v, uint32_t id, pv_client **out
     if (st == PV_OK) st = dev_alloc(&c->tiles, (size_t)(P + kPackTile - 1) / kPackTile * sizeof(int4), "tile summaries");
     if (st == PV_OK) st = dev_alloc(&c->totals, 4 * sizeof(uint32_t), "pack totals");
     if (st == PV_OK) st = dev_alloc(&c->tiles2, (size_t)(P + kPackTile - 1) / kPackTile * sizeof(int2), "tile summaries");
-    if (st == PV_OK) st = dev_alloc(&c->partial, (size_t)(P + kPackTile - 1) / kPackTile * 4, "pack checksum shares");
+    if (st == PV_OK) st = dev_alloc(&c->cks, kCksBytes, "pack checksum counters");
     if (st == PV_OK) st = dev_alloc(&c->tsum, (size_t)(P + kPackTile - 1) / kPackTile * 4, "tile summaries");
     if (st == PV_OK) st = dev_alloc(&c->packet, c->packet_cap, "packet");
     if (st == PV_OK) st = dev_alloc(&c->view, (size_t)P, "client view");
@@ -1199,6 +1199,7 @@ extern "C" pv_status pv_client_create(pv_volume *v, uint32_t id, pv_client **out
                         launch_zero(c->mask_irr, (size_t)P, s) != hipSuccess ||
                         launch_zero(c->mask_vis, (size_t)P, s) != hipSuccess ||
                         launch_zero(c->packet, 32, s) != hipSuccess ||
+                        launch_zero(c->cks, kCksBytes, s) != hipSuccess ||
                         hipStreamSynchronize(s) != hipSuccess))
         st = fail(PV_ERR_DEVICE, "client initialisation");
     if (st != PV_OK) {
@@ -1243,7 +1244,7 @@ extern "C" pv_status pv_pack_delta(pv_client *c, float tau_irr, float tau_vis, v
     b.tiles = c->tiles;
     b.totals = c->totals;
     b.tiles2 = c->tiles2;
-    b.partial = c->partial;
+    b.cks = c->cks;
     b.tsum = c->tsum;
     b.packet = c->packet;
     b.active = v->active;
@@ -1254,8 +1255,6 @@ extern "C" pv_status pv_pack_delta(pv_client *c, float tau_irr, float tau_vis, v
     HIP_TRY(timed(cx, PV_STAGE_PACK_MASK, s, [&] { return launch_pack_mask(b, P, tau_irr, tau_vis, s); }));
     if (!pack_fused(P)) HIP_TRY(timed(cx, PV_STAGE_PACK_SCAN, s, [&] { return launch_pack_scan(b, P, s); }));
     HIP_TRY(timed(cx, PV_STAGE_PACK_COMPACT, s, [&] { return launch_pack_compact(b, P, id, seq, s); }));
-    if (!pack_atomic_checksum((P + kPackTile - 1) / kPackTile))
-        HIP_TRY(timed(cx, PV_STAGE_PACK_FINISH, s, [&] { return launch_pack_checksum(b, P, s); }));
     c->seq++;
     return PV_OK;
 }
