@@ -8,24 +8,25 @@
 namespace pv {
 
 constexpr int kDirThreads = 256;
-static_assert(kDirThreads == 256, "a weight-table block is four wavefronts, one row tile each");
+static_assert(kDirThreads == 256, "a weight-table block is four wavefronts sharing one row tile");
 
 __host__ __device__ inline int dir_blocks(int n) { return (n + kDirThreads - 1) / kDirThreads; }
 __host__ __device__ inline int table_blocks(int mode) {
-    return (mode == kBlendBF16x3 || mode == kBlendF32 || mode == kBlendVALU) ? kMTiles / 4 : 0;
+    return (mode == kBlendBF16x3 || mode == kBlendF32 || mode == kBlendVALU) ? kMTiles : 0;
 }
 
 // Blocks [0, dir_blocks): one thread per ray direction; the next
-// table_blocks(mode) blocks: the weight table after the directions (four
-// row tiles each). queue: the work counters of the trace that follows,
+// table_blocks(mode) blocks: the weight table after the directions (one
+// row tile each). queue: the work counters of the trace that follows,
 // zeroed here.
 __global__ __launch_bounds__(kDirThreads) void k_raydirs(FrameParams fp, int n, float4 *dirs, int *queue, int mode,
                                                          int sharp) {
     __shared__ float3 sdir[PV_MAX_RAYS];
+    __shared__ float red[64];
     const int db = dir_blocks(n);
     if ((int)blockIdx.x >= db) {
         weight_table_block(fp, n, sharp, mode, reinterpret_cast<uint8_t *>(dirs) + dirs_span(n), blockIdx.x - db,
-                           sdir);
+                           sdir, red);
         return;
     }
     if (queue && blockIdx.x == 0 && threadIdx.x < 9) queue[threadIdx.x * kQueueStride] = 0;
@@ -38,6 +39,7 @@ __global__ __launch_bounds__(kDirThreads) void k_raydirs(FrameParams fp, int n, 
 __global__ __launch_bounds__(kDirThreads) void k_raydirs_batched(const BatchVolume *vols, const FrameParams *frames,
                                                                  int n_vols) {
     __shared__ float3 sdir[PV_MAX_RAYS];
+    __shared__ float red[64];
     const int v = blockIdx.y;
     if (v >= n_vols) return;
     const BatchVolume &bv = vols[v];
@@ -46,7 +48,7 @@ __global__ __launch_bounds__(kDirThreads) void k_raydirs_batched(const BatchVolu
         if ((int)blockIdx.x - db < table_blocks(bv.vp.blend_mode))
             weight_table_block(frames[v], n, bv.vp.vis_sharpness, bv.vp.blend_mode,
                                reinterpret_cast<uint8_t *>(const_cast<float4 *>(bv.dirs)) + dirs_span(n),
-                               blockIdx.x - db, sdir);
+                               blockIdx.x - db, sdir, red);
         return;
     }
     const int j = blockIdx.x * kDirThreads + threadIdx.x;
@@ -70,12 +72,28 @@ __global__ __launch_bounds__(kBlendThreads) void k_blend(VolumeParams vp, const 
 // per grouping, so that the small groups are not held to the registers of
 // the large ones).
 template <typename T, int MODE, int G>
-__global__ __launch_bounds__(64 * G) void k_blend_gemm(VolumeParams vp, const float4 *dirs, const float4 *rays, T *irr,
-                                                       T *vis, float h) {
+__device__ __forceinline__ void blend_gemm_grid(const VolumeParams &vp, const float4 *dirs, const float4 *rays, T *irr,
+                                                T *vis, float h) {
     __shared__ BlendSmemGemm<T> sm;
     const int cg = xcd_logical_block();
     if (cg >= blend_column_groups(vp.P)) return;
     blend_gemm_block<T, MODE, G>(vp, dirs, rays, irr, vis, h, cg, sm);
+}
+
+template <typename T, int MODE, int G>
+__global__ __launch_bounds__(64 * G) void k_blend_gemm(VolumeParams vp, const float4 *dirs, const float4 *rays, T *irr,
+                                                       T *vis, float h) {
+    blend_gemm_grid<T, MODE, G>(vp, dirs, rays, irr, vis, h);
+}
+
+// Binary16 maps in four-wavefront blocks (the large volumes): at most 128
+// registers per lane, so that four wavefronts share a SIMD and every block
+// of the encode-size grid is resident at once (the FP32 image's LDS allows
+// two blocks per CU whatever the registers).
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_blend_gemm_h4(
+    VolumeParams vp, const float4 *dirs, const float4 *rays, __half *irr, __half *vis, float h) {
+    blend_gemm_grid<__half, MODE, 4>(vp, dirs, rays, irr, vis, h);
 }
 
 hipError_t launch_raydirs(const FrameParams &fp, const VolumeParams &vp, float4 *dirs, int *queue, hipStream_t s) {
@@ -96,6 +114,17 @@ int blend_blocks(int P, int mode) {
     return blend_column_groups(P);
 }
 
+template <typename T, int MODE>
+static void launch_gemm(bool g4, dim3 grid, const VolumeParams &vp, const float4 *dirs, const float4 *rays, T *irr,
+                        T *vis, float h, hipStream_t s) {
+    if (!g4)
+        hipLaunchKernelGGL((k_blend_gemm<T, MODE, 8>), grid, dim3(512), 0, s, vp, dirs, rays, irr, vis, h);
+    else if constexpr (std::is_same_v<T, __half>)
+        hipLaunchKernelGGL((k_blend_gemm_h4<MODE>), grid, dim3(256), 0, s, vp, dirs, rays, irr, vis, h);
+    else
+        hipLaunchKernelGGL((k_blend_gemm<T, MODE, 4>), grid, dim3(256), 0, s, vp, dirs, rays, irr, vis, h);
+}
+
 template <typename T>
 static hipError_t launch_blend_t(const VolumeParams &vp, const float4 *dirs, const float4 *rays, T *irr, T *vis,
                                  float h, hipStream_t s) {
@@ -103,22 +132,13 @@ static hipError_t launch_blend_t(const VolumeParams &vp, const float4 *dirs, con
     const bool g4 = blend_row_groups(vp.P) == 4;
     switch (vp.blend_mode) {
     case kBlendBF16x3:
-        if (g4)
-            hipLaunchKernelGGL((k_blend_gemm<T, kBlendBF16x3, 4>), grid, dim3(256), 0, s, vp, dirs, rays, irr, vis, h);
-        else
-            hipLaunchKernelGGL((k_blend_gemm<T, kBlendBF16x3, 8>), grid, dim3(512), 0, s, vp, dirs, rays, irr, vis, h);
+        launch_gemm<T, kBlendBF16x3>(g4, grid, vp, dirs, rays, irr, vis, h, s);
         break;
     case kBlendF32:
-        if (g4)
-            hipLaunchKernelGGL((k_blend_gemm<T, kBlendF32, 4>), grid, dim3(256), 0, s, vp, dirs, rays, irr, vis, h);
-        else
-            hipLaunchKernelGGL((k_blend_gemm<T, kBlendF32, 8>), grid, dim3(512), 0, s, vp, dirs, rays, irr, vis, h);
+        launch_gemm<T, kBlendF32>(g4, grid, vp, dirs, rays, irr, vis, h, s);
         break;
     case kBlendVALU:
-        if (g4)
-            hipLaunchKernelGGL((k_blend_gemm<T, kBlendVALU, 4>), grid, dim3(256), 0, s, vp, dirs, rays, irr, vis, h);
-        else
-            hipLaunchKernelGGL((k_blend_gemm<T, kBlendVALU, 8>), grid, dim3(512), 0, s, vp, dirs, rays, irr, vis, h);
+        launch_gemm<T, kBlendVALU>(g4, grid, vp, dirs, rays, irr, vis, h, s);
         break;
     default:
         hipLaunchKernelGGL(k_blend<T>, grid, dim3(kBlendThreads), 0, s, vp, dirs, rays, irr, vis, h);

@@ -26,6 +26,8 @@
 // D[4(l/16) + r][l%16] in accumulator register r.
 #pragma once
 
+#include <type_traits>
+
 #include "blend_device.h"
 
 namespace pv {
@@ -47,25 +49,25 @@ __device__ __forceinline__ float3 row_dir(int m) {
     return m < 64 ? oct_texel_dir(8, m & 7, m >> 3) : oct_texel_dir(16, (m - 64) & 15, (m - 64) >> 4);
 }
 
-// Table rows of one 16-row tile by one wavefront of a 256-thread block:
-// the block first puts all n directions of the frame into LDS (the same FP32
-// values as the direction kernel), then every wavefront evaluates its own
-// tile's weights; the row totals are each lane's partial sum, then the sum
-// across the four lanes of a row (a fixed order, so every run gives the
-// same totals).
+// Table rows of one 16-row tile by a 256-thread block: the block first puts
+// all n directions of the frame into LDS (the same FP32 values as the
+// direction kernel), then wavefront w evaluates the tile's weights of steps
+// w, w + 4, ...; the row totals are each lane's partial sum, the sum across
+// the four lanes of a row, then the four wavefronts' sums in order (a fixed
+// order, so every run gives the same totals). red: 64 floats of LDS.
 template <int S>
 __device__ void weight_tile_block(const FrameParams &fp, int n, int sharp, int mode, uint8_t *tab, int mt,
-                                  float3 *sdir) {
+                                  float3 *sdir, float *red) {
     for (int j = threadIdx.x; j < n; j += blockDim.x) sdir[j] = xyz(raydir(fp, n, j));
     __syncthreads();
     if (mt >= kMTiles) return;
-    const int lane = threadIdx.x & 63, q = lane & 15, kq = lane >> 4;
+    const int lane = threadIdx.x & 63, q = lane & 15, kq = lane >> 4, wv = threadIdx.x >> 6;
     const int m = 16 * mt + q;
     const bool vis_row = m >= 64;
     const float3 om = row_dir(m);
     const int steps = (n + kWStep - 1) / kWStep;
     float sum = 0.f;
-    for (int s = 0; s < steps; ++s) {
+    for (int s = wv; s < steps; s += 4) {
         uint4 *dst = reinterpret_cast<uint4 *>(tab + (((size_t)s * kMTiles + mt) * 64 + lane) * 32);
         if (mode == kBlendBF16x3) {
             unsigned short hi[8], lo[8];
@@ -108,17 +110,20 @@ __device__ void weight_tile_block(const FrameParams &fp, int n, int sharp, int m
     }
     sum += __shfl_xor(sum, 16);
     sum += __shfl_xor(sum, 32);
-    if (kq == 0) reinterpret_cast<float *>(tab + wtab_steps(n) * kMTiles * 64 * 32)[m] = sum;
+    if (kq == 0) red[wv * 16 + q] = sum;
+    __syncthreads();
+    if (threadIdx.x < 16)
+        reinterpret_cast<float *>(tab + wtab_steps(n) * kMTiles * 64 * 32)[16 * mt + threadIdx.x] =
+            ((red[threadIdx.x] + red[16 + threadIdx.x]) + red[32 + threadIdx.x]) + red[48 + threadIdx.x];
 }
 
-// One table block (four row tiles) of the direction launch.
+// One table block (one row tile) of the direction launch.
 __device__ __forceinline__ void weight_table_block(const FrameParams &fp, int n, int sharp, int mode, uint8_t *tab,
-                                                   int wblock, float3 *sdir) {
-    const int mt = 4 * wblock + (threadIdx.x >> 6);
+                                                   int mt, float3 *sdir, float *red) {
     if (sharp == 50)
-        weight_tile_block<50>(fp, n, sharp, mode, tab, mt, sdir);
+        weight_tile_block<50>(fp, n, sharp, mode, tab, mt, sdir, red);
     else
-        weight_tile_block<0>(fp, n, sharp, mode, tab, mt, sdir);
+        weight_tile_block<0>(fp, n, sharp, mode, tab, mt, sdir, red);
 }
 
 __device__ __forceinline__ const uint8_t *weight_table(const float4 *dirs, int n) {
@@ -128,18 +133,6 @@ __device__ __forceinline__ const uint8_t *weight_table(const float4 *dirs, int n
 // ---------------------------------------------------------------------------
 // the product
 // ---------------------------------------------------------------------------
-// High and low BF16 halves of eight values.
-__device__ __forceinline__ void split8(const float *x, bf16x8 &hi, bf16x8 &lo) {
-    u16x8 h, l;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        h[i] = bf16_bits(x[i]);
-        l[i] = bf16_bits(x[i] - bf16_value(h[i]));
-    }
-    hi = __builtin_bit_cast(bf16x8, h);
-    lo = __builtin_bit_cast(bf16x8, l);
-}
-
 // Channel c of a ray record: radiance r, g, b (c < 3), distance, distance^2.
 __device__ __forceinline__ float channel(float4 r, int c) {
     return c == 0 ? r.x : c == 1 ? r.y : c == 2 ? r.z : c == 3 ? r.w : r.w * r.w;
@@ -185,19 +178,27 @@ struct BlendImage {
     T v[kIrrElems + kVisElems];
 };
 
+// BF16x3 records of one step, split once per block at staging: per buffer,
+// channel (r, g, b, distance, distance^2), half (high, low) and probe, the
+// 32 rays as 16 words of two BF16 values (ray 2w in the low half), so that
+// a lane's operand (rays 8 kq .. 8 kq + 7 of probe q) is one aligned
+// 16-byte read and a wavefront's 64 reads cover 1 KB without conflicts.
+struct BlendRecsBF {
+    uint32_t w[2][5][2][16][kWStep / 2];
+};
+
 template <typename T>
 union BlendSmemGemm {
     BlendRecs recs;
+    BlendRecsBF bf;
     BlendImage<T> img;
 };
 
-// Tile element e of an (N + 2)^2 tile -> the element whose value it holds:
-// itself inside, across an edge the interior texel the octahedral fold puts
-// next to it (rows first, then columns, which also maps the corners to the
-// diagonally opposite interior corner).
-__device__ __forceinline__ int guard_source(int N, int e) {
-    const int S = N + 2;
-    int y = e / S, x = e - y * S;
+// Tile element (y, x) of an (N + 2)^2 tile -> the element whose value it
+// holds: itself inside, across an edge the interior texel the octahedral
+// fold puts next to it (rows first, then columns, which also maps the
+// corners to the diagonally opposite interior corner).
+__device__ __forceinline__ int guard_source(int N, int y, int x) {
     if (y == 0 || y == N + 1) {
         y = y == 0 ? 1 : N;
         x = N + 1 - x;
@@ -206,46 +207,115 @@ __device__ __forceinline__ int guard_source(int N, int e) {
         x = x == 0 ? 1 : N;
         y = N + 1 - y;
     }
-    return y * S + x;
+    return y * (N + 2) + x;
 }
 
-// Copies between the maps and the block's LDS image in 16-byte chunks
-// (probes p0 .. p0 + np - 1; to_lds: load the stored tiles, else write the
-// image out with every guard texel taken from its interior source).
-template <typename T>
-__device__ __forceinline__ void image_copy(T *irr, T *vis, int p0, int np, BlendImage<T> &img, bool to_lds) {
+// Guard texels of one texture of the block's LDS image: tile k (of
+// n_tiles, (N + 2)^2 elements each from 'base'), border element g (G = 4N + 4
+// per tile: the top row, the bottom row, then the left and right columns
+// between them) takes the value of its interior source. Only guard texels
+// are written and only interiors read.
+template <typename T, int N>
+__device__ __forceinline__ void fill_guards(T *base, int n_tiles) {
+    constexpr int S = N + 2, G = 4 * N + 4;
+    for (int i = threadIdx.x; i < n_tiles * G; i += blockDim.x) {
+        const int k = i / G, g = i - k * G;
+        int y, x;
+        if (g < 2 * S) {
+            y = g < S ? 0 : S - 1;
+            x = g < S ? g : g - S;
+        } else {
+            const int r = g - 2 * S;
+            x = r < N ? 0 : S - 1;
+            y = 1 + (r < N ? r : r - N);
+        }
+        T *tile = base + k * S * S;
+        tile[y * S + x] = tile[guard_source(N, y, x)];
+    }
+}
+
+// Moves the tiles of probes p0 .. p0 + np - 1 between the maps and the
+// block's LDS image in 16-byte chunks, U per thread in flight (to_lds: load
+// the stored tiles; else write the image out whole). An odd probe count
+// leaves half a chunk of binary16 irradiance (648 elements per probe are
+// always whole chunks).
+template <typename T, bool TO_LDS, int U>
+__device__ __forceinline__ void image_move(T *irr, T *vis, int p0, int np, BlendImage<T> &img) {
     constexpr int kPer = 16 / (int)sizeof(T);
-    // whole chunks; an odd probe count leaves half a chunk of binary16
-    // irradiance (648 elements per probe are always whole chunks)
-    const int ni = np * 300 / kPer, nv = np * 648 / kPer;
+    static_assert(U == 2 || U == 4, "two or four chunks in flight");
+    const int ni = np * 300 / kPer, nc = ni + np * 648 / kPer;
     const int tail = np * 300 - ni * kPer;
-    if (threadIdx.x < tail) {
-        const int e = ni * kPer + threadIdx.x, tile = e / 100;
-        if (to_lds)
+    if ((int)threadIdx.x < tail) {
+        const int e = ni * kPer + threadIdx.x;
+        if (TO_LDS)
             img.v[e] = irr[(size_t)p0 * 300 + e];
         else
-            irr[(size_t)p0 * 300 + e] = img.v[tile * 100 + guard_source(8, e - tile * 100)];
+            irr[(size_t)p0 * 300 + e] = img.v[e];
     }
     uint4 *gi = reinterpret_cast<uint4 *>(irr + (size_t)p0 * 300), *gv = reinterpret_cast<uint4 *>(vis + (size_t)p0 * 648);
     uint4 *li = reinterpret_cast<uint4 *>(img.v), *lv = reinterpret_cast<uint4 *>(img.v + BlendImage<T>::kIrrElems);
-    for (int c = threadIdx.x; c < ni + nv; c += blockDim.x) {
-        const bool is_vis = c >= ni;
-        const int cc = is_vis ? c - ni : c;
-        if (to_lds) {
-            (is_vis ? lv : li)[cc] = (is_vis ? gv : gi)[cc];
-            continue;
+    // chunk c of the source and of the destination (irradiance chunks
+    // first); each side stays in its own address space
+    auto get = [&](int c) -> uint4 {
+        if constexpr (TO_LDS)
+            return c < ni ? gi[c] : gv[c - ni];
+        else
+            return c < ni ? li[c] : lv[c - ni];
+    };
+    auto put = [&](int c, uint4 x) {
+        if constexpr (TO_LDS) {
+            if (c < ni)
+                li[c] = x;
+            else
+                lv[c - ni] = x;
+        } else {
+            if (c < ni)
+                gi[c] = x;
+            else
+                gv[c - ni] = x;
         }
-        const int S2 = is_vis ? 324 : 100, N = is_vis ? 16 : 8;
-        const T *base = is_vis ? img.v + BlendImage<T>::kIrrElems : img.v;
-        T out[kPer];
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = cc * kPer + u, tile = e / S2;
-            out[u] = base[tile * S2 + guard_source(N, e - tile * S2)];
-        }
-        (is_vis ? gv : gi)[cc] = *reinterpret_cast<const uint4 *>(out);
+    };
+    for (int c0 = threadIdx.x; c0 < nc; c0 += U * blockDim.x) {
+        const int c1 = c0 + blockDim.x, c2 = c1 + blockDim.x, c3 = c2 + blockDim.x;
+        const uint4 x0 = get(c0);
+        const uint4 x1 = c1 < nc ? get(c1) : uint4{};
+        const uint4 x2 = U == 4 && c2 < nc ? get(c2) : uint4{};
+        const uint4 x3 = U == 4 && c3 < nc ? get(c3) : uint4{};
+        put(c0, x0);
+        if (c1 < nc) put(c1, x1);
+        if (U == 4 && c2 < nc) put(c2, x2);
+        if (U == 4 && c3 < nc) put(c3, x3);
     }
 }
+
+// Prefetch of step s's records for the BF16x3 product: thread t < 256 takes
+// rays 2 (t % 16) and 2 (t % 16) + 1 of probe t / 16 (32 contiguous bytes),
+// and at staging writes both rays' high and low BF16 halves of every channel
+// (the same split as the weights: x = hi + lo + O(2^-18 x)).
+struct RecPrefetchBF {
+    float4 v[2];
+    __device__ __forceinline__ void load(const float4 *rays, int n, int P, int cg, int s) {
+        const int t = threadIdx.x, qq = t >> 4, k = 2 * (t & 15);
+        const int p = 16 * cg + qq, j = s * kWStep + k;
+        const bool ok = t < 256 && p < P;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            v[u] = (ok && j + u < n) ? rays[(size_t)p * n + j + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __device__ __forceinline__ void store(BlendRecsBF &sm, int buf) const {
+        const int t = threadIdx.x;
+        if (t >= 256) return;
+        const int qq = t >> 4, w = t & 15;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const float x0 = channel(v[0], c), x1 = channel(v[1], c);
+            const unsigned short h0 = bf16_bits(x0), h1 = bf16_bits(x1);
+            const unsigned short l0 = bf16_bits(x0 - bf16_value(h0)), l1 = bf16_bits(x1 - bf16_value(h1));
+            sm.w[buf][c][0][qq][w] = (uint32_t)h0 | (uint32_t)h1 << 16;
+            sm.w[buf][c][1][qq][w] = (uint32_t)l0 | (uint32_t)l1 << 16;
+        }
+    }
+};
 
 // Prefetch of step s's records by the block's NT threads into registers.
 template <int NT>
@@ -279,6 +349,7 @@ template <typename T, int MODE, int NT, int I0, int NI, int V0, int NV>
 __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, const float4 *rays, T *irr, T *vis,
                                  float h, int cg, BlendSmemGemm<T> &smu) {
     BlendRecs &sm = smu.recs;
+    BlendRecsBF &sb = smu.bf;
     using TS = TileSet<I0, NI, V0, NV>;
     constexpr int RT = TS::kRowTiles, NC = TS::kChannels, C0 = TS::kC0;
     const int lane = threadIdx.x & 63, q = lane & 15, kq = lane >> 4;
@@ -290,9 +361,15 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
     TS ts;
 #pragma unroll
     for (int t = 0; t < TS::kTiles; ++t) ts.acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-    RecPrefetch<NT> pf;
+    // records through LDS: split into BF16 halves at staging for BF16x3,
+    // else whole FP32 records
+    using PF = std::conditional_t<MODE == kBlendBF16x3, RecPrefetchBF, RecPrefetch<NT>>;
+    PF pf;
     pf.load(rays, n, P, cg, 0);
-    pf.store(sm, 0);
+    if constexpr (MODE == kBlendBF16x3)
+        pf.store(sb, 0);
+    else
+        pf.store(sm, 0);
     __syncthreads();
     // weight fragments of every row tile of the wavefront for the current
     // step, requested at the step's start (a second set for the next step
@@ -342,19 +419,23 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
                 }
             }
         } else {
-            // the step's operand fragments: BF16x3 rays 8 kq .. 8 kq + 7, F32
-            // ray 4 i + kq of probe q
+            // the step's operand fragments: BF16x3 rays 8 kq .. 8 kq + 7 (high
+            // and low halves, staged split), F32 ray 4 i + kq of probe q
             bf16x8 bh[NC], bl[NC];
             float bf[NC][8];
+            if constexpr (MODE == kBlendBF16x3) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const float4 r = sm.r[buf][q][MODE == kBlendBF16x3 ? 8 * kq + i : 4 * i + kq];
+                for (int c = 0; c < NC; ++c) {
+                    bh[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&sb.w[buf][C0 + c][0][q][4 * kq]));
+                    bl[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&sb.w[buf][C0 + c][1][q][4 * kq]));
+                }
+            } else {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) bf[c][i] = channel(r, C0 + c);
-            }
-            if (MODE == kBlendBF16x3) {
+                for (int i = 0; i < 8; ++i) {
+                    const float4 r = sm.r[buf][q][4 * i + kq];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) split8(bf[c], bh[c], bl[c]);
+                    for (int c = 0; c < NC; ++c) bf[c][i] = channel(r, C0 + c);
+                }
             }
             // the products, ordered so that consecutive matrix instructions
             // feed different accumulators (each accumulator still takes its
@@ -401,8 +482,10 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
         }
         // every wavefront is done with the other buffer since the last step's barrier
         if (s + 1 < steps) {
-            pf.store(sm, buf ^ 1);
-
+            if constexpr (MODE == kBlendBF16x3)
+                pf.store(sb, buf ^ 1);
+            else
+                pf.store(sm, buf ^ 1);
         }
         __syncthreads();
     }
@@ -410,11 +493,11 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
     // stored tiles are loaded (coalesced), each wavefront replaces its
     // interior texels by the new values (estimate = sum / row total,
     // hysteresis, the map's rounding; a texel whose total is at most the
-    // floor keeps its value), and the tiles are written back whole, guard
-    // texels copied from their interior sources
+    // floor keeps its value), the guard texels are copied from their
+    // interior sources in LDS, and the tiles are written back whole
     BlendImage<T> &img = smu.img;
     const int np = min(16, P - 16 * cg);
-    image_copy<T>(irr, vis, 16 * cg, np, img, true);
+    image_move<T, true, 1024 / NT>(irr, vis, 16 * cg, np, img);
     __syncthreads();
     const float *rows = reinterpret_cast<const float *>(tab + wtab_steps(n) * kMTiles * 64 * 32);
     if (live) {
@@ -443,7 +526,10 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
         }
     }
     __syncthreads();
-    image_copy<T>(irr, vis, 16 * cg, np, img, false);
+    fill_guards<T, 8>(img.v, 3 * np);
+    fill_guards<T, 16>(img.v + BlendImage<T>::kIrrElems, 2 * np);
+    __syncthreads();
+    image_move<T, false, 1024 / NT>(irr, vis, 16 * cg, np, img);
 }
 
 // Row groups of a volume's blend: G row-group wavefronts per 16-probe column
