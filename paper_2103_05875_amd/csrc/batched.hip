@@ -93,6 +93,41 @@ __device__ __forceinline__ void blend_batched_block(const BatchVolume &bv, int l
         blend_gemm_block<T, kBlendF32, 4>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, local, g);
 }
 
+// Batches whose maps share one type and whose volumes use the automatic
+// blend modes (per-tile below the table's break-even, the FP32 table from
+// there): only those two paths are compiled in, so the launch holds their
+// registers instead of every path's (228 per lane: two wavefronts per SIMD).
+// Binary16 maps: at most 128 registers, four wavefronts per SIMD.
+template <typename T>
+union AutoBlendSmem {
+    BlendSmem tiles;
+    BlendSmemGemm<T> gemm;
+};
+
+template <typename T>
+__device__ __forceinline__ void blend_batched_auto(const BatchVolume *vols, int n_vols, AutoBlendSmem<T> &sm) {
+    const int g = xcd_logical_block();
+    const int v = __builtin_amdgcn_readfirstlane(find_volume<true>(vols, n_vols, g));
+    const BatchVolume &bv = vols[v];
+    const int local = g - bv.first_blend;
+    if (bv.vp.blend_mode == kBlendTiles)
+        blend_tile_any<T>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, (local / kBlendSplit) * kBlendTile,
+                          local % kBlendSplit, sm.tiles);
+    else
+        blend_gemm_block<T, kBlendF32, 4>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, local, sm.gemm);
+}
+
+__global__ __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_blend_batched_auto_h(
+    const BatchVolume *vols, int n_vols) {
+    __shared__ AutoBlendSmem<__half> sm;
+    blend_batched_auto<__half>(vols, n_vols, sm);
+}
+
+__global__ __launch_bounds__(kBlendThreads) void k_blend_batched_auto_f(const BatchVolume *vols, int n_vols) {
+    __shared__ AutoBlendSmem<float> sm;
+    blend_batched_auto<float>(vols, n_vols, sm);
+}
+
 __global__ __launch_bounds__(kBlendThreads) void k_blend_batched(const BatchVolume *vols, int n_vols) {
     __shared__ BatchedBlendSmem sm;
     const int g = xcd_logical_block();
@@ -117,8 +152,13 @@ hipError_t launch_trace_batched(const BatchVolume *vols_dev, int n_vols, int tot
     return hipGetLastError();
 }
 
-hipError_t launch_blend_batched(const BatchVolume *vols_dev, int n_vols, int total_blend, hipStream_t s) {
-    hipLaunchKernelGGL(k_blend_batched, dim3(total_blend), dim3(kBlendThreads), 0, s, vols_dev, n_vols);
+hipError_t launch_blend_batched(const BatchVolume *vols_dev, int n_vols, int total_blend, int kind, hipStream_t s) {
+    if (kind == kBatchBlendAutoHalf)
+        hipLaunchKernelGGL(k_blend_batched_auto_h, dim3(total_blend), dim3(kBlendThreads), 0, s, vols_dev, n_vols);
+    else if (kind == kBatchBlendAutoFloat)
+        hipLaunchKernelGGL(k_blend_batched_auto_f, dim3(total_blend), dim3(kBlendThreads), 0, s, vols_dev, n_vols);
+    else
+        hipLaunchKernelGGL(k_blend_batched, dim3(total_blend), dim3(kBlendThreads), 0, s, vols_dev, n_vols);
     return hipGetLastError();
 }
 

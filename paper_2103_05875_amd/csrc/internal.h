@@ -81,7 +81,10 @@ hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4
 // device; each volume's first_wave a multiple of 4).
 hipError_t launch_trace_batched(const BatchVolume *vols_dev, int n_vols, int total_waves, const FrameParams *frames_dev,
                                 bool short_stack, int max_top, hipStream_t s);
-hipError_t launch_blend_batched(const BatchVolume *vols_dev, int n_vols, int total_blend, hipStream_t s);
+// Which batched blend kernel a batch takes: every path and map type, or one
+// map type with the automatic modes only (per-tile and the FP32 table).
+enum : int { kBatchBlendAny = 0, kBatchBlendAutoHalf = 1, kBatchBlendAutoFloat = 2 };
+hipError_t launch_blend_batched(const BatchVolume *vols_dev, int n_vols, int total_blend, int kind, hipStream_t s);
 hipError_t launch_raydirs_batched(const BatchVolume *vols_dev, const FrameParams *frames_dev, int n_vols,
                                   int dir_blocks, hipStream_t s);
 

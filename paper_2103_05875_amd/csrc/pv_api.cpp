@@ -906,6 +906,7 @@ struct pv_batch_graph {
     BatchSlot slot;           // device descriptors + pinned staging owned by the graph
     size_t o_b = 0, o_f = 0, bytes = 0;
     int waves = 0, blend = 0, bounce = 0, classify = 0, dir_blocks = 0;
+    int blend_kind = kBatchBlendAny;  // the captured blend kernel (kBatchBlend*)
     bool short_stack = true;
     int max_top = 0;
     hipGraph_t graph = nullptr;
@@ -984,6 +985,19 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
     return PV_OK;
 }
 
+// The batched blend kernel for these volumes (kBatchBlend*).
+static int batch_blend_kind(pv_volume *const *vols, int n) {
+    bool half = true, flt = true;
+    for (int i = 0; i < n; ++i) {
+        const int m = vols[i]->blend_mode;
+        if (m != kBlendTiles && m != kBlendF32) return kBatchBlendAny;
+        const bool h = vols[i]->desc.format == PV_MAP_FP16;
+        half = half && h;
+        flt = flt && !h;
+    }
+    return half ? kBatchBlendAutoHalf : flt ? kBatchBlendAutoFloat : kBatchBlendAny;
+}
+
 static pv_status check_batch(pv_volume *const *vols, int n, pv_ctx **ctx) {
     if (!vols || n < 1) return fail(PV_ERR_ARG, "need at least one volume");
     pv_ctx *c = vols[0] ? vols[0]->ctx : nullptr;
@@ -1024,7 +1038,8 @@ extern "C" pv_status pv_update_probes_batched(pv_volume *const *vols, const pv_f
         HIP_TRY(timed(c, PV_STAGE_SELECT, s, [&] { return launch_classify_batched(slot.batch_dev, n, classify, s); }));
     if (bounce > 0)
         HIP_TRY(timed(c, PV_STAGE_BOUNCE, s, [&] { return launch_bounce_batched(slot.batch_dev, n, bounce, s); }));
-    HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend_batched(slot.batch_dev, n, blend, s); }));
+    const int kind = batch_blend_kind(vols, n);
+    HIP_TRY(timed(c, PV_STAGE_BLEND, s, [&] { return launch_blend_batched(slot.batch_dev, n, blend, kind, s); }));
     HIP_TRY(hipEventRecord(slot.done, s));
     for (int i = 0; i < n; ++i) {
         PV_TRY(note_scene_use(vols[i]->scene, s));
@@ -1078,7 +1093,8 @@ extern "C" pv_status pv_batch_graph_create(pv_volume *const *vols, int n, pv_bat
     if (e == hipSuccess) e = launch_trace_batched(b.batch_dev, n, g->waves, b.frames_dev, g->short_stack, g->max_top, cs);
     if (e == hipSuccess && g->classify > 0) e = launch_classify_batched(b.batch_dev, n, g->classify, cs);
     if (e == hipSuccess && g->bounce > 0) e = launch_bounce_batched(b.batch_dev, n, g->bounce, cs);
-    if (e == hipSuccess) e = launch_blend_batched(b.batch_dev, n, g->blend, cs);
+    g->blend_kind = batch_blend_kind(vols, n);
+    if (e == hipSuccess) e = launch_blend_batched(b.batch_dev, n, g->blend, g->blend_kind, cs);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &graph);
     if (e == hipSuccess) e = e2;
@@ -1113,8 +1129,9 @@ extern "C" pv_status pv_batch_graph_launch(pv_batch_graph *g, const pv_frame *fr
     PV_TRY(fill_batch(g->vols.data(), frames, n, (char *)g->slot.stage_host, offs, waves, blend, bounce, classify,
                       dir_blocks, short_stack, max_top));
     if (waves != g->waves || blend != g->blend || bounce != g->bounce || classify != g->classify ||
-        short_stack != g->short_stack || max_top != g->max_top)
-        return fail(PV_ERR_STATE, "a volume of the graph changed scene or trace shape since the graph was captured");
+        short_stack != g->short_stack || max_top != g->max_top || batch_blend_kind(g->vols.data(), n) != g->blend_kind)
+        return fail(PV_ERR_STATE,
+                    "a volume of the graph changed scene, trace shape or blend path since the graph was captured");
     hipStream_t s = pick(c, stream);
     HIP_TRY(timed(c, PV_STAGE_BATCHED, s, [&] { return hipGraphLaunch(g->exec, s); }));
     HIP_TRY(hipEventRecord(g->done, s));

@@ -606,12 +606,16 @@ def test_update_then_pack_round_trip(ps, ctx, O):
 
 
 # ------------------------------------------------------------------ batched = plain
-def test_batched_matches_plain_bitwise(ps, ctx, O):
+@pytest.mark.parametrize("maps", ["mixed", "fp16", "fp32", "fp16_bf16x3"])
+def test_batched_matches_plain_bitwise(ps, ctx, O, maps):
     """Six uneven volumes, three frames: the batched update equals the
     per-volume updates bit for bit; the batched volumes take different trace
     shapes (probe bricks, staged top nodes) of their own, the plain ones
-    other schedules."""
-    _say("batched vs plain, 6 uneven volumes, 3 frames")
+    other schedules. Map types and blend paths select the batched blend
+    kernel: mixed map types (every path compiled in), one map type with the
+    automatic paths (per-tile, and the FP32 table on the third volume), or a
+    split-BF16 volume among them (every path again)."""
+    _say(f"batched vs plain, 6 uneven volumes, 3 frames, maps {maps}")
     specs = [((4, 4, 4), 64, True, 2000), ((5, 3, 7), 128, True, 800), ((16, 2, 16), 256, True, 5000),
              ((1, 1, 1), 512, False, 300), ((8, 8, 4), 64, False, 1200), ((3, 3, 3), 1, True, 100)]
     shapes_b = [((8, 8, 1), 85), ((2, 4, 8), 0), ((16, 4, 1), 21), ((4, 4, 4), 85), ((8, 4, 2), 0), ((4, 4, 4), 21)]
@@ -621,6 +625,8 @@ def test_batched_matches_plain_bitwise(ps, ctx, O):
         sc_syn = synth.box_city(n_tris=nt, seed_layout=70 + i, seed_heights=80 + i, extent=16.0)
         sc = ps.Scene.from_synth(ctx, sc_syn)
         scenes.append(sc)
+        if maps != "mixed":
+            fp16 = maps != "fp32"
         cfg = synth.VolumeConfig(*g, (1.0, 0.3, 1.0), (2.0, 1.0, 2.0), n, fp16=fp16, max_distance=5.0,
                                  sky=(0.1, 0.15, 0.25))
         a, b = ps.Volume(ctx, cfg), ps.Volume(ctx, cfg)
@@ -628,6 +634,9 @@ def test_batched_matches_plain_bitwise(ps, ctx, O):
         b.set_scene(sc)
         a.set_trace_config(shapes_p[i][0], shapes_p[i][1], 21, 256, False)
         b.set_trace_config(shapes_b[i][0], 2, shapes_b[i][1], 256, False)
+        if i == 2 and maps != "mixed":
+            for v in (a, b):
+                v.set_blend_mode("bf16x3" if maps == "fp16_bf16x3" else "f32")
         plain.append(a)
         batched.append(b)
     for f in range(3):
