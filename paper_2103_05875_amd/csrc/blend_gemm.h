@@ -372,13 +372,26 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
         pf.store(sm, 0);
     __syncthreads();
     // weight fragments of every row tile of the wavefront for the current
-    // step, requested at the step's start (a second set for the next step
-    // would cost the registers of a third wavefront per SIMD)
-    uint4 acur[RT][2];
+    // step, requested at the step's start in four-wavefront blocks (a second
+    // set for the next step would cost the registers of a wavefront per
+    // SIMD on the encode-size grid); eight-wavefront blocks (small volumes,
+    // fewer blocks than resident slots) have registers to spare and request
+    // the next step's fragments with the next step's records, one step ahead
+    constexpr bool kAhead = NT == 512 && MODE != kBlendVALU;
+    uint4 acur[RT][2], anext[kAhead ? RT : 1][2];
+    if constexpr (kAhead) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) load_frag(tab, 0, TS::mtile(t), acur[t][0], acur[t][1]);
+    }
     for (int s = 0; s < steps; ++s) {
         const int buf = s & 1;
         if (s + 1 < steps) pf.load(rays, n, P, cg, s + 1);
-        if constexpr (MODE != kBlendVALU) {
+        if constexpr (kAhead) {
+            if (s + 1 < steps) {
+#pragma unroll
+                for (int t = 0; t < RT; ++t) load_frag(tab, s + 1, TS::mtile(t), anext[t][0], anext[t][1]);
+            }
+        } else if constexpr (MODE != kBlendVALU) {
 #pragma unroll
             for (int t = 0; t < RT; ++t) load_frag(tab, s, TS::mtile(t), acur[t][0], acur[t][1]);
         }
@@ -486,6 +499,13 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
                 pf.store(sb, buf ^ 1);
             else
                 pf.store(sm, buf ^ 1);
+            if constexpr (kAhead) {
+#pragma unroll
+                for (int t = 0; t < RT; ++t) {
+                    acur[t][0] = anext[t][0];
+                    acur[t][1] = anext[t][1];
+                }
+            }
         }
         __syncthreads();
     }
