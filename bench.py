@@ -709,7 +709,7 @@ def leg_blend_paths(ps, torch, reps: int = 20):
         torch.cuda.synchronize()
         R = synth.rotation(8, 0)
         row = {}
-        for mode in ("tiles", "f32", "bf16x3", "valu"):
+        for mode in ("tiles", "f32", "bf16x3", "valu", "bf16x6"):
             vol.set_blend_mode(mode)
             for _ in range(3):
                 vol.blend_rays(R, dev.data_ptr(), stream=stream)
@@ -724,7 +724,8 @@ def leg_blend_paths(ps, torch, reps: int = 20):
             ms = st["blend"][0] / max(st["blend"][1], 1)
             bytes_ = P * (16 * n + (192 + 512) * 2 + (300 + 648) * 2)
             flop = P * 1408 * n
-            peak = PEAK_BF16_MFMA / 3 if mode == "bf16x3" else PEAK_FP32_VECTOR
+            peak = (PEAK_BF16_MFMA / 3 if mode == "bf16x3" else PEAK_BF16_MFMA / 6 if mode == "bf16x6"
+                    else PEAK_FP32_VECTOR)
             row[mode] = {"ms": ms, "table_ms": st["raydirs"][0] / max(st["raydirs"][1], 1),
                          "hbm_frac": bytes_ / (ms / 1e3) / PEAK_HBM, "mfma_frac": flop / (ms / 1e3) / peak}
         out[name] = {"probes": P, "rays_per_probe": n, "paths": row}
@@ -1033,7 +1034,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "city: 16x8x16 probes, 256 rays/probe, 50k-triangle procedural city, FP16 maps, "
                                "moving light; step = full update + delta pack for one client (tau = 0)",
-                   "probes": P, "rays_per_probe": n, "triangles": scene.n_triangles},
+                   "probes": P, "rays_per_probe": n, "triangles": scene.n_triangles,
+                   "blend_path": vol.get_blend_mode()},
         "probes_per_s": P * 1e3 / ms_per_step,
         "trace_config": vol.get_trace_config(),
         "autotune": None if tuned is None else {"source": tuned["source"], "tried": tuned["tried"],

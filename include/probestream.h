@@ -483,12 +483,16 @@ typedef struct {
  * per term with FP32 accumulation (about 2^-16 relative per term).
  * PV_BLEND_F32: FP32 matrix cores. PV_BLEND_TILES: FP32 matrix cores with
  * the weights evaluated again by every 8-probe tile (no table).
- * PV_BLEND_VALU: the table on FP32 vector FMAs. PV_BLEND_AUTO (the default
- * of a new volume) resolves to PV_BLEND_TILES below 4,096 probes and to
- * PV_BLEND_F32 from there. Every path but PV_BLEND_BF16X3 meets the FP32
+ * PV_BLEND_VALU: the table on FP32 vector FMAs. PV_BLEND_BF16X6: BF16
+ * matrix cores, weights and records split into three BF16 parts (high,
+ * middle, low), the six products down to 2^-18 of the term with FP32
+ * accumulation (about 2^-25 relative per term). PV_BLEND_AUTO (the default
+ * of a new volume) resolves to PV_BLEND_TILES below 2,048 probes and to
+ * PV_BLEND_BF16X6 from there. Every path but PV_BLEND_BF16X3 meets the FP32
  * blend's 1e-5 bound. Takes effect from the next update; the mode is
  * reported as resolved. */
-enum { PV_BLEND_AUTO = 0, PV_BLEND_BF16X3 = 1, PV_BLEND_F32 = 2, PV_BLEND_TILES = 3, PV_BLEND_VALU = 4 };
+enum { PV_BLEND_AUTO = 0, PV_BLEND_BF16X3 = 1, PV_BLEND_F32 = 2, PV_BLEND_TILES = 3, PV_BLEND_VALU = 4,
+       PV_BLEND_BF16X6 = 5 };
 pv_status pv_volume_set_blend_mode(pv_volume *vol, int mode);
 pv_status pv_volume_get_blend_mode(pv_volume *vol, int *mode);
 pv_status pv_volume_set_trace_config(pv_volume *vol, const pv_trace_config *cfg);

@@ -89,15 +89,18 @@ __device__ __forceinline__ void blend_batched_block(const BatchVolume &bv, int l
         blend_gemm_block<T, kBlendBF16x3, 4>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, local, g);
     else if (mode == kBlendVALU)
         blend_gemm_block<T, kBlendVALU, 4>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, local, g);
+    else if (mode == kBlendBF16x6)
+        blend_gemm_block<T, kBlendBF16x6, 4>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, local, g);
     else
         blend_gemm_block<T, kBlendF32, 4>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, local, g);
 }
 
 // Batches whose maps share one type and whose volumes use the automatic
-// blend modes (per-tile below the table's break-even, the FP32 table from
-// there): only those two paths are compiled in, so the launch holds their
-// registers instead of every path's (228 per lane: two wavefronts per SIMD).
-// Binary16 maps: at most 128 registers, four wavefronts per SIMD.
+// blend paths (per-tile below the table's break-even, the BF16x6 table from
+// there) or the FP32 table: only those three paths are compiled in, so the
+// launch holds their registers instead of every path's (228 per lane: two
+// wavefronts per SIMD). Binary16 maps: at most 128 registers, four
+// wavefronts per SIMD.
 template <typename T>
 union AutoBlendSmem {
     BlendSmem tiles;
@@ -110,9 +113,12 @@ __device__ __forceinline__ void blend_batched_auto(const BatchVolume *vols, int 
     const int v = __builtin_amdgcn_readfirstlane(find_volume<true>(vols, n_vols, g));
     const BatchVolume &bv = vols[v];
     const int local = g - bv.first_blend;
-    if (bv.vp.blend_mode == kBlendTiles)
+    const int mode = bv.vp.blend_mode;
+    if (mode == kBlendTiles)
         blend_tile_any<T>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, (local / kBlendSplit) * kBlendTile,
                           local % kBlendSplit, sm.tiles);
+    else if (mode == kBlendBF16x6)
+        blend_gemm_block<T, kBlendBF16x6, 4>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, local, sm.gemm);
     else
         blend_gemm_block<T, kBlendF32, 4>(bv.vp, bv.dirs, bv.rays, (T *)bv.irr, (T *)bv.vis, bv.h, local, sm.gemm);
 }

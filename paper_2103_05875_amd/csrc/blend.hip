@@ -12,7 +12,7 @@ static_assert(kDirThreads == 256, "a weight-table block is four wavefronts shari
 
 __host__ __device__ inline int dir_blocks(int n) { return (n + kDirThreads - 1) / kDirThreads; }
 __host__ __device__ inline int table_blocks(int mode) {
-    return (mode == kBlendBF16x3 || mode == kBlendF32 || mode == kBlendVALU) ? kMTiles : 0;
+    return (mode == kBlendBF16x3 || mode == kBlendF32 || mode == kBlendVALU || mode == kBlendBF16x6) ? kMTiles : 0;
 }
 
 // Blocks [0, dir_blocks): one thread per ray direction; the next
@@ -139,6 +139,9 @@ static hipError_t launch_blend_t(const VolumeParams &vp, const float4 *dirs, con
         break;
     case kBlendVALU:
         launch_gemm<T, kBlendVALU>(g4, grid, vp, dirs, rays, irr, vis, h, s);
+        break;
+    case kBlendBF16x6:
+        launch_gemm<T, kBlendBF16x6>(g4, grid, vp, dirs, rays, irr, vis, h, s);
         break;
     default:
         hipLaunchKernelGGL(k_blend<T>, grid, dim3(kBlendThreads), 0, s, vp, dirs, rays, irr, vis, h);

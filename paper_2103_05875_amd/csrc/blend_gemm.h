@@ -68,8 +68,28 @@ __device__ void weight_tile_block(const FrameParams &fp, int n, int sharp, int m
     const int steps = (n + kWStep - 1) / kWStep;
     float sum = 0.f;
     for (int s = wv; s < steps; s += 4) {
-        uint4 *dst = reinterpret_cast<uint4 *>(tab + (((size_t)s * kMTiles + mt) * 64 + lane) * 32);
-        if (mode == kBlendBF16x3) {
+        uint4 *dst = reinterpret_cast<uint4 *>(tab + (((size_t)s * kMTiles + mt) * 64 + lane) * wtab_lane_bytes(mode));
+        if (mode == kBlendBF16x6) {
+            // three parts: x = hi + mid + lo + O(2^-27 x); each difference is
+            // exact in FP32 (it drops the leading bits the part took)
+            unsigned short hi[8], mi[8], lo[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int j = s * kWStep + 8 * kq + i;
+                const float w = j < n ? row_weight<S>(om, vis_row, sharp, sdir[j]) : 0.f;
+                sum += w;
+                hi[i] = bf16_bits(w);
+                const float r = w - bf16_value(hi[i]);
+                mi[i] = bf16_bits(r);
+                lo[i] = bf16_bits(r - bf16_value(mi[i]));
+            }
+            dst[0] = make_uint4(hi[0] | (uint32_t)hi[1] << 16, hi[2] | (uint32_t)hi[3] << 16,
+                                hi[4] | (uint32_t)hi[5] << 16, hi[6] | (uint32_t)hi[7] << 16);
+            dst[1] = make_uint4(mi[0] | (uint32_t)mi[1] << 16, mi[2] | (uint32_t)mi[3] << 16,
+                                mi[4] | (uint32_t)mi[5] << 16, mi[6] | (uint32_t)mi[7] << 16);
+            dst[2] = make_uint4(lo[0] | (uint32_t)lo[1] << 16, lo[2] | (uint32_t)lo[3] << 16,
+                                lo[4] | (uint32_t)lo[5] << 16, lo[6] | (uint32_t)lo[7] << 16);
+        } else if (mode == kBlendBF16x3) {
             unsigned short hi[8], lo[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -113,7 +133,7 @@ __device__ void weight_tile_block(const FrameParams &fp, int n, int sharp, int m
     if (kq == 0) red[wv * 16 + q] = sum;
     __syncthreads();
     if (threadIdx.x < 16)
-        reinterpret_cast<float *>(tab + wtab_steps(n) * kMTiles * 64 * 32)[16 * mt + threadIdx.x] =
+        reinterpret_cast<float *>(tab + wtab_rows_offset(n, mode))[16 * mt + threadIdx.x] =
             ((red[threadIdx.x] + red[16 + threadIdx.x]) + red[32 + threadIdx.x]) + red[48 + threadIdx.x];
 }
 
@@ -159,6 +179,14 @@ __device__ __forceinline__ void load_frag(const uint8_t *tab, int s, int mt, uin
     a1 = p[1];
 }
 
+// The three-part fragment of the BF16x6 table (48 bytes: high, middle, low).
+__device__ __forceinline__ void load_frag3(const uint8_t *tab, int s, int mt, uint4 *a) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(tab) + (((size_t)s * kMTiles + mt) * 64 + (threadIdx.x & 63)) * 3;
+    a[0] = p[0];
+    a[1] = p[1];
+    a[2] = p[2];
+}
+
 // Records of one 32-ray step of a column group, shared through LDS by the
 // group's row-group wavefronts (loaded once, coalesced: consecutive threads
 // take consecutive records of a probe). A probe's row is padded by one
@@ -178,13 +206,13 @@ struct BlendImage {
     T v[kIrrElems + kVisElems];
 };
 
-// BF16x3 records of one step, split once per block at staging: per buffer,
-// channel (r, g, b, distance, distance^2), half (high, low) and probe, the
+// Split-BF16 records of one step, split once per block at staging: per
+// buffer, channel (r, g, b, distance, distance^2), part and probe, the
 // 32 rays as 16 words of two BF16 values (ray 2w in the low half), so that
 // a lane's operand (rays 8 kq .. 8 kq + 7 of probe q) is one aligned
 // 16-byte read and a wavefront's 64 reads cover 1 KB without conflicts.
 struct BlendRecsBF {
-    uint32_t w[2][5][2][16][kWStep / 2];
+    uint32_t w[2][5][3][16][kWStep / 2];  // parts: high, low (BF16x3) or high, middle, low (BF16x6)
 };
 
 template <typename T>
@@ -288,10 +316,11 @@ __device__ __forceinline__ void image_move(T *irr, T *vis, int p0, int np, Blend
     }
 }
 
-// Prefetch of step s's records for the BF16x3 product: thread t < 256 takes
-// rays 2 (t % 16) and 2 (t % 16) + 1 of probe t / 16 (32 contiguous bytes),
-// and at staging writes both rays' high and low BF16 halves of every channel
-// (the same split as the weights: x = hi + lo + O(2^-18 x)).
+// Prefetch of step s's records for the split-BF16 products: thread t < 256
+// takes rays 2 (t % 16) and 2 (t % 16) + 1 of probe t / 16 (32 contiguous
+// bytes), and at staging writes both rays' BF16 parts of every channel (the
+// same split as the weights: two parts, x = hi + lo + O(2^-18 x), or three).
+template <int PARTS>
 struct RecPrefetchBF {
     float4 v[2];
     __device__ __forceinline__ void load(const float4 *rays, int n, int P, int cg, int s) {
@@ -310,9 +339,14 @@ struct RecPrefetchBF {
         for (int c = 0; c < 5; ++c) {
             const float x0 = channel(v[0], c), x1 = channel(v[1], c);
             const unsigned short h0 = bf16_bits(x0), h1 = bf16_bits(x1);
-            const unsigned short l0 = bf16_bits(x0 - bf16_value(h0)), l1 = bf16_bits(x1 - bf16_value(h1));
+            const float r0 = x0 - bf16_value(h0), r1 = x1 - bf16_value(h1);
+            const unsigned short m0 = bf16_bits(r0), m1 = bf16_bits(r1);
             sm.w[buf][c][0][qq][w] = (uint32_t)h0 | (uint32_t)h1 << 16;
-            sm.w[buf][c][1][qq][w] = (uint32_t)l0 | (uint32_t)l1 << 16;
+            sm.w[buf][c][1][qq][w] = (uint32_t)m0 | (uint32_t)m1 << 16;
+            if constexpr (PARTS == 3) {
+                const unsigned short l0 = bf16_bits(r0 - bf16_value(m0)), l1 = bf16_bits(r1 - bf16_value(m1));
+                sm.w[buf][c][2][qq][w] = (uint32_t)l0 | (uint32_t)l1 << 16;
+            }
         }
     }
 };
@@ -361,12 +395,14 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
     TS ts;
 #pragma unroll
     for (int t = 0; t < TS::kTiles; ++t) ts.acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-    // records through LDS: split into BF16 halves at staging for BF16x3,
-    // else whole FP32 records
-    using PF = std::conditional_t<MODE == kBlendBF16x3, RecPrefetchBF, RecPrefetch<NT>>;
+    // records through LDS: split into BF16 parts at staging for the split
+    // products, else whole FP32 records
+    constexpr bool kSplit = MODE == kBlendBF16x3 || MODE == kBlendBF16x6;
+    constexpr int kParts = MODE == kBlendBF16x6 ? 3 : 2;
+    using PF = std::conditional_t<kSplit, RecPrefetchBF<kParts>, RecPrefetch<NT>>;
     PF pf;
     pf.load(rays, n, P, cg, 0);
-    if constexpr (MODE == kBlendBF16x3)
+    if constexpr (kSplit)
         pf.store(sb, 0);
     else
         pf.store(sm, 0);
@@ -377,8 +413,8 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
     // SIMD on the encode-size grid); eight-wavefront blocks (small volumes,
     // fewer blocks than resident slots) have registers to spare and request
     // the next step's fragments with the next step's records, one step ahead
-    constexpr bool kAhead = NT == 512 && MODE != kBlendVALU;
-    uint4 acur[RT][2], anext[kAhead ? RT : 1][2];
+    constexpr bool kAhead = NT == 512 && MODE != kBlendVALU && MODE != kBlendBF16x6;
+    uint4 acur[MODE == kBlendBF16x6 ? 1 : RT][2], anext[kAhead ? RT : 1][2];
     if constexpr (kAhead) {
 #pragma unroll
         for (int t = 0; t < RT; ++t) load_frag(tab, 0, TS::mtile(t), acur[t][0], acur[t][1]);
@@ -391,7 +427,7 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
 #pragma unroll
                 for (int t = 0; t < RT; ++t) load_frag(tab, s + 1, TS::mtile(t), anext[t][0], anext[t][1]);
             }
-        } else if constexpr (MODE != kBlendVALU) {
+        } else if constexpr (MODE != kBlendVALU && MODE != kBlendBF16x6) {
 #pragma unroll
             for (int t = 0; t < RT; ++t) load_frag(tab, s, TS::mtile(t), acur[t][0], acur[t][1]);
         }
@@ -434,13 +470,14 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
         } else {
             // the step's operand fragments: BF16x3 rays 8 kq .. 8 kq + 7 (high
             // and low halves, staged split), F32 ray 4 i + kq of probe q
-            bf16x8 bh[NC], bl[NC];
+            bf16x8 bp[kParts][NC];
             float bf[NC][8];
-            if constexpr (MODE == kBlendBF16x3) {
+            if constexpr (kSplit) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    bh[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&sb.w[buf][C0 + c][0][q][4 * kq]));
-                    bl[c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&sb.w[buf][C0 + c][1][q][4 * kq]));
+                for (int k = 0; k < kParts; ++k) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        bp[k][c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&sb.w[buf][C0 + c][k][q][4 * kq]));
                 }
             } else {
 #pragma unroll
@@ -453,22 +490,49 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
             // the products, ordered so that consecutive matrix instructions
             // feed different accumulators (each accumulator still takes its
             // terms in the same order)
-            if (MODE == kBlendBF16x3) {
+            // products (weight part, record part): BF16x3 (0,0) (0,1) (1,0);
+            // BF16x6 also (0,2) (2,0) (1,1), the terms down to 2^-18 of the
+            // product
+            constexpr int kPa[6] = {0, 0, 1, 0, 2, 1}, kPb[6] = {0, 1, 0, 2, 0, 1};
+            if constexpr (MODE == kBlendBF16x6) {
+                // row tile by row tile, its three weight parts loaded for its
+                // six products (three parts of every row tile at once would
+                // not leave four wavefronts per SIMD)
 #pragma unroll
-                for (int pk = 0; pk < 3; ++pk) {
+                for (int t = 0; t < RT; ++t) {
+                    const bool it = t < NI;
+                    const int nch = it ? 3 : 2;
+                    const int acc0 = it ? 3 * t : 3 * NI + 2 * (t - NI);
+                    const int ch0 = it ? 0 : NC - 2;
+                    uint4 a3[3];
+                    load_frag3(tab, s, TS::mtile(t), a3);
+#pragma unroll
+                    for (int pk = 0; pk < 6; ++pk) {
+                        const bf16x8 aw = __builtin_bit_cast(bf16x8, a3[kPa[pk]]);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            if (c >= nch) continue;
+                            v4f &a = ts.acc[acc0 + c];
+                            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bp[kPb[pk]][ch0 + c], a, 0, 0, 0);
+                        }
+                    }
+                }
+            } else if constexpr (kSplit) {
+                constexpr int kProducts = 3;
+#pragma unroll
+                for (int pk = 0; pk < kProducts; ++pk) {
 #pragma unroll
                     for (int t = 0; t < RT; ++t) {
                         const bool it = t < NI;
                         const int nch = it ? 3 : 2;
                         const int acc0 = it ? 3 * t : 3 * NI + 2 * (t - NI);
                         const int ch0 = it ? 0 : NC - 2;  // first channel slot of the tile's texture
-                        const bf16x8 aw = __builtin_bit_cast(bf16x8, pk == 2 ? acur[t][1] : acur[t][0]);
+                        const bf16x8 aw = __builtin_bit_cast(bf16x8, acur[t][kPa[pk]]);
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
                             if (c >= nch) continue;
                             v4f &a = ts.acc[acc0 + c];
-                            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, pk == 1 ? bl[ch0 + c] : bh[ch0 + c], a,
-                                                                        0, 0, 0);
+                            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bp[kPb[pk]][ch0 + c], a, 0, 0, 0);
                         }
                     }
                 }
@@ -495,7 +559,7 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
         }
         // every wavefront is done with the other buffer since the last step's barrier
         if (s + 1 < steps) {
-            if constexpr (MODE == kBlendBF16x3)
+            if constexpr (kSplit)
                 pf.store(sb, buf ^ 1);
             else
                 pf.store(sm, buf ^ 1);
@@ -519,7 +583,7 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
     const int np = min(16, P - 16 * cg);
     image_move<T, true, 1024 / NT>(irr, vis, 16 * cg, np, img);
     __syncthreads();
-    const float *rows = reinterpret_cast<const float *>(tab + wtab_steps(n) * kMTiles * 64 * 32);
+    const float *rows = reinterpret_cast<const float *>(tab + wtab_rows_offset(n, MODE));
     if (live) {
 #pragma unroll
         for (int t = 0; t < RT; ++t) {

@@ -786,7 +786,7 @@ extern "C" pv_status pv_blend_rays(pv_volume *v, const pv_frame *f, const void *
 
 extern "C" pv_status pv_volume_set_blend_mode(pv_volume *v, int mode) {
     if (!v) return fail(PV_ERR_ARG, "volume is NULL");
-    if (mode < PV_BLEND_AUTO || mode > PV_BLEND_VALU) return fail(PV_ERR_ARG, "unknown blend mode");
+    if (mode < PV_BLEND_AUTO || mode > PV_BLEND_BF16X6) return fail(PV_ERR_ARG, "unknown blend mode");
     v->blend_mode = mode == PV_BLEND_AUTO ? auto_blend_mode(v->P) : mode;
     return PV_OK;
 }
@@ -990,7 +990,7 @@ static int batch_blend_kind(pv_volume *const *vols, int n) {
     bool half = true, flt = true;
     for (int i = 0; i < n; ++i) {
         const int m = vols[i]->blend_mode;
-        if (m != kBlendTiles && m != kBlendF32) return kBatchBlendAny;
+        if (m != kBlendTiles && m != kBlendF32 && m != kBlendBF16x6) return kBatchBlendAny;
         const bool h = vols[i]->desc.format == PV_MAP_FP16;
         half = half && h;
         flt = flt && !h;

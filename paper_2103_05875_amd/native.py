@@ -24,7 +24,7 @@ PV_MULTI_BOUNCE = 4
 PV_CLASSIFY = 8
 # blend paths (pv_volume_set_blend_mode)
 PV_BLEND_AUTO, PV_BLEND_BF16X3, PV_BLEND_F32, PV_BLEND_TILES, PV_BLEND_VALU = 0, 1, 2, 3, 4
-BLEND_MODES = {"auto": 0, "bf16x3": 1, "f32": 2, "tiles": 3, "valu": 4}
+BLEND_MODES = {"auto": 0, "bf16x3": 1, "f32": 2, "tiles": 3, "valu": 4, "bf16x6": 5}
 # pv_measure_ceiling kinds
 PV_CEIL_COPY, PV_CEIL_FMA_F32, PV_CEIL_MFMA_F32 = 0, 1, 2
 PV_MAX_LIGHTS = 8
@@ -424,7 +424,7 @@ class Volume:
         _check(lib().pv_volume_set_trace_config(self.h, ctypes.byref(c)))
 
     def set_blend_mode(self, mode):
-        """Blend path: "auto", "bf16x3", "f32", "tiles", "valu" or its number."""
+        """Blend path: "auto", "bf16x3", "f32", "tiles", "valu", "bf16x6" or its number."""
         _check(lib().pv_volume_set_blend_mode(self.h, BLEND_MODES.get(mode, mode) if isinstance(mode, str)
                                               else int(mode)))
 

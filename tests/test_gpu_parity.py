@@ -354,15 +354,16 @@ def test_blend_from_given_rays(ps, ctx, O, fp16, n, grid, sharp):
     vol.close()
 
 
-@pytest.mark.parametrize("mode", ["bf16x3", "f32", "tiles", "valu"])
+@pytest.mark.parametrize("mode", ["bf16x3", "f32", "tiles", "valu", "bf16x6"])
 @pytest.mark.parametrize("fp16,n,grid", [(False, 96, (19, 1, 1)), (True, 256, (9, 5, 3)), (True, 300, (3, 2, 2)),
                                           (False, 33, (2, 1, 1))])
 def test_blend_paths_against_oracle(ps, ctx, O, mode, fp16, n, grid):
-    """Every blend path (weight table with BF16x3 or FP32 products, or the
-    per-tile weights) on the same seeded ray records over four frames of
-    hysteresis: FP16 maps within 2 ulps (1 ulp for 99.9%) of the oracle's
-    FP16 trajectory; FP32 maps within 1e-5 (the BF16x3 products, whose terms
-    carry about 2^-16 of relative error, within 1e-4)."""
+    """Every blend path (weight table with split-BF16, FP32 or vector-FMA
+    products, or the per-tile weights) on the same seeded ray records over
+    four frames of hysteresis: FP16 maps within 2 ulps (1 ulp for 99.9%) of
+    the oracle's FP16 trajectory; FP32 maps within 1e-5 (the BF16x3
+    products, whose terms carry about 2^-16 of relative error, within
+    1e-4; BF16x6, about 2^-25, within 1e-5)."""
     import torch
     _say(f"blend path {mode} fp16={fp16} n={n} grid={grid}")
     cfg = synth.VolumeConfig(*grid, (0, 0, 0), (1, 1, 1), n, fp16=fp16, max_distance=4.0)
@@ -443,9 +444,9 @@ def test_tuner_over_frames_and_batched_buckets(ps, ctx):
 
 
 def test_blend_mode_default_follows_volume_size(ps, ctx):
-    """A new volume takes the per-tile weights below 4,096 probes and the FP32
-    table product from there; AUTO restores that choice."""
-    for grid, want in (((4, 4, 4), "tiles"), ((16, 8, 16), "tiles"), ((16, 16, 16), "f32")):
+    """A new volume takes the per-tile weights below 2,048 probes and the
+    three-part BF16 table product from there; AUTO restores that choice."""
+    for grid, want in (((4, 4, 4), "tiles"), ((16, 8, 15), "tiles"), ((16, 8, 16), "bf16x6"), ((16, 16, 16), "bf16x6")):
         vol = ps.Volume(ctx, synth.VolumeConfig(*grid, (0, 0, 0), (1, 1, 1), 64, fp16=True))
         assert vol.get_blend_mode() == want
         vol.set_blend_mode("valu")
@@ -613,8 +614,8 @@ def test_batched_matches_plain_bitwise(ps, ctx, O, maps):
     shapes (probe bricks, staged top nodes) of their own, the plain ones
     other schedules. Map types and blend paths select the batched blend
     kernel: mixed map types (every path compiled in), one map type with the
-    automatic paths (per-tile, and the FP32 table on the third volume), or a
-    split-BF16 volume among them (every path again)."""
+    per-tile, FP32-table (third volume) and BF16x6-table (fifth volume)
+    paths, or a BF16x3 volume among them (every path again)."""
     _say(f"batched vs plain, 6 uneven volumes, 3 frames, maps {maps}")
     specs = [((4, 4, 4), 64, True, 2000), ((5, 3, 7), 128, True, 800), ((16, 2, 16), 256, True, 5000),
              ((1, 1, 1), 512, False, 300), ((8, 8, 4), 64, False, 1200), ((3, 3, 3), 1, True, 100)]
@@ -634,9 +635,9 @@ def test_batched_matches_plain_bitwise(ps, ctx, O, maps):
         b.set_scene(sc)
         a.set_trace_config(shapes_p[i][0], shapes_p[i][1], 21, 256, False)
         b.set_trace_config(shapes_b[i][0], 2, shapes_b[i][1], 256, False)
-        if i == 2 and maps != "mixed":
+        if i in (2, 4) and maps != "mixed":
             for v in (a, b):
-                v.set_blend_mode("bf16x3" if maps == "fp16_bf16x3" else "f32")
+                v.set_blend_mode("bf16x3" if maps == "fp16_bf16x3" else "f32" if i == 2 else "bf16x6")
         plain.append(a)
         batched.append(b)
     for f in range(3):
