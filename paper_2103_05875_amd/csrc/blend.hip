@@ -8,20 +8,22 @@
 namespace pv {
 
 constexpr int kDirThreads = 256;
-static_assert(kDirThreads == 256, "a weight-table block is four wavefronts sharing one row tile");
+static_assert(kDirThreads == 256 && kWGroup == 4 && kWGroup * kWStep <= kDirThreads, "a weight-table block: four wavefronts, one step each, one direction per thread");
 
 __host__ __device__ inline int dir_blocks(int n) { return (n + kDirThreads - 1) / kDirThreads; }
-__host__ __device__ inline int table_blocks(int mode) {
-    return (mode == kBlendBF16x3 || mode == kBlendF32 || mode == kBlendVALU || mode == kBlendBF16x6) ? kMTiles : 0;
+__host__ __device__ inline int table_blocks(int mode, int n) {
+    return (mode == kBlendBF16x3 || mode == kBlendF32 || mode == kBlendVALU || mode == kBlendBF16x6)
+               ? kMTiles * wtab_groups(n)
+               : 0;
 }
 
 // Blocks [0, dir_blocks): one thread per ray direction; the next
-// table_blocks(mode) blocks: the weight table after the directions (one
-// row tile each). queue: the work counters of the trace that follows,
+// table_blocks(mode, n) blocks: the weight table after the directions (one
+// row tile over one group of steps each). queue: the work counters of the trace that follows,
 // zeroed here.
 __global__ __launch_bounds__(kDirThreads) void k_raydirs(FrameParams fp, int n, float4 *dirs, int *queue, int mode,
                                                          int sharp) {
-    __shared__ float3 sdir[PV_MAX_RAYS];
+    __shared__ float3 sdir[kWGroup * kWStep];
     __shared__ float red[64];
     const int db = dir_blocks(n);
     if ((int)blockIdx.x >= db) {
@@ -38,14 +40,14 @@ __global__ __launch_bounds__(kDirThreads) void k_raydirs(FrameParams fp, int n, 
 // weight table.
 __global__ __launch_bounds__(kDirThreads) void k_raydirs_batched(const BatchVolume *vols, const FrameParams *frames,
                                                                  int n_vols) {
-    __shared__ float3 sdir[PV_MAX_RAYS];
+    __shared__ float3 sdir[kWGroup * kWStep];
     __shared__ float red[64];
     const int v = blockIdx.y;
     if (v >= n_vols) return;
     const BatchVolume &bv = vols[v];
     const int n = bv.vp.n, db = dir_blocks(n);
     if ((int)blockIdx.x >= db) {
-        if ((int)blockIdx.x - db < table_blocks(bv.vp.blend_mode))
+        if ((int)blockIdx.x - db < table_blocks(bv.vp.blend_mode, n))
             weight_table_block(frames[v], n, bv.vp.vis_sharpness, bv.vp.blend_mode,
                                reinterpret_cast<uint8_t *>(const_cast<float4 *>(bv.dirs)) + dirs_span(n),
                                blockIdx.x - db, sdir, red);
@@ -56,7 +58,7 @@ __global__ __launch_bounds__(kDirThreads) void k_raydirs_batched(const BatchVolu
 }
 
 int raydir_blocks(int n) { return dir_blocks(n); }
-int weight_blocks(int mode) { return table_blocks(mode); }
+int weight_blocks(int mode, int n) { return table_blocks(mode, n); }
 
 template <typename T>
 __global__ __launch_bounds__(kBlendThreads) void k_blend(VolumeParams vp, const float4 *dirs, const float4 *rays, T *irr,
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 hipError_t launch_raydirs(const FrameParams &fp, const VolumeParams &vp, float4 *dirs, int *queue, hipStream_t s) {
-    hipLaunchKernelGGL(k_raydirs, dim3(dir_blocks(vp.n) + table_blocks(vp.blend_mode)), dim3(kDirThreads), 0, s, fp,
+    hipLaunchKernelGGL(k_raydirs, dim3(dir_blocks(vp.n) + table_blocks(vp.blend_mode, vp.n)), dim3(kDirThreads), 0, s, fp,
                        vp.n, dirs, queue, vp.blend_mode, vp.vis_sharpness);
     return hipGetLastError();
 }

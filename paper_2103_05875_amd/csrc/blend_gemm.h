@@ -49,25 +49,29 @@ __device__ __forceinline__ float3 row_dir(int m) {
     return m < 64 ? oct_texel_dir(8, m & 7, m >> 3) : oct_texel_dir(16, (m - 64) & 15, (m - 64) >> 4);
 }
 
-// Table rows of one 16-row tile by a 256-thread block: the block first puts
-// all n directions of the frame into LDS (the same FP32 values as the
-// direction kernel), then wavefront w evaluates the tile's weights of steps
-// w, w + 4, ...; the row totals are each lane's partial sum, the sum across
-// the four lanes of a row, then the four wavefronts' sums in order (a fixed
-// order, so every run gives the same totals). red: 64 floats of LDS.
+// Table rows of one 16-row tile over a group of four 32-ray steps by a
+// 256-thread block: the block first puts the group's 128 directions into LDS
+// (the same FP32 values as the direction kernel), then wavefront w evaluates
+// the tile's weights of step 4 g + w. The group's row sums (each lane's sum,
+// then across the four lanes of a row, then the four wavefronts' sums in
+// order) go to the group's row of partial totals; the blend adds the groups'
+// partials in order, so every run gives the same totals. sdir: 128 float3,
+// red: 64 floats of LDS.
 template <int S>
-__device__ void weight_tile_block(const FrameParams &fp, int n, int sharp, int mode, uint8_t *tab, int mt,
+__device__ void weight_tile_block(const FrameParams &fp, int n, int sharp, int mode, uint8_t *tab, int mt, int grp,
                                   float3 *sdir, float *red) {
-    for (int j = threadIdx.x; j < n; j += blockDim.x) sdir[j] = xyz(raydir(fp, n, j));
+    const int j0 = grp * kWGroup * kWStep;
+    if ((int)threadIdx.x < kWGroup * kWStep && j0 + (int)threadIdx.x < n)
+        sdir[threadIdx.x] = xyz(raydir(fp, n, j0 + threadIdx.x));
     __syncthreads();
-    if (mt >= kMTiles) return;
     const int lane = threadIdx.x & 63, q = lane & 15, kq = lane >> 4, wv = threadIdx.x >> 6;
     const int m = 16 * mt + q;
     const bool vis_row = m >= 64;
     const float3 om = row_dir(m);
     const int steps = (n + kWStep - 1) / kWStep;
     float sum = 0.f;
-    for (int s = wv; s < steps; s += 4) {
+    sdir -= j0;  // indexed by ray number below
+    for (int s = kWGroup * grp + wv; s < min(steps, kWGroup * (grp + 1)); s += 4) {
         uint4 *dst = reinterpret_cast<uint4 *>(tab + (((size_t)s * kMTiles + mt) * 64 + lane) * wtab_lane_bytes(mode));
         if (mode == kBlendBF16x6) {
             // three parts: x = hi + mid + lo + O(2^-27 x); each difference is
@@ -133,17 +137,19 @@ __device__ void weight_tile_block(const FrameParams &fp, int n, int sharp, int m
     if (kq == 0) red[wv * 16 + q] = sum;
     __syncthreads();
     if (threadIdx.x < 16)
-        reinterpret_cast<float *>(tab + wtab_rows_offset(n, mode))[16 * mt + threadIdx.x] =
+        reinterpret_cast<float *>(tab + wtab_rows_offset(n, mode))[grp * kTexRows + 16 * mt + threadIdx.x] =
             ((red[threadIdx.x] + red[16 + threadIdx.x]) + red[32 + threadIdx.x]) + red[48 + threadIdx.x];
 }
 
-// One table block (one row tile) of the direction launch.
+// Table block b of the direction launch: row tile b % kMTiles, step group
+// b / kMTiles.
 __device__ __forceinline__ void weight_table_block(const FrameParams &fp, int n, int sharp, int mode, uint8_t *tab,
-                                                   int mt, float3 *sdir, float *red) {
+                                                   int b, float3 *sdir, float *red) {
+    const int mt = b % kMTiles, grp = b / kMTiles;
     if (sharp == 50)
-        weight_tile_block<50>(fp, n, sharp, mode, tab, mt, sdir, red);
+        weight_tile_block<50>(fp, n, sharp, mode, tab, mt, grp, sdir, red);
     else
-        weight_tile_block<0>(fp, n, sharp, mode, tab, mt, sdir, red);
+        weight_tile_block<0>(fp, n, sharp, mode, tab, mt, grp, sdir, red);
 }
 
 __device__ __forceinline__ const uint8_t *weight_table(const float4 *dirs, int n) {
@@ -216,10 +222,13 @@ struct BlendRecsBF {
 };
 
 template <typename T>
-union BlendSmemGemm {
-    BlendRecs recs;
-    BlendRecsBF bf;
-    BlendImage<T> img;
+struct BlendSmemGemm {
+    union {
+        BlendRecs recs;
+        BlendRecsBF bf;
+        BlendImage<T> img;
+    };
+    float rows[kTexRows];  // row totals: the table's step-group partials added in order
 };
 
 // Tile element (y, x) of an (N + 2)^2 tile -> the element whose value it
@@ -402,6 +411,17 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
     using PF = std::conditional_t<kSplit, RecPrefetchBF<kParts>, RecPrefetch<NT>>;
     PF pf;
     pf.load(rays, n, P, cg, 0);
+    {
+        // the row totals of the epilogue: the table's step-group partials,
+        // added in order
+        const float *part = reinterpret_cast<const float *>(tab + wtab_rows_offset(n, MODE));
+        const int groups = wtab_groups(n);
+        for (int m = threadIdx.x; m < kTexRows; m += NT) {
+            float t = part[m];
+            for (int g = 1; g < groups; ++g) t += part[g * kTexRows + m];
+            smu.rows[m] = t;
+        }
+    }
     if constexpr (kSplit)
         pf.store(sb, 0);
     else
@@ -583,7 +603,7 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
     const int np = min(16, P - 16 * cg);
     image_move<T, true, 1024 / NT>(irr, vis, 16 * cg, np, img);
     __syncthreads();
-    const float *rows = reinterpret_cast<const float *>(tab + wtab_rows_offset(n, MODE));
+    const float *rows = smu.rows;
     if (live) {
 #pragma unroll
         for (int t = 0; t < RT; ++t) {

@@ -37,8 +37,9 @@ inline int auto_blend_mode(int P) { return P >= kTableMinProbes ? kBlendBF16x6 :
 // buffer: steps of kWStep rays x kMTiles row tiles of 16 texel rows x 64
 // lanes x 32 bytes (the lane's MFMA A-operand fragment of that step: eight
 // FP32 weights, or eight BF16 high halves then eight low halves; 48 bytes
-// for kBlendBF16x6: high, middle and low parts), then the kTexRows FP32 row
-// totals. The buffer is sized for the widest layout.
+// for kBlendBF16x6: high, middle and low parts), then per group of kWGroup
+// steps the kTexRows FP32 partial row totals. The buffer is sized for the
+// widest layout.
 constexpr int kWStep = 32;
 constexpr int kMTiles = kTexRows / 16;
 __host__ __device__ inline size_t dirs_span(int n) { return ((size_t)n * 16 + 255) / 256 * 256; }
@@ -47,7 +48,13 @@ __host__ __device__ inline int wtab_lane_bytes(int mode) { return mode == kBlend
 __host__ __device__ inline size_t wtab_rows_offset(int n, int mode) {
     return wtab_steps(n) * kMTiles * 64 * wtab_lane_bytes(mode);
 }
-__host__ __device__ inline size_t wtab_bytes(int n) { return wtab_rows_offset(n, kBlendBF16x6) + kTexRows * 4; }
+// Table blocks take groups of kWGroup steps; each group leaves its own row
+// of kTexRows partial totals, which the blend adds in order.
+constexpr int kWGroup = 4;
+__host__ __device__ inline int wtab_groups(int n) { return (int)((wtab_steps(n) + kWGroup - 1) / kWGroup); }
+__host__ __device__ inline size_t wtab_bytes(int n) {
+    return wtab_rows_offset(n, kBlendBF16x6) + (size_t)wtab_groups(n) * kTexRows * 4;
+}
 
 // Work description of one volume for the batched launch.
 struct BatchVolume {
@@ -81,7 +88,7 @@ struct BatchVolume {
 // (plus the weight table after the directions when the blend mode uses one)
 hipError_t launch_raydirs(const FrameParams &fp, const VolumeParams &vp, float4 *dirs, int *queue, hipStream_t s);
 int raydir_blocks(int n);
-int weight_blocks(int mode);  // extra blocks of the direction launch that build the table
+int weight_blocks(int mode, int n);  // extra blocks of the direction launch that build the table
 int blend_blocks(int P, int mode);  // 256-thread blocks of one volume's blend
 hipError_t launch_blend(const VolumeParams &vp, const float4 *dirs, const float4 *rays, void *irr, void *vis,
                         int fp16, float h, hipStream_t s);

@@ -940,7 +940,7 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
         b.sv = scene_view(v->scene);
         short_stack = short_stack && b.sv.stat.n_nodes <= 65536 && b.sv.dyn.n_nodes <= 65536;
         b.dirs = v->dirs;
-        dir_blocks = std::max(dir_blocks, raydir_blocks(v->n) + weight_blocks(v->blend_mode));
+        dir_blocks = std::max(dir_blocks, raydir_blocks(v->n) + weight_blocks(v->blend_mode, v->n));
         b.rays = v->rays;
         b.hits = v->hits;
         b.irr = v->irr;

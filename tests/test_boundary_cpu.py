@@ -71,8 +71,9 @@ def test_footprint_and_validation(ps):
     assert st == 0
     # maps (+ slack), ray records, directions then the blend's weight table
     # (steps of 32 rays x 20 row tiles x 64 lanes x 48 bytes, the widest
-    # fragment layout, then 320 row totals), work counters
-    wtab = (n // 32) * 20 * 64 * 48 + 320 * 4
+    # fragment layout, then 320 partial row totals per group of 4 steps),
+    # work counters
+    wtab = (n // 32) * 20 * 64 * 48 + (n // 32 + 3) // 4 * 320 * 4
     assert b == P * 300 * 2 + P * 648 * 2 + 512 + P * n * 16 + n * 16 + wtab + 9 * 32 * 4
     assert _fp(ps, cfg, nx=0)[0] == -1
     assert _fp(ps, cfg, nx=64, ny=32, nz=32)[0] == 0          # 65536 probes: the index limit
