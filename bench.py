@@ -126,7 +126,8 @@ def read_counters(path, trace_config):
         return None, "kernel sources changed since the counters were taken"
     if kv.get("trace_config") != config_string(trace_config):
         return None, "counters were taken with another launch shape"
-    return float(kv["traffic_bytes_per_launch"]), path
+    ap = os.path.abspath(path)  # named relative to the repository when it lies inside it
+    return float(kv["traffic_bytes_per_launch"]), os.path.relpath(ap, ROOT) if ap.startswith(ROOT + os.sep) else ap
 
 
 def read_lane_utilisation(path, trace_config):
