@@ -433,11 +433,21 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
     // SIMD on the encode-size grid); eight-wavefront blocks (small volumes,
     // fewer blocks than resident slots) have registers to spare and request
     // the next step's fragments with the next step's records, one step ahead
-    constexpr bool kAhead = NT == 512 && MODE != kBlendVALU && MODE != kBlendBF16x6;
-    uint4 acur[MODE == kBlendBF16x6 ? 1 : RT][2], anext[kAhead ? RT : 1][2];
+    constexpr bool kAhead = NT == 512 && MODE != kBlendVALU;
+    // fragment parts held per row tile: three for BF16x6 (whose
+    // four-wavefront blocks load them tile by tile in the product loop)
+    constexpr int kFp = MODE == kBlendBF16x6 ? 3 : 2;
+    constexpr bool kTileByTile = MODE == kBlendBF16x6 && !kAhead;
+    uint4 acur[kTileByTile ? 1 : RT][kFp], anext[kAhead ? RT : 1][kFp];
+    auto load_parts = [&](int step, int t, uint4 *a) {
+        if constexpr (kFp == 3)
+            load_frag3(tab, step, TS::mtile(t), a);
+        else
+            load_frag(tab, step, TS::mtile(t), a[0], a[1]);
+    };
     if constexpr (kAhead) {
 #pragma unroll
-        for (int t = 0; t < RT; ++t) load_frag(tab, 0, TS::mtile(t), acur[t][0], acur[t][1]);
+        for (int t = 0; t < RT; ++t) load_parts(0, t, acur[t]);
     }
     for (int s = 0; s < steps; ++s) {
         const int buf = s & 1;
@@ -445,7 +455,7 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
         if constexpr (kAhead) {
             if (s + 1 < steps) {
 #pragma unroll
-                for (int t = 0; t < RT; ++t) load_frag(tab, s + 1, TS::mtile(t), anext[t][0], anext[t][1]);
+                for (int t = 0; t < RT; ++t) load_parts(s + 1, t, anext[t]);
             }
         } else if constexpr (MODE != kBlendVALU && MODE != kBlendBF16x6) {
 #pragma unroll
@@ -514,7 +524,7 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
             // BF16x6 also (0,2) (2,0) (1,1), the terms down to 2^-18 of the
             // product
             constexpr int kPa[6] = {0, 0, 1, 0, 2, 1}, kPb[6] = {0, 1, 0, 2, 0, 1};
-            if constexpr (MODE == kBlendBF16x6) {
+            if constexpr (kTileByTile) {
                 // row tile by row tile, its three weight parts loaded for its
                 // six products (three parts of every row tile at once would
                 // not leave four wavefronts per SIMD)
@@ -538,7 +548,7 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
                     }
                 }
             } else if constexpr (kSplit) {
-                constexpr int kProducts = 3;
+                constexpr int kProducts = MODE == kBlendBF16x6 ? 6 : 3;
 #pragma unroll
                 for (int pk = 0; pk < kProducts; ++pk) {
 #pragma unroll
@@ -586,8 +596,8 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
             if constexpr (kAhead) {
 #pragma unroll
                 for (int t = 0; t < RT; ++t) {
-                    acur[t][0] = anext[t][0];
-                    acur[t][1] = anext[t][1];
+#pragma unroll
+                    for (int k = 0; k < kFp; ++k) acur[t][k] = anext[t][k];
                 }
             }
         }
