@@ -70,7 +70,6 @@ __device__ void weight_tile_block(const FrameParams &fp, int n, int sharp, int m
     const float3 om = row_dir(m);
     const int steps = (n + kWStep - 1) / kWStep;
     float sum = 0.f;
-    sdir -= j0;  // indexed by ray number below
     for (int s = kWGroup * grp + wv; s < min(steps, kWGroup * (grp + 1)); s += 4) {
         uint4 *dst = reinterpret_cast<uint4 *>(tab + (((size_t)s * kMTiles + mt) * 64 + lane) * wtab_lane_bytes(mode));
         if (mode == kBlendBF16x6) {
@@ -80,7 +79,7 @@ __device__ void weight_tile_block(const FrameParams &fp, int n, int sharp, int m
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int j = s * kWStep + 8 * kq + i;
-                const float w = j < n ? row_weight<S>(om, vis_row, sharp, sdir[j]) : 0.f;
+                const float w = j < n ? row_weight<S>(om, vis_row, sharp, sdir[j - j0]) : 0.f;
                 sum += w;
                 hi[i] = bf16_bits(w);
                 const float r = w - bf16_value(hi[i]);
@@ -98,7 +97,7 @@ __device__ void weight_tile_block(const FrameParams &fp, int n, int sharp, int m
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int j = s * kWStep + 8 * kq + i;
-                const float w = j < n ? row_weight<S>(om, vis_row, sharp, sdir[j]) : 0.f;
+                const float w = j < n ? row_weight<S>(om, vis_row, sharp, sdir[j - j0]) : 0.f;
                 sum += w;
                 hi[i] = bf16_bits(w);
                 lo[i] = bf16_bits(w - bf16_value(hi[i]));
@@ -114,7 +113,7 @@ __device__ void weight_tile_block(const FrameParams &fp, int n, int sharp, int m
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int k = 4 * i + kq, j = s * kWStep + k;
-                const float w = j < n ? row_weight<S>(om, vis_row, sharp, sdir[j]) : 0.f;
+                const float w = j < n ? row_weight<S>(om, vis_row, sharp, sdir[j - j0]) : 0.f;
                 sum += w;
                 dv[((q >> 2) * kWStep + k) * 4 + (q & 3)] = w;
             }
@@ -123,7 +122,7 @@ __device__ void weight_tile_block(const FrameParams &fp, int n, int sharp, int m
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int j = s * kWStep + 4 * i + kq;
-                w[i] = j < n ? row_weight<S>(om, vis_row, sharp, sdir[j]) : 0.f;
+                w[i] = j < n ? row_weight<S>(om, vis_row, sharp, sdir[j - j0]) : 0.f;
                 sum += w[i];
             }
             dst[0] = make_uint4(__float_as_uint(w[0]), __float_as_uint(w[1]), __float_as_uint(w[2]),
