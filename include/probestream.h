@@ -229,7 +229,11 @@ pv_status pv_batch_graph_destroy(pv_batch_graph *graph);
  */
 pv_status pv_blend_rays(pv_volume *vol, const pv_frame *frame, const void *rays_dev, void *stream);
 
-/* Borrowed device pointers to the current tiles (layout in pv_volume_desc). */
+/* Borrowed device pointers to the current tiles, densely packed in the
+ * volume's map format (float or binary16): irradiance [P][3][10][10]
+ * (channel r, g, b; 8x8 interior with its guard band), visibility
+ * [P][2][18][18] (mean distance, mean squared distance; 16x16 interior).
+ * Probe p's tiles start at element p * 300 and p * 648: no padding. */
 pv_status pv_get_maps(pv_volume *vol, void **irr_dev, void **vis_dev);
 /* Borrowed device pointers: ray records [P][n] float4, hit triangle ids
  * [P][n] int32 (-1 = miss; NULL unless PV_KEEP_HITS), directions [n] float4. */
