@@ -154,8 +154,9 @@ pv_status pv_ctx_create(int hip_device, pv_ctx **out);
 pv_status pv_ctx_destroy(pv_ctx *ctx);
 
 /*
- * Copies the scene to the device and builds its BVH on the host (binned
- * surface-area heuristic). Inputs must be finite and indices < n_vertices.
+ * The scene the server traces probe rays against (Sec. 3.1). Copies the
+ * scene to the device and builds its BVH on the host (binned surface-area
+ * heuristic). Inputs must be finite and indices < n_vertices.
  * The shadow-ray offset is 1e-4 times the diagonal of the bounding box of
  * the static triangles.
  */
@@ -183,15 +184,23 @@ pv_status pv_scene_destroy(pv_scene *scene);
 pv_status pv_scene_read_bvh(pv_scene *scene, int dynamic, void *nodes_host, uint64_t nodes_cap, void *tris_host,
                             uint64_t tris_cap, int64_t counts[2], float *eps);
 
-/* Maps zeroed, frame counter 0. */
+/* A probe volume (Sec. 3.2: a regular grid of probes, each with an
+ * octahedral irradiance tile and a visibility tile of mean and mean squared
+ * distance, both with a one-texel guard band). Maps zeroed, frame counter 0.
+ * PV_ERR_ARG for an invalid descriptor, PV_ERR_OOM when device memory runs
+ * out (nothing is left allocated). */
 pv_status pv_create_volume(pv_ctx *ctx, const pv_volume_desc *desc, pv_volume **out);
 pv_status pv_volume_destroy(pv_volume *vol);
 /* Device bytes pv_create_volume would allocate for desc (admission). */
 pv_status pv_volume_footprint(const pv_volume_desc *desc, uint64_t *bytes);
+/* The scene the volume's rays are traced against (Sec. 3.1); the scene is
+ * borrowed and must outlive the volume's updates. */
 pv_status pv_set_scene(pv_volume *vol, pv_scene *scene);
 
 /*
- * One full update (async): ray directions, trace + shade every
+ * One full update (async; Sec. 3.1 server ray tracing of probe textures,
+ * Sec. 3.2 blend of the rays into the irradiance and visibility maps, Eq. 1
+ * and Eq. 2, with hysteresis): ray directions, trace + shade every
  * (probe, ray), blend both maps with hysteresis, rebuild guard bands.
  * A texel whose weight sum over the rays is at most 1e-20 keeps its value.
  * Ray records are kept in the volume's ray buffer (pv_get_rays).
@@ -275,7 +284,9 @@ pv_status pv_client_footprint(const pv_volume_desc *desc, uint64_t *bytes);
 
 /*
  * Build the client's next packet on the device (async) from the volume's
- * current maps. A probe is sent for a texture when any interior texel
+ * current maps (Sec. 3.3: binary16 texels split into two byte planes;
+ * Sec. 3.4: change thresholding against the client's last-transmitted
+ * textures, probe index buffer). A probe is sent for a texture when any interior texel
  * differs from the client's reference: bit pattern differs (tau = 0), or
  * |cur - ref| > tau exactly (tau > 0). Sent probes are written to the
  * reference. Packet layout (little endian):
