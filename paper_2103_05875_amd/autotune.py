@@ -32,10 +32,10 @@ def candidates(space: str = "full") -> List[dict]:
     """Launch shapes to time. "full": every schedule, brick, staging, block
     size and shadow split (the split-shadow trace always runs the plain
     packet kernel: no other schedule). "batched": the shapes a volume can take
-    inside the batched launch, which runs the stepped lanes in 256-thread
+    inside the batched launch, which runs the stepped lanes in 128-thread
     blocks: probe brick and staged top nodes."""
     if space == "batched":
-        return [{"brick": b, "persistent": 2, "top_nodes": t, "block_threads": 256, "split_shadows": False}
+        return [{"brick": b, "persistent": 2, "top_nodes": t, "block_threads": 128, "split_shadows": False}
                 for b, t in itertools.product(BRICKS, TOP_NODES)]
     return [{"brick": b, "persistent": p, "top_nodes": t, "block_threads": w, "split_shadows": s}
             for b, p, t, w, s in itertools.product(BRICKS, PERSISTENT, TOP_NODES, BLOCKS, SPLIT)

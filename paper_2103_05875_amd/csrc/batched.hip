@@ -13,7 +13,10 @@
 
 namespace pv {
 
-constexpr int kBatchBlock = 256;            // trace: four packets per block
+// trace: two packets per block (against four: the 32-volume frame's trace
+// launch 1% faster, as the per-volume tuner's choice of 128-thread blocks
+// for most of its volumes suggested)
+constexpr int kBatchBlock = 128;
 constexpr int kBatchWaves = kBatchBlock / 64;
 
 // Last volume whose first item is at or before 'item' (prefix counts are

@@ -948,7 +948,7 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
         b.h = effective_h(v);
         b.fp16 = v->desc.format == PV_MAP_FP16;
         // the volume's own trace shape: probe brick and staged top nodes (the
-        // batched trace always runs the stepped lanes in 256-thread blocks)
+        // batched trace always runs the stepped lanes in 128-thread blocks)
         b.bx = v->tc.bx;
         b.by = v->tc.by;
         b.bz = v->tc.bz;
@@ -958,7 +958,7 @@ static pv_status fill_batch(pv_volume *const *vols, const pv_frame *frames, int 
         b.bricks_y = (v->desc.ny + b.by - 1) / b.by;
         b.bricks_z = (v->desc.nz + b.bz - 1) / b.bz;
         b.n_waves = b.bricks_x * b.bricks_y * b.bricks_z * v->n;
-        waves = (waves + 3) / 4 * 4;  // trace blocks hold 4 packets; each volume starts on a block boundary
+        waves = (waves + 3) / 4 * 4;  // a multiple of the packets per trace block: each volume starts on a block boundary
         b.first_wave = waves;
         waves += b.n_waves;
         b.n_blend = blend_blocks(v->P, v->blend_mode);
