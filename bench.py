@@ -1036,7 +1036,10 @@ def main():
         "config": {"workload": "city: 16x8x16 probes, 256 rays/probe, 50k-triangle procedural city, FP16 maps, "
                                "moving light; step = full update + delta pack for one client (tau = 0)",
                    "probes": P, "rays_per_probe": n, "triangles": scene.n_triangles,
-                   "blend_path": vol.get_blend_mode()},
+                   "blend_path": vol.get_blend_mode(),
+                   "arithmetic": "trace and shading FP32; blend products of FP32 operands split into three BF16 "
+                                 "parts (six products, FP32 accumulation, about 2^-25 relative per term, the "
+                                 "FP32 parity bars) when blend_path is bf16x6; FP16 maps"},
         "probes_per_s": P * 1e3 / ms_per_step,
         "trace_config": vol.get_trace_config(),
         "autotune": None if tuned is None else {"source": tuned["source"], "tried": tuned["tried"],
