@@ -356,7 +356,7 @@ def test_blend_from_given_rays(ps, ctx, O, fp16, n, grid, sharp):
 
 @pytest.mark.parametrize("mode", ["bf16x3", "f32", "tiles", "valu", "bf16x6"])
 @pytest.mark.parametrize("fp16,n,grid", [(False, 96, (19, 1, 1)), (True, 256, (9, 5, 3)), (True, 300, (3, 2, 2)),
-                                          (False, 33, (2, 1, 1))])
+                                          (False, 33, (2, 1, 1)), (True, 1, (3, 1, 1)), (False, 4096, (2, 1, 1))])
 def test_blend_paths_against_oracle(ps, ctx, O, mode, fp16, n, grid):
     """Every blend path (weight table with split-BF16, FP32 or vector-FMA
     products, or the per-tile weights) on the same seeded ray records over
@@ -465,10 +465,13 @@ def _grid_for(P):
 
 
 # 16,377 probes: 2,048 tiles, the last with one probe (the largest scan-free
-# pack); 16,392 probes: 2,049 tiles (the one-block scan runs)
+# pack); 16,392 probes: 2,049 tiles (the one-block scan runs); 256 and 257
+# probes: 32 and 33 tiles, one and two checksum shares in a group word (32
+# groups); 8,191 probes: 1,024 tiles, 32 shares per group, the last ragged
 @pytest.mark.parametrize("P,taus", [(1, (0.0, 0.0)), (37, (1.0 / 1024, 0.0)), (2048, (0.0, 1.0 / 1024)),
                                     (16384, (1.0 / 1024, 1.0 / 1024)), (1000, (0.01, 0.003)),
-                                    (16377, (0.0, 1.0 / 1024)), (16392, (1.0 / 1024, 0.0))])
+                                    (16377, (0.0, 1.0 / 1024)), (16392, (1.0 / 1024, 0.0)),
+                                    (256, (0.0, 0.0)), (257, (1.0 / 1024, 0.0)), (8191, (0.0, 1.0 / 1024))])
 def test_pack_bit_exact(ps, ctx, O, P, taus):
     _say(f"pack P={P} taus={taus}")
     nx, ny, nz = _grid_for(P)
