@@ -206,6 +206,16 @@ pv_status pv_set_scene(pv_volume *vol, pv_scene *scene);
  * Ray records are kept in the volume's ray buffer (pv_get_rays).
  */
 pv_status pv_update_probes(pv_volume *vol, const pv_frame *frame, void *stream);
+/*
+ * pv_update_probes for a pipeline of frames (the same kernels and results):
+ * the ray directions and the trace are enqueued at once, and the kernels
+ * after them, which rewrite what a pack of the previous frame reads (the
+ * maps, the probe activity), first wait for 'event' (a hipEvent_t passed as
+ * void*, recorded by the caller after those packs, e.g. on another stream).
+ * The packs of frame f then overlap the directions and trace of frame f + 1.
+ * PV_ERR_ARG when event is NULL.
+ */
+pv_status pv_update_probes_after(pv_volume *vol, const pv_frame *frame, void *stream, void *event);
 
 /*
  * The same update for n volumes in one go, enqueued on 'stream': three

@@ -668,7 +668,7 @@ static pv_status enqueue_trace(pv_volume *v, const FrameParams &fp, const SceneV
     return PV_OK;
 }
 
-extern "C" pv_status pv_update_probes(pv_volume *v, const pv_frame *f, void *stream) {
+static pv_status update_probes(pv_volume *v, const pv_frame *f, void *stream, void *after_trace) {
     if (!v) return fail(PV_ERR_ARG, "volume is NULL");
     if (!v->scene) return fail(PV_ERR_STATE, "no scene set on the volume");
     FrameParams fp;
@@ -681,6 +681,9 @@ extern "C" pv_status pv_update_probes(pv_volume *v, const pv_frame *f, void *str
     const int fp16 = v->desc.format == PV_MAP_FP16;
     const float h = effective_h(v);
     PV_TRY(enqueue_trace(v, fp, sv, nullptr, s));
+    // the kernels from here on rewrite what a pack of the previous frame
+    // reads (the maps, the activity): they wait for the caller's event
+    if (after_trace) HIP_TRY(hipStreamWaitEvent(s, (hipEvent_t)after_trace, 0));
     if (v->active)
         HIP_TRY(timed(c, PV_STAGE_SELECT, s, [&] { return launch_classify(vp, sv, v->dirs, v->active, s); }));
     if (v->desc.flags & PV_MULTI_BOUNCE)
@@ -690,6 +693,15 @@ extern "C" pv_status pv_update_probes(pv_volume *v, const pv_frame *f, void *str
     PV_TRY(note_scene_use(v->scene, s));
     v->frame++;
     return PV_OK;
+}
+
+extern "C" pv_status pv_update_probes(pv_volume *v, const pv_frame *f, void *stream) {
+    return update_probes(v, f, stream, nullptr);
+}
+
+extern "C" pv_status pv_update_probes_after(pv_volume *v, const pv_frame *f, void *stream, void *event) {
+    if (!event) return fail(PV_ERR_ARG, "event is NULL");
+    return update_probes(v, f, stream, event);
 }
 
 extern "C" pv_status pv_trace_counts(pv_volume *v, const pv_frame *f, uint64_t counts[3]) {

@@ -33,7 +33,7 @@ PV_MAX_LIGHTS = 8
 EXPORTED_SYMBOLS = [
     "pv_last_error", "pv_version", "pv_ctx_create", "pv_ctx_destroy", "pv_scene_create",
     "pv_scene_set_dynamic", "pv_scene_destroy", "pv_create_volume", "pv_volume_destroy",
-    "pv_volume_footprint", "pv_set_scene", "pv_update_probes", "pv_update_probes_batched",
+    "pv_volume_footprint", "pv_set_scene", "pv_update_probes", "pv_update_probes_after", "pv_update_probes_batched",
     "pv_blend_rays", "pv_get_maps", "pv_get_rays", "pv_set_maps", "pv_read_maps",
     "pv_client_create", "pv_client_destroy", "pv_client_reset", "pv_client_footprint",
     "pv_pack_delta", "pv_packet_device", "pv_packet_download", "pv_get_masks", "pv_sync",
@@ -125,6 +125,7 @@ def lib():
         "pv_volume_footprint": ([P(VolumeDesc), P(u64)], i32),
         "pv_set_scene": ([vp, vp], i32),
         "pv_update_probes": ([vp, P(Frame), vp], i32),
+        "pv_update_probes_after": ([vp, P(Frame), vp, vp], i32),
         "pv_update_probes_batched": ([P(vp), P(Frame), i32, vp], i32),
         "pv_blend_rays": ([vp, P(Frame), vp, vp], i32),
         "pv_get_maps": ([vp, P(vp), P(vp)], i32),
@@ -408,9 +409,16 @@ class Volume:
         _check(lib().pv_set_scene(self.h, scene.h))
         self.scene = scene
 
-    def update_probes(self, rotation, lights=None, stream=None):
+    def update_probes(self, rotation, lights=None, stream=None, after=None):
+        """One update on 'stream'. after: an event (torch.cuda.Event or a raw
+        hipEvent_t) that the kernels after the trace wait for (the packs of
+        the previous frame), or None."""
         f, keep = make_frame(rotation, lights)
-        _check(lib().pv_update_probes(self.h, ctypes.byref(f), _stream_handle(stream)))
+        if after is None:
+            _check(lib().pv_update_probes(self.h, ctypes.byref(f), _stream_handle(stream)))
+        else:
+            ev = after.cuda_event if hasattr(after, "cuda_event") else after
+            _check(lib().pv_update_probes_after(self.h, ctypes.byref(f), _stream_handle(stream), ctypes.c_void_p(ev)))
         del keep
 
     def set_trace_config(self, brick=(4, 4, 4), persistent=2, top_nodes=21, block_threads=256,

@@ -659,6 +659,53 @@ def test_batched_matches_plain_bitwise(ps, ctx, O, maps):
         h.close()
 
 
+def test_pipelined_update_and_pack_match_serial(ps, ctx, O):
+    """Frames pipelined over two streams (each pack on a second stream,
+    overlapping the next frame's directions and trace; the next blend waits
+    for it through pv_update_probes_after) give the serial maps and packets
+    bit for bit, with the BF16x6 table and the per-tile blend."""
+    import torch
+    _say("pipelined update + pack over two streams vs serial")
+    scene = synth.box_city(n_tris=6000, seed_layout=5, seed_heights=6, extent=16.0)
+    sc = ps.Scene.from_synth(ctx, scene)
+    for mode in ("bf16x6", "tiles"):
+        cfg = synth.VolumeConfig(16, 8, 16, (1.0, 0.3, 1.0), (1.0, 1.0, 1.0), 64, fp16=True, max_distance=4.0,
+                                 sky=(0.1, 0.15, 0.25))
+        a, b = ps.Volume(ctx, cfg), ps.Volume(ctx, cfg)
+        for v in (a, b):
+            v.set_scene(sc)
+            v.set_blend_mode(mode)
+        ca, cb = ps.Client(a, client_id=1), ps.Client(b, client_id=1)
+        frames = 6
+        want = []
+        for f in range(frames):
+            a.update_probes(synth.rotation(40, f))
+            ca.pack_delta(0.0, 0.0)
+            want.append(ca.packet_download())
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        evs = [torch.cuda.Event() for _ in range(2)]
+        got = []
+        b.update_probes(synth.rotation(40, 0), stream=s1)
+        for f in range(frames):
+            s2.wait_stream(s1)
+            cb.pack_delta(0.0, 0.0, stream=s2)
+            evs[f % 2].record(s2)
+            # the next frame's update is enqueued before this frame's packet
+            # is read: its directions and trace may run beside the pack
+            if f + 1 < frames:
+                b.update_probes(synth.rotation(40, f + 1), stream=s1, after=evs[f % 2])
+            got.append(cb.packet_download(stream=s2))
+        torch.cuda.synchronize()
+        assert got == want
+        ia, va, _ = a.read_maps()
+        ib, vb, _ = b.read_maps()
+        assert np.array_equal(ia.view(np.uint16), ib.view(np.uint16))
+        assert np.array_equal(va.view(np.uint16), vb.view(np.uint16))
+        for h in (ca, cb, a, b):
+            h.close()
+    sc.close()
+
+
 def test_checkpoint_export_import_continues_identically(ps, ctx, O):
     _say("checkpoint export/import")
     scene = synth.box_room()
