@@ -9,7 +9,7 @@
  * pv_scene_read_bvh (4-wide nodes with byte-quantized child boxes,
  * triangle slots with exact vertices) and shares no code with the HIP
  * path: the walk below is written from that layout and from the traversal
- * the GPU performs, which is the algorithm, not this build's source:
+ * the GPU performs, which is the algorithm, not the library's source:
  *   - closest hit over the static BVH, then the dynamic one, nearest inner
  *     child first (children ordered by entry distance), the others stacked;
  *     a node's hit leaf triangles tested in slot order; culling by the best
