@@ -689,8 +689,9 @@ def leg_codec(ps, torch, reps: int = 20):
 
 def leg_blend_paths(ps, torch, reps: int = 20):
     """The blend (weighted means, hysteresis, guard bands) of volumes of
-    2,048 (the city), 4,096, 8,192 and 16,384 (the encode workload) probes,
-    256 rays, FP16 maps, on every blend path, from the same seeded ray
+    512, 1,024, 2,048 (the city), 4,096, 8,192 and 16,384 (the encode
+    workload) probes, 256 rays (and 64 rays at 1,024 and 2,048 probes),
+    FP16 maps, on every blend path, from the same seeded ray
     records: event time of the blend kernel, its algorithmic bytes (ray
     records, stored interiors read, tiles written) against HBM and its FLOP
     (2 per weight x record term) against the peak of its unit (BF16x3
@@ -700,8 +701,10 @@ def leg_blend_paths(ps, torch, reps: int = 20):
     out = {}
     ctx = ps.Context(0)
     stream = torch.cuda.current_stream()
-    for name, (grid, n) in (("city", ((16, 8, 16), 256)), ("4096", ((16, 16, 16), 256)),
-                            ("8192", ((32, 16, 16), 256)), ("encode", ((32, 16, 32), 256))):
+    for name, (grid, n) in (("512", ((8, 8, 8), 256)), ("1024", ((16, 8, 8), 256)), ("1024_n64", ((16, 8, 8), 64)),
+                            ("city", ((16, 8, 16), 256)), ("city_n64", ((16, 8, 16), 64)),
+                            ("4096", ((16, 16, 16), 256)), ("8192", ((32, 16, 16), 256)),
+                            ("encode", ((32, 16, 32), 256))):
         cfg = synth.VolumeConfig(*grid, (0, 0, 0), (1, 1, 1), n, fp16=True, max_distance=3.0)
         P = cfg.n_probes
         vol = ps.Volume(ctx, cfg)
