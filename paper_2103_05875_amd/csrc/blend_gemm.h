@@ -324,20 +324,54 @@ __device__ __forceinline__ void image_move(T *irr, T *vis, int p0, int np, Blend
     }
 }
 
+// Four consecutive texels of a map row held as raw words: loaded early and
+// taken apart where they are used, so that the load is waited for there
+// (rows of interior texels start at any two-byte boundary).
+template <typename T>
+struct Texels4;
+template <>
+struct Texels4<__half> {
+    uint2 w;
+    __device__ __forceinline__ void load(const __half *p) { __builtin_memcpy(&w, p, sizeof(w)); }
+    __device__ __forceinline__ __half get(int r) const {
+        const uint32_t x = r < 2 ? w.x : w.y;
+        return __ushort_as_half((unsigned short)((r & 1) ? x >> 16 : x & 0xffffu));
+    }
+};
+template <>
+struct Texels4<float> {
+    uint4 w;
+    __device__ __forceinline__ void load(const float *p) { __builtin_memcpy(&w, p, sizeof(w)); }
+    __device__ __forceinline__ float get(int r) const {
+        return __uint_as_float(r == 0 ? w.x : r == 1 ? w.y : r == 2 ? w.z : w.w);
+    }
+};
+
+// s_waitcnt operand: vmcnt(2), no wait on the export and LDS/scalar counters
+// (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+constexpr int kWaitVm2 = 2 | (7 << 4) | (15 << 8);
+
 // Prefetch of step s's records for the split-BF16 products: thread t < 256
 // takes rays 2 (t % 16) and 2 (t % 16) + 1 of probe t / 16 (32 contiguous
-// bytes), and at staging writes both rays' BF16 parts of every channel (the
-// same split as the weights: two parts, x = hi + lo + O(2^-18 x), or three).
+// bytes; threads above load record 0 and stage nothing), and at staging
+// writes both rays' BF16 parts of every channel (the same split as the
+// weights: two parts, x = hi + lo + O(2^-18 x), or three).
 template <int PARTS>
 struct RecPrefetchBF {
     float4 v[2];
+    bool keep[2];
     __device__ __forceinline__ void load(const float4 *rays, int n, int P, int cg, int s) {
         const int t = threadIdx.x, qq = t >> 4, k = 2 * (t & 15);
         const int p = 16 * cg + qq, j = s * kWStep + k;
         const bool ok = t < 256 && p < P;
+        // every lane loads (record 0 in place of one outside the volume), so
+        // that every wavefront has the same loads in flight; the zeros are
+        // applied at staging
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-            v[u] = (ok && j + u < n) ? rays[(size_t)p * n + j + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int u = 0; u < 2; ++u) {
+            keep[u] = ok && j + u < n;
+            v[u] = rays[keep[u] ? (size_t)p * n + j + u : 0];
+        }
     }
     __device__ __forceinline__ void store(BlendRecsBF &sm, int buf) const {
         const int t = threadIdx.x;
@@ -345,7 +379,7 @@ struct RecPrefetchBF {
         const int qq = t >> 4, w = t & 15;
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            const float x0 = channel(v[0], c), x1 = channel(v[1], c);
+            const float x0 = keep[0] ? channel(v[0], c) : 0.f, x1 = keep[1] ? channel(v[1], c) : 0.f;
             const unsigned short h0 = bf16_bits(x0), h1 = bf16_bits(x1);
             const float r0 = x0 - bf16_value(h0), r1 = x1 - bf16_value(h1);
             const unsigned short m0 = bf16_bits(r0), m1 = bf16_bits(r1);
@@ -364,19 +398,21 @@ template <int NT>
 struct RecPrefetch {
     static constexpr int kPer = 16 * kWStep / NT;
     float4 v[kPer];
+    bool keep[kPer];
     __device__ __forceinline__ void load(const float4 *rays, int n, int P, int cg, int s) {
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int e = threadIdx.x + u * NT, qq = e / kWStep, k = e % kWStep;
             const int p = 16 * cg + qq, j = s * kWStep + k;
-            v[u] = (p < P && j < n) ? rays[(size_t)p * n + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+            keep[u] = p < P && j < n;
+            v[u] = rays[keep[u] ? (size_t)p * n + j : 0];  // record 0 in place of one outside
         }
     }
     __device__ __forceinline__ void store(BlendRecs &sm, int buf) const {
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int e = threadIdx.x + u * NT;
-            sm.r[buf][e / kWStep][e % kWStep] = v[u];
+            sm.r[buf][e / kWStep][e % kWStep] = keep[u] ? v[u] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     }
 };
@@ -400,6 +436,38 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
     const bool live = p < P;
     const uint8_t *tab = weight_table(dirs, n);
     const int steps = (n + kWStep - 1) / kWStep;
+    // weight fragments of every row tile of the wavefront for the current
+    // step, requested at the step's start in four-wavefront blocks (a second
+    // set for the next step would cost the registers of a wavefront per
+    // SIMD on the encode-size grid); eight-wavefront blocks (small volumes,
+    // fewer blocks than resident slots) have registers to spare and request
+    // the next step's fragments one step ahead
+    constexpr bool kAhead = NT == 512 && MODE != kBlendVALU;
+    // the same blocks (one per CU: the latency of their loads, not their
+    // products, sets their pace) request the records two steps ahead, into
+    // two register sets taken in turn (the others one step ahead, into one),
+    // and take the stored interior texels of their outputs into registers
+    // first, in flight under the products, instead of loading the block's
+    // tiles into LDS after them
+    constexpr bool kDeep = kAhead;
+    Texels4<T> old[kDeep ? TS::kTiles : 1];
+    if constexpr (kDeep) {
+        if (live) {
+#pragma unroll
+            for (int t = 0; t < TS::kRowTiles; ++t) {
+                const bool it = t < NI;
+                const int N = it ? 8 : 16, nch = it ? 3 : 2;
+                const int mloc = it ? I0 + t : V0 + (t - NI);
+                const int acc0 = it ? 3 * t : 3 * NI + 2 * (t - NI);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (c >= nch) continue;
+                    const T *tile = it ? irr + (size_t)p * 300 + c * 100 : vis + (size_t)p * 648 + c * 324;
+                    old[acc0 + c].load(tile + interior(N, 16 * mloc + 4 * kq));
+                }
+            }
+        }
+    }
     TS ts;
 #pragma unroll
     for (int t = 0; t < TS::kTiles; ++t) ts.acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -408,8 +476,8 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
     constexpr bool kSplit = MODE == kBlendBF16x3 || MODE == kBlendBF16x6;
     constexpr int kParts = MODE == kBlendBF16x6 ? 3 : 2;
     using PF = std::conditional_t<kSplit, RecPrefetchBF<kParts>, RecPrefetch<NT>>;
-    PF pf;
-    pf.load(rays, n, P, cg, 0);
+    PF pf0, pf1;
+    pf0.load(rays, n, P, cg, 0);
     {
         // the row totals of the epilogue: the table's step-group partials,
         // added in order
@@ -422,17 +490,10 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
         }
     }
     if constexpr (kSplit)
-        pf.store(sb, 0);
+        pf0.store(sb, 0);
     else
-        pf.store(sm, 0);
+        pf0.store(sm, 0);
     __syncthreads();
-    // weight fragments of every row tile of the wavefront for the current
-    // step, requested at the step's start in four-wavefront blocks (a second
-    // set for the next step would cost the registers of a wavefront per
-    // SIMD on the encode-size grid); eight-wavefront blocks (small volumes,
-    // fewer blocks than resident slots) have registers to spare and request
-    // the next step's fragments with the next step's records, one step ahead
-    constexpr bool kAhead = NT == 512 && MODE != kBlendVALU;
     // fragment parts held per row tile: three for BF16x6 (whose
     // four-wavefront blocks load them tile by tile in the product loop)
     constexpr int kFp = MODE == kBlendBF16x6 ? 3 : 2;
@@ -448,15 +509,32 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
 #pragma unroll
         for (int t = 0; t < RT; ++t) load_parts(0, t, acur[t]);
     }
-    for (int s = 0; s < steps; ++s) {
+    // (after the fragments: a step's first wait leaves in flight only the
+    // newest loads, the records of the next step). The loads of these
+    // blocks do not depend on the step count (past the last step they
+    // repeat its fragments and take record 0, which is never staged), so
+    // that every wait below counts the same loads on every path
+    if constexpr (kDeep) pf1.load(rays, n, P, cg, 1);
+    const int np = min(16, P - 16 * cg);
+    // step s: 'ld' takes the records of step s + 2 (kDeep) or s + 1, 'st'
+    // holds those of step s + 1 and stages them into LDS at the end
+    auto step = [&](int s, PF &ld, PF &st) {
         const int buf = s & 1;
-        if (s + 1 < steps) pf.load(rays, n, P, cg, s + 1);
-        if constexpr (kAhead) {
-            if (s + 1 < steps) {
+        if constexpr (kDeep) {
+            // everything but the two newest loads (this step's fragments
+            // arrived with the last step's copy; the next step's records stay
+            // in flight), so that the products below wait for nothing; then
+            // the next step's fragments and, after them, the records two
+            // steps ahead, in that order
+            __builtin_amdgcn_s_waitcnt(kWaitVm2);
 #pragma unroll
-                for (int t = 0; t < RT; ++t) load_parts(s + 1, t, anext[t]);
-            }
-        } else if constexpr (MODE != kBlendVALU && MODE != kBlendBF16x6) {
+            for (int t = 0; t < RT; ++t) load_parts(min(s + 1, steps - 1), t, anext[t]);
+            __builtin_amdgcn_sched_barrier(0);
+            ld.load(rays, n, P, cg, s + 2);
+        } else {
+            if (s + 1 < steps) ld.load(rays, n, P, cg, s + 1);
+        }
+        if constexpr (!kAhead && MODE != kBlendVALU && MODE != kBlendBF16x6) {
 #pragma unroll
             for (int t = 0; t < RT; ++t) load_frag(tab, s, TS::mtile(t), acur[t][0], acur[t][1]);
         }
@@ -589,9 +667,9 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
         // every wavefront is done with the other buffer since the last step's barrier
         if (s + 1 < steps) {
             if constexpr (kSplit)
-                pf.store(sb, buf ^ 1);
+                st.store(sb, buf ^ 1);
             else
-                pf.store(sm, buf ^ 1);
+                st.store(sm, buf ^ 1);
             if constexpr (kAhead) {
 #pragma unroll
                 for (int t = 0; t < RT; ++t) {
@@ -601,17 +679,31 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
             }
         }
         __syncthreads();
+    };
+    if constexpr (kDeep) {
+        // (the loop is entered only from its last step, so that no wait at
+        // its head has to cover loads issued by the first)
+        for (int s = 0;;) {
+            step(s, pf0, pf1);
+            if (++s == steps) break;
+            step(s, pf1, pf0);
+            if (++s == steps) break;
+        }
+    } else {
+        for (int s = 0; s < steps; ++s) step(s, pf0, pf0);
     }
     // epilogue, through the block's LDS image of its probes' tiles: the
-    // stored tiles are loaded (coalesced), each wavefront replaces its
+    // stored tiles are loaded (coalesced; eight-wavefront blocks hold their
+    // outputs' stored interior texels already), each wavefront replaces its
     // interior texels by the new values (estimate = sum / row total,
     // hysteresis, the map's rounding; a texel whose total is at most the
     // floor keeps its value), the guard texels are copied from their
     // interior sources in LDS, and the tiles are written back whole
     BlendImage<T> &img = smu.img;
-    const int np = min(16, P - 16 * cg);
-    image_move<T, true, 1024 / NT>(irr, vis, 16 * cg, np, img);
-    __syncthreads();
+    if constexpr (!kDeep) {
+        image_move<T, true, 1024 / NT>(irr, vis, 16 * cg, np, img);
+        __syncthreads();
+    }
     const float *rows = smu.rows;
     if (live) {
 #pragma unroll
@@ -630,10 +722,18 @@ __device__ void blend_gemm_tiles(const VolumeParams &vp, const float4 *dirs, con
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const float w = total[r];
-                    if (!(w > kWeightFloor)) continue;
                     T &dst = tile[interior(N, 16 * mloc + 4 * kq + r)];
+                    T prev;
+                    if constexpr (kDeep) {
+                        // every interior texel of the image is written here
+                        prev = old[acc0 + c].get(r);
+                        if (!(w > kWeightFloor)) dst = prev;
+                    } else {
+                        prev = dst;
+                    }
+                    if (!(w > kWeightFloor)) continue;
                     const float est = ts.acc[acc0 + c][r] * (1.0f / w);
-                    dst = to_map<T>(h > 0.f ? fmaf(h, load_map<T>(&dst), (1.0f - h) * est) : est);
+                    dst = to_map<T>(h > 0.f ? fmaf(h, load_map<T>(&prev), (1.0f - h) * est) : est);
                 }
             }
         }
