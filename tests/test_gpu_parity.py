@@ -357,7 +357,7 @@ def test_blend_from_given_rays(ps, ctx, O, fp16, n, grid, sharp):
 @pytest.mark.parametrize("mode", ["bf16x3", "f32", "tiles", "valu", "bf16x6"])
 @pytest.mark.parametrize("fp16,n,grid", [(False, 96, (19, 1, 1)), (True, 256, (9, 5, 3)), (True, 300, (3, 2, 2)),
                                           (False, 33, (2, 1, 1)), (True, 1, (3, 1, 1)), (False, 4096, (2, 1, 1)),
-                                          (True, 224, (5, 3, 2))])
+                                          (True, 224, (5, 3, 2)), (False, 1, (17, 1, 1))])
 def test_blend_paths_against_oracle(ps, ctx, O, mode, fp16, n, grid):
     """Every blend path (weight table with split-BF16, FP32 or vector-FMA
     products, or the per-tile weights) on the same seeded ray records over
@@ -366,7 +366,8 @@ def test_blend_paths_against_oracle(ps, ctx, O, mode, fp16, n, grid):
     products, whose terms carry about 2^-16 of relative error, within
     1e-4; BF16x6, about 2^-25, within 1e-5). Ray counts give one, two,
     three, seven and ten 32-ray steps (odd and even counts, ragged last
-    steps) and 128."""
+    steps) and 128; with one ray most texels have no weight and keep their
+    stored value (FP16 and FP32 maps)."""
     import torch
     _say(f"blend path {mode} fp16={fp16} n={n} grid={grid}")
     cfg = synth.VolumeConfig(*grid, (0, 0, 0), (1, 1, 1), n, fp16=fp16, max_distance=4.0)
