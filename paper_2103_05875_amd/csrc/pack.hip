@@ -52,10 +52,24 @@ __device__ __forceinline__ void stage_tiles(const PackBuffers &b, int p0, int P,
     const uint4 *gv = reinterpret_cast<const uint4 *>(b.cur_vis + (size_t)p0 * 648);
     // n * 1296 is a multiple of 16; n * 600 leaves 8 bytes when n is odd
     const int vi = n * 600 / 16, vv = n * 1296 / 16;
-    for (int i = threadIdx.x; i < vi; i += kPackThreads) sm.irr[i] = gi[i];
-    for (int i = threadIdx.x; i < vv; i += kPackThreads) sm.vis[i] = gv[i];
+    // every chunk of the thread is requested before any is stored, so that
+    // their latencies overlap (a load-store loop waits for each load in
+    // turn); a thread past the run takes the run's last chunk, loading and
+    // storing the same bytes as its owner (unconditional stores keep each
+    // load from being moved next to its store)
+    constexpr int kI = (kPackQ * 600 / 16 + kPackThreads - 1) / kPackThreads;
+    constexpr int kV = (kPackQ * 1296 / 16 + kPackThreads - 1) / kPackThreads;
+    uint4 ri[kI], rv[kV];
+#pragma unroll
+    for (int u = 0; u < kI; ++u) ri[u] = gi[min((int)threadIdx.x + u * kPackThreads, vi - 1)];
+#pragma unroll
+    for (int u = 0; u < kV; ++u) rv[u] = gv[min((int)threadIdx.x + u * kPackThreads, vv - 1)];
     if ((n & 1) && threadIdx.x == 0)
         reinterpret_cast<uint2 *>(sm.irr)[2 * vi] = reinterpret_cast<const uint2 *>(gi)[2 * vi];
+#pragma unroll
+    for (int u = 0; u < kI; ++u) sm.irr[min((int)threadIdx.x + u * kPackThreads, vi - 1)] = ri[u];
+#pragma unroll
+    for (int u = 0; u < kV; ++u) sm.vis[min((int)threadIdx.x + u * kPackThreads, vv - 1)] = rv[u];
 }
 
 // Unit u of the tile (irradiance units first): probe q, texture (0 irr,
