@@ -77,6 +77,31 @@ __device__ __forceinline__ float load_map<float>(const float *p) { return *p; }
 template <>
 __device__ __forceinline__ float load_map<__half>(const __half *p) { return __half2float(*p); }
 
+// Four consecutive texels of a map row held as raw words: loaded early and
+// taken apart where they are used, so that the load is waited for there
+// (rows of interior texels start at any two-byte boundary).
+template <typename T>
+struct Texels4;
+template <>
+struct Texels4<__half> {
+    uint2 w;
+    __device__ __forceinline__ void load(const __half *p) { __builtin_memcpy(&w, p, sizeof(w)); }
+    __device__ __forceinline__ __half get(int r) const {
+        const uint32_t x = r < 2 ? w.x : w.y;
+        return __ushort_as_half((unsigned short)((r & 1) ? x >> 16 : x & 0xffffu));
+    }
+    __device__ __forceinline__ float getf(int r) const { return __half2float(get(r)); }
+};
+template <>
+struct Texels4<float> {
+    uint4 w;
+    __device__ __forceinline__ void load(const float *p) { __builtin_memcpy(&w, p, sizeof(w)); }
+    __device__ __forceinline__ float get(int r) const {
+        return __uint_as_float(r == 0 ? w.x : r == 1 ? w.y : r == 2 ? w.z : w.w);
+    }
+    __device__ __forceinline__ float getf(int r) const { return get(r); }
+};
+
 template <typename T>
 __device__ __forceinline__ T to_map(float v);
 template <>
@@ -168,15 +193,15 @@ __device__ void blend_tile(const VolumeParams &vp, const float4 *dirs, const flo
     // half, or blue) and their stored values (rows 4 krow + r)
     T *itile = irr + ((size_t)min(p, P - 1) * 3 + (ctile ? 2 : half)) * 100;
     T *vtile = vis + ((size_t)min(p, P - 1) * 2 + half) * 324;
-    float old_i[4] = {0.f, 0.f, 0.f, 0.f}, old_v0[4] = {0.f, 0.f, 0.f, 0.f}, old_v1[4] = {0.f, 0.f, 0.f, 0.f};
-    if (h > 0.f && p < P) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int ti = 16 * (g >> 1) + 4 * krow + r, tv0 = 32 * g + 4 * krow + r;
-            if (has_i) old_i[r] = load_map<T>(itile + interior(8, ti));
-            old_v0[r] = load_map<T>(vtile + interior(16, tv0));
-            old_v1[r] = load_map<T>(vtile + interior(16, tv0 + 16));
-        }
+    // (rows 4 krow .. 4 krow + 3 are four consecutive texels of one tile
+    // row; the tiles above are those of a probe inside the volume, so every
+    // lane loads, used or not, and no load waits in a branch of its own)
+    Texels4<T> old_i, old_v0, old_v1;
+    {
+        const int ti = 16 * (g >> 1) + 4 * krow, tv0 = 32 * g + 4 * krow;
+        old_i.load(itile + interior(8, ti));
+        old_v0.load(vtile + interior(16, tv0));
+        old_v1.load(vtile + interior(16, tv0 + 16));
     }
 
     // chunk staging: consecutive threads take consecutive LDS records (8
@@ -251,10 +276,10 @@ __device__ void blend_tile(const VolumeParams &vp, const float4 *dirs, const flo
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int ti = 16 * (g >> 1) + 4 * krow + r;
-        if (has_i) blend_store<T>(itile, 8, ti, acc_i[r], sm.rows[ti], h, old_i[r]);
+        if (has_i) blend_store<T>(itile, 8, ti, acc_i[r], sm.rows[ti], h, old_i.getf(r));
         const int tv0 = 32 * g + 4 * krow + r, tv1 = tv0 + 16;
-        blend_store<T>(vtile, 16, tv0, acc_v0[r], sm.rows[kIrrRows + tv0], h, old_v0[r]);
-        blend_store<T>(vtile, 16, tv1, acc_v1[r], sm.rows[kIrrRows + tv1], h, old_v1[r]);
+        blend_store<T>(vtile, 16, tv0, acc_v0[r], sm.rows[kIrrRows + tv0], h, old_v0.getf(r));
+        blend_store<T>(vtile, 16, tv1, acc_v1[r], sm.rows[kIrrRows + tv1], h, old_v1.getf(r));
     }
 }
 

@@ -324,29 +324,6 @@ __device__ __forceinline__ void image_move(T *irr, T *vis, int p0, int np, Blend
     }
 }
 
-// Four consecutive texels of a map row held as raw words: loaded early and
-// taken apart where they are used, so that the load is waited for there
-// (rows of interior texels start at any two-byte boundary).
-template <typename T>
-struct Texels4;
-template <>
-struct Texels4<__half> {
-    uint2 w;
-    __device__ __forceinline__ void load(const __half *p) { __builtin_memcpy(&w, p, sizeof(w)); }
-    __device__ __forceinline__ __half get(int r) const {
-        const uint32_t x = r < 2 ? w.x : w.y;
-        return __ushort_as_half((unsigned short)((r & 1) ? x >> 16 : x & 0xffffu));
-    }
-};
-template <>
-struct Texels4<float> {
-    uint4 w;
-    __device__ __forceinline__ void load(const float *p) { __builtin_memcpy(&w, p, sizeof(w)); }
-    __device__ __forceinline__ float get(int r) const {
-        return __uint_as_float(r == 0 ? w.x : r == 1 ? w.y : r == 2 ? w.z : w.w);
-    }
-};
-
 // s_waitcnt operand: vmcnt(2), no wait on the export and LDS/scalar counters
 // (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
 constexpr int kWaitVm2 = 2 | (7 << 4) | (15 << 8);
